@@ -1,0 +1,166 @@
+"""Eddy-viscosity models (Sec. 2.1, Eqs. smag, dsmag, cs, lij, mij; Sec. 2.2, SGS
+evaluation and test-filter paragraph).  Test infrastructure only.
+
+Inputs are ghosted velocity arrays whose ghost planes follow bc.fill_velocity; the strain
+for the model uses bc.strain_ghosts.  Outputs are nu_t (or |S| and c_s) on the interior
+planes k = 1..nz, shape (nz, ny, nx).
+"""
+import numpy as np
+
+from . import bc
+from .case import ZBC_PERIODIC, ZBC_WALLMODEL, SGS_SMAG, SGS_SMAG_VD, SGS_DSM
+from .ops import centre_strain, strain_magnitude, xm, xp, ym, yp
+
+
+def model_strain(case, g, u, v, w):
+    """S_ij at cell centres with the SGS-strain ghosts (one-sided wall-normal derivative
+    in the first layer when the wall model is on, Sec. 2.2)."""
+    us, vs = bc.strain_ghosts(case, g, u, v)
+    return centre_strain(g, us, vs, w)
+
+
+def smagorinsky(case, g, u, v, w, utau_walls=None):
+    """Static model, Eq. smag: nu_t = (C_s Delta D)^2 |S|.
+    Delta per R5.  D = 1 - exp(-y*/25) (van Driest, Sec. 2.1) for SGS_SMAG_VD, with
+    y* = d u_tau / nu, d the distance to the nearer wall and u_tau that wall's friction
+    velocity (R6: utau_walls = (u_tau bottom, u_tau top)); D = 1 for SGS_SMAG."""
+    s = model_strain(case, g, u, v, w)
+    smag = strain_magnitude(s)
+    delta = g.delta()[:, None, None]
+    damp = np.ones((g.nz, 1, 1))
+    if case.sgs == SGS_SMAG_VD and case.zbc != ZBC_PERIODIC:
+        zc = g.zc[1:g.nz + 1]
+        lower = zc <= 0.5 * g.lz
+        dist = np.where(lower, zc, g.lz - zc)
+        ut = np.where(lower, utau_walls[0], utau_walls[1])
+        damp = (1.0 - np.exp(-dist * ut / case.nu / 25.0))[:, None, None]
+    return (case.cs * delta * damp) ** 2 * smag
+
+
+def friction_velocity(tau):
+    """R6: per-wall friction velocity from the plane-mean wall-stress vector,
+    u_tau = sqrt(|(<tau_x>, <tau_y>)|).  tau = (tx_bot, ty_bot, tx_top, ty_top)."""
+    txb, tyb, txt, tyt = tau
+    ub = np.sqrt(np.hypot(np.mean(txb), np.mean(tyb)))
+    ut = np.sqrt(np.hypot(np.mean(txt), np.mean(tyt)))
+    return ub, ut
+
+
+# ---------------------------------------------------------------- dynamic model
+def _filter_xy(q):
+    """Trapezoidal box filter (1/4, 1/2, 1/4) in x then y (R7, uniform weights, Sec. 2.2)."""
+    q = 0.25 * xm(q) + 0.5 * q + 0.25 * xp(q)
+    return 0.25 * ym(q) + 0.5 * q + 0.25 * yp(q)
+
+
+def _pad_z_centre(case, q):
+    """Ghost planes for a z-centred quantity before the z pass of the test filter: periodic
+    copy, or (R9) linear extrapolation in index space, q_0 = 2 q_1 - q_2, which makes the
+    z pass the identity on the first off-wall layer (the paper's 2-D filter there)."""
+    n = q.shape[0]
+    out = np.empty((n + 2,) + q.shape[1:])
+    out[1:n + 1] = q
+    if case.zbc == ZBC_PERIODIC:
+        out[0], out[n + 1] = q[n - 1], q[0]
+    else:
+        out[0] = 2.0 * q[0] - q[1]
+        out[n + 1] = 2.0 * q[n - 1] - q[n - 2]
+    return out
+
+
+def test_filter_centre(case, q):
+    """3-D test filter of a z-centred quantity on the interior planes (nz, ny, nx)."""
+    qp = _pad_z_centre(case, _filter_xy(q))
+    return 0.25 * qp[:-2] + 0.5 * qp[1:-1] + 0.25 * qp[2:]
+
+
+def test_filter_velocity(case, g, u, v, w):
+    """Test-filtered staggered velocity, each component on its own grid (R8).  u and v are
+    z-centred (filtered like test_filter_centre); w lives on z-faces and uses the true
+    wall values w = 0 (or periodic copies) as its z neighbours.  Ghost planes of the result
+    follow the SGS-strain rule of the unfiltered field."""
+    n = g.nz
+    I = slice(1, n + 1)
+    uf, vf, wf = np.zeros_like(u), np.zeros_like(v), np.zeros_like(w)
+    uf[I] = test_filter_centre(case, u[I])
+    vf[I] = test_filter_centre(case, v[I])
+    wxy = _filter_xy(w)
+    wf[I] = 0.25 * wxy[0:n] + 0.5 * wxy[1:n + 1] + 0.25 * wxy[2:n + 2]
+    if case.zbc == ZBC_PERIODIC:
+        bc.fill_velocity(case, g, uf, vf, wf)
+    else:
+        wf[0] = 0.0
+        wf[n] = 0.0
+        wf[n + 1] = 0.0
+        if case.zbc == ZBC_WALLMODEL:
+            pass        # strain_ghosts() below extrapolates
+        else:
+            uf[0], uf[n + 1] = -uf[1], -uf[n]
+            vf[0], vf[n + 1] = -vf[1], -vf[n]
+    return uf, vf, wf
+
+
+def dynamic_coefficient(case, g, u, v, w):
+    """Dynamic procedure (Eqs. cs, lij, mij; Sec. 2.2 test-filter paragraph).
+    1. velocities averaged to cell centres; 2. S_ij and |S| at centres;
+    3. L_ij = F(uc_i uc_j) - F(uc_i) F(uc_j);
+    4. S~_ij from the test-filtered staggered velocity with the same strain routine;
+    5. M_ij = 2 Delta^2 [F(|S| S_ij) - alpha^2 |S~| S~_ij] with alpha^2 = 4 (alpha = 2 in
+       3-D) and alpha^2 = 4^(2/3) on the first off-wall layers (alpha = 4^(1/3));
+    6. c_s = <L_ij M_ij>/<M_ij M_ij> over each x-y plane (over the whole box when z is
+       periodic), clipped at zero; R10: c_s = 0 where <M M> = 0.
+    Returns (c_s per plane (nz,), |S| (nz, ny, nx), sum LM per plane, sum MM per plane)."""
+    n = g.nz
+    I, Im = slice(1, n + 1), slice(0, n)
+    uc = 0.5 * (u[I] + xm(u[I]))
+    vc = 0.5 * (v[I] + ym(v[I]))
+    wc = 0.5 * (w[I] + w[Im])
+    s = model_strain(case, g, u, v, w)
+    smag = strain_magnitude(s)
+    F = lambda q: test_filter_centre(case, q)
+    vel = (uc, vc, wc)
+    fvel = [F(q) for q in vel]
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]   # order of s: 11 22 33 12 13 23
+    uf, vf, wf = test_filter_velocity(case, g, u, v, w)
+    st = model_strain(case, g, uf, vf, wf)
+    stmag = strain_magnitude(st)
+    delta2 = (g.delta() ** 2)[:, None, None]
+    alpha2 = np.full((n, 1, 1), 4.0)
+    if case.zbc != ZBC_PERIODIC:
+        alpha2[0] = alpha2[n - 1] = 4.0 ** (2.0 / 3.0)
+    lm = np.zeros_like(smag)
+    mm = np.zeros_like(smag)
+    for c, (a, b) in enumerate(pairs):
+        L = F(vel[a] * vel[b]) - fvel[a] * fvel[b]
+        M = 2.0 * delta2 * (F(smag * s[c]) - alpha2 * stmag * st[c])
+        wgt = 1.0 if a == b else 2.0          # symmetric tensors: off-diagonals twice
+        lm += wgt * L * M
+        mm += wgt * M * M
+    if case.zbc == ZBC_PERIODIC:
+        slm = np.full(n, lm.sum())
+        smm = np.full(n, mm.sum())
+    else:
+        slm = lm.sum(axis=(1, 2))
+        smm = mm.sum(axis=(1, 2))
+    cs = np.where(smm > 0.0, np.maximum(slm / np.where(smm > 0.0, smm, 1.0), 0.0), 0.0)
+    return cs, smag, slm, smm
+
+
+def dynamic_smagorinsky(case, g, u, v, w):
+    """Eq. dsmag: nu_t = c_s Delta^2 |S|.  Returns (nu_t, c_s)."""
+    cs, smag, _, _ = dynamic_coefficient(case, g, u, v, w)
+    return cs[:, None, None] * (g.delta() ** 2)[:, None, None] * smag, cs
+
+
+def eddy_viscosity(case, g, u, v, w, tau=None):
+    """nu_t on the interior planes for the configured model (SGS_NONE gives zeros)."""
+    if case.sgs in (SGS_SMAG, SGS_SMAG_VD):
+        ut = None
+        if case.sgs == SGS_SMAG_VD and case.zbc != ZBC_PERIODIC:
+            if tau is None:
+                tau = bc.noslip_wall_stress(case, g, u, v)
+            ut = friction_velocity(tau)
+        return smagorinsky(case, g, u, v, w, ut), None
+    if case.sgs == SGS_DSM:
+        return dynamic_smagorinsky(case, g, u, v, w)
+    return np.zeros((g.nz, g.ny, g.nx)), None

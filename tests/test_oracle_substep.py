@@ -1,0 +1,189 @@
+"""Pins of the oracle's RK3 substep (Alg. 1) against closed forms and exact invariants."""
+import numpy as np
+import pytest
+
+from oracle import Case, Grid, ops, substep as S
+from oracle.case import ZBC_PERIODIC, ZBC_NOSLIP, ZBC_WALLMODEL, SGS_NONE, SGS_SMAG, SGS_DSM
+from synth import taylor_green_field, isotropic_field, channel_field, random_state
+
+
+def _step(case, g, st, dt):
+    for k in range(3):
+        st = S.substep(case, g, st, k, dt)
+    return st
+
+
+def test_rk3_coefficients():
+    """Sec. 2.2: gamma = alpha + beta = (8/15, 2/15, 1/3) and sum(gamma) = 1."""
+    assert np.allclose(S.GAMMA, (8 / 15, 2 / 15, 1 / 3), rtol=0, atol=1e-16)
+    assert abs(sum(S.GAMMA) - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("n,nu,dt", [(16, 0.05, 0.05), (8, 0.3, 0.02)])
+def test_taylor_green_viscous_amplification(n, nu, dt):
+    """Advection off: u = eps sin x cos y is discretely divergence-free and an eigenmode of
+    the viscous operator with lambda = -(8/dx^2) sin^2(dx/2); one full RK3 step multiplies
+    it by R(z) = 1 + z + z^2/2 + z^3/6, z = nu lambda dt (derived from alpha, beta)."""
+    case = Case(n, n, 4, 2 * np.pi, 2 * np.pi, 2.0, zbc=ZBC_PERIODIC, nu=nu, advection=False)
+    g = Grid(case)
+    u, v, w = taylor_green_field(n, 4, 1.0)
+    st = S.initial_state(case, g, u, v, w)
+    u0 = st.u.copy()
+    st = _step(case, g, st, dt)
+    lam = -(8.0 / g.dx ** 2) * np.sin(g.dx / 2) ** 2
+    z = nu * lam * dt
+    R = 1 + z + z * z / 2 + z ** 3 / 6
+    assert np.max(np.abs(st.u[1:5] - R * u0[1:5])) < 1e-13
+    assert np.max(np.abs(st.p)) < 1e-12
+
+
+def test_taylor_green_decay_with_advection_second_order():
+    """Finite amplitude: the decay of the kinetic energy follows exp(-4 nu t) with an error
+    that falls by about 4x per grid doubling (second order in space)."""
+    nu, T = 0.05, 0.4
+    errs = []
+    for n in (16, 32):
+        case = Case(n, n, 2, 2 * np.pi, 2 * np.pi, 1.0, zbc=ZBC_PERIODIC, nu=nu)
+        g = Grid(case)
+        u, v, w = taylor_green_field(n, 2, 1.0)
+        st = S.initial_state(case, g, u, v, w)
+        e0 = np.mean(st.u[1:3] ** 2 + st.v[1:3] ** 2)
+        steps = 40
+        for _ in range(steps):
+            st = _step(case, g, st, T / steps)
+        e = np.mean(st.u[1:3] ** 2 + st.v[1:3] ** 2)
+        errs.append(abs(e / e0 - np.exp(-4 * nu * T)))
+    assert errs[1] < errs[0] / 3.0
+
+
+def test_cn_z_eigen_ratio():
+    """CN in z (Eqs. twostar_imp1d, onestar_imp1d): for a discrete eigenvector of the
+    no-slip L_zz (found with numpy.linalg.eig on the assembled matrix), each substep
+    multiplies the profile by (1 + gamma z/2)/(1 - gamma z/2), z = nu mu dt."""
+    nz = 10
+    case = Case(4, 4, nz, 1.0, 1.0, 2.0, zbc=ZBC_NOSLIP, beta=1.3, nu=0.02, implicit_z=True)
+    g = Grid(case)
+    A = np.zeros((nz, nz))
+    for c in range(nz):
+        a = np.zeros((nz + 2, 1, 1))
+        a[c + 1] = 1.0
+        a[0], a[nz + 1] = -a[1], -a[nz]
+        A[:, c] = S.ops.lap_z_centre(g, a)[:, 0, 0]
+    mu, vec = np.linalg.eig(A)
+    q = np.argsort(np.abs(mu))[2]
+    prof = np.real(vec[:, q])
+    u = np.zeros((nz + 2, 4, 4))
+    u[1:nz + 1] = prof[:, None, None]
+    st = S.initial_state(case, g, u, np.zeros_like(u), np.zeros_like(u))
+    dt = 0.7
+    ratio = 1.0
+    for k in range(3):
+        st = S.substep(case, g, st, k, dt)
+        z = case.nu * np.real(mu[q]) * dt
+        ratio *= (1 + S.GAMMA[k] * z / 2) / (1 - S.GAMMA[k] * z / 2)
+        assert np.allclose(st.u[1:nz + 1], ratio * u[1:nz + 1], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("zbc,implicit,model", [(ZBC_PERIODIC, False, SGS_SMAG),
+                                                (ZBC_NOSLIP, True, SGS_SMAG),
+                                                (ZBC_WALLMODEL, True, SGS_DSM),
+                                                (ZBC_WALLMODEL, False, SGS_DSM)])
+def test_divergence_free_and_bulk_after_substep(zbc, implicit, model):
+    """Eq. correc makes D u = 0 up to roundoff: max|D u| <= 1e-13 max|u| / min spacing;
+    the flow-rate shift keeps <u> = U_b to roundoff."""
+    nx, ny, nz = 16, 8, 12
+    per = zbc == ZBC_PERIODIC
+    case = Case(nx, ny, nz, 2 * np.pi, np.pi, 2.0, zbc=zbc, beta=0.0 if per else 1.5,
+                nu=1e-3 if per else 5e-5, sgs=model, cs=0.17, implicit_z=implicit,
+                ubulk=0.0 if per else 1.0)
+    g = Grid(case)
+    if per:
+        u, v, w, _ = random_state(nx, ny, nz, 3)
+    else:
+        u, v, w = channel_field(nx, ny, nz, g.zc, seed=2)
+    st = S.initial_state(case, g, u, v, w)
+    dt = 0.2 * S.time_step(case, g, st)
+    for k in range(3):
+        st = S.substep(case, g, st, k, dt)
+        d = ops.divergence(g, st.u, st.v, st.w)
+        hmin = min(g.dx, g.dy, np.min(g.dzf[1:nz + 1]))
+        umax = max(np.abs(st.u).max(), np.abs(st.v).max(), np.abs(st.w).max())
+        assert np.max(np.abs(d)) <= 1e-13 * umax / hmin
+        if not per:
+            assert abs(S.bulk_velocity(g, st.u) - 1.0) < 1e-14
+            assert np.all(st.w[0] == 0) and np.all(st.w[nz] == 0)
+
+
+def test_inviscid_energy_error_is_fourth_order_in_dt():
+    """With nu = nu_t = 0 the divergence-form advection conserves energy on a uniform
+    periodic grid when D u = 0 (Sec. 1: energy preserving in the inviscid limit); the only
+    error left is the RK3 one, O(dt^4) per step: halving dt cuts it by ~16x."""
+    n = 12
+    case = Case(n, n, n, 2 * np.pi, 2 * np.pi, 2 * np.pi, zbc=ZBC_PERIODIC, nu=0.0)
+    g = Grid(case)
+    u, v, w = isotropic_field(n, seed=5, k0=2.0)
+    st0 = S.initial_state(case, g, u, v, w)
+    st0 = S.substep(case, g, st0, 0, 1e-6)          # project to discrete divergence-free
+    st0.p[:] = 0.0
+    st0.rprev = None
+    I = slice(1, n + 1)
+    # Spatial pin: sum u . C(u) = 0 exactly for the projected field
+    ax, ay, az = ops.advection(g, st0.u, st0.v, st0.w)
+    dot = np.sum(st0.u[I] * ax) + np.sum(st0.v[I] * ay) + np.sum(st0.w[I] * az)
+    assert abs(dot) < 1e-12 * np.sum(st0.u[I] ** 2)
+    E = lambda st: np.sum(st.u[I] ** 2 + st.v[I] ** 2 + st.w[I] ** 2)
+    errs = []
+    for dt in (0.08, 0.04):
+        st = _step(case, g, st0.copy(), dt)
+        errs.append(abs(E(st) - E(st0)) / E(st0))
+    assert 10.0 < errs[0] / errs[1] < 24.0
+
+
+@pytest.mark.parametrize("implicit", [True, False])
+def test_poiseuille_discrete_steady_state(implicit):
+    """Laminar channel with constant flow rate and no model: the solution of the 1-D discrete
+    problem nu L_zz U = -f, sum(U dzf) = U_b lz (solved directly as a bordered linear system)
+    is a fixed point of the RK3 substep (explicit and CN in z), and it matches the parabola
+    1.5 U_b (1 - (z-1)^2) to O(dz^2)."""
+    nz = 16
+    case = Case(4, 4, nz, 1.0, 1.0, 2.0, zbc=ZBC_NOSLIP, beta=1.2, nu=0.5, sgs=SGS_NONE,
+                implicit_z=implicit, ubulk=1.0)
+    g = Grid(case)
+    A = np.zeros((nz + 1, nz + 1))
+    for c in range(nz):
+        a = np.zeros((nz + 2, 1, 1))
+        a[c + 1] = 1.0
+        a[0], a[nz + 1] = -a[1], -a[nz]
+        A[:nz, c] = case.nu * S.ops.lap_z_centre(g, a)[:, 0, 0]
+    A[:nz, nz] = 1.0
+    A[nz, :nz] = g.dzf[1:nz + 1]
+    rhs = np.zeros(nz + 1)
+    rhs[nz] = 1.0 * 2.0
+    sol = np.linalg.solve(A, rhs)[:nz]
+    u = np.zeros((nz + 2, 4, 4))
+    u[1:nz + 1] = sol[:, None, None]
+    st = S.initial_state(case, g, u, np.zeros_like(u), np.zeros_like(u))
+    dt = 0.5 * S.time_step(case, g, st)
+    for _ in range(5):
+        st = _step(case, g, st, dt)
+    assert np.max(np.abs(st.u[1:nz + 1] - sol[:, None, None])) < 1e-12
+    assert np.max(np.abs(st.v)) < 1e-13 and np.max(np.abs(st.w)) < 1e-13
+    z = g.zc[1:nz + 1]
+    assert np.max(np.abs(sol - 1.5 * (1 - (z - 1) ** 2))) < 0.05
+    # a perturbed profile is not a fixed point (the check above has teeth)
+    u2 = u.copy()
+    u2[3] += 1e-3
+    st2 = _step(case, g, S.initial_state(case, g, u2, np.zeros_like(u), np.zeros_like(u)), dt)
+    assert np.max(np.abs(st2.u[1:nz + 1] - u2[1:nz + 1])) > 1e-6
+
+
+def test_time_step_limits():
+    n = 8
+    case = Case(n, n, n, 2 * np.pi, 2 * np.pi, 2 * np.pi, zbc=ZBC_PERIODIC, nu=1e-3, sgs=SGS_SMAG)
+    g = Grid(case)
+    u = np.zeros((n + 2, n, n)) + 2.0
+    st = S.initial_state(case, g, u, np.zeros_like(u), np.zeros_like(u))
+    assert abs(S.time_step(case, g, st, cfl=0.5) - 0.5 * g.dx / 2.0) < 1e-15
+    case2 = Case(n, n, n, 2 * np.pi, 2 * np.pi, 2 * np.pi, zbc=ZBC_PERIODIC, nu=10.0)
+    st2 = S.initial_state(case2, g, np.zeros_like(u), np.zeros_like(u), np.zeros_like(u))
+    assert abs(S.time_step(case2, g, st2) - 0.95 * 2.51 / (4 * 10.0 * 3 / g.dx ** 2)) < 1e-15
