@@ -1,0 +1,200 @@
+/*
+ * les.h - C ABI of the MI355X large-eddy-simulation substep library.
+ *
+ * The library advances the filtered incompressible Navier-Stokes equations by one
+ * low-storage third-order Runge-Kutta substep on a staggered (MAC) finite-difference
+ * grid, as described in Xiao et al., "CaLES: A GPU-accelerated solver for large-eddy
+ * simulation of wall-bounded flows" (arXiv 2411.09364):
+ *   predictor            Sec. 2.2, Eq. onestar_exp (explicit viscous terms) or
+ *                        Eqs. twostar_imp1d, onestar_imp1d (Crank-Nicolson in z)
+ *   pressure Poisson     Eq. poi, solved by eigenfunction expansion: FFTs in the periodic
+ *                        x and y directions, tridiagonal (Thomas) solves along the
+ *                        non-uniform z direction (Sec. 2.2)
+ *   projection           Eqs. correc, p_update_exp / p_update_imp1d
+ *   eddy viscosity       Sec. 2.1: Smagorinsky with optional van Driest damping (Eq. smag),
+ *                        dynamic Smagorinsky (Eqs. dsmag, cs, lij, mij), or a learned
+ *                        coefficient network
+ *   wall model           Sec. 2.1 Eq. wm (log law) with the coupling of Sec. 2.2
+ *   boundary order       Alg. 2; substep order Alg. 1
+ *
+ * Axes: x and y periodic; z either periodic or bounded by walls at z = 0 and z = lz.
+ * (The paper calls the wall-normal direction y; here it is z, the solver's stretched axis.)
+ *
+ * Memory: every device buffer is allocated by the caller (the library never allocates
+ * device memory) and must stay valid while the context uses it.  Fields are dense
+ * arrays of shape [nz + 2][ny][nx] (x fastest) in the storage type reported by
+ * les_layout (double for LES_FP64, float for LES_MIXED).  Planes 0 and nz + 1 are ghost
+ * planes.  Face positions: u[k][j][i] at x = (i+1) dx, y = (j+1/2) dy, z = zc[k];
+ * v at ((i+1/2) dx, (j+1) dy, zc[k]); w at ((i+1/2) dx, (j+1/2) dy, zf[k]) where zf[k] is
+ * the top face of cell k (zf[0] = 0, zf[nz] = lz); p at cell centres.
+ *
+ * Streams: all device work is enqueued on the HIP stream given to les_init, in order,
+ * without synchronising, unless a function says it synchronises.  A context is not
+ * thread-safe.  Asynchronous device faults surface as LES_EDEVICE at the next
+ * synchronising call.
+ *
+ * Errors: every function returns les_status and never aborts.  Arguments are validated
+ * before any device work is enqueued; on error nothing is enqueued and les_last_error
+ * describes the problem.
+ */
+#ifndef LES_H
+#define LES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LES_ABI_VERSION 1
+
+typedef enum {
+  LES_OK = 0,
+  LES_EINVAL = -1,      /* invalid argument or configuration                         */
+  LES_ENOMEM = -2,      /* caller buffer too small                                   */
+  LES_EDEVICE = -3,     /* HIP runtime error (launch failure, earlier fault, ...)    */
+  LES_ENOTSUP = -4,     /* valid but unsupported combination (e.g. FFT length)       */
+  LES_ENONFINITE = -5,  /* non-finite value detected in the state                    */
+  LES_ESTATE = -6       /* call out of order (e.g. field not bound)                  */
+} les_status;
+
+enum { LES_ZBC_PERIODIC = 0, LES_ZBC_NOSLIP = 1, LES_ZBC_WALLMODEL = 2 };
+enum { LES_SGS_NONE = 0, LES_SGS_SMAG = 1, LES_SGS_SMAG_VD = 2, LES_SGS_DSM = 3, LES_SGS_MLP = 4 };
+enum { LES_FP64 = 0, LES_MIXED = 1 };
+
+typedef struct les_ctx les_ctx;   /* opaque, owned by the library */
+
+/* Problem description.  Plain data, copied by les_init. */
+typedef struct {
+  int32_t abi_version;  /* must be LES_ABI_VERSION                                        */
+  int32_t nx, ny, nz;   /* cells; nx, ny even, of the form 2^a or 3 * 2^a, 8..1024;
+                           4 <= nz <= 512 (wall-bounded) or, when z is periodic, of that form   */
+  double lx, ly, lz;    /* box lengths (> 0)                                             */
+  int32_t zbc;          /* LES_ZBC_*                                                     */
+  double beta;          /* tanh wall clustering (wall-bounded z); 0 = uniform            */
+  double nu;            /* kinematic viscosity (> 0)                                     */
+  int32_t sgs;          /* LES_SGS_*                                                     */
+  double cs;            /* Smagorinsky constant for LES_SGS_SMAG / _SMAG_VD              */
+  int32_t implicit_z;   /* 0: explicit viscous terms; 1: Crank-Nicolson in z (walls only) */
+  int32_t precision;    /* LES_FP64, or LES_MIXED: float storage, stencils and FFTs,
+                           double tridiagonal solves, zero mode and reductions           */
+  double ubulk;         /* > 0: constant flow rate (bulk velocity) in x; 0: off          */
+  double h_wm;          /* wall-model height; 0 = first off-wall cell centre            */
+  double kappa, bconst; /* log-law constants (Eq. wm); 0 selects 0.41 and 5.2            */
+} les_config;
+
+/* Bindable and readable buffers. */
+enum {
+  LES_FIELD_U = 0, LES_FIELD_V = 1, LES_FIELD_W = 2, LES_FIELD_P = 3,
+  LES_FIELD_WORKSPACE = 4,  /* scratch + internal state (RK history, |S|, spectra, ...) */
+  LES_FIELD_NUT = 5,        /* readable only: eddy viscosity at cell centres, field layout */
+  LES_FIELD_CS = 6,         /* readable only: per-plane model coefficient, double[nz]      */
+  LES_FIELD_TAUW = 7,       /* readable only: wall stress, double[4][ny][nx]:
+                               tau_x bottom, tau_y bottom, tau_x top, tau_y top            */
+  LES_FIELD_ZGRID = 8       /* readable only, host memory: double zf[nz+1], zc[nz+2]       */
+};
+
+typedef struct {
+  int64_t nx, ny, nz;        /* interior cells                                     */
+  int64_t dims[3];           /* [nz+2, ny, nx] for fields                          */
+  int64_t elem_bytes;        /* 8 (double) or 4 (float) for fields                 */
+  int64_t bytes;             /* total bytes required for the requested buffer      */
+} les_layout_t;
+
+/* Diagnostics (les_diag synchronises the stream). */
+typedef struct {
+  double max_div;            /* max |D u| over cells                                 */
+  double ubulk;              /* volume-mean u                                        */
+  double max_vel;            /* max |u|, |v|, |w|                                    */
+  double tauw_mean[2];       /* plane-mean tau_x at bottom / top wall (wall model)   */
+  double dt;                 /* current time step in the device slot                 */
+  int64_t nonfinite;         /* count of non-finite values in u, v, w, p             */
+  int64_t mlp_flagged;       /* learned closure: points that fell back last call     */
+} les_diag_t;
+
+/* Validate cfg, compute the grid metrics and solver tables on the host, and create a
+ * context bound to hip_stream (a hipStream_t, NULL = default stream).  No device work
+ * is done.  On error *out is NULL. */
+les_status les_init(const les_config* cfg, void* hip_stream, les_ctx** out);
+
+/* Size and shape of a bindable or readable buffer (LES_FIELD_*). */
+les_status les_layout(const les_ctx* ctx, int field, les_layout_t* out);
+
+/* Bind caller-owned device memory to LES_FIELD_U/V/W/P or LES_FIELD_WORKSPACE.  The
+ * pointer must be 256-byte aligned and hold les_layout(field).bytes.  Binding the
+ * workspace enqueues the upload of the solver tables (grid metrics, eigenvalues,
+ * twiddles) and zeroes the internal state. */
+les_status les_bind(les_ctx* ctx, int field, void* device_ptr);
+
+/* Alg. 1, line 2 and Alg. 2: fill the ghost planes of u, v, w, p, evaluate the wall
+ * model (zbc = WALLMODEL) and the eddy viscosity from the bound velocity.  Must be called
+ * once after the initial fields are written and before the first substep. */
+les_status les_nut(les_ctx* ctx);
+
+/* Time step: Courant-limited (cfl times the inverse of max |u|/dx + |v|/dy + |w|/dzf)
+ * and viscous-limited (0.95 * 2.51 / (4 max(nu + nu_t) sum 1/h^2), z term dropped with
+ * CN in z), the minimum of the two, written to the context's device time-step slot.  If
+ * dt_host is not NULL the stream is synchronised and the value returned there. */
+les_status les_dt(les_ctx* ctx, double cfl, double* dt_host);
+
+/* Write dt into the device time-step slot (enqueued; no synchronisation). */
+les_status les_set_dt(les_ctx* ctx, double dt);
+
+/* One RK3 substep, stage = 0, 1, 2 (Alg. 1 inner loop body): predictor, optional CN-z
+ * Helmholtz solves, Poisson solve, correction, pressure update, flow-rate forcing,
+ * boundary conditions, wall model and eddy viscosity of the new velocity.  Uses the
+ * time step in the device slot. */
+les_status les_substep(les_ctx* ctx, int stage);
+
+/* Three substeps.  use_graph != 0 records them once into a hipGraph on first use and
+ * replays it afterwards (the time step is read from the device slot, so replays see
+ * the current value). */
+les_status les_step(les_ctx* ctx, int use_graph);
+
+/* Solve D(G phi) = f (Eq. poi's discrete operator, zero-flux walls or periodic z) in
+ * place: f_inout is a device buffer in field layout (storage type of the context); on
+ * return its interior holds phi with zero dzf-weighted mean and its ghost planes are
+ * filled.  Uses the workspace. */
+les_status les_poisson(les_ctx* ctx, void* f_inout);
+
+/* Copy a readable quantity (LES_FIELD_NUT, _CS, _TAUW to device memory dst; _ZGRID to
+ * host memory dst).  Enqueued, except _ZGRID which is immediate. */
+les_status les_read(les_ctx* ctx, int field, void* dst);
+
+/* Synchronise and compute diagnostics. */
+les_status les_diag(les_ctx* ctx, les_diag_t* out);
+
+/* Learned closure (sgs = LES_SGS_MLP, or training alongside any model).
+ * Parameters: 4737 floats in the order W1[64][7], b1[64], W2[64][64], b2[64], W3[1][64],
+ * b3[1] (float32 master copy, device memory owned by the caller); lo/hi: the 7 feature
+ * ranges for min-max scaling (host, copied).  Inference rounds W1, W2 and the layer
+ * inputs to bfloat16 and accumulates in float32; points whose scaled features leave
+ * [-0.05, 1.05] take the plane coefficient of the dynamic model instead. */
+les_status les_mlp_bind(les_ctx* ctx, float* params_dev, const double* lo, const double* hi);
+
+/* Gather training pairs at the current state: for n_samples cells chosen by a
+ * counter-based hash of (seed, sample index), write the 7 scaled features to x_dev
+ * (float[n][7]) and the dynamic-model coefficient of the cell's plane to y_dev
+ * (float[n]).  Requires the dynamic model's coefficient (sgs = DSM). */
+les_status les_mlp_sample(les_ctx* ctx, uint64_t seed, int64_t n_samples,
+                          float* x_dev, float* y_dev);
+
+/* One Adam step on the mean-squared error over n samples (x_dev float[n][7], y_dev
+ * float[n]); m_dev, v_dev: float[4737] moments; step: 1-based Adam counter; loss_dev:
+ * one float receiving the loss before the update.  Forward and backward run on the
+ * matrix cores in bfloat16 with float32 accumulation. */
+les_status les_mlp_train_step(les_ctx* ctx, const float* x_dev, const float* y_dev,
+                              int64_t n, float lr, int step, float* m_dev, float* v_dev,
+                              float* loss_dev);
+
+/* Destroy the context (does not free caller memory). */
+les_status les_free(les_ctx* ctx);
+
+const char* les_strerror(les_status s);
+const char* les_last_error(const les_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LES_H */

@@ -1,0 +1,578 @@
+// C ABI of the substep library (declarations and argument contracts in include/les.h):
+// validation, host-side grid metrics and solver tables, workspace carving, and the
+// kernel schedule of one RK3 substep (Alg. 1) with the boundary order of Alg. 2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "les_internal.h"
+
+using namespace les;
+
+struct les_ctx {
+  Ctx c;
+};
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+bool fft_size_ok(int n) {
+  if (n < 4 || n > 1024) return false;
+  int m = n;
+  if (m % 3 == 0) m /= 3;
+  while (m % 2 == 0) m /= 2;
+  return m == 1;
+}
+
+les_status fail(Ctx* c, les_status s, const char* msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+les_status check_hip(Ctx& c, hipError_t e, const char* where) {
+  if (e == hipSuccess) return LES_OK;
+  c.err = std::string(where) + ": " + hipGetErrorString(e);
+  return LES_EDEVICE;
+}
+
+les_status check_launch(Ctx& c, const char* where) {
+  return check_hip(c, hipGetLastError(), where);
+}
+
+// Wall-normal faces: uniform, or tanh clustering zf(k) = (lz/2)[1 + tanh(beta(2k/nz - 1))/tanh(beta)]
+// made exactly mirror-symmetric (the lower half is snapped so that lz - zf is exact).
+void build_grid(Ctx& c) {
+  const les_config& f = c.cfg;
+  const int n = f.nz;
+  c.zf.assign(n + 1, 0.0);
+  const bool stretch = f.zbc != LES_ZBC_PERIODIC && f.beta > 0.0;
+  for (int k = 0; k <= n; ++k) {
+    if (stretch)
+      c.zf[k] = 0.5 * f.lz * (1.0 + std::tanh(f.beta * (2.0 * k / n - 1.0)) / std::tanh(f.beta));
+    else
+      c.zf[k] = f.lz * k / n;
+  }
+  if (stretch) {
+    for (int k = 0; k < (n + 1) / 2; ++k) {
+      const double b = f.lz - c.zf[k];
+      c.zf[n - k] = b;
+      c.zf[k] = f.lz - b;
+    }
+    if (n % 2 == 0) c.zf[n / 2] = 0.5 * f.lz;
+  }
+  c.zf[0] = 0.0;
+  c.zf[n] = f.lz;
+  c.zc.assign(n + 2, 0.0);
+  c.dzf.assign(n + 2, 0.0);
+  for (int k = 1; k <= n; ++k) {
+    c.zc[k] = 0.5 * (c.zf[k - 1] + c.zf[k]);
+    c.dzf[k] = c.zf[k] - c.zf[k - 1];
+  }
+  if (f.zbc == LES_ZBC_PERIODIC) {
+    c.zc[0] = c.zc[n] - f.lz;
+    c.zc[n + 1] = c.zc[1] + f.lz;
+    c.dzf[0] = c.dzf[n];
+    c.dzf[n + 1] = c.dzf[1];
+  } else {
+    c.zc[0] = -c.zc[1];
+    c.zc[n + 1] = 2.0 * f.lz - c.zc[n];
+    c.dzf[0] = c.dzf[1];
+    c.dzf[n + 1] = c.dzf[n];
+  }
+  c.dzc.assign(n + 2, 0.0);
+  for (int k = 0; k <= n; ++k) c.dzc[k] = c.zc[k + 1] - c.zc[k];
+  c.dzc[n + 1] = c.dzc[n];
+  const double dx = f.lx / f.nx, dy = f.ly / f.ny;
+  c.delta2.assign(n + 2, 0.0);
+  for (int k = 0; k <= n + 1; ++k) {
+    const double d = std::pow(dx * dy * c.dzf[k], 1.0 / 3.0);
+    c.delta2[k] = d * d;
+  }
+  // Poisson rows of D G along z (zero flux through walls)
+  c.pa.assign(n, 0.0);
+  c.pb.assign(n, 0.0);
+  c.pc.assign(n, 0.0);
+  for (int k = 1; k <= n; ++k) {
+    double a = 1.0 / (c.dzc[k - 1] * c.dzf[k]);
+    double cc = 1.0 / (c.dzc[k] * c.dzf[k]);
+    if (f.zbc != LES_ZBC_PERIODIC) {
+      if (k == 1) a = 0.0;
+      if (k == n) cc = 0.0;
+    }
+    c.pa[k - 1] = a;
+    c.pc[k - 1] = cc;
+    c.pb[k - 1] = -(a + cc);
+  }
+  // eigenvalues of the periodic second difference, -(4/h^2) sin^2(pi l/n)
+  auto eig = [](int nn, double h, int l) {
+    const double s = std::sin(kPi * l / nn);
+    return -(4.0 / (h * h)) * s * s;
+  };
+  c.lamx.resize(f.nx / 2 + 1);
+  for (int l = 0; l <= f.nx / 2; ++l) c.lamx[l] = eig(f.nx, dx, l);
+  c.lamy.resize(f.ny);
+  for (int m = 0; m < f.ny; ++m) c.lamy[m] = eig(f.ny, dy, m);
+  c.lamz.assign(n, 0.0);
+  if (f.zbc == LES_ZBC_PERIODIC)
+    for (int q = 0; q < n; ++q) c.lamz[q] = eig(n, f.lz / n, q);
+  auto tw = [](int nn, std::vector<double>& t) {
+    t.resize(2 * nn);
+    for (int q = 0; q < nn; ++q) {
+      t[2 * q] = std::cos(2.0 * kPi * q / nn);
+      t[2 * q + 1] = std::sin(2.0 * kPi * q / nn);
+    }
+  };
+  tw(f.nx, c.twx);
+  tw(f.ny, c.twy);
+  tw(n, c.twz);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace layout.  With base == nullptr only the size is computed.
+size_t carve(Ctx& c, char* base) {
+  const les_config& f = c.cfg;
+  const int n = f.nz;
+  const size_t F = c.field_elems, E = c.elem;
+  const int64_t sxy = (int64_t)f.nx * f.ny;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = align256(off + bytes);
+    return p;
+  };
+  Tables& t = c.t;
+  t.zc = (double*)take((n + 2) * 8);
+  t.dzf = (double*)take((n + 2) * 8);
+  t.dzc = (double*)take((n + 2) * 8);
+  t.delta2 = (double*)take((n + 2) * 8);
+  t.coef = (double*)take((n + 2) * 8);
+  t.cs = (double*)take(n * 8);
+  t.pa = (double*)take(n * 8);
+  t.pb = (double*)take(n * 8);
+  t.pc = (double*)take(n * 8);
+  t.lamx = (double*)take((f.nx / 2 + 1) * 8);
+  t.lamy = (double*)take(f.ny * 8);
+  t.lamz = (double*)take(n * 8);
+  t.twx = (double*)take(2 * f.nx * 8);
+  t.twy = (double*)take(2 * f.ny * 8);
+  t.twz = (double*)take(2 * n * 8);
+  t.twx_f = (float*)take(2 * f.nx * 4);
+  t.twy_f = (float*)take(2 * f.ny * 4);
+  t.twz_f = (float*)take(2 * n * 4);
+  t.hfac = (double*)take(6 * n * 8);
+  t.dt = (double*)take(16 * 8);
+  t.red_n = 4096;
+  t.red = (double*)take(t.red_n * 8);
+  const int64_t npairs = (int64_t)n * (f.ny / 2);
+  t.bulk = (double*)take((size_t)std::max<int64_t>(npairs, 1) * 8);
+  t.zcol = (double*)take(3 * n * 8);
+  t.tau = (double*)take(4 * sxy * 8);
+  t.utau = (double*)take(4 * sxy * 8);
+  Launch3 L = point_launch(c.g, n);
+  t.nblk_xy = (int)(L.grid.x * L.grid.y);
+  t.dsm_part = (double*)take((size_t)2 * n * t.nblk_xy * 8);
+  c.ru = take(F * E);
+  c.rv = take(F * E);
+  c.rw = take(F * E);
+  c.us = take(F * E);
+  c.vs = take(F * E);
+  c.wsf = take(F * E);
+  c.nut = take(F * E);
+  c.phi = take(F * E);
+  c.spec = take((size_t)(f.nx / 2 + 1) * f.ny * n * 2 * E);
+  if (f.sgs == LES_SGS_DSM || f.sgs == LES_SGS_MLP) {
+    c.q9 = take(9 * F * E);
+    c.fvel = take(3 * F * E);
+  } else {
+    c.q9 = c.fvel = nullptr;
+  }
+  return off;
+}
+
+template <typename T>
+les_status substep_body(Ctx& c, int stage) {
+  static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
+  launch_predictor<T>(c, stage);
+  if (c.cfg.implicit_z) launch_helmholtz<T>(c, stage);
+  launch_poisson_rhs_fwd<T>(c, (const T*)c.us, (const T*)c.vs, (const T*)c.wsf, G[stage], stage);
+  launch_poisson_solve_spectral<T>(c);
+  launch_poisson_inverse<T>(c, (T*)c.phi);
+  launch_correct<T>(c, stage);
+  if (c.cfg.zbc == LES_ZBC_WALLMODEL) launch_wallmodel<T>(c);
+  launch_eddy_viscosity<T>(c);
+  return check_launch(c, "les_substep");
+}
+
+les_status substep_any(Ctx& c, int stage) {
+  return c.cfg.precision == LES_MIXED ? substep_body<float>(c, stage) : substep_body<double>(c, stage);
+}
+
+les_status ready(Ctx& c, bool need_init) {
+  if (!c.u || !c.v || !c.w || !c.p || !c.ws) return fail(&c, LES_ESTATE, "fields and workspace must be bound");
+  if (need_init && !c.initialised) return fail(&c, LES_ESTATE, "les_nut must be called before stepping");
+  return LES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* les_strerror(les_status s) {
+  switch (s) {
+    case LES_OK: return "ok";
+    case LES_EINVAL: return "invalid argument";
+    case LES_ENOMEM: return "buffer too small";
+    case LES_EDEVICE: return "device error";
+    case LES_ENOTSUP: return "unsupported configuration";
+    case LES_ENONFINITE: return "non-finite state";
+    case LES_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* les_last_error(const les_ctx* ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+les_status les_init(const les_config* cfg, void* hip_stream, les_ctx** out) {
+  if (!out) return LES_EINVAL;
+  *out = nullptr;
+  if (!cfg) return LES_EINVAL;
+  if (cfg->abi_version != LES_ABI_VERSION) return LES_EINVAL;
+  const les_config& f = *cfg;
+  if (!fft_size_ok(f.nx) || !fft_size_ok(f.ny) || f.nx % 2 || f.ny % 2) return LES_ENOTSUP;
+  if (f.zbc < 0 || f.zbc > 2) return LES_EINVAL;
+  if (f.zbc == LES_ZBC_PERIODIC) {
+    if (!fft_size_ok(f.nz)) return LES_ENOTSUP;
+  } else if (f.nz < 4 || f.nz > 512) {
+    return LES_EINVAL;
+  }
+  auto pos = [](double x) { return std::isfinite(x) && x > 0.0; };
+  if (!pos(f.lx) || !pos(f.ly) || !pos(f.lz) || !pos(f.nu)) return LES_EINVAL;
+  if (!(std::isfinite(f.beta) && f.beta >= 0.0 && f.beta < 20.0)) return LES_EINVAL;
+  if (f.sgs < 0 || f.sgs > 4) return LES_EINVAL;
+  if (!(std::isfinite(f.cs) && f.cs >= 0.0)) return LES_EINVAL;
+  if (f.implicit_z != 0 && f.implicit_z != 1) return LES_EINVAL;
+  if (f.implicit_z && f.zbc == LES_ZBC_PERIODIC) return LES_ENOTSUP;
+  if (f.precision != LES_FP64 && f.precision != LES_MIXED) return LES_EINVAL;
+  if (!(std::isfinite(f.ubulk) && f.ubulk >= 0.0)) return LES_EINVAL;
+  if (!(std::isfinite(f.h_wm) && f.h_wm >= 0.0)) return LES_EINVAL;
+  if (!(std::isfinite(f.kappa) && f.kappa >= 0.0) || !std::isfinite(f.bconst)) return LES_EINVAL;
+  les_ctx* h = new (std::nothrow) les_ctx();
+  if (!h) return LES_ENOMEM;
+  Ctx& c = h->c;
+  c.cfg = f;
+  if (c.cfg.kappa == 0.0) c.cfg.kappa = 0.41;
+  if (c.cfg.bconst == 0.0) c.cfg.bconst = 5.2;
+  c.stream = (hipStream_t)hip_stream;
+  c.elem = f.precision == LES_MIXED ? 4 : 8;
+  c.field_elems = (size_t)(f.nz + 2) * f.ny * f.nx;
+  build_grid(c);
+  if (f.zbc == LES_ZBC_WALLMODEL && f.h_wm > 0.0) {
+    if (f.h_wm < c.zc[1] || f.h_wm > c.zc[f.nz / 2]) {
+      delete h;
+      return LES_EINVAL;
+    }
+  }
+  GridP& g = c.g;
+  g.nx = f.nx;
+  g.ny = f.ny;
+  g.nz = f.nz;
+  g.zbc = f.zbc;
+  g.sxy = (int64_t)f.nx * f.ny;
+  g.dx = f.lx / f.nx;
+  g.dy = f.ly / f.ny;
+  g.rdx = 1.0 / g.dx;
+  g.rdy = 1.0 / g.dy;
+  g.lz = f.lz;
+  g.nu = f.nu;
+  c.ws_bytes = carve(c, nullptr);
+  *out = h;
+  return LES_OK;
+}
+
+les_status les_layout(const les_ctx* ctx, int field, les_layout_t* out) {
+  if (!ctx || !out) return LES_EINVAL;
+  const Ctx& c = ctx->c;
+  const les_config& f = c.cfg;
+  std::memset(out, 0, sizeof(*out));
+  out->nx = f.nx;
+  out->ny = f.ny;
+  out->nz = f.nz;
+  out->dims[0] = f.nz + 2;
+  out->dims[1] = f.ny;
+  out->dims[2] = f.nx;
+  out->elem_bytes = (int64_t)c.elem;
+  switch (field) {
+    case LES_FIELD_U: case LES_FIELD_V: case LES_FIELD_W: case LES_FIELD_P: case LES_FIELD_NUT:
+      out->bytes = (int64_t)(c.field_elems * c.elem);
+      return LES_OK;
+    case LES_FIELD_WORKSPACE:
+      out->bytes = (int64_t)c.ws_bytes;
+      out->elem_bytes = 1;
+      return LES_OK;
+    case LES_FIELD_CS:
+      out->bytes = 8LL * f.nz;
+      out->elem_bytes = 8;
+      return LES_OK;
+    case LES_FIELD_TAUW:
+      out->bytes = 8LL * 4 * f.nx * f.ny;
+      out->elem_bytes = 8;
+      return LES_OK;
+    case LES_FIELD_ZGRID:
+      out->bytes = 8LL * (2 * f.nz + 3);
+      out->elem_bytes = 8;
+      return LES_OK;
+  }
+  return LES_EINVAL;
+}
+
+les_status les_bind(les_ctx* ctx, int field, void* ptr) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  if (!ptr) return fail(&c, LES_EINVAL, "null pointer");
+  if (((uintptr_t)ptr) & 255) return fail(&c, LES_EINVAL, "pointer must be 256-byte aligned");
+  switch (field) {
+    case LES_FIELD_U: c.u = ptr; break;
+    case LES_FIELD_V: c.v = ptr; break;
+    case LES_FIELD_W: c.w = ptr; break;
+    case LES_FIELD_P: c.p = ptr; break;
+    case LES_FIELD_WORKSPACE: {
+      c.ws = ptr;
+      carve(c, (char*)ptr);
+      GridP& g = c.g;
+      g.zc = c.t.zc;
+      g.dzf = c.t.dzf;
+      g.dzc = c.t.dzc;
+      g.delta2 = c.t.delta2;
+      const les_config& f = c.cfg;
+      const int n = f.nz;
+      les_status s = check_hip(c, hipMemsetAsync(ptr, 0, c.ws_bytes, c.stream), "zero workspace");
+      if (s != LES_OK) return s;
+      auto up = [&](void* dst, const void* src, size_t bytes) {
+        return check_hip(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.stream), "upload tables");
+      };
+      // host staging kept in the context so the asynchronous copies stay valid
+      c.twx_f_host.clear();
+      for (double x : c.twx) c.twx_f_host.push_back((float)x);
+      c.twy_f_host.clear();
+      for (double x : c.twy) c.twy_f_host.push_back((float)x);
+      c.twz_f_host.clear();
+      for (double x : c.twz) c.twz_f_host.push_back((float)x);
+      c.coef_host.assign(n + 2, 0.0);
+      if (f.sgs == LES_SGS_SMAG || f.sgs == LES_SGS_SMAG_VD)
+        for (int k = 0; k <= n + 1; ++k) {
+          const double d = std::pow((f.lx / f.nx) * (f.ly / f.ny) * c.dzf[k], 1.0 / 3.0);
+          c.coef_host[k] = (f.cs * d) * (f.cs * d);
+        }
+      c.hfac_host.assign(6 * n, 0.0);
+      for (int k = 0; k < n; ++k) c.hfac_host[4 * n + k] = 1.0;
+      if ((s = up(c.t.zc, c.zc.data(), (n + 2) * 8)) != LES_OK) return s;
+      if ((s = up(c.t.dzf, c.dzf.data(), (n + 2) * 8)) != LES_OK) return s;
+      if ((s = up(c.t.dzc, c.dzc.data(), (n + 2) * 8)) != LES_OK) return s;
+      if ((s = up(c.t.delta2, c.delta2.data(), (n + 2) * 8)) != LES_OK) return s;
+      if ((s = up(c.t.coef, c.coef_host.data(), (n + 2) * 8)) != LES_OK) return s;
+      if ((s = up(c.t.pa, c.pa.data(), n * 8)) != LES_OK) return s;
+      if ((s = up(c.t.pb, c.pb.data(), n * 8)) != LES_OK) return s;
+      if ((s = up(c.t.pc, c.pc.data(), n * 8)) != LES_OK) return s;
+      if ((s = up(c.t.lamx, c.lamx.data(), c.lamx.size() * 8)) != LES_OK) return s;
+      if ((s = up(c.t.lamy, c.lamy.data(), c.lamy.size() * 8)) != LES_OK) return s;
+      if ((s = up(c.t.lamz, c.lamz.data(), c.lamz.size() * 8)) != LES_OK) return s;
+      if ((s = up(c.t.twx, c.twx.data(), c.twx.size() * 8)) != LES_OK) return s;
+      if ((s = up(c.t.twy, c.twy.data(), c.twy.size() * 8)) != LES_OK) return s;
+      if ((s = up(c.t.twz, c.twz.data(), c.twz.size() * 8)) != LES_OK) return s;
+      if ((s = up(c.t.twx_f, c.twx_f_host.data(), c.twx_f_host.size() * 4)) != LES_OK) return s;
+      if ((s = up(c.t.twy_f, c.twy_f_host.data(), c.twy_f_host.size() * 4)) != LES_OK) return s;
+      if ((s = up(c.t.twz_f, c.twz_f_host.data(), c.twz_f_host.size() * 4)) != LES_OK) return s;
+      if ((s = up(c.t.hfac, c.hfac_host.data(), c.hfac_host.size() * 8)) != LES_OK) return s;
+      c.initialised = false;
+      if (c.graph_exec) {
+        hipGraphExecDestroy(c.graph_exec);
+        c.graph_exec = nullptr;
+      }
+      if (c.graph) {
+        hipGraphDestroy(c.graph);
+        c.graph = nullptr;
+      }
+      break;
+    }
+    default:
+      return fail(&c, LES_EINVAL, "field is not bindable");
+  }
+  return LES_OK;
+}
+
+les_status les_nut(les_ctx* ctx) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  les_status s = ready(c, false);
+  if (s != LES_OK) return s;
+  if (c.cfg.precision == LES_MIXED) {
+    launch_bc_fill<float>(c, (float*)c.u, (float*)c.v, (float*)c.w, (float*)c.p);
+    if (c.cfg.zbc == LES_ZBC_WALLMODEL) launch_wallmodel<float>(c);
+    launch_eddy_viscosity<float>(c);
+  } else {
+    launch_bc_fill<double>(c, (double*)c.u, (double*)c.v, (double*)c.w, (double*)c.p);
+    if (c.cfg.zbc == LES_ZBC_WALLMODEL) launch_wallmodel<double>(c);
+    launch_eddy_viscosity<double>(c);
+  }
+  s = check_launch(c, "les_nut");
+  if (s == LES_OK) c.initialised = true;
+  return s;
+}
+
+les_status les_dt(les_ctx* ctx, double cfl, double* dt_host) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  les_status s = ready(c, true);
+  if (s != LES_OK) return s;
+  if (!(std::isfinite(cfl) && cfl > 0.0)) return fail(&c, LES_EINVAL, "cfl must be positive");
+  if (c.cfg.precision == LES_MIXED) launch_dt<float>(c, cfl);
+  else launch_dt<double>(c, cfl);
+  if ((s = check_launch(c, "les_dt")) != LES_OK) return s;
+  if (dt_host) {
+    if ((s = check_hip(c, hipMemcpyAsync(dt_host, c.t.dt, 8, hipMemcpyDeviceToHost, c.stream), "dt copy")) != LES_OK)
+      return s;
+    if ((s = check_hip(c, hipStreamSynchronize(c.stream), "dt sync")) != LES_OK) return s;
+  }
+  return LES_OK;
+}
+
+les_status les_set_dt(les_ctx* ctx, double dt) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  if (!c.ws) return fail(&c, LES_ESTATE, "workspace not bound");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(&c, LES_EINVAL, "dt must be positive");
+  launch_set_dt(c, dt);
+  return check_launch(c, "les_set_dt");
+}
+
+les_status les_substep(les_ctx* ctx, int stage) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  les_status s = ready(c, true);
+  if (s != LES_OK) return s;
+  if (stage < 0 || stage > 2) return fail(&c, LES_EINVAL, "stage must be 0, 1 or 2");
+  return substep_any(c, stage);
+}
+
+les_status les_step(les_ctx* ctx, int use_graph) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  les_status s = ready(c, true);
+  if (s != LES_OK) return s;
+  if (!use_graph) {
+    for (int k = 0; k < 3; ++k)
+      if ((s = substep_any(c, k)) != LES_OK) return s;
+    return LES_OK;
+  }
+  if (!c.stream) return fail(&c, LES_EINVAL, "graph replay needs a non-default stream");
+  if (!c.graph_exec) {
+    if ((s = check_hip(c, hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal), "begin capture")) != LES_OK)
+      return s;
+    les_status body = LES_OK;
+    for (int k = 0; k < 3 && body == LES_OK; ++k) body = substep_any(c, k);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c.stream, &graph);
+    if (body != LES_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return body;
+    }
+    if ((s = check_hip(c, e, "end capture")) != LES_OK) return s;
+    c.graph = graph;
+    if ((s = check_hip(c, hipGraphInstantiate(&c.graph_exec, c.graph, nullptr, nullptr, 0), "instantiate")) != LES_OK)
+      return s;
+  }
+  return check_hip(c, hipGraphLaunch(c.graph_exec, c.stream), "graph launch");
+}
+
+les_status les_poisson(les_ctx* ctx, void* f) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  if (!c.ws) return fail(&c, LES_ESTATE, "workspace not bound");
+  if (!f) return fail(&c, LES_EINVAL, "null buffer");
+  if (c.cfg.precision == LES_MIXED) launch_poisson_field<float>(c, (float*)f);
+  else launch_poisson_field<double>(c, (double*)f);
+  return check_launch(c, "les_poisson");
+}
+
+les_status les_read(les_ctx* ctx, int field, void* dst) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  if (!dst) return fail(&c, LES_EINVAL, "null destination");
+  const les_config& f = c.cfg;
+  if (field == LES_FIELD_ZGRID) {
+    std::memcpy(dst, c.zf.data(), (f.nz + 1) * 8);
+    std::memcpy((double*)dst + f.nz + 1, c.zc.data(), (f.nz + 2) * 8);
+    return LES_OK;
+  }
+  if (!c.ws) return fail(&c, LES_ESTATE, "workspace not bound");
+  switch (field) {
+    case LES_FIELD_NUT:
+      if (f.precision == LES_MIXED) launch_read_nut<float>(c, (float*)dst);
+      else launch_read_nut<double>(c, (double*)dst);
+      return check_launch(c, "les_read");
+    case LES_FIELD_CS:
+      return check_hip(c, hipMemcpyAsync(dst, c.t.cs, 8 * f.nz, hipMemcpyDeviceToDevice, c.stream), "read cs");
+    case LES_FIELD_TAUW:
+      return check_hip(c, hipMemcpyAsync(dst, c.t.tau, 8 * 4 * c.g.sxy, hipMemcpyDeviceToDevice, c.stream),
+                       "read tau");
+  }
+  return fail(&c, LES_EINVAL, "field is not readable");
+}
+
+les_status les_diag(les_ctx* ctx, les_diag_t* out) {
+  if (!ctx || !out) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  les_status s = ready(c, false);
+  if (s != LES_OK) return s;
+  double* dev = c.t.red;
+  if (c.cfg.precision == LES_MIXED) launch_diag<float>(c, dev);
+  else launch_diag<double>(c, dev);
+  if ((s = check_launch(c, "les_diag")) != LES_OK) return s;
+  double h[8] = {0};
+  double dt = 0.0;
+  if ((s = check_hip(c, hipMemcpyAsync(h, dev, 6 * 8, hipMemcpyDeviceToHost, c.stream), "diag copy")) != LES_OK)
+    return s;
+  if ((s = check_hip(c, hipMemcpyAsync(&dt, c.t.dt, 8, hipMemcpyDeviceToHost, c.stream), "diag copy")) != LES_OK)
+    return s;
+  if ((s = check_hip(c, hipStreamSynchronize(c.stream), "diag sync")) != LES_OK) return s;
+  std::memset(out, 0, sizeof(*out));
+  out->max_div = h[0];
+  out->ubulk = h[1] / ((double)c.g.sxy * c.cfg.lz);
+  out->max_vel = h[2];
+  out->nonfinite = (int64_t)h[3];
+  out->tauw_mean[0] = h[4] / (double)c.g.sxy;
+  out->tauw_mean[1] = h[5] / (double)c.g.sxy;
+  out->dt = dt;
+  return out->nonfinite ? LES_ENONFINITE : LES_OK;
+}
+
+les_status les_mlp_bind(les_ctx* ctx, float*, const double*, const double*) {
+  if (!ctx) return LES_EINVAL;
+  return fail(&ctx->c, LES_ENOTSUP, "learned closure not built");
+}
+
+les_status les_mlp_sample(les_ctx* ctx, uint64_t, int64_t, float*, float*) {
+  if (!ctx) return LES_EINVAL;
+  return fail(&ctx->c, LES_ENOTSUP, "learned closure not built");
+}
+
+les_status les_mlp_train_step(les_ctx* ctx, const float*, const float*, int64_t, float, int, float*, float*, float*) {
+  if (!ctx) return LES_EINVAL;
+  return fail(&ctx->c, LES_ENOTSUP, "learned closure not built");
+}
+
+les_status les_free(les_ctx* ctx) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  if (c.graph_exec) hipGraphExecDestroy(c.graph_exec);
+  if (c.graph) hipGraphDestroy(c.graph);
+  delete ctx;
+  return LES_OK;
+}
+
+}  // extern "C"

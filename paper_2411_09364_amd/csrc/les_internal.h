@@ -1,0 +1,130 @@
+// Internal declarations shared by the library's HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/les.h"
+
+namespace les {
+
+// ---------------------------------------------------------------------------- grid
+// Plain-data view of the grid passed by value to every kernel.  Metric arrays live
+// in the workspace (device memory) and are indexed by plane k = 0..nz+1.
+struct GridP {
+  int nx, ny, nz;
+  int zbc;            // LES_ZBC_*
+  int64_t sxy;        // nx * ny
+  double dx, dy, rdx, rdy;
+  double lz, nu;
+  const double* zc;   // [nz+2]
+  const double* dzf;  // [nz+2]
+  const double* dzc;  // [nz+1]
+  const double* delta2;  // [nz+2] filter width squared per plane (ghosts copy neighbours)
+};
+
+__host__ __device__ inline int64_t idx3(const GridP& g, int k, int j, int i) {
+  return ((int64_t)k * g.ny + j) * g.nx + i;
+}
+__device__ inline int wrap_p(int i, int n) { return i + 1 == n ? 0 : i + 1; }
+__device__ inline int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+
+// Device-side tables carved out of the workspace.
+struct Tables {
+  double* zc;       // nz+2
+  double* dzf;      // nz+2
+  double* dzc;      // nz+1 (padded)
+  double* delta2;   // nz+2
+  double* coef;     // nz+2: nu_t = coef[k] * nut_field (see les.cpp)
+  double* cs;       // nz: dynamic coefficient per plane
+  double* pa;       // nz: Poisson z rows (lower)
+  double* pb;       // nz: (diagonal without eigenvalues)
+  double* pc;       // nz: (upper)
+  double* lamx;     // nx/2+1
+  double* lamy;     // ny
+  double* lamz;     // nz (periodic z)
+  double* twx;      // 2*nx : cos, sin pairs of exp(-2 pi i q/nx)
+  double* twy;      // 2*ny
+  double* twz;      // 2*nz
+  float* twx_f;     // float copies
+  float* twy_f;
+  float* twz_f;
+  double* hfac;     // 6*nz: CN-z factorisation (cp, rpiv) for u/v rows and w rows + q profile
+  double* dt;       // [0] time step; [1] bulk shift s; [2..] scratch scalars
+  double* red;      // reduction partials (size red_n)
+  double* bulk;     // flow-rate partial sums, one per forward-x block
+  double* zcol;     // 3*nz scratch of the singular (0, 0) Poisson column
+  double* tau;      // 4*nx*ny wall stresses
+  double* utau;     // 4*nx*ny Newton state
+  double* dsm_part; // 2*nz*nblk_xy plane partial sums (LM, MM)
+  int64_t red_n;
+  int nblk_xy;      // number of x-y tiles used by plane reductions
+};
+
+// Per-context state (host side).
+struct Ctx {
+  les_config cfg;
+  hipStream_t stream;
+  GridP g;               // device metric pointers filled at workspace bind
+  // host copies of the tables
+  std::vector<double> zf, zc, dzf, dzc, delta2, pa, pb, pc, lamx, lamy, lamz;
+  std::vector<double> twx, twy, twz;
+  // host staging of uploaded tables (kept alive for the asynchronous copies)
+  std::vector<float> twx_f_host, twy_f_host, twz_f_host;
+  std::vector<double> coef_host, hfac_host;
+  // bound buffers
+  void* u = nullptr;
+  void* v = nullptr;
+  void* w = nullptr;
+  void* p = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t field_elems = 0;   // (nz+2)*ny*nx
+  size_t elem = 8;          // storage bytes
+  // workspace carving (byte offsets into ws)
+  Tables t{};
+  void* ru = nullptr;  void* rv = nullptr;  void* rw = nullptr;   // RK history R^{k-1}
+  void* us = nullptr;  void* vs = nullptr;  void* wsf = nullptr;  // u*, v*, w*
+  void* nut = nullptr;    // |S| (all Smagorinsky variants) or learned nu_t/Delta^2
+  void* phi = nullptr;    // pressure correction (field layout)
+  void* spec = nullptr;   // complex spectrum [nz][ny][nx/2+1]
+  void* q9 = nullptr;     // dynamic model: 9 centre quantities (uc, |S| S_ij)
+  void* fvel = nullptr;   // dynamic model: 3 test-filtered velocity fields
+  // learned closure
+  float* mlp_params = nullptr;
+  double mlp_lo[7], mlp_hi[7];
+  int64_t* flag_count = nullptr;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool initialised = false;  // les_nut called
+  std::string err;
+};
+
+// kernel launchers (defined in the .hip files)
+template <typename T> void launch_predictor(Ctx& c, int stage);
+template <typename T> void launch_helmholtz(Ctx& c, int stage);
+template <typename T> void launch_poisson_rhs_fwd(Ctx& c, const T* us, const T* vs, const T* ws, double scale_by_gamma_dt, int stage);
+template <typename T> void launch_poisson_solve_spectral(Ctx& c);
+template <typename T> void launch_poisson_inverse(Ctx& c, T* phi_out);
+template <typename T> void launch_correct(Ctx& c, int stage);
+template <typename T> void launch_bc_fill(Ctx& c, T* u, T* v, T* w, T* p);
+template <typename T> void launch_wallmodel(Ctx& c);
+template <typename T> void launch_eddy_viscosity(Ctx& c);
+template <typename T> void launch_dt(Ctx& c, double cfl);
+template <typename T> void launch_poisson_field(Ctx& c, T* f);
+template <typename T> void launch_read_nut(Ctx& c, T* dst);
+template <typename T> void launch_diag(Ctx& c, double* out_dev);
+void launch_set_dt(Ctx& c, double dt);
+void launch_helmholtz_factor(Ctx& c, int stage);
+
+// launch geometry for one-thread-per-point kernels over interior planes
+struct Launch3 {
+  dim3 grid, block;
+};
+Launch3 point_launch(const GridP& g, int planes);
+
+}  // namespace les

@@ -1,0 +1,541 @@
+// Eigenfunction-expansion Poisson solver (Sec. 2.2: Fourier transforms in the periodic
+// directions and the Thomas algorithm along the non-uniform one; Eq. poi).
+//
+//   k_rfftx      f = D u* / (gamma dt) (or a given field) on two neighbouring x-rows,
+//                packed as one complex row, Stockham FFT in LDS, split into the two
+//                half spectra l = 0..nx/2; also the flow-rate partial sums of u*.
+//   k_fft_lines  complex FFT along y (or z) for tiles of consecutive l, in LDS.
+//   k_thomas     FP64 Thomas solve along z for every (l, m) column, pivots' companion
+//                values in LDS; the singular (0, 0) column is pinned and mean-corrected.
+//   k_fftz_solve periodic z: forward FFT along z, division by the eigenvalue sum, inverse.
+//   k_irfftx     Hermitian reconstruction of two rows, inverse FFT, real and imaginary
+//                parts back to the two rows of phi.
+//
+// Spectrum layout: complex [nz][ny][nx/2+1] (l fastest), interior planes only.
+// Normalisation: forward transforms unscaled; the solve multiplies by 1/(nx ny [nz]) so
+// the inverse transforms are plain sums.
+#include "les_internal.h"
+
+#include <algorithm>
+
+namespace les {
+
+template <typename R>
+struct cpx {
+  R x, y;
+};
+
+struct FftPlan {
+  int n;
+  int nst;
+  int rad[16];
+};
+
+FftPlan make_plan(int n) {
+  FftPlan p{};
+  p.n = n;
+  int m = n;
+  int s = 0;
+  if (m % 3 == 0) {
+    p.rad[s++] = 3;
+    m /= 3;
+  }
+  while (m % 4 == 0) {
+    p.rad[s++] = 4;
+    m /= 4;
+  }
+  while (m % 2 == 0) {
+    p.rad[s++] = 2;
+    m /= 2;
+  }
+  p.nst = s;
+  return p;
+}
+
+// Stockham autosort FFT (sub-transform size Ns grows by the radix each stage).  src and
+// dst are ping-pong LDS buffers of one transform; `lane` and `team` split the butterflies
+// of a stage among the team's threads.  DIR = -1 forward (exp(-2 pi i q/N)), +1 inverse.
+// tw holds (cos, sin)(2 pi q/N), q = 0..N-1.  Each radix has its own body so that the
+// butterfly operands stay in registers.
+template <typename R, int DIR>
+__device__ inline cpx<R> twiddle(cpx<R> a, const R* __restrict__ tw, int qq) {
+  const R c = tw[2 * qq], sn = (R)DIR * tw[2 * qq + 1];
+  return {a.x * c - a.y * sn, a.x * sn + a.y * c};
+}
+
+template <typename R, int DIR>
+__device__ inline void stage2(const cpx<R>* src, cpx<R>* dst, int N, int Ns, const R* tw, int lane, int team) {
+  const int nb = N / 2, ts = N / (Ns * 2);
+  for (int b = lane; b < nb; b += team) {
+    const int k = b % Ns;
+    const cpx<R> v0 = src[b];
+    const cpx<R> v1 = twiddle<R, DIR>(src[b + nb], tw, k * ts);
+    const int o = (b / Ns) * Ns * 2 + k;
+    dst[o] = {v0.x + v1.x, v0.y + v1.y};
+    dst[o + Ns] = {v0.x - v1.x, v0.y - v1.y};
+  }
+}
+
+template <typename R, int DIR>
+__device__ inline void stage4(const cpx<R>* src, cpx<R>* dst, int N, int Ns, const R* tw, int lane, int team) {
+  const int nb = N / 4, ts = N / (Ns * 4);
+  for (int b = lane; b < nb; b += team) {
+    const int k = b % Ns;
+    const cpx<R> v0 = src[b];
+    const cpx<R> v1 = twiddle<R, DIR>(src[b + nb], tw, k * ts);
+    const cpx<R> v2 = twiddle<R, DIR>(src[b + 2 * nb], tw, 2 * k * ts);
+    const cpx<R> v3 = twiddle<R, DIR>(src[b + 3 * nb], tw, 3 * k * ts);
+    const cpx<R> s02 = {v0.x + v2.x, v0.y + v2.y}, d02 = {v0.x - v2.x, v0.y - v2.y};
+    const cpx<R> s13 = {v1.x + v3.x, v1.y + v3.y}, d13 = {v1.x - v3.x, v1.y - v3.y};
+    const cpx<R> jd = {-(R)DIR * d13.y, (R)DIR * d13.x};   // DIR * i * d13
+    const int o = (b / Ns) * Ns * 4 + k;
+    dst[o] = {s02.x + s13.x, s02.y + s13.y};
+    dst[o + Ns] = {d02.x + jd.x, d02.y + jd.y};
+    dst[o + 2 * Ns] = {s02.x - s13.x, s02.y - s13.y};
+    dst[o + 3 * Ns] = {d02.x - jd.x, d02.y - jd.y};
+  }
+}
+
+template <typename R, int DIR>
+__device__ inline void stage3(const cpx<R>* src, cpx<R>* dst, int N, int Ns, const R* tw, int lane, int team) {
+  const int nb = N / 3, ts = N / (Ns * 3);
+  const R h3 = (R)0.86602540378443864676;
+  for (int b = lane; b < nb; b += team) {
+    const int k = b % Ns;
+    const cpx<R> v0 = src[b];
+    const cpx<R> v1 = twiddle<R, DIR>(src[b + nb], tw, k * ts);
+    const cpx<R> v2 = twiddle<R, DIR>(src[b + 2 * nb], tw, 2 * k * ts);
+    const cpx<R> s12 = {v1.x + v2.x, v1.y + v2.y}, d12 = {v1.x - v2.x, v1.y - v2.y};
+    const cpx<R> m = {v0.x - (R)0.5 * s12.x, v0.y - (R)0.5 * s12.y};
+    const cpx<R> jd = {-(R)DIR * h3 * d12.y, (R)DIR * h3 * d12.x};
+    const int o = (b / Ns) * Ns * 3 + k;
+    dst[o] = {v0.x + s12.x, v0.y + s12.y};
+    dst[o + Ns] = {m.x + jd.x, m.y + jd.y};
+    dst[o + 2 * Ns] = {m.x - jd.x, m.y - jd.y};
+  }
+}
+
+template <typename R, int DIR>
+__device__ cpx<R>* stockham(cpx<R>* src, cpx<R>* dst, const FftPlan& P, const R* __restrict__ tw, int lane, int team) {
+  const int N = P.n;
+  int Ns = 1;
+  for (int s = 0; s < P.nst; ++s) {
+    const int r = P.rad[s];
+    if (r == 4) stage4<R, DIR>(src, dst, N, Ns, tw, lane, team);
+    else if (r == 2) stage2<R, DIR>(src, dst, N, Ns, tw, lane, team);
+    else stage3<R, DIR>(src, dst, N, Ns, tw, lane, team);
+    __syncthreads();
+    cpx<R>* t = src;
+    src = dst;
+    dst = t;
+    Ns *= r;
+  }
+  return src;
+}
+
+template <typename T>
+__device__ inline const T* twsel(const double* d, const float* f);
+template <>
+__device__ inline const double* twsel<double>(const double* d, const float*) { return d; }
+template <>
+__device__ inline const float* twsel<float>(const double*, const float* f) { return f; }
+
+// ============================================================================ forward x
+// MODE 0: f = D u* scaled; MODE 1: f given (les_poisson).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_rfftx(GridP g, FftPlan P, const T* __restrict__ us, const T* __restrict__ vs,
+                                               const T* __restrict__ ws, const T* __restrict__ fin,
+                                               cpx<T>* __restrict__ spec, const double* __restrict__ twd,
+                                               const float* __restrict__ twf, const double* __restrict__ dtp,
+                                               double gamma, int npair_blk, double* __restrict__ bulk_part) {
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int nx = g.nx, nxh = nx / 2 + 1, nyh = g.ny / 2;
+  cpx<T>* B = A + npair_blk * nx;
+  const int64_t npairs = (int64_t)g.nz * nyh;
+  const T scale = MODE == 0 ? (T)(1.0 / (gamma * dtp[0])) : (T)1;
+  double bsum = 0.0;
+  for (int e = threadIdx.x; e < npair_blk * nx; e += blockDim.x) {
+    const int p = e / nx, i = e % nx;
+    const int64_t gp = (int64_t)blockIdx.x * npair_blk + p;
+    cpx<T> z = {(T)0, (T)0};
+    if (gp < npairs) {
+      const int k = (int)(gp / nyh) + 1;
+      const int j0 = 2 * (int)(gp % nyh);
+      T fv[2];
+      for (int r = 0; r < 2; ++r) {
+        const int j = j0 + r;
+        const int64_t c = idx3(g, k, j, i);
+        if (MODE == 0) {
+          const T d = (us[c] - us[idx3(g, k, j, wrap_m(i, nx))]) * (T)g.rdx +
+                      (vs[c] - vs[idx3(g, k, wrap_m(j, g.ny), i)]) * (T)g.rdy +
+                      (ws[c] - ((k == 1 && g.zbc == LES_ZBC_PERIODIC) ? ws[idx3(g, g.nz, j, i)] : ws[c - g.sxy])) *
+                          (T)(1.0 / g.dzf[k]);
+          fv[r] = d * scale;
+          if (bulk_part) bsum += (double)us[c] * g.dzf[k];
+        } else {
+          fv[r] = fin[c];
+        }
+      }
+      z = {fv[0], fv[1]};
+    }
+    A[e] = z;
+  }
+  if (bulk_part) {
+    __shared__ double red[256];
+    red[threadIdx.x] = bsum;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) bulk_part[blockIdx.x] = red[0];
+  }
+  __syncthreads();
+  const int team = blockDim.x / npair_blk;
+  const int p = threadIdx.x / team, lane = threadIdx.x % team;
+  cpx<T>* res = nullptr;
+  {
+    const T* tw = twsel<T>(twd, twf);
+    res = stockham<T, -1>(A + p * nx, B + p * nx, P, tw, lane, team);
+  }
+  // res points into A or B for team p (same parity for all teams)
+  const int64_t gp = (int64_t)blockIdx.x * npair_blk + p;
+  if (gp >= npairs) return;
+  const int k = (int)(gp / nyh);
+  const int j0 = 2 * (int)(gp % nyh);
+  cpx<T>* s0 = spec + ((int64_t)k * g.ny + j0) * nxh;
+  cpx<T>* s1 = s0 + nxh;
+  for (int l = lane; l < nxh; l += team) {
+    const cpx<T> a = res[l];
+    const cpx<T> b = res[(nx - l) % nx];
+    // A_l = (Z_l + conj Z_{N-l})/2, B_l = (Z_l - conj Z_{N-l})/(2i)
+    s0[l] = {(T)0.5 * (a.x + b.x), (T)0.5 * (a.y - b.y)};
+    s1[l] = {(T)0.5 * (a.y + b.y), (T)0.5 * (b.x - a.x)};
+  }
+}
+
+// ============================================================================ inverse x
+template <typename T>
+__global__ void __launch_bounds__(256) k_irfftx(GridP g, FftPlan P, const cpx<T>* __restrict__ spec,
+                                                T* __restrict__ out, const double* __restrict__ twd,
+                                                const float* __restrict__ twf, int npair_blk) {
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int nx = g.nx, nxh = nx / 2 + 1, nyh = g.ny / 2;
+  cpx<T>* B = A + npair_blk * nx;
+  const int64_t npairs = (int64_t)g.nz * nyh;
+  for (int e = threadIdx.x; e < npair_blk * nx; e += blockDim.x) {
+    const int p = e / nx, l = e % nx;
+    const int64_t gp = (int64_t)blockIdx.x * npair_blk + p;
+    cpx<T> z = {(T)0, (T)0};
+    if (gp < npairs) {
+      const int k = (int)(gp / nyh);
+      const int j0 = 2 * (int)(gp % nyh);
+      const cpx<T>* s0 = spec + ((int64_t)k * g.ny + j0) * nxh;
+      const cpx<T>* s1 = s0 + nxh;
+      if (l < nxh) {
+        const cpx<T> a = s0[l], b = s1[l];
+        z = {a.x - b.y, a.y + b.x};
+      } else {
+        const cpx<T> a = s0[nx - l], b = s1[nx - l];
+        z = {a.x + b.y, -a.y + b.x};
+      }
+    }
+    A[e] = z;
+  }
+  __syncthreads();
+  const int team = blockDim.x / npair_blk;
+  const int p = threadIdx.x / team, lane = threadIdx.x % team;
+  const T* tw = twsel<T>(twd, twf);
+  cpx<T>* res = stockham<T, 1>(A + p * nx, B + p * nx, P, tw, lane, team);
+  const int64_t gp = (int64_t)blockIdx.x * npair_blk + p;
+  if (gp >= npairs) return;
+  const int k = (int)(gp / nyh) + 1;
+  const int j0 = 2 * (int)(gp % nyh);
+  for (int i = lane; i < nx; i += team) {
+    out[idx3(g, k, j0, i)] = res[i].x;
+    out[idx3(g, k, j0 + 1, i)] = res[i].y;
+  }
+}
+
+// ============================================================================ strided lines
+// Complex FFT of length P.n along a strided dimension for L consecutive l values:
+// element t of line (l, o) is at base + o*ostride + t*lstride + l.  grid.x covers l tiles,
+// grid.y covers o.  SOLVE (periodic z only): forward FFT, multiply by
+// 1/(lamx + lamy + lamz) (0 for the zero mode) and the normalisation, inverse FFT.
+template <typename T, int DIR, bool SOLVE>
+__global__ void __launch_bounds__(256) k_fft_lines(FftPlan P, cpx<T>* __restrict__ data, int nl, int64_t lstride,
+                                                   int64_t ostride, int L, const double* __restrict__ twd,
+                                                   const float* __restrict__ twf, const double* __restrict__ lamx,
+                                                   const double* __restrict__ lamy, const double* __restrict__ lamz,
+                                                   double norm) {
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int N = P.n;
+  cpx<T>* B = A + L * N;
+  const int l0 = blockIdx.x * L;
+  const int o = blockIdx.y;
+  cpx<T>* base = data + (int64_t)o * ostride;
+  for (int e = threadIdx.x; e < L * N; e += blockDim.x) {
+    const int t = e / L, ll = e % L;
+    const int l = l0 + ll;
+    A[ll * N + t] = l < nl ? base[(int64_t)t * lstride + l] : cpx<T>{(T)0, (T)0};
+  }
+  __syncthreads();
+  const int team = blockDim.x / L;
+  const int ll = threadIdx.x / team, lane = threadIdx.x % team;
+  const T* tw = twsel<T>(twd, twf);
+  cpx<T>* res = stockham<T, DIR>(A + ll * N, B + ll * N, P, tw, lane, team);
+  if (SOLVE) {
+    // res holds the z spectrum of column (l, m = o); o indexes y modes here
+    const int l = l0 + ll;
+    for (int t = lane; t < N; t += team) {
+      double lam = (l < nl ? lamx[l] : 0.0) + lamy[o] + lamz[t];
+      double f = (lam != 0.0) ? norm / lam : 0.0;
+      res[t].x = (T)((double)res[t].x * f);
+      res[t].y = (T)((double)res[t].y * f);
+    }
+    __syncthreads();
+    cpx<T>* other = (res == A + ll * N) ? B + ll * N : A + ll * N;
+    res = stockham<T, 1>(res, other, P, tw, lane, team);
+  }
+  // every team's result lies in the same buffer (A or B)
+  cpx<T>* R = (res == A + ll * N) ? A : B;
+  __syncthreads();
+  for (int e = threadIdx.x; e < L * N; e += blockDim.x) {
+    const int t = e / L, l2 = e % L;
+    const int l = l0 + l2;
+    if (l < nl) base[(int64_t)t * lstride + l] = R[l2 * N + t];
+  }
+}
+
+// ============================================================================ Thomas
+// One thread per (l, m) column: (A_z + lamx(l) + lamy(m)) x = g, g = f_hat/(nx ny).
+// Elimination in double; cp kept in LDS (type C), d' stored in place.  The (0, 0) column
+// is singular: its last unknown is pinned to zero, the first nz-1 rows solved, and the
+// dzf-weighted mean subtracted (done in double in the scratch `zcol`).
+template <typename T, typename C>
+__global__ void k_thomas(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ pa,
+                         const double* __restrict__ pb, const double* __restrict__ pc,
+                         const double* __restrict__ lamx, const double* __restrict__ lamy, double norm,
+                         double* __restrict__ zcol) {
+  extern __shared__ unsigned char smem_raw[];
+  C* cps = reinterpret_cast<C*>(smem_raw);
+  const int nxh = g.nx / 2 + 1;
+  const int64_t ncol = (int64_t)nxh * g.ny;
+  const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  const int l = (int)(col % nxh), m = (int)(col / nxh);
+  const int n = g.nz;
+  const int64_t st = ncol;
+  cpx<T>* x = spec + col;
+  C* cp = cps + threadIdx.x;
+  const int cs = blockDim.x;
+  if (l == 0 && m == 0) {
+    // singular column, all in double
+    const int nn = n - 1;
+    double cprev = 0.0, dprev = 0.0;
+    for (int k = 0; k < nn; ++k) {
+      const double a = pa[k];
+      const double piv = pb[k] - a * cprev;
+      const double cc = pc[k] / piv;
+      const double d = ((double)x[k * st].x * norm - a * dprev) / piv;
+      zcol[k] = cc;
+      zcol[n + k] = d;
+      cprev = cc;
+      dprev = d;
+    }
+    double xn = dprev;
+    zcol[2 * n + nn - 1] = xn;
+    for (int k = nn - 2; k >= 0; --k) {
+      xn = zcol[n + k] - zcol[k] * xn;
+      zcol[2 * n + k] = xn;
+    }
+    zcol[2 * n + n - 1] = 0.0;
+    double sw = 0.0, sd = 0.0;
+    for (int k = 0; k < n; ++k) {
+      sw += zcol[2 * n + k] * g.dzf[k + 1];
+      sd += g.dzf[k + 1];
+    }
+    const double mean = sw / sd;
+    for (int k = 0; k < n; ++k) x[k * st] = {(T)(zcol[2 * n + k] - mean), (T)0};
+    return;
+  }
+  const double lam = lamx[l] + lamy[m];
+  double cprev = 0.0, drx = 0.0, dry = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double a = pa[k];
+    const double piv = (pb[k] + lam) - a * cprev;
+    const double r = 1.0 / piv;
+    const double cc = pc[k] * r;
+    const cpx<T> f = x[k * st];
+    drx = ((double)f.x * norm - a * drx) * r;
+    dry = ((double)f.y * norm - a * dry) * r;
+    cp[k * cs] = (C)cc;
+    x[k * st] = {(T)drx, (T)dry};
+    cprev = cc;
+  }
+  double xr = drx, xi = dry;
+  for (int k = n - 2; k >= 0; --k) {
+    const cpx<T> d = x[k * st];
+    const double c = (double)cp[k * cs];
+    xr = (double)d.x - c * xr;
+    xi = (double)d.y - c * xi;
+    x[k * st] = {(T)xr, (T)xi};
+  }
+}
+
+// ============================================================================ bulk
+// s = (U_b - <u*>) / <q>, <.> the dzf-weighted volume mean; stored in dt[1].
+__global__ void k_bulk_final(const double* part, int nblk, double* dtp, const double* q, const double* dzf, int nz,
+                             double ubulk, double cells_xy, double lz) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[b];
+  const double mean = s / (cells_xy * lz);
+  double qs = 0.0, ds = 0.0;
+  for (int k = 1; k <= nz; ++k) {
+    qs += q[k - 1] * dzf[k];
+    ds += dzf[k];
+  }
+  dtp[1] = (ubulk - mean) / (qs / ds);
+}
+
+// ghost planes of a cell-centred scalar (Neumann walls or periodic copies)
+template <typename T>
+__global__ void k_scalar_ghosts(GridP g, T* f) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= g.sxy) return;
+  const int64_t s = g.sxy, n = g.nz;
+  if (g.zbc == LES_ZBC_PERIODIC) {
+    f[c] = f[n * s + c];
+    f[(n + 1) * s + c] = f[s + c];
+  } else {
+    f[c] = f[s + c];
+    f[(n + 1) * s + c] = f[n * s + c];
+  }
+}
+
+// ============================================================================ launchers
+// Transforms per 256-thread block: a power of two (so the block splits into equal teams)
+// with at most 1024 complex points per buffer (two buffers: <= 32 KiB in double).
+static int pow2_floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+static int pairs_per_block(int nx) {
+  int p = pow2_floor(std::max(1, 1024 / nx));
+  return std::min(p, 8);
+}
+static int lines_per_block(int n) {
+  int L = pow2_floor(std::max(1, 1024 / n));
+  return std::min(L, 32);
+}
+
+template <typename T>
+static void fwd_x(Ctx& c, int mode, const T* us, const T* vs, const T* ws, const T* fin, double gamma, bool bulk) {
+  const FftPlan P = make_plan(c.g.nx);
+  const int pb = pairs_per_block(c.g.nx);
+  const int64_t npairs = (int64_t)c.g.nz * (c.g.ny / 2);
+  const unsigned nblk = (unsigned)((npairs + pb - 1) / pb);
+  const size_t sh = 2 * (size_t)pb * c.g.nx * sizeof(cpx<T>);
+  double* bp = bulk ? c.t.bulk : nullptr;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_rfftx<T, 0>), dim3(nblk), dim3(256), sh, c.stream, c.g, P, us, vs, ws, fin,
+                       (cpx<T>*)c.spec, c.t.twx, c.t.twx_f, c.t.dt, gamma, pb, bp);
+  else
+    hipLaunchKernelGGL((k_rfftx<T, 1>), dim3(nblk), dim3(256), sh, c.stream, c.g, P, us, vs, ws, fin,
+                       (cpx<T>*)c.spec, c.t.twx, c.t.twx_f, c.t.dt, gamma, pb, bp);
+  if (bulk)
+    hipLaunchKernelGGL(k_bulk_final, dim3(1), dim3(64), 0, c.stream, c.t.bulk, (int)nblk, c.t.dt,
+                       c.t.hfac + 4 * c.g.nz, c.t.dzf, c.g.nz, c.cfg.ubulk, (double)c.g.sxy, c.cfg.lz);
+}
+
+template <typename T>
+static void spectral_solve(Ctx& c) {
+  const int nxh = c.g.nx / 2 + 1;
+  const int ny = c.g.ny, nz = c.g.nz;
+  cpx<T>* sp = (cpx<T>*)c.spec;
+  // y transform
+  {
+    const FftPlan P = make_plan(ny);
+    const int L = lines_per_block(ny);
+    dim3 grid((nxh + L - 1) / L, nz);
+    const size_t sh = 2 * (size_t)L * ny * sizeof(cpx<T>);
+    hipLaunchKernelGGL((k_fft_lines<T, -1, false>), grid, dim3(256), sh, c.stream, P, sp, nxh, (int64_t)nxh,
+                       (int64_t)nxh * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
+  }
+  if (c.cfg.zbc == LES_ZBC_PERIODIC) {
+    const FftPlan P = make_plan(nz);
+    const int L = lines_per_block(nz);
+    dim3 grid((nxh + L - 1) / L, ny);
+    const size_t sh = 2 * (size_t)L * nz * sizeof(cpx<T>);
+    const double norm = 1.0 / ((double)c.g.nx * ny * nz);
+    hipLaunchKernelGGL((k_fft_lines<T, -1, true>), grid, dim3(256), sh, c.stream, P, sp, nxh, (int64_t)nxh * ny,
+                       (int64_t)nxh, L, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy, c.t.lamz, norm);
+  } else {
+    const int64_t ncol = (int64_t)nxh * ny;
+    int tpb = 64;
+    while (tpb > 16 && (size_t)tpb * nz * sizeof(T) > 65536) tpb /= 2;
+    const size_t sh = (size_t)tpb * nz * sizeof(T);
+    const double norm = 1.0 / ((double)c.g.nx * ny);
+    double* zcol = c.t.zcol;
+    hipLaunchKernelGGL((k_thomas<T, T>), dim3((unsigned)((ncol + tpb - 1) / tpb)), dim3(tpb), sh, c.stream, c.g, sp,
+                       c.t.pa, c.t.pb, c.t.pc, c.t.lamx, c.t.lamy, norm, zcol);
+  }
+  {
+    const FftPlan P = make_plan(ny);
+    const int L = lines_per_block(ny);
+    dim3 grid((nxh + L - 1) / L, nz);
+    const size_t sh = 2 * (size_t)L * ny * sizeof(cpx<T>);
+    hipLaunchKernelGGL((k_fft_lines<T, 1, false>), grid, dim3(256), sh, c.stream, P, sp, nxh, (int64_t)nxh,
+                       (int64_t)nxh * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
+  }
+}
+
+template <typename T>
+static void inv_x(Ctx& c, T* out) {
+  const FftPlan P = make_plan(c.g.nx);
+  const int pb = pairs_per_block(c.g.nx);
+  const int64_t npairs = (int64_t)c.g.nz * (c.g.ny / 2);
+  const unsigned nblk = (unsigned)((npairs + pb - 1) / pb);
+  const size_t sh = 2 * (size_t)pb * c.g.nx * sizeof(cpx<T>);
+  hipLaunchKernelGGL((k_irfftx<T>), dim3(nblk), dim3(256), sh, c.stream, c.g, P, (const cpx<T>*)c.spec, out,
+                     c.t.twx, c.t.twx_f, pb);
+}
+
+template <typename T>
+void launch_poisson_rhs_fwd(Ctx& c, const T* us, const T* vs, const T* ws, double gamma, int stage) {
+  (void)stage;
+  fwd_x<T>(c, 0, us, vs, ws, nullptr, gamma, c.cfg.ubulk > 0.0);
+}
+
+template <typename T>
+void launch_poisson_solve_spectral(Ctx& c) {
+  spectral_solve<T>(c);
+}
+
+template <typename T>
+void launch_poisson_inverse(Ctx& c, T* phi_out) {
+  inv_x<T>(c, phi_out);
+}
+
+template <typename T>
+void launch_poisson_field(Ctx& c, T* f) {
+  fwd_x<T>(c, 1, nullptr, nullptr, nullptr, f, 1.0, false);
+  spectral_solve<T>(c);
+  inv_x<T>(c, f);
+  hipLaunchKernelGGL(k_scalar_ghosts<T>, dim3((unsigned)((c.g.sxy + 255) / 256)), dim3(256), 0, c.stream, c.g, f);
+}
+
+#define INST(T)                                                                              \
+  template void launch_poisson_rhs_fwd<T>(Ctx&, const T*, const T*, const T*, double, int); \
+  template void launch_poisson_solve_spectral<T>(Ctx&);                                      \
+  template void launch_poisson_inverse<T>(Ctx&, T*);                                         \
+  template void launch_poisson_field<T>(Ctx&, T*);
+INST(double)
+INST(float)
+
+}  // namespace les

@@ -1,0 +1,615 @@
+// Momentum predictor, Crank-Nicolson z solves, projection, boundary planes, wall model
+// and time step: the point-wise and column-wise parts of one RK3 substep
+// (Alg. 1; Eqs. onestar_exp, twostar_imp1d, onestar_imp1d, correc, p_update_exp,
+// p_update_imp1d; Eq. wm with the coupling of Sec. 2.2; Alg. 2).
+#include "les_internal.h"
+
+namespace les {
+
+Launch3 point_launch(const GridP& g, int planes) {
+  Launch3 L;
+  int bx = g.nx >= 64 ? 64 : g.nx;
+  int by = 256 / bx;
+  if (by > g.ny) by = g.ny;
+  L.block = dim3(bx, by, 1);
+  L.grid = dim3((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, planes);
+  return L;
+}
+
+// nu_t at a cell centre: plane coefficient times the stored field.
+template <typename T>
+__device__ inline T nut_at(const T* nut, const double* coef, const GridP& g, int k, int j, int i) {
+  return (T)coef[k] * nut[idx3(g, k, j, i)];
+}
+
+// ============================================================================ predictor
+// R_i = -d(u_i u_j)/dx_j + d(2 nu_t S_ij)/dx_j + nu L u_i (explicit) or with L_xx + L_yy
+// only (CN in z); u* = u + dt (alpha R^k + beta R^{k-1} - gamma G p), or with CN in z the
+// Helmholtz right-hand side u** - gamma nu dt/2 L_zz u^k where
+// u** = u + dt (alpha R^k + beta R^{k-1} - gamma G p) + gamma nu dt L_zz u^k.
+template <typename T, bool IMPLICIT>
+__global__ void __launch_bounds__(256) k_predictor(GridP g, const T* __restrict__ u, const T* __restrict__ v,
+                                                   const T* __restrict__ w, const T* __restrict__ p,
+                                                   const T* __restrict__ nut, const double* __restrict__ coef,
+                                                   T* __restrict__ ru, T* __restrict__ rv, T* __restrict__ rw,
+                                                   T* __restrict__ us, T* __restrict__ vs, T* __restrict__ ws,
+                                                   const double* __restrict__ dtp, double alpha, double beta,
+                                                   double gamma, int use_rprev, int write_r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z + 1;
+  if (i >= g.nx || j >= g.ny) return;
+  const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx);
+  const int jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
+  const int kp = k + 1, km = k - 1;
+  const T dt = (T)dtp[0];
+  const T rdx = (T)g.rdx, rdy = (T)g.rdy;
+  const T rdzf = (T)(1.0 / g.dzf[k]);
+  const T rdzc = (T)(1.0 / g.dzc[k]);
+  const T rdzcm = (T)(1.0 / g.dzc[km]);
+  const T rdzfp = (T)(1.0 / g.dzf[kp]);
+  const T nu = (T)g.nu;
+  const T h = (T)0.5, q = (T)0.25, two = (T)2;
+#define U(kk, jj, ii) u[idx3(g, kk, jj, ii)]
+#define V(kk, jj, ii) v[idx3(g, kk, jj, ii)]
+#define W(kk, jj, ii) w[idx3(g, kk, jj, ii)]
+#define NU(kk, jj, ii) nut_at(nut, coef, g, kk, jj, ii)
+  const int64_t c0 = idx3(g, k, j, i);
+  const T u0 = u[c0], v0 = v[c0], w0 = w[c0];
+  const T uip = U(k, j, ip), uim = U(k, j, im), ujp = U(k, jp, i), ujm = U(k, jm, i), ukp = U(kp, j, i), ukm = U(km, j, i);
+  const T vip = V(k, j, ip), vim = V(k, j, im), vjp = V(k, jp, i), vjm = V(k, jm, i), vkp = V(kp, j, i), vkm = V(km, j, i);
+  const T wip = W(k, j, ip), wim = W(k, j, im), wjp = W(k, jp, i), wjm = W(k, jm, i), wkp = W(kp, j, i), wkm = W(km, j, i);
+  const T vjm_ip = V(k, jm, ip), wkm_ip = W(km, j, ip), wkm_jp = W(km, jp, i);
+  const T ujp_im = U(k, jp, im), ukp_im = U(kp, j, im), vip_jm = vjm_ip, vkp_jm = V(kp, jm, i);
+  const T uim_jp = ujp_im;
+  const T n0 = NU(k, j, i), nip = NU(k, j, ip), njp = NU(k, jp, i), nkp = NU(kp, j, i);
+  const T nim = NU(k, j, im), njm = NU(k, jm, i), nkm = NU(km, j, i);
+
+  // ---------------- u-momentum at (i+1/2, j, k)
+  T ax, ay, az, sx, sy, sz, lx, ly, lz;
+  {
+    const T fxx_r = (h * (u0 + uip)) * (h * (u0 + uip));
+    const T fxx_l = (h * (uim + u0)) * (h * (uim + u0));
+    const T fxy_t = h * (u0 + ujp) * (h * (v0 + vip));
+    const T fxy_b = h * (ujm + u0) * (h * (vjm + vjm_ip));
+    const T fxz_t = h * (u0 + ukp) * (h * (w0 + wip));
+    const T fxz_b = h * (ukm + u0) * (h * (wkm + wkm_ip));
+    ax = (fxx_r - fxx_l) * rdx + (fxy_t - fxy_b) * rdy + (fxz_t - fxz_b) * rdzf;
+    // SGS
+    const T t11_r = two * nip * ((uip - u0) * rdx);
+    const T t11_l = two * n0 * ((u0 - uim) * rdx);
+    const T nu12_t = q * (n0 + nip + njp + NU(k, jp, ip));
+    const T e12_t = h * ((ujp - u0) * rdy + (vip - v0) * rdx);
+    const T nu12_b = q * (njm + NU(k, jm, ip) + n0 + nip);
+    const T e12_b = h * ((u0 - ujm) * rdy + (vjm_ip - vjm) * rdx);
+    const T nu13_t = q * (n0 + nip + nkp + NU(kp, j, ip));
+    const T e13_t = h * ((ukp - u0) * rdzc + (wip - w0) * rdx);
+    const T nu13_b = q * (nkm + NU(km, j, ip) + n0 + nip);
+    const T e13_b = h * ((u0 - ukm) * rdzcm + (wkm_ip - wkm) * rdx);
+    sx = (t11_r - t11_l) * rdx + (two * nu12_t * e12_t - two * nu12_b * e12_b) * rdy +
+         (two * nu13_t * e13_t - two * nu13_b * e13_b) * rdzf;
+    lx = (uip - two * u0 + uim) * (rdx * rdx) + (ujp - two * u0 + ujm) * (rdy * rdy);
+    lz = ((ukp - u0) * rdzc - (u0 - ukm) * rdzcm) * rdzf;
+  }
+  const T lzu = lz;
+  T Ru = -ax + sx + nu * (IMPLICIT ? lx : lx + lz);
+  // ---------------- v-momentum at (i, j+1/2, k)
+  {
+    const T fyx_r = h * (v0 + vip) * (h * (u0 + ujp));
+    const T fyx_l = h * (vim + v0) * (h * (uim + uim_jp));
+    const T fyy_t = (h * (v0 + vjp)) * (h * (v0 + vjp));
+    const T fyy_b = (h * (vjm + v0)) * (h * (vjm + v0));
+    const T fyz_t = h * (v0 + vkp) * (h * (w0 + wjp));
+    const T fyz_b = h * (vkm + v0) * (h * (wkm + wkm_jp));
+    ay = (fyx_r - fyx_l) * rdx + (fyy_t - fyy_b) * rdy + (fyz_t - fyz_b) * rdzf;
+    const T nu12_r = q * (n0 + nip + njp + NU(k, jp, ip));
+    const T e12_r = h * ((ujp - u0) * rdy + (vip - v0) * rdx);
+    const T nu12_l = q * (nim + n0 + NU(k, jp, im) + njp);
+    const T e12_l = h * ((uim_jp - uim) * rdy + (v0 - vim) * rdx);
+    const T t22_t = two * njp * ((vjp - v0) * rdy);
+    const T t22_b = two * n0 * ((v0 - vjm) * rdy);
+    const T nu23_t = q * (n0 + njp + nkp + NU(kp, jp, i));
+    const T e23_t = h * ((vkp - v0) * rdzc + (wjp - w0) * rdy);
+    const T nu23_b = q * (nkm + NU(km, jp, i) + n0 + njp);
+    const T e23_b = h * ((v0 - vkm) * rdzcm + (wkm_jp - wkm) * rdy);
+    sy = (two * nu12_r * e12_r - two * nu12_l * e12_l) * rdx + (t22_t - t22_b) * rdy +
+         (two * nu23_t * e23_t - two * nu23_b * e23_b) * rdzf;
+    lx = (vip - two * v0 + vim) * (rdx * rdx) + (vjp - two * v0 + vjm) * (rdy * rdy);
+    lz = ((vkp - v0) * rdzc - (v0 - vkm) * rdzcm) * rdzf;
+  }
+  const T lzv = lz;
+  T Rv = -ay + sy + nu * (IMPLICIT ? lx : lx + lz);
+  // ---------------- w-momentum at (i, j, k+1/2)
+  {
+    const T fzx_r = h * (w0 + wip) * (h * (u0 + ukp));
+    const T fzx_l = h * (wim + w0) * (h * (uim + ukp_im));
+    const T fzy_t = h * (w0 + wjp) * (h * (v0 + vkp));
+    const T fzy_b = h * (wjm + w0) * (h * (vjm + vkp_jm));
+    const T fzz_t = (h * (w0 + wkp)) * (h * (w0 + wkp));
+    const T fzz_b = (h * (wkm + w0)) * (h * (wkm + w0));
+    az = (fzx_r - fzx_l) * rdx + (fzy_t - fzy_b) * rdy + (fzz_t - fzz_b) * rdzc;
+    const T nu13_r = q * (n0 + nip + nkp + NU(kp, j, ip));
+    const T e13_r = h * ((ukp - u0) * rdzc + (wip - w0) * rdx);
+    const T nu13_l = q * (nim + n0 + NU(kp, j, im) + nkp);
+    const T e13_l = h * ((ukp_im - uim) * rdzc + (w0 - wim) * rdx);
+    const T nu23_r = q * (n0 + njp + nkp + NU(kp, jp, i));
+    const T e23_r = h * ((vkp - v0) * rdzc + (wjp - w0) * rdy);
+    const T nu23_l = q * (njm + n0 + NU(kp, jm, i) + nkp);
+    const T e23_l = h * ((vkp_jm - vjm) * rdzc + (w0 - wjm) * rdy);
+    const T t33_t = two * nkp * ((wkp - w0) * rdzfp);
+    const T t33_b = two * n0 * ((w0 - wkm) * rdzf);
+    sz = (two * nu13_r * e13_r - two * nu13_l * e13_l) * rdx + (two * nu23_r * e23_r - two * nu23_l * e23_l) * rdy +
+         (t33_t - t33_b) * rdzc;
+    lx = (wip - two * w0 + wim) * (rdx * rdx) + (wjp - two * w0 + wjm) * (rdy * rdy);
+    lz = ((wkp - w0) * rdzfp - (w0 - wkm) * rdzf) * rdzc;
+  }
+  const T lzw = lz;
+  T Rw = -az + sz + nu * (IMPLICIT ? lx : lx + lz);
+#undef U
+#undef V
+#undef W
+#undef NU
+  const T ta = (T)alpha, tb = (T)beta, tg = (T)gamma;
+  T iu = ta * Ru, iv = ta * Rv, iw = ta * Rw;
+  if (use_rprev) {
+    iu = iu + tb * ru[c0];
+    iv = iv + tb * rv[c0];
+    iw = iw + tb * rw[c0];
+  }
+  const T p0 = p[c0];
+  iu = iu - tg * ((p[idx3(g, k, j, ip)] - p0) * rdx);
+  iv = iv - tg * ((p[idx3(g, k, jp, i)] - p0) * rdy);
+  iw = iw - tg * ((p[idx3(g, kp, j, i)] - p0) * rdzc);
+  if (write_r) {
+    ru[c0] = Ru;
+    rv[c0] = Rv;
+    rw[c0] = Rw;
+  }
+  const bool wall_face = (g.zbc != LES_ZBC_PERIODIC) && (k == g.nz);
+  if (IMPLICIT) {
+    const T cg = tg * nu, ch = tg * nu * dt / two;
+    us[c0] = (u0 + dt * (iu + cg * lzu)) - ch * lzu;
+    vs[c0] = (v0 + dt * (iv + cg * lzv)) - ch * lzv;
+    ws[c0] = wall_face ? (T)0 : (w0 + dt * (iw + cg * lzw)) - ch * lzw;
+  } else {
+    us[c0] = u0 + dt * iu;
+    vs[c0] = v0 + dt * iv;
+    ws[c0] = wall_face ? (T)0 : w0 + dt * iw;
+  }
+}
+
+template <typename T>
+void launch_predictor(Ctx& c, int stage) {
+  static const double A[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+  static const double B[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+  const double G = A[stage] + B[stage];
+  Launch3 L = point_launch(c.g, c.g.nz);
+  const int use_rprev = stage > 0;
+  const int write_r = stage < 2;
+  auto f = c.cfg.implicit_z ? k_predictor<T, true> : k_predictor<T, false>;
+  hipLaunchKernelGGL(f, L.grid, L.block, 0, c.stream, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
+                     (const T*)c.p, (const T*)c.nut, c.t.coef, (T*)c.ru, (T*)c.rv, (T*)c.rw, (T*)c.us, (T*)c.vs,
+                     (T*)c.wsf, c.t.dt, A[stage], B[stage], G, use_rprev, write_r);
+}
+
+// ============================================================================ CN in z
+// The matrix (1 - c L_zz), c = gamma nu dt / 2, is the same for every (i, j) column, so
+// its Thomas factorisation (pivots and normalised super-diagonal) is computed once per
+// substep by three threads: u/v rows, w rows, and the flow-rate profile q = H^-1 1 of
+// the u rows (no-slip walls; 1 otherwise).  Layout of hfac: [cp_uv | rp_uv | cp_w | rp_w
+// | q | -] each nz long.
+__global__ void k_helmholtz_factor(GridP g, double* hfac, const double* dtp, double gamma, int wallmodel) {
+  const int n = g.nz;
+  const double c = gamma * g.nu * dtp[0] / 2.0;
+  double* cp_uv = hfac;
+  double* rp_uv = hfac + n;
+  double* cp_w = hfac + 2 * n;
+  double* rp_w = hfac + 3 * n;
+  double* qv = hfac + 4 * n;
+  if (threadIdx.x == 0) {
+    double cprev = 0.0;
+    for (int kk = 1; kk <= n; ++kk) {
+      double lo = 1.0 / (g.dzc[kk - 1] * g.dzf[kk]);
+      double up = 1.0 / (g.dzc[kk] * g.dzf[kk]);
+      double dg = -(lo + up);
+      if (kk == 1) dg += wallmodel ? lo : -lo;
+      if (kk == n) dg += wallmodel ? up : -up;
+      if (kk == 1) lo = 0.0;
+      if (kk == n) up = 0.0;
+      const double a = -c * lo, b = 1.0 - c * dg, cc = -c * up;
+      const double piv = b - a * cprev;
+      rp_uv[kk - 1] = 1.0 / piv;
+      cprev = cc / piv;
+      cp_uv[kk - 1] = cprev;
+    }
+    // q = H^-1 1 for the bulk-forcing profile (CN in z with no-slip rows)
+    if (!wallmodel) {
+      double dp = 0.0;
+      for (int kk = 1; kk <= n; ++kk) {
+        double lo = kk == 1 ? 0.0 : 1.0 / (g.dzc[kk - 1] * g.dzf[kk]);
+        dp = (1.0 - (-c * lo) * dp) * rp_uv[kk - 1];
+        qv[kk - 1] = dp;
+      }
+      for (int kk = n - 1; kk >= 1; --kk) qv[kk - 1] = qv[kk - 1] - cp_uv[kk - 1] * qv[kk];
+    } else {
+      for (int kk = 0; kk < n; ++kk) qv[kk] = 1.0;
+    }
+  } else if (threadIdx.x == 1) {
+    const int m = n - 1;
+    double cprev = 0.0;
+    for (int kk = 1; kk <= m; ++kk) {
+      double lo = 1.0 / (g.dzf[kk] * g.dzc[kk]);
+      double up = 1.0 / (g.dzf[kk + 1] * g.dzc[kk]);
+      const double dg = -(lo + up);
+      if (kk == 1) lo = 0.0;
+      if (kk == m) up = 0.0;
+      const double a = -c * lo, b = 1.0 - c * dg, cc = -c * up;
+      const double piv = b - a * cprev;
+      rp_w[kk - 1] = 1.0 / piv;
+      cprev = cc / piv;
+      cp_w[kk - 1] = cprev;
+    }
+  }
+}
+
+void launch_helmholtz_factor(Ctx& c, int stage) {
+  static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
+  hipLaunchKernelGGL(k_helmholtz_factor, dim3(1), dim3(64), 0, c.stream, c.g, c.t.hfac, c.t.dt, G[stage],
+                     c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);
+}
+
+// One thread per (component, j, i) column: forward elimination with the shared factors,
+// back substitution, in place on the right-hand side produced by the predictor.  The
+// wall-model rows take the lagged wall stress (from u^k) as a known flux.
+template <typename T>
+__global__ void __launch_bounds__(256) k_helmholtz(GridP g, T* __restrict__ us, T* __restrict__ vs,
+                                                   T* __restrict__ ws, const double* __restrict__ hfac,
+                                                   const double* __restrict__ tau, const double* __restrict__ dtp,
+                                                   double gamma, int wallmodel) {
+  const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int comp = blockIdx.y;
+  if (col >= g.sxy) return;
+  const int n = g.nz;
+  const double c = gamma * g.nu * dtp[0] / 2.0;
+  T* x = comp == 0 ? us : (comp == 1 ? vs : ws);
+  const double* cp = hfac + (comp < 2 ? 0 : 2 * n);
+  const double* rp = hfac + (comp < 2 ? n : 3 * n);
+  const int m = comp < 2 ? n : n - 1;
+  const int64_t s = g.sxy;
+  T* xc = x + s + col;  // plane 1
+  double lo_prev = 0.0;
+  double dp = 0.0;
+  for (int kk = 1; kk <= m; ++kk) {
+    double r = (double)xc[(int64_t)(kk - 1) * s];
+    if (comp < 2 && wallmodel) {
+      if (kk == 1) r += c * (-(tau[(comp == 0 ? 0 : 1) * s + col] / g.nu) / g.dzf[1]);
+      if (kk == n) r += c * (-(tau[(comp == 0 ? 2 : 3) * s + col] / g.nu) / g.dzf[n]);
+    }
+    double lo;
+    if (comp < 2) lo = kk == 1 ? 0.0 : 1.0 / (g.dzc[kk - 1] * g.dzf[kk]);
+    else lo = kk == 1 ? 0.0 : 1.0 / (g.dzf[kk] * g.dzc[kk]);
+    dp = (r - (-c * lo) * dp) * rp[kk - 1];
+    xc[(int64_t)(kk - 1) * s] = (T)dp;
+    (void)lo_prev;
+  }
+  double xn = dp;
+  for (int kk = m - 1; kk >= 1; --kk) {
+    const double d = (double)xc[(int64_t)(kk - 1) * s];
+    xn = d - cp[kk - 1] * xn;
+    xc[(int64_t)(kk - 1) * s] = (T)xn;
+  }
+}
+
+template <typename T>
+void launch_helmholtz(Ctx& c, int stage) {
+  static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
+  launch_helmholtz_factor(c, stage);
+  dim3 block(256), grid((unsigned)((c.g.sxy + 255) / 256), 3);
+  hipLaunchKernelGGL(k_helmholtz<T>, grid, block, 0, c.stream, c.g, (T*)c.us, (T*)c.vs, (T*)c.wsf, c.t.hfac,
+                     c.t.tau, c.t.dt, G[stage], c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);
+}
+
+// ============================================================================ boundary planes
+// Ghost planes after an update (Alg. 2 without the wall model): periodic copies, or
+// w = 0 on wall faces, p Neumann, u and v odd (no-slip).  One thread per (j, i).
+template <typename T>
+__global__ void k_bc_fill(GridP g, T* u, T* v, T* w, T* p) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= g.sxy) return;
+  const int64_t s = g.sxy, n = g.nz;
+  if (g.zbc == LES_ZBC_PERIODIC) {
+    T* f[4] = {u, v, w, p};
+    for (int a = 0; a < 4; ++a) {
+      f[a][c] = f[a][n * s + c];
+      f[a][(n + 1) * s + c] = f[a][s + c];
+    }
+    return;
+  }
+  u[c] = -u[s + c];
+  v[c] = -v[s + c];
+  u[(n + 1) * s + c] = -u[n * s + c];
+  v[(n + 1) * s + c] = -v[n * s + c];
+  w[c] = (T)0;
+  w[n * s + c] = (T)0;
+  w[(n + 1) * s + c] = (T)0;
+  p[c] = p[s + c];
+  p[(n + 1) * s + c] = p[n * s + c];
+}
+
+template <typename T>
+void launch_bc_fill(Ctx& c, T* u, T* v, T* w, T* p) {
+  hipLaunchKernelGGL(k_bc_fill<T>, dim3((unsigned)((c.g.sxy + 255) / 256)), dim3(256), 0, c.stream, c.g, u, v, w,
+                     p);
+}
+
+// ============================================================================ correction
+// u = u* - gamma dt G phi (Eq. correc), p += phi (Eq. p_update_exp) or
+// p += phi - gamma nu dt/2 L_zz phi (Eq. p_update_imp1d), flow-rate shift s q(z) on u,
+// then the non-wall-model ghost planes.  phi ghosts follow the Poisson boundary
+// condition (zero flux at walls, periodic copy otherwise) and are read on the fly.
+template <typename T>
+__global__ void __launch_bounds__(256) k_correct(GridP g, const T* __restrict__ us, const T* __restrict__ vs,
+                                                 const T* __restrict__ ws, const T* __restrict__ phi, T* __restrict__ u,
+                                                 T* __restrict__ v, T* __restrict__ w, T* __restrict__ p,
+                                                 const double* __restrict__ dtp, const double* __restrict__ qprof,
+                                                 double gamma, int implicit) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z + 1;
+  if (i >= g.nx || j >= g.ny) return;
+  const int n = g.nz;
+  const bool per = g.zbc == LES_ZBC_PERIODIC;
+  const int kp = (k == n) ? (per ? 1 : n) : k + 1;   // phi ghost plane by BC
+  const int km = (k == 1) ? (per ? n : 1) : k - 1;
+  const int64_t c0 = idx3(g, k, j, i);
+  const T gdt = (T)(gamma * dtp[0]);
+  const T ph = phi[c0];
+  const T phx = phi[idx3(g, k, j, wrap_p(i, g.nx))];
+  const T phy = phi[idx3(g, k, wrap_p(j, g.ny), i)];
+  const T phz = phi[idx3(g, kp, j, i)];
+  T un = us[c0] - gdt * ((phx - ph) * (T)g.rdx);
+  if (qprof != nullptr) un = un + (T)(dtp[1] * qprof[k - 1]);
+  const T vn = vs[c0] - gdt * ((phy - ph) * (T)g.rdy);
+  T wn;
+  if (!per && k == n) wn = (T)0;
+  else wn = ws[c0] - gdt * ((phz - ph) * (T)(1.0 / g.dzc[k]));
+  T pn = p[c0] + ph;
+  if (implicit) {
+    const T phm = phi[idx3(g, km, j, i)];
+    const T lz = ((phz - ph) * (T)(1.0 / g.dzc[k]) - (ph - phm) * (T)(1.0 / g.dzc[k - 1])) * (T)(1.0 / g.dzf[k]);
+    pn = pn - (T)(gamma * g.nu * dtp[0] / 2.0) * lz;
+  }
+  u[c0] = un;
+  v[c0] = vn;
+  w[c0] = wn;
+  p[c0] = pn;
+  // ghost planes
+  const int64_t s = g.sxy;
+  const int64_t c2 = (int64_t)j * g.nx + i;
+  if (per) {
+    if (k == n) { u[c2] = un; v[c2] = vn; w[c2] = wn; p[c2] = pn; }
+    if (k == 1) { u[(n + 1) * s + c2] = un; v[(n + 1) * s + c2] = vn; w[(n + 1) * s + c2] = wn; p[(n + 1) * s + c2] = pn; }
+  } else {
+    if (k == 1) { u[c2] = -un; v[c2] = -vn; w[c2] = (T)0; p[c2] = pn; }
+    if (k == n) { u[(n + 1) * s + c2] = -un; v[(n + 1) * s + c2] = -vn; w[(n + 1) * s + c2] = (T)0; p[(n + 1) * s + c2] = pn; }
+  }
+}
+
+template <typename T>
+void launch_correct(Ctx& c, int stage) {
+  static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
+  Launch3 L = point_launch(c.g, c.g.nz);
+  const double* q = c.cfg.ubulk > 0.0 ? c.t.hfac + 4 * c.g.nz : nullptr;
+  hipLaunchKernelGGL(k_correct<T>, L.grid, L.block, 0, c.stream, c.g, (const T*)c.us, (const T*)c.vs,
+                     (const T*)c.wsf, (const T*)c.phi, (T*)c.u, (T*)c.v, (T*)c.w, (T*)c.p, c.t.dt, q, G[stage],
+                     c.cfg.implicit_z);
+}
+
+// ============================================================================ wall model
+// Newton-Raphson for u_tau in u_tau [ln(u_tau h/nu)/kappa + B] = U (Eq. wm, Sec. 2.2),
+// kept on the increasing branch of the convex left-hand side, to |du| <= 1e-14 u_tau.
+__device__ inline double wm_newton(double U, double h, double nu, double kappa, double bconst, double guess) {
+  if (!(U > 0.0)) return 0.0;
+  const double xmin = nu / h * exp(-kappa * bconst - 1.0);
+  double x = guess > xmin ? guess : fmax(sqrt(nu * U / h), 2.0 * xmin);
+  for (int it = 0; it < 100; ++it) {
+    const double lg = log(x * h / nu);
+    const double f = x * (lg / kappa + bconst) - U;
+    const double fp = lg / kappa + bconst + 1.0 / kappa;
+    double xn = x - f / fp;
+    if (xn <= xmin) xn = 0.5 * (x + xmin);
+    if (fabs(xn - x) <= 1e-14 * xn) return xn;
+    x = xn;
+  }
+  return x;
+}
+
+// One thread per (wall, component, j, i): interpolate to h_wm, bring the other component
+// to the same face by its four-face mean, solve for u_tau, store tau and the ghost value
+// that makes the viscous wall flux equal to tau.
+template <typename T>
+__global__ void k_wallmodel(GridP g, T* u, T* v, double* tau, double* utau, int kb0, int kb1, double tb, double hb,
+                            int kt0, int kt1, double tt, double ht, double kappa, double bconst) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int which = blockIdx.y;  // 0 bot-x, 1 bot-y, 2 top-x, 3 top-y
+  if (c >= g.sxy) return;
+  const int i = (int)(c % g.nx), j = (int)(c / g.nx);
+  const bool top = which >= 2;
+  const bool isx = (which & 1) == 0;
+  const int k0 = top ? kt0 : kb0, k1 = top ? kt1 : kb1;
+  const double t = top ? tt : tb, h = top ? ht : hb;
+  auto at = [&](const T* f, int jj, int ii) {
+    return (1.0 - t) * (double)f[idx3(g, k0, jj, ii)] + t * (double)f[idx3(g, k1, jj, ii)];
+  };
+  double a, b;
+  if (isx) {
+    a = at(u, j, i);
+    const int ip = wrap_p(i, g.nx), jm = wrap_m(j, g.ny);
+    b = 0.25 * (at(v, j, i) + at(v, j, ip) + at(v, jm, i) + at(v, jm, ip));
+  } else {
+    a = at(v, j, i);
+    const int im = wrap_m(i, g.nx), jp = wrap_p(j, g.ny);
+    b = 0.25 * (at(u, j, i) + at(u, j, im) + at(u, jp, i) + at(u, jp, im));
+  }
+  const double U = sqrt(a * a + b * b);
+  const int64_t o = (int64_t)which * g.sxy + c;
+  const double x = wm_newton(U, h, g.nu, kappa, bconst, utau[o]);
+  utau[o] = x;
+  const double tw = U > 0.0 ? x * x * a / U : 0.0;
+  tau[o] = tw;
+  T* f = isx ? u : v;
+  const int n = g.nz;
+  if (!top) f[c] = (T)((double)f[g.sxy + c] - g.dzc[0] * tw / g.nu);
+  else f[(int64_t)(n + 1) * g.sxy + c] = (T)((double)f[(int64_t)n * g.sxy + c] - g.dzc[n] * tw / g.nu);
+}
+
+template <typename T>
+void launch_wallmodel(Ctx& c) {
+  const int n = c.g.nz;
+  int kb0 = 1, kb1 = 2, kt0 = n, kt1 = n - 1;
+  double tb = 0.0, tt = 0.0, hb = c.zc[1], ht = c.cfg.lz - c.zc[n];
+  if (c.cfg.h_wm > 0.0) {
+    const double h = c.cfg.h_wm;
+    for (int k = 1; k < n; ++k)
+      if (c.zc[k] <= h) kb0 = k;
+    kb1 = kb0 + 1;
+    tb = (h - c.zc[kb0]) / (c.zc[kb1] - c.zc[kb0]);
+    for (int k = n; k >= 2; --k)
+      if (c.cfg.lz - c.zc[k] <= h) kt0 = k;
+    kt1 = kt0 - 1;
+    const double lo = c.cfg.lz - c.zc[kt0], hi = c.cfg.lz - c.zc[kt1];
+    tt = (h - lo) / (hi - lo);
+    hb = ht = h;
+  }
+  dim3 grid((unsigned)((c.g.sxy + 255) / 256), 4);
+  hipLaunchKernelGGL(k_wallmodel<T>, grid, dim3(256), 0, c.stream, c.g, (T*)c.u, (T*)c.v, c.t.tau, c.t.utau, kb0,
+                     kb1, tb, hb, kt0, kt1, tt, ht, c.cfg.kappa, c.cfg.bconst);
+}
+
+// ============================================================================ time step
+// Block maxima of |u|/dx + |v|/dy + |w|/dzf and of nu_t, reduced in a fixed order by a
+// single block which then writes dt (R22 reading of the paper's time-step rule).
+template <typename T>
+__global__ void __launch_bounds__(256) k_cfl_partial(GridP g, const T* u, const T* v, const T* w, const T* nut,
+                                                     const double* coef, double* part) {
+  __shared__ double sm[2][256];
+  double mc = 0.0, mn = 0.0;
+  const int64_t total = (int64_t)g.nz * g.sxy;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e / g.sxy) + 1;
+    const int64_t c = (int64_t)k * g.sxy + e % g.sxy;
+    const double a = fabs((double)u[c]) * g.rdx + fabs((double)v[c]) * g.rdy + fabs((double)w[c]) / g.dzf[k];
+    mc = fmax(mc, a);
+    mn = fmax(mn, coef[k] * (double)nut[c]);
+  }
+  sm[0][threadIdx.x] = mc;
+  sm[1][threadIdx.x] = mn;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sm[0][threadIdx.x] = fmax(sm[0][threadIdx.x], sm[0][threadIdx.x + s]);
+      sm[1][threadIdx.x] = fmax(sm[1][threadIdx.x], sm[1][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sm[0][0];
+    part[2 * blockIdx.x + 1] = sm[1][0];
+  }
+}
+
+__global__ void k_cfl_final(const double* part, int nblk, double* dtp, double cfl, double nu, double sinv) {
+  if (threadIdx.x != 0) return;
+  double mc = 0.0, mn = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    mc = fmax(mc, part[2 * b]);
+    mn = fmax(mn, part[2 * b + 1]);
+  }
+  const double dtv = 0.95 * 2.51 / (4.0 * (nu + mn) * sinv);
+  const double dtc = mc > 0.0 ? cfl / mc : INFINITY;
+  dtp[0] = fmin(dtc, dtv);
+}
+
+template <typename T>
+void launch_dt(Ctx& c, double cfl) {
+  const int nblk = 512;
+  hipLaunchKernelGGL(k_cfl_partial<T>, dim3(nblk), dim3(256), 0, c.stream, c.g, (const T*)c.u, (const T*)c.v,
+                     (const T*)c.w, (const T*)c.nut, c.t.coef, c.t.red);
+  double sinv = 1.0 / (c.g.dx * c.g.dx) + 1.0 / (c.g.dy * c.g.dy);
+  if (!c.cfg.implicit_z) {
+    double dmin = 1e300;
+    for (int k = 1; k <= c.g.nz; ++k) dmin = std::min(dmin, c.dzf[k]);
+    sinv += 1.0 / (dmin * dmin);
+  }
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, c.stream, c.t.red, nblk, c.t.dt, cfl, c.cfg.nu, sinv);
+}
+
+__global__ void k_set_dt(double* dtp, double dt) {
+  if (threadIdx.x == 0) dtp[0] = dt;
+}
+void launch_set_dt(Ctx& c, double dt) { hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, c.stream, c.t.dt, dt); }
+
+// ============================================================================ diagnostics
+// out: [0] max|div|, [1] sum(u dzf), [2] max |vel|, [3] nonfinite count, [4] sum tau_x bot,
+// [5] sum tau_x top.  Single block, fixed-order (used synchronously by les_diag).
+template <typename T>
+__global__ void k_diag(GridP g, const T* u, const T* v, const T* w, const T* p, const double* tau, double* out) {
+  __shared__ double sm[6][256];
+  double md = 0.0, su = 0.0, mv = 0.0, nf = 0.0, tb = 0.0, tt = 0.0;
+  const bool per = g.zbc == LES_ZBC_PERIODIC;
+  const int64_t total = (int64_t)g.nz * g.sxy;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int k = (int)(e / g.sxy) + 1;
+    const int64_t r = e % g.sxy;
+    const int i = (int)(r % g.nx), j = (int)(r / g.nx);
+    const int64_t c = (int64_t)k * g.sxy + r;
+    const double d = ((double)u[c] - (double)u[idx3(g, k, j, wrap_m(i, g.nx))]) * g.rdx +
+                     ((double)v[c] - (double)v[idx3(g, k, wrap_m(j, g.ny), i)]) * g.rdy +
+                     ((double)w[c] - (double)w[c - g.sxy]) / g.dzf[k];
+    md = fmax(md, fabs(d));
+    su += (double)u[c] * g.dzf[k];
+    mv = fmax(mv, fmax(fabs((double)u[c]), fmax(fabs((double)v[c]), fabs((double)w[c]))));
+    if (!isfinite((double)u[c]) || !isfinite((double)v[c]) || !isfinite((double)w[c]) || !isfinite((double)p[c]))
+      nf += 1.0;
+  }
+  if (!per && tau != nullptr)
+    for (int64_t r = threadIdx.x; r < g.sxy; r += blockDim.x) {
+      tb += tau[r];
+      tt += tau[2 * g.sxy + r];
+    }
+  double vals[6] = {md, su, mv, nf, tb, tt};
+  for (int a = 0; a < 6; ++a) sm[a][threadIdx.x] = vals[a];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sm[0][threadIdx.x] = fmax(sm[0][threadIdx.x], sm[0][threadIdx.x + s]);
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+      sm[2][threadIdx.x] = fmax(sm[2][threadIdx.x], sm[2][threadIdx.x + s]);
+      sm[3][threadIdx.x] += sm[3][threadIdx.x + s];
+      sm[4][threadIdx.x] += sm[4][threadIdx.x + s];
+      sm[5][threadIdx.x] += sm[5][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) out[threadIdx.x] = sm[threadIdx.x][0];
+}
+
+template <typename T>
+void launch_diag(Ctx& c, double* out_dev) {
+  hipLaunchKernelGGL(k_diag<T>, dim3(1), dim3(256), 0, c.stream, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
+                     (const T*)c.p, c.cfg.zbc == LES_ZBC_WALLMODEL ? c.t.tau : nullptr, out_dev);
+}
+
+// ============================================================================ instantiations
+#define INST(T)                                                  \
+  template void launch_predictor<T>(Ctx&, int);                  \
+  template void launch_helmholtz<T>(Ctx&, int);                  \
+  template void launch_correct<T>(Ctx&, int);                    \
+  template void launch_bc_fill<T>(Ctx&, T*, T*, T*, T*);         \
+  template void launch_wallmodel<T>(Ctx&);                       \
+  template void launch_dt<T>(Ctx&, double);                      \
+  template void launch_diag<T>(Ctx&, double*);
+INST(double)
+INST(float)
+
+}  // namespace les

@@ -1,0 +1,278 @@
+"""ctypes binding of the C ABI in include/les.h (argument marshalling only).
+
+Every step of the substep runs in the HIP library liblesmi.so; this module only loads
+it, converts arguments, and lets torch own the device buffers and the stream.  If the
+library is missing the import fails: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "liblesmi.so")
+
+LES_OK, LES_EINVAL, LES_ENOMEM, LES_EDEVICE, LES_ENOTSUP, LES_ENONFINITE, LES_ESTATE = 0, -1, -2, -3, -4, -5, -6
+ZBC_PERIODIC, ZBC_NOSLIP, ZBC_WALLMODEL = 0, 1, 2
+SGS_NONE, SGS_SMAG, SGS_SMAG_VD, SGS_DSM, SGS_MLP = 0, 1, 2, 3, 4
+FP64, MIXED = 0, 1
+FIELD_U, FIELD_V, FIELD_W, FIELD_P, FIELD_WORKSPACE, FIELD_NUT, FIELD_CS, FIELD_TAUW, FIELD_ZGRID = range(9)
+ABI_VERSION = 1
+
+
+class LesConfig(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("lz", ctypes.c_double), ("zbc", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("nu", ctypes.c_double), ("sgs", ctypes.c_int32), ("cs", ctypes.c_double),
+                ("implicit_z", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("ubulk", ctypes.c_double), ("h_wm", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("bconst", ctypes.c_double)]
+
+
+class LesLayout(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("dims", ctypes.c_int64 * 3), ("elem_bytes", ctypes.c_int64), ("bytes", ctypes.c_int64)]
+
+
+class LesDiag(ctypes.Structure):
+    _fields_ = [("max_div", ctypes.c_double), ("ubulk", ctypes.c_double), ("max_vel", ctypes.c_double),
+                ("tauw_mean", ctypes.c_double * 2), ("dt", ctypes.c_double),
+                ("nonfinite", ctypes.c_int64), ("mlp_flagged", ctypes.c_int64)]
+
+
+class LesError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"HIP library not built: {LIBPATH} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIBPATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "les_init": [ctypes.POINTER(LesConfig), vp, ctypes.POINTER(vp)],
+        "les_layout": [vp, i32, ctypes.POINTER(LesLayout)],
+        "les_bind": [vp, i32, vp],
+        "les_nut": [vp],
+        "les_dt": [vp, dbl, ctypes.POINTER(dbl)],
+        "les_set_dt": [vp, dbl],
+        "les_substep": [vp, i32],
+        "les_step": [vp, i32],
+        "les_poisson": [vp, vp],
+        "les_read": [vp, i32, vp],
+        "les_diag": [vp, ctypes.POINTER(LesDiag)],
+        "les_mlp_bind": [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
+        "les_mlp_sample": [vp, ctypes.c_uint64, ctypes.c_int64, vp, vp],
+        "les_mlp_train_step": [vp, vp, vp, ctypes.c_int64, ctypes.c_float, i32, vp, vp, vp],
+        "les_free": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.les_strerror.argtypes = [ctypes.c_int]
+    lib.les_strerror.restype = ctypes.c_char_p
+    lib.les_last_error.argtypes = [vp]
+    lib.les_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+LIB = _load()
+
+
+def exported_symbols():
+    """Names of the ABI functions the binding resolves (all must exist in the library)."""
+    return ["les_init", "les_layout", "les_bind", "les_nut", "les_dt", "les_set_dt", "les_substep",
+            "les_step", "les_poisson", "les_read", "les_diag", "les_mlp_bind", "les_mlp_sample",
+            "les_mlp_train_step", "les_free", "les_strerror", "les_last_error"]
+
+
+def make_config(nx, ny, nz, lx, ly, lz, zbc=ZBC_PERIODIC, beta=0.0, nu=1e-3, sgs=SGS_NONE, cs=0.17,
+                implicit_z=0, precision=FP64, ubulk=0.0, h_wm=0.0, kappa=0.41, bconst=5.2):
+    return LesConfig(ABI_VERSION, nx, ny, nz, lx, ly, lz, zbc, beta, nu, sgs, cs, int(implicit_z),
+                     precision, ubulk, h_wm, kappa, bconst)
+
+
+def _check(ctx, st, what):
+    if st != LES_OK:
+        detail = LIB.les_last_error(ctx).decode() if ctx else LIB.les_strerror(st).decode()
+        raise LesError(st, f"{what}: {detail or LIB.les_strerror(st).decode()}")
+
+
+# ---------------------------------------------------------------- thin wrappers (same names)
+def les_init(cfg, stream_handle=0):
+    out = ctypes.c_void_p()
+    st = LIB.les_init(ctypes.byref(cfg), ctypes.c_void_p(stream_handle), ctypes.byref(out))
+    if st != LES_OK:
+        raise LesError(st, f"les_init: {LIB.les_strerror(st).decode()}")
+    return out
+
+
+def les_layout(ctx, field):
+    lay = LesLayout()
+    _check(ctx, LIB.les_layout(ctx, field, ctypes.byref(lay)), "les_layout")
+    return lay
+
+
+def les_bind(ctx, field, ptr):
+    _check(ctx, LIB.les_bind(ctx, field, ctypes.c_void_p(ptr)), "les_bind")
+
+
+def les_nut(ctx):
+    _check(ctx, LIB.les_nut(ctx), "les_nut")
+
+
+def les_dt(ctx, cfl, sync=True):
+    out = ctypes.c_double(0.0)
+    _check(ctx, LIB.les_dt(ctx, cfl, ctypes.byref(out) if sync else None), "les_dt")
+    return out.value if sync else None
+
+
+def les_set_dt(ctx, dt):
+    _check(ctx, LIB.les_set_dt(ctx, dt), "les_set_dt")
+
+
+def les_substep(ctx, stage):
+    _check(ctx, LIB.les_substep(ctx, stage), "les_substep")
+
+
+def les_step(ctx, use_graph=False):
+    _check(ctx, LIB.les_step(ctx, 1 if use_graph else 0), "les_step")
+
+
+def les_poisson(ctx, ptr):
+    _check(ctx, LIB.les_poisson(ctx, ctypes.c_void_p(ptr)), "les_poisson")
+
+
+def les_read(ctx, field, ptr):
+    _check(ctx, LIB.les_read(ctx, field, ctypes.c_void_p(ptr)), "les_read")
+
+
+def les_diag(ctx):
+    d = LesDiag()
+    st = LIB.les_diag(ctx, ctypes.byref(d))
+    if st not in (LES_OK, LES_ENONFINITE):
+        _check(ctx, st, "les_diag")
+    return d, st
+
+
+def les_free(ctx):
+    _check(None, LIB.les_free(ctx), "les_free")
+
+
+# ---------------------------------------------------------------- torch-owned solver
+class Solver:
+    """One context with torch-allocated fields and workspace on its own stream.
+
+    Fields are torch tensors of shape (nz + 2, ny, nx) in the context's storage type.
+    """
+
+    def __init__(self, cfg, device="cuda"):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.stream = torch.cuda.Stream(device=device)
+        self.ctx = les_init(cfg, self.stream.cuda_stream)
+        lay = les_layout(self.ctx, FIELD_U)
+        self.dtype = torch.float64 if lay.elem_bytes == 8 else torch.float32
+        self.shape = (cfg.nz + 2, cfg.ny, cfg.nx)
+        with torch.cuda.stream(self.stream):
+            self.u, self.v, self.w, self.p = (torch.zeros(self.shape, dtype=self.dtype, device=device)
+                                              for _ in range(4))
+            wsb = les_layout(self.ctx, FIELD_WORKSPACE).bytes
+            self.workspace = torch.empty(wsb + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        for f, t in ((FIELD_U, self.u), (FIELD_V, self.v), (FIELD_W, self.w), (FIELD_P, self.p)):
+            les_bind(self.ctx, f, t.data_ptr())
+        self.stream.synchronize()
+        les_bind(self.ctx, FIELD_WORKSPACE, base + off)
+        self.workspace_bytes = wsb
+
+    def set_state(self, u, v, w, p=None):
+        """Copy host arrays (numpy, field shape) into the device fields."""
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            for dst, src in ((self.u, u), (self.v, v), (self.w, w), (self.p, p)):
+                if src is None:
+                    dst.zero_()
+                else:
+                    dst.copy_(torch.as_tensor(src, dtype=self.dtype))
+        self.stream.synchronize()
+
+    def nut(self):
+        les_nut(self.ctx)
+
+    def set_dt(self, dt):
+        les_set_dt(self.ctx, dt)
+
+    def dt(self, cfl=0.5):
+        return les_dt(self.ctx, cfl)
+
+    def substep(self, stage):
+        les_substep(self.ctx, stage)
+
+    def step(self, use_graph=False):
+        les_step(self.ctx, use_graph)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def fields(self):
+        """Host float64 copies of u, v, w, p."""
+        self.synchronize()
+        return tuple(t.double().cpu().numpy() for t in (self.u, self.v, self.w, self.p))
+
+    def eddy_viscosity(self):
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            out = torch.empty(self.shape, dtype=self.dtype, device=self.u.device)
+        les_read(self.ctx, FIELD_NUT, out.data_ptr())
+        self.synchronize()
+        return out.double().cpu().numpy()
+
+    def coefficient(self):
+        torch = self.torch
+        out = torch.empty(self.cfg.nz, dtype=torch.float64, device=self.u.device)
+        les_read(self.ctx, FIELD_CS, out.data_ptr())
+        self.synchronize()
+        return out.cpu().numpy()
+
+    def wall_stress(self):
+        torch = self.torch
+        out = torch.empty((4, self.cfg.ny, self.cfg.nx), dtype=torch.float64, device=self.u.device)
+        les_read(self.ctx, FIELD_TAUW, out.data_ptr())
+        self.synchronize()
+        return out.cpu().numpy()
+
+    def zgrid(self):
+        import numpy as np
+        buf = np.zeros(2 * self.cfg.nz + 3)
+        les_read(self.ctx, FIELD_ZGRID, buf.ctypes.data)
+        return buf[:self.cfg.nz + 1], buf[self.cfg.nz + 1:]
+
+    def poisson(self, f):
+        """Solve D G phi = f for a host array f (field shape); returns phi (host)."""
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            t = torch.as_tensor(f, dtype=self.dtype).to(self.u.device)
+        self.stream.synchronize()
+        les_poisson(self.ctx, t.data_ptr())
+        self.synchronize()
+        return t.double().cpu().numpy()
+
+    def diag(self):
+        return les_diag(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            self.synchronize()
+            les_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
