@@ -188,6 +188,16 @@ les_status les_mlp_train_step(les_ctx* ctx, const float* x_dev, const float* y_d
                               int64_t n, float lr, int step, float* m_dev, float* v_dev,
                               float* loss_dev);
 
+/* Per-kernel timing.  les_timing(ctx, 1) starts recording: every kernel the context
+ * enqueues afterwards is bracketed by two HIP events on the context stream and tagged with
+ * its algorithmic byte count (each array the kernel reads or writes counted once).
+ * les_timing(ctx, 0) stops recording.  Recording is refused inside les_step's graph
+ * capture (LES_ESTATE).  les_timing_report synchronises, writes a JSON object
+ * {"kernel": {"count": n, "ms": total_ms, "bytes": total_bytes}, ...} into buf (len
+ * bytes, NUL-terminated; LES_ENOMEM if too short) and clears the records. */
+les_status les_timing(les_ctx* ctx, int enable);
+les_status les_timing_report(les_ctx* ctx, char* buf, size_t len);
+
 /* Destroy the context (does not free caller memory). */
 les_status les_free(les_ctx* ctx);
 

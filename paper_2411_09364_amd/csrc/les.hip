@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -470,6 +471,7 @@ les_status les_step(les_ctx* ctx, int use_graph) {
     return LES_OK;
   }
   if (!c.stream) return fail(&c, LES_EINVAL, "graph replay needs a non-default stream");
+  if (c.timing) return fail(&c, LES_ESTATE, "timing cannot be recorded into a graph");
   if (!c.graph_exec) {
     if ((s = check_hip(c, hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal), "begin capture")) != LES_OK)
       return s;
@@ -566,9 +568,63 @@ les_status les_mlp_train_step(les_ctx* ctx, const float*, const float*, int64_t,
   return fail(&ctx->c, LES_ENOTSUP, "learned closure not built");
 }
 
+static void clear_timing(Ctx& c) {
+  for (auto& t : c.timed) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  c.timed.clear();
+}
+
+les_status les_timing(les_ctx* ctx, int enable) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  if (enable && !c.timing) clear_timing(c);
+  c.timing = enable != 0;
+  return LES_OK;
+}
+
+les_status les_timing_report(les_ctx* ctx, char* buf, size_t len) {
+  if (!ctx || !buf || len == 0) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  les_status s = check_hip(c, hipStreamSynchronize(c.stream), "timing sync");
+  if (s != LES_OK) return s;
+  struct Acc {
+    std::string name;
+    long count;
+    double ms, bytes;
+  };
+  std::vector<Acc> acc;
+  for (auto& t : c.timed) {
+    float ms = 0.f;
+    if ((s = check_hip(c, hipEventElapsedTime(&ms, t.a, t.b), "event time")) != LES_OK) return s;
+    auto it = std::find_if(acc.begin(), acc.end(), [&](const Acc& a) { return a.name == t.name; });
+    if (it == acc.end()) {
+      acc.push_back({t.name, 0, 0.0, 0.0});
+      it = acc.end() - 1;
+    }
+    it->count += 1;
+    it->ms += ms;
+    it->bytes += t.bytes;
+  }
+  std::string out = "{";
+  for (size_t i = 0; i < acc.size(); ++i) {
+    char tmp[256];
+    std::snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"count\": %ld, \"ms\": %.6f, \"bytes\": %.0f}", i ? ", " : "",
+                  acc[i].name.c_str(), acc[i].count, acc[i].ms, acc[i].bytes);
+    out += tmp;
+  }
+  out += "}";
+  clear_timing(c);
+  if (out.size() + 1 > len) return fail(&c, LES_ENOMEM, "timing report buffer too small");
+  std::memcpy(buf, out.c_str(), out.size() + 1);
+  return LES_OK;
+}
+
 les_status les_free(les_ctx* ctx) {
   if (!ctx) return LES_EINVAL;
   Ctx& c = ctx->c;
+  clear_timing(c);
   if (c.graph_exec) hipGraphExecDestroy(c.graph_exec);
   if (c.graph) hipGraphDestroy(c.graph);
   delete ctx;

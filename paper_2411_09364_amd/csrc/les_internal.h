@@ -101,6 +101,14 @@ struct Ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool initialised = false;  // les_nut called
+  // per-launch timing (HIP events on the context stream), enabled by les_timing
+  struct Timed {
+    const char* name;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool timing = false;
+  std::vector<Timed> timed;
   std::string err;
 };
 
@@ -120,6 +128,24 @@ template <typename T> void launch_read_nut(Ctx& c, T* dst);
 template <typename T> void launch_diag(Ctx& c, double* out_dev);
 void launch_set_dt(Ctx& c, double dt);
 void launch_helmholtz_factor(Ctx& c, int stage);
+
+// Kernel launch on the context stream.  With timing enabled the launch is bracketed by
+// two HIP events and tagged with its algorithmic byte count (minimum HBM traffic of the
+// kernel as designed: each input and output array touched once).
+#define LES_LAUNCH(ctx, name, bytes, kernel, grid, block, shmem, ...)                          \
+  do {                                                                                          \
+    hipEvent_t les_ev_a_ = nullptr, les_ev_b_ = nullptr;                                        \
+    if ((ctx).timing) {                                                                         \
+      hipEventCreate(&les_ev_a_);                                                               \
+      hipEventCreate(&les_ev_b_);                                                               \
+      hipEventRecord(les_ev_a_, (ctx).stream);                                                  \
+    }                                                                                           \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, (ctx).stream, __VA_ARGS__);                  \
+    if ((ctx).timing) {                                                                         \
+      hipEventRecord(les_ev_b_, (ctx).stream);                                                  \
+      (ctx).timed.push_back({name, les_ev_a_, les_ev_b_, (double)(bytes)});                     \
+    }                                                                                           \
+  } while (0)
 
 // launch geometry for one-thread-per-point kernels over interior planes
 struct Launch3 {

@@ -442,14 +442,16 @@ static void fwd_x(Ctx& c, int mode, const T* us, const T* vs, const T* ws, const
   const unsigned nblk = (unsigned)((npairs + pb - 1) / pb);
   const size_t sh = 2 * (size_t)pb * c.g.nx * sizeof(cpx<T>);
   double* bp = bulk ? c.t.bulk : nullptr;
+  const double spec_bytes = (double)(c.g.nx / 2 + 1) * c.g.ny * c.g.nz * 2 * sizeof(T);
+  const double in_bytes = (mode == 0 ? 3.0 : 1.0) * c.g.sxy * c.g.nz * sizeof(T);
   if (mode == 0)
-    hipLaunchKernelGGL((k_rfftx<T, 0>), dim3(nblk), dim3(256), sh, c.stream, c.g, P, us, vs, ws, fin,
+    LES_LAUNCH(c, "rfftx_div", in_bytes + spec_bytes, (k_rfftx<T, 0>), dim3(nblk), dim3(256), sh, c.g, P, us, vs, ws, fin,
                        (cpx<T>*)c.spec, c.t.twx, c.t.twx_f, c.t.dt, gamma, pb, bp);
   else
-    hipLaunchKernelGGL((k_rfftx<T, 1>), dim3(nblk), dim3(256), sh, c.stream, c.g, P, us, vs, ws, fin,
+    LES_LAUNCH(c, "rfftx", in_bytes + spec_bytes, (k_rfftx<T, 1>), dim3(nblk), dim3(256), sh, c.g, P, us, vs, ws, fin,
                        (cpx<T>*)c.spec, c.t.twx, c.t.twx_f, c.t.dt, gamma, pb, bp);
   if (bulk)
-    hipLaunchKernelGGL(k_bulk_final, dim3(1), dim3(64), 0, c.stream, c.t.bulk, (int)nblk, c.t.dt,
+    LES_LAUNCH(c, "bulk_final", 0, k_bulk_final, dim3(1), dim3(64), 0, c.t.bulk, (int)nblk, c.t.dt,
                        c.t.hfac + 4 * c.g.nz, c.t.dzf, c.g.nz, c.cfg.ubulk, (double)c.g.sxy, c.cfg.lz);
 }
 
@@ -458,13 +460,14 @@ static void spectral_solve(Ctx& c) {
   const int nxh = c.g.nx / 2 + 1;
   const int ny = c.g.ny, nz = c.g.nz;
   cpx<T>* sp = (cpx<T>*)c.spec;
+  const double spec_bytes = (double)nxh * ny * nz * 2 * sizeof(T);
   // y transform
   {
     const FftPlan P = make_plan(ny);
     const int L = lines_per_block(ny);
     dim3 grid((nxh + L - 1) / L, nz);
     const size_t sh = 2 * (size_t)L * ny * sizeof(cpx<T>);
-    hipLaunchKernelGGL((k_fft_lines<T, -1, false>), grid, dim3(256), sh, c.stream, P, sp, nxh, (int64_t)nxh,
+    LES_LAUNCH(c, "ffty_fwd", 2 * spec_bytes, (k_fft_lines<T, -1, false>), grid, dim3(256), sh, P, sp, nxh, (int64_t)nxh,
                        (int64_t)nxh * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
   }
   if (c.cfg.zbc == LES_ZBC_PERIODIC) {
@@ -473,7 +476,7 @@ static void spectral_solve(Ctx& c) {
     dim3 grid((nxh + L - 1) / L, ny);
     const size_t sh = 2 * (size_t)L * nz * sizeof(cpx<T>);
     const double norm = 1.0 / ((double)c.g.nx * ny * nz);
-    hipLaunchKernelGGL((k_fft_lines<T, -1, true>), grid, dim3(256), sh, c.stream, P, sp, nxh, (int64_t)nxh * ny,
+    LES_LAUNCH(c, "fftz_solve", 2 * spec_bytes, (k_fft_lines<T, -1, true>), grid, dim3(256), sh, P, sp, nxh, (int64_t)nxh * ny,
                        (int64_t)nxh, L, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy, c.t.lamz, norm);
   } else {
     const int64_t ncol = (int64_t)nxh * ny;
@@ -482,7 +485,8 @@ static void spectral_solve(Ctx& c) {
     const size_t sh = (size_t)tpb * nz * sizeof(T);
     const double norm = 1.0 / ((double)c.g.nx * ny);
     double* zcol = c.t.zcol;
-    hipLaunchKernelGGL((k_thomas<T, T>), dim3((unsigned)((ncol + tpb - 1) / tpb)), dim3(tpb), sh, c.stream, c.g, sp,
+    LES_LAUNCH(c, "thomas_z", 2 * spec_bytes, (k_thomas<T, T>), dim3((unsigned)((ncol + tpb - 1) / tpb)), dim3(tpb), sh,
+               c.g, sp,
                        c.t.pa, c.t.pb, c.t.pc, c.t.lamx, c.t.lamy, norm, zcol);
   }
   {
@@ -490,7 +494,7 @@ static void spectral_solve(Ctx& c) {
     const int L = lines_per_block(ny);
     dim3 grid((nxh + L - 1) / L, nz);
     const size_t sh = 2 * (size_t)L * ny * sizeof(cpx<T>);
-    hipLaunchKernelGGL((k_fft_lines<T, 1, false>), grid, dim3(256), sh, c.stream, P, sp, nxh, (int64_t)nxh,
+    LES_LAUNCH(c, "ffty_inv", 2 * spec_bytes, (k_fft_lines<T, 1, false>), grid, dim3(256), sh, P, sp, nxh, (int64_t)nxh,
                        (int64_t)nxh * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
   }
 }
@@ -502,7 +506,9 @@ static void inv_x(Ctx& c, T* out) {
   const int64_t npairs = (int64_t)c.g.nz * (c.g.ny / 2);
   const unsigned nblk = (unsigned)((npairs + pb - 1) / pb);
   const size_t sh = 2 * (size_t)pb * c.g.nx * sizeof(cpx<T>);
-  hipLaunchKernelGGL((k_irfftx<T>), dim3(nblk), dim3(256), sh, c.stream, c.g, P, (const cpx<T>*)c.spec, out,
+  const double spec_bytes = (double)(c.g.nx / 2 + 1) * c.g.ny * c.g.nz * 2 * sizeof(T);
+  LES_LAUNCH(c, "irfftx", spec_bytes + (double)c.g.sxy * c.g.nz * sizeof(T), (k_irfftx<T>), dim3(nblk), dim3(256), sh,
+             c.g, P, (const cpx<T>*)c.spec, out,
                      c.t.twx, c.t.twx_f, pb);
 }
 
@@ -527,7 +533,8 @@ void launch_poisson_field(Ctx& c, T* f) {
   fwd_x<T>(c, 1, nullptr, nullptr, nullptr, f, 1.0, false);
   spectral_solve<T>(c);
   inv_x<T>(c, f);
-  hipLaunchKernelGGL(k_scalar_ghosts<T>, dim3((unsigned)((c.g.sxy + 255) / 256)), dim3(256), 0, c.stream, c.g, f);
+  LES_LAUNCH(c, "scalar_ghosts", 4.0 * c.g.sxy * sizeof(T), k_scalar_ghosts<T>, dim3((unsigned)((c.g.sxy + 255) / 256)),
+             dim3(256), 0, c.g, f);
 }
 
 #define INST(T)                                                                              \

@@ -378,11 +378,12 @@ void launch_eddy_viscosity(Ctx& c) {
   Launch3 L = point_launch(g, g.nz);
   const int model = c.cfg.sgs;
   if (model == LES_SGS_NONE) return;
+  const double pts = (double)g.sxy * g.nz;
   if (model == LES_SGS_SMAG || model == LES_SGS_SMAG_VD) {
-    hipLaunchKernelGGL(k_strain_mag<T>, L.grid, L.block, 0, c.stream, g, (const T*)c.u, (const T*)c.v,
+    LES_LAUNCH(c, "strain_mag", 4 * pts * sizeof(T), k_strain_mag<T>, L.grid, L.block, 0, g, (const T*)c.u, (const T*)c.v,
                        (const T*)c.w, (T*)c.nut);
     if (model == LES_SGS_SMAG_VD && c.cfg.zbc != LES_ZBC_PERIODIC)
-      hipLaunchKernelGGL(k_vd_coef<T>, dim3(1), dim3(256), 0, c.stream, g, (const T*)c.u, (const T*)c.v, c.t.tau,
+      LES_LAUNCH(c, "vd_coef", 0, k_vd_coef<T>, dim3(1), dim3(256), 0, g, (const T*)c.u, (const T*)c.v, c.t.tau,
                          c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.cfg.cs, c.t.coef);
     return;
   }
@@ -390,14 +391,14 @@ void launch_eddy_viscosity(Ctx& c) {
     const int64_t fs = (int64_t)c.field_elems;
     T* q9 = (T*)c.q9;
     T* fv = (T*)c.fvel;
-    hipLaunchKernelGGL(k_dsm_centre<T>, L.grid, L.block, 0, c.stream, g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
+    LES_LAUNCH(c, "dsm_centre", 13 * pts * sizeof(T), k_dsm_centre<T>, L.grid, L.block, 0, g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
                        (T*)c.nut, q9, fs);
-    hipLaunchKernelGGL(k_dsm_fvel<T>, L.grid, L.block, 0, c.stream, g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
+    LES_LAUNCH(c, "dsm_fvel", 6 * pts * sizeof(T), k_dsm_fvel<T>, L.grid, L.block, 0, g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
                        fv, fv + fs, fv + 2 * fs);
-    hipLaunchKernelGGL(k_dsm_lm<T>, L.grid, L.block, 0, c.stream, g, (const T*)q9, fs, (const T*)fv,
+    LES_LAUNCH(c, "dsm_lm", 12 * pts * sizeof(T), k_dsm_lm<T>, L.grid, L.block, 0, g, (const T*)q9, fs, (const T*)fv,
                        (const T*)(fv + fs), (const T*)(fv + 2 * fs), c.t.dsm_part);
     const int ntile = (int)(L.grid.x * L.grid.y);
-    hipLaunchKernelGGL(k_dsm_reduce, dim3(1), dim3(256), 0, c.stream, g, c.t.dsm_part, ntile, c.t.cs, c.t.coef);
+    LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(1), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs, c.t.coef);
   }
 }
 
@@ -412,7 +413,7 @@ __global__ void k_read_nut(GridP g, const T* nut, const double* coef, T* dst, in
 template <typename T>
 void launch_read_nut(Ctx& c, T* dst) {
   const int64_t n = (int64_t)c.field_elems;
-  hipLaunchKernelGGL(k_read_nut<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, c.g,
+  LES_LAUNCH(c, "read_nut", 2.0 * n * sizeof(T), k_read_nut<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.g,
                      (const T*)c.nut, c.t.coef, dst, n);
 }
 

@@ -187,7 +187,9 @@ void launch_predictor(Ctx& c, int stage) {
   const int use_rprev = stage > 0;
   const int write_r = stage < 2;
   auto f = c.cfg.implicit_z ? k_predictor<T, true> : k_predictor<T, false>;
-  hipLaunchKernelGGL(f, L.grid, L.block, 0, c.stream, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
+  const double pts = (double)c.g.sxy * c.g.nz;
+  const double words = 8 + 3 * use_rprev + 3 * write_r;
+  LES_LAUNCH(c, "predictor", words * pts * sizeof(T), f, L.grid, L.block, 0, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
                      (const T*)c.p, (const T*)c.nut, c.t.coef, (T*)c.ru, (T*)c.rv, (T*)c.rw, (T*)c.us, (T*)c.vs,
                      (T*)c.wsf, c.t.dt, A[stage], B[stage], G, use_rprev, write_r);
 }
@@ -254,7 +256,7 @@ __global__ void k_helmholtz_factor(GridP g, double* hfac, const double* dtp, dou
 
 void launch_helmholtz_factor(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
-  hipLaunchKernelGGL(k_helmholtz_factor, dim3(1), dim3(64), 0, c.stream, c.g, c.t.hfac, c.t.dt, G[stage],
+  LES_LAUNCH(c, "helmholtz_factor", 0, k_helmholtz_factor, dim3(1), dim3(64), 0, c.g, c.t.hfac, c.t.dt, G[stage],
                      c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);
 }
 
@@ -305,7 +307,7 @@ void launch_helmholtz(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
   launch_helmholtz_factor(c, stage);
   dim3 block(256), grid((unsigned)((c.g.sxy + 255) / 256), 3);
-  hipLaunchKernelGGL(k_helmholtz<T>, grid, block, 0, c.stream, c.g, (T*)c.us, (T*)c.vs, (T*)c.wsf, c.t.hfac,
+  LES_LAUNCH(c, "helmholtz_z", 6.0 * c.g.sxy * c.g.nz * sizeof(T), k_helmholtz<T>, grid, block, 0, c.g, (T*)c.us, (T*)c.vs, (T*)c.wsf, c.t.hfac,
                      c.t.tau, c.t.dt, G[stage], c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);
 }
 
@@ -338,8 +340,8 @@ __global__ void k_bc_fill(GridP g, T* u, T* v, T* w, T* p) {
 
 template <typename T>
 void launch_bc_fill(Ctx& c, T* u, T* v, T* w, T* p) {
-  hipLaunchKernelGGL(k_bc_fill<T>, dim3((unsigned)((c.g.sxy + 255) / 256)), dim3(256), 0, c.stream, c.g, u, v, w,
-                     p);
+  LES_LAUNCH(c, "bc_fill", 14.0 * c.g.sxy * sizeof(T), k_bc_fill<T>, dim3((unsigned)((c.g.sxy + 255) / 256)),
+             dim3(256), 0, c.g, u, v, w, p);
 }
 
 // ============================================================================ correction
@@ -400,7 +402,7 @@ void launch_correct(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
   Launch3 L = point_launch(c.g, c.g.nz);
   const double* q = c.cfg.ubulk > 0.0 ? c.t.hfac + 4 * c.g.nz : nullptr;
-  hipLaunchKernelGGL(k_correct<T>, L.grid, L.block, 0, c.stream, c.g, (const T*)c.us, (const T*)c.vs,
+  LES_LAUNCH(c, "correct", 9.0 * c.g.sxy * c.g.nz * sizeof(T), k_correct<T>, L.grid, L.block, 0, c.g, (const T*)c.us, (const T*)c.vs,
                      (const T*)c.wsf, (const T*)c.phi, (T*)c.u, (T*)c.v, (T*)c.w, (T*)c.p, c.t.dt, q, G[stage],
                      c.cfg.implicit_z);
 }
@@ -482,7 +484,7 @@ void launch_wallmodel(Ctx& c) {
     hb = ht = h;
   }
   dim3 grid((unsigned)((c.g.sxy + 255) / 256), 4);
-  hipLaunchKernelGGL(k_wallmodel<T>, grid, dim3(256), 0, c.stream, c.g, (T*)c.u, (T*)c.v, c.t.tau, c.t.utau, kb0,
+  LES_LAUNCH(c, "wallmodel", c.g.sxy * (8.0 * sizeof(T) + 4 * 3 * 8.0), k_wallmodel<T>, grid, dim3(256), 0, c.g, (T*)c.u, (T*)c.v, c.t.tau, c.t.utau, kb0,
                      kb1, tb, hb, kt0, kt1, tt, ht, c.cfg.kappa, c.cfg.bconst);
 }
 
@@ -533,7 +535,7 @@ __global__ void k_cfl_final(const double* part, int nblk, double* dtp, double cf
 template <typename T>
 void launch_dt(Ctx& c, double cfl) {
   const int nblk = 512;
-  hipLaunchKernelGGL(k_cfl_partial<T>, dim3(nblk), dim3(256), 0, c.stream, c.g, (const T*)c.u, (const T*)c.v,
+  LES_LAUNCH(c, "cfl_partial", 4.0 * c.g.sxy * c.g.nz * sizeof(T), k_cfl_partial<T>, dim3(nblk), dim3(256), 0, c.g, (const T*)c.u, (const T*)c.v,
                      (const T*)c.w, (const T*)c.nut, c.t.coef, c.t.red);
   double sinv = 1.0 / (c.g.dx * c.g.dx) + 1.0 / (c.g.dy * c.g.dy);
   if (!c.cfg.implicit_z) {
@@ -541,13 +543,13 @@ void launch_dt(Ctx& c, double cfl) {
     for (int k = 1; k <= c.g.nz; ++k) dmin = std::min(dmin, c.dzf[k]);
     sinv += 1.0 / (dmin * dmin);
   }
-  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, c.stream, c.t.red, nblk, c.t.dt, cfl, c.cfg.nu, sinv);
+  LES_LAUNCH(c, "cfl_final", 0, k_cfl_final, dim3(1), dim3(64), 0, c.t.red, nblk, c.t.dt, cfl, c.cfg.nu, sinv);
 }
 
 __global__ void k_set_dt(double* dtp, double dt) {
   if (threadIdx.x == 0) dtp[0] = dt;
 }
-void launch_set_dt(Ctx& c, double dt) { hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, c.stream, c.t.dt, dt); }
+void launch_set_dt(Ctx& c, double dt) { LES_LAUNCH(c, "set_dt", 0, k_set_dt, dim3(1), dim3(64), 0, c.t.dt, dt); }
 
 // ============================================================================ diagnostics
 // out: [0] max|div|, [1] sum(u dzf), [2] max |vel|, [3] nonfinite count, [4] sum tau_x bot,
@@ -596,7 +598,7 @@ __global__ void k_diag(GridP g, const T* u, const T* v, const T* w, const T* p, 
 
 template <typename T>
 void launch_diag(Ctx& c, double* out_dev) {
-  hipLaunchKernelGGL(k_diag<T>, dim3(1), dim3(256), 0, c.stream, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
+  LES_LAUNCH(c, "diag", 0, k_diag<T>, dim3(1), dim3(256), 0, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
                      (const T*)c.p, c.cfg.zbc == LES_ZBC_WALLMODEL ? c.t.tau : nullptr, out_dev);
 }
 

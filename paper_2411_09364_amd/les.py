@@ -66,6 +66,8 @@ def _load():
         "les_mlp_sample": [vp, ctypes.c_uint64, ctypes.c_int64, vp, vp],
         "les_mlp_train_step": [vp, vp, vp, ctypes.c_int64, ctypes.c_float, i32, vp, vp, vp],
         "les_free": [vp],
+        "les_timing": [vp, i32],
+        "les_timing_report": [vp, ctypes.c_char_p, ctypes.c_size_t],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -85,7 +87,8 @@ def exported_symbols():
     """Names of the ABI functions the binding resolves (all must exist in the library)."""
     return ["les_init", "les_layout", "les_bind", "les_nut", "les_dt", "les_set_dt", "les_substep",
             "les_step", "les_poisson", "les_read", "les_diag", "les_mlp_bind", "les_mlp_sample",
-            "les_mlp_train_step", "les_free", "les_strerror", "les_last_error"]
+            "les_mlp_train_step", "les_free", "les_strerror", "les_last_error", "les_timing",
+            "les_timing_report"]
 
 
 def make_config(nx, ny, nz, lx, ly, lz, zbc=ZBC_PERIODIC, beta=0.0, nu=1e-3, sgs=SGS_NONE, cs=0.17,
@@ -155,6 +158,17 @@ def les_diag(ctx):
     if st not in (LES_OK, LES_ENONFINITE):
         _check(ctx, st, "les_diag")
     return d, st
+
+
+def les_timing(ctx, enable):
+    _check(ctx, LIB.les_timing(ctx, 1 if enable else 0), "les_timing")
+
+
+def les_timing_report(ctx):
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(ctx, LIB.les_timing_report(ctx, buf, len(buf)), "les_timing_report")
+    return json.loads(buf.value.decode())
 
 
 def les_free(ctx):

@@ -6,6 +6,10 @@ Tolerances (max |gpu - oracle| / max |oracle| per field, interior planes):
              roundoff amplified at most by the Poisson solve's conditioning.
   mixed path 1e-5 per substep, the oracle started from the float32-rounded state; float32
              roundoff (6e-8) through ~10 chained stencil/FFT operations with magnitude growth.
+             The pressure is compared on the dynamic-pressure scale max|u|^2: rounding u* to
+             float32 (relative 6e-8) leaves a spurious divergence that the projection turns
+             into a pressure error of order 6e-8 |u|^2 / (gamma_k CFL), independent of how
+             small the pressure itself is.
 Sizes span several 64x4 tiles with ragged tails in x and y, radix-3 FFT lengths and
 stretched walls, and stay small enough for the oracle to finish in seconds.
 """
@@ -71,9 +75,9 @@ NUT_CASES = [
     ("dsm-periodic", dict(nx=24, ny=24, nz=24, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, sgs=SGS_DSM), "iso"),
     ("dsm-noslip", dict(nx=96, ny=12, nz=10, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_NOSLIP, beta=1.5,
                         sgs=SGS_DSM), "random"),
-    ("dsm-wm", dict(nx=48, ny=20, nz=12, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5,
+    ("dsm-wm", dict(nx=48, ny=24, nz=12, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5,
                     nu=5e-5, sgs=SGS_DSM), "channel"),
-    ("dsm-wm-hwm", dict(nx=48, ny=20, nz=16, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.0,
+    ("dsm-wm-hwm", dict(nx=48, ny=12, nz=16, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.0,
                         nu=5e-5, sgs=SGS_SMAG_VD, cs=0.1, h_wm=0.2), "channel"),
 ]
 
@@ -199,9 +203,10 @@ def test_mixed_precision_substeps(les, name, cfgd, kind):
         st = S.substep(case, g, st, k, dt)
         solver.substep(k)
         gu, gv, gw, gp = solver.fields()
-        errs = dict(u=rel_err(gu, st.u, I), v=rel_err(gv, st.v, I), w=rel_err(gw, st.w, I),
-                    p=rel_err(mean_free(gp, g), mean_free(st.p, g), I))
+        umax2 = max(np.max(np.abs(st.u[I])), np.max(np.abs(st.v[I])), np.max(np.abs(st.w[I]))) ** 2
+        dp = np.max(np.abs(mean_free(gp, g)[I] - mean_free(st.p, g)[I])) / umax2
+        errs = dict(u=rel_err(gu, st.u, I), v=rel_err(gv, st.v, I), w=rel_err(gw, st.w, I), p=dp)
         say(f"  substep {k}: " + " ".join(f"{a}={b:.2e}" for a, b in errs.items()))
         for a, e in errs.items():
-            assert e < 1e-5 * (k + 1), (k, a, e)
+            assert e < 1e-5, (k, a, e)
     solver.close()
