@@ -174,8 +174,12 @@ size_t carve(Ctx& c, char* base) {
   t.zcol = (double*)take(3 * n * 8);
   t.tau = (double*)take(4 * sxy * 8);
   t.utau = (double*)take(4 * sxy * 8);
-  Launch3 L = point_launch(c.g, n);
-  t.nblk_xy = (int)(L.grid.x * L.grid.y);
+  // plane partial sums: one per x-y tile of the fused dynamic-model kernel (32 x 8)
+  t.nblk_xy = ((f.nx + 31) / 32) * ((f.ny + 7) / 8);
+  {
+    const int64_t want = (int64_t)n * t.nblk_xy / 1024;   // aim at >= 1024 blocks
+    c.dsm_kc = (int)std::max<int64_t>(8, std::min<int64_t>(n, want));
+  }
   t.dsm_part = (double*)take((size_t)2 * n * t.nblk_xy * 8);
   c.ru = take(F * E);
   c.rv = take(F * E);
@@ -186,12 +190,6 @@ size_t carve(Ctx& c, char* base) {
   c.nut = take(F * E);
   c.phi = take(F * E);
   c.spec = take((size_t)(f.nx / 2 + 1) * f.ny * n * 2 * E);
-  if (f.sgs == LES_SGS_DSM || f.sgs == LES_SGS_MLP) {
-    c.q9 = take(9 * F * E);
-    c.fvel = take(3 * F * E);
-  } else {
-    c.q9 = c.fvel = nullptr;
-  }
   return off;
 }
 

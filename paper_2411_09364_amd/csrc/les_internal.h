@@ -91,8 +91,7 @@ struct Ctx {
   void* nut = nullptr;    // |S| (all Smagorinsky variants) or learned nu_t/Delta^2
   void* phi = nullptr;    // pressure correction (field layout)
   void* spec = nullptr;   // complex spectrum [nz][ny][nx/2+1]
-  void* q9 = nullptr;     // dynamic model: 9 centre quantities (uc, |S| S_ij)
-  void* fvel = nullptr;   // dynamic model: 3 test-filtered velocity fields
+  int dsm_kc = 8;         // planes per z chunk of the fused dynamic-model kernel
   // learned closure
   float* mlp_params = nullptr;
   double mlp_lo[7], mlp_hi[7];

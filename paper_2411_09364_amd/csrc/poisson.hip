@@ -387,19 +387,31 @@ __global__ void k_thomas(GridP g, cpx<T>* __restrict__ spec, const double* __res
 }
 
 // ============================================================================ bulk
-// s = (U_b - <u*>) / <q>, <.> the dzf-weighted volume mean; stored in dt[1].
-__global__ void k_bulk_final(const double* part, int nblk, double* dtp, const double* q, const double* dzf, int nz,
-                             double ubulk, double cells_xy, double lz) {
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[b];
-  const double mean = s / (cells_xy * lz);
-  double qs = 0.0, ds = 0.0;
-  for (int k = 1; k <= nz; ++k) {
-    qs += q[k - 1] * dzf[k];
-    ds += dzf[k];
+// s = (U_b - <u*>) / <q>, <.> the dzf-weighted volume mean; stored in dt[1].  One block:
+// strided partial sums per thread, then a fixed-order tree (deterministic).
+__global__ void __launch_bounds__(256) k_bulk_final(const double* part, int nblk, double* dtp, const double* q,
+                                                    const double* dzf, int nz, double ubulk, double cells_xy,
+                                                    double lz) {
+  __shared__ double sm[3][256];
+  double a = 0.0, b = 0.0, d = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) a += part[i];
+  for (int k = threadIdx.x; k < nz; k += 256) {
+    b += q[k] * dzf[k + 1];
+    d += dzf[k + 1];
   }
-  dtp[1] = (ubulk - mean) / (qs / ds);
+  sm[0][threadIdx.x] = a;
+  sm[1][threadIdx.x] = b;
+  sm[2][threadIdx.x] = d;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int r = 0; r < 3; ++r) sm[r][threadIdx.x] += sm[r][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mean = sm[0][0] / (cells_xy * lz);
+    dtp[1] = (ubulk - mean) / (sm[1][0] / sm[2][0]);
+  }
 }
 
 // ghost planes of a cell-centred scalar (Neumann walls or periodic copies)
@@ -451,7 +463,7 @@ static void fwd_x(Ctx& c, int mode, const T* us, const T* vs, const T* ws, const
     LES_LAUNCH(c, "rfftx", in_bytes + spec_bytes, (k_rfftx<T, 1>), dim3(nblk), dim3(256), sh, c.g, P, us, vs, ws, fin,
                        (cpx<T>*)c.spec, c.t.twx, c.t.twx_f, c.t.dt, gamma, pb, bp);
   if (bulk)
-    LES_LAUNCH(c, "bulk_final", 0, k_bulk_final, dim3(1), dim3(64), 0, c.t.bulk, (int)nblk, c.t.dt,
+    LES_LAUNCH(c, "bulk_final", 0, k_bulk_final, dim3(1), dim3(256), 0, c.t.bulk, (int)nblk, c.t.dt,
                        c.t.hfac + 4 * c.g.nz, c.t.dzf, c.g.nz, c.cfg.ubulk, (double)c.g.sxy, c.cfg.lz);
 }
 

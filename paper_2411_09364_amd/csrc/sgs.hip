@@ -155,219 +155,332 @@ __global__ void k_vd_coef(GridP g, const T* u, const T* v, const double* tau, in
 }
 
 // ============================================================================ dynamic model
-// Sweep 1: centre velocities and |S| S_ij (9 fields), |S| into the eddy-viscosity field.
-template <typename T>
-__global__ void __launch_bounds__(256) k_dsm_centre(GridP g, const T* __restrict__ u, const T* __restrict__ v,
-                                                    const T* __restrict__ w, T* __restrict__ nut, T* __restrict__ q9,
-                                                    int64_t fstride) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z + 1;
-  if (i >= g.nx || j >= g.ny) return;
-  T s[6];
-  centre_strain(g, u, v, w, k, j, i, s);
-  const T sm = strain_mag(s);
-  store_nut(g, nut, k, j, i, sm);
-  const int64_t c = idx3(g, k, j, i);
-  const T h = (T)0.5;
-  q9[c] = h * (u[c] + u[idx3(g, k, j, wrap_m(i, g.nx))]);
-  q9[fstride + c] = h * (v[c] + v[idx3(g, k, wrap_m(j, g.ny), i)]);
-  q9[2 * fstride + c] = h * (w[c] + w[c - g.sxy]);
-  for (int a = 0; a < 6; ++a) q9[(3 + a) * fstride + c] = sm * s[a];
-}
-
-// x-y trapezoidal filter (1/4, 1/2, 1/4)^2 of field f at plane kk around (j, i).
-template <typename T>
-__device__ inline T filt_xy(const GridP& g, const T* f, int kk, int j, int i) {
-  const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx), jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
-  const T a = (T)0.25, b = (T)0.5;
-  auto row = [&](int jj) {
-    return a * f[idx3(g, kk, jj, im)] + b * f[idx3(g, kk, jj, i)] + a * f[idx3(g, kk, jj, ip)];
-  };
-  return a * row(jm) + b * row(j) + a * row(jp);
-}
-
-// z-neighbour plane indices of a z-centred quantity (periodic wrap) or -1 for the
-// extrapolated wall ghost.
-__device__ inline int znb(const GridP& g, int k) {
-  if (g.zbc == LES_ZBC_PERIODIC) {
-    if (k == 0) return g.nz;
-    if (k == g.nz + 1) return 1;
-    return k;
-  }
-  if (k == 0 || k == g.nz + 1) return -1;
-  return k;
-}
-
-// 3-D test filter of a z-centred field at (k, j, i): xy filter on planes k-1, k, k+1, then
-// (1/4, 1/2, 1/4) in z; at a wall the missing plane is the extrapolation 2 q_1 - q_2 (R9).
-template <typename T>
-__device__ inline T filt3_centre(const GridP& g, const T* f, int k, int j, int i) {
-  const T c = filt_xy(g, f, k, j, i);
-  const int km = znb(g, k - 1), kp = znb(g, k + 1);
-  T lo, hi;
-  if (km >= 0) lo = filt_xy(g, f, km, j, i);
-  if (kp >= 0) hi = filt_xy(g, f, kp, j, i);
-  if (km < 0) lo = (T)2 * c - hi;
-  if (kp < 0) hi = (T)2 * c - lo;
-  return (T)0.25 * lo + (T)0.5 * c + (T)0.25 * hi;
-}
-
-// Sweep 2: test-filtered staggered velocity, each component on its own grid, with the
-// ghost planes the strain routine expects.
-template <typename T>
-__global__ void __launch_bounds__(256) k_dsm_fvel(GridP g, const T* __restrict__ u, const T* __restrict__ v,
-                                                  const T* __restrict__ w, T* __restrict__ uf, T* __restrict__ vf,
-                                                  T* __restrict__ wf) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z + 1;
-  if (i >= g.nx || j >= g.ny) return;
-  const int n = g.nz;
-  const bool per = g.zbc == LES_ZBC_PERIODIC;
-  const T a = filt3_centre(g, u, k, j, i);
-  const T b = filt3_centre(g, v, k, j, i);
-  T cw;
-  if (!per && k == n) cw = (T)0;
-  else cw = (T)0.25 * filt_xy(g, w, k - 1, j, i) + (T)0.5 * filt_xy(g, w, k, j, i) + (T)0.25 * filt_xy(g, w, k + 1, j, i);
-  const int64_t c = idx3(g, k, j, i);
-  uf[c] = a;
-  vf[c] = b;
-  wf[c] = cw;
-  const int64_t c2 = (int64_t)j * g.nx + i, s = g.sxy;
-  if (per) {
-    if (k == n) { uf[c2] = a; vf[c2] = b; wf[c2] = cw; }
-    if (k == 1) { uf[(n + 1) * s + c2] = a; vf[(n + 1) * s + c2] = b; wf[(n + 1) * s + c2] = cw; }
-  } else {
-    if (k == 1) { uf[c2] = -a; vf[c2] = -b; wf[c2] = (T)0; }
-    if (k == n) { uf[(n + 1) * s + c2] = -a; vf[(n + 1) * s + c2] = -b; wf[(n + 1) * s + c2] = (T)0; }
-  }
-}
-
-// Sweep 3: L_ij and M_ij at each cell, L_ij M_ij and M_ij M_ij summed per block and plane.
-template <typename T>
-__global__ void __launch_bounds__(256) k_dsm_lm(GridP g, const T* __restrict__ q9, int64_t fstride,
-                                                const T* __restrict__ uf, const T* __restrict__ vf,
-                                                const T* __restrict__ wf, double* __restrict__ part) {
-  __shared__ double red[2][256];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z + 1;
-  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-  const int nthr = blockDim.x * blockDim.y;
-  for (int t = tid; t < 256; t += nthr) red[0][t] = red[1][t] = 0.0;
-  __syncthreads();
-  double lm = 0.0, mm = 0.0;
-  if (i < g.nx && j < g.ny) {
-    const int n = g.nz;
-    const bool wall_layer = g.zbc != LES_ZBC_PERIODIC && (k == 1 || k == n);
-    const T alpha2 = wall_layer ? (T)2.5198420997897464 : (T)4;   // 4^(2/3) or 2^2
-    const T d2 = (T)g.delta2[k];
-    // filtered centre quantities; products formed point-wise before filtering
-    const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx), jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
-    const int is[3] = {im, i, ip}, js[3] = {jm, j, jp};
-    const T wgt[3] = {(T)0.25, (T)0.5, (T)0.25};
-    T acc[3][15];
-    const int kmn = znb(g, k - 1), kpn = znb(g, k + 1);
-    const int planes[3] = {kmn, k, kpn};
-    for (int pz = 0; pz < 3; ++pz) {
-      for (int a = 0; a < 15; ++a) acc[pz][a] = (T)0;
-      const int kk = planes[pz];
-      if (kk < 0) continue;
-      for (int dy = 0; dy < 3; ++dy) {
-        T row[15];
-        for (int a = 0; a < 15; ++a) row[a] = (T)0;
-        for (int dx = 0; dx < 3; ++dx) {
-          const int64_t c = idx3(g, kk, js[dy], is[dx]);
-          const T uc = q9[c], vc = q9[fstride + c], wc = q9[2 * fstride + c];
-          const T val[15] = {uc, vc, wc, uc * uc, vc * vc, wc * wc, uc * vc, uc * wc, vc * wc,
-                             q9[3 * fstride + c], q9[4 * fstride + c], q9[5 * fstride + c],
-                             q9[6 * fstride + c], q9[7 * fstride + c], q9[8 * fstride + c]};
-          for (int a = 0; a < 15; ++a) row[a] = row[a] + wgt[dx] * val[a];
-        }
-        for (int a = 0; a < 15; ++a) acc[pz][a] = acc[pz][a] + wgt[dy] * row[a];
-      }
-    }
-    if (kmn < 0)
-      for (int a = 0; a < 15; ++a) acc[0][a] = (T)2 * acc[1][a] - acc[2][a];
-    if (kpn < 0)
-      for (int a = 0; a < 15; ++a) acc[2][a] = (T)2 * acc[1][a] - acc[0][a];
-    T F[15];
-    for (int a = 0; a < 15; ++a) F[a] = (T)0.25 * acc[0][a] + (T)0.5 * acc[1][a] + (T)0.25 * acc[2][a];
-    T st[6];
-    centre_strain(g, uf, vf, wf, k, j, i, st);
-    const T stm = strain_mag(st);
-    // component order 11 22 33 12 13 23
-    const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
-    for (int c = 0; c < 6; ++c) {
-      const T L = F[3 + c] - F[pa[c]] * F[pb[c]];
-      const T M = (T)2 * d2 * (F[9 + c] - alpha2 * stm * st[c]);
-      const double wgt2 = c < 3 ? 1.0 : 2.0;
-      lm += wgt2 * (double)L * (double)M;
-      mm += wgt2 * (double)M * (double)M;
-    }
-  }
-  red[0][tid] = lm;
-  red[1][tid] = mm;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) {
-      red[0][tid] += red[0][tid + s];
-      red[1][tid] += red[1][tid + s];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const int64_t tile = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    const int64_t o = ((int64_t)(k - 1) * gridDim.x * gridDim.y + tile) * 2;
-    part[o] = red[0][0];
-    part[o + 1] = red[1][0];
-  }
-}
-
 // Plane sums in a fixed order -> c_s(k) = max(0, <LM>/<MM>) (0 if <MM> = 0), whole box
-// when z is periodic; coef[k] = c_s Delta_k^2 with ghost copies.
-__global__ void k_dsm_reduce(GridP g, const double* part, int ntile, double* cs, double* coef) {
+// when z is periodic; coef[k] = c_s Delta_k^2 with ghost copies.  One block per plane:
+// strided partial sums over the tiles, then a fixed-order tree.  With periodic z every block
+// forms the total over all planes itself (same order in every block).
+__global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part, int ntile, double* cs,
+                                                    double* coef) {
+  __shared__ double sm[2][256];
   const int n = g.nz;
   const bool per = g.zbc == LES_ZBC_PERIODIC;
-  __shared__ double tot[2];
+  const int k = blockIdx.x;
+  double a = 0.0, b = 0.0;
   if (per) {
-    if (threadIdx.x == 0) {
-      double a = 0.0, b = 0.0;
-      for (int k = 0; k < n; ++k) {
-        double pl = 0.0, pm = 0.0;
-        for (int t = 0; t < ntile; ++t) {
-          pl += part[((int64_t)k * ntile + t) * 2];
-          pm += part[((int64_t)k * ntile + t) * 2 + 1];
-        }
-        a += pl;
-        b += pm;
-      }
-      tot[0] = a;
-      tot[1] = b;
+    for (int64_t e = threadIdx.x; e < (int64_t)n * ntile; e += 256) {
+      a += part[2 * e];
+      b += part[2 * e + 1];
+    }
+  } else {
+    for (int t = threadIdx.x; t < ntile; t += 256) {
+      a += part[((int64_t)k * ntile + t) * 2];
+      b += part[((int64_t)k * ntile + t) * 2 + 1];
+    }
+  }
+  sm[0][threadIdx.x] = a;
+  sm[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + st];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + st];
     }
     __syncthreads();
   }
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    double a = 0.0, b = 0.0;
-    if (per) {
-      a = tot[0];
-      b = tot[1];
-    } else {
-      for (int t = 0; t < ntile; ++t) {
-        a += part[((int64_t)k * ntile + t) * 2];
-        b += part[((int64_t)k * ntile + t) * 2 + 1];
-      }
-    }
-    const double c = b > 0.0 ? fmax(a / b, 0.0) : 0.0;
+  if (threadIdx.x == 0) {
+    const double sa = sm[0][0], sb = sm[1][0];
+    const double c = sb > 0.0 ? fmax(sa / sb, 0.0) : 0.0;
     cs[k] = c;
     coef[k + 1] = c * g.delta2[k + 1];
+    if (k == 0) coef[per ? n + 1 : 0] = c * g.delta2[1];
+    if (k == n - 1) coef[per ? 0 : n + 1] = c * g.delta2[n];
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double c1 = g.delta2[1] * cs[0], cn = g.delta2[n] * cs[n - 1];
-    coef[0] = per ? cn : c1;
-    coef[n + 1] = per ? c1 : cn;
+}
+
+// ============================================================================ fused dynamic model
+// One z-marching pass per (32 x 8 tile, chunk of planes) computing |S| and the plane sums
+// of L_ij M_ij and M_ij M_ij, reading u, v, w once (halo 2) and writing |S| once.
+//   LDS: velocity ring of 3 planes on the tile + 2 halo (strain ghosts substituted),
+//        the 9 centre quantities (uc_i, |S| S_ij) of one plane on the tile + 1 halo,
+//        the test-filtered staggered velocity ring of 3 planes on the tile + 1 halo.
+//   Registers: the x-y-filtered 15 quantities of planes k-1, k, k+1 for the thread's cell.
+// The stage of plane p computes the centre quantities and the filtered velocity of p from
+// velocity planes p-1..p+1; once stage p is done the cell values of plane p-1 are final
+// (z pass of the test filter, S~ from the filtered velocity, L and M).
+// Wall rules as in the rest of the dynamic model: on the first off-wall layers the z pass of
+// the filter is the identity (index-space extrapolation), filtered-velocity ghosts follow the
+// strain ghost rule, alpha^2 = 4^(2/3) there.
+namespace fused {
+constexpr int TX = 32, TY = 8, NT = TX * TY;
+constexpr int RX2 = TX + 4, RY2 = TY + 4, N2 = RX2 * RY2;  // halo 2
+constexpr int RX1 = TX + 2, RY1 = TY + 2, N1 = RX1 * RY1;  // halo 1
+}  // namespace fused
+
+// strain at a centre from an accessor A(c, dz, dy, dx) giving component c (0 u, 1 v, 2 w)
+// at offsets relative to the cell (dz in {-1, 0, 1}: planes k-1, k, k+1; w at dz is the face
+// on top of plane k+dz).
+template <typename T, typename Acc>
+__device__ inline void strain_from(const Acc& A, T rdx, T rdy, T rdzf, T rdzc, T rdzcm, T s[6]) {
+  const T h = (T)0.5, q = (T)0.25;
+  const T u0 = A(0, 0, 0, 0), uim = A(0, 0, 0, -1), ujp = A(0, 0, 1, 0), ujm = A(0, 0, -1, 0);
+  const T ujp_im = A(0, 0, 1, -1), ujm_im = A(0, 0, -1, -1);
+  const T v0 = A(1, 0, 0, 0), vjm = A(1, 0, -1, 0), vip = A(1, 0, 0, 1), vim = A(1, 0, 0, -1);
+  const T vjm_ip = A(1, 0, -1, 1), vjm_im = A(1, 0, -1, -1);
+  s[0] = (u0 - uim) * rdx;
+  s[1] = (v0 - vjm) * rdy;
+  s[2] = (A(2, 0, 0, 0) - A(2, -1, 0, 0)) * rdzf;
+  const T e_a = h * ((ujp - u0) * rdy + (vip - v0) * rdx);
+  const T e_b = h * ((ujp_im - uim) * rdy + (v0 - vim) * rdx);
+  const T e_c = h * ((u0 - ujm) * rdy + (vjm_ip - vjm) * rdx);
+  const T e_d = h * ((uim - ujm_im) * rdy + (vjm - vjm_im) * rdx);
+  s[3] = q * (e_a + e_b + e_c + e_d);
+  const T ukp = A(0, 1, 0, 0), ukm = A(0, -1, 0, 0), ukp_im = A(0, 1, 0, -1), ukm_im = A(0, -1, 0, -1);
+  const T f_a = h * ((ukp - u0) * rdzc + (A(2, 0, 0, 1) - A(2, 0, 0, 0)) * rdx);
+  const T f_b = h * ((ukp_im - uim) * rdzc + (A(2, 0, 0, 0) - A(2, 0, 0, -1)) * rdx);
+  const T f_c = h * ((u0 - ukm) * rdzcm + (A(2, -1, 0, 1) - A(2, -1, 0, 0)) * rdx);
+  const T f_d = h * ((uim - ukm_im) * rdzcm + (A(2, -1, 0, 0) - A(2, -1, 0, -1)) * rdx);
+  s[4] = q * (f_a + f_b + f_c + f_d);
+  const T vkp = A(1, 1, 0, 0), vkm = A(1, -1, 0, 0), vkp_jm = A(1, 1, -1, 0), vkm_jm = A(1, -1, -1, 0);
+  const T g_a = h * ((vkp - v0) * rdzc + (A(2, 0, 1, 0) - A(2, 0, 0, 0)) * rdy);
+  const T g_b = h * ((vkp_jm - vjm) * rdzc + (A(2, 0, 0, 0) - A(2, 0, -1, 0)) * rdy);
+  const T g_c = h * ((v0 - vkm) * rdzcm + (A(2, -1, 1, 0) - A(2, -1, 0, 0)) * rdy);
+  const T g_d = h * ((vjm - vkm_jm) * rdzcm + (A(2, -1, 0, 0) - A(2, -1, -1, 0)) * rdy);
+  s[5] = q * (g_a + g_b + g_c + g_d);
+}
+
+template <typename T>
+__device__ inline int ring3(int q) {
+  return ((q % 3) + 3) % 3;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dsm_fused(GridP g, const T* __restrict__ u, const T* __restrict__ v,
+                                                   const T* __restrict__ w, T* __restrict__ nut,
+                                                   double* __restrict__ part, int kc) {
+  using namespace fused;
+  __shared__ T vel[3][3][N2];   // [slot][component][R2]
+  __shared__ T qb[9][N1];       // centre quantities of the current stage plane
+  __shared__ T ut[3][3][N1];    // filtered velocity [slot][component][R1]
+  __shared__ double red[2][NT / 64];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int nz = g.nz;
+  const int kb = 1 + blockIdx.z * kc;
+  const int ke = min(nz, kb + kc - 1);
+  const bool per = g.zbc == LES_ZBC_PERIODIC;
+  const bool wm = g.zbc == LES_ZBC_WALLMODEL;
+  const int ntile = gridDim.x * gridDim.y;
+  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+  const T rdx = (T)g.rdx, rdy = (T)g.rdy;
+  const T W0 = (T)0.25, W1 = (T)0.5;
+  auto wrapi = [&](int i) { return ((i % g.nx) + g.nx) % g.nx; };   // tiles may exceed the grid
+  auto wrapj = [&](int j) { return ((j % g.ny) + g.ny) % g.ny; };
+  auto phys = [&](int q) {  // logical plane -> stored plane (periodic wrap of interior planes)
+    if (!per) return q;
+    int m = (q - 1) % nz;
+    if (m < 0) m += nz;
+    return m + 1;
+  };
+  // ---- load velocity plane q into its slot (strain ghost rule on wall ghost planes)
+  auto load_plane = [&](int q) {
+    const int sl = ring3<T>(q);
+    const int pq = phys(q);
+    for (int e = tid; e < N2; e += NT) {
+      const int rx = e % RX2, ry = e / RX2;
+      const int i = wrapi(i0 - 2 + rx), j = wrapj(j0 - 2 + ry);
+      T a, b;
+      if (wm && pq == 0) {
+        const T a1 = u[idx3(g, 1, j, i)], a2 = u[idx3(g, 2, j, i)];
+        const T b1 = v[idx3(g, 1, j, i)], b2 = v[idx3(g, 2, j, i)];
+        a = a1 - (T)g.dzc[0] * ((a2 - a1) / (T)g.dzc[1]);
+        b = b1 - (T)g.dzc[0] * ((b2 - b1) / (T)g.dzc[1]);
+      } else if (wm && pq == nz + 1) {
+        const T a1 = u[idx3(g, nz, j, i)], a0 = u[idx3(g, nz - 1, j, i)];
+        const T b1 = v[idx3(g, nz, j, i)], b0 = v[idx3(g, nz - 1, j, i)];
+        a = a1 + (T)g.dzc[nz] * ((a1 - a0) / (T)g.dzc[nz - 1]);
+        b = b1 + (T)g.dzc[nz] * ((b1 - b0) / (T)g.dzc[nz - 1]);
+      } else {
+        a = u[idx3(g, pq, j, i)];
+        b = v[idx3(g, pq, j, i)];
+      }
+      vel[sl][0][e] = a;
+      vel[sl][1][e] = b;
+      vel[sl][2][e] = w[idx3(g, pq, j, i)];
+    }
+  };
+  // register ring of x-y filtered quantities: A = plane k-1, B = k, C = k+1
+  T qA[15], qB[15], qC[15];
+  // ---- stage p: centre quantities and filtered velocity of plane p, then x-y filter
+  auto stage = [&](int p) {
+    const int pq = phys(p);
+    const int sm = ring3<T>(p - 1), s0 = ring3<T>(p), sp = ring3<T>(p + 1);
+    const T rdzf = (T)(1.0 / g.dzf[pq]), rdzc = (T)(1.0 / g.dzc[pq]), rdzcm = (T)(1.0 / g.dzc[pq - 1]);
+    const bool zid = !per && (p == 1 || p == nz);   // z pass of the filter is the identity
+    const bool wtop = !per && p == nz;               // w face on top of plane nz is the wall
+    for (int e = tid; e < N1; e += NT) {
+      const int rx = e % RX1, ry = e / RX1;
+      const int x = rx + 1, y = ry + 1;  // in R2
+      auto A = [&](int c, int dz, int dy, int dx) -> T {
+        const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
+        return vel[sl][c][(y + dy) * RX2 + x + dx];
+      };
+      T s[6];
+      strain_from<T>(A, rdx, rdy, rdzf, rdzc, rdzcm, s);
+      const T sm_ = sqrt((T)2 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2]) +
+                         (T)4 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
+      qb[0][e] = (T)0.5 * (A(0, 0, 0, 0) + A(0, 0, 0, -1));
+      qb[1][e] = (T)0.5 * (A(1, 0, 0, 0) + A(1, 0, -1, 0));
+      qb[2][e] = (T)0.5 * (A(2, 0, 0, 0) + A(2, -1, 0, 0));
+      for (int a = 0; a < 6; ++a) qb[3 + a][e] = sm_ * s[a];
+      if (rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && p >= kb && p <= ke) {
+        const int i = i0 + rx - 1, j = j0 + ry - 1;
+        if (i < g.nx && j < g.ny) store_nut(g, nut, p, j, i, sm_);
+      }
+      // test-filtered staggered velocity at plane p
+      for (int c = 0; c < 3; ++c) {
+        T acc = (T)0;
+        if (c == 2 && wtop) {
+          acc = (T)0;
+        } else {
+          for (int dz = -1; dz <= 1; ++dz) {
+            T wz = dz == 0 ? W1 : W0;
+            if (c < 2 && zid) wz = dz == 0 ? (T)1 : (T)0;
+            if (wz == (T)0) continue;
+            const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
+            T pl = (T)0;
+            for (int dy = -1; dy <= 1; ++dy) {
+              const T* r = &vel[sl][c][(y + dy) * RX2 + x];
+              const T row = W0 * r[-1] + W1 * r[0] + W0 * r[1];
+              pl = pl + (dy == 0 ? W1 : W0) * row;
+            }
+            acc = acc + wz * pl;
+          }
+        }
+        ut[s0][c][e] = acc;
+      }
+    }
+    __syncthreads();
+    // x-y filter of the 15 quantities at the thread's own cell (R1 coords tx+1, ty+1)
+    for (int a = 0; a < 15; ++a) qC[a] = (T)0;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const T wy = dy == 0 ? W1 : W0;
+      T row[15];
+      for (int a = 0; a < 15; ++a) row[a] = (T)0;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const T wx = dx == 0 ? W1 : W0;
+        const int e = (ty + 1 + dy) * RX1 + tx + 1 + dx;
+        const T uc = qb[0][e], vc = qb[1][e], wc = qb[2][e];
+        const T val[15] = {uc, vc, wc, uc * uc, vc * vc, wc * wc, uc * vc, uc * wc, vc * wc,
+                           qb[3][e], qb[4][e], qb[5][e], qb[6][e], qb[7][e], qb[8][e]};
+        for (int a = 0; a < 15; ++a) row[a] = row[a] + wx * val[a];
+      }
+      for (int a = 0; a < 15; ++a) qC[a] = qC[a] + wy * row[a];
+    }
+  };
+  // ---- output plane k from the register ring (lo, mid, hi) and the filtered-velocity ring
+  auto output = [&](int k, const T* lo, const T* mid, const T* hi) {
+    const int pk = phys(k);
+    // wall ghosts of the filtered velocity (strain ghost rule): fill the free ring slot
+    if (!per && (k == 1 || k == nz)) {
+      const int sg = ring3<T>(k == 1 ? 0 : nz + 1);
+      const int s1 = ring3<T>(k == 1 ? 1 : nz), s2 = ring3<T>(k == 1 ? 2 : nz - 1);
+      for (int e = tid; e < N1; e += NT) {
+        for (int c = 0; c < 2; ++c) {
+          const T a1 = ut[s1][c][e], a2 = ut[s2][c][e];
+          T gh;
+          if (wm) {
+            gh = k == 1 ? a1 - (T)g.dzc[0] * ((a2 - a1) / (T)g.dzc[1])
+                        : a1 + (T)g.dzc[nz] * ((a1 - a2) / (T)g.dzc[nz - 1]);
+          } else {
+            gh = -a1;
+          }
+          ut[sg][c][e] = gh;
+        }
+        ut[sg][2][e] = (T)0;
+      }
+      __syncthreads();
+    }
+    double lm = 0.0, mm = 0.0;
+    const int i = i0 + tx, j = j0 + ty;
+    if (i < g.nx && j < g.ny) {
+      T F[15];
+      for (int a = 0; a < 15; ++a) F[a] = W0 * lo[a] + W1 * mid[a] + W0 * hi[a];
+      const int sm = ring3<T>(k - 1), s0 = ring3<T>(k), sp = ring3<T>(k + 1);
+      const int x = tx + 1, y = ty + 1;  // own cell in R1
+      auto A = [&](int c, int dz, int dy, int dx) -> T {
+        const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
+        return ut[sl][c][(y + dy) * RX1 + x + dx];
+      };
+      T st[6];
+      strain_from<T>(A, rdx, rdy, (T)(1.0 / g.dzf[pk]), (T)(1.0 / g.dzc[pk]), (T)(1.0 / g.dzc[pk - 1]), st);
+      const T stm = sqrt((T)2 * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2]) +
+                         (T)4 * (st[3] * st[3] + st[4] * st[4] + st[5] * st[5]));
+      const bool wall_layer = !per && (k == 1 || k == nz);
+      const T alpha2 = wall_layer ? (T)2.5198420997897464 : (T)4;
+      const T d2 = (T)g.delta2[pk];
+      const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+      for (int c = 0; c < 6; ++c) {
+        const T L = F[3 + c] - F[pa[c]] * F[pb[c]];
+        const T M = (T)2 * d2 * (F[9 + c] - alpha2 * stm * st[c]);
+        const double wgt2 = c < 3 ? 1.0 : 2.0;
+        lm += wgt2 * (double)L * (double)M;
+        mm += wgt2 * (double)M * (double)M;
+      }
+    }
+    // block sums in a fixed order: wave shuffles, then the waves in order
+    for (int off = 32; off > 0; off >>= 1) {
+      lm += __shfl_down(lm, off, 64);
+      mm += __shfl_down(mm, off, 64);
+    }
+    const int wave = tid / 64, lane = tid % 64;
+    if (lane == 0) {
+      red[0][wave] = lm;
+      red[1][wave] = mm;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int q = 0; q < NT / 64; ++q) {
+        a += red[0][q];
+        b += red[1][q];
+      }
+      const int64_t o = ((int64_t)(k - 1) * ntile + tile) * 2;
+      part[o] = a;
+      part[o + 1] = b;
+    }
+  };
+  // ---- march
+  const int pstart = per ? kb - 1 : max(kb - 1, 1);
+  const int pend = per ? ke + 1 : min(ke + 1, nz);
+  load_plane(pstart - 1);
+  load_plane(pstart);
+  for (int p = pstart; p <= pend; ++p) {
+    load_plane(p + 1);
+    __syncthreads();
+    for (int a = 0; a < 15; ++a) {
+      qA[a] = qB[a];
+      qB[a] = qC[a];
+    }
+    stage(p);
+    __syncthreads();
+    const int k = p - 1;
+    if (k >= kb && k <= ke) {
+      if (!per && k == 1) {
+        T ext[15];
+        for (int a = 0; a < 15; ++a) ext[a] = (T)2 * qB[a] - qC[a];
+        output(k, ext, qB, qC);
+      } else {
+        output(k, qA, qB, qC);
+      }
+    }
+    __syncthreads();
+  }
+  if (!per && ke == nz) {
+    // plane nz: the stage of nz + 1 does not exist; its z neighbour is extrapolated
+    // (plane nz - 1 is always staged: pstart <= kb - 1 <= nz - 1)
+    T ext[15];
+    for (int a = 0; a < 15; ++a) ext[a] = (T)2 * qC[a] - qB[a];
+    output(nz, qB, qC, ext);
   }
 }
 
@@ -388,17 +501,12 @@ void launch_eddy_viscosity(Ctx& c) {
     return;
   }
   if (model == LES_SGS_DSM || model == LES_SGS_MLP) {
-    const int64_t fs = (int64_t)c.field_elems;
-    T* q9 = (T*)c.q9;
-    T* fv = (T*)c.fvel;
-    LES_LAUNCH(c, "dsm_centre", 13 * pts * sizeof(T), k_dsm_centre<T>, L.grid, L.block, 0, g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
-                       (T*)c.nut, q9, fs);
-    LES_LAUNCH(c, "dsm_fvel", 6 * pts * sizeof(T), k_dsm_fvel<T>, L.grid, L.block, 0, g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
-                       fv, fv + fs, fv + 2 * fs);
-    LES_LAUNCH(c, "dsm_lm", 12 * pts * sizeof(T), k_dsm_lm<T>, L.grid, L.block, 0, g, (const T*)q9, fs, (const T*)fv,
-                       (const T*)(fv + fs), (const T*)(fv + 2 * fs), c.t.dsm_part);
-    const int ntile = (int)(L.grid.x * L.grid.y);
-    LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(1), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs, c.t.coef);
+    const int kc = c.dsm_kc;
+    dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + fused::TY - 1) / fused::TY, (g.nz + kc - 1) / kc);
+    LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, fused::TY), 0, g,
+               (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.t.dsm_part, kc);
+    const int ntile = (int)(grid.x * grid.y);
+    LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs, c.t.coef);
   }
 }
 

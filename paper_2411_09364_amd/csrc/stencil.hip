@@ -200,8 +200,17 @@ void launch_predictor(Ctx& c, int stage) {
 // substep by three threads: u/v rows, w rows, and the flow-rate profile q = H^-1 1 of
 // the u rows (no-slip walls; 1 otherwise).  Layout of hfac: [cp_uv | rp_uv | cp_w | rp_w
 // | q | -] each nz long.
-__global__ void k_helmholtz_factor(GridP g, double* hfac, const double* dtp, double gamma, int wallmodel) {
+__global__ void __launch_bounds__(256) k_helmholtz_factor(GridP g, double* hfac, const double* dtp, double gamma,
+                                                          int wallmodel) {
+  extern __shared__ double shm[];
   const int n = g.nz;
+  double* dzf = shm;            // [n + 2]
+  double* dzc = shm + n + 2;    // [n + 2]
+  for (int k = threadIdx.x; k < n + 2; k += blockDim.x) {
+    dzf[k] = g.dzf[k];
+    dzc[k] = g.dzc[k];
+  }
+  __syncthreads();
   const double c = gamma * g.nu * dtp[0] / 2.0;
   double* cp_uv = hfac;
   double* rp_uv = hfac + n;
@@ -209,46 +218,42 @@ __global__ void k_helmholtz_factor(GridP g, double* hfac, const double* dtp, dou
   double* rp_w = hfac + 3 * n;
   double* qv = hfac + 4 * n;
   if (threadIdx.x == 0) {
-    double cprev = 0.0;
+    double cprev = 0.0, dp = 0.0;
     for (int kk = 1; kk <= n; ++kk) {
-      double lo = 1.0 / (g.dzc[kk - 1] * g.dzf[kk]);
-      double up = 1.0 / (g.dzc[kk] * g.dzf[kk]);
+      double lo = 1.0 / (dzc[kk - 1] * dzf[kk]);
+      double up = 1.0 / (dzc[kk] * dzf[kk]);
       double dg = -(lo + up);
       if (kk == 1) dg += wallmodel ? lo : -lo;
       if (kk == n) dg += wallmodel ? up : -up;
       if (kk == 1) lo = 0.0;
       if (kk == n) up = 0.0;
       const double a = -c * lo, b = 1.0 - c * dg, cc = -c * up;
-      const double piv = b - a * cprev;
-      rp_uv[kk - 1] = 1.0 / piv;
-      cprev = cc / piv;
+      const double r = 1.0 / (b - a * cprev);
+      rp_uv[kk - 1] = r;
+      cprev = cc * r;
       cp_uv[kk - 1] = cprev;
+      // forward sweep of q = H^-1 1 (bulk-forcing profile, no-slip rows) alongside
+      dp = (1.0 - a * dp) * r;
+      qv[kk - 1] = dp;
     }
-    // q = H^-1 1 for the bulk-forcing profile (CN in z with no-slip rows)
     if (!wallmodel) {
-      double dp = 0.0;
-      for (int kk = 1; kk <= n; ++kk) {
-        double lo = kk == 1 ? 0.0 : 1.0 / (g.dzc[kk - 1] * g.dzf[kk]);
-        dp = (1.0 - (-c * lo) * dp) * rp_uv[kk - 1];
-        qv[kk - 1] = dp;
-      }
       for (int kk = n - 1; kk >= 1; --kk) qv[kk - 1] = qv[kk - 1] - cp_uv[kk - 1] * qv[kk];
     } else {
       for (int kk = 0; kk < n; ++kk) qv[kk] = 1.0;
     }
-  } else if (threadIdx.x == 1) {
+  } else if (threadIdx.x == 64) {
     const int m = n - 1;
     double cprev = 0.0;
     for (int kk = 1; kk <= m; ++kk) {
-      double lo = 1.0 / (g.dzf[kk] * g.dzc[kk]);
-      double up = 1.0 / (g.dzf[kk + 1] * g.dzc[kk]);
+      double lo = 1.0 / (dzf[kk] * dzc[kk]);
+      double up = 1.0 / (dzf[kk + 1] * dzc[kk]);
       const double dg = -(lo + up);
       if (kk == 1) lo = 0.0;
       if (kk == m) up = 0.0;
       const double a = -c * lo, b = 1.0 - c * dg, cc = -c * up;
-      const double piv = b - a * cprev;
-      rp_w[kk - 1] = 1.0 / piv;
-      cprev = cc / piv;
+      const double r = 1.0 / (b - a * cprev);
+      rp_w[kk - 1] = r;
+      cprev = cc * r;
       cp_w[kk - 1] = cprev;
     }
   }
@@ -256,7 +261,7 @@ __global__ void k_helmholtz_factor(GridP g, double* hfac, const double* dtp, dou
 
 void launch_helmholtz_factor(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
-  LES_LAUNCH(c, "helmholtz_factor", 0, k_helmholtz_factor, dim3(1), dim3(64), 0, c.g, c.t.hfac, c.t.dt, G[stage],
+  LES_LAUNCH(c, "helmholtz_factor", 0, k_helmholtz_factor, dim3(1), dim3(128), 2 * (c.g.nz + 2) * sizeof(double), c.g, c.t.hfac, c.t.dt, G[stage],
                      c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);
 }
 
@@ -520,16 +525,29 @@ __global__ void __launch_bounds__(256) k_cfl_partial(GridP g, const T* u, const 
   }
 }
 
-__global__ void k_cfl_final(const double* part, int nblk, double* dtp, double cfl, double nu, double sinv) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(256) k_cfl_final(const double* part, int nblk, double* dtp, double cfl, double nu,
+                                                   double sinv) {
+  __shared__ double sm[2][256];
   double mc = 0.0, mn = 0.0;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = threadIdx.x; b < nblk; b += 256) {
     mc = fmax(mc, part[2 * b]);
     mn = fmax(mn, part[2 * b + 1]);
   }
-  const double dtv = 0.95 * 2.51 / (4.0 * (nu + mn) * sinv);
-  const double dtc = mc > 0.0 ? cfl / mc : INFINITY;
-  dtp[0] = fmin(dtc, dtv);
+  sm[0][threadIdx.x] = mc;
+  sm[1][threadIdx.x] = mn;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sm[0][threadIdx.x] = fmax(sm[0][threadIdx.x], sm[0][threadIdx.x + s]);
+      sm[1][threadIdx.x] = fmax(sm[1][threadIdx.x], sm[1][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double dtv = 0.95 * 2.51 / (4.0 * (nu + sm[1][0]) * sinv);
+    const double dtc = sm[0][0] > 0.0 ? cfl / sm[0][0] : INFINITY;
+    dtp[0] = fmin(dtc, dtv);
+  }
 }
 
 template <typename T>
@@ -543,7 +561,7 @@ void launch_dt(Ctx& c, double cfl) {
     for (int k = 1; k <= c.g.nz; ++k) dmin = std::min(dmin, c.dzf[k]);
     sinv += 1.0 / (dmin * dmin);
   }
-  LES_LAUNCH(c, "cfl_final", 0, k_cfl_final, dim3(1), dim3(64), 0, c.t.red, nblk, c.t.dt, cfl, c.cfg.nu, sinv);
+  LES_LAUNCH(c, "cfl_final", 0, k_cfl_final, dim3(1), dim3(256), 0, c.t.red, nblk, c.t.dt, cfl, c.cfg.nu, sinv);
 }
 
 __global__ void k_set_dt(double* dtp, double dt) {
