@@ -165,28 +165,59 @@ les_status les_read(les_ctx* ctx, int field, void* dst);
 /* Synchronise and compute diagnostics. */
 les_status les_diag(les_ctx* ctx, les_diag_t* out);
 
-/* Learned closure (sgs = LES_SGS_MLP, or training alongside any model).
- * Parameters: 4737 floats in the order W1[64][7], b1[64], W2[64][64], b2[64], W3[1][64],
- * b3[1] (float32 master copy, device memory owned by the caller); lo/hi: the 7 feature
- * ranges for min-max scaling (host, copied).  Inference rounds W1, W2 and the layer
- * inputs to bfloat16 and accumulates in float32; points whose scaled features leave
- * [-0.05, 1.05] take the plane coefficient of the dynamic model instead. */
-les_status les_mlp_bind(les_ctx* ctx, float* params_dev, const double* lo, const double* hi);
+/* ---------------------------------------------------------------- learned closure
+ * Not in the paper, which motivates SGS closures trained on data produced by the LES solver
+ * itself (Sec. 1).  Network: 7 -> 64 -> 64 -> 1 with SiLU, output clipped at zero, giving the
+ * coefficient c of nu_t = c Delta^2 |S| (the role c_s plays in Eq. dsmag).  Inputs per cell:
+ * tr(S^2), tr(O^2), tr(S^3), tr(O^2 S), tr(O^2 S^2) of S/n and O/n (S strain, O rotation,
+ * n = sqrt(S_ij S_ij + O_ij O_ij)), y+ = d u_tau/nu (d distance to the nearer wall, u_tau from
+ * that wall's plane-mean stress; 0 when z is periodic) and Delta (channel half-height 1),
+ * each min-max scaled with the training ranges lo, hi.
+ * Parameters: 4737 floats, W1[64][7] | b1[64] | W2[64][64] | b2[64] | W3[64] | b3, float32
+ * master copy in caller-owned device memory.  W1, W2 and the inputs of the two 64-wide
+ * products are rounded to bfloat16 (nearest-even) for the matrix cores, accumulation is
+ * float32; the output layer is float32. */
 
-/* Gather training pairs at the current state: for n_samples cells chosen by a
- * counter-based hash of (seed, sample index), write the 7 scaled features to x_dev
- * (float[n][7]) and the dynamic-model coefficient of the cell's plane to y_dev
- * (float[n]).  Requires the dynamic model's coefficient (sgs = DSM). */
-les_status les_mlp_sample(les_ctx* ctx, uint64_t seed, int64_t n_samples,
-                          float* x_dev, float* y_dev);
+/* Use the network for nu_t (context created with sgs = LES_SGS_MLP; until this is called such
+ * a context runs the dynamic model).  params must stay valid; lo, hi: host double[7], copied.
+ * Points whose scaled inputs leave [-0.05, 1.05] take the dynamic-model coefficient of their
+ * plane instead; the dynamic model is re-evaluated (on the device, without host round trip)
+ * in every nu_t evaluation that follows one in which a point fell back. */
+les_status les_mlp_bind(les_ctx* ctx, const float* params_dev, const double* lo, const double* hi);
 
-/* One Adam step on the mean-squared error over n samples (x_dev float[n][7], y_dev
- * float[n]); m_dev, v_dev: float[4737] moments; step: 1-based Adam counter; loss_dev:
- * one float receiving the loss before the update.  Forward and backward run on the
- * matrix cores in bfloat16 with float32 accumulation. */
-les_status les_mlp_train_step(les_ctx* ctx, const float* x_dev, const float* y_dev,
-                              int64_t n, float lr, int step, float* m_dev, float* v_dev,
-                              float* loss_dev);
+/* Training pairs from the current state: sample s sits at the cell drawn by SplitMix64 from
+ * (seed, s); x_raw_dev (float[n][7]) receives its raw (unscaled) inputs and y_dev (float[n])
+ * the dynamic-model coefficient of its plane (context with sgs = DSM, after les_nut or a
+ * substep). */
+les_status les_mlp_sample(les_ctx* ctx, uint64_t seed, int64_t n_samples, float* x_raw_dev, float* y_dev);
+
+/* The functions below need no context; they enqueue on hip_stream (NULL = default). */
+
+/* x = (x_raw - lo)/(hi - lo) per input (device float[n][7] in and out; lo, hi host double[7]). */
+les_status les_mlp_normalize(void* hip_stream, const float* x_raw_dev, int64_t n, const double* lo,
+                             const double* hi, float* x_dev);
+
+/* y_dev[n] = network(x_dev[n][7]) (scaled inputs, no clipping). */
+les_status les_mlp_forward(void* hip_stream, const float* params_dev, const float* x_dev, int64_t n, float* y_dev);
+
+/* Bytes of device workspace les_mlp_grad needs for n samples. */
+int64_t les_mlp_workspace_bytes(int64_t n);
+
+/* Gradient of the mean-squared error mean((network(x) - y)^2) over n samples: grad_dev
+ * (float[4737]) and loss_dev (one float, may be NULL).  dz2 and dz1 enter the products in
+ * bfloat16; per-block partial gradients are summed in a fixed order (run-to-run identical). */
+les_status les_mlp_grad(void* hip_stream, const float* params_dev, const float* x_dev, const float* y_dev,
+                        int64_t n, void* workspace_dev, float* grad_dev, float* loss_dev);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on params_dev with moments m_dev, v_dev
+ * (float[4737] each); step is the 1-based Adam counter. */
+les_status les_mlp_adam(void* hip_stream, float* params_dev, const float* grad_dev, float* m_dev, float* v_dev,
+                        int step, float lr);
+
+/* les_mlp_grad followed by les_mlp_adam. */
+les_status les_mlp_train_step(void* hip_stream, float* params_dev, const float* x_dev, const float* y_dev,
+                              int64_t n, void* workspace_dev, float* grad_dev, float* m_dev, float* v_dev,
+                              int step, float lr, float* loss_dev);
 
 /* Per-kernel timing.  les_timing(ctx, 1) starts recording: every kernel the context
  * enqueues afterwards is bracketed by two HIP events on the context stream and tagged with

@@ -167,6 +167,7 @@ size_t carve(Ctx& c, char* base) {
   t.twz_f = (float*)take(2 * n * 4);
   t.hfac = (double*)take(6 * n * 8);
   t.dt = (double*)take(16 * 8);
+  c.mlp_cnt = (int*)take(2 * sizeof(int));
   t.red_n = 4096;
   t.red = (double*)take(t.red_n * 8);
   const int64_t npairs = (int64_t)n * (f.ny / 2);
@@ -362,6 +363,7 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       c.twz_f_host.clear();
       for (double x : c.twz) c.twz_f_host.push_back((float)x);
       c.coef_host.assign(n + 2, 0.0);
+      if (f.sgs == LES_SGS_MLP && c.mlp_params != nullptr) c.coef_host = c.delta2;
       if (f.sgs == LES_SGS_SMAG || f.sgs == LES_SGS_SMAG_VD)
         for (int k = 0; k <= n + 1; ++k) {
           const double d = std::pow((f.lx / f.nx) * (f.ly / f.ny) * c.dzf[k], 1.0 / 3.0);
@@ -387,6 +389,9 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       if ((s = up(c.t.twy_f, c.twy_f_host.data(), c.twy_f_host.size() * 4)) != LES_OK) return s;
       if ((s = up(c.t.twz_f, c.twz_f_host.data(), c.twz_f_host.size() * 4)) != LES_OK) return s;
       if ((s = up(c.t.hfac, c.hfac_host.data(), c.hfac_host.size() * 8)) != LES_OK) return s;
+      // learned closure: the first evaluation runs the dynamic model (fallback coefficients)
+      static const int cnt_init[2] = {0, 1};
+      if ((s = up(c.mlp_cnt, cnt_init, sizeof(cnt_init))) != LES_OK) return s;
       c.initialised = false;
       if (c.graph_exec) {
         hipGraphExecDestroy(c.graph_exec);
@@ -539,6 +544,10 @@ les_status les_diag(les_ctx* ctx, les_diag_t* out) {
     return s;
   if ((s = check_hip(c, hipMemcpyAsync(&dt, c.t.dt, 8, hipMemcpyDeviceToHost, c.stream), "diag copy")) != LES_OK)
     return s;
+  int cnt[2] = {0, 0};
+  if ((s = check_hip(c, hipMemcpyAsync(cnt, c.mlp_cnt, sizeof(cnt), hipMemcpyDeviceToHost, c.stream), "diag copy")) !=
+      LES_OK)
+    return s;
   if ((s = check_hip(c, hipStreamSynchronize(c.stream), "diag sync")) != LES_OK) return s;
   std::memset(out, 0, sizeof(*out));
   out->max_div = h[0];
@@ -548,22 +557,98 @@ les_status les_diag(les_ctx* ctx, les_diag_t* out) {
   out->tauw_mean[0] = h[4] / (double)c.g.sxy;
   out->tauw_mean[1] = h[5] / (double)c.g.sxy;
   out->dt = dt;
+  out->mlp_flagged = cnt[1];
   return out->nonfinite ? LES_ENONFINITE : LES_OK;
 }
 
-les_status les_mlp_bind(les_ctx* ctx, float*, const double*, const double*) {
+les_status les_mlp_bind(les_ctx* ctx, const float* params, const double* lo, const double* hi) {
   if (!ctx) return LES_EINVAL;
-  return fail(&ctx->c, LES_ENOTSUP, "learned closure not built");
+  Ctx& c = ctx->c;
+  if (c.cfg.sgs != LES_SGS_MLP) return fail(&c, LES_ESTATE, "context was not created with sgs = LES_SGS_MLP");
+  if (!c.ws) return fail(&c, LES_ESTATE, "workspace not bound");
+  if (!params || !lo || !hi) return fail(&c, LES_EINVAL, "null argument");
+  for (int a = 0; a < 7; ++a)
+    if (!(std::isfinite(lo[a]) && std::isfinite(hi[a]) && hi[a] > lo[a]))
+      return fail(&c, LES_EINVAL, "feature ranges must satisfy lo < hi");
+  c.mlp_params = const_cast<float*>(params);
+  for (int a = 0; a < 7; ++a) {
+    c.mlp_lo[a] = lo[a];
+    c.mlp_hi[a] = hi[a];
+  }
+  // nu_t = Delta^2 * (c |S|) for the learned closure
+  les_status s = check_hip(c, hipMemcpyAsync(c.t.coef, c.delta2.data(), (c.cfg.nz + 2) * 8, hipMemcpyHostToDevice,
+                                             c.stream), "mlp coef");
+  if (s != LES_OK) return s;
+  static const int cnt_init[2] = {0, 1};
+  s = check_hip(c, hipMemcpyAsync(c.mlp_cnt, cnt_init, sizeof(cnt_init), hipMemcpyHostToDevice, c.stream), "mlp cnt");
+  if (s != LES_OK) return s;
+  if (c.graph_exec) {
+    hipGraphExecDestroy(c.graph_exec);
+    c.graph_exec = nullptr;
+  }
+  if (c.graph) {
+    hipGraphDestroy(c.graph);
+    c.graph = nullptr;
+  }
+  return LES_OK;
 }
 
-les_status les_mlp_sample(les_ctx* ctx, uint64_t, int64_t, float*, float*) {
+les_status les_mlp_sample(les_ctx* ctx, uint64_t seed, int64_t n, float* x, float* y) {
   if (!ctx) return LES_EINVAL;
-  return fail(&ctx->c, LES_ENOTSUP, "learned closure not built");
+  Ctx& c = ctx->c;
+  les_status s = ready(c, true);
+  if (s != LES_OK) return s;
+  if (c.cfg.sgs != LES_SGS_DSM && c.cfg.sgs != LES_SGS_MLP)
+    return fail(&c, LES_ESTATE, "sampling needs the dynamic-model coefficient (sgs = DSM)");
+  if (n <= 0 || !x || !y) return fail(&c, LES_EINVAL, "bad sample buffers");
+  if (c.cfg.precision == LES_MIXED) launch_mlp_sample<float>(c, seed, n, x, y);
+  else launch_mlp_sample<double>(c, seed, n, x, y);
+  return check_launch(c, "les_mlp_sample");
 }
 
-les_status les_mlp_train_step(les_ctx* ctx, const float*, const float*, int64_t, float, int, float*, float*, float*) {
-  if (!ctx) return LES_EINVAL;
-  return fail(&ctx->c, LES_ENOTSUP, "learned closure not built");
+int64_t les_mlp_workspace_bytes(int64_t n) {
+  if (n <= 0) return 0;
+  return mlp_grad_blocks(n) * (int64_t)(4737 + 1) * 4;
+}
+
+static les_status mlp_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LES_OK : LES_EDEVICE;
+}
+
+les_status les_mlp_forward(void* stream, const float* params, const float* x, int64_t n, float* y) {
+  if (!params || !x || !y || n <= 0) return LES_EINVAL;
+  launch_mlp_forward((hipStream_t)stream, params, x, n, y);
+  return mlp_status();
+}
+
+les_status les_mlp_normalize(void* stream, const float* x_raw, int64_t n, const double* lo, const double* hi,
+                             float* x) {
+  if (!x_raw || !x || !lo || !hi || n <= 0) return LES_EINVAL;
+  for (int a = 0; a < 7; ++a)
+    if (!(std::isfinite(lo[a]) && std::isfinite(hi[a]) && hi[a] > lo[a])) return LES_EINVAL;
+  launch_mlp_normalize((hipStream_t)stream, x_raw, n, lo, hi, x);
+  return mlp_status();
+}
+
+les_status les_mlp_grad(void* stream, const float* params, const float* x, const float* y, int64_t n, void* ws,
+                        float* grad, float* loss) {
+  if (!params || !x || !y || !ws || !grad || n <= 0) return LES_EINVAL;
+  launch_mlp_grad((hipStream_t)stream, params, x, y, n, (float*)ws, grad, loss);
+  return mlp_status();
+}
+
+les_status les_mlp_adam(void* stream, float* params, const float* grad, float* m, float* v, int step, float lr) {
+  if (!params || !grad || !m || !v || step < 1 || !(lr > 0.0f)) return LES_EINVAL;
+  launch_mlp_adam((hipStream_t)stream, params, grad, m, v, step, lr);
+  return mlp_status();
+}
+
+les_status les_mlp_train_step(void* stream, float* params, const float* x, const float* y, int64_t n, void* ws,
+                              float* grad, float* m, float* v, int step, float lr, float* loss) {
+  les_status s = les_mlp_grad(stream, params, x, y, n, ws, grad, loss);
+  if (s != LES_OK) return s;
+  return les_mlp_adam(stream, params, grad, m, v, step, lr);
 }
 
 static void clear_timing(Ctx& c) {

@@ -93,9 +93,9 @@ struct Ctx {
   void* spec = nullptr;   // complex spectrum [nz][ny][nx/2+1]
   int dsm_kc = 8;         // planes per z chunk of the fused dynamic-model kernel
   // learned closure
-  float* mlp_params = nullptr;
-  double mlp_lo[7], mlp_hi[7];
-  int64_t* flag_count = nullptr;
+  float* mlp_params = nullptr;   // caller-owned float32 parameters (les_mlp_bind)
+  double mlp_lo[7], mlp_hi[7];    // feature ranges for min-max scaling
+  int* mlp_cnt = nullptr;         // [2] fallback counters in the workspace
   // graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -125,8 +125,14 @@ template <typename T> void launch_dt(Ctx& c, double cfl);
 template <typename T> void launch_poisson_field(Ctx& c, T* f);
 template <typename T> void launch_read_nut(Ctx& c, T* dst);
 template <typename T> void launch_diag(Ctx& c, double* out_dev);
+template <typename T> void launch_mlp_sample(Ctx& c, uint64_t seed, int64_t n, float* x, float* y);
+int64_t mlp_grad_blocks(int64_t n);
+void launch_mlp_forward(hipStream_t st, const float* P, const float* x, int64_t n, float* y);
+void launch_mlp_grad(hipStream_t st, const float* P, const float* x, const float* t, int64_t n, float* part,
+                     float* grad, float* loss);
+void launch_mlp_adam(hipStream_t st, float* P, const float* g, float* m, float* v, int step, float lr);
+void launch_mlp_normalize(hipStream_t st, const float* xr, int64_t n, const double* lo, const double* hi, float* x);
 void launch_set_dt(Ctx& c, double dt);
-void launch_helmholtz_factor(Ctx& c, int stage);
 
 // Kernel launch on the context stream.  With timing enabled the launch is bracketed by
 // two HIP events and tagged with its algorithmic byte count (minimum HBM traffic of the
@@ -135,13 +141,13 @@ void launch_helmholtz_factor(Ctx& c, int stage);
   do {                                                                                          \
     hipEvent_t les_ev_a_ = nullptr, les_ev_b_ = nullptr;                                        \
     if ((ctx).timing) {                                                                         \
-      hipEventCreate(&les_ev_a_);                                                               \
-      hipEventCreate(&les_ev_b_);                                                               \
-      hipEventRecord(les_ev_a_, (ctx).stream);                                                  \
+      (void)hipEventCreate(&les_ev_a_);                                                         \
+      (void)hipEventCreate(&les_ev_b_);                                                         \
+      (void)hipEventRecord(les_ev_a_, (ctx).stream);                                            \
     }                                                                                           \
     hipLaunchKernelGGL(kernel, grid, block, shmem, (ctx).stream, __VA_ARGS__);                  \
     if ((ctx).timing) {                                                                         \
-      hipEventRecord(les_ev_b_, (ctx).stream);                                                  \
+      (void)hipEventRecord(les_ev_b_, (ctx).stream);                                            \
       (ctx).timed.push_back({name, les_ev_a_, les_ev_b_, (double)(bytes)});                     \
     }                                                                                           \
   } while (0)

@@ -1,0 +1,133 @@
+// Device building blocks of the learned-closure perceptron shared by the training kernels
+// (mlp.hip) and the fused eddy-viscosity inference (sgs.hip).  See mlp.hip for the design.
+#pragma once
+
+#include "les_internal.h"
+
+namespace les {
+namespace mlp {
+
+constexpr int H = 64, F = 7, FP = 16;
+constexpr int P_W1 = 0, P_B1 = 448, P_W2 = 512, P_B2 = 4608, P_W3 = 4672, P_B3 = 4736, NPARAM = 4737;
+constexpr int WAVES = 4, NT = 64 * WAVES;   // 4 waves of 64 samples per block
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// round-to-nearest-even float32 -> bfloat16 bits
+__device__ inline unsigned short f2bf(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float silu(float z) { return z / (1.0f + expf(-z)); }
+__device__ inline float dsilu(float z) {
+  const float s = 1.0f / (1.0f + expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+__device__ inline f4 mfma(s4 a, s4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+__device__ inline s4 lds4(const unsigned short* p) {
+  const unsigned int* q = reinterpret_cast<const unsigned int*>(p);
+  const unsigned int a = q[0], b = q[1];
+  s4 r;
+  r.x = (short)(a & 0xFFFF);
+  r.y = (short)(a >> 16);
+  r.z = (short)(b & 0xFFFF);
+  r.w = (short)(b >> 16);
+  return r;
+}
+__device__ inline s4 pack4(float a, float b, float c, float d) {
+  s4 r;
+  r.x = (short)f2bf(a);
+  r.y = (short)f2bf(b);
+  r.z = (short)f2bf(c);
+  r.w = (short)f2bf(d);
+  return r;
+}
+
+// Weights staged once per block: bf16 W1 (padded to 16 features), W2 and W2^T; float32
+// biases and output layer.
+struct Weights {
+  unsigned short w1[H * FP];
+  unsigned short w2[H * H];
+  unsigned short w2t[H * H];
+  float b1[H], b2[H], w3[H];
+  float b3;
+};
+
+__device__ void load_weights(const float* __restrict__ P, Weights& W, int tid, int nthr) {
+  for (int e = tid; e < H * FP; e += nthr) {
+    const int r = e / FP, f = e % FP;
+    W.w1[e] = f < F ? f2bf(P[P_W1 + r * F + f]) : (unsigned short)0;
+  }
+  for (int e = tid; e < H * H; e += nthr) {
+    const int r = e / H, c = e % H;
+    const unsigned short b = f2bf(P[P_W2 + e]);
+    W.w2[e] = b;
+    W.w2t[c * H + r] = b;
+  }
+  for (int e = tid; e < H; e += nthr) {
+    W.b1[e] = P[P_B1 + e];
+    W.b2[e] = P[P_B2 + e];
+    W.w3[e] = P[P_W3 + e];
+  }
+  if (tid == 0) W.b3 = P[P_B3];
+}
+
+// Forward pass of one wave over 64 samples whose bf16 features sit in xb[64][16].
+// Outputs (registers, tile (a, sb) holds hidden rows 16a + 4(l/16) + i, sample 16sb + l%16):
+// z1, h1b (bf16 of silu(z1)), z2, h2 = silu(z2), and y[sb] for sample 16sb + l%16.
+struct Fwd {
+  f4 z1[4][4];
+  s4 h1b[4][4];
+  f4 z2[4][4];
+  f4 h2[4][4];
+  float y[4];
+};
+
+template <bool KEEP>
+__device__ void forward_wave(const Weights& W, const unsigned short* xb, int lane, Fwd& o) {
+  const int r16 = lane % 16, g4 = 4 * (lane / 16);
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+  // layer 1: Z1^T(16a.., 16sb..) = W1 tile a  x  X^T tile sb
+  for (int a = 0; a < 4; ++a) {
+    const s4 A = lds4(&W.w1[(16 * a + r16) * FP + g4]);
+    for (int sb = 0; sb < 4; ++sb) {
+      const s4 B = lds4(&xb[(16 * sb + r16) * FP + g4]);
+      f4 z = mfma(A, B, zero);
+      float h[4];
+      for (int i = 0; i < 4; ++i) {
+        z[i] += W.b1[16 * a + g4 + i];
+        h[i] = silu(z[i]);
+      }
+      if (KEEP) o.z1[a][sb] = z;
+      o.h1b[a][sb] = pack4(h[0], h[1], h[2], h[3]);
+    }
+  }
+  // layer 2: Z2^T(16a.., 16sb..) = sum_kb W2 tile (a, kb)  x  H1^T tile (kb, sb)
+  for (int a = 0; a < 4; ++a) {
+    for (int sb = 0; sb < 4; ++sb) {
+      f4 z = zero;
+      for (int kb = 0; kb < 4; ++kb) z = mfma(lds4(&W.w2[(16 * a + r16) * H + 16 * kb + g4]), o.h1b[kb][sb], z);
+      f4 h;
+      for (int i = 0; i < 4; ++i) {
+        z[i] += W.b2[16 * a + g4 + i];
+        h[i] = silu(z[i]);
+      }
+      if (KEEP) o.z2[a][sb] = z;
+      o.h2[a][sb] = h;
+    }
+  }
+  // layer 3 (float32): y = W3 . h2 + b3, reduced over the four lane groups
+  for (int sb = 0; sb < 4; ++sb) {
+    float p = 0.f;
+    for (int a = 0; a < 4; ++a)
+      for (int i = 0; i < 4; ++i) p += W.w3[16 * a + g4 + i] * o.h2[a][sb][i];
+    p += __shfl_xor(p, 16, 64);
+    p += __shfl_xor(p, 32, 64);
+    o.y[sb] = p + W.b3;
+  }
+}
+
+}  // namespace mlp
+}  // namespace les

@@ -333,56 +333,85 @@ __global__ void k_thomas(GridP g, cpx<T>* __restrict__ spec, const double* __res
   C* cp = cps + threadIdx.x;
   const int cs = blockDim.x;
   if (l == 0 && m == 0) {
-    // singular column, all in double
+    // singular column, all in double, scratch in LDS (3 nz doubles after the cp columns)
+    double* z = reinterpret_cast<double*>(smem_raw + (size_t)blockDim.x * n * sizeof(C));
     const int nn = n - 1;
     double cprev = 0.0, dprev = 0.0;
     for (int k = 0; k < nn; ++k) {
       const double a = pa[k];
       const double piv = pb[k] - a * cprev;
       const double cc = pc[k] / piv;
-      const double d = ((double)x[k * st].x * norm - a * dprev) / piv;
-      zcol[k] = cc;
-      zcol[n + k] = d;
+      const double d = ((double)x[(int64_t)k * st].x * norm - a * dprev) / piv;
+      z[k] = cc;
+      z[n + k] = d;
       cprev = cc;
       dprev = d;
     }
     double xn = dprev;
-    zcol[2 * n + nn - 1] = xn;
+    z[2 * n + nn - 1] = xn;
     for (int k = nn - 2; k >= 0; --k) {
-      xn = zcol[n + k] - zcol[k] * xn;
-      zcol[2 * n + k] = xn;
+      xn = z[n + k] - z[k] * xn;
+      z[2 * n + k] = xn;
     }
-    zcol[2 * n + n - 1] = 0.0;
+    z[2 * n + n - 1] = 0.0;
     double sw = 0.0, sd = 0.0;
     for (int k = 0; k < n; ++k) {
-      sw += zcol[2 * n + k] * g.dzf[k + 1];
+      sw += z[2 * n + k] * g.dzf[k + 1];
       sd += g.dzf[k + 1];
     }
     const double mean = sw / sd;
-    for (int k = 0; k < n; ++k) x[k * st] = {(T)(zcol[2 * n + k] - mean), (T)0};
+    for (int k = 0; k < n; ++k) x[(int64_t)k * st] = {(T)(z[2 * n + k] - mean), (T)0};
+    (void)zcol;
     return;
   }
   const double lam = lamx[l] + lamy[m];
+  // The loads do not depend on the recurrence: fetch PF levels ahead into registers.
+  constexpr int PF = 8;
+  cpx<T> cur[PF], nxt[PF];
+  for (int t = 0; t < PF; ++t) cur[t] = t < n ? x[(int64_t)t * st] : cpx<T>{(T)0, (T)0};
   double cprev = 0.0, drx = 0.0, dry = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double a = pa[k];
-    const double piv = (pb[k] + lam) - a * cprev;
-    const double r = 1.0 / piv;
-    const double cc = pc[k] * r;
-    const cpx<T> f = x[k * st];
-    drx = ((double)f.x * norm - a * drx) * r;
-    dry = ((double)f.y * norm - a * dry) * r;
-    cp[k * cs] = (C)cc;
-    x[k * st] = {(T)drx, (T)dry};
-    cprev = cc;
+  for (int k0 = 0; k0 < n; k0 += PF) {
+    for (int t = 0; t < PF; ++t) {
+      const int kk = k0 + PF + t;
+      nxt[t] = kk < n ? x[(int64_t)kk * st] : cpx<T>{(T)0, (T)0};
+    }
+    for (int t = 0; t < PF; ++t) {
+      const int k = k0 + t;
+      if (k < n) {
+        const double a = pa[k];
+        const double piv = (pb[k] + lam) - a * cprev;
+        const double r = 1.0 / piv;
+        const double cc = pc[k] * r;
+        drx = ((double)cur[t].x * norm - a * drx) * r;
+        dry = ((double)cur[t].y * norm - a * dry) * r;
+        cp[k * cs] = (C)cc;
+        x[(int64_t)k * st] = {(T)drx, (T)dry};
+        cprev = cc;
+      }
+    }
+    for (int t = 0; t < PF; ++t) cur[t] = nxt[t];
   }
   double xr = drx, xi = dry;
-  for (int k = n - 2; k >= 0; --k) {
-    const cpx<T> d = x[k * st];
-    const double c = (double)cp[k * cs];
-    xr = (double)d.x - c * xr;
-    xi = (double)d.y - c * xi;
-    x[k * st] = {(T)xr, (T)xi};
+  // backward sweep over k = n-2 .. 0, PF levels fetched ahead
+  for (int t = 0; t < PF; ++t) {
+    const int k = n - 2 - t;
+    cur[t] = k >= 0 ? x[(int64_t)k * st] : cpx<T>{(T)0, (T)0};
+  }
+  for (int k0 = n - 2; k0 >= 0; k0 -= PF) {
+    for (int t = 0; t < PF; ++t) {
+      const int k = k0 - PF - t;
+      nxt[t] = k >= 0 ? x[(int64_t)k * st] : cpx<T>{(T)0, (T)0};
+    }
+    for (int t = 0; t < PF; ++t) {
+      const int k = k0 - t;
+      if (k >= 0) {
+        const double c = (double)cp[k * cs];
+        xr = (double)cur[t].x - c * xr;
+        xi = (double)cur[t].y - c * xi;
+        x[(int64_t)k * st] = {(T)xr, (T)xi};
+      }
+    }
+    for (int t = 0; t < PF; ++t) cur[t] = nxt[t];
   }
 }
 
@@ -431,7 +460,8 @@ __global__ void k_scalar_ghosts(GridP g, T* f) {
 
 // ============================================================================ launchers
 // Transforms per 256-thread block: a power of two (so the block splits into equal teams)
-// with at most 1024 complex points per buffer (two buffers: <= 32 KiB in double).
+// with at most 1024 complex points per buffer (two buffers: <= 32 KiB in double; larger
+// tiles measured slower on the channel workload).
 static int pow2_floor(int v) {
   int p = 1;
   while (p * 2 <= v) p *= 2;
@@ -494,7 +524,7 @@ static void spectral_solve(Ctx& c) {
     const int64_t ncol = (int64_t)nxh * ny;
     int tpb = 64;
     while (tpb > 16 && (size_t)tpb * nz * sizeof(T) > 65536) tpb /= 2;
-    const size_t sh = (size_t)tpb * nz * sizeof(T);
+    const size_t sh = (size_t)tpb * nz * sizeof(T) + 3 * (size_t)nz * sizeof(double);
     const double norm = 1.0 / ((double)c.g.nx * ny);
     double* zcol = c.t.zcol;
     LES_LAUNCH(c, "thomas_z", 2 * spec_bytes, (k_thomas<T, T>), dim3((unsigned)((ncol + tpb - 1) / tpb)), dim3(tpb), sh,

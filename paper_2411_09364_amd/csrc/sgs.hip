@@ -13,6 +13,9 @@
 // linear extrapolation in z of the first two interior values (one-sided wall-normal
 // derivative in the first layer, Sec. 2.2); otherwise the stored ghosts are used.
 #include "les_internal.h"
+#include "mlp_core.h"
+
+#include <algorithm>
 
 namespace les {
 
@@ -160,7 +163,8 @@ __global__ void k_vd_coef(GridP g, const T* u, const T* v, const double* tau, in
 // strided partial sums over the tiles, then a fixed-order tree.  With periodic z every block
 // forms the total over all planes itself (same order in every block).
 __global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part, int ntile, double* cs,
-                                                    double* coef) {
+                                                    double* coef, const int* gate) {
+  if (gate != nullptr && gate[0] == 0) return;
   __shared__ double sm[2][256];
   const int n = g.nz;
   const bool per = g.zbc == LES_ZBC_PERIODIC;
@@ -191,9 +195,11 @@ __global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part,
     const double sa = sm[0][0], sb = sm[1][0];
     const double c = sb > 0.0 ? fmax(sa / sb, 0.0) : 0.0;
     cs[k] = c;
-    coef[k + 1] = c * g.delta2[k + 1];
-    if (k == 0) coef[per ? n + 1 : 0] = c * g.delta2[1];
-    if (k == n - 1) coef[per ? 0 : n + 1] = c * g.delta2[n];
+    if (coef != nullptr) {
+      coef[k + 1] = c * g.delta2[k + 1];
+      if (k == 0) coef[per ? n + 1 : 0] = c * g.delta2[1];
+      if (k == n - 1) coef[per ? 0 : n + 1] = c * g.delta2[n];
+    }
   }
 }
 
@@ -256,8 +262,9 @@ __device__ inline int ring3(int q) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_dsm_fused(GridP g, const T* __restrict__ u, const T* __restrict__ v,
                                                    const T* __restrict__ w, T* __restrict__ nut,
-                                                   double* __restrict__ part, int kc) {
+                                                   double* __restrict__ part, int kc, const int* __restrict__ gate) {
   using namespace fused;
+  if (gate != nullptr && gate[0] == 0) return;   // learned closure: no point fell back
   __shared__ T vel[3][3][N2];   // [slot][component][R2]
   __shared__ T qb[9][N1];       // centre quantities of the current stage plane
   __shared__ T ut[3][3][N1];    // filtered velocity [slot][component][R1]
@@ -484,6 +491,241 @@ __global__ void __launch_bounds__(256) k_dsm_fused(GridP g, const T* __restrict_
   }
 }
 
+// ============================================================================ learned closure
+// Friction velocity of each wall from the plane-mean wall stress (wall-model stresses or
+// the no-slip viscous flux), stored in dt[2] (bottom) and dt[3] (top); also rotates the
+// fallback counters: cnt[0] = points that fell back in the previous evaluation (gate of the
+// dynamic-model fallback), cnt[1] = 0.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mlp_prep(GridP g, const T* u, const T* v, const double* tau, int wallmodel,
+                                                  double* dtp, int* cnt) {
+  __shared__ double sm[4][256];
+  double a[4] = {0, 0, 0, 0};
+  const int64_t s = g.sxy;
+  const int n = g.nz;
+  if (g.zbc != LES_ZBC_PERIODIC)
+    for (int64_t c = threadIdx.x; c < s; c += 256) {
+      if (wallmodel) {
+        for (int q = 0; q < 4; ++q) a[q] += tau[q * s + c];
+      } else {
+        a[0] += g.nu * ((double)u[s + c] - (double)u[c]) / g.dzc[0];
+        a[1] += g.nu * ((double)v[s + c] - (double)v[c]) / g.dzc[0];
+        a[2] += g.nu * ((double)u[(int64_t)n * s + c] - (double)u[(int64_t)(n + 1) * s + c]) / g.dzc[n];
+        a[3] += g.nu * ((double)v[(int64_t)n * s + c] - (double)v[(int64_t)(n + 1) * s + c]) / g.dzc[n];
+      }
+    }
+  for (int q = 0; q < 4; ++q) sm[q][threadIdx.x] = a[q];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int q = 0; q < 4; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    dtp[2] = sqrt(hypot(sm[0][0] / s, sm[1][0] / s));
+    dtp[3] = sqrt(hypot(sm[2][0] / s, sm[3][0] / s));
+    if (cnt != nullptr) {
+      cnt[0] = cnt[1];
+      cnt[1] = 0;
+    }
+  }
+}
+
+// Rotation tensor at the cell centre (edges, then the four-edge mean, like the strain),
+// with the strain ghost rule: o[0..2] = O12, O13, O23.
+template <typename T>
+__device__ inline void centre_rotation(const GridP& g, const T* u, const T* v, const T* w, int k, int j, int i,
+                                       double o[3]) {
+  const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx), jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
+  const double rdx = g.rdx, rdy = g.rdy, rdzc = 1.0 / g.dzc[k], rdzcm = 1.0 / g.dzc[k - 1];
+  auto U = [&](int kk, int jj, int ii) { return (double)sval(g, u, kk, jj, ii); };
+  auto V = [&](int kk, int jj, int ii) { return (double)sval(g, v, kk, jj, ii); };
+  auto W = [&](int kk, int jj, int ii) { return (double)w[idx3(g, kk, jj, ii)]; };
+  auto r12 = [&](int jj, int ii) {
+    return 0.5 * ((U(k, wrap_p(jj, g.ny), ii) - U(k, jj, ii)) * rdy - (V(k, jj, wrap_p(ii, g.nx)) - V(k, jj, ii)) * rdx);
+  };
+  o[0] = 0.25 * (r12(j, i) + r12(j, im) + r12(jm, i) + r12(jm, im));
+  auto r13 = [&](int kk, int ii, double rz) {
+    return 0.5 * ((U(kk + 1, j, ii) - U(kk, j, ii)) * rz - (W(kk, j, wrap_p(ii, g.nx)) - W(kk, j, ii)) * rdx);
+  };
+  o[1] = 0.25 * (r13(k, i, rdzc) + r13(k, im, rdzc) + r13(k - 1, i, rdzcm) + r13(k - 1, im, rdzcm));
+  auto r23 = [&](int kk, int jj, double rz) {
+    return 0.5 * ((V(kk + 1, jj, i) - V(kk, jj, i)) * rz - (W(kk, wrap_p(jj, g.ny), i) - W(kk, jj, i)) * rdy);
+  };
+  o[2] = 0.25 * (r23(k, j, rdzc) + r23(k, jm, rdzc) + r23(k - 1, j, rdzcm) + r23(k - 1, jm, rdzcm));
+  (void)ip;
+  (void)jp;
+}
+
+// The seven raw inputs of the network at a cell (see les.h): invariants of S/n and O/n,
+// n = sqrt(S_ij S_ij + O_ij O_ij), then y+ and Delta/delta (delta = 1).
+__device__ inline void raw_features(const double s[6], const double o[3], double yplus, double delta, double f[7]) {
+  const double S[3][3] = {{s[0], s[3], s[4]}, {s[3], s[1], s[5]}, {s[4], s[5], s[2]}};
+  const double O[3][3] = {{0.0, o[0], o[1]}, {-o[0], 0.0, o[2]}, {-o[1], -o[2], 0.0}};
+  double ss = 0.0, oo = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      ss += S[a][b] * S[a][b];
+      oo += O[a][b] * O[a][b];
+    }
+  const double nrm = sqrt(ss + oo);
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  double Sh[3][3], Oh[3][3], S2[3][3], O2[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      Sh[a][b] = S[a][b] * inv;
+      Oh[a][b] = O[a][b] * inv;
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double x = 0.0, y = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        x += Sh[a][c] * Sh[c][b];
+        y += Oh[a][c] * Oh[c][b];
+      }
+      S2[a][b] = x;
+      O2[a][b] = y;
+    }
+  double t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    t0 += S2[a][a];
+    t1 += O2[a][a];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      t2 += S2[a][c] * Sh[c][a];
+      t3 += O2[a][c] * Sh[c][a];
+      t4 += O2[a][c] * S2[c][a];
+    }
+  }
+  f[0] = t0;
+  f[1] = t1;
+  f[2] = t2;
+  f[3] = t3;
+  f[4] = t4;
+  f[5] = yplus;
+  f[6] = delta;
+}
+
+struct MlpNorm {
+  double lo[7], hi[7];
+};
+
+template <typename T>
+__device__ inline void cell_features(const GridP& g, const T* u, const T* v, const T* w, int k, int j, int i,
+                                     const double* dtp, double f[7], T s6[6]) {
+  centre_strain(g, u, v, w, k, j, i, s6);
+  double s[6];
+  for (int a = 0; a < 6; ++a) s[a] = (double)s6[a];
+  double o[3];
+  centre_rotation(g, u, v, w, k, j, i, o);
+  double yplus = 0.0;
+  if (g.zbc != LES_ZBC_PERIODIC) {
+    const double zc = g.zc[k];
+    const bool lower = zc <= 0.5 * g.lz;
+    const double d = lower ? zc : g.lz - zc;
+    yplus = d * (lower ? dtp[2] : dtp[3]) / g.nu;
+  }
+  raw_features(s, o, yplus, sqrt(g.delta2[k]), f);
+}
+
+// Fused inference: each wave takes 64 cells, computes their features, runs the network on
+// the matrix cores and stores c |S| (nu_t = Delta^2 c |S|, c = max(0, MLP)); a cell whose
+// scaled inputs leave [-0.05, 1.05] takes the dynamic coefficient of its plane instead and
+// is counted.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mlp_nut(GridP g, const T* __restrict__ u, const T* __restrict__ v,
+                                                 const T* __restrict__ w, T* __restrict__ nut,
+                                                 const float* __restrict__ P, MlpNorm nm, const double* __restrict__ cs,
+                                                 const double* __restrict__ dtp, int* __restrict__ cnt) {
+  using namespace mlp;
+  __shared__ Weights Wt;
+  __shared__ unsigned short xs[WAVES][64 * FP];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  load_weights(P, Wt, tid, NT);
+  __syncthreads();
+  const int64_t ncell = (int64_t)g.nz * g.sxy;
+  const int64_t nchunk = (ncell + NT - 1) / NT;
+  int flagged = 0;
+  for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const int64_t e = ch * NT + tid;
+    const bool ok = e < ncell;
+    int k = 1, j = 0, i = 0;
+    if (ok) {
+      k = (int)(e / g.sxy) + 1;
+      const int64_t r = e % g.sxy;
+      j = (int)(r / g.nx);
+      i = (int)(r % g.nx);
+    }
+    double f[7];
+    T s6[6];
+    bool flag = false;
+    if (ok) {
+      cell_features(g, u, v, w, k, j, i, dtp, f, s6);
+      for (int a = 0; a < 7; ++a) {
+        const double xn = (f[a] - nm.lo[a]) / (nm.hi[a] - nm.lo[a]);
+        flag = flag || xn < -0.05 || xn > 1.05;
+        f[a] = xn;
+      }
+    }
+    for (int a = 0; a < FP; ++a) xs[wave][lane * FP + a] = (a < F && ok) ? f2bf((float)f[a]) : (unsigned short)0;
+    __syncthreads();
+    Fwd o;
+    forward_wave<false>(Wt, xs[wave], lane, o);
+    // this lane's own sample is 16 (lane/16) + lane%16 = lane (select, not an indexed
+    // load, so the activations stay in registers)
+    const int q4 = lane >> 4;
+    const float y = q4 == 0 ? o.y[0] : (q4 == 1 ? o.y[1] : (q4 == 2 ? o.y[2] : o.y[3]));
+    if (ok) {
+      const T smag = strain_mag(s6);
+      double c = y > 0.0f ? (double)y : 0.0;
+      if (flag) {
+        c = cs[k - 1];
+        ++flagged;
+      }
+      store_nut(g, nut, k, j, i, (T)c * smag);
+    }
+    __syncthreads();
+  }
+  if (cnt != nullptr) {
+    for (int off = 32; off > 0; off >>= 1) flagged += __shfl_down(flagged, off, 64);
+    if (lane == 0 && flagged) atomicAdd(&cnt[1], flagged);
+  }
+}
+
+// Training pairs: sample s sits at the cell hashed from (seed, s) (SplitMix64); x gets
+// its seven raw features, y the dynamic coefficient of its plane.
+__device__ inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void k_mlp_sample(GridP g, const T* u, const T* v, const T* w, const double* cs, const double* dtp,
+                             uint64_t seed, int64_t n, float* x, float* y) {
+  const int64_t sidx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (sidx >= n) return;
+  const uint64_t ncell = (uint64_t)g.nz * (uint64_t)g.sxy;
+  const uint64_t e = splitmix64(seed ^ splitmix64((uint64_t)sidx)) % ncell;
+  const int k = (int)(e / (uint64_t)g.sxy) + 1;
+  const int64_t r = (int64_t)(e % (uint64_t)g.sxy);
+  const int j = (int)(r / g.nx), i = (int)(r % g.nx);
+  double f[7];
+  T s6[6];
+  cell_features(g, u, v, w, k, j, i, dtp, f, s6);
+  for (int a = 0; a < 7; ++a) x[sidx * 7 + a] = (float)f[a];
+  y[sidx] = (float)cs[k - 1];
+}
+
 // ============================================================================ launcher
 template <typename T>
 void launch_eddy_viscosity(Ctx& c) {
@@ -501,14 +743,42 @@ void launch_eddy_viscosity(Ctx& c) {
     return;
   }
   if (model == LES_SGS_DSM || model == LES_SGS_MLP) {
+    const bool learned = model == LES_SGS_MLP && c.mlp_params != nullptr;
+    const int* gate = learned ? c.mlp_cnt : nullptr;
+    if (learned)
+      LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep<T>, dim3(1), dim3(256), 0, g, (const T*)c.u, (const T*)c.v, c.t.tau,
+                 c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.dt, c.mlp_cnt);
     const int kc = c.dsm_kc;
     dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + fused::TY - 1) / fused::TY, (g.nz + kc - 1) / kc);
     LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, fused::TY), 0, g,
-               (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.t.dsm_part, kc);
+               (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.t.dsm_part, kc, gate);
     const int ntile = (int)(grid.x * grid.y);
-    LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs, c.t.coef);
+    LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs,
+               learned ? nullptr : c.t.coef, gate);
+    if (learned) {
+      MlpNorm nm;
+      for (int a = 0; a < 7; ++a) {
+        nm.lo[a] = c.mlp_lo[a];
+        nm.hi[a] = c.mlp_hi[a];
+      }
+      const int64_t nchunk = ((int64_t)g.nz * g.sxy + mlp::NT - 1) / mlp::NT;
+      const unsigned nb = (unsigned)std::min<int64_t>(nchunk, 2048);
+      LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), k_mlp_nut<T>, dim3(nb), dim3(mlp::NT), 0, g, (const T*)c.u,
+                 (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm, c.t.cs, c.t.dt, c.mlp_cnt);
+    }
   }
 }
+
+template <typename T>
+void launch_mlp_sample(Ctx& c, uint64_t seed, int64_t n, float* x, float* y) {
+  const GridP& g = c.g;
+  LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep<T>, dim3(1), dim3(256), 0, g, (const T*)c.u, (const T*)c.v, c.t.tau,
+             c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.dt, (int*)nullptr);
+  LES_LAUNCH(c, "mlp_sample", 0, k_mlp_sample<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g, (const T*)c.u,
+             (const T*)c.v, (const T*)c.w, c.t.cs, c.t.dt, seed, n, x, y);
+}
+template void launch_mlp_sample<double>(Ctx&, uint64_t, int64_t, float*, float*);
+template void launch_mlp_sample<float>(Ctx&, uint64_t, int64_t, float*, float*);
 
 template <typename T>
 __global__ void k_read_nut(GridP g, const T* nut, const double* coef, T* dst, int64_t n) {

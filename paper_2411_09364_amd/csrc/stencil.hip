@@ -6,6 +6,11 @@
 
 namespace les {
 
+constexpr int kMaxNz = 512;   // largest wall-bounded nz accepted by les_init
+
+__device__ void helmholtz_factor_body(const GridP& g, double* hfac, const double* dtp, double gamma, int wallmodel,
+                                      double* dzf, double* dzc, int tid, int nthr);
+
 Launch3 point_launch(const GridP& g, int planes) {
   Launch3 L;
   int bx = g.nx >= 64 ? 64 : g.nx;
@@ -34,10 +39,20 @@ __global__ void __launch_bounds__(256) k_predictor(GridP g, const T* __restrict_
                                                    T* __restrict__ ru, T* __restrict__ rv, T* __restrict__ rw,
                                                    T* __restrict__ us, T* __restrict__ vs, T* __restrict__ ws,
                                                    const double* __restrict__ dtp, double alpha, double beta,
-                                                   double gamma, int use_rprev, int write_r) {
+                                                   double gamma, int use_rprev, int write_r, double* hfac,
+                                                   int wallmodel) {
+  if (IMPLICIT && blockIdx.z == 0) {
+    // the first z slice of blocks is scheduled first: one block computes the shared CN
+    // factorisation of this substep while the others run the stencil
+    __shared__ double fz[2][kMaxNz + 2];
+    if (blockIdx.x == 0 && blockIdx.y == 0)
+      helmholtz_factor_body(g, hfac, dtp, gamma, wallmodel, fz[0], fz[1], threadIdx.y * blockDim.x + threadIdx.x,
+                            blockDim.x * blockDim.y);
+    return;
+  }
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z + 1;
+  const int k = IMPLICIT ? blockIdx.z : blockIdx.z + 1;
   if (i >= g.nx || j >= g.ny) return;
   const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx);
   const int jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
@@ -183,7 +198,7 @@ void launch_predictor(Ctx& c, int stage) {
   static const double A[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
   static const double B[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
   const double G = A[stage] + B[stage];
-  Launch3 L = point_launch(c.g, c.g.nz);
+  Launch3 L = point_launch(c.g, c.g.nz + (c.cfg.implicit_z ? 1 : 0));
   const int use_rprev = stage > 0;
   const int write_r = stage < 2;
   auto f = c.cfg.implicit_z ? k_predictor<T, true> : k_predictor<T, false>;
@@ -191,7 +206,8 @@ void launch_predictor(Ctx& c, int stage) {
   const double words = 8 + 3 * use_rprev + 3 * write_r;
   LES_LAUNCH(c, "predictor", words * pts * sizeof(T), f, L.grid, L.block, 0, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
                      (const T*)c.p, (const T*)c.nut, c.t.coef, (T*)c.ru, (T*)c.rv, (T*)c.rw, (T*)c.us, (T*)c.vs,
-                     (T*)c.wsf, c.t.dt, A[stage], B[stage], G, use_rprev, write_r);
+                     (T*)c.wsf, c.t.dt, A[stage], B[stage], G, use_rprev, write_r, c.t.hfac,
+                     c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);
 }
 
 // ============================================================================ CN in z
@@ -200,13 +216,13 @@ void launch_predictor(Ctx& c, int stage) {
 // substep by three threads: u/v rows, w rows, and the flow-rate profile q = H^-1 1 of
 // the u rows (no-slip walls; 1 otherwise).  Layout of hfac: [cp_uv | rp_uv | cp_w | rp_w
 // | q | -] each nz long.
-__global__ void __launch_bounds__(256) k_helmholtz_factor(GridP g, double* hfac, const double* dtp, double gamma,
-                                                          int wallmodel) {
-  extern __shared__ double shm[];
+// Runs in one block of nthr threads; dzf/dzc are LDS copies of the metrics.  Thread 0 runs
+// the u/v chain (and the flow-rate profile), thread 64 (thread 0 in small blocks) the w chain.
+__device__ void helmholtz_factor_body(const GridP& g, double* hfac, const double* dtp, double gamma, int wallmodel,
+                                      double* dzf, double* dzc, int tid, int nthr) {
   const int n = g.nz;
-  double* dzf = shm;            // [n + 2]
-  double* dzc = shm + n + 2;    // [n + 2]
-  for (int k = threadIdx.x; k < n + 2; k += blockDim.x) {
+  const int wthread = nthr > 64 ? 64 : 0;
+  for (int k = tid; k < n + 2; k += nthr) {
     dzf[k] = g.dzf[k];
     dzc[k] = g.dzc[k];
   }
@@ -217,7 +233,7 @@ __global__ void __launch_bounds__(256) k_helmholtz_factor(GridP g, double* hfac,
   double* cp_w = hfac + 2 * n;
   double* rp_w = hfac + 3 * n;
   double* qv = hfac + 4 * n;
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     double cprev = 0.0, dp = 0.0;
     for (int kk = 1; kk <= n; ++kk) {
       double lo = 1.0 / (dzc[kk - 1] * dzf[kk]);
@@ -241,7 +257,8 @@ __global__ void __launch_bounds__(256) k_helmholtz_factor(GridP g, double* hfac,
     } else {
       for (int kk = 0; kk < n; ++kk) qv[kk] = 1.0;
     }
-  } else if (threadIdx.x == 64) {
+  }
+  if (tid == wthread) {
     const int m = n - 1;
     double cprev = 0.0;
     for (int kk = 1; kk <= m; ++kk) {
@@ -257,12 +274,6 @@ __global__ void __launch_bounds__(256) k_helmholtz_factor(GridP g, double* hfac,
       cp_w[kk - 1] = cprev;
     }
   }
-}
-
-void launch_helmholtz_factor(Ctx& c, int stage) {
-  static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
-  LES_LAUNCH(c, "helmholtz_factor", 0, k_helmholtz_factor, dim3(1), dim3(128), 2 * (c.g.nz + 2) * sizeof(double), c.g, c.t.hfac, c.t.dt, G[stage],
-                     c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);
 }
 
 // One thread per (component, j, i) column: forward elimination with the shared factors,
@@ -284,33 +295,57 @@ __global__ void __launch_bounds__(256) k_helmholtz(GridP g, T* __restrict__ us, 
   const int m = comp < 2 ? n : n - 1;
   const int64_t s = g.sxy;
   T* xc = x + s + col;  // plane 1
-  double lo_prev = 0.0;
+  constexpr int PF = 8;
+  T cur[PF], nxt[PF];
+  for (int t = 0; t < PF; ++t) cur[t] = t < m ? xc[(int64_t)t * s] : (T)0;
   double dp = 0.0;
-  for (int kk = 1; kk <= m; ++kk) {
-    double r = (double)xc[(int64_t)(kk - 1) * s];
-    if (comp < 2 && wallmodel) {
-      if (kk == 1) r += c * (-(tau[(comp == 0 ? 0 : 1) * s + col] / g.nu) / g.dzf[1]);
-      if (kk == n) r += c * (-(tau[(comp == 0 ? 2 : 3) * s + col] / g.nu) / g.dzf[n]);
+  for (int k0 = 0; k0 < m; k0 += PF) {
+    for (int t = 0; t < PF; ++t) {
+      const int kk = k0 + PF + t;
+      nxt[t] = kk < m ? xc[(int64_t)kk * s] : (T)0;
     }
-    double lo;
-    if (comp < 2) lo = kk == 1 ? 0.0 : 1.0 / (g.dzc[kk - 1] * g.dzf[kk]);
-    else lo = kk == 1 ? 0.0 : 1.0 / (g.dzf[kk] * g.dzc[kk]);
-    dp = (r - (-c * lo) * dp) * rp[kk - 1];
-    xc[(int64_t)(kk - 1) * s] = (T)dp;
-    (void)lo_prev;
+    for (int t = 0; t < PF; ++t) {
+      const int kk = k0 + t + 1;   // row index 1..m
+      if (kk <= m) {
+        double r = (double)cur[t];
+        if (comp < 2 && wallmodel) {
+          if (kk == 1) r += c * (-(tau[(comp == 0 ? 0 : 1) * s + col] / g.nu) / g.dzf[1]);
+          if (kk == n) r += c * (-(tau[(comp == 0 ? 2 : 3) * s + col] / g.nu) / g.dzf[n]);
+        }
+        double lo;
+        if (comp < 2) lo = kk == 1 ? 0.0 : 1.0 / (g.dzc[kk - 1] * g.dzf[kk]);
+        else lo = kk == 1 ? 0.0 : 1.0 / (g.dzf[kk] * g.dzc[kk]);
+        dp = (r - (-c * lo) * dp) * rp[kk - 1];
+        xc[(int64_t)(kk - 1) * s] = (T)dp;
+      }
+    }
+    for (int t = 0; t < PF; ++t) cur[t] = nxt[t];
   }
   double xn = dp;
-  for (int kk = m - 1; kk >= 1; --kk) {
-    const double d = (double)xc[(int64_t)(kk - 1) * s];
-    xn = d - cp[kk - 1] * xn;
-    xc[(int64_t)(kk - 1) * s] = (T)xn;
+  // back substitution over rows m-1 .. 1
+  for (int t = 0; t < PF; ++t) {
+    const int kk = m - 1 - t;
+    cur[t] = kk >= 1 ? xc[(int64_t)(kk - 1) * s] : (T)0;
+  }
+  for (int k0 = m - 1; k0 >= 1; k0 -= PF) {
+    for (int t = 0; t < PF; ++t) {
+      const int kk = k0 - PF - t;
+      nxt[t] = kk >= 1 ? xc[(int64_t)(kk - 1) * s] : (T)0;
+    }
+    for (int t = 0; t < PF; ++t) {
+      const int kk = k0 - t;
+      if (kk >= 1) {
+        xn = (double)cur[t] - cp[kk - 1] * xn;
+        xc[(int64_t)(kk - 1) * s] = (T)xn;
+      }
+    }
+    for (int t = 0; t < PF; ++t) cur[t] = nxt[t];
   }
 }
 
 template <typename T>
 void launch_helmholtz(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
-  launch_helmholtz_factor(c, stage);
   dim3 block(256), grid((unsigned)((c.g.sxy + 255) / 256), 3);
   LES_LAUNCH(c, "helmholtz_z", 6.0 * c.g.sxy * c.g.nz * sizeof(T), k_helmholtz<T>, grid, block, 0, c.g, (T*)c.us, (T*)c.vs, (T*)c.wsf, c.t.hfac,
                      c.t.tau, c.t.dt, G[stage], c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);

@@ -64,7 +64,11 @@ def _load():
         "les_diag": [vp, ctypes.POINTER(LesDiag)],
         "les_mlp_bind": [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
         "les_mlp_sample": [vp, ctypes.c_uint64, ctypes.c_int64, vp, vp],
-        "les_mlp_train_step": [vp, vp, vp, ctypes.c_int64, ctypes.c_float, i32, vp, vp, vp],
+        "les_mlp_normalize": [vp, vp, ctypes.c_int64, ctypes.POINTER(dbl), ctypes.POINTER(dbl), vp],
+        "les_mlp_forward": [vp, vp, vp, ctypes.c_int64, vp],
+        "les_mlp_grad": [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp],
+        "les_mlp_adam": [vp, vp, vp, vp, vp, i32, ctypes.c_float],
+        "les_mlp_train_step": [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp, i32, ctypes.c_float, vp],
         "les_free": [vp],
         "les_timing": [vp, i32],
         "les_timing_report": [vp, ctypes.c_char_p, ctypes.c_size_t],
@@ -73,6 +77,8 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    lib.les_mlp_workspace_bytes.argtypes = [ctypes.c_int64]
+    lib.les_mlp_workspace_bytes.restype = ctypes.c_int64
     lib.les_strerror.argtypes = [ctypes.c_int]
     lib.les_strerror.restype = ctypes.c_char_p
     lib.les_last_error.argtypes = [vp]
@@ -87,8 +93,9 @@ def exported_symbols():
     """Names of the ABI functions the binding resolves (all must exist in the library)."""
     return ["les_init", "les_layout", "les_bind", "les_nut", "les_dt", "les_set_dt", "les_substep",
             "les_step", "les_poisson", "les_read", "les_diag", "les_mlp_bind", "les_mlp_sample",
-            "les_mlp_train_step", "les_free", "les_strerror", "les_last_error", "les_timing",
-            "les_timing_report"]
+            "les_mlp_normalize", "les_mlp_forward", "les_mlp_workspace_bytes", "les_mlp_grad",
+            "les_mlp_adam", "les_mlp_train_step", "les_free", "les_strerror", "les_last_error",
+            "les_timing", "les_timing_report"]
 
 
 def make_config(nx, ny, nz, lx, ly, lz, zbc=ZBC_PERIODIC, beta=0.0, nu=1e-3, sgs=SGS_NONE, cs=0.17,
@@ -158,6 +165,98 @@ def les_diag(ctx):
     if st not in (LES_OK, LES_ENONFINITE):
         _check(ctx, st, "les_diag")
     return d, st
+
+
+def _d7(a):
+    return (ctypes.c_double * 7)(*[float(x) for x in a])
+
+
+def les_mlp_bind(ctx, params_ptr, lo, hi):
+    _check(ctx, LIB.les_mlp_bind(ctx, ctypes.c_void_p(params_ptr), _d7(lo), _d7(hi)), "les_mlp_bind")
+
+
+def les_mlp_sample(ctx, seed, n, x_ptr, y_ptr):
+    _check(ctx, LIB.les_mlp_sample(ctx, seed, n, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr)), "les_mlp_sample")
+
+
+def les_mlp_normalize(stream, xraw_ptr, n, lo, hi, x_ptr):
+    _check(None, LIB.les_mlp_normalize(ctypes.c_void_p(stream), ctypes.c_void_p(xraw_ptr), n, _d7(lo), _d7(hi),
+                                       ctypes.c_void_p(x_ptr)), "les_mlp_normalize")
+
+
+def les_mlp_forward(stream, params_ptr, x_ptr, n, y_ptr):
+    _check(None, LIB.les_mlp_forward(ctypes.c_void_p(stream), ctypes.c_void_p(params_ptr), ctypes.c_void_p(x_ptr), n,
+                                     ctypes.c_void_p(y_ptr)), "les_mlp_forward")
+
+
+def les_mlp_workspace_bytes(n):
+    return int(LIB.les_mlp_workspace_bytes(n))
+
+
+def les_mlp_grad(stream, params_ptr, x_ptr, y_ptr, n, ws_ptr, grad_ptr, loss_ptr):
+    vp = ctypes.c_void_p
+    _check(None, LIB.les_mlp_grad(vp(stream), vp(params_ptr), vp(x_ptr), vp(y_ptr), n, vp(ws_ptr), vp(grad_ptr),
+                                  vp(loss_ptr)), "les_mlp_grad")
+
+
+def les_mlp_adam(stream, params_ptr, grad_ptr, m_ptr, v_ptr, step, lr):
+    vp = ctypes.c_void_p
+    _check(None, LIB.les_mlp_adam(vp(stream), vp(params_ptr), vp(grad_ptr), vp(m_ptr), vp(v_ptr), step, lr),
+           "les_mlp_adam")
+
+
+def les_mlp_train_step(stream, params_ptr, x_ptr, y_ptr, n, ws_ptr, grad_ptr, m_ptr, v_ptr, step, lr, loss_ptr):
+    vp = ctypes.c_void_p
+    _check(None, LIB.les_mlp_train_step(vp(stream), vp(params_ptr), vp(x_ptr), vp(y_ptr), n, vp(ws_ptr),
+                                        vp(grad_ptr), vp(m_ptr), vp(v_ptr), step, lr, vp(loss_ptr)),
+           "les_mlp_train_step")
+
+
+class Mlp:
+    """Torch-owned parameters, Adam moments and gradient workspace of the learned closure;
+    every operation runs in the library's kernels on the given stream."""
+
+    NPARAM = 4737
+
+    def __init__(self, params_host, stream=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.params = torch.as_tensor(params_host, dtype=torch.float32).to(device).contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.step_count = 0
+        self._ws = None
+        torch.cuda.synchronize()   # the copies above ran on torch's current stream
+
+    def _workspace(self, n):
+        torch = self.torch
+        need = les_mlp_workspace_bytes(n)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.params.device)
+        return self._ws
+
+    def forward(self, x):
+        torch = self.torch
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        les_mlp_forward(self.stream.cuda_stream, self.params.data_ptr(), x.data_ptr(), x.shape[0], y.data_ptr())
+        return y
+
+    def gradient(self, x, y):
+        ws = self._workspace(x.shape[0])
+        les_mlp_grad(self.stream.cuda_stream, self.params.data_ptr(), x.data_ptr(), y.data_ptr(), x.shape[0],
+                     ws.data_ptr(), self.grad.data_ptr(), self.loss.data_ptr())
+        return self.grad, self.loss
+
+    def train_step(self, x, y, lr):
+        ws = self._workspace(x.shape[0])
+        self.step_count += 1
+        les_mlp_train_step(self.stream.cuda_stream, self.params.data_ptr(), x.data_ptr(), y.data_ptr(),
+                           x.shape[0], ws.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                           self.step_count, lr, self.loss.data_ptr())
+        return self.loss
 
 
 def les_timing(ctx, enable):
@@ -278,6 +377,18 @@ class Solver:
 
     def diag(self):
         return les_diag(self.ctx)
+
+    def mlp_bind(self, mlp, lo, hi):
+        les_mlp_bind(self.ctx, mlp.params.data_ptr(), lo, hi)
+        self._mlp = mlp   # keep the parameters alive while bound
+
+    def mlp_sample(self, seed, n):
+        torch = self.torch
+        x = torch.empty((n, 7), dtype=torch.float32, device=self.u.device)
+        y = torch.empty(n, dtype=torch.float32, device=self.u.device)
+        les_mlp_sample(self.ctx, seed, n, x.data_ptr(), y.data_ptr())
+        self.synchronize()
+        return x, y
 
     def close(self):
         if self.ctx:

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "les.h")).read()
-    return sorted(set(re.findall(r"^(?:les_status|const char\*)\s+(les_\w+)\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:les_status|const char\*|int64_t)\s+(les_\w+)\(", src, re.M)))
 
 
 def test_header_declares_entry_points():
