@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-learned", action="store_true")
     return ap.parse_args()
 
 
@@ -99,6 +100,72 @@ def cpu_baseline(cfgd, budget_s):
     return {"value": cells * n / el / 1e6, "unit": "Mpts·substeps/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} oracle substep(s) of the full {cfgd['nx']}x{cfgd['ny']}x{cfgd['nz']} workload "
                       f"in {el:.1f} s, numpy float64, 1 thread"}
+
+
+def learned_closure(les, torch, cfgd, solver, steps, warmup, use_graph):
+    """Same workload with the learned closure: the network is trained on the GPU from
+    dynamic-model pairs sampled from the plain solver's current state (400 Adam steps on
+    2^16 samples), bound to a second context started from the same initial field, and the
+    same step loop is timed."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    xr, yr = solver.mlp_sample(7, 1 << 16)
+    xn = xr.cpu().numpy().astype(np.float64)
+    lo, hi = xn.min(axis=0), xn.max(axis=0)
+    pad = 0.25 * (hi - lo) + 1e-12
+    lo, hi = lo - pad, hi + pad
+    x = torch.empty_like(xr)
+    les.les_mlp_normalize(solver.stream.cuda_stream, xr.data_ptr(), xr.shape[0], lo, hi, x.data_ptr())
+    rng = np.random.Generator(np.random.PCG64(5))
+    init = []
+    for shape in ((64, 7), (64,), (64, 64), (64,), (1, 64), (1,)):
+        if len(shape) == 2:
+            lim = np.sqrt(6.0 / shape[1]) * 0.5
+            init.append(rng.uniform(-lim, lim, size=shape).ravel())
+        else:
+            init.append(np.zeros(shape))
+    mlp = les.Mlp(np.concatenate(init), stream=solver.stream)
+    t0 = time.perf_counter()
+    for it in range(400):
+        loss = mlp.train_step(x, yr, 3e-3 if it < 300 else 1e-3)
+    solver.synchronize()
+    train_s = time.perf_counter() - t0
+    cfg = les.make_config(cfgd["nx"], cfgd["ny"], cfgd["nz"], cfgd["lx"], cfgd["ly"], cfgd["lz"], zbc=cfgd["zbc"],
+                          beta=cfgd["beta"], nu=cfgd["nu"], sgs=les.SGS_MLP, cs=cfgd["cs"],
+                          implicit_z=cfgd["implicit_z"], precision=cfgd["precision"], ubulk=cfgd["ubulk"])
+    s2 = les.Solver(cfg)
+    zf, zc = s2.zgrid()
+    u, v, w = initial_fields(cfgd, zc)
+    s2.set_state(u, v, w)
+    s2.mlp_bind(mlp, lo, hi)
+    s2.nut()
+    ctx = s2.ctx
+
+    def step(graph):
+        les.les_dt(ctx, 0.5, sync=False)
+        les.les_step(ctx, graph)
+
+    for _ in range(warmup):
+        step(use_graph)
+    s2.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(use_graph)
+    s2.synchronize()
+    el = time.perf_counter() - t0
+    les.les_timing(ctx, True)
+    step(False)
+    les.les_timing(ctx, False)
+    rep = les.les_timing_report(ctx)
+    d, _ = s2.diag()
+    cells = cfgd["nx"] * cfgd["ny"] * cfgd["nz"]
+    out = {"value": round(cells * 3 * steps / el / 1e6, 3), "unit": "Mpts·substeps/s",
+           "ms_per_step": round(el / steps * 1e3, 4), "train_loss": float(loss.item()),
+           "train_seconds": round(train_s, 3), "fallback_points_last_eval": int(d.mlp_flagged),
+           "nut_kernel_us": {k: round(1e3 * v["ms"] / v["count"], 2) for k, v in rep.items()
+                             if k.startswith("mlp") or k.startswith("dsm")}}
+    s2.close()
+    return out
 
 
 def traffic_entry(kernel, launches_bytes):
@@ -197,6 +264,8 @@ def main():
         "kernels": kernels,
         "state_check": {"max_div": diag.max_div, "ubulk": diag.ubulk, "nonfinite": int(diag.nonfinite)},
     }
+    if not args.no_learned and cfgd["sgs"] == 3:
+        out["learned_closure"] = learned_closure(les, torch, cfgd, solver, args.steps, args.warmup, use_graph)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfgd, args.cpu_seconds)
     solver.close()

@@ -229,6 +229,43 @@ les_status les_mlp_train_step(void* hip_stream, float* params_dev, const float* 
 les_status les_timing(les_ctx* ctx, int enable);
 les_status les_timing_report(les_ctx* ctx, char* buf, size_t len);
 
+/* ---------------------------------------------------------------- batched ensembles
+ * Many triply periodic boxes of (possibly) different sizes, viscosities and lengths advanced
+ * together: each kernel of the substep runs for all boxes in one launch (blocks assigned to
+ * boxes by prefix sums of the boxes' block counts), every box keeps its own time step and
+ * model coefficient, and a whole step can be replayed from one hipGraph.
+ * Every box config must have zbc = PERIODIC, implicit_z = 0, ubulk = 0; all boxes share sgs
+ * (NONE, SMAG or DSM) and precision.  Fields of all boxes are concatenated in one caller buffer
+ * per field (box b starts at les_batch_offset), the workspace is one caller buffer. */
+typedef struct les_batch les_batch;
+
+les_status les_batch_init(const les_config* cfgs, int nbox, void* hip_stream, les_batch** out);
+/* Total bytes of the concatenated U/V/W/P buffers (each) or of the workspace. */
+les_status les_batch_layout(const les_batch* b, int field, les_layout_t* out);
+/* Byte offset of box `box` inside the U/V/W/P buffers or the workspace. */
+les_status les_batch_offset(const les_batch* b, int box, int field, int64_t* byte_offset);
+les_status les_batch_bind(les_batch* b, int field, void* device_ptr);
+/* Ghost planes and eddy viscosity of every box (once, after writing the initial fields). */
+les_status les_batch_nut(les_batch* b);
+/* Per-box CFL time step into each box's device slot (same rule as les_dt). */
+les_status les_batch_dt(les_batch* b, double cfl);
+les_status les_batch_set_dt(les_batch* b, double dt);
+les_status les_batch_substep(les_batch* b, int stage);
+/* Per-box time step (skipped when cfl = 0: the slots keep their values) and three substeps;
+ * use_graph != 0 records them into a hipGraph on first use and replays it afterwards (the
+ * graph keeps the cfl it was recorded with). */
+les_status les_batch_step(les_batch* b, double cfl, int use_graph);
+/* Time `substeps` batched substeps for each candidate of the dynamic-model chunk length and
+ * of the FFT lines per block, keep the fastest, and write a JSON report into report (may be
+ * NULL).  The timed substeps advance the bound state: call it before writing the initial
+ * fields (the time-step slots must hold a positive value). */
+les_status les_batch_autotune(les_batch* b, int substeps, char* report, size_t len);
+/* Readable quantities and diagnostics of one box (as les_read / les_diag). */
+les_status les_batch_read(les_batch* b, int box, int field, void* dst);
+les_status les_batch_diag(les_batch* b, int box, les_diag_t* out);
+const char* les_batch_last_error(const les_batch* b);
+les_status les_batch_free(les_batch* b);
+
 /* Destroy the context (does not free caller memory). */
 les_status les_free(les_ctx* ctx);
 

@@ -13,10 +13,6 @@
 
 using namespace les;
 
-struct les_ctx {
-  Ctx c;
-};
-
 namespace {
 
 const double kPi = 3.14159265358979323846;

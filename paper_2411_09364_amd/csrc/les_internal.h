@@ -32,6 +32,14 @@ __host__ __device__ inline int64_t idx3(const GridP& g, int k, int j, int i) {
 __device__ inline int wrap_p(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 __device__ inline int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 
+// Radix plan of an LDS Stockham FFT (radix 3 first, then 4s, then a 2).
+struct FftPlan {
+  int n;
+  int nst;
+  int rad[16];
+};
+FftPlan make_plan(int n);
+
 // Device-side tables carved out of the workspace.
 struct Tables {
   double* zc;       // nz+2
@@ -158,4 +166,71 @@ struct Launch3 {
 };
 Launch3 point_launch(const GridP& g, int planes);
 
+// ---------------------------------------------------------------------------- batches
+// Kernel kinds of a batched substep; each batched launch covers all boxes, block b of the
+// launch belongs to the box whose prefix range holds b.
+enum BatchKind { BK_POINT = 0, BK_RFFTX, BK_FFTY, BK_FFTZ, BK_DSM, BK_DSMRED, BK_CFL, BK_NKIND };
+
+// Everything a batched kernel needs to run one box (device memory, one per box).
+struct BoxDesc {
+  GridP g;
+  void *u, *v, *w, *p;
+  void *ru, *rv, *rw, *us, *vs, *wsf, *nut, *phi, *spec;
+  double *coef, *cs, *dt, *red, *dsm_part, *lamx, *lamy, *lamz, *twx, *twy, *twz;
+  float *twx_f, *twy_f, *twz_f;
+  FftPlan px, py, pz;
+  int pbx;              // x-row pairs per forward/inverse x block
+  int ly, lz;           // lines per y / z FFT block
+  int kc;               // planes per dynamic-model chunk
+  int sgs;
+  double cs_smag;       // static coefficient (SMAG)
+  int gdim[BK_NKIND][3];  // per-kind block grid of this box
+};
+
+// Batch lookup: prefix[kind][box] = first block of box, prefix[kind][nbox] = total.
+constexpr int kMaxBox = 256;
+struct BatchMap {
+  const BoxDesc* desc;
+  const int* prefix;    // [BK_NKIND][nbox + 1]
+  int nbox;
+};
+
+__device__ inline int batch_box(const BatchMap& m, int kind, int b) {
+  const int* pre = m.prefix + kind * (m.nbox + 1);
+  int lo = 0, hi = m.nbox;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Block index of block b of a batched launch inside its box's own grid.
+__device__ inline dim3 batch_bid(const BatchMap& m, int kind, int b, int& box) {
+  box = batch_box(m, kind, b);
+  const int* pre = m.prefix + kind * (m.nbox + 1);
+  const int local = b - pre[box];
+  const int* gd = m.desc[box].gdim[kind];
+  return dim3(local % gd[0], (local / gd[0]) % gd[1], local / (gd[0] * gd[1]));
+}
+
+// batch launchers (all boxes of a batch in one launch per kernel kind)
+template <typename T> void batch_predictor(hipStream_t st, const BatchMap& m, int total, int stage);
+template <typename T> void batch_correct(hipStream_t st, const BatchMap& m, int total, int stage);
+template <typename T> void batch_dt(hipStream_t st, const BatchMap& m, int total_cfl, int nbox, double cfl);
+void batch_set_dt(hipStream_t st, const BatchMap& m, int nbox, double dt);
+template <typename T>
+void batch_poisson(hipStream_t st, const BatchMap& m, const int* totals, size_t sh_x, size_t sh_y, size_t sh_z,
+                   int stage);
+template <typename T>
+void batch_eddy_viscosity(hipStream_t st, const BatchMap& m, const int* totals, int any_dsm, int any_smag);
+int fft_pairs_per_block(int nx);
+int fft_lines_per_block(int n);
+
 }  // namespace les
+
+// opaque ABI handle of one context
+struct les_ctx {
+  les::Ctx c;
+};

@@ -25,12 +25,6 @@ struct cpx {
   R x, y;
 };
 
-struct FftPlan {
-  int n;
-  int nst;
-  int rad[16];
-};
-
 FftPlan make_plan(int n) {
   FftPlan p{};
   p.n = n;
@@ -143,7 +137,7 @@ __device__ inline const float* twsel<float>(const double*, const float* f) { ret
 // ============================================================================ forward x
 // MODE 0: f = D u* scaled; MODE 1: f given (les_poisson).
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_rfftx(GridP g, FftPlan P, const T* __restrict__ us, const T* __restrict__ vs,
+__device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, FftPlan P, const T* __restrict__ us, const T* __restrict__ vs,
                                                const T* __restrict__ ws, const T* __restrict__ fin,
                                                cpx<T>* __restrict__ spec, const double* __restrict__ twd,
                                                const float* __restrict__ twf, const double* __restrict__ dtp,
@@ -157,7 +151,7 @@ __global__ void __launch_bounds__(256) k_rfftx(GridP g, FftPlan P, const T* __re
   double bsum = 0.0;
   for (int e = threadIdx.x; e < npair_blk * nx; e += blockDim.x) {
     const int p = e / nx, i = e % nx;
-    const int64_t gp = (int64_t)blockIdx.x * npair_blk + p;
+    const int64_t gp = (int64_t)bid.x * npair_blk + p;
     cpx<T> z = {(T)0, (T)0};
     if (gp < npairs) {
       const int k = (int)(gp / nyh) + 1;
@@ -189,7 +183,7 @@ __global__ void __launch_bounds__(256) k_rfftx(GridP g, FftPlan P, const T* __re
       if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
       __syncthreads();
     }
-    if (threadIdx.x == 0) bulk_part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) bulk_part[bid.x] = red[0];
   }
   __syncthreads();
   const int team = blockDim.x / npair_blk;
@@ -200,7 +194,7 @@ __global__ void __launch_bounds__(256) k_rfftx(GridP g, FftPlan P, const T* __re
     res = stockham<T, -1>(A + p * nx, B + p * nx, P, tw, lane, team);
   }
   // res points into A or B for team p (same parity for all teams)
-  const int64_t gp = (int64_t)blockIdx.x * npair_blk + p;
+  const int64_t gp = (int64_t)bid.x * npair_blk + p;
   if (gp >= npairs) return;
   const int k = (int)(gp / nyh);
   const int j0 = 2 * (int)(gp % nyh);
@@ -215,9 +209,25 @@ __global__ void __launch_bounds__(256) k_rfftx(GridP g, FftPlan P, const T* __re
   }
 }
 
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_rfftx(GridP g, FftPlan P, const T* us, const T* vs, const T* ws, const T* fin,
+                                               cpx<T>* spec, const double* twd, const float* twf, const double* dtp,
+                                               double gamma, int npair_blk, double* bulk_part) {
+  rfftx_body<T, MODE>(blockIdx, g, P, us, vs, ws, fin, spec, twd, twf, dtp, gamma, npair_blk, bulk_part);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rfftx(BatchMap m, double gamma) {
+  int box;
+  const dim3 bid = batch_bid(m, BK_RFFTX, blockIdx.x, box);
+  const BoxDesc& d = m.desc[box];
+  rfftx_body<T, 0>(bid, d.g, d.px, (const T*)d.us, (const T*)d.vs, (const T*)d.wsf, nullptr, (cpx<T>*)d.spec, d.twx,
+                   d.twx_f, d.dt, gamma, d.pbx, nullptr);
+}
+
 // ============================================================================ inverse x
 template <typename T>
-__global__ void __launch_bounds__(256) k_irfftx(GridP g, FftPlan P, const cpx<T>* __restrict__ spec,
+__device__ __forceinline__ void irfftx_body(dim3 bid, GridP g, FftPlan P, const cpx<T>* __restrict__ spec,
                                                 T* __restrict__ out, const double* __restrict__ twd,
                                                 const float* __restrict__ twf, int npair_blk) {
   extern __shared__ unsigned char smem_raw[];
@@ -227,7 +237,7 @@ __global__ void __launch_bounds__(256) k_irfftx(GridP g, FftPlan P, const cpx<T>
   const int64_t npairs = (int64_t)g.nz * nyh;
   for (int e = threadIdx.x; e < npair_blk * nx; e += blockDim.x) {
     const int p = e / nx, l = e % nx;
-    const int64_t gp = (int64_t)blockIdx.x * npair_blk + p;
+    const int64_t gp = (int64_t)bid.x * npair_blk + p;
     cpx<T> z = {(T)0, (T)0};
     if (gp < npairs) {
       const int k = (int)(gp / nyh);
@@ -249,7 +259,7 @@ __global__ void __launch_bounds__(256) k_irfftx(GridP g, FftPlan P, const cpx<T>
   const int p = threadIdx.x / team, lane = threadIdx.x % team;
   const T* tw = twsel<T>(twd, twf);
   cpx<T>* res = stockham<T, 1>(A + p * nx, B + p * nx, P, tw, lane, team);
-  const int64_t gp = (int64_t)blockIdx.x * npair_blk + p;
+  const int64_t gp = (int64_t)bid.x * npair_blk + p;
   if (gp >= npairs) return;
   const int k = (int)(gp / nyh) + 1;
   const int j0 = 2 * (int)(gp % nyh);
@@ -259,13 +269,27 @@ __global__ void __launch_bounds__(256) k_irfftx(GridP g, FftPlan P, const cpx<T>
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_irfftx(GridP g, FftPlan P, const cpx<T>* spec, T* out, const double* twd,
+                                                const float* twf, int npair_blk) {
+  irfftx_body<T>(blockIdx, g, P, spec, out, twd, twf, npair_blk);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_irfftx(BatchMap m) {
+  int box;
+  const dim3 bid = batch_bid(m, BK_RFFTX, blockIdx.x, box);
+  const BoxDesc& d = m.desc[box];
+  irfftx_body<T>(bid, d.g, d.px, (const cpx<T>*)d.spec, (T*)d.phi, d.twx, d.twx_f, d.pbx);
+}
+
 // ============================================================================ strided lines
 // Complex FFT of length P.n along a strided dimension for L consecutive l values:
 // element t of line (l, o) is at base + o*ostride + t*lstride + l.  grid.x covers l tiles,
 // grid.y covers o.  SOLVE (periodic z only): forward FFT, multiply by
 // 1/(lamx + lamy + lamz) (0 for the zero mode) and the normalisation, inverse FFT.
 template <typename T, int DIR, bool SOLVE>
-__global__ void __launch_bounds__(256) k_fft_lines(FftPlan P, cpx<T>* __restrict__ data, int nl, int64_t lstride,
+__device__ __forceinline__ void fft_lines_body(dim3 bid, FftPlan P, cpx<T>* __restrict__ data, int nl, int64_t lstride,
                                                    int64_t ostride, int L, const double* __restrict__ twd,
                                                    const float* __restrict__ twf, const double* __restrict__ lamx,
                                                    const double* __restrict__ lamy, const double* __restrict__ lamz,
@@ -274,8 +298,8 @@ __global__ void __launch_bounds__(256) k_fft_lines(FftPlan P, cpx<T>* __restrict
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
   const int N = P.n;
   cpx<T>* B = A + L * N;
-  const int l0 = blockIdx.x * L;
-  const int o = blockIdx.y;
+  const int l0 = bid.x * L;
+  const int o = bid.y;
   cpx<T>* base = data + (int64_t)o * ostride;
   for (int e = threadIdx.x; e < L * N; e += blockDim.x) {
     const int t = e / L, ll = e % L;
@@ -308,6 +332,28 @@ __global__ void __launch_bounds__(256) k_fft_lines(FftPlan P, cpx<T>* __restrict
     const int l = l0 + l2;
     if (l < nl) base[(int64_t)t * lstride + l] = R[l2 * N + t];
   }
+}
+
+template <typename T, int DIR, bool SOLVE>
+__global__ void __launch_bounds__(256) k_fft_lines(FftPlan P, cpx<T>* data, int nl, int64_t lstride, int64_t ostride,
+                                                   int L, const double* twd, const float* twf, const double* lamx,
+                                                   const double* lamy, const double* lamz, double norm) {
+  fft_lines_body<T, DIR, SOLVE>(blockIdx, P, data, nl, lstride, ostride, L, twd, twf, lamx, lamy, lamz, norm);
+}
+
+// Batched y transforms (SOLVE = false) or periodic-z spectral solve (SOLVE = true).
+template <typename T, int DIR, bool SOLVE>
+__global__ void __launch_bounds__(256) kb_fft_lines(BatchMap m) {
+  int box;
+  const dim3 bid = batch_bid(m, SOLVE ? BK_FFTZ : BK_FFTY, blockIdx.x, box);
+  const BoxDesc& d = m.desc[box];
+  const int nxh = d.g.nx / 2 + 1;
+  if (SOLVE)
+    fft_lines_body<T, DIR, true>(bid, d.pz, (cpx<T>*)d.spec, nxh, (int64_t)nxh * d.g.ny, (int64_t)nxh, d.lz, d.twz,
+                                 d.twz_f, d.lamx, d.lamy, d.lamz, 1.0 / ((double)d.g.nx * d.g.ny * d.g.nz));
+  else
+    fft_lines_body<T, DIR, false>(bid, d.py, (cpx<T>*)d.spec, nxh, (int64_t)nxh, (int64_t)nxh * d.g.ny, d.ly,
+                                  d.twy, d.twy_f, d.lamx, d.lamy, d.lamz, 1.0);
 }
 
 // ============================================================================ Thomas
@@ -578,6 +624,23 @@ void launch_poisson_field(Ctx& c, T* f) {
   LES_LAUNCH(c, "scalar_ghosts", 4.0 * c.g.sxy * sizeof(T), k_scalar_ghosts<T>, dim3((unsigned)((c.g.sxy + 255) / 256)),
              dim3(256), 0, c.g, f);
 }
+
+// ============================================================================ batch launchers
+template <typename T>
+void batch_poisson(hipStream_t st, const BatchMap& m, const int* totals, size_t sh_x, size_t sh_y, size_t sh_z,
+                   int stage) {
+  static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
+  hipLaunchKernelGGL(kb_rfftx<T>, dim3(totals[BK_RFFTX]), dim3(256), sh_x, st, m, G[stage]);
+  hipLaunchKernelGGL((kb_fft_lines<T, -1, false>), dim3(totals[BK_FFTY]), dim3(256), sh_y, st, m);
+  hipLaunchKernelGGL((kb_fft_lines<T, -1, true>), dim3(totals[BK_FFTZ]), dim3(256), sh_z, st, m);
+  hipLaunchKernelGGL((kb_fft_lines<T, 1, false>), dim3(totals[BK_FFTY]), dim3(256), sh_y, st, m);
+  hipLaunchKernelGGL(kb_irfftx<T>, dim3(totals[BK_RFFTX]), dim3(256), sh_x, st, m);
+}
+template void batch_poisson<float>(hipStream_t, const BatchMap&, const int*, size_t, size_t, size_t, int);
+template void batch_poisson<double>(hipStream_t, const BatchMap&, const int*, size_t, size_t, size_t, int);
+
+int fft_pairs_per_block(int nx) { return pairs_per_block(nx); }
+int fft_lines_per_block(int n) { return lines_per_block(n); }
 
 #define INST(T)                                                                              \
   template void launch_poisson_rhs_fwd<T>(Ctx&, const T*, const T*, const T*, double, int); \

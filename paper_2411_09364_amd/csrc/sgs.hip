@@ -162,13 +162,12 @@ __global__ void k_vd_coef(GridP g, const T* u, const T* v, const double* tau, in
 // when z is periodic; coef[k] = c_s Delta_k^2 with ghost copies.  One block per plane:
 // strided partial sums over the tiles, then a fixed-order tree.  With periodic z every block
 // forms the total over all planes itself (same order in every block).
-__global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part, int ntile, double* cs,
-                                                    double* coef, const int* gate) {
+__device__ __forceinline__ void dsm_reduce_body(int k, GridP g, const double* part, int ntile, double* cs,
+                                                double* coef, const int* gate) {
   if (gate != nullptr && gate[0] == 0) return;
   __shared__ double sm[2][256];
   const int n = g.nz;
   const bool per = g.zbc == LES_ZBC_PERIODIC;
-  const int k = blockIdx.x;
   double a = 0.0, b = 0.0;
   if (per) {
     for (int64_t e = threadIdx.x; e < (int64_t)n * ntile; e += 256) {
@@ -201,6 +200,11 @@ __global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part,
       if (k == n - 1) coef[per ? 0 : n + 1] = c * g.delta2[n];
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part, int ntile, double* cs,
+                                                    double* coef, const int* gate) {
+  dsm_reduce_body(blockIdx.x, g, part, ntile, cs, coef, gate);
 }
 
 // ============================================================================ fused dynamic model
@@ -260,7 +264,8 @@ __device__ inline int ring3(int q) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_dsm_fused(GridP g, const T* __restrict__ u, const T* __restrict__ v,
+__device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP g, const T* __restrict__ u,
+                                               const T* __restrict__ v,
                                                    const T* __restrict__ w, T* __restrict__ nut,
                                                    double* __restrict__ part, int kc, const int* __restrict__ gate) {
   using namespace fused;
@@ -270,14 +275,14 @@ __global__ void __launch_bounds__(256) k_dsm_fused(GridP g, const T* __restrict_
   __shared__ T ut[3][3][N1];    // filtered velocity [slot][component][R1]
   __shared__ double red[2][NT / 64];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int i0 = bid.x * TX, j0 = bid.y * TY;
   const int nz = g.nz;
-  const int kb = 1 + blockIdx.z * kc;
+  const int kb = 1 + bid.z * kc;
   const int ke = min(nz, kb + kc - 1);
   const bool per = g.zbc == LES_ZBC_PERIODIC;
   const bool wm = g.zbc == LES_ZBC_WALLMODEL;
-  const int ntile = gridDim.x * gridDim.y;
-  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+  const int ntile = gdx * gdy;
+  const int tile = bid.y * gdx + bid.x;
   const T rdx = (T)g.rdx, rdy = (T)g.rdy;
   const T W0 = (T)0.25, W1 = (T)0.5;
   auto wrapi = [&](int i) { return ((i % g.nx) + g.nx) % g.nx; };   // tiles may exceed the grid
@@ -491,20 +496,60 @@ __global__ void __launch_bounds__(256) k_dsm_fused(GridP g, const T* __restrict_
   }
 }
 
-// ============================================================================ learned closure
-// Friction velocity of each wall from the plane-mean wall stress (wall-model stresses or
-// the no-slip viscous flux), stored in dt[2] (bottom) and dt[3] (top); also rotates the
-// fallback counters: cnt[0] = points that fell back in the previous evaluation (gate of the
-// dynamic-model fallback), cnt[1] = 0.
 template <typename T>
-__global__ void __launch_bounds__(256) k_mlp_prep(GridP g, const T* u, const T* v, const double* tau, int wallmodel,
-                                                  double* dtp, int* cnt) {
+__global__ void __launch_bounds__(256) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
+                                                   int kc, const int* gate) {
+  dsm_fused_body<T>(blockIdx, gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
+}
+
+// Batched dynamic model (and its plane / volume reduction) over all boxes of a batch.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_dsm_fused(BatchMap m) {
+  int box;
+  const dim3 bid = batch_bid(m, BK_DSM, blockIdx.x, box);
+  const BoxDesc& d = m.desc[box];
+  dsm_fused_body<T>(bid, d.gdim[BK_DSM][0], d.gdim[BK_DSM][1], d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w,
+                    (T*)d.nut, d.dsm_part, d.kc, nullptr);
+}
+
+__global__ void __launch_bounds__(256) kb_dsm_reduce(BatchMap m) {
+  int box;
+  const dim3 bid = batch_bid(m, BK_DSMRED, blockIdx.x, box);
+  const BoxDesc& d = m.desc[box];
+  dsm_reduce_body(bid.x, d.g, d.dsm_part, d.gdim[BK_DSM][0] * d.gdim[BK_DSM][1], d.cs, d.coef, nullptr);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_strain_mag(BatchMap m) {
+  int box;
+  const dim3 bid = batch_bid(m, BK_POINT, blockIdx.x, box);
+  const BoxDesc& d = m.desc[box];
+  const int i = bid.x * blockDim.x + threadIdx.x;
+  const int j = bid.y * blockDim.y + threadIdx.y;
+  const int k = bid.z + 1;
+  if (i >= d.g.nx || j >= d.g.ny) return;
+  T s[6];
+  centre_strain(d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w, k, j, i, s);
+  store_nut(d.g, (T*)d.nut, k, j, i, strain_mag(s));
+}
+
+// ============================================================================ learned closure
+// Plane sums of the four wall-stress components (bottom x, bottom y, top x, top y) from the
+// wall-model stresses or the no-slip viscous flux: stage 1, WM_BLOCKS blocks over
+// contiguous chunks of the plane, each a fixed-order tree.
+constexpr int WM_BLOCKS = 64;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_wall_mean_partial(GridP g, const T* u, const T* v, const double* tau,
+                                                           int wallmodel, double* part) {
   __shared__ double sm[4][256];
   double a[4] = {0, 0, 0, 0};
   const int64_t s = g.sxy;
   const int n = g.nz;
+  const int64_t chunk = (s + WM_BLOCKS - 1) / WM_BLOCKS;
+  const int64_t c0 = blockIdx.x * chunk, c1 = c0 + chunk < s ? c0 + chunk : s;
   if (g.zbc != LES_ZBC_PERIODIC)
-    for (int64_t c = threadIdx.x; c < s; c += 256) {
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += 256) {
       if (wallmodel) {
         for (int q = 0; q < 4; ++q) a[q] += tau[q * s + c];
       } else {
@@ -521,13 +566,24 @@ __global__ void __launch_bounds__(256) k_mlp_prep(GridP g, const T* u, const T* 
       for (int q = 0; q < 4; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    dtp[2] = sqrt(hypot(sm[0][0] / s, sm[1][0] / s));
-    dtp[3] = sqrt(hypot(sm[2][0] / s, sm[3][0] / s));
-    if (cnt != nullptr) {
-      cnt[0] = cnt[1];
-      cnt[1] = 0;
-    }
+  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+// Stage 2: friction velocity of each wall, u_tau = sqrt(|(<tau_x>, <tau_y>)|), stored in
+// dt[2] (bottom) and dt[3] (top); also rotates the learned closure's fallback counters:
+// cnt[0] = points that fell back in the previous evaluation (gate of the dynamic-model
+// fallback), cnt[1] = 0.
+__global__ void k_mlp_prep(GridP g, const double* part, double* dtp, int* cnt) {
+  if (threadIdx.x != 0) return;
+  double a[4] = {0, 0, 0, 0};
+  for (int b = 0; b < WM_BLOCKS; ++b)
+    for (int q = 0; q < 4; ++q) a[q] += part[b * 4 + q];
+  const double s = (double)g.sxy;
+  dtp[2] = sqrt(hypot(a[0] / s, a[1] / s));
+  dtp[3] = sqrt(hypot(a[2] / s, a[3] / s));
+  if (cnt != nullptr) {
+    cnt[0] = cnt[1];
+    cnt[1] = 0;
   }
 }
 
@@ -636,61 +692,141 @@ __device__ inline void cell_features(const GridP& g, const T* u, const T* v, con
   raw_features(s, o, yplus, sqrt(g.delta2[k]), f);
 }
 
-// Fused inference: each wave takes 64 cells, computes their features, runs the network on
-// the matrix cores and stores c |S| (nu_t = Delta^2 c |S|, c = max(0, MLP)); a cell whose
-// scaled inputs leave [-0.05, 1.05] takes the dynamic coefficient of its plane instead and
-// is counted.
+// Fused inference, z-marching over a chunk of planes per 32 x 8 tile (like the dynamic
+// model): the velocity ring of 3 planes on the tile + 1 halo sits in LDS (strain ghost rule
+// applied on wall ghost planes).  Per plane each thread forms the velocity-gradient tensor
+// of its cell (diagonal at the centre, off-diagonal terms as four-edge means, so S and O are
+// its symmetric and antisymmetric parts), the seven scaled inputs, and each wave of 64 cells
+// runs the network on the matrix cores.  c = max(0, MLP) or, for a cell whose scaled inputs
+// leave [-0.05, 1.05], the dynamic coefficient of its plane (counted); stores c |S|.
+namespace tiled {
+constexpr int TX = 32, TY = 8, NT = TX * TY;
+constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY;
+}  // namespace tiled
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_mlp_nut(GridP g, const T* __restrict__ u, const T* __restrict__ v,
                                                  const T* __restrict__ w, T* __restrict__ nut,
                                                  const float* __restrict__ P, MlpNorm nm, const double* __restrict__ cs,
-                                                 const double* __restrict__ dtp, int* __restrict__ cnt) {
+                                                 const double* __restrict__ dtp, int* __restrict__ cnt, int kc) {
   using namespace mlp;
+  using tiled::TX;
+  using tiled::TY;
+  using tiled::RX;
+  using tiled::RY;
+  using tiled::N1;
   __shared__ Weights Wt;
   __shared__ unsigned short xs[WAVES][64 * FP];
-  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  load_weights(P, Wt, tid, NT);
-  __syncthreads();
-  const int64_t ncell = (int64_t)g.nz * g.sxy;
-  const int64_t nchunk = (ncell + NT - 1) / NT;
+  __shared__ T vel[3][3][N1];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const int wave = tid / 64, lane = tid % 64;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int nz = g.nz;
+  const int kb = 1 + blockIdx.z * kc;
+  const int ke = min(nz, kb + kc - 1);
+  const bool per = g.zbc == LES_ZBC_PERIODIC;
+  const bool wm = g.zbc == LES_ZBC_WALLMODEL;
+  load_weights(P, Wt, tid, tiled::NT);
+  auto wrapi = [&](int i) { return ((i % g.nx) + g.nx) % g.nx; };
+  auto wrapj = [&](int j) { return ((j % g.ny) + g.ny) % g.ny; };
+  auto phys = [&](int q) {
+    if (!per) return q;
+    int m = (q - 1) % nz;
+    if (m < 0) m += nz;
+    return m + 1;
+  };
+  auto slot = [](int q) { return ((q % 3) + 3) % 3; };
+  auto load_plane = [&](int q) {
+    const int sl = slot(q), pq = phys(q);
+    for (int e = tid; e < N1; e += tiled::NT) {
+      const int rx = e % RX, ry = e / RX;
+      const int i = wrapi(i0 - 1 + rx), j = wrapj(j0 - 1 + ry);
+      T a, b;
+      if (wm && pq == 0) {
+        const T a1 = u[idx3(g, 1, j, i)], a2 = u[idx3(g, 2, j, i)];
+        const T b1 = v[idx3(g, 1, j, i)], b2 = v[idx3(g, 2, j, i)];
+        a = a1 - (T)g.dzc[0] * ((a2 - a1) / (T)g.dzc[1]);
+        b = b1 - (T)g.dzc[0] * ((b2 - b1) / (T)g.dzc[1]);
+      } else if (wm && pq == nz + 1) {
+        const T a1 = u[idx3(g, nz, j, i)], a0 = u[idx3(g, nz - 1, j, i)];
+        const T b1 = v[idx3(g, nz, j, i)], b0 = v[idx3(g, nz - 1, j, i)];
+        a = a1 + (T)g.dzc[nz] * ((a1 - a0) / (T)g.dzc[nz - 1]);
+        b = b1 + (T)g.dzc[nz] * ((b1 - b0) / (T)g.dzc[nz - 1]);
+      } else {
+        a = u[idx3(g, pq, j, i)];
+        b = v[idx3(g, pq, j, i)];
+      }
+      vel[sl][0][e] = a;
+      vel[sl][1][e] = b;
+      vel[sl][2][e] = w[idx3(g, pq, j, i)];
+    }
+  };
+  load_plane(kb - 1);
+  load_plane(kb);
   int flagged = 0;
-  for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-    const int64_t e = ch * NT + tid;
-    const bool ok = e < ncell;
-    int k = 1, j = 0, i = 0;
-    if (ok) {
-      k = (int)(e / g.sxy) + 1;
-      const int64_t r = e % g.sxy;
-      j = (int)(r / g.nx);
-      i = (int)(r % g.nx);
+  const int i = i0 + tx, j = j0 + ty;
+  const bool inside = i < g.nx && j < g.ny;
+  for (int k = kb; k <= ke; ++k) {
+    load_plane(k + 1);
+    __syncthreads();
+    const int pk = phys(k);
+    const int sm = slot(k - 1), s0 = slot(k), sp = slot(k + 1);
+    const int x = tx + 1, y = ty + 1;
+    auto A = [&](int c, int dz, int dy, int dx) -> T {
+      const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
+      return vel[sl][c][(y + dy) * RX + x + dx];
+    };
+    const T rdx = (T)g.rdx, rdy = (T)g.rdy, rdzf = (T)(1.0 / g.dzf[pk]);
+    const T rdzc = (T)(1.0 / g.dzc[pk]), rdzcm = (T)(1.0 / g.dzc[pk - 1]);
+    const T q4 = (T)0.25, h = (T)0.5;
+    // velocity-gradient tensor at the centre
+    const T a11 = (A(0, 0, 0, 0) - A(0, 0, 0, -1)) * rdx;
+    const T a22 = (A(1, 0, 0, 0) - A(1, 0, -1, 0)) * rdy;
+    const T a33 = (A(2, 0, 0, 0) - A(2, -1, 0, 0)) * rdzf;
+    const T dudy = q4 * (((A(0, 0, 1, 0) - A(0, 0, 0, 0)) + (A(0, 0, 1, -1) - A(0, 0, 0, -1)) +
+                          (A(0, 0, 0, 0) - A(0, 0, -1, 0)) + (A(0, 0, 0, -1) - A(0, 0, -1, -1))) * rdy);
+    const T dvdx = q4 * (((A(1, 0, 0, 1) - A(1, 0, 0, 0)) + (A(1, 0, 0, 0) - A(1, 0, 0, -1)) +
+                          (A(1, 0, -1, 1) - A(1, 0, -1, 0)) + (A(1, 0, -1, 0) - A(1, 0, -1, -1))) * rdx);
+    const T dudz = q4 * ((A(0, 1, 0, 0) - A(0, 0, 0, 0)) * rdzc + (A(0, 1, 0, -1) - A(0, 0, 0, -1)) * rdzc +
+                         (A(0, 0, 0, 0) - A(0, -1, 0, 0)) * rdzcm + (A(0, 0, 0, -1) - A(0, -1, 0, -1)) * rdzcm);
+    const T dwdx = q4 * (((A(2, 0, 0, 1) - A(2, 0, 0, 0)) + (A(2, 0, 0, 0) - A(2, 0, 0, -1)) +
+                          (A(2, -1, 0, 1) - A(2, -1, 0, 0)) + (A(2, -1, 0, 0) - A(2, -1, 0, -1))) * rdx);
+    const T dvdz = q4 * ((A(1, 1, 0, 0) - A(1, 0, 0, 0)) * rdzc + (A(1, 1, -1, 0) - A(1, 0, -1, 0)) * rdzc +
+                         (A(1, 0, 0, 0) - A(1, -1, 0, 0)) * rdzcm + (A(1, 0, -1, 0) - A(1, -1, -1, 0)) * rdzcm);
+    const T dwdy = q4 * (((A(2, 0, 1, 0) - A(2, 0, 0, 0)) + (A(2, 0, 0, 0) - A(2, 0, -1, 0)) +
+                          (A(2, -1, 1, 0) - A(2, -1, 0, 0)) + (A(2, -1, 0, 0) - A(2, -1, -1, 0))) * rdy);
+    T s6[6] = {a11, a22, a33, h * (dudy + dvdx), h * (dudz + dwdx), h * (dvdz + dwdy)};
+    const double s[6] = {(double)s6[0], (double)s6[1], (double)s6[2], (double)s6[3], (double)s6[4], (double)s6[5]};
+    const double o[3] = {0.5 * ((double)dudy - (double)dvdx), 0.5 * ((double)dudz - (double)dwdx),
+                         0.5 * ((double)dvdz - (double)dwdy)};
+    double yplus = 0.0;
+    if (!per) {
+      const double zc = g.zc[pk];
+      const bool lower = zc <= 0.5 * g.lz;
+      yplus = (lower ? zc : g.lz - zc) * (lower ? dtp[2] : dtp[3]) / g.nu;
     }
     double f[7];
-    T s6[6];
+    raw_features(s, o, yplus, sqrt(g.delta2[pk]), f);
     bool flag = false;
-    if (ok) {
-      cell_features(g, u, v, w, k, j, i, dtp, f, s6);
-      for (int a = 0; a < 7; ++a) {
-        const double xn = (f[a] - nm.lo[a]) / (nm.hi[a] - nm.lo[a]);
-        flag = flag || xn < -0.05 || xn > 1.05;
-        f[a] = xn;
-      }
+    for (int a = 0; a < 7; ++a) {
+      const double xn = (f[a] - nm.lo[a]) / (nm.hi[a] - nm.lo[a]);
+      flag = flag || xn < -0.05 || xn > 1.05;
+      f[a] = xn;
     }
-    for (int a = 0; a < FP; ++a) xs[wave][lane * FP + a] = (a < F && ok) ? f2bf((float)f[a]) : (unsigned short)0;
+    for (int a = 0; a < FP; ++a) xs[wave][lane * FP + a] = (a < F && inside) ? f2bf((float)f[a]) : (unsigned short)0;
     __syncthreads();
-    Fwd o;
-    forward_wave<false>(Wt, xs[wave], lane, o);
-    // this lane's own sample is 16 (lane/16) + lane%16 = lane (select, not an indexed
-    // load, so the activations stay in registers)
-    const int q4 = lane >> 4;
-    const float y = q4 == 0 ? o.y[0] : (q4 == 1 ? o.y[1] : (q4 == 2 ? o.y[2] : o.y[3]));
-    if (ok) {
+    Fwd out;
+    forward_wave<false>(Wt, xs[wave], lane, out);
+    const int qq = lane >> 4;
+    const float yv = qq == 0 ? out.y[0] : (qq == 1 ? out.y[1] : (qq == 2 ? out.y[2] : out.y[3]));
+    if (inside) {
       const T smag = strain_mag(s6);
-      double c = y > 0.0f ? (double)y : 0.0;
+      double c = yv > 0.0f ? (double)yv : 0.0;
       if (flag) {
-        c = cs[k - 1];
+        c = cs[pk - 1];
         ++flagged;
       }
-      store_nut(g, nut, k, j, i, (T)c * smag);
+      store_nut(g, nut, pk, j, i, (T)c * smag);
     }
     __syncthreads();
   }
@@ -745,9 +881,11 @@ void launch_eddy_viscosity(Ctx& c) {
   if (model == LES_SGS_DSM || model == LES_SGS_MLP) {
     const bool learned = model == LES_SGS_MLP && c.mlp_params != nullptr;
     const int* gate = learned ? c.mlp_cnt : nullptr;
-    if (learned)
-      LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep<T>, dim3(1), dim3(256), 0, g, (const T*)c.u, (const T*)c.v, c.t.tau,
-                 c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.dt, c.mlp_cnt);
+    if (learned) {
+      LES_LAUNCH(c, "wall_mean", 0, k_wall_mean_partial<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
+                 (const T*)c.v, c.t.tau, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
+      LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, c.t.red, c.t.dt, c.mlp_cnt);
+    }
     const int kc = c.dsm_kc;
     dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + fused::TY - 1) / fused::TY, (g.nz + kc - 1) / kc);
     LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, fused::TY), 0, g,
@@ -761,19 +899,31 @@ void launch_eddy_viscosity(Ctx& c) {
         nm.lo[a] = c.mlp_lo[a];
         nm.hi[a] = c.mlp_hi[a];
       }
-      const int64_t nchunk = ((int64_t)g.nz * g.sxy + mlp::NT - 1) / mlp::NT;
-      const unsigned nb = (unsigned)std::min<int64_t>(nchunk, 2048);
-      LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), k_mlp_nut<T>, dim3(nb), dim3(mlp::NT), 0, g, (const T*)c.u,
-                 (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm, c.t.cs, c.t.dt, c.mlp_cnt);
+      dim3 tgrid((g.nx + tiled::TX - 1) / tiled::TX, (g.ny + tiled::TY - 1) / tiled::TY, (g.nz + kc - 1) / kc);
+      LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), k_mlp_nut<T>, tgrid, dim3(tiled::TX, tiled::TY), 0, g,
+                 (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm, c.t.cs, c.t.dt, c.mlp_cnt,
+                 kc);
     }
   }
 }
 
 template <typename T>
+void batch_eddy_viscosity(hipStream_t st, const BatchMap& m, const int* totals, int any_dsm, int any_smag) {
+  if (any_smag) hipLaunchKernelGGL(kb_strain_mag<T>, dim3(totals[BK_POINT]), dim3(32, 8), 0, st, m);
+  if (any_dsm) {
+    hipLaunchKernelGGL(kb_dsm_fused<T>, dim3(totals[BK_DSM]), dim3(fused::TX, fused::TY), 0, st, m);
+    hipLaunchKernelGGL(kb_dsm_reduce, dim3(totals[BK_DSMRED]), dim3(256), 0, st, m);
+  }
+}
+template void batch_eddy_viscosity<float>(hipStream_t, const BatchMap&, const int*, int, int);
+template void batch_eddy_viscosity<double>(hipStream_t, const BatchMap&, const int*, int, int);
+
+template <typename T>
 void launch_mlp_sample(Ctx& c, uint64_t seed, int64_t n, float* x, float* y) {
   const GridP& g = c.g;
-  LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep<T>, dim3(1), dim3(256), 0, g, (const T*)c.u, (const T*)c.v, c.t.tau,
-             c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.dt, (int*)nullptr);
+  LES_LAUNCH(c, "wall_mean", 0, k_wall_mean_partial<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
+             (const T*)c.v, c.t.tau, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
+  LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, c.t.red, c.t.dt, (int*)nullptr);
   LES_LAUNCH(c, "mlp_sample", 0, k_mlp_sample<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g, (const T*)c.u,
              (const T*)c.v, (const T*)c.w, c.t.cs, c.t.dt, seed, n, x, y);
 }

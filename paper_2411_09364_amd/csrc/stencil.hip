@@ -33,7 +33,7 @@ __device__ inline T nut_at(const T* nut, const double* coef, const GridP& g, int
 // Helmholtz right-hand side u** - gamma nu dt/2 L_zz u^k where
 // u** = u + dt (alpha R^k + beta R^{k-1} - gamma G p) + gamma nu dt L_zz u^k.
 template <typename T, bool IMPLICIT>
-__global__ void __launch_bounds__(256) k_predictor(GridP g, const T* __restrict__ u, const T* __restrict__ v,
+__device__ __forceinline__ void predictor_body(dim3 bid, GridP g, const T* __restrict__ u, const T* __restrict__ v,
                                                    const T* __restrict__ w, const T* __restrict__ p,
                                                    const T* __restrict__ nut, const double* __restrict__ coef,
                                                    T* __restrict__ ru, T* __restrict__ rv, T* __restrict__ rw,
@@ -41,18 +41,18 @@ __global__ void __launch_bounds__(256) k_predictor(GridP g, const T* __restrict_
                                                    const double* __restrict__ dtp, double alpha, double beta,
                                                    double gamma, int use_rprev, int write_r, double* hfac,
                                                    int wallmodel) {
-  if (IMPLICIT && blockIdx.z == 0) {
+  if (IMPLICIT && bid.z == 0) {
     // the first z slice of blocks is scheduled first: one block computes the shared CN
     // factorisation of this substep while the others run the stencil
     __shared__ double fz[2][kMaxNz + 2];
-    if (blockIdx.x == 0 && blockIdx.y == 0)
+    if (bid.x == 0 && bid.y == 0)
       helmholtz_factor_body(g, hfac, dtp, gamma, wallmodel, fz[0], fz[1], threadIdx.y * blockDim.x + threadIdx.x,
                             blockDim.x * blockDim.y);
     return;
   }
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = IMPLICIT ? blockIdx.z : blockIdx.z + 1;
+  const int i = bid.x * blockDim.x + threadIdx.x;
+  const int j = bid.y * blockDim.y + threadIdx.y;
+  const int k = IMPLICIT ? bid.z : bid.z + 1;
   if (i >= g.nx || j >= g.ny) return;
   const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx);
   const int jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
@@ -191,6 +191,28 @@ __global__ void __launch_bounds__(256) k_predictor(GridP g, const T* __restrict_
     vs[c0] = v0 + dt * iv;
     ws[c0] = wall_face ? (T)0 : w0 + dt * iw;
   }
+}
+
+template <typename T, bool IMPLICIT>
+__global__ void __launch_bounds__(256) k_predictor(GridP g, const T* u, const T* v, const T* w, const T* p,
+                                                   const T* nut, const double* coef, T* ru, T* rv, T* rw, T* us,
+                                                   T* vs, T* ws, const double* dtp, double alpha, double beta,
+                                                   double gamma, int use_rprev, int write_r, double* hfac,
+                                                   int wallmodel) {
+  predictor_body<T, IMPLICIT>(blockIdx, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta, gamma,
+                              use_rprev, write_r, hfac, wallmodel);
+}
+
+// Batched predictor (explicit viscous terms): one launch over all boxes of a batch.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_predictor(BatchMap m, double alpha, double beta, double gamma,
+                                                    int use_rprev, int write_r) {
+  int box;
+  const dim3 bid = batch_bid(m, BK_POINT, blockIdx.x, box);
+  const BoxDesc& d = m.desc[box];
+  predictor_body<T, false>(bid, d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w, (const T*)d.p, (const T*)d.nut,
+                           d.coef, (T*)d.ru, (T*)d.rv, (T*)d.rw, (T*)d.us, (T*)d.vs, (T*)d.wsf, d.dt, alpha, beta,
+                           gamma, use_rprev, write_r, nullptr, 0);
 }
 
 template <typename T>
@@ -390,14 +412,14 @@ void launch_bc_fill(Ctx& c, T* u, T* v, T* w, T* p) {
 // then the non-wall-model ghost planes.  phi ghosts follow the Poisson boundary
 // condition (zero flux at walls, periodic copy otherwise) and are read on the fly.
 template <typename T>
-__global__ void __launch_bounds__(256) k_correct(GridP g, const T* __restrict__ us, const T* __restrict__ vs,
+__device__ __forceinline__ void correct_body(dim3 bid, GridP g, const T* __restrict__ us, const T* __restrict__ vs,
                                                  const T* __restrict__ ws, const T* __restrict__ phi, T* __restrict__ u,
                                                  T* __restrict__ v, T* __restrict__ w, T* __restrict__ p,
                                                  const double* __restrict__ dtp, const double* __restrict__ qprof,
                                                  double gamma, int implicit) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z + 1;
+  const int i = bid.x * blockDim.x + threadIdx.x;
+  const int j = bid.y * blockDim.y + threadIdx.y;
+  const int k = bid.z + 1;
   if (i >= g.nx || j >= g.ny) return;
   const int n = g.nz;
   const bool per = g.zbc == LES_ZBC_PERIODIC;
@@ -435,6 +457,22 @@ __global__ void __launch_bounds__(256) k_correct(GridP g, const T* __restrict__ 
     if (k == 1) { u[c2] = -un; v[c2] = -vn; w[c2] = (T)0; p[c2] = pn; }
     if (k == n) { u[(n + 1) * s + c2] = -un; v[(n + 1) * s + c2] = -vn; w[(n + 1) * s + c2] = (T)0; p[(n + 1) * s + c2] = pn; }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_correct(GridP g, const T* us, const T* vs, const T* ws, const T* phi, T* u,
+                                                 T* v, T* w, T* p, const double* dtp, const double* qprof,
+                                                 double gamma, int implicit) {
+  correct_body<T>(blockIdx, g, us, vs, ws, phi, u, v, w, p, dtp, qprof, gamma, implicit);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_correct(BatchMap m, double gamma) {
+  int box;
+  const dim3 bid = batch_bid(m, BK_POINT, blockIdx.x, box);
+  const BoxDesc& d = m.desc[box];
+  correct_body<T>(bid, d.g, (const T*)d.us, (const T*)d.vs, (const T*)d.wsf, (const T*)d.phi, (T*)d.u, (T*)d.v,
+                  (T*)d.w, (T*)d.p, d.dt, nullptr, gamma, 0);
 }
 
 template <typename T>
@@ -532,12 +570,12 @@ void launch_wallmodel(Ctx& c) {
 // Block maxima of |u|/dx + |v|/dy + |w|/dzf and of nu_t, reduced in a fixed order by a
 // single block which then writes dt (R22 reading of the paper's time-step rule).
 template <typename T>
-__global__ void __launch_bounds__(256) k_cfl_partial(GridP g, const T* u, const T* v, const T* w, const T* nut,
-                                                     const double* coef, double* part) {
+__device__ __forceinline__ void cfl_partial_body(int b, int nb, GridP g, const T* u, const T* v, const T* w,
+                                                 const T* nut, const double* coef, double* part) {
   __shared__ double sm[2][256];
   double mc = 0.0, mn = 0.0;
   const int64_t total = (int64_t)g.nz * g.sxy;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = b * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)nb * blockDim.x) {
     const int k = (int)(e / g.sxy) + 1;
     const int64_t c = (int64_t)k * g.sxy + e % g.sxy;
     const double a = fabs((double)u[c]) * g.rdx + fabs((double)v[c]) * g.rdy + fabs((double)w[c]) / g.dzf[k];
@@ -555,13 +593,19 @@ __global__ void __launch_bounds__(256) k_cfl_partial(GridP g, const T* u, const 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = sm[0][0];
-    part[2 * blockIdx.x + 1] = sm[1][0];
+    part[2 * b] = sm[0][0];
+    part[2 * b + 1] = sm[1][0];
   }
 }
 
-__global__ void __launch_bounds__(256) k_cfl_final(const double* part, int nblk, double* dtp, double cfl, double nu,
-                                                   double sinv) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_cfl_partial(GridP g, const T* u, const T* v, const T* w, const T* nut,
+                                                     const double* coef, double* part) {
+  cfl_partial_body<T>(blockIdx.x, gridDim.x, g, u, v, w, nut, coef, part);
+}
+
+__device__ __forceinline__ void cfl_final_body(const double* part, int nblk, double* dtp, double cfl, double nu,
+                                               double sinv) {
   __shared__ double sm[2][256];
   double mc = 0.0, mn = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 256) {
@@ -583,6 +627,35 @@ __global__ void __launch_bounds__(256) k_cfl_final(const double* part, int nblk,
     const double dtc = sm[0][0] > 0.0 ? cfl / sm[0][0] : INFINITY;
     dtp[0] = fmin(dtc, dtv);
   }
+}
+
+__global__ void __launch_bounds__(256) k_cfl_final(const double* part, int nblk, double* dtp, double cfl, double nu,
+                                                   double sinv) {
+  cfl_final_body(part, nblk, dtp, cfl, nu, sinv);
+}
+
+// Batched time step: BK_CFL blocks per box write partials into the box's reduction area,
+// then one block per box forms that box's dt (explicit viscous terms in all directions).
+template <typename T>
+__global__ void __launch_bounds__(256) kb_cfl_partial(BatchMap m) {
+  int box;
+  const dim3 bid = batch_bid(m, BK_CFL, blockIdx.x, box);
+  const BoxDesc& d = m.desc[box];
+  cfl_partial_body<T>(bid.x, d.gdim[BK_CFL][0], d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w, (const T*)d.nut,
+                      d.coef, d.red);
+}
+
+__global__ void __launch_bounds__(256) kb_cfl_final(BatchMap m, double cfl) {
+  const BoxDesc& d = m.desc[blockIdx.x];
+  double dmin = 1e300;
+  for (int k = 1; k <= d.g.nz; ++k) dmin = fmin(dmin, d.g.dzf[k]);
+  const double sinv = d.g.rdx * d.g.rdx + d.g.rdy * d.g.rdy + 1.0 / (dmin * dmin);
+  cfl_final_body(d.red, d.gdim[BK_CFL][0], d.dt, cfl, d.g.nu, sinv);
+}
+
+// Batched dt from the host: dt for every box.
+__global__ void kb_set_dt(BatchMap m, double dt) {
+  if (threadIdx.x == 0) m.desc[blockIdx.x].dt[0] = dt;
 }
 
 template <typename T>
@@ -654,6 +727,34 @@ void launch_diag(Ctx& c, double* out_dev) {
   LES_LAUNCH(c, "diag", 0, k_diag<T>, dim3(1), dim3(256), 0, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
                      (const T*)c.p, c.cfg.zbc == LES_ZBC_WALLMODEL ? c.t.tau : nullptr, out_dev);
 }
+
+// ============================================================================ batch launchers
+template <typename T>
+void batch_predictor(hipStream_t st, const BatchMap& m, int total, int stage) {
+  static const double A[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+  static const double B[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+  hipLaunchKernelGGL(kb_predictor<T>, dim3(total), dim3(32, 8), 0, st, m, A[stage], B[stage], A[stage] + B[stage],
+                     stage > 0 ? 1 : 0, stage < 2 ? 1 : 0);
+}
+template <typename T>
+void batch_correct(hipStream_t st, const BatchMap& m, int total, int stage) {
+  static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
+  hipLaunchKernelGGL(kb_correct<T>, dim3(total), dim3(32, 8), 0, st, m, G[stage]);
+}
+template <typename T>
+void batch_dt(hipStream_t st, const BatchMap& m, int total_cfl, int nbox, double cfl) {
+  hipLaunchKernelGGL(kb_cfl_partial<T>, dim3(total_cfl), dim3(256), 0, st, m);
+  hipLaunchKernelGGL(kb_cfl_final, dim3(nbox), dim3(256), 0, st, m, cfl);
+}
+void batch_set_dt(hipStream_t st, const BatchMap& m, int nbox, double dt) {
+  hipLaunchKernelGGL(kb_set_dt, dim3(nbox), dim3(64), 0, st, m, dt);
+}
+template void batch_predictor<float>(hipStream_t, const BatchMap&, int, int);
+template void batch_predictor<double>(hipStream_t, const BatchMap&, int, int);
+template void batch_correct<float>(hipStream_t, const BatchMap&, int, int);
+template void batch_correct<double>(hipStream_t, const BatchMap&, int, int);
+template void batch_dt<float>(hipStream_t, const BatchMap&, int, int, double);
+template void batch_dt<double>(hipStream_t, const BatchMap&, int, int, double);
 
 // ============================================================================ instantiations
 #define INST(T)                                                  \

@@ -71,6 +71,19 @@ def _load():
         "les_mlp_train_step": [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp, i32, ctypes.c_float, vp],
         "les_free": [vp],
         "les_timing": [vp, i32],
+        "les_batch_init": [ctypes.POINTER(LesConfig), i32, vp, ctypes.POINTER(vp)],
+        "les_batch_layout": [vp, i32, ctypes.POINTER(LesLayout)],
+        "les_batch_offset": [vp, i32, i32, ctypes.POINTER(ctypes.c_int64)],
+        "les_batch_bind": [vp, i32, vp],
+        "les_batch_nut": [vp],
+        "les_batch_dt": [vp, dbl],
+        "les_batch_set_dt": [vp, dbl],
+        "les_batch_substep": [vp, i32],
+        "les_batch_step": [vp, dbl, i32],
+        "les_batch_autotune": [vp, i32, ctypes.c_char_p, ctypes.c_size_t],
+        "les_batch_read": [vp, i32, i32, vp],
+        "les_batch_diag": [vp, i32, ctypes.POINTER(LesDiag)],
+        "les_batch_free": [vp],
         "les_timing_report": [vp, ctypes.c_char_p, ctypes.c_size_t],
     }
     for name, args in sig.items():
@@ -79,6 +92,8 @@ def _load():
         f.restype = ctypes.c_int
     lib.les_mlp_workspace_bytes.argtypes = [ctypes.c_int64]
     lib.les_mlp_workspace_bytes.restype = ctypes.c_int64
+    lib.les_batch_last_error.argtypes = [vp]
+    lib.les_batch_last_error.restype = ctypes.c_char_p
     lib.les_strerror.argtypes = [ctypes.c_int]
     lib.les_strerror.restype = ctypes.c_char_p
     lib.les_last_error.argtypes = [vp]
@@ -95,7 +110,10 @@ def exported_symbols():
             "les_step", "les_poisson", "les_read", "les_diag", "les_mlp_bind", "les_mlp_sample",
             "les_mlp_normalize", "les_mlp_forward", "les_mlp_workspace_bytes", "les_mlp_grad",
             "les_mlp_adam", "les_mlp_train_step", "les_free", "les_strerror", "les_last_error",
-            "les_timing", "les_timing_report"]
+            "les_timing", "les_timing_report", "les_batch_init", "les_batch_layout", "les_batch_offset",
+            "les_batch_bind", "les_batch_nut", "les_batch_dt", "les_batch_set_dt", "les_batch_substep",
+            "les_batch_step", "les_batch_autotune", "les_batch_read", "les_batch_diag",
+            "les_batch_last_error", "les_batch_free"]
 
 
 def make_config(nx, ny, nz, lx, ly, lz, zbc=ZBC_PERIODIC, beta=0.0, nu=1e-3, sgs=SGS_NONE, cs=0.17,
@@ -395,6 +413,128 @@ class Solver:
             self.synchronize()
             les_free(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- batched ensembles
+def _bcheck(b, st, what):
+    if st != LES_OK:
+        msg = LIB.les_batch_last_error(b).decode() if b else ""
+        raise LesError(st, f"{what}: {msg or LIB.les_strerror(st).decode()}")
+
+
+class Batch:
+    """Many periodic boxes advanced together (one launch per kernel kind for all boxes).
+    Fields of box b are views into the concatenated torch buffers."""
+
+    def __init__(self, cfgs, device="cuda"):
+        import torch
+        self.torch = torch
+        self.cfgs = list(cfgs)
+        self.stream = torch.cuda.Stream(device=device)
+        arr = (LesConfig * len(self.cfgs))(*self.cfgs)
+        h = ctypes.c_void_p()
+        st = LIB.les_batch_init(arr, len(self.cfgs), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != LES_OK:
+            raise LesError(st, f"les_batch_init: {LIB.les_strerror(st).decode()}")
+        self.h = h
+        lay = LesLayout()
+        _bcheck(h, LIB.les_batch_layout(h, FIELD_U, ctypes.byref(lay)), "les_batch_layout")
+        self.dtype = torch.float64 if lay.elem_bytes == 8 else torch.float32
+        fbytes = lay.bytes
+        _bcheck(h, LIB.les_batch_layout(h, FIELD_WORKSPACE, ctypes.byref(lay)), "les_batch_layout")
+        wbytes = lay.bytes
+        esz = 8 if self.dtype == torch.float64 else 4
+        with torch.cuda.stream(self.stream):
+            self.buf = [torch.zeros(fbytes // esz + 64, dtype=self.dtype, device=device) for _ in range(4)]
+            self.workspace = torch.empty(wbytes + 256, dtype=torch.uint8, device=device)
+        self.stream.synchronize()
+        self.ptrs = []
+        for q in range(4):
+            base = self.buf[q].data_ptr()
+            off = (-base) % 256
+            self.ptrs.append(base + off)
+            _bcheck(h, LIB.les_batch_bind(h, q, ctypes.c_void_p(base + off)), "les_batch_bind")
+        wb = self.workspace.data_ptr()
+        _bcheck(h, LIB.les_batch_bind(h, FIELD_WORKSPACE, ctypes.c_void_p(wb + ((-wb) % 256))), "les_batch_bind")
+        self.offsets = []
+        for b in range(len(self.cfgs)):
+            o = ctypes.c_int64()
+            _bcheck(h, LIB.les_batch_offset(h, b, FIELD_U, ctypes.byref(o)), "les_batch_offset")
+            self.offsets.append(o.value)
+
+    def field(self, q, b):
+        """Torch view of field q (0 u, 1 v, 2 w, 3 p) of box b."""
+        c = self.cfgs[b]
+        n = (c.nz + 2) * c.ny * c.nx
+        esz = 8 if self.dtype == self.torch.float64 else 4
+        start = (self.ptrs[q] - self.buf[q].data_ptr() + self.offsets[b]) // esz
+        return self.buf[q][start:start + n].view(c.nz + 2, c.ny, c.nx)
+
+    def set_state(self, b, u, v, w, p=None):
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            for q, src in enumerate((u, v, w, p)):
+                dst = self.field(q, b)
+                if src is None:
+                    dst.zero_()
+                else:
+                    dst.copy_(torch.as_tensor(src, dtype=self.dtype))
+        self.stream.synchronize()
+
+    def fields(self, b):
+        self.stream.synchronize()
+        return tuple(self.field(q, b).double().cpu().numpy() for q in range(4))
+
+    def nut(self):
+        _bcheck(self.h, LIB.les_batch_nut(self.h), "les_batch_nut")
+
+    def set_dt(self, dt):
+        _bcheck(self.h, LIB.les_batch_set_dt(self.h, dt), "les_batch_set_dt")
+
+    def dt(self, cfl):
+        _bcheck(self.h, LIB.les_batch_dt(self.h, cfl), "les_batch_dt")
+
+    def substep(self, stage):
+        _bcheck(self.h, LIB.les_batch_substep(self.h, stage), "les_batch_substep")
+
+    def step(self, cfl=0.5, use_graph=False):
+        _bcheck(self.h, LIB.les_batch_step(self.h, cfl, 1 if use_graph else 0), "les_batch_step")
+
+    def autotune(self, substeps=6):
+        import json
+        buf = ctypes.create_string_buffer(4096)
+        _bcheck(self.h, LIB.les_batch_autotune(self.h, substeps, buf, len(buf)), "les_batch_autotune")
+        return json.loads(buf.value.decode())
+
+    def eddy_viscosity(self, b):
+        torch = self.torch
+        c = self.cfgs[b]
+        out = torch.empty((c.nz + 2, c.ny, c.nx), dtype=self.dtype, device=self.buf[0].device)
+        _bcheck(self.h, LIB.les_batch_read(self.h, b, FIELD_NUT, ctypes.c_void_p(out.data_ptr())), "les_batch_read")
+        self.stream.synchronize()
+        return out.double().cpu().numpy()
+
+    def box_dt(self, b):
+        d = LesDiag()
+        st = LIB.les_batch_diag(self.h, b, ctypes.byref(d))
+        if st not in (LES_OK, LES_ENONFINITE):
+            _bcheck(self.h, st, "les_batch_diag")
+        return d
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if self.h:
+            self.stream.synchronize()
+            LIB.les_batch_free(self.h)
+            self.h = None
 
     def __del__(self):
         try:
