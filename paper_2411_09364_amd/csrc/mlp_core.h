@@ -20,9 +20,14 @@ __device__ inline unsigned short f2bf(float f) {
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (unsigned short)(u >> 16);
 }
-__device__ inline float silu(float z) { return z / (1.0f + expf(-z)); }
+// Logistic function from the hardware base-2 exponential and reciprocal (about 1 ulp each):
+// sigma(z) = 1 / (1 + 2^(-z log2 e)); saturates to 0 and 1 without special cases.
+__device__ inline float sigmoid(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
+__device__ inline float silu(float z) { return z * sigmoid(z); }
 __device__ inline float dsilu(float z) {
-  const float s = 1.0f / (1.0f + expf(-z));
+  const float s = sigmoid(z);
   return s * (1.0f + z * (1.0f - s));
 }
 __device__ inline f4 mfma(s4 a, s4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
@@ -104,7 +109,10 @@ __device__ void forward_wave(const Weights& W, const unsigned short* xb, int lan
       o.h1b[a][sb] = pack4(h[0], h[1], h[2], h[3]);
     }
   }
-  // layer 2: Z2^T(16a.., 16sb..) = sum_kb W2 tile (a, kb)  x  H1^T tile (kb, sb)
+  // layer 2: Z2^T(16a.., 16sb..) = sum_kb W2 tile (a, kb)  x  H1^T tile (kb, sb); layer 3
+  // (float32, y = W3 . h2 + b3) accumulated per lane as the tiles come, then reduced over the
+  // four lane groups
+  float py[4] = {0.f, 0.f, 0.f, 0.f};
   for (int a = 0; a < 4; ++a) {
     for (int sb = 0; sb < 4; ++sb) {
       f4 z = zero;
@@ -113,16 +121,16 @@ __device__ void forward_wave(const Weights& W, const unsigned short* xb, int lan
       for (int i = 0; i < 4; ++i) {
         z[i] += W.b2[16 * a + g4 + i];
         h[i] = silu(z[i]);
+        py[sb] += W.w3[16 * a + g4 + i] * h[i];
       }
-      if (KEEP) o.z2[a][sb] = z;
-      o.h2[a][sb] = h;
+      if (KEEP) {
+        o.z2[a][sb] = z;
+        o.h2[a][sb] = h;
+      }
     }
   }
-  // layer 3 (float32): y = W3 . h2 + b3, reduced over the four lane groups
   for (int sb = 0; sb < 4; ++sb) {
-    float p = 0.f;
-    for (int a = 0; a < 4; ++a)
-      for (int i = 0; i < 4; ++i) p += W.w3[16 * a + g4 + i] * o.h2[a][sb][i];
+    float p = py[sb];
     p += __shfl_xor(p, 16, 64);
     p += __shfl_xor(p, 32, 64);
     o.y[sb] = p + W.b3;

@@ -265,11 +265,13 @@ __device__ inline int ring3(int q) {
 
 template <typename T>
 __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP g, const T* __restrict__ u,
-                                               const T* __restrict__ v,
-                                                   const T* __restrict__ w, T* __restrict__ nut,
-                                                   double* __restrict__ part, int kc, const int* __restrict__ gate) {
+                                               const T* __restrict__ v, const T* __restrict__ w,
+                                               T* __restrict__ nut, double* __restrict__ part, int kc,
+                                               const int* __restrict__ gate) {
   using namespace fused;
   if (gate != nullptr && gate[0] == 0) return;   // learned closure: no point fell back
+  constexpr int NL = (N2 + NT - 1) / NT;          // halo-2 points per thread (loads)
+  constexpr int NH = (N1 + NT - 1) / NT;          // halo-1 points per thread (stage)
   __shared__ T vel[3][3][N2];   // [slot][component][R2]
   __shared__ T qb[9][N1];       // centre quantities of the current stage plane
   __shared__ T ut[3][3][N1];    // filtered velocity [slot][component][R1]
@@ -285,39 +287,98 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   const int tile = bid.y * gdx + bid.x;
   const T rdx = (T)g.rdx, rdy = (T)g.rdy;
   const T W0 = (T)0.25, W1 = (T)0.5;
-  auto wrapi = [&](int i) { return ((i % g.nx) + g.nx) % g.nx; };   // tiles may exceed the grid
-  auto wrapj = [&](int j) { return ((j % g.ny) + g.ny) % g.ny; };
+  const int64_t sxy = g.sxy;
   auto phys = [&](int q) {  // logical plane -> stored plane (periodic wrap of interior planes)
     if (!per) return q;
     int m = (q - 1) % nz;
     if (m < 0) m += nz;
     return m + 1;
   };
-  // ---- load velocity plane q into its slot (strain ghost rule on wall ghost planes)
-  auto load_plane = [&](int q) {
-    const int sl = ring3<T>(q);
+  // in-plane offsets of the thread's halo-2 load points (tiles may exceed the grid: wrap)
+  int lofs[NL];
+  for (int r = 0; r < NL; ++r) {
+    const int e = tid + r * NT;
+    const int rx = e % RX2, ry = e / RX2;
+    int i = (i0 - 2 + rx) % g.nx, j = (j0 - 2 + ry) % g.ny;
+    if (i < 0) i += g.nx;
+    if (j < 0) j += g.ny;
+    lofs[r] = e < N2 ? j * g.nx + i : 0;
+  }
+  // velocity of one plane held in registers between its fetch and its commit to LDS, so that
+  // the global loads of plane p + 2 overlap the work on plane p (strain ghost rule applied at
+  // fetch on wall ghost planes)
+  T ra[NL], rb[NL], rc[NL];
+  auto fetch = [&](int q) {
     const int pq = phys(q);
-    for (int e = tid; e < N2; e += NT) {
-      const int rx = e % RX2, ry = e / RX2;
-      const int i = wrapi(i0 - 2 + rx), j = wrapj(j0 - 2 + ry);
-      T a, b;
-      if (wm && pq == 0) {
-        const T a1 = u[idx3(g, 1, j, i)], a2 = u[idx3(g, 2, j, i)];
-        const T b1 = v[idx3(g, 1, j, i)], b2 = v[idx3(g, 2, j, i)];
-        a = a1 - (T)g.dzc[0] * ((a2 - a1) / (T)g.dzc[1]);
-        b = b1 - (T)g.dzc[0] * ((b2 - b1) / (T)g.dzc[1]);
-      } else if (wm && pq == nz + 1) {
-        const T a1 = u[idx3(g, nz, j, i)], a0 = u[idx3(g, nz - 1, j, i)];
-        const T b1 = v[idx3(g, nz, j, i)], b0 = v[idx3(g, nz - 1, j, i)];
-        a = a1 + (T)g.dzc[nz] * ((a1 - a0) / (T)g.dzc[nz - 1]);
-        b = b1 + (T)g.dzc[nz] * ((b1 - b0) / (T)g.dzc[nz - 1]);
-      } else {
-        a = u[idx3(g, pq, j, i)];
-        b = v[idx3(g, pq, j, i)];
+    const bool gb = wm && pq == 0, gt = wm && pq == nz + 1;
+    const int64_t bw = (int64_t)pq * sxy;
+    for (int r = 0; r < NL; ++r) {
+      if (tid + r * NT < N2) {
+        rc[r] = w[bw + lofs[r]];
+        if (gb) {
+          const T a1 = u[sxy + lofs[r]], a2 = u[2 * sxy + lofs[r]];
+          const T b1 = v[sxy + lofs[r]], b2 = v[2 * sxy + lofs[r]];
+          ra[r] = a1 - (T)g.dzc[0] * ((a2 - a1) / (T)g.dzc[1]);
+          rb[r] = b1 - (T)g.dzc[0] * ((b2 - b1) / (T)g.dzc[1]);
+        } else if (gt) {
+          const T a1 = u[nz * sxy + lofs[r]], a0 = u[(nz - 1) * sxy + lofs[r]];
+          const T b1 = v[nz * sxy + lofs[r]], b0 = v[(nz - 1) * sxy + lofs[r]];
+          ra[r] = a1 + (T)g.dzc[nz] * ((a1 - a0) / (T)g.dzc[nz - 1]);
+          rb[r] = b1 + (T)g.dzc[nz] * ((b1 - b0) / (T)g.dzc[nz - 1]);
+        } else {
+          ra[r] = u[bw + lofs[r]];
+          rb[r] = v[bw + lofs[r]];
+        }
       }
-      vel[sl][0][e] = a;
-      vel[sl][1][e] = b;
-      vel[sl][2][e] = w[idx3(g, pq, j, i)];
+    }
+  };
+  auto commit = [&](int q) {
+    const int sl = ring3<T>(q);
+    for (int r = 0; r < NL; ++r) {
+      const int e = tid + r * NT;
+      if (e < N2) {
+        vel[sl][0][e] = ra[r];
+        vel[sl][1][e] = rb[r];
+        vel[sl][2][e] = rc[r];
+      }
+    }
+  };
+  // the thread's halo-1 points (R2 coordinates) and the x-y test filter of the velocity there:
+  // a register ring over planes p-1, p, p+1 (each plane filtered once)
+  int hx[NH], hy[NH];
+  for (int r = 0; r < NH; ++r) {
+    const int e = tid + r * NT;
+    hx[r] = e % RX1 + 1;
+    hy[r] = e / RX1 + 1;
+  }
+  // z pass by partial sums: G1 holds plane p's sum without its upper neighbour, G2 plane
+  // p + 1's lower-neighbour term; z weights per plane (lower, centre, upper) are (0, 1, 0)
+  // for u, v on the first off-wall layers and 0 for w on the top wall face
+  T G1[NH][3], G2[NH][3];
+  auto zw = [&](int q, int c, int which) -> T {
+    if (!per && c == 2 && q == nz) return (T)0;
+    if (!per && c < 2 && (q == 1 || q == nz)) return which == 1 ? (T)1 : (T)0;
+    return which == 1 ? W1 : W0;
+  };
+  // x-y filter of velocity plane q at the thread's halo-1 points, folded into the z sums;
+  // completes the filtered velocity of plane q - 1 (written to the ut ring when put != 0)
+  auto filter_xy = [&](int q, bool put) {
+    const int sl = ring3<T>(q), so = ring3<T>(q - 1);
+    for (int r = 0; r < NH; ++r) {
+      const int e = tid + r * NT;
+      if (e < N1) {
+        for (int c = 0; c < 3; ++c) {
+          T pl = (T)0;
+          for (int dy = -1; dy <= 1; ++dy) {
+            const T* rr = &vel[sl][c][(hy[r] + dy) * RX2 + hx[r]];
+            const T row = W0 * rr[-1] + W1 * rr[0] + W0 * rr[1];
+            pl = pl + (dy == 0 ? W1 : W0) * row;
+          }
+          if (put) ut[so][c][e] = G1[r][c] + zw(q - 1, c, 2) * pl;
+          G1[r][c] = G2[r][c] + zw(q, c, 1) * pl;
+          G2[r][c] = zw(q + 1, c, 0) * pl;
+        }
+      }
     }
   };
   // register ring of x-y filtered quantities: A = plane k-1, B = k, C = k+1
@@ -327,11 +388,10 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     const int pq = phys(p);
     const int sm = ring3<T>(p - 1), s0 = ring3<T>(p), sp = ring3<T>(p + 1);
     const T rdzf = (T)(1.0 / g.dzf[pq]), rdzc = (T)(1.0 / g.dzc[pq]), rdzcm = (T)(1.0 / g.dzc[pq - 1]);
-    const bool zid = !per && (p == 1 || p == nz);   // z pass of the filter is the identity
-    const bool wtop = !per && p == nz;               // w face on top of plane nz is the wall
+    const bool own = p >= kb && p <= ke;
+#pragma unroll 1
     for (int e = tid; e < N1; e += NT) {
-      const int rx = e % RX1, ry = e / RX1;
-      const int x = rx + 1, y = ry + 1;  // in R2
+      const int x = e % RX1 + 1, y = e / RX1 + 1;
       auto A = [&](int c, int dz, int dy, int dx) -> T {
         const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
         return vel[sl][c][(y + dy) * RX2 + x + dx];
@@ -344,50 +404,24 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       qb[1][e] = (T)0.5 * (A(1, 0, 0, 0) + A(1, 0, -1, 0));
       qb[2][e] = (T)0.5 * (A(2, 0, 0, 0) + A(2, -1, 0, 0));
       for (int a = 0; a < 6; ++a) qb[3 + a][e] = sm_ * s[a];
-      if (rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && p >= kb && p <= ke) {
-        const int i = i0 + rx - 1, j = j0 + ry - 1;
+      if (own && x >= 2 && x <= TX + 1 && y >= 2 && y <= TY + 1) {
+        const int i = i0 + x - 2, j = j0 + y - 2;
         if (i < g.nx && j < g.ny) store_nut(g, nut, p, j, i, sm_);
-      }
-      // test-filtered staggered velocity at plane p
-      for (int c = 0; c < 3; ++c) {
-        T acc = (T)0;
-        if (c == 2 && wtop) {
-          acc = (T)0;
-        } else {
-          for (int dz = -1; dz <= 1; ++dz) {
-            T wz = dz == 0 ? W1 : W0;
-            if (c < 2 && zid) wz = dz == 0 ? (T)1 : (T)0;
-            if (wz == (T)0) continue;
-            const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
-            T pl = (T)0;
-            for (int dy = -1; dy <= 1; ++dy) {
-              const T* r = &vel[sl][c][(y + dy) * RX2 + x];
-              const T row = W0 * r[-1] + W1 * r[0] + W0 * r[1];
-              pl = pl + (dy == 0 ? W1 : W0) * row;
-            }
-            acc = acc + wz * pl;
-          }
-        }
-        ut[s0][c][e] = acc;
       }
     }
     __syncthreads();
     // x-y filter of the 15 quantities at the thread's own cell (R1 coords tx+1, ty+1)
     for (int a = 0; a < 15; ++a) qC[a] = (T)0;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const T wy = dy == 0 ? W1 : W0;
-      T row[15];
-      for (int a = 0; a < 15; ++a) row[a] = (T)0;
+#pragma unroll 1
+    for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
-        const T wx = dx == 0 ? W1 : W0;
+        const T wxy = (dy == 0 ? W1 : W0) * (dx == 0 ? W1 : W0);
         const int e = (ty + 1 + dy) * RX1 + tx + 1 + dx;
         const T uc = qb[0][e], vc = qb[1][e], wc = qb[2][e];
         const T val[15] = {uc, vc, wc, uc * uc, vc * vc, wc * wc, uc * vc, uc * wc, vc * wc,
                            qb[3][e], qb[4][e], qb[5][e], qb[6][e], qb[7][e], qb[8][e]};
-        for (int a = 0; a < 15; ++a) row[a] = row[a] + wx * val[a];
+        for (int a = 0; a < 15; ++a) qC[a] = qC[a] + wxy * val[a];
       }
-      for (int a = 0; a < 15; ++a) qC[a] = qC[a] + wy * row[a];
-    }
   };
   // ---- output plane k from the register ring (lo, mid, hi) and the filtered-velocity ring
   auto output = [&](int k, const T* lo, const T* mid, const T* hi) {
@@ -415,8 +449,6 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     double lm = 0.0, mm = 0.0;
     const int i = i0 + tx, j = j0 + ty;
     if (i < g.nx && j < g.ny) {
-      T F[15];
-      for (int a = 0; a < 15; ++a) F[a] = W0 * lo[a] + W1 * mid[a] + W0 * hi[a];
       const int sm = ring3<T>(k - 1), s0 = ring3<T>(k), sp = ring3<T>(k + 1);
       const int x = tx + 1, y = ty + 1;  // own cell in R1
       auto A = [&](int c, int dz, int dy, int dx) -> T {
@@ -430,10 +462,13 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       const bool wall_layer = !per && (k == 1 || k == nz);
       const T alpha2 = wall_layer ? (T)2.5198420997897464 : (T)4;
       const T d2 = (T)g.delta2[pk];
-      const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+      // z pass of the test filter, one quantity at a time
+      auto Fz = [&](int a) { return W0 * lo[a] + W1 * mid[a] + W0 * hi[a]; };
+      const T F0 = Fz(0), F1 = Fz(1), F2 = Fz(2);
+      const T Fa[6] = {F0, F1, F2, F0, F0, F1}, Fb[6] = {F0, F1, F2, F1, F2, F2};
       for (int c = 0; c < 6; ++c) {
-        const T L = F[3 + c] - F[pa[c]] * F[pb[c]];
-        const T M = (T)2 * d2 * (F[9 + c] - alpha2 * stm * st[c]);
+        const T L = Fz(3 + c) - Fa[c] * Fb[c];
+        const T M = (T)2 * d2 * (Fz(9 + c) - alpha2 * stm * st[c]);
         const double wgt2 = c < 3 ? 1.0 : 2.0;
         lm += wgt2 * (double)L * (double)M;
         mm += wgt2 * (double)M * (double)M;
@@ -461,14 +496,25 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       part[o + 1] = b;
     }
   };
-  // ---- march
+  // ---- march: velocity plane p + 1 is committed to LDS at the top of iteration p, the loads
+  // of plane p + 2 are issued right after and complete under the work on plane p
   const int pstart = per ? kb - 1 : max(kb - 1, 1);
   const int pend = per ? ke + 1 : min(ke + 1, nz);
-  load_plane(pstart - 1);
-  load_plane(pstart);
+  fetch(pstart - 1);
+  commit(pstart - 1);
+  fetch(pstart);
+  commit(pstart);
+  fetch(pstart + 1);
+  __syncthreads();
+  for (int r = 0; r < NH; ++r)
+    for (int c = 0; c < 3; ++c) G2[r][c] = (T)0;
+  filter_xy(pstart - 1, false);
+  filter_xy(pstart, false);
   for (int p = pstart; p <= pend; ++p) {
-    load_plane(p + 1);
+    commit(p + 1);
     __syncthreads();
+    if (p + 2 <= pend + 1) fetch(p + 2);
+    filter_xy(p + 1, true);
     for (int a = 0; a < 15; ++a) {
       qA[a] = qB[a];
       qB[a] = qC[a];
@@ -497,14 +543,14 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
+__global__ void __launch_bounds__(256, 2) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
                                                    int kc, const int* gate) {
   dsm_fused_body<T>(blockIdx, gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
 }
 
 // Batched dynamic model (and its plane / volume reduction) over all boxes of a batch.
 template <typename T>
-__global__ void __launch_bounds__(256) kb_dsm_fused(BatchMap m) {
+__global__ void __launch_bounds__(256, 2) kb_dsm_fused(BatchMap m) {
   int box;
   const dim3 bid = batch_bid(m, BK_DSM, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
@@ -705,7 +751,7 @@ constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY;
 }  // namespace tiled
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_mlp_nut(GridP g, const T* __restrict__ u, const T* __restrict__ v,
+__global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict__ u, const T* __restrict__ v,
                                                  const T* __restrict__ w, T* __restrict__ nut,
                                                  const float* __restrict__ P, MlpNorm nm, const double* __restrict__ cs,
                                                  const double* __restrict__ dtp, int* __restrict__ cnt, int kc) {
@@ -727,8 +773,6 @@ __global__ void __launch_bounds__(256) k_mlp_nut(GridP g, const T* __restrict__ 
   const bool per = g.zbc == LES_ZBC_PERIODIC;
   const bool wm = g.zbc == LES_ZBC_WALLMODEL;
   load_weights(P, Wt, tid, tiled::NT);
-  auto wrapi = [&](int i) { return ((i % g.nx) + g.nx) % g.nx; };
-  auto wrapj = [&](int j) { return ((j % g.ny) + g.ny) % g.ny; };
   auto phys = [&](int q) {
     if (!per) return q;
     int m = (q - 1) % nz;
@@ -736,39 +780,67 @@ __global__ void __launch_bounds__(256) k_mlp_nut(GridP g, const T* __restrict__ 
     return m + 1;
   };
   auto slot = [](int q) { return ((q % 3) + 3) % 3; };
-  auto load_plane = [&](int q) {
-    const int sl = slot(q), pq = phys(q);
-    for (int e = tid; e < N1; e += tiled::NT) {
-      const int rx = e % RX, ry = e / RX;
-      const int i = wrapi(i0 - 1 + rx), j = wrapj(j0 - 1 + ry);
-      T a, b;
-      if (wm && pq == 0) {
-        const T a1 = u[idx3(g, 1, j, i)], a2 = u[idx3(g, 2, j, i)];
-        const T b1 = v[idx3(g, 1, j, i)], b2 = v[idx3(g, 2, j, i)];
-        a = a1 - (T)g.dzc[0] * ((a2 - a1) / (T)g.dzc[1]);
-        b = b1 - (T)g.dzc[0] * ((b2 - b1) / (T)g.dzc[1]);
-      } else if (wm && pq == nz + 1) {
-        const T a1 = u[idx3(g, nz, j, i)], a0 = u[idx3(g, nz - 1, j, i)];
-        const T b1 = v[idx3(g, nz, j, i)], b0 = v[idx3(g, nz - 1, j, i)];
-        a = a1 + (T)g.dzc[nz] * ((a1 - a0) / (T)g.dzc[nz - 1]);
-        b = b1 + (T)g.dzc[nz] * ((b1 - b0) / (T)g.dzc[nz - 1]);
-      } else {
-        a = u[idx3(g, pq, j, i)];
-        b = v[idx3(g, pq, j, i)];
+  // in-plane offsets of the thread's halo points (tiles may exceed the grid: wrap), and the
+  // velocity of one plane held in registers from its fetch to its commit to LDS, so that the
+  // loads of plane k + 2 overlap the work on plane k (strain ghost rule applied at fetch)
+  constexpr int NL = (N1 + tiled::NT - 1) / tiled::NT;
+  int lofs[NL];
+  for (int r = 0; r < NL; ++r) {
+    const int e = tid + r * tiled::NT;
+    int ii = (i0 - 1 + e % RX) % g.nx, jj = (j0 - 1 + e / RX) % g.ny;
+    if (ii < 0) ii += g.nx;
+    if (jj < 0) jj += g.ny;
+    lofs[r] = e < N1 ? jj * g.nx + ii : 0;
+  }
+  const int64_t sxy = g.sxy;
+  T ra[NL], rb[NL], rc[NL];
+  auto fetch = [&](int q) {
+    const int pq = phys(q);
+    const bool gb = wm && pq == 0, gt = wm && pq == nz + 1;
+    const int64_t bw = (int64_t)pq * sxy;
+    for (int r = 0; r < NL; ++r) {
+      if (tid + r * tiled::NT < N1) {
+        rc[r] = w[bw + lofs[r]];
+        if (gb) {
+          const T a1 = u[sxy + lofs[r]], a2 = u[2 * sxy + lofs[r]];
+          const T b1 = v[sxy + lofs[r]], b2 = v[2 * sxy + lofs[r]];
+          ra[r] = a1 - (T)g.dzc[0] * ((a2 - a1) / (T)g.dzc[1]);
+          rb[r] = b1 - (T)g.dzc[0] * ((b2 - b1) / (T)g.dzc[1]);
+        } else if (gt) {
+          const T a1 = u[nz * sxy + lofs[r]], a0 = u[(nz - 1) * sxy + lofs[r]];
+          const T b1 = v[nz * sxy + lofs[r]], b0 = v[(nz - 1) * sxy + lofs[r]];
+          ra[r] = a1 + (T)g.dzc[nz] * ((a1 - a0) / (T)g.dzc[nz - 1]);
+          rb[r] = b1 + (T)g.dzc[nz] * ((b1 - b0) / (T)g.dzc[nz - 1]);
+        } else {
+          ra[r] = u[bw + lofs[r]];
+          rb[r] = v[bw + lofs[r]];
+        }
       }
-      vel[sl][0][e] = a;
-      vel[sl][1][e] = b;
-      vel[sl][2][e] = w[idx3(g, pq, j, i)];
     }
   };
-  load_plane(kb - 1);
-  load_plane(kb);
+  auto commit = [&](int q) {
+    const int sl = slot(q);
+    for (int r = 0; r < NL; ++r) {
+      const int e = tid + r * tiled::NT;
+      if (e < N1) {
+        vel[sl][0][e] = ra[r];
+        vel[sl][1][e] = rb[r];
+        vel[sl][2][e] = rc[r];
+      }
+    }
+  };
+  fetch(kb - 1);
+  commit(kb - 1);
+  fetch(kb);
+  commit(kb);
+  fetch(kb + 1);
   int flagged = 0;
   const int i = i0 + tx, j = j0 + ty;
   const bool inside = i < g.nx && j < g.ny;
   for (int k = kb; k <= ke; ++k) {
-    load_plane(k + 1);
+    commit(k + 1);
     __syncthreads();
+    if (k + 2 <= ke + 1) fetch(k + 2);
     const int pk = phys(k);
     const int sm = slot(k - 1), s0 = slot(k), sp = slot(k + 1);
     const int x = tx + 1, y = ty + 1;
