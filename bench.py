@@ -38,8 +38,12 @@ CONFIGS = {
     "c3": dict(name="channel 1024x512x256 mixed DSM+WM explicit", nx=1024, ny=512, nz=256,
                lx=2 * 3.141592653589793, ly=3.141592653589793, lz=2.0, zbc=2, beta=1.5, nu=1.6e-5, sgs=3,
                cs=0.17, implicit_z=0, precision=1, ubulk=1.0, init="channel", seed=3, dtype="f32/f64"),
+    "c4": dict(name="channel 512x256x128 fp64 learned closure vs DSM, WM, CN-z", nx=512, ny=256, nz=128,
+               lx=2 * 3.141592653589793, ly=3.141592653589793, lz=2.0, zbc=2, beta=1.5, nu=5e-5, sgs=3,
+               cs=0.17, implicit_z=1, precision=0, ubulk=1.0, init="channel", seed=4, dtype="f64"),
+    "c5": dict(name="64 isotropic boxes 32^3/48^3/64^3/96^3 fp32 DSM explicit, batched", nbox=64, seed=5,
+               dtype="f32"),
 }
-
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -51,6 +55,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--compare-steps", type=int, default=100,
+                    help="c3: steps of the mixed vs FP64 comparison; c4: steps of the mean-profile comparison")
+    ap.add_argument("--spinup", type=int, default=300, help="c4: dynamic-model steps before sampling")
+    ap.add_argument("--snapshots", type=int, default=20, help="c4: training snapshots")
+    ap.add_argument("--per-snapshot", type=int, default=1 << 19, help="c4: samples per snapshot")
+    ap.add_argument("--epochs", type=int, default=5, help="c4: training epochs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of known size (calibration of HBM counters)")
     return ap.parse_args()
 
 
@@ -102,6 +114,70 @@ def cpu_baseline(cfgd, budget_s):
                       f"in {el:.1f} s, numpy float64, 1 thread"}
 
 
+def initial_params(seed):
+    """Seeded initial weights of the 7-64-64-1 network (uniform, half the Glorot limit;
+    zero biases), flattened in the library's parameter order."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    init = []
+    for shape in ((64, 7), (64,), (64, 64), (64,), (1, 64), (1,)):
+        if len(shape) == 2:
+            lim = np.sqrt(6.0 / shape[1]) * 0.5
+            init.append(rng.uniform(-lim, lim, size=shape).ravel())
+        else:
+            init.append(np.zeros(shape))
+    return np.concatenate(init)
+
+
+def feature_range(torch, xr):
+    """Scaling range of the raw features: the sample min/max widened by a quarter of the
+    span on each side (inputs beyond it, with the 5 % margin, fall back to the dynamic
+    model)."""
+    lo = xr.min(dim=0).values.double().cpu().numpy()
+    hi = xr.max(dim=0).values.double().cpu().numpy()
+    pad = 0.25 * (hi - lo) + 1e-12
+    return lo - pad, hi + pad
+
+
+def run_steps(les, s, n, use_graph=True):
+    for _ in range(n):
+        les.les_dt(s.ctx, 0.5, sync=False)
+        les.les_step(s.ctx, use_graph)
+
+
+def copy_state(torch, dst, src):
+    """Device copy of u, v, w, p from one context's fields into another's."""
+    src.synchronize()
+    with torch.cuda.stream(dst.stream):
+        for a, b in ((dst.u, src.u), (dst.v, src.v), (dst.w, src.w), (dst.p, src.p)):
+            a.copy_(b)
+    dst.synchronize()
+
+
+def kernel_report(les, ctx, nsteps):
+    """Per-kernel HIP-event timing over nsteps un-captured steps; returns (kernels, dominant)."""
+    les.les_timing(ctx, True)
+    for _ in range(nsteps):
+        les.les_dt(ctx, 0.5, sync=False)
+        les.les_step(ctx, False)
+    les.les_timing(ctx, False)
+    rep = les.les_timing_report(ctx)
+    kernels = {k: {"launches": v["count"], "avg_us": 1e3 * v["ms"] / v["count"],
+                   "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] > 0 else None,
+                   "share": 0.0} for k, v in rep.items()}
+    tot_ms = sum(v["ms"] for v in rep.values())
+    for k, v in rep.items():
+        kernels[k]["share"] = v["ms"] / tot_ms if tot_ms > 0 else 0.0
+    dom = max((k for k in rep if rep[k]["bytes"] > 0), key=lambda k: rep[k]["ms"])
+    d = rep[dom]
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    per_launch = d["bytes"] / d["count"]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(dom, per_launch),
+            "alg_bytes_per_launch": per_launch, "avg_launch_us": round(1e3 * d["ms"] / d["count"], 3)}
+    return kernels, roof
+
+
 def learned_closure(les, torch, cfgd, solver, steps, warmup, use_graph):
     """Same workload with the learned closure: the network is trained on the GPU from
     dynamic-model pairs sampled from the plain solver's current state (400 Adam steps on
@@ -110,21 +186,10 @@ def learned_closure(les, torch, cfgd, solver, steps, warmup, use_graph):
     import numpy as np
     sys.path.insert(0, ROOT)
     xr, yr = solver.mlp_sample(7, 1 << 16)
-    xn = xr.cpu().numpy().astype(np.float64)
-    lo, hi = xn.min(axis=0), xn.max(axis=0)
-    pad = 0.25 * (hi - lo) + 1e-12
-    lo, hi = lo - pad, hi + pad
+    lo, hi = feature_range(torch, xr)
     x = torch.empty_like(xr)
     les.les_mlp_normalize(solver.stream.cuda_stream, xr.data_ptr(), xr.shape[0], lo, hi, x.data_ptr())
-    rng = np.random.Generator(np.random.PCG64(5))
-    init = []
-    for shape in ((64, 7), (64,), (64, 64), (64,), (1, 64), (1,)):
-        if len(shape) == 2:
-            lim = np.sqrt(6.0 / shape[1]) * 0.5
-            init.append(rng.uniform(-lim, lim, size=shape).ravel())
-        else:
-            init.append(np.zeros(shape))
-    mlp = les.Mlp(np.concatenate(init), stream=solver.stream)
+    mlp = les.Mlp(initial_params(5), stream=solver.stream)
     t0 = time.perf_counter()
     for it in range(400):
         loss = mlp.train_step(x, yr, 3e-3 if it < 300 else 1e-3)
@@ -188,59 +253,66 @@ def traffic_entry(kernel, launches_bytes):
         return None
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not "
-              f"built in this library", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    torch.cuda.set_device(0)
-    cfgd = CONFIGS[args.config]
+def precision_check(les, torch, cfgd, steps):
+    """Mixed precision against FP64 on the same workload.  Both contexts start from the same
+    seeded field (rounded to FP32 so both hold identical values) and advance `steps` steps,
+    each with its own device-side time step.  Reported: max |D u| and the flow rate of each
+    run, the largest difference of the plane-mean streamwise velocity profiles (relative to
+    U_b) and of the velocity fields (relative to the FP64 field's largest magnitude)."""
+    import numpy as np
+    _, s64 = make_solver(dict(cfgd, precision=0))
+    _, s32 = make_solver(cfgd)
+    zf, zc = s64.zgrid()
+    u, v, w = initial_fields(cfgd, zc)
+    u, v, w = (a.astype(np.float32).astype(np.float64) for a in (u, v, w))
+    for s in (s64, s32):
+        s.set_state(u, v, w)
+        s.nut()
+    del u, v, w
+    secs = {}
+    for name, s in (("fp64", s64), ("mixed", s32)):
+        t0 = time.perf_counter()
+        run_steps(les, s, steps)
+        s.synchronize()
+        secs[name] = round(time.perf_counter() - t0, 3)
+    n = cfgd["nz"]
+    out = {"steps": steps, "seconds": secs}
+    for name, s in (("fp64", s64), ("mixed", s32)):
+        d, _ = s.diag()
+        out[name] = {"max_div": d.max_div, "ubulk": d.ubulk, "nonfinite": int(d.nonfinite)}
+    p64 = s64.u[1:n + 1].mean(dim=(1, 2))
+    p32 = s32.u[1:n + 1].double().mean(dim=(1, 2))
+    out["mean_u_profile_max_abs_err_over_ub"] = float((p32 - p64).abs().max().item()) / cfgd["ubulk"]
+    for name, a64, a32 in (("u", s64.u, s32.u), ("v", s64.v, s32.v), ("w", s64.w, s32.w)):
+        ref = float(a64[1:n + 1].abs().max().item())
+        out[f"{name}_max_rel_err"] = float((a32[1:n + 1].double() - a64[1:n + 1]).abs().max().item()) / ref
+    s64.close()
+    s32.close()
+    return out
+
+
+def solver_line(args, torch, cfgd):
     les, solver = make_solver(cfgd)
     zf, zc = solver.zgrid()
     u, v, w = initial_fields(cfgd, zc)
     solver.set_state(u, v, w)
     solver.nut()
+    del u, v, w
     ctx = solver.ctx
     use_graph = not args.no_graph
     cells = cfgd["nx"] * cfgd["ny"] * cfgd["nz"]
-
-    def step(graph):
-        les.les_dt(ctx, 0.5, sync=False)
-        les.les_step(ctx, graph)
-
-    for _ in range(args.warmup):
-        step(use_graph)
+    run_steps(les, solver, args.warmup, use_graph)
     solver.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(use_graph)
+    run_steps(les, solver, args.steps, use_graph)
     solver.synchronize()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms_per_step = el / args.steps * 1e3
     value = cells * 3 * args.steps / el / 1e6
-
     # per-kernel pass: same steps without the graph, every launch bracketed by HIP events
-    ksteps = max(1, min(args.steps, 10))
-    les.les_timing(ctx, True)
-    for _ in range(ksteps):
-        step(False)
-    les.les_timing(ctx, False)
-    rep = les.les_timing_report(ctx)
-    kernels = {k: {"launches": v["count"], "avg_us": 1e3 * v["ms"] / v["count"],
-                   "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] > 0 else None,
-                   "share": 0.0} for k, v in rep.items()}
-    tot_ms = sum(v["ms"] for v in rep.values())
-    for k, v in rep.items():
-        kernels[k]["share"] = v["ms"] / tot_ms if tot_ms > 0 else 0.0
-    dom = max((k for k in rep if rep[k]["bytes"] > 0), key=lambda k: rep[k]["ms"])
-    d = rep[dom]
-    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-    per_launch = d["bytes"] / d["count"]
-    traffic = traffic_entry(dom, per_launch)
+    kernels, roof = kernel_report(les, ctx, max(1, min(args.steps, 10)))
     diag, status = solver.diag()
     out = {
         "metric": METRIC,
@@ -258,17 +330,259 @@ def main():
         "config": {"workload": cfgd["name"], "grid": [cfgd["nx"], cfgd["ny"], cfgd["nz"]],
                    "substeps_per_step": 3, "graph": use_graph, "closure": "dynamic Smagorinsky"
                    if cfgd["sgs"] == 3 else "Smagorinsky"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "alg_bytes_per_launch": per_launch, "avg_launch_us": round(1e3 * d["ms"] / d["count"], 3)},
+        "roofline": roof,
         "kernels": kernels,
         "state_check": {"max_div": diag.max_div, "ubulk": diag.ubulk, "nonfinite": int(diag.nonfinite)},
     }
-    if not args.no_learned and cfgd["sgs"] == 3:
+    if not args.no_learned and cfgd["sgs"] == 3 and args.config == "c2":
         out["learned_closure"] = learned_closure(les, torch, cfgd, solver, args.steps, args.warmup, use_graph)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfgd, args.cpu_seconds)
     solver.close()
+    if args.config == "c3":
+        out["precision_check"] = precision_check(les, torch, cfgd, args.compare_steps)
+    if not args.no_cpu_baseline and args.config in ("c1", "c2"):
+        out["cpu_baseline"] = cpu_baseline(cfgd, args.cpu_seconds)
+    return out
+
+
+def learned_line(args, torch):
+    """Learned closure against the dynamic model on the 512 x 256 x 128 channel.
+    1. Dynamic-model run from the seeded laminar-plus-noise field for `spinup` steps.
+    2. Training pairs (raw features, dynamic c_s of the cell's plane) sampled on the GPU at
+       `snapshots` states 10 steps apart, `per_snapshot` cells each; the batches interleave
+       the snapshots.
+    3. Training on the GPU with the library's kernels (Adam, batches of 2^16, `epochs` passes).
+    4. On the last dynamic-model state: the learned and the dynamic eddy viscosity of the
+       same velocity; the learned closure's effective plane coefficient
+       c_eff(k) = c_s(k) <nu_t,learned>(k) / <nu_t,dynamic>(k) against c_s(k).
+    5. Throughput of both closures from that state (graph-replayed steps).
+    6. Both runs restarted from that state for `compare_steps` steps: plane-mean streamwise
+       velocity profiles compared."""
+    import numpy as np
+    cfgd = CONFIGS["c4"]
+    use_graph = not args.no_graph
+    les, sd = make_solver(cfgd)
+    zf, zc = sd.zgrid()
+    u, v, w = initial_fields(cfgd, zc)
+    sd.set_state(u, v, w)
+    sd.nut()
+    del u, v, w
+    t0 = time.perf_counter()
+    run_steps(les, sd, args.spinup, use_graph)
+    sd.synchronize()
+    spin_s = time.perf_counter() - t0
+    xs, ys = [], []
+    for q in range(args.snapshots):
+        run_steps(les, sd, 10, use_graph)
+        x, y = sd.mlp_sample(1000 + q, args.per_snapshot)
+        xs.append(x)
+        ys.append(y)
+    sd.synchronize()
+    X = torch.stack(xs, 1).reshape(-1, 7).contiguous()
+    Y = torch.stack(ys, 1).reshape(-1).contiguous()
+    del xs, ys
+    torch.cuda.synchronize()
+    lo, hi = feature_range(torch, X)
+    Xn = torch.empty_like(X)
+    les.les_mlp_normalize(sd.stream.cuda_stream, X.data_ptr(), X.shape[0], lo, hi, Xn.data_ptr())
+    mlp = les.Mlp(initial_params(5), stream=sd.stream)
+    B = 1 << 16
+    nb = X.shape[0] // B
+    total = args.epochs * nb
+    t0 = time.perf_counter()
+    it = 0
+    for ep in range(args.epochs):
+        for b in range(nb):
+            lr = 3e-3 if it < 0.6 * total else (1e-3 if it < 0.9 * total else 3e-4)
+            loss = mlp.train_step(Xn[b * B:(b + 1) * B], Y[b * B:(b + 1) * B], lr)
+            it += 1
+    sd.synchronize()
+    train_s = time.perf_counter() - t0
+    final_loss = float(loss.item())
+    target_var = float(Y.double().var().item())
+    del X, Xn, Y
+    cfg_m = les.make_config(cfgd["nx"], cfgd["ny"], cfgd["nz"], cfgd["lx"], cfgd["ly"], cfgd["lz"], zbc=cfgd["zbc"],
+                            beta=cfgd["beta"], nu=cfgd["nu"], sgs=les.SGS_MLP, cs=cfgd["cs"],
+                            implicit_z=cfgd["implicit_z"], precision=cfgd["precision"], ubulk=cfgd["ubulk"])
+    sm = les.Solver(cfg_m)
+    sm.mlp_bind(mlp, lo, hi)
+    copy_state(torch, sm, sd)
+    sd.nut()
+    sm.nut()
+    sd.synchronize()
+    sm.synchronize()
+    snap = [t.clone() for t in (sd.u, sd.v, sd.w, sd.p)]
+    torch.cuda.synchronize()
+    n = cfgd["nz"]
+    nut_d = sd.eddy_viscosity()[1:n + 1]
+    nut_m = sm.eddy_viscosity()[1:n + 1]
+    cs_d = sd.coefficient()
+    md, mm = nut_d.mean(axis=(1, 2)), nut_m.mean(axis=(1, 2))
+    ok = md > 0
+    ceff = np.where(ok, cs_d * mm / np.where(ok, md, 1.0), 0.0)
+    coef_err = float(np.linalg.norm(ceff - cs_d) / max(np.linalg.norm(cs_d), 1e-300))
+    nut_plane_err = float(np.linalg.norm(mm - md) / max(np.linalg.norm(md), 1e-300))
+    nut_point_err = float(np.sqrt(np.mean((nut_m - nut_d) ** 2)) / max(np.sqrt(np.mean(nut_d ** 2)), 1e-300))
+    dm, _ = sm.diag()
+    flagged = int(dm.mlp_flagged)
+    del nut_d, nut_m
+    cells = cfgd["nx"] * cfgd["ny"] * cfgd["nz"]
+    thr = {}
+    for name, s in (("dynamic", sd), ("learned", sm)):
+        run_steps(les, s, args.warmup, use_graph)
+        s.synchronize()
+        t0 = time.perf_counter()
+        run_steps(les, s, args.steps, use_graph)
+        s.synchronize()
+        el = time.perf_counter() - t0
+        thr[name] = (cells * 3 * args.steps / el / 1e6, el / args.steps * 1e3)
+    kernels, roof = kernel_report(les, sm.ctx, max(1, min(args.steps, 10)))
+    # mean-profile comparison from the same state
+    torch.cuda.synchronize()
+    for s in (sd, sm):
+        with torch.cuda.stream(s.stream):
+            for a, b in zip((s.u, s.v, s.w, s.p), snap):
+                a.copy_(b)
+        s.nut()
+    for s in (sd, sm):
+        run_steps(les, s, args.compare_steps, use_graph)
+        s.synchronize()
+    pd = sd.u[1:n + 1].mean(dim=(1, 2))
+    pm = sm.u[1:n + 1].mean(dim=(1, 2))
+    prof_err = float((pm - pd).abs().max().item()) / cfgd["ubulk"]
+    d1, _ = sd.diag()
+    d2, _ = sm.diag()
+    out = {
+        "metric": METRIC,
+        "value": round(thr["learned"][0], 3),
+        "unit": "Mpts·substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(thr["learned"][1], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": cfgd["dtype"],
+        "data": "synthetic",
+        "config": {"workload": cfgd["name"], "grid": [cfgd["nx"], cfgd["ny"], cfgd["nz"]],
+                   "substeps_per_step": 3, "graph": use_graph, "closure": "learned (BF16 MFMA) with dynamic fallback"},
+        "roofline": roof,
+        "kernels": kernels,
+        "dynamic_value": round(thr["dynamic"][0], 3),
+        "dynamic_ms_per_step": round(thr["dynamic"][1], 4),
+        "training": {"spinup_steps": args.spinup, "spinup_seconds": round(spin_s, 2), "snapshots": args.snapshots,
+                     "samples": nb * B, "epochs": args.epochs, "adam_steps": total,
+                     "seconds": round(train_s, 2), "final_batch_mse": final_loss, "target_variance": target_var},
+        "coefficient_error": {"plane_coefficient_rel_l2": coef_err, "plane_nut_rel_l2": nut_plane_err,
+                              "pointwise_nut_rel_rms": nut_point_err, "fallback_points": flagged},
+        "mean_profile": {"steps": args.compare_steps, "max_abs_diff_over_ub": prof_err,
+                         "max_div": [d1.max_div, d2.max_div], "ubulk": [d1.ubulk, d2.ubulk],
+                         "nonfinite": [int(d1.nonfinite), int(d2.nonfinite)]},
+    }
+    sd.close()
+    sm.close()
+    return out
+
+
+def batch_line(args, torch):
+    """64 periodic boxes of mixed sizes advanced together: one launch per kernel kind per
+    substep for all boxes, per-box device time step, the whole step replayed from a
+    hipGraph, tiles chosen by the autotuner first (its time reported separately)."""
+    from paper_2411_09364_amd import les
+    from synth import box_ensemble, isotropic_field
+    cfgd = CONFIGS["c5"]
+    two_pi = 2 * 3.141592653589793
+    ens = box_ensemble(cfgd["nbox"], seed=cfgd["seed"])
+    cfgs = [les.make_config(e["n"], e["n"], e["n"], two_pi, two_pi, two_pi, zbc=0, nu=e["nu"], sgs=3, cs=0.17,
+                            implicit_z=0, precision=1) for e in ens]
+    b = les.Batch(cfgs)
+    init = [isotropic_field(e["n"], seed=e["seed"], k0=e["k0"]) for e in ens]
+
+    def load():
+        for i, (u, v, w) in enumerate(init):
+            b.set_state(i, u, v, w)
+        b.nut()
+
+    # the autotuner advances the state it times: tune on the initial fields, then reload them
+    load()
+    b.dt(0.5)
+    t0 = time.perf_counter()
+    tune = b.autotune(6)
+    b.synchronize()
+    tune_s = time.perf_counter() - t0
+    load()
+    use_graph = not args.no_graph
+    for _ in range(args.warmup):
+        b.step(0.5, use_graph)
+    b.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.step(0.5, use_graph)
+    b.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cells = sum(e["n"] ** 3 for e in ens)
+    value = cells * 3 * args.steps / el / 1e6
+    divs, bad = [], 0
+    for i in range(len(ens)):
+        d = b.box_dt(i)
+        divs.append(d.max_div)
+        bad += int(d.nonfinite)
+    alg = 25 * 4   # minimal-sweep words per point and substep (explicit), FP32 storage
+    achieved = value * 1e6 * alg / 1e9
+    b.close()
+    sizes = {}
+    for e in ens:
+        sizes[e["n"]] = sizes.get(e["n"], 0) + 1
+    return {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mpts·substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": cfgd["dtype"],
+        "data": "synthetic",
+        "config": {"workload": cfgd["name"], "boxes": {str(k): v for k, v in sorted(sizes.items())},
+                   "cells": cells, "substeps_per_step": 3, "graph": use_graph},
+        "roofline": {"bound": "hbm", "kernel": "whole substep (all kernels, minimal-sweep bytes)",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "alg_bytes_per_point": alg},
+        "autotune": {"seconds": round(tune_s, 3), "choice": tune},
+        "state_check": {"max_div": max(divs), "nonfinite": bad},
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not "
+              f"built in this library", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        # elementwise kernel reading 2^25 doubles and writing 2^25 doubles (256 MiB each way)
+        n = 1 << 25
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe": {"kernel": "elementwise mul by 1.0", "read_bytes": 8 * n,
+                                         "write_bytes": 8 * n, "launches": 5}}), flush=True)
+        return
+    if args.config == "c5":
+        out = batch_line(args, torch)
+    elif args.config == "c4":
+        out = learned_line(args, torch)
+    else:
+        out = solver_line(args, torch, CONFIGS[args.config])
     print(json.dumps(out), flush=True)
 
 

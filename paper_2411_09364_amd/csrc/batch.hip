@@ -128,8 +128,8 @@ les_status prepare(les_batch* b) {
     set(BK_DSMRED, nz, 1, 1);
     set(BK_CFL, 64, 1, 1);
     b->sh_x = std::max(b->sh_x, 2 * (size_t)d.pbx * nx * 2 * E);
-    b->sh_y = std::max(b->sh_y, 2 * (size_t)d.ly * ny * 2 * E);
-    b->sh_z = std::max(b->sh_z, 2 * (size_t)d.lz * nz * 2 * E);
+    b->sh_y = std::max(b->sh_y, 2 * (size_t)d.ly * (ny + 1) * 2 * E);
+    b->sh_z = std::max(b->sh_z, 2 * (size_t)d.lz * (nz + 1) * 2 * E);
   }
   for (int k = 0; k < BK_NKIND; ++k) {
     int* pre = &b->hprefix[(size_t)k * (b->nbox + 1)];

@@ -161,23 +161,29 @@ size_t carve(Ctx& c, char* base) {
   t.twx_f = (float*)take(2 * f.nx * 4);
   t.twy_f = (float*)take(2 * f.ny * 4);
   t.twz_f = (float*)take(2 * n * 4);
-  t.hfac = (double*)take(6 * n * 8);
+  t.hfac = (double*)take(8 * n * 8);
   t.dt = (double*)take(16 * 8);
   c.mlp_cnt = (int*)take(2 * sizeof(int));
   t.red_n = 4096;
   t.red = (double*)take(t.red_n * 8);
   const int64_t npairs = (int64_t)n * (f.ny / 2);
   t.bulk = (double*)take((size_t)std::max<int64_t>(npairs, 1) * 8);
-  t.zcol = (double*)take(3 * n * 8);
   t.tau = (double*)take(4 * sxy * 8);
   t.utau = (double*)take(4 * sxy * 8);
-  // plane partial sums: one per x-y tile of the fused dynamic-model kernel (32 x 8)
+  // plane partial sums (LM, MM): one per wave of each x-y tile of the fused dynamic-model
+  // kernel (32 x 8 cells, 4 waves)
   t.nblk_xy = ((f.nx + 31) / 32) * ((f.ny + 7) / 8);
   {
-    const int64_t want = (int64_t)n * t.nblk_xy / 1024;   // aim at >= 1024 blocks
-    c.dsm_kc = (int)std::max<int64_t>(8, std::min<int64_t>(n, want));
+    // z chunk lengths: whole rounds of resident blocks (the dynamic-model kernel holds two
+    // blocks per CU, the learned-closure inference three, on 256 CUs), at least 8 planes
+    auto chunk = [&](int64_t slots) {
+      const int64_t want = ((int64_t)n * t.nblk_xy + slots - 1) / slots;
+      return (int)std::max<int64_t>(std::min<int64_t>(8, n), std::min<int64_t>(n, want));
+    };
+    c.dsm_kc = chunk(512);
+    c.mlp_kc = chunk(768);
   }
-  t.dsm_part = (double*)take((size_t)2 * n * t.nblk_xy * 8);
+  t.dsm_part = (double*)take((size_t)2 * n * t.nblk_xy * 4 * 8);
   c.ru = take(F * E);
   c.rv = take(F * E);
   c.rw = take(F * E);
@@ -187,6 +193,8 @@ size_t carve(Ctx& c, char* base) {
   c.nut = take(F * E);
   c.phi = take(F * E);
   c.spec = take((size_t)(f.nx / 2 + 1) * f.ny * n * 2 * E);
+  // factor pairs of the z systems of every (l, m) column (walls only)
+  t.pfac = (double*)take(f.zbc == LES_ZBC_PERIODIC ? 0 : (size_t)(f.nx / 2 + 1) * f.ny * n * 2 * 8);
   return off;
 }
 
@@ -365,7 +373,7 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
           const double d = std::pow((f.lx / f.nx) * (f.ly / f.ny) * c.dzf[k], 1.0 / 3.0);
           c.coef_host[k] = (f.cs * d) * (f.cs * d);
         }
-      c.hfac_host.assign(6 * n, 0.0);
+      c.hfac_host.assign(8 * n, 0.0);
       for (int k = 0; k < n; ++k) c.hfac_host[4 * n + k] = 1.0;
       if ((s = up(c.t.zc, c.zc.data(), (n + 2) * 8)) != LES_OK) return s;
       if ((s = up(c.t.dzf, c.dzf.data(), (n + 2) * 8)) != LES_OK) return s;
@@ -388,6 +396,10 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       // learned closure: the first evaluation runs the dynamic model (fallback coefficients)
       static const int cnt_init[2] = {0, 1};
       if ((s = up(c.mlp_cnt, cnt_init, sizeof(cnt_init))) != LES_OK) return s;
+      if (f.zbc != LES_ZBC_PERIODIC) {
+        launch_thomas_factor(c);
+        if ((s = check_hip(c, hipGetLastError(), "thomas factorisation")) != LES_OK) return s;
+      }
       c.initialised = false;
       if (c.graph_exec) {
         hipGraphExecDestroy(c.graph_exec);

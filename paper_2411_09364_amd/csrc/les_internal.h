@@ -60,14 +60,15 @@ struct Tables {
   float* twx_f;     // float copies
   float* twy_f;
   float* twz_f;
-  double* hfac;     // 6*nz: CN-z factorisation (cp, rpiv) for u/v rows and w rows + q profile
+  double* hfac;     // 8*nz: CN-z factorisation: c', 1/pivot for u/v rows and for w rows, the
+                    //   flow-rate profile q, unused, sub-diagonals for u/v rows and for w rows
   double* dt;       // [0] time step; [1] bulk shift s; [2..] scratch scalars
   double* red;      // reduction partials (size red_n)
   double* bulk;     // flow-rate partial sums, one per forward-x block
-  double* zcol;     // 3*nz scratch of the singular (0, 0) Poisson column
   double* tau;      // 4*nx*ny wall stresses
   double* utau;     // 4*nx*ny Newton state
-  double* dsm_part; // 2*nz*nblk_xy plane partial sums (LM, MM)
+  double* dsm_part; // 2*nz*nblk_xy*4 plane partial sums (LM, MM) per tile and wave
+  double* pfac;     // walls: (c', 1/pivot) of every (l, m) z system, [nz][ny][nx/2+1] pairs
   int64_t red_n;
   int nblk_xy;      // number of x-y tiles used by plane reductions
 };
@@ -100,6 +101,7 @@ struct Ctx {
   void* phi = nullptr;    // pressure correction (field layout)
   void* spec = nullptr;   // complex spectrum [nz][ny][nx/2+1]
   int dsm_kc = 8;         // planes per z chunk of the fused dynamic-model kernel
+  int mlp_kc = 8;         // planes per z chunk of the learned-closure inference kernel
   // learned closure
   float* mlp_params = nullptr;   // caller-owned float32 parameters (les_mlp_bind)
   double mlp_lo[7], mlp_hi[7];    // feature ranges for min-max scaling
@@ -124,6 +126,7 @@ template <typename T> void launch_predictor(Ctx& c, int stage);
 template <typename T> void launch_helmholtz(Ctx& c, int stage);
 template <typename T> void launch_poisson_rhs_fwd(Ctx& c, const T* us, const T* vs, const T* ws, double scale_by_gamma_dt, int stage);
 template <typename T> void launch_poisson_solve_spectral(Ctx& c);
+void launch_thomas_factor(Ctx& c);
 template <typename T> void launch_poisson_inverse(Ctx& c, T* phi_out);
 template <typename T> void launch_correct(Ctx& c, int stage);
 template <typename T> void launch_bc_fill(Ctx& c, T* u, T* v, T* w, T* p);

@@ -41,12 +41,18 @@ __device__ inline s4 lds4(const unsigned short* p) {
   r.w = (short)(b >> 16);
   return r;
 }
+// four float32 -> bfloat16 (round to nearest even) with the packed hardware conversion
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
 __device__ inline s4 pack4(float a, float b, float c, float d) {
+  const fl2 lo = {a, b}, hi = {c, d};
+  const unsigned int x = __builtin_bit_cast(unsigned int, __builtin_convertvector(lo, bf2));
+  const unsigned int y = __builtin_bit_cast(unsigned int, __builtin_convertvector(hi, bf2));
   s4 r;
-  r.x = (short)f2bf(a);
-  r.y = (short)f2bf(b);
-  r.z = (short)f2bf(c);
-  r.w = (short)f2bf(d);
+  r.x = (short)(x & 0xFFFF);
+  r.y = (short)(x >> 16);
+  r.z = (short)(y & 0xFFFF);
+  r.w = (short)(y >> 16);
   return r;
 }
 

@@ -5,8 +5,8 @@
 //                packed as one complex row, Stockham FFT in LDS, split into the two
 //                half spectra l = 0..nx/2; also the flow-rate partial sums of u*.
 //   k_fft_lines  complex FFT along y (or z) for tiles of consecutive l, in LDS.
-//   k_thomas     FP64 Thomas solve along z for every (l, m) column, pivots' companion
-//                values in LDS; the singular (0, 0) column is pinned and mean-corrected.
+//   k_thomas     FP64 Thomas solve along z for every (l, m) column, staged through LDS;
+//                the singular (0, 0) column is pinned and mean-corrected.
 //   k_fftz_solve periodic z: forward FFT along z, division by the eigenvalue sum, inverse.
 //   k_irfftx     Hermitian reconstruction of two rows, inverse FFT, real and imaginary
 //                parts back to the two rows of phi.
@@ -137,7 +137,7 @@ __device__ inline const float* twsel<float>(const double*, const float* f) { ret
 // ============================================================================ forward x
 // MODE 0: f = D u* scaled; MODE 1: f given (les_poisson).
 template <typename T, int MODE>
-__device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, FftPlan P, const T* __restrict__ us, const T* __restrict__ vs,
+__device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, const FftPlan& P, const T* __restrict__ us, const T* __restrict__ vs,
                                                const T* __restrict__ ws, const T* __restrict__ fin,
                                                cpx<T>* __restrict__ spec, const double* __restrict__ twd,
                                                const float* __restrict__ twf, const double* __restrict__ dtp,
@@ -149,31 +149,61 @@ __device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, FftPlan P, const T
   const int64_t npairs = (int64_t)g.nz * nyh;
   const T scale = MODE == 0 ? (T)(1.0 / (gamma * dtp[0])) : (T)1;
   double bsum = 0.0;
-  for (int e = threadIdx.x; e < npair_blk * nx; e += blockDim.x) {
-    const int p = e / nx, i = e % nx;
-    const int64_t gp = (int64_t)bid.x * npair_blk + p;
-    cpx<T> z = {(T)0, (T)0};
-    if (gp < npairs) {
-      const int k = (int)(gp / nyh) + 1;
-      const int j0 = 2 * (int)(gp % nyh);
-      T fv[2];
+  // batches of RB elements per thread: every load of the batch is issued before the
+  // arithmetic and the LDS stores (out-of-range lanes read cell 0 and store zero)
+  constexpr int RB = 2;
+  const int total = npair_blk * nx;
+  for (int e0 = 0; e0 < total; e0 += RB * (int)blockDim.x) {
+    T q[RB][2][6];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      const int p = e / nx, i = e % nx;
+      const int64_t gp = (int64_t)bid.x * npair_blk + p;
+      const bool ok = e < total && gp < npairs;
+      const int k = ok ? (int)(gp / nyh) + 1 : 1;
+      const int j0 = ok ? 2 * (int)(gp % nyh) : 0;
+#pragma unroll
       for (int r = 0; r < 2; ++r) {
         const int j = j0 + r;
         const int64_t c = idx3(g, k, j, i);
         if (MODE == 0) {
-          const T d = (us[c] - us[idx3(g, k, j, wrap_m(i, nx))]) * (T)g.rdx +
-                      (vs[c] - vs[idx3(g, k, wrap_m(j, g.ny), i)]) * (T)g.rdy +
-                      (ws[c] - ((k == 1 && g.zbc == LES_ZBC_PERIODIC) ? ws[idx3(g, g.nz, j, i)] : ws[c - g.sxy])) *
-                          (T)(1.0 / g.dzf[k]);
-          fv[r] = d * scale;
-          if (bulk_part) bsum += (double)us[c] * g.dzf[k];
+          q[b][r][0] = us[c];
+          q[b][r][1] = us[idx3(g, k, j, wrap_m(i, nx))];
+          q[b][r][2] = vs[c];
+          q[b][r][3] = vs[idx3(g, k, wrap_m(j, g.ny), i)];
+          q[b][r][4] = ws[c];
+          q[b][r][5] = (k == 1 && g.zbc == LES_ZBC_PERIODIC) ? ws[idx3(g, g.nz, j, i)] : ws[c - g.sxy];
         } else {
-          fv[r] = fin[c];
+          q[b][r][0] = fin[c];
         }
       }
-      z = {fv[0], fv[1]};
     }
-    A[e] = z;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      if (e >= total) continue;
+      const int p = e / nx;
+      const int64_t gp = (int64_t)bid.x * npair_blk + p;
+      cpx<T> z = {(T)0, (T)0};
+      if (gp < npairs) {
+        const int k = (int)(gp / nyh) + 1;
+        T fv[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          if (MODE == 0) {
+            const T d = (q[b][r][0] - q[b][r][1]) * (T)g.rdx + (q[b][r][2] - q[b][r][3]) * (T)g.rdy +
+                        (q[b][r][4] - q[b][r][5]) * (T)(1.0 / g.dzf[k]);
+            fv[r] = d * scale;
+            if (bulk_part) bsum += (double)q[b][r][0] * g.dzf[k];
+          } else {
+            fv[r] = q[b][r][0];
+          }
+        }
+        z = {fv[0], fv[1]};
+      }
+      A[e] = z;
+    }
   }
   if (bulk_part) {
     __shared__ double red[256];
@@ -227,7 +257,7 @@ __global__ void __launch_bounds__(256) kb_rfftx(BatchMap m, double gamma) {
 
 // ============================================================================ inverse x
 template <typename T>
-__device__ __forceinline__ void irfftx_body(dim3 bid, GridP g, FftPlan P, const cpx<T>* __restrict__ spec,
+__device__ __forceinline__ void irfftx_body(dim3 bid, GridP g, const FftPlan& P, const cpx<T>* __restrict__ spec,
                                                 T* __restrict__ out, const double* __restrict__ twd,
                                                 const float* __restrict__ twf, int npair_blk) {
   extern __shared__ unsigned char smem_raw[];
@@ -235,24 +265,37 @@ __device__ __forceinline__ void irfftx_body(dim3 bid, GridP g, FftPlan P, const 
   const int nx = g.nx, nxh = nx / 2 + 1, nyh = g.ny / 2;
   cpx<T>* B = A + npair_blk * nx;
   const int64_t npairs = (int64_t)g.nz * nyh;
-  for (int e = threadIdx.x; e < npair_blk * nx; e += blockDim.x) {
-    const int p = e / nx, l = e % nx;
-    const int64_t gp = (int64_t)bid.x * npair_blk + p;
-    cpx<T> z = {(T)0, (T)0};
-    if (gp < npairs) {
-      const int k = (int)(gp / nyh);
-      const int j0 = 2 * (int)(gp % nyh);
-      const cpx<T>* s0 = spec + ((int64_t)k * g.ny + j0) * nxh;
-      const cpx<T>* s1 = s0 + nxh;
-      if (l < nxh) {
-        const cpx<T> a = s0[l], b = s1[l];
-        z = {a.x - b.y, a.y + b.x};
-      } else {
-        const cpx<T> a = s0[nx - l], b = s1[nx - l];
-        z = {a.x + b.y, -a.y + b.x};
-      }
+  // Hermitian reconstruction of two rows' spectra; loads in batches of four per thread,
+  // all issued before their LDS stores
+  const int total = npair_blk * nx;
+  for (int e0 = 0; e0 < total; e0 += 4 * (int)blockDim.x) {
+    cpx<T> va[4], vb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      const int p = e / nx, l = e % nx;
+      const int64_t gp = (int64_t)bid.x * npair_blk + p;
+      const bool ok = e < total && gp < npairs;
+      const int64_t k = ok ? gp / nyh : 0;
+      const int j0 = ok ? 2 * (int)(gp % nyh) : 0;
+      const int ls = l < nxh ? l : nx - l;
+      const cpx<T>* s0 = spec + (k * g.ny + j0) * nxh;
+      va[b] = s0[ls];
+      vb[b] = s0[nxh + ls];
     }
-    A[e] = z;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      if (e >= total) continue;
+      const int p = e / nx, l = e % nx;
+      const int64_t gp = (int64_t)bid.x * npair_blk + p;
+      cpx<T> z = {(T)0, (T)0};
+      if (gp < npairs) {
+        const cpx<T> a = va[b], bb = vb[b];
+        z = l < nxh ? cpx<T>{a.x - bb.y, a.y + bb.x} : cpx<T>{a.x + bb.y, -a.y + bb.x};
+      }
+      A[e] = z;
+    }
   }
   __syncthreads();
   const int team = blockDim.x / npair_blk;
@@ -289,7 +332,7 @@ __global__ void __launch_bounds__(256) kb_irfftx(BatchMap m) {
 // grid.y covers o.  SOLVE (periodic z only): forward FFT, multiply by
 // 1/(lamx + lamy + lamz) (0 for the zero mode) and the normalisation, inverse FFT.
 template <typename T, int DIR, bool SOLVE>
-__device__ __forceinline__ void fft_lines_body(dim3 bid, FftPlan P, cpx<T>* __restrict__ data, int nl, int64_t lstride,
+__device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T>* __restrict__ data, int nl, int64_t lstride,
                                                    int64_t ostride, int L, const double* __restrict__ twd,
                                                    const float* __restrict__ twf, const double* __restrict__ lamx,
                                                    const double* __restrict__ lamy, const double* __restrict__ lamz,
@@ -297,20 +340,35 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, FftPlan P, cpx<T>* __re
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
   const int N = P.n;
-  cpx<T>* B = A + L * N;
+  const int NP = N + 1;   // padded line stride in LDS (spreads the l-interleaved stores over banks)
+  cpx<T>* B = A + L * NP;
   const int l0 = bid.x * L;
   const int o = bid.y;
   cpx<T>* base = data + (int64_t)o * ostride;
-  for (int e = threadIdx.x; e < L * N; e += blockDim.x) {
-    const int t = e / L, ll = e % L;
-    const int l = l0 + ll;
-    A[ll * N + t] = l < nl ? base[(int64_t)t * lstride + l] : cpx<T>{(T)0, (T)0};
+  // loads in batches of four per thread, all issued before their LDS stores (out-of-range
+  // lanes read element 0 and store zero)
+  const int total = L * N;
+  for (int e0 = 0; e0 < total; e0 += 4 * (int)blockDim.x) {
+    cpx<T> v[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      const int t = e / L, l = l0 + e % L;
+      const bool ok = e < total && l < nl;
+      v[b] = base[ok ? (int64_t)t * lstride + l : 0];
+      if (!ok) v[b] = cpx<T>{(T)0, (T)0};
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      if (e < total) A[(e % L) * NP + e / L] = v[b];
+    }
   }
   __syncthreads();
   const int team = blockDim.x / L;
   const int ll = threadIdx.x / team, lane = threadIdx.x % team;
   const T* tw = twsel<T>(twd, twf);
-  cpx<T>* res = stockham<T, DIR>(A + ll * N, B + ll * N, P, tw, lane, team);
+  cpx<T>* res = stockham<T, DIR>(A + ll * NP, B + ll * NP, P, tw, lane, team);
   if (SOLVE) {
     // res holds the z spectrum of column (l, m = o); o indexes y modes here
     const int l = l0 + ll;
@@ -321,16 +379,16 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, FftPlan P, cpx<T>* __re
       res[t].y = (T)((double)res[t].y * f);
     }
     __syncthreads();
-    cpx<T>* other = (res == A + ll * N) ? B + ll * N : A + ll * N;
+    cpx<T>* other = (res == A + ll * NP) ? B + ll * NP : A + ll * NP;
     res = stockham<T, 1>(res, other, P, tw, lane, team);
   }
   // every team's result lies in the same buffer (A or B)
-  cpx<T>* R = (res == A + ll * N) ? A : B;
+  cpx<T>* R = (res == A + ll * NP) ? A : B;
   __syncthreads();
   for (int e = threadIdx.x; e < L * N; e += blockDim.x) {
     const int t = e / L, l2 = e % L;
     const int l = l0 + l2;
-    if (l < nl) base[(int64_t)t * lstride + l] = R[l2 * N + t];
+    if (l < nl) base[(int64_t)t * lstride + l] = R[l2 * NP + t];
   }
 }
 
@@ -356,108 +414,151 @@ __global__ void __launch_bounds__(256) kb_fft_lines(BatchMap m) {
                                   d.twy, d.twy_f, d.lamx, d.lamy, d.lamz, 1.0);
 }
 
-// ============================================================================ Thomas
-// One thread per (l, m) column: (A_z + lamx(l) + lamy(m)) x = g, g = f_hat/(nx ny).
-// Elimination in double; cp kept in LDS (type C), d' stored in place.  The (0, 0) column
-// is singular: its last unknown is pinned to zero, the first nz-1 rows solved, and the
-// dzf-weighted mean subtracted (done in double in the scratch `zcol`).
-template <typename T, typename C>
-__global__ void k_thomas(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ pa,
-                         const double* __restrict__ pb, const double* __restrict__ pc,
-                         const double* __restrict__ lamx, const double* __restrict__ lamy, double norm,
-                         double* __restrict__ zcol) {
-  extern __shared__ unsigned char smem_raw[];
-  C* cps = reinterpret_cast<C*>(smem_raw);
+// Factorisation of the z systems of every (l, m) column (Sec. 2.2: one tridiagonal system
+// per wavenumber pair), once per grid: the Poisson matrix depends on the geometry only, so
+// c'_k = c_k / p_k and 1/p_k, p_k = b_k + lambda_x(l) + lambda_y(m) - a_k c'_{k-1}, are kept
+// in the workspace ([k][m][l] pairs, FP64).  The singular (0, 0) column is factorised where
+// it is solved.
+__global__ void __launch_bounds__(256) k_thomas_factor(GridP g, const double* __restrict__ pa,
+                                                       const double* __restrict__ pb, const double* __restrict__ pc,
+                                                       const double* __restrict__ lamx,
+                                                       const double* __restrict__ lamy, double2* __restrict__ pfac) {
   const int nxh = g.nx / 2 + 1;
   const int64_t ncol = (int64_t)nxh * g.ny;
   const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (col >= ncol) return;
   const int l = (int)(col % nxh), m = (int)(col / nxh);
-  const int n = g.nz;
-  const int64_t st = ncol;
-  cpx<T>* x = spec + col;
-  C* cp = cps + threadIdx.x;
-  const int cs = blockDim.x;
-  if (l == 0 && m == 0) {
-    // singular column, all in double, scratch in LDS (3 nz doubles after the cp columns)
-    double* z = reinterpret_cast<double*>(smem_raw + (size_t)blockDim.x * n * sizeof(C));
-    const int nn = n - 1;
-    double cprev = 0.0, dprev = 0.0;
-    for (int k = 0; k < nn; ++k) {
-      const double a = pa[k];
-      const double piv = pb[k] - a * cprev;
-      const double cc = pc[k] / piv;
-      const double d = ((double)x[(int64_t)k * st].x * norm - a * dprev) / piv;
-      z[k] = cc;
-      z[n + k] = d;
-      cprev = cc;
-      dprev = d;
-    }
-    double xn = dprev;
-    z[2 * n + nn - 1] = xn;
-    for (int k = nn - 2; k >= 0; --k) {
-      xn = z[n + k] - z[k] * xn;
-      z[2 * n + k] = xn;
-    }
-    z[2 * n + n - 1] = 0.0;
-    double sw = 0.0, sd = 0.0;
-    for (int k = 0; k < n; ++k) {
-      sw += z[2 * n + k] * g.dzf[k + 1];
-      sd += g.dzf[k + 1];
-    }
-    const double mean = sw / sd;
-    for (int k = 0; k < n; ++k) x[(int64_t)k * st] = {(T)(z[2 * n + k] - mean), (T)0};
-    (void)zcol;
-    return;
-  }
+  if (l == 0 && m == 0) return;
   const double lam = lamx[l] + lamy[m];
-  // The loads do not depend on the recurrence: fetch PF levels ahead into registers.
-  constexpr int PF = 8;
-  cpx<T> cur[PF], nxt[PF];
-  for (int t = 0; t < PF; ++t) cur[t] = t < n ? x[(int64_t)t * st] : cpx<T>{(T)0, (T)0};
-  double cprev = 0.0, drx = 0.0, dry = 0.0;
-  for (int k0 = 0; k0 < n; k0 += PF) {
-    for (int t = 0; t < PF; ++t) {
-      const int kk = k0 + PF + t;
-      nxt[t] = kk < n ? x[(int64_t)kk * st] : cpx<T>{(T)0, (T)0};
+  double cprev = 0.0;
+  for (int k = 0; k < g.nz; ++k) {
+    const double a = pa[k];
+    const double rr = 1.0 / ((pb[k] + lam) - a * cprev);
+    const double cc = pc[k] * rr;
+    pfac[(int64_t)k * ncol + col] = make_double2(cc, rr);
+    cprev = cc;
+  }
+}
+
+void launch_thomas_factor(Ctx& c) {
+  const int64_t ncol = (int64_t)(c.g.nx / 2 + 1) * c.g.ny;
+  hipLaunchKernelGGL(k_thomas_factor, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, c.stream, c.g, c.t.pa,
+                     c.t.pb, c.t.pc, c.t.lamx, c.t.lamy, (double2*)c.t.pfac);
+}
+
+// FP64 Thomas solve along z for every (l, m) column with the stored factors, staged
+// through LDS: a block takes TC consecutive columns of the flattened (m, l) index
+// (contiguous in each plane); all threads load the nz x TC complex right-hand sides
+// (scaled by the transform normalisation, held in double) and factor pairs, two threads per
+// column (real and imaginary parts) run the forward and back substitution from LDS, all
+// threads store.  The singular (0, 0) column has its last unknown pinned to zero, the first
+// nz-1 rows solved and the dzf-weighted mean removed.
+template <typename T>
+__global__ void __launch_bounds__(256) k_thomas(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ pa,
+                                                const double* __restrict__ pb, const double* __restrict__ pc,
+                                                const double2* __restrict__ pfac, double norm, int tc) {
+  extern __shared__ double tsm[];
+  const int nxh = g.nx / 2 + 1;
+  const int64_t ncol = (int64_t)nxh * g.ny;
+  const int n = g.nz;
+  const int64_t col0 = (int64_t)blockIdx.x * tc;
+  const int cw = (int)(ncol - col0 < tc ? ncol - col0 : tc);
+  cpx<T>* x = spec + col0;
+  double* fx = tsm;                        // [n][tc][re, im]
+  double* fc = tsm + 2 * (size_t)n * tc;   // [n][tc][c', 1/pivot]
+  double* rows = fc + 2 * (size_t)n * tc;  // a, b, c of the rows
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    rows[e] = pa[e];
+    rows[n + e] = pb[e];
+    rows[2 * n + e] = pc[e];
+  }
+  // loads in batches of TB per thread, all issued before their LDS stores
+  constexpr int TB = 8;
+  const int total = n * tc;
+  for (int e0 = 0; e0 < total; e0 += TB * (int)blockDim.x) {
+    cpx<T> v[TB];
+    double2 w[TB];
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      const int k = e / tc, q = e % tc;
+      const int64_t o = (e < total && q < cw) ? (int64_t)k * ncol + q : 0;
+      v[b] = x[o];
+      w[b] = pfac[col0 + o];
     }
-    for (int t = 0; t < PF; ++t) {
-      const int k = k0 + t;
-      if (k < n) {
-        const double a = pa[k];
-        const double piv = (pb[k] + lam) - a * cprev;
-        const double r = 1.0 / piv;
-        const double cc = pc[k] * r;
-        drx = ((double)cur[t].x * norm - a * drx) * r;
-        dry = ((double)cur[t].y * norm - a * dry) * r;
-        cp[k * cs] = (C)cc;
-        x[(int64_t)k * st] = {(T)drx, (T)dry};
-        cprev = cc;
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      if (e < total) {
+        fx[2 * e] = (double)v[b].x * norm;
+        fx[2 * e + 1] = (double)v[b].y * norm;
+        fc[2 * e] = w[b].x;
+        fc[2 * e + 1] = w[b].y;
       }
     }
-    for (int t = 0; t < PF; ++t) cur[t] = nxt[t];
   }
-  double xr = drx, xi = dry;
-  // backward sweep over k = n-2 .. 0, PF levels fetched ahead
-  for (int t = 0; t < PF; ++t) {
-    const int k = n - 2 - t;
-    cur[t] = k >= 0 ? x[(int64_t)k * st] : cpx<T>{(T)0, (T)0};
-  }
-  for (int k0 = n - 2; k0 >= 0; k0 -= PF) {
-    for (int t = 0; t < PF; ++t) {
-      const int k = k0 - PF - t;
-      nxt[t] = k >= 0 ? x[(int64_t)k * st] : cpx<T>{(T)0, (T)0};
-    }
-    for (int t = 0; t < PF; ++t) {
-      const int k = k0 - t;
-      if (k >= 0) {
-        const double c = (double)cp[k * cs];
-        xr = (double)cur[t].x - c * xr;
-        xi = (double)cur[t].y - c * xi;
-        x[(int64_t)k * st] = {(T)xr, (T)xi};
+  __syncthreads();
+  const double* ra = rows;           // sub-diagonal
+  const double* rb = rows + n;       // diagonal without the eigenvalues
+  const double* rc = rows + 2 * n;   // super-diagonal
+  const int t = threadIdx.x;
+  if (t < 2 * cw) {
+    const int q = t >> 1, r = t & 1;
+    const int64_t cidx = col0 + q;
+    const int fs = 2 * tc;
+    double* f = fx + 2 * q + r;   // row k at f[k fs]
+    const double* cf = fc + 2 * q;   // row k: c' at cf[k fs], 1/pivot at cf[k fs + 1]
+    if (cidx == 0) {
+      if (r == 0) {
+        // singular column: its own factorisation (last unknown pinned), in the c' slots
+        double* cq = fc + 2 * q;
+        const int nn = n - 1;
+        double cprev = 0.0, dprev = 0.0;
+        for (int k = 0; k < nn; ++k) {
+          const double a = ra[k];
+          const double piv = rb[k] - a * cprev;
+          const double cc = rc[k] / piv;
+          const double d = (f[k * fs] - a * dprev) / piv;
+          f[k * fs] = d;
+          cq[k * fs] = cc;
+          cprev = cc;
+          dprev = d;
+        }
+        double xn = dprev;
+        for (int k = nn - 2; k >= 0; --k) {
+          xn = f[k * fs] - cq[k * fs] * xn;
+          f[k * fs] = xn;
+        }
+        f[(n - 1) * fs] = 0.0;
+        double sw = 0.0, sd = 0.0;
+        for (int k = 0; k < n; ++k) {
+          sw += f[k * fs] * g.dzf[k + 1];
+          sd += g.dzf[k + 1];
+        }
+        const double mean = sw / sd;
+        for (int k = 0; k < n; ++k) f[k * fs] -= mean;
+      } else {
+        for (int k = 0; k < n; ++k) f[k * fs] = 0.0;
+      }
+    } else {
+      double d = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < n; ++k) {
+        d = (f[k * fs] - ra[k] * d) * cf[k * fs + 1];
+        f[k * fs] = d;
+      }
+      double xv = d;
+#pragma unroll 8
+      for (int k = n - 2; k >= 0; --k) {
+        xv = f[k * fs] - cf[k * fs] * xv;
+        f[k * fs] = xv;
       }
     }
-    for (int t = 0; t < PF; ++t) cur[t] = nxt[t];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * tc; e += blockDim.x) {
+    const int k = e / tc, q = e % tc;
+    if (q < cw) x[(int64_t)k * ncol + q] = {(T)fx[2 * e], (T)fx[2 * e + 1]};
   }
 }
 
@@ -554,7 +655,7 @@ static void spectral_solve(Ctx& c) {
     const FftPlan P = make_plan(ny);
     const int L = lines_per_block(ny);
     dim3 grid((nxh + L - 1) / L, nz);
-    const size_t sh = 2 * (size_t)L * ny * sizeof(cpx<T>);
+    const size_t sh = 2 * (size_t)L * (ny + 1) * sizeof(cpx<T>);
     LES_LAUNCH(c, "ffty_fwd", 2 * spec_bytes, (k_fft_lines<T, -1, false>), grid, dim3(256), sh, P, sp, nxh, (int64_t)nxh,
                        (int64_t)nxh * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
   }
@@ -562,26 +663,26 @@ static void spectral_solve(Ctx& c) {
     const FftPlan P = make_plan(nz);
     const int L = lines_per_block(nz);
     dim3 grid((nxh + L - 1) / L, ny);
-    const size_t sh = 2 * (size_t)L * nz * sizeof(cpx<T>);
+    const size_t sh = 2 * (size_t)L * (nz + 1) * sizeof(cpx<T>);
     const double norm = 1.0 / ((double)c.g.nx * ny * nz);
     LES_LAUNCH(c, "fftz_solve", 2 * spec_bytes, (k_fft_lines<T, -1, true>), grid, dim3(256), sh, P, sp, nxh, (int64_t)nxh * ny,
                        (int64_t)nxh, L, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy, c.t.lamz, norm);
   } else {
     const int64_t ncol = (int64_t)nxh * ny;
-    int tpb = 64;
-    while (tpb > 16 && (size_t)tpb * nz * sizeof(T) > 65536) tpb /= 2;
-    const size_t sh = (size_t)tpb * nz * sizeof(T) + 3 * (size_t)nz * sizeof(double);
+    // columns per block: the largest power of two <= 32 whose LDS (32 bytes per entry and
+    // the rows) stays within 64 KB
+    int tc = 32;
+    while (tc > 2 && (size_t)nz * (32 * tc + 24) > 65536) tc /= 2;
+    const size_t sh = (size_t)nz * (32 * tc + 24);
     const double norm = 1.0 / ((double)c.g.nx * ny);
-    double* zcol = c.t.zcol;
-    LES_LAUNCH(c, "thomas_z", 2 * spec_bytes, (k_thomas<T, T>), dim3((unsigned)((ncol + tpb - 1) / tpb)), dim3(tpb), sh,
-               c.g, sp,
-                       c.t.pa, c.t.pb, c.t.pc, c.t.lamx, c.t.lamy, norm, zcol);
+    LES_LAUNCH(c, "thomas_z", 2 * spec_bytes, (k_thomas<T>), dim3((unsigned)((ncol + tc - 1) / tc)), dim3(256), sh,
+               c.g, sp, c.t.pa, c.t.pb, c.t.pc, (const double2*)c.t.pfac, norm, tc);
   }
   {
     const FftPlan P = make_plan(ny);
     const int L = lines_per_block(ny);
     dim3 grid((nxh + L - 1) / L, nz);
-    const size_t sh = 2 * (size_t)L * ny * sizeof(cpx<T>);
+    const size_t sh = 2 * (size_t)L * (ny + 1) * sizeof(cpx<T>);
     LES_LAUNCH(c, "ffty_inv", 2 * spec_bytes, (k_fft_lines<T, 1, false>), grid, dim3(256), sh, P, sp, nxh, (int64_t)nxh,
                        (int64_t)nxh * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
   }

@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part,
 // the filter is the identity (index-space extrapolation), filtered-velocity ghosts follow the
 // strain ghost rule, alpha^2 = 4^(2/3) there.
 namespace fused {
-constexpr int TX = 32, TY = 8, NT = TX * TY;
+constexpr int TX = 32, TY = 8, NT = TX * TY, WV = NT / 64;
 constexpr int RX2 = TX + 4, RY2 = TY + 4, N2 = RX2 * RY2;  // halo 2
 constexpr int RX1 = TX + 2, RY1 = TY + 2, N1 = RX1 * RY1;  // halo 1
 }  // namespace fused
@@ -275,7 +275,6 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   __shared__ T vel[3][3][N2];   // [slot][component][R2]
   __shared__ T qb[9][N1];       // centre quantities of the current stage plane
   __shared__ T ut[3][3][N1];    // filtered velocity [slot][component][R1]
-  __shared__ double red[2][NT / 64];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   const int i0 = bid.x * TX, j0 = bid.y * TY;
   const int nz = g.nz;
@@ -428,6 +427,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     const int pk = phys(k);
     // wall ghosts of the filtered velocity (strain ghost rule): fill the free ring slot
     if (!per && (k == 1 || k == nz)) {
+      __syncthreads();   // the free slot may still be read by the previous plane's output
       const int sg = ring3<T>(k == 1 ? 0 : nz + 1);
       const int s1 = ring3<T>(k == 1 ? 1 : nz), s2 = ring3<T>(k == 1 ? 2 : nz - 1);
       for (int e = tid; e < N1; e += NT) {
@@ -474,26 +474,16 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
         mm += wgt2 * (double)M * (double)M;
       }
     }
-    // block sums in a fixed order: wave shuffles, then the waves in order
+    // wave sums in a fixed order (shuffle tree); the waves' partials go out per plane and
+    // are summed over (tile, wave) in a fixed order by the plane reduction
     for (int off = 32; off > 0; off >>= 1) {
       lm += __shfl_down(lm, off, 64);
       mm += __shfl_down(mm, off, 64);
     }
-    const int wave = tid / 64, lane = tid % 64;
-    if (lane == 0) {
-      red[0][wave] = lm;
-      red[1][wave] = mm;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double a = 0.0, b = 0.0;
-      for (int q = 0; q < NT / 64; ++q) {
-        a += red[0][q];
-        b += red[1][q];
-      }
-      const int64_t o = ((int64_t)(k - 1) * ntile + tile) * 2;
-      part[o] = a;
-      part[o + 1] = b;
+    if (tid % 64 == 0) {
+      const int64_t o = ((int64_t)(k - 1) * ntile * WV + tile * WV + tid / 64) * 2;
+      part[o] = lm;
+      part[o + 1] = mm;
     }
   };
   // ---- march: velocity plane p + 1 is committed to LDS at the top of iteration p, the loads
@@ -520,7 +510,6 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       qB[a] = qC[a];
     }
     stage(p);
-    __syncthreads();
     const int k = p - 1;
     if (k >= kb && k <= ke) {
       if (!per && k == 1) {
@@ -531,7 +520,6 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
         output(k, qA, qB, qC);
       }
     }
-    __syncthreads();
   }
   if (!per && ke == nz) {
     // plane nz: the stage of nz + 1 does not exist; its z neighbour is extrapolated
@@ -543,14 +531,14 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256, 2) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
+__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
                                                    int kc, const int* gate) {
   dsm_fused_body<T>(blockIdx, gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
 }
 
 // Batched dynamic model (and its plane / volume reduction) over all boxes of a batch.
 template <typename T>
-__global__ void __launch_bounds__(256, 2) kb_dsm_fused(BatchMap m) {
+__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) kb_dsm_fused(BatchMap m) {
   int box;
   const dim3 bid = batch_bid(m, BK_DSM, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
@@ -562,7 +550,7 @@ __global__ void __launch_bounds__(256) kb_dsm_reduce(BatchMap m) {
   int box;
   const dim3 bid = batch_bid(m, BK_DSMRED, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
-  dsm_reduce_body(bid.x, d.g, d.dsm_part, d.gdim[BK_DSM][0] * d.gdim[BK_DSM][1], d.cs, d.coef, nullptr);
+  dsm_reduce_body(bid.x, d.g, d.dsm_part, d.gdim[BK_DSM][0] * d.gdim[BK_DSM][1] * fused::WV, d.cs, d.coef, nullptr);
 }
 
 template <typename T>
@@ -662,56 +650,29 @@ __device__ inline void centre_rotation(const GridP& g, const T* u, const T* v, c
 // The seven raw inputs of the network at a cell (see les.h): invariants of S/n and O/n,
 // n = sqrt(S_ij S_ij + O_ij O_ij), then y+ and Delta/delta (delta = 1).
 __device__ inline void raw_features(const double s[6], const double o[3], double yplus, double delta, double f[7]) {
-  const double S[3][3] = {{s[0], s[3], s[4]}, {s[3], s[1], s[5]}, {s[4], s[5], s[2]}};
-  const double O[3][3] = {{0.0, o[0], o[1]}, {-o[0], 0.0, o[2]}, {-o[1], -o[2], 0.0}};
-  double ss = 0.0, oo = 0.0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      ss += S[a][b] * S[a][b];
-      oo += O[a][b] * O[a][b];
-    }
+  // closed forms for a symmetric S = (s11 s22 s33 s12 s13 s23) and an antisymmetric O with
+  // upper entries (o12 o13 o23): P = O^2 (symmetric), Q = S^2 (symmetric)
+  const double s11 = s[0], s22 = s[1], s33 = s[2], s12 = s[3], s13 = s[4], s23 = s[5];
+  const double o1 = o[0], o2 = o[1], o3 = o[2];
+  const double ss = s11 * s11 + s22 * s22 + s33 * s33 + 2.0 * (s12 * s12 + s13 * s13 + s23 * s23);
+  const double oo = 2.0 * (o1 * o1 + o2 * o2 + o3 * o3);
   const double nrm = sqrt(ss + oo);
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  double Sh[3][3], Oh[3][3], S2[3][3], O2[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      Sh[a][b] = S[a][b] * inv;
-      Oh[a][b] = O[a][b] * inv;
-    }
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      double x = 0.0, y = 0.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        x += Sh[a][c] * Sh[c][b];
-        y += Oh[a][c] * Oh[c][b];
-      }
-      S2[a][b] = x;
-      O2[a][b] = y;
-    }
-  double t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    t0 += S2[a][a];
-    t1 += O2[a][a];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      t2 += S2[a][c] * Sh[c][a];
-      t3 += O2[a][c] * Sh[c][a];
-      t4 += O2[a][c] * S2[c][a];
-    }
-  }
-  f[0] = t0;
-  f[1] = t1;
-  f[2] = t2;
-  f[3] = t3;
-  f[4] = t4;
+  const double i2 = inv * inv, i3 = i2 * inv, i4 = i2 * i2;
+  const double p00 = -(o1 * o1 + o2 * o2), p11 = -(o1 * o1 + o3 * o3), p22 = -(o2 * o2 + o3 * o3);
+  const double p01 = -o2 * o3, p02 = o1 * o3, p12 = -o1 * o2;
+  const double q00 = s11 * s11 + s12 * s12 + s13 * s13, q11 = s12 * s12 + s22 * s22 + s23 * s23;
+  const double q22 = s13 * s13 + s23 * s23 + s33 * s33;
+  const double q01 = s11 * s12 + s12 * s22 + s13 * s23, q02 = s11 * s13 + s12 * s23 + s13 * s33;
+  const double q12 = s12 * s13 + s22 * s23 + s23 * s33;
+  const double s3 = q00 * s11 + q11 * s22 + q22 * s33 + 2.0 * (q01 * s12 + q02 * s13 + q12 * s23);   // tr S^3
+  const double ps = p00 * s11 + p11 * s22 + p22 * s33 + 2.0 * (p01 * s12 + p02 * s13 + p12 * s23);   // tr O^2 S
+  const double pq = p00 * q00 + p11 * q11 + p22 * q22 + 2.0 * (p01 * q01 + p02 * q02 + p12 * q12);   // tr O^2 S^2
+  f[0] = ss * i2;
+  f[1] = -oo * i2;
+  f[2] = s3 * i3;
+  f[3] = ps * i3;
+  f[4] = pq * i4;
   f[5] = yplus;
   f[6] = delta;
 }
@@ -762,7 +723,7 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
   using tiled::RY;
   using tiled::N1;
   __shared__ Weights Wt;
-  __shared__ unsigned short xs[WAVES][64 * FP];
+  __shared__ __align__(16) unsigned short xs[WAVES][64 * FP];
   __shared__ T vel[3][3][N1];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   const int wave = tid / 64, lane = tid % 64;
@@ -885,7 +846,17 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
       flag = flag || xn < -0.05 || xn > 1.05;
       f[a] = xn;
     }
-    for (int a = 0; a < FP; ++a) xs[wave][lane * FP + a] = (a < F && inside) ? f2bf((float)f[a]) : (unsigned short)0;
+    {
+      // seven bf16 inputs (zero-padded to 16) as two 16-byte LDS stores
+      auto pk = [&](int a) -> unsigned int {
+        if (!inside) return 0u;
+        const fl2 pr = {(float)f[a], a + 1 < F ? (float)f[a + 1] : 0.0f};
+        return __builtin_bit_cast(unsigned int, __builtin_convertvector(pr, bf2));
+      };
+      uint4* dst = reinterpret_cast<uint4*>(&xs[wave][lane * FP]);
+      dst[0] = make_uint4(pk(0), pk(2), pk(4), pk(6));
+      dst[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
     __syncthreads();
     Fwd out;
     forward_wave<false>(Wt, xs[wave], lane, out);
@@ -962,7 +933,7 @@ void launch_eddy_viscosity(Ctx& c) {
     dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + fused::TY - 1) / fused::TY, (g.nz + kc - 1) / kc);
     LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, fused::TY), 0, g,
                (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.t.dsm_part, kc, gate);
-    const int ntile = (int)(grid.x * grid.y);
+    const int ntile = (int)(grid.x * grid.y) * fused::WV;
     LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs,
                learned ? nullptr : c.t.coef, gate);
     if (learned) {
@@ -971,10 +942,11 @@ void launch_eddy_viscosity(Ctx& c) {
         nm.lo[a] = c.mlp_lo[a];
         nm.hi[a] = c.mlp_hi[a];
       }
-      dim3 tgrid((g.nx + tiled::TX - 1) / tiled::TX, (g.ny + tiled::TY - 1) / tiled::TY, (g.nz + kc - 1) / kc);
+      const int mkc = c.mlp_kc;
+      dim3 tgrid((g.nx + tiled::TX - 1) / tiled::TX, (g.ny + tiled::TY - 1) / tiled::TY, (g.nz + mkc - 1) / mkc);
       LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), k_mlp_nut<T>, tgrid, dim3(tiled::TX, tiled::TY), 0, g,
                  (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm, c.t.cs, c.t.dt, c.mlp_cnt,
-                 kc);
+                 mkc);
     }
   }
 }

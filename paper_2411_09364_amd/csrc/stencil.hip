@@ -255,6 +255,8 @@ __device__ void helmholtz_factor_body(const GridP& g, double* hfac, const double
   double* cp_w = hfac + 2 * n;
   double* rp_w = hfac + 3 * n;
   double* qv = hfac + 4 * n;
+  double* a_uv = hfac + 6 * n;
+  double* a_w = hfac + 7 * n;
   if (tid == 0) {
     double cprev = 0.0, dp = 0.0;
     for (int kk = 1; kk <= n; ++kk) {
@@ -268,6 +270,7 @@ __device__ void helmholtz_factor_body(const GridP& g, double* hfac, const double
       const double a = -c * lo, b = 1.0 - c * dg, cc = -c * up;
       const double r = 1.0 / (b - a * cprev);
       rp_uv[kk - 1] = r;
+      a_uv[kk - 1] = a;
       cprev = cc * r;
       cp_uv[kk - 1] = cprev;
       // forward sweep of q = H^-1 1 (bulk-forcing profile, no-slip rows) alongside
@@ -292,85 +295,96 @@ __device__ void helmholtz_factor_body(const GridP& g, double* hfac, const double
       const double a = -c * lo, b = 1.0 - c * dg, cc = -c * up;
       const double r = 1.0 / (b - a * cprev);
       rp_w[kk - 1] = r;
+      a_w[kk - 1] = a;
       cprev = cc * r;
       cp_w[kk - 1] = cprev;
     }
   }
 }
 
-// One thread per (component, j, i) column: forward elimination with the shared factors,
-// back substitution, in place on the right-hand side produced by the predictor.  The
-// wall-model rows take the lagged wall stress (from u^k) as a known flux.
+// CN-z Helmholtz solves (Eq. onestar_imp1d), staged through LDS: a block takes hc
+// consecutive (j, i) columns of one component, all threads load the m x hc right-hand sides
+// produced by the predictor (coalesced along i, held in double), hc threads run the FP64
+// elimination with the shared factors, all threads store.  The wall-model rows take the
+// lagged wall stress (from u^k) as a known flux.
 template <typename T>
 __global__ void __launch_bounds__(256) k_helmholtz(GridP g, T* __restrict__ us, T* __restrict__ vs,
                                                    T* __restrict__ ws, const double* __restrict__ hfac,
                                                    const double* __restrict__ tau, const double* __restrict__ dtp,
-                                                   double gamma, int wallmodel) {
-  const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+                                                   double gamma, int wallmodel, int hc) {
+  extern __shared__ double hsm[];   // [m][hc]
   const int comp = blockIdx.y;
-  if (col >= g.sxy) return;
   const int n = g.nz;
-  const double c = gamma * g.nu * dtp[0] / 2.0;
-  T* x = comp == 0 ? us : (comp == 1 ? vs : ws);
-  const double* cp = hfac + (comp < 2 ? 0 : 2 * n);
-  const double* rp = hfac + (comp < 2 ? n : 3 * n);
   const int m = comp < 2 ? n : n - 1;
   const int64_t s = g.sxy;
-  T* xc = x + s + col;  // plane 1
-  constexpr int PF = 8;
-  T cur[PF], nxt[PF];
-  for (int t = 0; t < PF; ++t) cur[t] = t < m ? xc[(int64_t)t * s] : (T)0;
-  double dp = 0.0;
-  for (int k0 = 0; k0 < m; k0 += PF) {
-    for (int t = 0; t < PF; ++t) {
-      const int kk = k0 + PF + t;
-      nxt[t] = kk < m ? xc[(int64_t)kk * s] : (T)0;
-    }
-    for (int t = 0; t < PF; ++t) {
-      const int kk = k0 + t + 1;   // row index 1..m
-      if (kk <= m) {
-        double r = (double)cur[t];
-        if (comp < 2 && wallmodel) {
-          if (kk == 1) r += c * (-(tau[(comp == 0 ? 0 : 1) * s + col] / g.nu) / g.dzf[1]);
-          if (kk == n) r += c * (-(tau[(comp == 0 ? 2 : 3) * s + col] / g.nu) / g.dzf[n]);
-        }
-        double lo;
-        if (comp < 2) lo = kk == 1 ? 0.0 : 1.0 / (g.dzc[kk - 1] * g.dzf[kk]);
-        else lo = kk == 1 ? 0.0 : 1.0 / (g.dzf[kk] * g.dzc[kk]);
-        dp = (r - (-c * lo) * dp) * rp[kk - 1];
-        xc[(int64_t)(kk - 1) * s] = (T)dp;
-      }
-    }
-    for (int t = 0; t < PF; ++t) cur[t] = nxt[t];
+  const int64_t col0 = (int64_t)blockIdx.x * hc;
+  const int cw = (int)(s - col0 < hc ? s - col0 : hc);
+  T* x = (comp == 0 ? us : (comp == 1 ? vs : ws)) + s + col0;   // plane 1
+  double* fac = hsm + (size_t)m * hc;   // c', 1/pivot, sub-diagonal of this component's rows
+  for (int e = threadIdx.x; e < m; e += blockDim.x) {
+    fac[e] = hfac[(comp < 2 ? 0 : 2 * n) + e];
+    fac[m + e] = hfac[(comp < 2 ? n : 3 * n) + e];
+    fac[2 * m + e] = hfac[(comp < 2 ? 6 * n : 7 * n) + e];
   }
-  double xn = dp;
-  // back substitution over rows m-1 .. 1
-  for (int t = 0; t < PF; ++t) {
-    const int kk = m - 1 - t;
-    cur[t] = kk >= 1 ? xc[(int64_t)(kk - 1) * s] : (T)0;
+  // loads in batches of HB per thread, all issued before their LDS stores
+  constexpr int HB = 8;
+  const int total = m * hc;
+  for (int e0 = 0; e0 < total; e0 += HB * (int)blockDim.x) {
+    T v[HB];
+#pragma unroll
+    for (int b = 0; b < HB; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      const int k = e / hc, q = e % hc;
+      v[b] = (e < total && q < cw) ? x[(int64_t)k * s + q] : (T)0;
+    }
+#pragma unroll
+    for (int b = 0; b < HB; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      if (e < total) hsm[e] = (double)v[b];
+    }
   }
-  for (int k0 = m - 1; k0 >= 1; k0 -= PF) {
-    for (int t = 0; t < PF; ++t) {
-      const int kk = k0 - PF - t;
-      nxt[t] = kk >= 1 ? xc[(int64_t)(kk - 1) * s] : (T)0;
+  __syncthreads();
+  if ((int)threadIdx.x < cw) {
+    const int q = threadIdx.x;
+    const double* cp = fac;
+    const double* rp = fac + m;
+    const double* av = fac + 2 * m;
+    double* col = hsm + q;   // row k at col[k hc]
+    if (comp < 2 && wallmodel) {
+      const double c = gamma * g.nu * dtp[0] / 2.0;
+      col[0] += c * (-(tau[(comp == 0 ? 0 : 1) * s + col0 + q] / g.nu) / g.dzf[1]);
+      col[(n - 1) * hc] += c * (-(tau[(comp == 0 ? 2 : 3) * s + col0 + q] / g.nu) / g.dzf[n]);
     }
-    for (int t = 0; t < PF; ++t) {
-      const int kk = k0 - t;
-      if (kk >= 1) {
-        xn = (double)cur[t] - cp[kk - 1] * xn;
-        xc[(int64_t)(kk - 1) * s] = (T)xn;
-      }
+    double dp = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < m; ++k) {
+      dp = (col[k * hc] - av[k] * dp) * rp[k];
+      col[k * hc] = dp;
     }
-    for (int t = 0; t < PF; ++t) cur[t] = nxt[t];
+    double xn = dp;
+#pragma unroll 8
+    for (int k = m - 2; k >= 0; --k) {
+      xn = col[k * hc] - cp[k] * xn;
+      col[k * hc] = xn;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * hc; e += blockDim.x) {
+    const int k = e / hc, q = e % hc;
+    if (q < cw) x[(int64_t)k * s + q] = (T)hsm[e];
   }
 }
 
 template <typename T>
 void launch_helmholtz(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
-  dim3 block(256), grid((unsigned)((c.g.sxy + 255) / 256), 3);
-  LES_LAUNCH(c, "helmholtz_z", 6.0 * c.g.sxy * c.g.nz * sizeof(T), k_helmholtz<T>, grid, block, 0, c.g, (T*)c.us, (T*)c.vs, (T*)c.wsf, c.t.hfac,
-                     c.t.tau, c.t.dt, G[stage], c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);
+  // columns per block: the largest power of two <= 64 whose rows fit 64 KB of LDS
+  int hc = 64;
+  while (hc > 8 && (size_t)c.g.nz * (hc + 3) * sizeof(double) > 65536) hc /= 2;
+  const size_t sh = (size_t)c.g.nz * (hc + 3) * sizeof(double);
+  dim3 block(256), grid((unsigned)((c.g.sxy + hc - 1) / hc), 3);
+  LES_LAUNCH(c, "helmholtz_z", 6.0 * c.g.sxy * c.g.nz * sizeof(T), k_helmholtz<T>, grid, block, sh, c.g, (T*)c.us,
+             (T*)c.vs, (T*)c.wsf, c.t.hfac, c.t.tau, c.t.dt, G[stage], c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, hc);
 }
 
 // ============================================================================ boundary planes
