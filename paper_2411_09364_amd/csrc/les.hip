@@ -192,9 +192,11 @@ size_t carve(Ctx& c, char* base) {
   c.wsf = take(F * E);
   c.nut = take(F * E);
   c.phi = take(F * E);
-  c.spec = take((size_t)(f.nx / 2 + 1) * f.ny * n * 2 * E);
+  const size_t rq = f.precision == LES_MIXED ? 16 : 8;
+  const size_t nxp = ((size_t)(f.nx / 2 + 1) + rq - 1) / rq * rq;
+  c.spec = take(nxp * f.ny * n * 2 * E);
   // factor pairs of the z systems of every (l, m) column (walls only)
-  t.pfac = (double*)take(f.zbc == LES_ZBC_PERIODIC ? 0 : (size_t)(f.nx / 2 + 1) * f.ny * n * 2 * 8);
+  t.pfac = (double*)take(f.zbc == LES_ZBC_PERIODIC ? 0 : nxp * f.ny * n * 2 * 8);
   return off;
 }
 
@@ -287,6 +289,9 @@ les_status les_init(const les_config* cfg, void* hip_stream, les_ctx** out) {
   g.nz = f.nz;
   g.zbc = f.zbc;
   g.sxy = (int64_t)f.nx * f.ny;
+  // 128-byte spectrum rows: 8 double or 16 float complex values
+  const int rq = f.precision == LES_MIXED ? 16 : 8;
+  g.nxp = ((f.nx / 2 + 1) + rq - 1) / rq * rq;
   g.dx = f.lx / f.nx;
   g.dy = f.ly / f.ny;
   g.rdx = 1.0 / g.dx;

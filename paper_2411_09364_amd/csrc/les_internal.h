@@ -18,6 +18,7 @@ struct GridP {
   int nx, ny, nz;
   int zbc;            // LES_ZBC_*
   int64_t sxy;        // nx * ny
+  int nxp;            // row stride of the spectrum (complex values): nx/2+1 rounded up to 128 bytes
   double dx, dy, rdx, rdy;
   double lz, nu;
   const double* zc;   // [nz+2]

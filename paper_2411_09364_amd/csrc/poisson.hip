@@ -228,8 +228,8 @@ __device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, const FftPlan& P, 
   if (gp >= npairs) return;
   const int k = (int)(gp / nyh);
   const int j0 = 2 * (int)(gp % nyh);
-  cpx<T>* s0 = spec + ((int64_t)k * g.ny + j0) * nxh;
-  cpx<T>* s1 = s0 + nxh;
+  cpx<T>* s0 = spec + ((int64_t)k * g.ny + j0) * g.nxp;
+  cpx<T>* s1 = s0 + g.nxp;
   for (int l = lane; l < nxh; l += team) {
     const cpx<T> a = res[l];
     const cpx<T> b = res[(nx - l) % nx];
@@ -279,9 +279,9 @@ __device__ __forceinline__ void irfftx_body(dim3 bid, GridP g, const FftPlan& P,
       const int64_t k = ok ? gp / nyh : 0;
       const int j0 = ok ? 2 * (int)(gp % nyh) : 0;
       const int ls = l < nxh ? l : nx - l;
-      const cpx<T>* s0 = spec + (k * g.ny + j0) * nxh;
+      const cpx<T>* s0 = spec + (k * g.ny + j0) * g.nxp;
       va[b] = s0[ls];
-      vb[b] = s0[nxh + ls];
+      vb[b] = s0[g.nxp + ls];
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -407,10 +407,10 @@ __global__ void __launch_bounds__(256) kb_fft_lines(BatchMap m) {
   const BoxDesc& d = m.desc[box];
   const int nxh = d.g.nx / 2 + 1;
   if (SOLVE)
-    fft_lines_body<T, DIR, true>(bid, d.pz, (cpx<T>*)d.spec, nxh, (int64_t)nxh * d.g.ny, (int64_t)nxh, d.lz, d.twz,
+    fft_lines_body<T, DIR, true>(bid, d.pz, (cpx<T>*)d.spec, nxh, (int64_t)d.g.nxp * d.g.ny, (int64_t)d.g.nxp, d.lz, d.twz,
                                  d.twz_f, d.lamx, d.lamy, d.lamz, 1.0 / ((double)d.g.nx * d.g.ny * d.g.nz));
   else
-    fft_lines_body<T, DIR, false>(bid, d.py, (cpx<T>*)d.spec, nxh, (int64_t)nxh, (int64_t)nxh * d.g.ny, d.ly,
+    fft_lines_body<T, DIR, false>(bid, d.py, (cpx<T>*)d.spec, nxh, (int64_t)d.g.nxp, (int64_t)d.g.nxp * d.g.ny, d.ly,
                                   d.twy, d.twy_f, d.lamx, d.lamy, d.lamz, 1.0);
 }
 
@@ -424,11 +424,11 @@ __global__ void __launch_bounds__(256) k_thomas_factor(GridP g, const double* __
                                                        const double* __restrict__ lamx,
                                                        const double* __restrict__ lamy, double2* __restrict__ pfac) {
   const int nxh = g.nx / 2 + 1;
-  const int64_t ncol = (int64_t)nxh * g.ny;
+  const int64_t ncol = (int64_t)g.nxp * g.ny;   // padded rows: l >= nx/2+1 are not modes
   const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (col >= ncol) return;
-  const int l = (int)(col % nxh), m = (int)(col / nxh);
-  if (l == 0 && m == 0) return;
+  const int l = (int)(col % g.nxp), m = (int)(col / g.nxp);
+  if ((l == 0 && m == 0) || l >= nxh) return;
   const double lam = lamx[l] + lamy[m];
   double cprev = 0.0;
   for (int k = 0; k < g.nz; ++k) {
@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(256) k_thomas_factor(GridP g, const double* __
 }
 
 void launch_thomas_factor(Ctx& c) {
-  const int64_t ncol = (int64_t)(c.g.nx / 2 + 1) * c.g.ny;
+  const int64_t ncol = (int64_t)c.g.nxp * c.g.ny;
   hipLaunchKernelGGL(k_thomas_factor, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, c.stream, c.g, c.t.pa,
                      c.t.pb, c.t.pc, c.t.lamx, c.t.lamy, (double2*)c.t.pfac);
 }
@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(256) k_thomas(GridP g, cpx<T>* __restrict__ sp
                                                 const double2* __restrict__ pfac, double norm, int tc) {
   extern __shared__ double tsm[];
   const int nxh = g.nx / 2 + 1;
-  const int64_t ncol = (int64_t)nxh * g.ny;
+  const int64_t ncol = (int64_t)g.nxp * g.ny;   // flattened (m, l) over the padded rows
   const int n = g.nz;
   const int64_t col0 = (int64_t)blockIdx.x * tc;
   const int cw = (int)(ncol - col0 < tc ? ncol - col0 : tc);
@@ -508,7 +508,9 @@ __global__ void __launch_bounds__(256) k_thomas(GridP g, cpx<T>* __restrict__ sp
     const int fs = 2 * tc;
     double* f = fx + 2 * q + r;   // row k at f[k fs]
     const double* cf = fc + 2 * q;   // row k: c' at cf[k fs], 1/pivot at cf[k fs + 1]
-    if (cidx == 0) {
+    if ((int)(cidx % g.nxp) >= nxh) {
+      // padding column of a row: not a mode, left as it is
+    } else if (cidx == 0) {
       if (r == 0) {
         // singular column: its own factorisation (last unknown pinned), in the c' slots
         double* cq = fc + 2 * q;
@@ -656,8 +658,8 @@ static void spectral_solve(Ctx& c) {
     const int L = lines_per_block(ny);
     dim3 grid((nxh + L - 1) / L, nz);
     const size_t sh = 2 * (size_t)L * (ny + 1) * sizeof(cpx<T>);
-    LES_LAUNCH(c, "ffty_fwd", 2 * spec_bytes, (k_fft_lines<T, -1, false>), grid, dim3(256), sh, P, sp, nxh, (int64_t)nxh,
-                       (int64_t)nxh * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
+    LES_LAUNCH(c, "ffty_fwd", 2 * spec_bytes, (k_fft_lines<T, -1, false>), grid, dim3(256), sh, P, sp, nxh, (int64_t)c.g.nxp,
+                       (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
   }
   if (c.cfg.zbc == LES_ZBC_PERIODIC) {
     const FftPlan P = make_plan(nz);
@@ -665,17 +667,17 @@ static void spectral_solve(Ctx& c) {
     dim3 grid((nxh + L - 1) / L, ny);
     const size_t sh = 2 * (size_t)L * (nz + 1) * sizeof(cpx<T>);
     const double norm = 1.0 / ((double)c.g.nx * ny * nz);
-    LES_LAUNCH(c, "fftz_solve", 2 * spec_bytes, (k_fft_lines<T, -1, true>), grid, dim3(256), sh, P, sp, nxh, (int64_t)nxh * ny,
-                       (int64_t)nxh, L, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy, c.t.lamz, norm);
+    LES_LAUNCH(c, "fftz_solve", 2 * spec_bytes, (k_fft_lines<T, -1, true>), grid, dim3(256), sh, P, sp, nxh, (int64_t)c.g.nxp * ny,
+                       (int64_t)c.g.nxp, L, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy, c.t.lamz, norm);
   } else {
-    const int64_t ncol = (int64_t)nxh * ny;
+    const int64_t ncol = (int64_t)c.g.nxp * ny;
     // columns per block: the largest power of two <= 32 whose LDS (32 bytes per entry and
     // the rows) stays within 64 KB
     int tc = 32;
     while (tc > 2 && (size_t)nz * (32 * tc + 24) > 65536) tc /= 2;
     const size_t sh = (size_t)nz * (32 * tc + 24);
     const double norm = 1.0 / ((double)c.g.nx * ny);
-    LES_LAUNCH(c, "thomas_z", 2 * spec_bytes, (k_thomas<T>), dim3((unsigned)((ncol + tc - 1) / tc)), dim3(256), sh,
+    LES_LAUNCH(c, "thomas_z", 2 * spec_bytes + (double)nxh * ny * nz * 16, (k_thomas<T>), dim3((unsigned)((ncol + tc - 1) / tc)), dim3(256), sh,
                c.g, sp, c.t.pa, c.t.pb, c.t.pc, (const double2*)c.t.pfac, norm, tc);
   }
   {
@@ -683,8 +685,8 @@ static void spectral_solve(Ctx& c) {
     const int L = lines_per_block(ny);
     dim3 grid((nxh + L - 1) / L, nz);
     const size_t sh = 2 * (size_t)L * (ny + 1) * sizeof(cpx<T>);
-    LES_LAUNCH(c, "ffty_inv", 2 * spec_bytes, (k_fft_lines<T, 1, false>), grid, dim3(256), sh, P, sp, nxh, (int64_t)nxh,
-                       (int64_t)nxh * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
+    LES_LAUNCH(c, "ffty_inv", 2 * spec_bytes, (k_fft_lines<T, 1, false>), grid, dim3(256), sh, P, sp, nxh, (int64_t)c.g.nxp,
+                       (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
   }
 }
 
