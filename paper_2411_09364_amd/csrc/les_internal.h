@@ -30,6 +30,18 @@ struct GridP {
 __host__ __device__ inline int64_t idx3(const GridP& g, int k, int j, int i) {
   return ((int64_t)k * g.ny + j) * g.nx + i;
 }
+// XCD-aware tile order.  Workgroups are dispatched to the 8 XCDs in turn by linear index;
+// when a plane holds a multiple of 8 tiles, XCD x gets the contiguous band of tiles
+// [x n/8, (x+1) n/8) of every plane, so tiles that are neighbours in y, and the same tile
+// in the planes above and below, share that XCD's L2.
+__device__ inline dim3 xcd_tile(dim3 bid, dim3 grid) {
+  const unsigned n = grid.x * grid.y;
+  if (n % 8 != 0) return bid;
+  const unsigned t = bid.y * grid.x + bid.x;
+  const unsigned tt = (t % 8) * (n / 8) + t / 8;
+  return dim3(tt % grid.x, tt / grid.x, bid.z);
+}
+
 __device__ inline int wrap_p(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 __device__ inline int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 

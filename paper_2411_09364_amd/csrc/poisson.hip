@@ -149,61 +149,31 @@ __device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, const FftPlan& P, 
   const int64_t npairs = (int64_t)g.nz * nyh;
   const T scale = MODE == 0 ? (T)(1.0 / (gamma * dtp[0])) : (T)1;
   double bsum = 0.0;
-  // batches of RB elements per thread: every load of the batch is issued before the
-  // arithmetic and the LDS stores (out-of-range lanes read cell 0 and store zero)
-  constexpr int RB = 2;
-  const int total = npair_blk * nx;
-  for (int e0 = 0; e0 < total; e0 += RB * (int)blockDim.x) {
-    T q[RB][2][6];
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
-      const int p = e / nx, i = e % nx;
-      const int64_t gp = (int64_t)bid.x * npair_blk + p;
-      const bool ok = e < total && gp < npairs;
-      const int k = ok ? (int)(gp / nyh) + 1 : 1;
-      const int j0 = ok ? 2 * (int)(gp % nyh) : 0;
-#pragma unroll
+  for (int e = threadIdx.x; e < npair_blk * nx; e += blockDim.x) {
+    const int p = e / nx, i = e % nx;
+    const int64_t gp = (int64_t)bid.x * npair_blk + p;
+    cpx<T> z = {(T)0, (T)0};
+    if (gp < npairs) {
+      const int k = (int)(gp / nyh) + 1;
+      const int j0 = 2 * (int)(gp % nyh);
+      T fv[2];
       for (int r = 0; r < 2; ++r) {
         const int j = j0 + r;
         const int64_t c = idx3(g, k, j, i);
         if (MODE == 0) {
-          q[b][r][0] = us[c];
-          q[b][r][1] = us[idx3(g, k, j, wrap_m(i, nx))];
-          q[b][r][2] = vs[c];
-          q[b][r][3] = vs[idx3(g, k, wrap_m(j, g.ny), i)];
-          q[b][r][4] = ws[c];
-          q[b][r][5] = (k == 1 && g.zbc == LES_ZBC_PERIODIC) ? ws[idx3(g, g.nz, j, i)] : ws[c - g.sxy];
+          const T d = (us[c] - us[idx3(g, k, j, wrap_m(i, nx))]) * (T)g.rdx +
+                      (vs[c] - vs[idx3(g, k, wrap_m(j, g.ny), i)]) * (T)g.rdy +
+                      (ws[c] - ((k == 1 && g.zbc == LES_ZBC_PERIODIC) ? ws[idx3(g, g.nz, j, i)] : ws[c - g.sxy])) *
+                          (T)(1.0 / g.dzf[k]);
+          fv[r] = d * scale;
+          if (bulk_part) bsum += (double)us[c] * g.dzf[k];
         } else {
-          q[b][r][0] = fin[c];
+          fv[r] = fin[c];
         }
       }
+      z = {fv[0], fv[1]};
     }
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
-      if (e >= total) continue;
-      const int p = e / nx;
-      const int64_t gp = (int64_t)bid.x * npair_blk + p;
-      cpx<T> z = {(T)0, (T)0};
-      if (gp < npairs) {
-        const int k = (int)(gp / nyh) + 1;
-        T fv[2];
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          if (MODE == 0) {
-            const T d = (q[b][r][0] - q[b][r][1]) * (T)g.rdx + (q[b][r][2] - q[b][r][3]) * (T)g.rdy +
-                        (q[b][r][4] - q[b][r][5]) * (T)(1.0 / g.dzf[k]);
-            fv[r] = d * scale;
-            if (bulk_part) bsum += (double)q[b][r][0] * g.dzf[k];
-          } else {
-            fv[r] = q[b][r][0];
-          }
-        }
-        z = {fv[0], fv[1]};
-      }
-      A[e] = z;
-    }
+    A[e] = z;
   }
   if (bulk_part) {
     __shared__ double red[256];

@@ -533,7 +533,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
 template <typename T>
 __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
                                                    int kc, const int* gate) {
-  dsm_fused_body<T>(blockIdx, gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
+  dsm_fused_body<T>(xcd_tile(blockIdx, gridDim), gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
 }
 
 // Batched dynamic model (and its plane / volume reduction) over all boxes of a batch.
@@ -678,7 +678,7 @@ __device__ inline void raw_features(const double s[6], const double o[3], double
 }
 
 struct MlpNorm {
-  double lo[7], hi[7];
+  double lo[7], inv[7];   // scaled input = (raw - lo) * inv, inv = 1 / (hi - lo)
 };
 
 template <typename T>
@@ -727,9 +727,10 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
   __shared__ T vel[3][3][N1];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   const int wave = tid / 64, lane = tid % 64;
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const dim3 bid = xcd_tile(blockIdx, gridDim);
+  const int i0 = bid.x * TX, j0 = bid.y * TY;
   const int nz = g.nz;
-  const int kb = 1 + blockIdx.z * kc;
+  const int kb = 1 + bid.z * kc;
   const int ke = min(nz, kb + kc - 1);
   const bool per = g.zbc == LES_ZBC_PERIODIC;
   const bool wm = g.zbc == LES_ZBC_WALLMODEL;
@@ -842,7 +843,7 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
     raw_features(s, o, yplus, sqrt(g.delta2[pk]), f);
     bool flag = false;
     for (int a = 0; a < 7; ++a) {
-      const double xn = (f[a] - nm.lo[a]) / (nm.hi[a] - nm.lo[a]);
+      const double xn = (f[a] - nm.lo[a]) * nm.inv[a];
       flag = flag || xn < -0.05 || xn > 1.05;
       f[a] = xn;
     }
@@ -857,7 +858,8 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
       dst[0] = make_uint4(pk(0), pk(2), pk(4), pk(6));
       dst[1] = make_uint4(0u, 0u, 0u, 0u);
     }
-    __syncthreads();
+    // each wave reads only its own inputs: LDS operations of a wave complete in order
+    __builtin_amdgcn_wave_barrier();
     Fwd out;
     forward_wave<false>(Wt, xs[wave], lane, out);
     const int qq = lane >> 4;
@@ -940,7 +942,7 @@ void launch_eddy_viscosity(Ctx& c) {
       MlpNorm nm;
       for (int a = 0; a < 7; ++a) {
         nm.lo[a] = c.mlp_lo[a];
-        nm.hi[a] = c.mlp_hi[a];
+        nm.inv[a] = 1.0 / (c.mlp_hi[a] - c.mlp_lo[a]);
       }
       const int mkc = c.mlp_kc;
       dim3 tgrid((g.nx + tiled::TX - 1) / tiled::TX, (g.ny + tiled::TY - 1) / tiled::TY, (g.nz + mkc - 1) / mkc);

@@ -21,6 +21,18 @@ Launch3 point_launch(const GridP& g, int planes) {
   return L;
 }
 
+// 32 x 8 tiles for the stencil sweeps (a wave covers two 256-byte rows in FP64).
+Launch3 tile_launch(const GridP& g, int planes) {
+  Launch3 L;
+  const int bx = g.nx >= 32 ? 32 : g.nx;
+  int by = 256 / bx;
+  if (by > 8 && bx == 32) by = 8;
+  if (by > g.ny) by = g.ny;
+  L.block = dim3(bx, by, 1);
+  L.grid = dim3((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, planes);
+  return L;
+}
+
 // nu_t at a cell centre: plane coefficient times the stored field.
 template <typename T>
 __device__ inline T nut_at(const T* nut, const double* coef, const GridP& g, int k, int j, int i) {
@@ -199,8 +211,8 @@ __global__ void __launch_bounds__(256) k_predictor(GridP g, const T* u, const T*
                                                    T* vs, T* ws, const double* dtp, double alpha, double beta,
                                                    double gamma, int use_rprev, int write_r, double* hfac,
                                                    int wallmodel) {
-  predictor_body<T, IMPLICIT>(blockIdx, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta, gamma,
-                              use_rprev, write_r, hfac, wallmodel);
+  predictor_body<T, IMPLICIT>(xcd_tile(blockIdx, gridDim), g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp,
+                              alpha, beta, gamma, use_rprev, write_r, hfac, wallmodel);
 }
 
 // Batched predictor (explicit viscous terms): one launch over all boxes of a batch.
@@ -220,7 +232,7 @@ void launch_predictor(Ctx& c, int stage) {
   static const double A[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
   static const double B[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
   const double G = A[stage] + B[stage];
-  Launch3 L = point_launch(c.g, c.g.nz + (c.cfg.implicit_z ? 1 : 0));
+  Launch3 L = tile_launch(c.g, c.g.nz + (c.cfg.implicit_z ? 1 : 0));
   const int use_rprev = stage > 0;
   const int write_r = stage < 2;
   auto f = c.cfg.implicit_z ? k_predictor<T, true> : k_predictor<T, false>;
@@ -477,7 +489,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_correct(GridP g, const T* us, const T* vs, const T* ws, const T* phi, T* u,
                                                  T* v, T* w, T* p, const double* dtp, const double* qprof,
                                                  double gamma, int implicit) {
-  correct_body<T>(blockIdx, g, us, vs, ws, phi, u, v, w, p, dtp, qprof, gamma, implicit);
+  correct_body<T>(xcd_tile(blockIdx, gridDim), g, us, vs, ws, phi, u, v, w, p, dtp, qprof, gamma, implicit);
 }
 
 template <typename T>
@@ -492,7 +504,7 @@ __global__ void __launch_bounds__(256) kb_correct(BatchMap m, double gamma) {
 template <typename T>
 void launch_correct(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
-  Launch3 L = point_launch(c.g, c.g.nz);
+  Launch3 L = tile_launch(c.g, c.g.nz);
   const double* q = c.cfg.ubulk > 0.0 ? c.t.hfac + 4 * c.g.nz : nullptr;
   LES_LAUNCH(c, "correct", 9.0 * c.g.sxy * c.g.nz * sizeof(T), k_correct<T>, L.grid, L.block, 0, c.g, (const T*)c.us, (const T*)c.vs,
                      (const T*)c.wsf, (const T*)c.phi, (T*)c.u, (T*)c.v, (T*)c.w, (T*)c.p, c.t.dt, q, G[stage],
