@@ -114,6 +114,7 @@ les_status prepare(les_batch* b) {
     d.ly = b->tune_l ? std::min(b->tune_l, pow2_at_most(std::max(1, 2048 / ny))) : fft_lines_per_block(ny);
     d.lz = b->tune_l ? std::min(b->tune_l, pow2_at_most(std::max(1, 2048 / nz))) : fft_lines_per_block(nz);
     d.kc = b->tune_kc ? std::min(b->tune_kc, nz) : c.dsm_kc;
+    d.pkc = c.pred_kc;
     d.sgs = c.cfg.sgs;
     auto set = [&](int kind, int x, int y, int z) {
       d.gdim[kind][0] = x;
@@ -127,6 +128,7 @@ les_status prepare(les_batch* b) {
     set(BK_DSM, (nx + 31) / 32, (ny + 7) / 8, (nz + d.kc - 1) / d.kc);
     set(BK_DSMRED, nz, 1, 1);
     set(BK_CFL, 64, 1, 1);
+    set(BK_PRED, (nx + 31) / 32, (ny + 7) / 8, (nz + d.pkc - 1) / d.pkc);
     b->sh_x = std::max(b->sh_x, 2 * (size_t)d.pbx * nx * 2 * E);
     b->sh_y = std::max(b->sh_y, 2 * (size_t)d.ly * (ny + 1) * 2 * E);
     b->sh_z = std::max(b->sh_z, 2 * (size_t)d.lz * (nz + 1) * 2 * E);
@@ -159,7 +161,7 @@ BatchMap map_of(const les_batch* b) { return BatchMap{b->ddesc, b->dprefix, b->n
 template <typename T>
 void substep_batch(les_batch* b, int stage) {
   const BatchMap m = map_of(b);
-  batch_predictor<T>(b->stream, m, b->totals[BK_POINT], stage);
+  batch_predictor<T>(b->stream, m, b->totals[BK_PRED], stage);
   batch_poisson<T>(b->stream, m, b->totals, b->sh_x, b->sh_y, b->sh_z, stage);
   batch_correct<T>(b->stream, m, b->totals[BK_POINT], stage);
   batch_eddy_viscosity<T>(b->stream, m, b->totals, b->sgs == LES_SGS_DSM, b->sgs == LES_SGS_SMAG);

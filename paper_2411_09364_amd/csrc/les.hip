@@ -182,6 +182,7 @@ size_t carve(Ctx& c, char* base) {
     };
     c.dsm_kc = chunk(512);
     c.mlp_kc = chunk(768);
+    c.pred_kc = chunk(512);   // z-marching predictor: two blocks per CU (FP64)
   }
   t.dsm_part = (double*)take((size_t)2 * n * t.nblk_xy * 4 * 8);
   c.ru = take(F * E);

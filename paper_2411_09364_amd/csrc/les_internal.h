@@ -115,6 +115,7 @@ struct Ctx {
   void* spec = nullptr;   // complex spectrum [nz][ny][nx/2+1]
   int dsm_kc = 8;         // planes per z chunk of the fused dynamic-model kernel
   int mlp_kc = 8;         // planes per z chunk of the learned-closure inference kernel
+  int pred_kc = 8;        // planes per z chunk of the z-marching predictor
   // learned closure
   float* mlp_params = nullptr;   // caller-owned float32 parameters (les_mlp_bind)
   double mlp_lo[7], mlp_hi[7];    // feature ranges for min-max scaling
@@ -185,7 +186,7 @@ Launch3 point_launch(const GridP& g, int planes);
 // ---------------------------------------------------------------------------- batches
 // Kernel kinds of a batched substep; each batched launch covers all boxes, block b of the
 // launch belongs to the box whose prefix range holds b.
-enum BatchKind { BK_POINT = 0, BK_RFFTX, BK_FFTY, BK_FFTZ, BK_DSM, BK_DSMRED, BK_CFL, BK_NKIND };
+enum BatchKind { BK_POINT = 0, BK_RFFTX, BK_FFTY, BK_FFTZ, BK_DSM, BK_DSMRED, BK_CFL, BK_PRED, BK_NKIND };
 
 // Everything a batched kernel needs to run one box (device memory, one per box).
 struct BoxDesc {
@@ -198,6 +199,7 @@ struct BoxDesc {
   int pbx;              // x-row pairs per forward/inverse x block
   int ly, lz;           // lines per y / z FFT block
   int kc;               // planes per dynamic-model chunk
+  int pkc;              // planes per predictor chunk
   int sgs;
   double cs_smag;       // static coefficient (SMAG)
   int gdim[BK_NKIND][3];  // per-kind block grid of this box

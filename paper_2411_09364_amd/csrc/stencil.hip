@@ -40,36 +40,31 @@ __device__ inline T nut_at(const T* nut, const double* coef, const GridP& g, int
 }
 
 // ============================================================================ predictor
+// Neighbourhood of one cell used by the momentum right-hand side.  Suffixes give the offset:
+// ip/im = i +- 1, jp/jm = j +- 1, kp/km = k +- 1 (u, v, w at their faces; n = nu_t and p at
+// centres).
+template <typename T>
+struct Nb {
+  T u0, uip, uim, ujp, ujm, ukp, ukm, ujp_im, ukp_im;
+  T v0, vip, vim, vjp, vjm, vkp, vkm, vjm_ip, vkp_jm;
+  T w0, wip, wim, wjp, wjm, wkp, wkm, wkm_ip, wkm_jp;
+  T n0, nip, nim, njp, njm, nkp, nkm, n_jp_ip, n_jm_ip, n_kp_ip, n_km_ip, n_jp_im, n_kp_jp, n_km_jp, n_kp_im, n_kp_jm;
+  T p0, pip, pjp, pkp;
+};
+
 // R_i = -d(u_i u_j)/dx_j + d(2 nu_t S_ij)/dx_j + nu L u_i (explicit) or with L_xx + L_yy
 // only (CN in z); u* = u + dt (alpha R^k + beta R^{k-1} - gamma G p), or with CN in z the
 // Helmholtz right-hand side u** - gamma nu dt/2 L_zz u^k where
 // u** = u + dt (alpha R^k + beta R^{k-1} - gamma G p) + gamma nu dt L_zz u^k.
+// One cell (plane k) from its neighbourhood b and, when use_rprev, R^{k-1} (rup, rvp, rwp).
 template <typename T, bool IMPLICIT>
-__device__ __forceinline__ void predictor_body(dim3 bid, GridP g, const T* __restrict__ u, const T* __restrict__ v,
-                                                   const T* __restrict__ w, const T* __restrict__ p,
-                                                   const T* __restrict__ nut, const double* __restrict__ coef,
-                                                   T* __restrict__ ru, T* __restrict__ rv, T* __restrict__ rw,
-                                                   T* __restrict__ us, T* __restrict__ vs, T* __restrict__ ws,
-                                                   const double* __restrict__ dtp, double alpha, double beta,
-                                                   double gamma, int use_rprev, int write_r, double* hfac,
-                                                   int wallmodel) {
-  if (IMPLICIT && bid.z == 0) {
-    // the first z slice of blocks is scheduled first: one block computes the shared CN
-    // factorisation of this substep while the others run the stencil
-    __shared__ double fz[2][kMaxNz + 2];
-    if (bid.x == 0 && bid.y == 0)
-      helmholtz_factor_body(g, hfac, dtp, gamma, wallmodel, fz[0], fz[1], threadIdx.y * blockDim.x + threadIdx.x,
-                            blockDim.x * blockDim.y);
-    return;
-  }
-  const int i = bid.x * blockDim.x + threadIdx.x;
-  const int j = bid.y * blockDim.y + threadIdx.y;
-  const int k = IMPLICIT ? bid.z : bid.z + 1;
-  if (i >= g.nx || j >= g.ny) return;
-  const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx);
-  const int jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
+__device__ __forceinline__ void predictor_cell(const Nb<T>& b, const GridP& g, int k, T dt, double alpha,
+                                               double beta, double gamma, bool use_rprev, T rup, T rvp, T rwp,
+                                               T& Ru_out, T& Rv_out, T& Rw_out, T& uo, T& vo, T& wo) {
+  // fused multiply-adds only where an expression asks for one, so that every kernel that
+  // inlines this function rounds identically
+#pragma clang fp contract(on)
   const int kp = k + 1, km = k - 1;
-  const T dt = (T)dtp[0];
   const T rdx = (T)g.rdx, rdy = (T)g.rdy;
   const T rdzf = (T)(1.0 / g.dzf[k]);
   const T rdzc = (T)(1.0 / g.dzc[k]);
@@ -77,154 +72,319 @@ __device__ __forceinline__ void predictor_body(dim3 bid, GridP g, const T* __res
   const T rdzfp = (T)(1.0 / g.dzf[kp]);
   const T nu = (T)g.nu;
   const T h = (T)0.5, q = (T)0.25, two = (T)2;
-#define U(kk, jj, ii) u[idx3(g, kk, jj, ii)]
-#define V(kk, jj, ii) v[idx3(g, kk, jj, ii)]
-#define W(kk, jj, ii) w[idx3(g, kk, jj, ii)]
-#define NU(kk, jj, ii) nut_at(nut, coef, g, kk, jj, ii)
-  const int64_t c0 = idx3(g, k, j, i);
-  const T u0 = u[c0], v0 = v[c0], w0 = w[c0];
-  const T uip = U(k, j, ip), uim = U(k, j, im), ujp = U(k, jp, i), ujm = U(k, jm, i), ukp = U(kp, j, i), ukm = U(km, j, i);
-  const T vip = V(k, j, ip), vim = V(k, j, im), vjp = V(k, jp, i), vjm = V(k, jm, i), vkp = V(kp, j, i), vkm = V(km, j, i);
-  const T wip = W(k, j, ip), wim = W(k, j, im), wjp = W(k, jp, i), wjm = W(k, jm, i), wkp = W(kp, j, i), wkm = W(km, j, i);
-  const T vjm_ip = V(k, jm, ip), wkm_ip = W(km, j, ip), wkm_jp = W(km, jp, i);
-  const T ujp_im = U(k, jp, im), ukp_im = U(kp, j, im), vip_jm = vjm_ip, vkp_jm = V(kp, jm, i);
-  const T uim_jp = ujp_im;
-  const T n0 = NU(k, j, i), nip = NU(k, j, ip), njp = NU(k, jp, i), nkp = NU(kp, j, i);
-  const T nim = NU(k, j, im), njm = NU(k, jm, i), nkm = NU(km, j, i);
-
   // ---------------- u-momentum at (i+1/2, j, k)
   T ax, ay, az, sx, sy, sz, lx, ly, lz;
   {
-    const T fxx_r = (h * (u0 + uip)) * (h * (u0 + uip));
-    const T fxx_l = (h * (uim + u0)) * (h * (uim + u0));
-    const T fxy_t = h * (u0 + ujp) * (h * (v0 + vip));
-    const T fxy_b = h * (ujm + u0) * (h * (vjm + vjm_ip));
-    const T fxz_t = h * (u0 + ukp) * (h * (w0 + wip));
-    const T fxz_b = h * (ukm + u0) * (h * (wkm + wkm_ip));
+    const T fxx_r = (h * (b.u0 + b.uip)) * (h * (b.u0 + b.uip));
+    const T fxx_l = (h * (b.uim + b.u0)) * (h * (b.uim + b.u0));
+    const T fxy_t = h * (b.u0 + b.ujp) * (h * (b.v0 + b.vip));
+    const T fxy_b = h * (b.ujm + b.u0) * (h * (b.vjm + b.vjm_ip));
+    const T fxz_t = h * (b.u0 + b.ukp) * (h * (b.w0 + b.wip));
+    const T fxz_b = h * (b.ukm + b.u0) * (h * (b.wkm + b.wkm_ip));
     ax = (fxx_r - fxx_l) * rdx + (fxy_t - fxy_b) * rdy + (fxz_t - fxz_b) * rdzf;
     // SGS
-    const T t11_r = two * nip * ((uip - u0) * rdx);
-    const T t11_l = two * n0 * ((u0 - uim) * rdx);
-    const T nu12_t = q * (n0 + nip + njp + NU(k, jp, ip));
-    const T e12_t = h * ((ujp - u0) * rdy + (vip - v0) * rdx);
-    const T nu12_b = q * (njm + NU(k, jm, ip) + n0 + nip);
-    const T e12_b = h * ((u0 - ujm) * rdy + (vjm_ip - vjm) * rdx);
-    const T nu13_t = q * (n0 + nip + nkp + NU(kp, j, ip));
-    const T e13_t = h * ((ukp - u0) * rdzc + (wip - w0) * rdx);
-    const T nu13_b = q * (nkm + NU(km, j, ip) + n0 + nip);
-    const T e13_b = h * ((u0 - ukm) * rdzcm + (wkm_ip - wkm) * rdx);
+    const T t11_r = two * b.nip * ((b.uip - b.u0) * rdx);
+    const T t11_l = two * b.n0 * ((b.u0 - b.uim) * rdx);
+    const T nu12_t = q * (b.n0 + b.nip + b.njp + b.n_jp_ip);
+    const T e12_t = h * ((b.ujp - b.u0) * rdy + (b.vip - b.v0) * rdx);
+    const T nu12_b = q * (b.njm + b.n_jm_ip + b.n0 + b.nip);
+    const T e12_b = h * ((b.u0 - b.ujm) * rdy + (b.vjm_ip - b.vjm) * rdx);
+    const T nu13_t = q * (b.n0 + b.nip + b.nkp + b.n_kp_ip);
+    const T e13_t = h * ((b.ukp - b.u0) * rdzc + (b.wip - b.w0) * rdx);
+    const T nu13_b = q * (b.nkm + b.n_km_ip + b.n0 + b.nip);
+    const T e13_b = h * ((b.u0 - b.ukm) * rdzcm + (b.wkm_ip - b.wkm) * rdx);
     sx = (t11_r - t11_l) * rdx + (two * nu12_t * e12_t - two * nu12_b * e12_b) * rdy +
          (two * nu13_t * e13_t - two * nu13_b * e13_b) * rdzf;
-    lx = (uip - two * u0 + uim) * (rdx * rdx) + (ujp - two * u0 + ujm) * (rdy * rdy);
-    lz = ((ukp - u0) * rdzc - (u0 - ukm) * rdzcm) * rdzf;
+    lx = (b.uip - two * b.u0 + b.uim) * (rdx * rdx) + (b.ujp - two * b.u0 + b.ujm) * (rdy * rdy);
+    lz = ((b.ukp - b.u0) * rdzc - (b.u0 - b.ukm) * rdzcm) * rdzf;
   }
   const T lzu = lz;
   T Ru = -ax + sx + nu * (IMPLICIT ? lx : lx + lz);
   // ---------------- v-momentum at (i, j+1/2, k)
   {
-    const T fyx_r = h * (v0 + vip) * (h * (u0 + ujp));
-    const T fyx_l = h * (vim + v0) * (h * (uim + uim_jp));
-    const T fyy_t = (h * (v0 + vjp)) * (h * (v0 + vjp));
-    const T fyy_b = (h * (vjm + v0)) * (h * (vjm + v0));
-    const T fyz_t = h * (v0 + vkp) * (h * (w0 + wjp));
-    const T fyz_b = h * (vkm + v0) * (h * (wkm + wkm_jp));
+    const T fyx_r = h * (b.v0 + b.vip) * (h * (b.u0 + b.ujp));
+    const T fyx_l = h * (b.vim + b.v0) * (h * (b.uim + b.ujp_im));
+    const T fyy_t = (h * (b.v0 + b.vjp)) * (h * (b.v0 + b.vjp));
+    const T fyy_b = (h * (b.vjm + b.v0)) * (h * (b.vjm + b.v0));
+    const T fyz_t = h * (b.v0 + b.vkp) * (h * (b.w0 + b.wjp));
+    const T fyz_b = h * (b.vkm + b.v0) * (h * (b.wkm + b.wkm_jp));
     ay = (fyx_r - fyx_l) * rdx + (fyy_t - fyy_b) * rdy + (fyz_t - fyz_b) * rdzf;
-    const T nu12_r = q * (n0 + nip + njp + NU(k, jp, ip));
-    const T e12_r = h * ((ujp - u0) * rdy + (vip - v0) * rdx);
-    const T nu12_l = q * (nim + n0 + NU(k, jp, im) + njp);
-    const T e12_l = h * ((uim_jp - uim) * rdy + (v0 - vim) * rdx);
-    const T t22_t = two * njp * ((vjp - v0) * rdy);
-    const T t22_b = two * n0 * ((v0 - vjm) * rdy);
-    const T nu23_t = q * (n0 + njp + nkp + NU(kp, jp, i));
-    const T e23_t = h * ((vkp - v0) * rdzc + (wjp - w0) * rdy);
-    const T nu23_b = q * (nkm + NU(km, jp, i) + n0 + njp);
-    const T e23_b = h * ((v0 - vkm) * rdzcm + (wkm_jp - wkm) * rdy);
+    const T nu12_r = q * (b.n0 + b.nip + b.njp + b.n_jp_ip);
+    const T e12_r = h * ((b.ujp - b.u0) * rdy + (b.vip - b.v0) * rdx);
+    const T nu12_l = q * (b.nim + b.n0 + b.n_jp_im + b.njp);
+    const T e12_l = h * ((b.ujp_im - b.uim) * rdy + (b.v0 - b.vim) * rdx);
+    const T t22_t = two * b.njp * ((b.vjp - b.v0) * rdy);
+    const T t22_b = two * b.n0 * ((b.v0 - b.vjm) * rdy);
+    const T nu23_t = q * (b.n0 + b.njp + b.nkp + b.n_kp_jp);
+    const T e23_t = h * ((b.vkp - b.v0) * rdzc + (b.wjp - b.w0) * rdy);
+    const T nu23_b = q * (b.nkm + b.n_km_jp + b.n0 + b.njp);
+    const T e23_b = h * ((b.v0 - b.vkm) * rdzcm + (b.wkm_jp - b.wkm) * rdy);
     sy = (two * nu12_r * e12_r - two * nu12_l * e12_l) * rdx + (t22_t - t22_b) * rdy +
          (two * nu23_t * e23_t - two * nu23_b * e23_b) * rdzf;
-    lx = (vip - two * v0 + vim) * (rdx * rdx) + (vjp - two * v0 + vjm) * (rdy * rdy);
-    lz = ((vkp - v0) * rdzc - (v0 - vkm) * rdzcm) * rdzf;
+    lx = (b.vip - two * b.v0 + b.vim) * (rdx * rdx) + (b.vjp - two * b.v0 + b.vjm) * (rdy * rdy);
+    lz = ((b.vkp - b.v0) * rdzc - (b.v0 - b.vkm) * rdzcm) * rdzf;
   }
   const T lzv = lz;
   T Rv = -ay + sy + nu * (IMPLICIT ? lx : lx + lz);
   // ---------------- w-momentum at (i, j, k+1/2)
   {
-    const T fzx_r = h * (w0 + wip) * (h * (u0 + ukp));
-    const T fzx_l = h * (wim + w0) * (h * (uim + ukp_im));
-    const T fzy_t = h * (w0 + wjp) * (h * (v0 + vkp));
-    const T fzy_b = h * (wjm + w0) * (h * (vjm + vkp_jm));
-    const T fzz_t = (h * (w0 + wkp)) * (h * (w0 + wkp));
-    const T fzz_b = (h * (wkm + w0)) * (h * (wkm + w0));
+    const T fzx_r = h * (b.w0 + b.wip) * (h * (b.u0 + b.ukp));
+    const T fzx_l = h * (b.wim + b.w0) * (h * (b.uim + b.ukp_im));
+    const T fzy_t = h * (b.w0 + b.wjp) * (h * (b.v0 + b.vkp));
+    const T fzy_b = h * (b.wjm + b.w0) * (h * (b.vjm + b.vkp_jm));
+    const T fzz_t = (h * (b.w0 + b.wkp)) * (h * (b.w0 + b.wkp));
+    const T fzz_b = (h * (b.wkm + b.w0)) * (h * (b.wkm + b.w0));
     az = (fzx_r - fzx_l) * rdx + (fzy_t - fzy_b) * rdy + (fzz_t - fzz_b) * rdzc;
-    const T nu13_r = q * (n0 + nip + nkp + NU(kp, j, ip));
-    const T e13_r = h * ((ukp - u0) * rdzc + (wip - w0) * rdx);
-    const T nu13_l = q * (nim + n0 + NU(kp, j, im) + nkp);
-    const T e13_l = h * ((ukp_im - uim) * rdzc + (w0 - wim) * rdx);
-    const T nu23_r = q * (n0 + njp + nkp + NU(kp, jp, i));
-    const T e23_r = h * ((vkp - v0) * rdzc + (wjp - w0) * rdy);
-    const T nu23_l = q * (njm + n0 + NU(kp, jm, i) + nkp);
-    const T e23_l = h * ((vkp_jm - vjm) * rdzc + (w0 - wjm) * rdy);
-    const T t33_t = two * nkp * ((wkp - w0) * rdzfp);
-    const T t33_b = two * n0 * ((w0 - wkm) * rdzf);
+    const T nu13_r = q * (b.n0 + b.nip + b.nkp + b.n_kp_ip);
+    const T e13_r = h * ((b.ukp - b.u0) * rdzc + (b.wip - b.w0) * rdx);
+    const T nu13_l = q * (b.nim + b.n0 + b.n_kp_im + b.nkp);
+    const T e13_l = h * ((b.ukp_im - b.uim) * rdzc + (b.w0 - b.wim) * rdx);
+    const T nu23_r = q * (b.n0 + b.njp + b.nkp + b.n_kp_jp);
+    const T e23_r = h * ((b.vkp - b.v0) * rdzc + (b.wjp - b.w0) * rdy);
+    const T nu23_l = q * (b.njm + b.n0 + b.n_kp_jm + b.nkp);
+    const T e23_l = h * ((b.vkp_jm - b.vjm) * rdzc + (b.w0 - b.wjm) * rdy);
+    const T t33_t = two * b.nkp * ((b.wkp - b.w0) * rdzfp);
+    const T t33_b = two * b.n0 * ((b.w0 - b.wkm) * rdzf);
     sz = (two * nu13_r * e13_r - two * nu13_l * e13_l) * rdx + (two * nu23_r * e23_r - two * nu23_l * e23_l) * rdy +
          (t33_t - t33_b) * rdzc;
-    lx = (wip - two * w0 + wim) * (rdx * rdx) + (wjp - two * w0 + wjm) * (rdy * rdy);
-    lz = ((wkp - w0) * rdzfp - (w0 - wkm) * rdzf) * rdzc;
+    lx = (b.wip - two * b.w0 + b.wim) * (rdx * rdx) + (b.wjp - two * b.w0 + b.wjm) * (rdy * rdy);
+    lz = ((b.wkp - b.w0) * rdzfp - (b.w0 - b.wkm) * rdzf) * rdzc;
   }
   const T lzw = lz;
   T Rw = -az + sz + nu * (IMPLICIT ? lx : lx + lz);
+  const T ta = (T)alpha, tb = (T)beta, tg = (T)gamma;
+  T iu = ta * Ru, iv = ta * Rv, iw = ta * Rw;
+  if (use_rprev) {
+    iu = iu + tb * rup;
+    iv = iv + tb * rvp;
+    iw = iw + tb * rwp;
+  }
+  iu = iu - tg * ((b.pip - b.p0) * rdx);
+  iv = iv - tg * ((b.pjp - b.p0) * rdy);
+  iw = iw - tg * ((b.pkp - b.p0) * rdzc);
+  Ru_out = Ru;
+  Rv_out = Rv;
+  Rw_out = Rw;
+  const bool wall_face = (g.zbc != LES_ZBC_PERIODIC) && (k == g.nz);
+  if (IMPLICIT) {
+    const T cg = tg * nu, ch = tg * nu * dt / two;
+    uo = (b.u0 + dt * (iu + cg * lzu)) - ch * lzu;
+    vo = (b.v0 + dt * (iv + cg * lzv)) - ch * lzv;
+    wo = wall_face ? (T)0 : (b.w0 + dt * (iw + cg * lzw)) - ch * lzw;
+  } else {
+    uo = b.u0 + dt * iu;
+    vo = b.v0 + dt * iv;
+    wo = wall_face ? (T)0 : b.w0 + dt * iw;
+  }
+}
+
+// Point version: one thread per cell, neighbours read from global memory (batched boxes).
+template <typename T, bool IMPLICIT>
+__device__ __forceinline__ void predictor_body(dim3 bid, GridP g, const T* __restrict__ u, const T* __restrict__ v,
+                                               const T* __restrict__ w, const T* __restrict__ p,
+                                               const T* __restrict__ nut, const double* __restrict__ coef,
+                                               T* __restrict__ ru, T* __restrict__ rv, T* __restrict__ rw,
+                                               T* __restrict__ us, T* __restrict__ vs, T* __restrict__ ws,
+                                               const double* __restrict__ dtp, double alpha, double beta,
+                                               double gamma, int use_rprev, int write_r) {
+  const int i = bid.x * blockDim.x + threadIdx.x;
+  const int j = bid.y * blockDim.y + threadIdx.y;
+  const int k = IMPLICIT ? bid.z : bid.z + 1;
+  if (i >= g.nx || j >= g.ny) return;
+  const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx);
+  const int jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
+  const int kp = k + 1, km = k - 1;
+#define U(kk, jj, ii) u[idx3(g, kk, jj, ii)]
+#define V(kk, jj, ii) v[idx3(g, kk, jj, ii)]
+#define W(kk, jj, ii) w[idx3(g, kk, jj, ii)]
+#define NU(kk, jj, ii) nut_at(nut, coef, g, kk, jj, ii)
+  Nb<T> b;
+  b.u0 = U(k, j, i), b.uip = U(k, j, ip), b.uim = U(k, j, im), b.ujp = U(k, jp, i), b.ujm = U(k, jm, i);
+  b.ukp = U(kp, j, i), b.ukm = U(km, j, i), b.ujp_im = U(k, jp, im), b.ukp_im = U(kp, j, im);
+  b.v0 = V(k, j, i), b.vip = V(k, j, ip), b.vim = V(k, j, im), b.vjp = V(k, jp, i), b.vjm = V(k, jm, i);
+  b.vkp = V(kp, j, i), b.vkm = V(km, j, i), b.vjm_ip = V(k, jm, ip), b.vkp_jm = V(kp, jm, i);
+  b.w0 = W(k, j, i), b.wip = W(k, j, ip), b.wim = W(k, j, im), b.wjp = W(k, jp, i), b.wjm = W(k, jm, i);
+  b.wkp = W(kp, j, i), b.wkm = W(km, j, i), b.wkm_ip = W(km, j, ip), b.wkm_jp = W(km, jp, i);
+  b.n0 = NU(k, j, i), b.nip = NU(k, j, ip), b.nim = NU(k, j, im), b.njp = NU(k, jp, i), b.njm = NU(k, jm, i);
+  b.nkp = NU(kp, j, i), b.nkm = NU(km, j, i);
+  b.n_jp_ip = NU(k, jp, ip), b.n_jm_ip = NU(k, jm, ip), b.n_kp_ip = NU(kp, j, ip), b.n_km_ip = NU(km, j, ip);
+  b.n_jp_im = NU(k, jp, im), b.n_kp_jp = NU(kp, jp, i), b.n_km_jp = NU(km, jp, i), b.n_kp_im = NU(kp, j, im);
+  b.n_kp_jm = NU(kp, jm, i);
+  b.p0 = p[idx3(g, k, j, i)], b.pip = p[idx3(g, k, j, ip)], b.pjp = p[idx3(g, k, jp, i)];
+  b.pkp = p[idx3(g, kp, j, i)];
 #undef U
 #undef V
 #undef W
 #undef NU
-  const T ta = (T)alpha, tb = (T)beta, tg = (T)gamma;
-  T iu = ta * Ru, iv = ta * Rv, iw = ta * Rw;
+  const int64_t c0 = idx3(g, k, j, i);
+  T rup = (T)0, rvp = (T)0, rwp = (T)0;
   if (use_rprev) {
-    iu = iu + tb * ru[c0];
-    iv = iv + tb * rv[c0];
-    iw = iw + tb * rw[c0];
+    rup = ru[c0];
+    rvp = rv[c0];
+    rwp = rw[c0];
   }
-  const T p0 = p[c0];
-  iu = iu - tg * ((p[idx3(g, k, j, ip)] - p0) * rdx);
-  iv = iv - tg * ((p[idx3(g, k, jp, i)] - p0) * rdy);
-  iw = iw - tg * ((p[idx3(g, kp, j, i)] - p0) * rdzc);
+  T Ru, Rv, Rw, uo, vo, wo;
+  predictor_cell<T, IMPLICIT>(b, g, k, (T)dtp[0], alpha, beta, gamma, use_rprev != 0, rup, rvp, rwp, Ru, Rv, Rw, uo,
+                              vo, wo);
   if (write_r) {
     ru[c0] = Ru;
     rv[c0] = Rv;
     rw[c0] = Rw;
   }
-  const bool wall_face = (g.zbc != LES_ZBC_PERIODIC) && (k == g.nz);
-  if (IMPLICIT) {
-    const T cg = tg * nu, ch = tg * nu * dt / two;
-    us[c0] = (u0 + dt * (iu + cg * lzu)) - ch * lzu;
-    vs[c0] = (v0 + dt * (iv + cg * lzv)) - ch * lzv;
-    ws[c0] = wall_face ? (T)0 : (w0 + dt * (iw + cg * lzw)) - ch * lzw;
-  } else {
-    us[c0] = u0 + dt * iu;
-    vs[c0] = v0 + dt * iv;
-    ws[c0] = wall_face ? (T)0 : w0 + dt * iw;
+  us[c0] = uo;
+  vs[c0] = vo;
+  ws[c0] = wo;
+}
+
+// z-marching predictor: a 32 x 8 tile walks a chunk of kc planes.  A ring of three planes of
+// u, v, w, nu_t (coefficient applied) and p on the tile + 1 halo sits in LDS; the loads of
+// plane k + 2 are issued right after plane k + 1 is committed and complete under the work
+// on plane k.  With CN in z the first z slice of blocks holds the block that factorises the
+// substep's Helmholtz matrices (the others of that slice return at once).
+namespace zmarch {
+constexpr int TX = 32, TY = 8, NT = TX * TY;
+constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY, NL = (N1 + NT - 1) / NT;
+}  // namespace zmarch
+
+template <typename T, bool IMPLICIT>
+__device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, const T* __restrict__ u,
+                                                  const T* __restrict__ v, const T* __restrict__ w,
+                                                  const T* __restrict__ p, const T* __restrict__ nut,
+                                                  const double* __restrict__ coef, T* __restrict__ ru,
+                                                  T* __restrict__ rv, T* __restrict__ rw, T* __restrict__ us,
+                                                  T* __restrict__ vs, T* __restrict__ ws,
+                                                  const double* __restrict__ dtp, double alpha, double beta,
+                                                  double gamma, int use_rprev, int write_r, int kc, int chunk) {
+  using namespace zmarch;
+  __shared__ T ring[3][5][N1];   // [plane slot][u v w nu p][tile + 1 halo]
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const int i0 = bid.x * TX, j0 = bid.y * TY;
+  const int kb = 1 + chunk * kc;
+  const int ke = min(g.nz, kb + kc - 1);
+  const int64_t sxy = g.sxy;
+  int lofs[NL];
+  for (int r = 0; r < NL; ++r) {
+    const int e = tid + r * NT;
+    int ii = (i0 - 1 + e % RX) % g.nx, jj = (j0 - 1 + e / RX) % g.ny;
+    if (ii < 0) ii += g.nx;
+    if (jj < 0) jj += g.ny;
+    lofs[r] = e < N1 ? jj * g.nx + ii : 0;
+  }
+  T rg[NL][5];
+  auto fetch = [&](int q) {   // planes 0 .. nz+1 are stored (ghosts included)
+    const int64_t base = (int64_t)q * sxy;
+    const T cq = (T)coef[q];
+    for (int r = 0; r < NL; ++r) {
+      if (tid + r * NT < N1) {
+        const int64_t o = base + lofs[r];
+        rg[r][0] = u[o];
+        rg[r][1] = v[o];
+        rg[r][2] = w[o];
+        rg[r][3] = cq * nut[o];
+        rg[r][4] = p[o];
+      }
+    }
+  };
+  auto commit = [&](int q) {
+    const int sl = q % 3;
+    for (int r = 0; r < NL; ++r) {
+      const int e = tid + r * NT;
+      if (e < N1)
+        for (int f = 0; f < 5; ++f) ring[sl][f][e] = rg[r][f];
+    }
+  };
+  fetch(kb - 1);
+  commit(kb - 1);
+  fetch(kb);
+  commit(kb);
+  fetch(kb + 1);
+  const int i = i0 + tx, j = j0 + ty;
+  const bool inside = i < g.nx && j < g.ny;
+  const T dt = (T)dtp[0];
+  for (int k = kb; k <= ke; ++k) {
+    commit(k + 1);
+    __syncthreads();
+    if (k + 2 <= ke + 1) fetch(k + 2);
+    if (inside) {
+      const int sm = (k - 1) % 3, s0 = k % 3, sp = (k + 1) % 3;
+      const int x = tx + 1, y = ty + 1;
+      auto A = [&](int f, int sl, int dy, int dx) -> T { return ring[sl][f][(y + dy) * RX + x + dx]; };
+      Nb<T> b;
+      b.u0 = A(0, s0, 0, 0), b.uip = A(0, s0, 0, 1), b.uim = A(0, s0, 0, -1), b.ujp = A(0, s0, 1, 0);
+      b.ujm = A(0, s0, -1, 0), b.ukp = A(0, sp, 0, 0), b.ukm = A(0, sm, 0, 0), b.ujp_im = A(0, s0, 1, -1);
+      b.ukp_im = A(0, sp, 0, -1);
+      b.v0 = A(1, s0, 0, 0), b.vip = A(1, s0, 0, 1), b.vim = A(1, s0, 0, -1), b.vjp = A(1, s0, 1, 0);
+      b.vjm = A(1, s0, -1, 0), b.vkp = A(1, sp, 0, 0), b.vkm = A(1, sm, 0, 0), b.vjm_ip = A(1, s0, -1, 1);
+      b.vkp_jm = A(1, sp, -1, 0);
+      b.w0 = A(2, s0, 0, 0), b.wip = A(2, s0, 0, 1), b.wim = A(2, s0, 0, -1), b.wjp = A(2, s0, 1, 0);
+      b.wjm = A(2, s0, -1, 0), b.wkp = A(2, sp, 0, 0), b.wkm = A(2, sm, 0, 0), b.wkm_ip = A(2, sm, 0, 1);
+      b.wkm_jp = A(2, sm, 1, 0);
+      b.n0 = A(3, s0, 0, 0), b.nip = A(3, s0, 0, 1), b.nim = A(3, s0, 0, -1), b.njp = A(3, s0, 1, 0);
+      b.njm = A(3, s0, -1, 0), b.nkp = A(3, sp, 0, 0), b.nkm = A(3, sm, 0, 0);
+      b.n_jp_ip = A(3, s0, 1, 1), b.n_jm_ip = A(3, s0, -1, 1), b.n_kp_ip = A(3, sp, 0, 1), b.n_km_ip = A(3, sm, 0, 1);
+      b.n_jp_im = A(3, s0, 1, -1), b.n_kp_jp = A(3, sp, 1, 0), b.n_km_jp = A(3, sm, 1, 0), b.n_kp_im = A(3, sp, 0, -1);
+      b.n_kp_jm = A(3, sp, -1, 0);
+      b.p0 = A(4, s0, 0, 0), b.pip = A(4, s0, 0, 1), b.pjp = A(4, s0, 1, 0), b.pkp = A(4, sp, 0, 0);
+      const int64_t c0 = idx3(g, k, j, i);
+      T rup = (T)0, rvp = (T)0, rwp = (T)0;
+      if (use_rprev) {
+        rup = ru[c0];
+        rvp = rv[c0];
+        rwp = rw[c0];
+      }
+      T Ru, Rv, Rw, uo, vo, wo;
+      predictor_cell<T, IMPLICIT>(b, g, k, dt, alpha, beta, gamma, use_rprev != 0, rup, rvp, rwp, Ru, Rv, Rw, uo,
+                                  vo, wo);
+      if (write_r) {
+        ru[c0] = Ru;
+        rv[c0] = Rv;
+        rw[c0] = Rw;
+      }
+      us[c0] = uo;
+      vs[c0] = vo;
+      ws[c0] = wo;
+    }
+    __syncthreads();
   }
 }
 
 template <typename T, bool IMPLICIT>
-__global__ void __launch_bounds__(256) k_predictor(GridP g, const T* u, const T* v, const T* w, const T* p,
-                                                   const T* nut, const double* coef, T* ru, T* rv, T* rw, T* us,
-                                                   T* vs, T* ws, const double* dtp, double alpha, double beta,
-                                                   double gamma, int use_rprev, int write_r, double* hfac,
-                                                   int wallmodel) {
-  predictor_body<T, IMPLICIT>(xcd_tile(blockIdx, gridDim), g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp,
-                              alpha, beta, gamma, use_rprev, write_r, hfac, wallmodel);
+__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) k_predictor(GridP g, const T* __restrict__ u,
+                                                                        const T* __restrict__ v,
+                                                                        const T* __restrict__ w,
+                                                                        const T* __restrict__ p,
+                                                                        const T* __restrict__ nut,
+                                                                        const double* __restrict__ coef,
+                                                                        T* __restrict__ ru, T* __restrict__ rv,
+                                                                        T* __restrict__ rw, T* __restrict__ us,
+                                                                        T* __restrict__ vs, T* __restrict__ ws,
+                                                                        const double* __restrict__ dtp,
+                                                                        double alpha, double beta, double gamma,
+                                                                        int use_rprev, int write_r, double* hfac,
+                                                                        int wallmodel, int kc) {
+  const dim3 bid = xcd_tile(blockIdx, gridDim);
+  if (IMPLICIT && bid.z == 0) {
+    __shared__ double fz[2][kMaxNz + 2];   // metric copies of the factorisation
+    if (bid.x == 0 && bid.y == 0)
+      helmholtz_factor_body(g, hfac, dtp, gamma, wallmodel, fz[0], fz[1], threadIdx.y * blockDim.x + threadIdx.x,
+                            blockDim.x * blockDim.y);
+    return;
+  }
+  predictor_zm_body<T, IMPLICIT>(bid, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta, gamma,
+                                 use_rprev, write_r, kc, IMPLICIT ? (int)bid.z - 1 : (int)bid.z);
 }
 
-// Batched predictor (explicit viscous terms): one launch over all boxes of a batch.
+// Batched predictor (explicit viscous terms): one launch over all boxes of a batch, the same
+// z-marching body per box.
 template <typename T>
-__global__ void __launch_bounds__(256) kb_predictor(BatchMap m, double alpha, double beta, double gamma,
-                                                    int use_rprev, int write_r) {
+__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) kb_predictor(BatchMap m, double alpha, double beta,
+                                                                         double gamma, int use_rprev, int write_r) {
   int box;
-  const dim3 bid = batch_bid(m, BK_POINT, blockIdx.x, box);
+  const dim3 bid = batch_bid(m, BK_PRED, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
-  predictor_body<T, false>(bid, d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w, (const T*)d.p, (const T*)d.nut,
-                           d.coef, (T*)d.ru, (T*)d.rv, (T*)d.rw, (T*)d.us, (T*)d.vs, (T*)d.wsf, d.dt, alpha, beta,
-                           gamma, use_rprev, write_r, nullptr, 0);
+  predictor_zm_body<T, false>(bid, d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w, (const T*)d.p,
+                              (const T*)d.nut, d.coef, (T*)d.ru, (T*)d.rv, (T*)d.rw, (T*)d.us, (T*)d.vs, (T*)d.wsf,
+                              d.dt, alpha, beta, gamma, use_rprev, write_r, d.pkc, (int)bid.z);
 }
 
 template <typename T>
@@ -232,16 +392,19 @@ void launch_predictor(Ctx& c, int stage) {
   static const double A[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
   static const double B[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
   const double G = A[stage] + B[stage];
-  Launch3 L = tile_launch(c.g, c.g.nz + (c.cfg.implicit_z ? 1 : 0));
+  using namespace zmarch;
+  const int kc = c.pred_kc;
+  const unsigned nch = (unsigned)((c.g.nz + kc - 1) / kc);
+  const dim3 grid((c.g.nx + TX - 1) / TX, (c.g.ny + TY - 1) / TY, nch + (c.cfg.implicit_z ? 1 : 0));
   const int use_rprev = stage > 0;
   const int write_r = stage < 2;
   auto f = c.cfg.implicit_z ? k_predictor<T, true> : k_predictor<T, false>;
   const double pts = (double)c.g.sxy * c.g.nz;
   const double words = 8 + 3 * use_rprev + 3 * write_r;
-  LES_LAUNCH(c, "predictor", words * pts * sizeof(T), f, L.grid, L.block, 0, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
-                     (const T*)c.p, (const T*)c.nut, c.t.coef, (T*)c.ru, (T*)c.rv, (T*)c.rw, (T*)c.us, (T*)c.vs,
-                     (T*)c.wsf, c.t.dt, A[stage], B[stage], G, use_rprev, write_r, c.t.hfac,
-                     c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);
+  LES_LAUNCH(c, "predictor", words * pts * sizeof(T), f, grid, dim3(TX, TY), 0, c.g, (const T*)c.u, (const T*)c.v,
+             (const T*)c.w, (const T*)c.p, (const T*)c.nut, c.t.coef, (T*)c.ru, (T*)c.rv, (T*)c.rw, (T*)c.us,
+             (T*)c.vs, (T*)c.wsf, c.t.dt, A[stage], B[stage], G, use_rprev, write_r, c.t.hfac,
+             c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, kc);
 }
 
 // ============================================================================ CN in z
