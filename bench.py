@@ -154,6 +154,17 @@ def copy_state(torch, dst, src):
     dst.synchronize()
 
 
+def substep_roofline(value, cfgd):
+    """Whole-substep HBM fraction: the minimal-sweep bytes per point and substep (25 words
+    with explicit viscous terms, 34 with Crank-Nicolson in z; 8-byte words in FP64, 4-byte
+    in the mixed mode) times the measured points*substeps/s, against 8 TB/s."""
+    words = 34 if cfgd["implicit_z"] else 25
+    wb = 4 if cfgd["precision"] == 1 else 8
+    gbps = value * 1e6 * words * wb / 1e9
+    return {"bound": "hbm", "alg_bytes_per_point": words * wb, "achieved": round(gbps, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4)}
+
+
 def kernel_report(les, ctx, nsteps):
     """Per-kernel HIP-event timing over nsteps un-captured steps; returns (kernels, dominant)."""
     les.les_timing(ctx, True)
@@ -331,6 +342,7 @@ def solver_line(args, torch, cfgd):
                    "substeps_per_step": 3, "graph": use_graph, "closure": "dynamic Smagorinsky"
                    if cfgd["sgs"] == 3 else "Smagorinsky"},
         "roofline": roof,
+        "substep_roofline": substep_roofline(value, cfgd),
         "kernels": kernels,
         "state_check": {"max_div": diag.max_div, "ubulk": diag.ubulk, "nonfinite": int(diag.nonfinite)},
     }
@@ -467,6 +479,7 @@ def learned_line(args, torch):
         "config": {"workload": cfgd["name"], "grid": [cfgd["nx"], cfgd["ny"], cfgd["nz"]],
                    "substeps_per_step": 3, "graph": use_graph, "closure": "learned (BF16 MFMA) with dynamic fallback"},
         "roofline": roof,
+        "substep_roofline": substep_roofline(thr["learned"][0], cfgd),
         "kernels": kernels,
         "dynamic_value": round(thr["dynamic"][0], 3),
         "dynamic_ms_per_step": round(thr["dynamic"][1], 4),
