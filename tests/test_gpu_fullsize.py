@@ -1,0 +1,185 @@
+"""GPU checks at the benchmark sizes, in the launch configuration the benchmark times
+(device time step slot, three substeps replayed from one hipGraph).
+
+  channel 256 x 128 x 96 FP64 (dynamic model, wall model, CN in z): one full step against
+      the oracle element by element (FP64 1e-12 on the state; the dynamic-model nu_t within
+      the propagated rounding bound of its plane coefficient);
+  the same grid's Poisson solve: residual of D G phi = f evaluated by the oracle's operators;
+  channel 1024 x 512 x 256 mixed precision: one step, properties that hold at any size
+      (divergence at float32 level, flow rate, finite state) and the FP64 library run of the
+      same step within 1e-5 (the FP64 path is oracle-checked above and at small sizes);
+  64-box ensemble (32^3 .. 96^3, FP32): one batched step replayed from the graph, a sample of
+      two boxes of every size against the oracle within the mixed tolerance;
+  degenerate states: fluid at rest stays at rest with a zero dynamic coefficient, a uniform
+      flow stays uniform.
+"""
+import numpy as np
+import pytest
+
+from oracle import substep as S, ops as OO
+from oracle.case import ZBC_PERIODIC, ZBC_WALLMODEL, SGS_DSM
+from synth import box_ensemble, isotropic_field
+from tests.cases import make_pair, initial_fields, rel_err, mean_free, say, dsm_nut_check, round32
+
+pytestmark = pytest.mark.gpu
+TWO_PI = 2 * np.pi
+CHANNEL = dict(nx=256, ny=128, nz=96, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=5e-5,
+               sgs=SGS_DSM, cs=0.17, implicit_z=True, ubulk=1.0)
+
+
+@pytest.fixture(scope="module")
+def les():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2411_09364_amd import les as L
+    return L
+
+
+def test_channel_full_size_step_matches_oracle(les):
+    say("full-size channel step 256x128x96")
+    case, g, cfg = make_pair(**CHANNEL)
+    u, v, w = initial_fields(case, g, 2, "channel")
+    st = S.initial_state(case, g, u, v, w)
+    dt = S.time_step(case, g, st, cfl=0.5)
+    solver = les.Solver(cfg)
+    solver.set_state(u, v, w)
+    solver.nut()
+    solver.set_dt(dt)
+    les.les_step(solver.ctx, True)   # graph replay of the three substeps
+    for k in range(3):
+        st = S.substep(case, g, st, k, dt)
+    I = slice(1, g.nz + 1)
+    gu, gv, gw, gp = solver.fields()
+    errs = dict(u=rel_err(gu, st.u, I), v=rel_err(gv, st.v, I), w=rel_err(gw, st.w, I),
+                p=rel_err(mean_free(gp, g), mean_free(st.p, g), I))
+    say("  " + " ".join(f"{a}={b:.2e}" for a, b in errs.items()))
+    for a, e in errs.items():
+        assert e < 1e-12, (a, e)
+    ok, ratio, bnd = dsm_nut_check(case, g, st, solver.eddy_viscosity())
+    say(f"  nu_t vs allowance: worst ratio {ratio:.3f} (c_s rounding bound {bnd:.2e})")
+    assert ok
+    d, status = solver.diag()
+    assert status == 0 and d.nonfinite == 0
+    assert abs(d.ubulk - 1.0) < 1e-13
+    solver.close()
+
+
+def test_channel_full_size_poisson_residual(les):
+    say("full-size Poisson residual 256x128x96")
+    case, g, cfg = make_pair(**CHANNEL)
+    rng = np.random.Generator(np.random.PCG64(11))
+    f = np.zeros((g.nz + 2, g.ny, g.nx))
+    f[1:g.nz + 1] = rng.standard_normal((g.nz, g.ny, g.nx))
+    I = slice(1, g.nz + 1)
+    # the Neumann problem needs a zero dzf-weighted mean of f
+    f[I] -= np.sum(f[I] * g.dzf[I][:, None, None]) / (np.sum(g.dzf[I]) * g.nx * g.ny)
+    solver = les.Solver(cfg)
+    phi = solver.poisson(f)
+    phi[0], phi[g.nz + 1] = phi[1], phi[g.nz]   # zero-flux wall ghosts
+    gx, gy, gz = OO.gradient(g, phi)
+    U, V, W = (np.zeros_like(phi) for _ in range(3))
+    U[I], V[I], W[I] = gx, gy, gz
+    W[0] = W[g.nz] = 0.0                          # no flux through the walls
+    res = OO.divergence(g, U, V, W) - f[I]
+    rel = np.max(np.abs(res)) / np.max(np.abs(f[I]))
+    say(f"  max |D G phi - f| / max |f| = {rel:.2e}")
+    assert rel < 1e-11
+    solver.close()
+
+
+def test_mixed_full_size_step_properties(les):
+    say("full-size mixed channel step 1024x512x256")
+    cfgd = dict(CHANNEL, nx=1024, ny=512, nz=256, nu=1.6e-5, implicit_z=False)
+    case, g, cfg32 = make_pair(precision=1, **cfgd)
+    _, _, cfg64 = make_pair(precision=0, **cfgd)
+    u, v, w = round32(*initial_fields(case, g, 3, "channel"))
+    runs = []
+    for cfg in (cfg64, cfg32):
+        s = les.Solver(cfg)
+        s.set_state(u, v, w)
+        s.nut()
+        runs.append(s)
+    dt = runs[0].dt(0.5)
+    for s in runs:
+        s.set_dt(dt)
+        les.les_step(s.ctx, True)
+        s.synchronize()
+    d64, st64 = runs[0].diag()
+    d32, st32 = runs[1].diag()
+    say(f"  max|div| fp64 {d64.max_div:.2e} mixed {d32.max_div:.2e}; U_b {d64.ubulk!r} {d32.ubulk!r}")
+    assert st64 == 0 and st32 == 0 and d32.nonfinite == 0
+    assert d64.max_div < 1e-11 and d32.max_div < 1e-3
+    assert abs(d64.ubulk - 1.0) < 1e-13 and abs(d32.ubulk - 1.0) < 1e-6
+    n = g.nz
+    for name, a64, a32 in (("u", runs[0].u, runs[1].u), ("v", runs[0].v, runs[1].v), ("w", runs[0].w, runs[1].w)):
+        ref = float(a64[1:n + 1].abs().max().item())
+        e = float((a32[1:n + 1].double() - a64[1:n + 1]).abs().max().item()) / ref
+        say(f"  {name}: mixed vs FP64 {e:.2e}")
+        assert e < 1e-5, (name, e)
+    for s in runs:
+        s.close()
+
+
+def test_ensemble_full_size_step(les):
+    say("64-box ensemble, one graph-replayed step")
+    ens = box_ensemble(64, seed=5)
+    pairs = [make_pair(e["n"], e["n"], e["n"], TWO_PI, TWO_PI, TWO_PI, nu=e["nu"], sgs=SGS_DSM, cs=0.17,
+                       precision=1) for e in ens]
+    batch = les.Batch([p[2] for p in pairs])
+    fields = []
+    for b, e in enumerate(ens):
+        f = round32(*isotropic_field(e["n"], seed=e["seed"], k0=e["k0"]))
+        fields.append(f)
+        batch.set_state(b, *f)
+    batch.nut()
+    dts = []
+    for b, (case, g, cfg) in enumerate(pairs):
+        st = S.initial_state(case, g, *fields[b])
+        dts.append((S.time_step(case, g, st, cfl=0.5), st))
+    batch.dt(0.5)
+    batch.step(0.0, True)   # cfl = 0: keep the device slots, three substeps from the graph
+    batch.synchronize()
+    sample = []
+    for n in (32, 48, 64, 96):
+        sample += [b for b, e in enumerate(ens) if e["n"] == n][:2]
+    for b in sample:
+        case, g, cfg = pairs[b]
+        d = batch.box_dt(b)
+        st = dts[b][1]
+        for k in range(3):
+            st = S.substep(case, g, st, k, d.dt)
+        gu, gv, gw, gp = batch.fields(b)
+        I = slice(1, g.nz + 1)
+        errs = dict(u=rel_err(gu, st.u, I), v=rel_err(gv, st.v, I), w=rel_err(gw, st.w, I))
+        say(f"  box {b} ({case.nx}^3): " + " ".join(f"{a}={e:.2e}" for a, e in errs.items()))
+        for a, e in errs.items():
+            assert e < 3e-5, (b, a, e)
+    batch.close()
+
+
+@pytest.mark.parametrize("kind", ["rest", "uniform"])
+def test_degenerate_states(les, kind):
+    say("degenerate state", kind)
+    if kind == "rest":
+        cfgd = dict(CHANNEL, nx=64, ny=32, nz=24, ubulk=0.0)
+    else:
+        cfgd = dict(nx=32, ny=32, nz=32, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, zbc=ZBC_PERIODIC, nu=1e-3, sgs=SGS_DSM)
+    case, g, cfg = make_pair(**cfgd)
+    shape = (g.nz + 2, g.ny, g.nx)
+    u = np.zeros(shape) + (0.7 if kind == "uniform" else 0.0)
+    v = np.zeros(shape) + (-0.3 if kind == "uniform" else 0.0)
+    w = np.zeros(shape) + (0.2 if kind == "uniform" else 0.0)
+    solver = les.Solver(cfg)
+    solver.set_state(u, v, w)
+    solver.nut()
+    solver.set_dt(1e-2)
+    les.les_step(solver.ctx, True)
+    gu, gv, gw, gp = solver.fields()
+    I = slice(1, g.nz + 1)
+    assert np.all(np.isfinite(gu[I])) and np.all(np.isfinite(gp[I]))
+    assert np.max(np.abs(gu[I] - u[I])) < 1e-14
+    assert np.max(np.abs(gv[I] - v[I])) < 1e-14
+    assert np.max(np.abs(gw[I] - w[I])) < 1e-14
+    assert np.all(solver.coefficient() == 0.0)
+    assert np.max(np.abs(solver.eddy_viscosity()[I])) == 0.0
+    solver.close()

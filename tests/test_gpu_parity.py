@@ -10,8 +10,9 @@ Tolerances (max |gpu - oracle| / max |oracle| per field, interior planes):
              float32 (relative 6e-8) leaves a spurious divergence that the projection turns
              into a pressure error of order 6e-8 |u|^2 / (gamma_k CFL), independent of how
              small the pressure itself is.
-Sizes span several 64x4 tiles with ragged tails in x and y, radix-3 FFT lengths and
-stretched walls, and stay small enough for the oracle to finish in seconds.
+Sizes span several 32x8 tiles with ragged tails in x and y, radix-3 FFT lengths and
+stretched walls, and stay small enough for the oracle to finish in seconds; the benchmark
+sizes are covered in test_gpu_fullsize.py.
 """
 import numpy as np
 import pytest
