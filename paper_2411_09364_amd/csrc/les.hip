@@ -112,7 +112,10 @@ void build_grid(Ctx& c) {
   c.lamx.resize(f.nx / 2 + 1);
   for (int l = 0; l <= f.nx / 2; ++l) c.lamx[l] = eig(f.nx, dx, l);
   c.lamy.resize(f.ny);
-  for (int m = 0; m < f.ny; ++m) c.lamy[m] = eig(f.ny, dy, m);
+  // y modes m and ny - m share their eigenvalue exactly (mirrored), so their z systems and
+  // factors coincide
+  for (int m = 0; m <= f.ny / 2; ++m) c.lamy[m] = eig(f.ny, dy, m);
+  for (int m = f.ny / 2 + 1; m < f.ny; ++m) c.lamy[m] = c.lamy[f.ny - m];
   c.lamz.assign(n, 0.0);
   if (f.zbc == LES_ZBC_PERIODIC)
     for (int q = 0; q < n; ++q) c.lamz[q] = eig(n, f.lz / n, q);
@@ -196,8 +199,8 @@ size_t carve(Ctx& c, char* base) {
   const size_t rq = f.precision == LES_MIXED ? 16 : 8;
   const size_t nxp = ((size_t)(f.nx / 2 + 1) + rq - 1) / rq * rq;
   c.spec = take(nxp * f.ny * n * 2 * E);
-  // factor pairs of the z systems of every (l, m) column (walls only)
-  t.pfac = (double*)take(f.zbc == LES_ZBC_PERIODIC ? 0 : nxp * f.ny * n * 2 * 8);
+  // factor pairs of the z systems of every (l, m <= ny/2) column (walls only)
+  t.pfac = (double*)take(f.zbc == LES_ZBC_PERIODIC ? 0 : nxp * (f.ny / 2 + 1) * n * 2 * 8);
   return off;
 }
 

@@ -81,7 +81,7 @@ struct Tables {
   double* tau;      // 4*nx*ny wall stresses
   double* utau;     // 4*nx*ny Newton state
   double* dsm_part; // 2*nz*nblk_xy*4 plane partial sums (LM, MM) per tile and wave
-  double* pfac;     // walls: (c', 1/pivot) of every (l, m) z system, [nz][ny][nx/2+1] pairs
+  double* pfac;     // walls: (c', 1/pivot) of the (l, m <= ny/2) z systems, [nz][ny/2+1][nxp] pairs
   int64_t red_n;
   int nblk_xy;      // number of x-y tiles used by plane reductions
 };

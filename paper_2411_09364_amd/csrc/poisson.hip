@@ -387,14 +387,15 @@ __global__ void __launch_bounds__(256) kb_fft_lines(BatchMap m) {
 // Factorisation of the z systems of every (l, m) column (Sec. 2.2: one tridiagonal system
 // per wavenumber pair), once per grid: the Poisson matrix depends on the geometry only, so
 // c'_k = c_k / p_k and 1/p_k, p_k = b_k + lambda_x(l) + lambda_y(m) - a_k c'_{k-1}, are kept
-// in the workspace ([k][m][l] pairs, FP64).  The singular (0, 0) column is factorised where
-// it is solved.
+// in the workspace ([k][m][l] pairs, FP64) for m <= ny/2; mode ny - m has the same
+// eigenvalue and reads the pairs of m.  The singular (0, 0) column is factorised where it is
+// solved.
 __global__ void __launch_bounds__(256) k_thomas_factor(GridP g, const double* __restrict__ pa,
                                                        const double* __restrict__ pb, const double* __restrict__ pc,
                                                        const double* __restrict__ lamx,
                                                        const double* __restrict__ lamy, double2* __restrict__ pfac) {
   const int nxh = g.nx / 2 + 1;
-  const int64_t ncol = (int64_t)g.nxp * g.ny;   // padded rows: l >= nx/2+1 are not modes
+  const int64_t ncol = (int64_t)g.nxp * (g.ny / 2 + 1);   // m <= ny/2; l >= nx/2+1 are padding
   const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (col >= ncol) return;
   const int l = (int)(col % g.nxp), m = (int)(col / g.nxp);
@@ -411,18 +412,18 @@ __global__ void __launch_bounds__(256) k_thomas_factor(GridP g, const double* __
 }
 
 void launch_thomas_factor(Ctx& c) {
-  const int64_t ncol = (int64_t)c.g.nxp * c.g.ny;
+  const int64_t ncol = (int64_t)c.g.nxp * (c.g.ny / 2 + 1);
   hipLaunchKernelGGL(k_thomas_factor, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, c.stream, c.g, c.t.pa,
                      c.t.pb, c.t.pc, c.t.lamx, c.t.lamy, (double2*)c.t.pfac);
 }
 
-// FP64 Thomas solve along z for every (l, m) column with the stored factors, staged
-// through LDS: a block takes TC consecutive columns of the flattened (m, l) index
-// (contiguous in each plane); all threads load the nz x TC complex right-hand sides
-// (scaled by the transform normalisation, held in double) and factor pairs, two threads per
-// column (real and imaginary parts) run the forward and back substitution from LDS, all
-// threads store.  The singular (0, 0) column has its last unknown pinned to zero, the first
-// nz-1 rows solved and the dzf-weighted mean removed.
+// FP64 Thomas solve along z for every (l, m) column with the stored factors, staged through
+// LDS: a block takes TC consecutive columns of the flattened (m, l) index (contiguous in each
+// plane); all threads load the nz x TC complex right-hand sides (scaled by the transform
+// normalisation, held in double) with their factor pairs, two threads per column (real and
+// imaginary parts) run the forward and back substitution from LDS, all threads store.  The
+// singular (0, 0) column has its last unknown pinned to zero, the first nz-1 rows solved and
+// the dzf-weighted mean removed.
 template <typename T>
 __global__ void __launch_bounds__(256) k_thomas(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ pa,
                                                 const double* __restrict__ pb, const double* __restrict__ pc,
@@ -434,6 +435,7 @@ __global__ void __launch_bounds__(256) k_thomas(GridP g, cpx<T>* __restrict__ sp
   const int64_t col0 = (int64_t)blockIdx.x * tc;
   const int cw = (int)(ncol - col0 < tc ? ncol - col0 : tc);
   cpx<T>* x = spec + col0;
+  const int64_t nfac = (int64_t)g.nxp * (g.ny / 2 + 1);   // factor pairs per plane
   double* fx = tsm;                        // [n][tc][re, im]
   double* fc = tsm + 2 * (size_t)n * tc;   // [n][tc][c', 1/pivot]
   double* rows = fc + 2 * (size_t)n * tc;  // a, b, c of the rows
@@ -454,7 +456,10 @@ __global__ void __launch_bounds__(256) k_thomas(GridP g, cpx<T>* __restrict__ sp
       const int k = e / tc, q = e % tc;
       const int64_t o = (e < total && q < cw) ? (int64_t)k * ncol + q : 0;
       v[b] = x[o];
-      w[b] = pfac[col0 + o];
+      const int64_t cc = col0 + (e < total && q < cw ? q : 0);
+      const int64_t m = cc / g.nxp;
+      const int64_t mm = m <= g.ny / 2 ? m : g.ny - m;   // mode ny - m uses the pairs of m
+      w[b] = pfac[((e < total && q < cw) ? (int64_t)k * nfac : 0) + mm * g.nxp + cc % g.nxp];
     }
 #pragma unroll
     for (int b = 0; b < TB; ++b) {
@@ -647,8 +652,9 @@ static void spectral_solve(Ctx& c) {
     while (tc > 2 && (size_t)nz * (32 * tc + 24) > 65536) tc /= 2;
     const size_t sh = (size_t)nz * (32 * tc + 24);
     const double norm = 1.0 / ((double)c.g.nx * ny);
-    LES_LAUNCH(c, "thomas_z", 2 * spec_bytes + (double)nxh * ny * nz * 16, (k_thomas<T>), dim3((unsigned)((ncol + tc - 1) / tc)), dim3(256), sh,
-               c.g, sp, c.t.pa, c.t.pb, c.t.pc, (const double2*)c.t.pfac, norm, tc);
+    LES_LAUNCH(c, "thomas_z", 2 * spec_bytes + (double)nxh * (ny / 2 + 1) * nz * 16, (k_thomas<T>),
+               dim3((unsigned)((ncol + tc - 1) / tc)), dim3(256), sh, c.g, sp, c.t.pa, c.t.pb, c.t.pc,
+               (const double2*)c.t.pfac, norm, tc);
   }
   {
     const FftPlan P = make_plan(ny);

@@ -868,14 +868,21 @@ void launch_set_dt(Ctx& c, double dt) { LES_LAUNCH(c, "set_dt", 0, k_set_dt, dim
 
 // ============================================================================ diagnostics
 // out: [0] max|div|, [1] sum(u dzf), [2] max |vel|, [3] nonfinite count, [4] sum tau_x bot,
-// [5] sum tau_x top.  Single block, fixed-order (used synchronously by les_diag).
+// [5] sum tau_x top.  Stage 1: DIAG_BLOCKS blocks over contiguous chunks of the cells, each a
+// fixed-order tree into 6 partials; stage 2: one block combines them in order (used
+// synchronously by les_diag).
+constexpr int DIAG_BLOCKS = 512;
+
 template <typename T>
-__global__ void k_diag(GridP g, const T* u, const T* v, const T* w, const T* p, const double* tau, double* out) {
+__global__ void __launch_bounds__(256) k_diag_partial(GridP g, const T* u, const T* v, const T* w, const T* p,
+                                                      const double* tau, double* part) {
   __shared__ double sm[6][256];
   double md = 0.0, su = 0.0, mv = 0.0, nf = 0.0, tb = 0.0, tt = 0.0;
   const bool per = g.zbc == LES_ZBC_PERIODIC;
   const int64_t total = (int64_t)g.nz * g.sxy;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+  const int64_t chunk = (total + DIAG_BLOCKS - 1) / DIAG_BLOCKS;
+  const int64_t e0 = blockIdx.x * chunk, e1 = e0 + chunk < total ? e0 + chunk : total;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int k = (int)(e / g.sxy) + 1;
     const int64_t r = e % g.sxy;
     const int i = (int)(r % g.nx), j = (int)(r / g.nx);
@@ -889,11 +896,14 @@ __global__ void k_diag(GridP g, const T* u, const T* v, const T* w, const T* p, 
     if (!isfinite((double)u[c]) || !isfinite((double)v[c]) || !isfinite((double)w[c]) || !isfinite((double)p[c]))
       nf += 1.0;
   }
-  if (!per && tau != nullptr)
-    for (int64_t r = threadIdx.x; r < g.sxy; r += blockDim.x) {
+  if (!per && tau != nullptr) {
+    const int64_t pc = (g.sxy + DIAG_BLOCKS - 1) / DIAG_BLOCKS;
+    const int64_t r0 = blockIdx.x * pc, r1 = r0 + pc < g.sxy ? r0 + pc : g.sxy;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
       tb += tau[r];
       tt += tau[2 * g.sxy + r];
     }
+  }
   double vals[6] = {md, su, mv, nf, tb, tt};
   for (int a = 0; a < 6; ++a) sm[a][threadIdx.x] = vals[a];
   __syncthreads();
@@ -908,13 +918,29 @@ __global__ void k_diag(GridP g, const T* u, const T* v, const T* w, const T* p, 
     }
     __syncthreads();
   }
-  if (threadIdx.x < 6) out[threadIdx.x] = sm[threadIdx.x][0];
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(const double* part, double* out) {
+  if (threadIdx.x != 0) return;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < DIAG_BLOCKS; ++b) {
+    v[0] = fmax(v[0], part[b * 6]);
+    v[1] += part[b * 6 + 1];
+    v[2] = fmax(v[2], part[b * 6 + 2]);
+    v[3] += part[b * 6 + 3];
+    v[4] += part[b * 6 + 4];
+    v[5] += part[b * 6 + 5];
+  }
+  for (int a = 0; a < 6; ++a) out[a] = v[a];
 }
 
 template <typename T>
 void launch_diag(Ctx& c, double* out_dev) {
-  LES_LAUNCH(c, "diag", 0, k_diag<T>, dim3(1), dim3(256), 0, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
-                     (const T*)c.p, c.cfg.zbc == LES_ZBC_WALLMODEL ? c.t.tau : nullptr, out_dev);
+  static_assert(DIAG_BLOCKS * 6 <= 4096, "partials fit the reduction area");
+  LES_LAUNCH(c, "diag", 0, k_diag_partial<T>, dim3(DIAG_BLOCKS), dim3(256), 0, c.g, (const T*)c.u, (const T*)c.v,
+             (const T*)c.w, (const T*)c.p, c.cfg.zbc == LES_ZBC_WALLMODEL ? c.t.tau : nullptr, c.t.red);
+  LES_LAUNCH(c, "diag_final", 0, k_diag_final, dim3(1), dim3(64), 0, c.t.red, out_dev);
 }
 
 // ============================================================================ batch launchers
