@@ -19,6 +19,7 @@ class Case:
     sgs: int = SGS_NONE
     cs: float = 0.17           # Smagorinsky constant for SMAG / SMAG_VD
     implicit_z: bool = False   # Crank-Nicolson in z (Eqs. twostar_imp1d..p_update_imp1d)
+    implicit_3d: bool = False  # Crank-Nicolson in x, y and z (Eqs. twostar_imp3d..p_update_imp3d)
     ubulk: float = 0.0         # > 0: constant flow rate in x (Sec. 4.2)
     h_wm: float = 0.0          # wall-model height, 0 = first cell centre
     kappa: float = 0.41

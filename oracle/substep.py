@@ -73,12 +73,21 @@ def explicit_rhs(case, g, st):
     else:
         ax = ay = az = 0.0
     sx, sy, sz = ops.sgs_divergence(g, u, v, w, st.nut)
+    if case.implicit_3d:
+        # Eq. twostar_imp3d: the explicit part H_i holds advection and SGS stresses only
+        return (-ax + sx, -ay + sy, -az + sz)
     lu, lv, lw = ops.lap_xy(g, u), ops.lap_xy(g, v), ops.lap_xy(g, w)
     if not case.implicit_z:
         lu = lu + ops.lap_z_centre(g, u)
         lv = lv + ops.lap_z_centre(g, v)
         lw = lw + ops.lap_z_face(g, w)
     return (-ax + sx + case.nu * lu, -ay + sy + case.nu * lv, -az + sz + case.nu * lw)
+
+
+def laplacian(g, vel, comp):
+    """Full three-dimensional L of u, v (z-centred) or w (z-faces)."""
+    lz = ops.lap_z_face(g, vel) if comp == 2 else ops.lap_z_centre(g, vel)
+    return ops.lap_xy(g, vel) + lz
 
 
 def predictor(case, g, st, k, dt):
@@ -97,6 +106,8 @@ def predictor(case, g, st, k, dt):
         if case.implicit_z:
             lz = ops.lap_z_face(g, vel) if comp == 2 else ops.lap_z_centre(g, vel)
             incr = incr + c * case.nu * lz
+        elif case.implicit_3d:
+            incr = incr + c * case.nu * laplacian(g, vel, comp)
         out.append(vel[I] + dt * incr)
     return tuple(out), r
 
@@ -148,6 +159,79 @@ def helmholtz_z(case, g, st, ustar2, k, dt):
     return tuple(out)
 
 
+def helmholtz_3d(case, g, st, ustar2, k, dt):
+    """Eq. onestar_imp3d: (1 - gamma nu dt/2 L) u* = u** - gamma nu dt/2 L u^k with the full
+    Laplacian, solved with the Poisson solver's method (Sec. 2.2): Fourier transforms in x
+    and y, then per wavenumber pair (l, m) the z system with the diagonal shifted by
+    -c (lambda_x(l) + lambda_y(m)), c = gamma nu dt/2, by the Thomas algorithm in FP64 (an
+    FFT in z as well when z is periodic).  Boundary rows as in helmholtz_z: u, v no-slip
+    (ghost -x_1 folded into the diagonal) or wall model (wall-stress flux from u^k on the
+    right-hand side); w zero on the wall faces."""
+    n = g.nz
+    c = GAMMA[k] * case.nu * dt / 2.0
+    lam = poisson.eigenvalues(g.ny, g.dy)[:, None] + poisson.eigenvalues(g.nx, g.dx)[None, :]
+    out = []
+    for comp in range(3):
+        vel = (st.u, st.v, st.w)[comp]
+        rhs = ustar2[comp] - c * laplacian(g, vel, comp)
+        if case.zbc == ZBC_PERIODIC:
+            lzv = poisson.eigenvalues(n, g.lz / n)
+            spec = np.fft.fftn(rhs, axes=(0, 1, 2))
+            spec = spec / (1.0 - c * (lzv[:, None, None] + lam[None, :, :]))
+            out.append(np.real(np.fft.ifftn(spec, axes=(0, 1, 2))))
+            continue
+        if comp < 2:
+            lo = np.array([1.0 / (g.dzc[kk - 1] * g.dzf[kk]) for kk in range(1, n + 1)])
+            up = np.array([1.0 / (g.dzc[kk] * g.dzf[kk]) for kk in range(1, n + 1)])
+            dg = -(lo + up)
+            rhs = rhs.copy()
+            if case.zbc == ZBC_WALLMODEL:
+                txb, tyb, txt, tyt = st.tau
+                tb, tt = (txb, txt) if comp == 0 else (tyb, tyt)
+                dg[0] += lo[0]
+                dg[n - 1] += up[n - 1]
+                rhs[0] = rhs[0] + c * (-(tb / case.nu) / g.dzf[1])
+                rhs[n - 1] = rhs[n - 1] + c * (-(tt / case.nu) / g.dzf[n])
+            else:
+                dg[0] -= lo[0]
+                dg[n - 1] -= up[n - 1]
+            lo[0] = 0.0
+            up[n - 1] = 0.0
+            m = n
+        else:
+            m = n - 1
+            lo = np.array([1.0 / (g.dzf[kk] * g.dzc[kk]) for kk in range(1, m + 1)])
+            up = np.array([1.0 / (g.dzf[kk + 1] * g.dzc[kk]) for kk in range(1, m + 1)])
+            dg = -(lo + up)
+            lo[0] = 0.0
+            up[m - 1] = 0.0
+        spec = np.fft.fft2(rhs[:m], axes=(1, 2))
+        diag = 1.0 - c * dg[:, None, None] - c * lam[None, :, :]
+        sol = np.zeros_like(rhs)
+        sol[:m] = np.real(np.fft.ifft2(_tridiag_columns(-c * lo, diag, -c * up, spec), axes=(1, 2)))
+        out.append(sol)
+    return tuple(out)
+
+
+def _tridiag_columns(lo, dg, up, rhs):
+    """Thomas algorithm for every column of rhs[k, m, l] with a per-column diagonal
+    dg[k, m, l] and shared off-diagonals lo[k], up[k]."""
+    n = rhs.shape[0]
+    cp = np.zeros(dg.shape)
+    dp = np.zeros(rhs.shape, dtype=rhs.dtype)
+    cp[0] = up[0] / dg[0]
+    dp[0] = rhs[0] / dg[0]
+    for k in range(1, n):
+        m = dg[k] - lo[k] * cp[k - 1]
+        cp[k] = up[k] / m
+        dp[k] = (rhs[k] - lo[k] * dp[k - 1]) / m
+    x = np.zeros(rhs.shape, dtype=rhs.dtype)
+    x[n - 1] = dp[n - 1]
+    for k in range(n - 2, -1, -1):
+        x[k] = dp[k] - cp[k] * x[k + 1]
+    return x
+
+
 def _tridiag(lo, dg, up, rhs):
     """Thomas algorithm per column for rows lo_k x_{k-1} + dg_k x_k + up_k x_{k+1} = rhs_k."""
     n = rhs.shape[0]
@@ -194,6 +278,9 @@ def project(case, g, st, ustar, k, dt):
     p[I] = st.p[I] + phi[I]
     if case.implicit_z:
         p[I] = p[I] - gk * case.nu * dt / 2.0 * ops.lap_z_centre(g, phi)
+    elif case.implicit_3d:
+        # Eq. p_update_imp3d
+        p[I] = p[I] - gk * case.nu * dt / 2.0 * (ops.lap_xy(g, phi) + ops.lap_z_centre(g, phi))
     return u, v, w, p, phi
 
 
@@ -211,7 +298,7 @@ def bulk_profile(case, g, k, dt):
     Helmholtz solve, so q = H^-1 1 with H the same tridiagonal matrix as the u rows of
     helmholtz_z (no-slip rows; wall-model rows have zero-flux form and give q = 1)."""
     n = g.nz
-    if not case.implicit_z or case.zbc != ZBC_NOSLIP:
+    if not (case.implicit_z or case.implicit_3d) or case.zbc != ZBC_NOSLIP:
         return np.ones(n)
     c = GAMMA[k] * case.nu * dt / 2.0
     lo = np.array([1.0 / (g.dzc[kk - 1] * g.dzf[kk]) for kk in range(1, n + 1)])
@@ -245,6 +332,8 @@ def substep(case, g, st, k, dt):
     ustar, r = predictor(case, g, st, k, dt)
     if case.implicit_z:
         ustar = helmholtz_z(case, g, st, ustar, k, dt)
+    elif case.implicit_3d:
+        ustar = helmholtz_3d(case, g, st, ustar, k, dt)
     u, v, w, p, _ = project(case, g, st, ustar, k, dt)
     force_bulk(case, g, u, k, dt)
     new = State(u, v, w, p, rprev=r, utau=st.utau, tau=st.tau)
@@ -265,15 +354,17 @@ def time_step(case, g, st, cfl=0.5, visc_safety=0.95):
     convective limit cfl / max(|u|/dx + |v|/dy + |w|/dzf) over the face values sharing an
     index, viscous limit visc_safety * 2.51 / (4 max(nu + nu_t) (dx^-2 + dy^-2 [+ dz_min^-2]))
     (2.51: the RK3 stability bound on the negative real axis; the z term is dropped with CN
-    in z).  Returns min of the two."""
+    in z).  R30: with CN in all directions the molecular viscosity is implicit and only the
+    explicit SGS viscosity limits, in all three directions (no limit where nu_t = 0).
+    Returns min of the two."""
     n = g.nz
     I = slice(1, n + 1)
     dzf = g.dzf[I][:, None, None]
     conv = np.max(np.abs(st.u[I]) / g.dx + np.abs(st.v[I]) / g.dy + np.abs(st.w[I]) / dzf)
-    numax = case.nu + max(0.0, float(np.max(st.nut[I])))
+    numax = (0.0 if case.implicit_3d else case.nu) + max(0.0, float(np.max(st.nut[I])))
     s = 1.0 / g.dx ** 2 + 1.0 / g.dy ** 2
     if not case.implicit_z:
         s += 1.0 / np.min(g.dzf[I]) ** 2
-    dt_v = visc_safety * 2.51 / (4.0 * numax * s)
+    dt_v = visc_safety * 2.51 / (4.0 * numax * s) if numax > 0.0 else np.inf
     dt_c = cfl / conv if conv > 0.0 else np.inf
     return min(dt_c, dt_v)

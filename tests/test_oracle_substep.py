@@ -187,3 +187,129 @@ def test_time_step_limits():
     case2 = Case(n, n, n, 2 * np.pi, 2 * np.pi, 2 * np.pi, zbc=ZBC_PERIODIC, nu=10.0)
     st2 = S.initial_state(case2, g, np.zeros_like(u), np.zeros_like(u), np.zeros_like(u))
     assert abs(S.time_step(case2, g, st2) - 0.95 * 2.51 / (4 * 10.0 * 3 / g.dx ** 2)) < 1e-15
+
+
+@pytest.mark.parametrize("comp,zbc", [(0, ZBC_NOSLIP), (1, ZBC_NOSLIP), (2, ZBC_PERIODIC)])
+def test_cn_3d_eigen_ratio(comp, zbc):
+    """CN in all directions (Eqs. twostar_imp3d, onestar_imp3d): a divergence-free mode that
+    is a discrete eigenfunction of the full viscous operator (Fourier in the periodic
+    directions, an eigenvector of the no-slip L_zz found with numpy.linalg.eig) is multiplied
+    by (1 + gamma z/2)/(1 - gamma z/2) per substep, z = nu (lambda_x + lambda_y + mu) dt.
+    u varies in y and z, v in x and z (both divergence-free), w in x and y with periodic z."""
+    nx, ny, nz = 8, 6, 10
+    per = zbc == ZBC_PERIODIC
+    case = Case(nx, ny, nz, 1.0, 1.5, 2.0, zbc=zbc, beta=0.0 if per else 1.3, nu=0.02,
+                implicit_3d=True, advection=False)
+    g = Grid(case)
+    if per:
+        prof, mu = np.ones(nz), 0.0
+    else:
+        A = np.zeros((nz, nz))
+        for c in range(nz):
+            a = np.zeros((nz + 2, 1, 1))
+            a[c + 1] = 1.0
+            a[0], a[nz + 1] = -a[1], -a[nz]
+            A[:, c] = S.ops.lap_z_centre(g, a)[:, 0, 0]
+        ev, vec = np.linalg.eig(A)
+        q = np.argsort(np.abs(ev))[1]
+        prof, mu = np.real(vec[:, q]), float(np.real(ev[q]))
+    x = (np.arange(nx) + (1.0 if comp == 0 else 0.5)) * g.dx
+    y = (np.arange(ny) + (1.0 if comp == 1 else 0.5)) * g.dy
+    lam = 0.0
+    shape = (nz + 2, ny, nx)
+    fld = np.zeros(shape)
+    if comp == 0:     # u(y, z)
+        fld[1:nz + 1] = prof[:, None, None] * np.cos(2 * np.pi * 2 * y / case.ly)[None, :, None]
+        lam = -(4 / g.dy ** 2) * np.sin(np.pi * 2 / ny) ** 2
+    elif comp == 1:   # v(x, z)
+        fld[1:nz + 1] = prof[:, None, None] * np.sin(2 * np.pi * 3 * x / case.lx)[None, None, :]
+        lam = -(4 / g.dx ** 2) * np.sin(np.pi * 3 / nx) ** 2
+    else:             # w(x, y), constant in periodic z
+        fld[1:nz + 1] = (np.cos(2 * np.pi * x / case.lx)[None, None, :] * np.sin(2 * np.pi * y / case.ly)[None, :, None])
+        lam = -(4 / g.dx ** 2) * np.sin(np.pi / nx) ** 2 - (4 / g.dy ** 2) * np.sin(np.pi / ny) ** 2
+    vel = [np.zeros(shape), np.zeros(shape), np.zeros(shape)]
+    vel[comp] = fld
+    st = S.initial_state(case, g, *vel)
+    dt = 0.9
+    ratio = 1.0
+    for k in range(3):
+        st = S.substep(case, g, st, k, dt)
+        z = case.nu * (lam + mu) * dt
+        ratio *= (1 + S.GAMMA[k] * z / 2) / (1 - S.GAMMA[k] * z / 2)
+        got = (st.u, st.v, st.w)[comp]
+        assert np.allclose(got[1:nz + 1], ratio * fld[1:nz + 1], rtol=0, atol=1e-13)
+        for other in range(3):
+            if other != comp:
+                assert np.max(np.abs((st.u, st.v, st.w)[other][1:nz + 1])) < 1e-14
+
+
+def test_cn_3d_reduces_to_cn_z_for_z_profiles():
+    """With no variation in x and y only the (0, 0) Fourier mode carries the field, and the
+    fully implicit scheme takes the same steps as CN in z (to roundoff) on a wall-modelled
+    channel profile with the dynamic model."""
+    nz = 12
+    kw = dict(zbc=ZBC_WALLMODEL, beta=1.4, nu=5e-4, sgs=SGS_DSM, ubulk=1.0)
+    c1 = Case(8, 4, nz, 2.0, 1.0, 2.0, implicit_z=True, **kw)
+    c3 = Case(8, 4, nz, 2.0, 1.0, 2.0, implicit_3d=True, **kw)
+    g = Grid(c1)
+    u = np.zeros((nz + 2, 4, 8))
+    zc = g.zc[1:nz + 1]
+    u[1:nz + 1] = (1.5 * (1 - (zc - 1) ** 2) + 0.1 * np.sin(3 * zc))[:, None, None]
+    s1 = S.initial_state(c1, g, u, np.zeros_like(u), np.zeros_like(u))
+    s3 = S.initial_state(c3, g, u, np.zeros_like(u), np.zeros_like(u))
+    dt = 0.05
+    for k in range(3):
+        s1 = S.substep(c1, g, s1, k, dt)
+        s3 = S.substep(c3, g, s3, k, dt)
+    assert np.max(np.abs(s1.u - s3.u)) < 1e-13 * np.max(np.abs(s1.u))
+    assert np.max(np.abs(s1.p - s3.p)) < 1e-12
+
+
+def test_poiseuille_fixed_point_fully_implicit():
+    """The discrete Poiseuille solution is also a fixed point of the fully implicit scheme."""
+    nz = 16
+    case = Case(4, 4, nz, 1.0, 1.0, 2.0, zbc=ZBC_NOSLIP, beta=1.2, nu=0.5, sgs=SGS_NONE,
+                implicit_3d=True, ubulk=1.0)
+    g = Grid(case)
+    A = np.zeros((nz + 1, nz + 1))
+    for c in range(nz):
+        a = np.zeros((nz + 2, 1, 1))
+        a[c + 1] = 1.0
+        a[0], a[nz + 1] = -a[1], -a[nz]
+        A[:nz, c] = case.nu * S.ops.lap_z_centre(g, a)[:, 0, 0]
+    A[:nz, nz] = 1.0
+    A[nz, :nz] = g.dzf[1:nz + 1]
+    rhs = np.zeros(nz + 1)
+    rhs[nz] = 2.0
+    sol = np.linalg.solve(A, rhs)[:nz]
+    u = np.zeros((nz + 2, 4, 4))
+    u[1:nz + 1] = sol[:, None, None]
+    st = S.initial_state(case, g, u, np.zeros_like(u), np.zeros_like(u))
+    for _ in range(3):
+        st = _step(case, g, st, 0.3)
+    assert np.max(np.abs(st.u[1:nz + 1] - sol[:, None, None])) < 1e-12
+
+
+def test_pressure_update_fully_implicit_identity():
+    """Eq. p_update_imp3d with L = D G (the Poisson operator): since D G phi = D u*/(gamma dt),
+    p^{k+1/2} - p^{k-1/2} - phi = -(nu/2) D u* exactly (to roundoff), on a random state of a
+    no-slip channel."""
+    nx, ny, nz = 8, 6, 10
+    case = Case(nx, ny, nz, 1.0, 1.0, 2.0, zbc=ZBC_NOSLIP, beta=1.3, nu=0.05, sgs=SGS_SMAG,
+                implicit_3d=True)
+    g = Grid(case)
+    u, v, w, _ = random_state(nx, ny, nz, 4)
+    w[nz] = 0.0
+    st = S.initial_state(case, g, u, v, w)
+    k, dt = 1, 0.02
+    ustar, _ = S.predictor(case, g, st, k, dt)
+    ustar = S.helmholtz_3d(case, g, st, ustar, k, dt)
+    un, vn, wn, p, phi = S.project(case, g, st, ustar, k, dt)
+    I = slice(1, nz + 1)
+    us, vs, ws = np.zeros_like(u), np.zeros_like(u), np.zeros_like(u)
+    us[I], vs[I], ws[I] = ustar
+    ws[0] = ws[nz] = 0.0
+    div = ops.divergence(g, us, vs, ws)
+    lhs = p[I] - st.p[I] - phi[I]
+    assert np.max(np.abs(lhs + 0.5 * case.nu * div)) < 1e-12 * max(1.0, np.max(np.abs(div)))
+    assert np.max(np.abs(div)) > 1e-3          # the identity is not trivially zero
