@@ -41,6 +41,9 @@ CONFIGS = {
     "c4": dict(name="channel 512x256x128 fp64 learned closure vs DSM, WM, CN-z", nx=512, ny=256, nz=128,
                lx=2 * 3.141592653589793, ly=3.141592653589793, lz=2.0, zbc=2, beta=1.5, nu=5e-5, sgs=3,
                cs=0.17, implicit_z=1, precision=0, ubulk=1.0, init="channel", seed=4, dtype="f64"),
+    "f1": dict(name="channel 256x128x96 fp64 DSM+WM CN in x, y and z", nx=256, ny=128, nz=96,
+               lx=2 * 3.141592653589793, ly=3.141592653589793, lz=2.0, zbc=2, beta=1.5, nu=5e-5, sgs=3, cs=0.17,
+               implicit_z=2, precision=0, ubulk=1.0, init="channel", seed=2, dtype="f64"),
     "c5": dict(name="64 isotropic boxes 32^3/48^3/64^3/96^3 fp32 DSM explicit, batched", nbox=64, seed=5,
                dtype="f32"),
 }
@@ -93,7 +96,8 @@ def cpu_baseline(cfgd, budget_s):
     from oracle import substep as S
     case = oracle.Case(cfgd["nx"], cfgd["ny"], cfgd["nz"], cfgd["lx"], cfgd["ly"], cfgd["lz"], zbc=cfgd["zbc"],
                        beta=cfgd["beta"], nu=cfgd["nu"], sgs=cfgd["sgs"], cs=cfgd["cs"],
-                       implicit_z=bool(cfgd["implicit_z"]), ubulk=cfgd["ubulk"])
+                       implicit_z=cfgd["implicit_z"] == 1, implicit_3d=cfgd["implicit_z"] == 2,
+                       ubulk=cfgd["ubulk"])
     g = oracle.Grid(case)
     u, v, w = initial_fields(cfgd, g.zc)
     st = S.initial_state(case, g, u, v, w)
@@ -156,8 +160,9 @@ def copy_state(torch, dst, src):
 
 def substep_roofline(value, cfgd):
     """Whole-substep HBM fraction: the minimal-sweep bytes per point and substep (25 words
-    with explicit viscous terms, 34 with Crank-Nicolson in z; 8-byte words in FP64, 4-byte
-    in the mixed mode) times the measured points*substeps/s, against 8 TB/s."""
+    with explicit viscous terms, 34 with Crank-Nicolson in z or in all directions: the
+    Helmholtz solves read and write each component once; 8-byte words in FP64, 4-byte in the
+    mixed mode) times the measured points*substeps/s, against 8 TB/s."""
     words = 34 if cfgd["implicit_z"] else 25
     wb = 4 if cfgd["precision"] == 1 else 8
     gbps = value * 1e6 * words * wb / 1e9
@@ -165,7 +170,7 @@ def substep_roofline(value, cfgd):
             "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4)}
 
 
-def kernel_report(les, ctx, nsteps):
+def kernel_report(les, ctx, nsteps, workload):
     """Per-kernel HIP-event timing over nsteps un-captured steps; returns (kernels, dominant)."""
     les.les_timing(ctx, True)
     for _ in range(nsteps):
@@ -184,7 +189,7 @@ def kernel_report(les, ctx, nsteps):
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
     per_launch = d["bytes"] / d["count"]
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(dom, per_launch),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(dom, per_launch, workload),
             "alg_bytes_per_launch": per_launch, "avg_launch_us": round(1e3 * d["ms"] / d["count"], 3)}
     return kernels, roof
 
@@ -244,16 +249,16 @@ def learned_closure(les, torch, cfgd, solver, steps, warmup, use_graph):
     return out
 
 
-def traffic_entry(kernel, launches_bytes):
+def traffic_entry(kernel, launches_bytes, workload):
     """Counter-derived HBM traffic for the dominant kernel, if a summary for the current
-    kernel source exists under profiles/ (else None)."""
+    kernel source and this workload exists under profiles/ (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         data = json.load(open(path))
         ent = data.get(kernel)
-        if not ent:
+        if not ent or ent.get("workload", CONFIGS["c2"]["name"]) != workload:
             return None
         src = os.path.join(ROOT, "paper_2411_09364_amd", "csrc", ent["source"])
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -323,7 +328,7 @@ def solver_line(args, torch, cfgd):
     ms_per_step = el / args.steps * 1e3
     value = cells * 3 * args.steps / el / 1e6
     # per-kernel pass: same steps without the graph, every launch bracketed by HIP events
-    kernels, roof = kernel_report(les, ctx, max(1, min(args.steps, 10)))
+    kernels, roof = kernel_report(les, ctx, max(1, min(args.steps, 10)), cfgd["name"])
     diag, status = solver.diag()
     out = {
         "metric": METRIC,
@@ -351,7 +356,7 @@ def solver_line(args, torch, cfgd):
     solver.close()
     if args.config == "c3":
         out["precision_check"] = precision_check(les, torch, cfgd, args.compare_steps)
-    if not args.no_cpu_baseline and args.config in ("c1", "c2"):
+    if not args.no_cpu_baseline and args.config in ("c1", "c2", "f1"):
         out["cpu_baseline"] = cpu_baseline(cfgd, args.cpu_seconds)
     return out
 
@@ -447,7 +452,7 @@ def learned_line(args, torch):
         s.synchronize()
         el = time.perf_counter() - t0
         thr[name] = (cells * 3 * args.steps / el / 1e6, el / args.steps * 1e3)
-    kernels, roof = kernel_report(les, sm.ctx, max(1, min(args.steps, 10)))
+    kernels, roof = kernel_report(les, sm.ctx, max(1, min(args.steps, 10)), cfgd["name"])
     # mean-profile comparison from the same state
     torch.cuda.synchronize()
     for s in (sd, sm):

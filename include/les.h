@@ -62,6 +62,8 @@ typedef enum {
 enum { LES_ZBC_PERIODIC = 0, LES_ZBC_NOSLIP = 1, LES_ZBC_WALLMODEL = 2 };
 enum { LES_SGS_NONE = 0, LES_SGS_SMAG = 1, LES_SGS_SMAG_VD = 2, LES_SGS_DSM = 3, LES_SGS_MLP = 4 };
 enum { LES_FP64 = 0, LES_MIXED = 1 };
+/* Viscous-term treatment (les_config.implicit_z). */
+enum { LES_VISC_EXPLICIT = 0, LES_VISC_CN_Z = 1, LES_VISC_CN_3D = 2 };
 
 typedef struct les_ctx les_ctx;   /* opaque, owned by the library */
 
@@ -76,7 +78,11 @@ typedef struct {
   double nu;            /* kinematic viscosity (> 0)                                     */
   int32_t sgs;          /* LES_SGS_*                                                     */
   double cs;            /* Smagorinsky constant for LES_SGS_SMAG / _SMAG_VD              */
-  int32_t implicit_z;   /* 0: explicit viscous terms; 1: Crank-Nicolson in z (walls only) */
+  int32_t implicit_z;   /* LES_VISC_*: explicit viscous terms (Eq. twostar_exp); Crank-Nicolson
+                           in z (Eqs. twostar_imp1d, onestar_imp1d; walls only); or Crank-
+                           Nicolson in all directions (Eqs. twostar_imp3d, onestar_imp3d,
+                           p_update_imp3d; the Helmholtz systems solved by FFTs in x and y
+                           and FP64 Thomas in z, or FFTs in z as well when z is periodic)  */
   int32_t precision;    /* LES_FP64, or LES_MIXED: float storage, stencils and FFTs,
                            double tridiagonal solves, zero mode and reductions           */
   double ubulk;         /* > 0: constant flow rate (bulk velocity) in x; 0: off          */

@@ -164,7 +164,7 @@ size_t carve(Ctx& c, char* base) {
   t.twx_f = (float*)take(2 * f.nx * 4);
   t.twy_f = (float*)take(2 * f.ny * 4);
   t.twz_f = (float*)take(2 * n * 4);
-  t.hfac = (double*)take(8 * n * 8);
+  t.hfac = (double*)take(12 * n * 8);
   t.dt = (double*)take(16 * 8);
   c.mlp_cnt = (int*)take(2 * sizeof(int));
   t.red_n = 4096;
@@ -208,7 +208,8 @@ template <typename T>
 les_status substep_body(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
   launch_predictor<T>(c, stage);
-  if (c.cfg.implicit_z) launch_helmholtz<T>(c, stage);
+  if (c.cfg.implicit_z == LES_VISC_CN_Z) launch_helmholtz<T>(c, stage);
+  if (c.cfg.implicit_z == LES_VISC_CN_3D) launch_helmholtz_3d<T>(c, stage);
   launch_poisson_rhs_fwd<T>(c, (const T*)c.us, (const T*)c.vs, (const T*)c.wsf, G[stage], stage);
   launch_poisson_solve_spectral<T>(c);
   launch_poisson_inverse<T>(c, (T*)c.phi);
@@ -265,8 +266,8 @@ les_status les_init(const les_config* cfg, void* hip_stream, les_ctx** out) {
   if (!(std::isfinite(f.beta) && f.beta >= 0.0 && f.beta < 20.0)) return LES_EINVAL;
   if (f.sgs < 0 || f.sgs > 4) return LES_EINVAL;
   if (!(std::isfinite(f.cs) && f.cs >= 0.0)) return LES_EINVAL;
-  if (f.implicit_z != 0 && f.implicit_z != 1) return LES_EINVAL;
-  if (f.implicit_z && f.zbc == LES_ZBC_PERIODIC) return LES_ENOTSUP;
+  if (f.implicit_z < LES_VISC_EXPLICIT || f.implicit_z > LES_VISC_CN_3D) return LES_EINVAL;
+  if (f.implicit_z == LES_VISC_CN_Z && f.zbc == LES_ZBC_PERIODIC) return LES_ENOTSUP;
   if (f.precision != LES_FP64 && f.precision != LES_MIXED) return LES_EINVAL;
   if (!(std::isfinite(f.ubulk) && f.ubulk >= 0.0)) return LES_EINVAL;
   if (!(std::isfinite(f.h_wm) && f.h_wm >= 0.0)) return LES_EINVAL;
@@ -382,7 +383,7 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
           const double d = std::pow((f.lx / f.nx) * (f.ly / f.ny) * c.dzf[k], 1.0 / 3.0);
           c.coef_host[k] = (f.cs * d) * (f.cs * d);
         }
-      c.hfac_host.assign(8 * n, 0.0);
+      c.hfac_host.assign(12 * n, 0.0);
       for (int k = 0; k < n; ++k) c.hfac_host[4 * n + k] = 1.0;
       if ((s = up(c.t.zc, c.zc.data(), (n + 2) * 8)) != LES_OK) return s;
       if ((s = up(c.t.dzf, c.dzf.data(), (n + 2) * 8)) != LES_OK) return s;

@@ -73,8 +73,9 @@ struct Tables {
   float* twx_f;     // float copies
   float* twy_f;
   float* twz_f;
-  double* hfac;     // 8*nz: CN-z factorisation: c', 1/pivot for u/v rows and for w rows, the
-                    //   flow-rate profile q, unused, sub-diagonals for u/v rows and for w rows
+  double* hfac;     // 12*nz: CN factorisation: c', 1/pivot for u/v rows and for w rows, the
+                    //   flow-rate profile q, unused, sub-diagonals (u/v, w), diagonals and
+                    //   super-diagonals (u/v, w)
   double* dt;       // [0] time step; [1] bulk shift s; [2..] scratch scalars
   double* red;      // reduction partials (size red_n)
   double* bulk;     // flow-rate partial sums, one per forward-x block
@@ -138,6 +139,7 @@ struct Ctx {
 // kernel launchers (defined in the .hip files)
 template <typename T> void launch_predictor(Ctx& c, int stage);
 template <typename T> void launch_helmholtz(Ctx& c, int stage);
+template <typename T> void launch_helmholtz_3d(Ctx& c, int stage);
 template <typename T> void launch_poisson_rhs_fwd(Ctx& c, const T* us, const T* vs, const T* ws, double scale_by_gamma_dt, int stage);
 template <typename T> void launch_poisson_solve_spectral(Ctx& c);
 void launch_thomas_factor(Ctx& c);

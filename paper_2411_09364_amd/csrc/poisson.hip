@@ -299,14 +299,18 @@ __global__ void __launch_bounds__(256) kb_irfftx(BatchMap m) {
 // ============================================================================ strided lines
 // Complex FFT of length P.n along a strided dimension for L consecutive l values:
 // element t of line (l, o) is at base + o*ostride + t*lstride + l.  grid.x covers l tiles,
-// grid.y covers o.  SOLVE (periodic z only): forward FFT, multiply by
-// 1/(lamx + lamy + lamz) (0 for the zero mode) and the normalisation, inverse FFT.
+// grid.y covers o.  SOLVE (periodic z only): forward FFT, multiply by the normalisation
+// over the eigenvalue lam = lamx + lamy + lamz of the operator, inverse FFT.  The operator
+// is the Laplacian when hg = 0 (Poisson; the zero mode is set to 0), else the Helmholtz
+// operator 1 - hg dt lam of Crank-Nicolson in all directions (hg = gamma nu / 2, dt from
+// the device slot).
 template <typename T, int DIR, bool SOLVE>
 __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T>* __restrict__ data, int nl, int64_t lstride,
                                                    int64_t ostride, int L, const double* __restrict__ twd,
                                                    const float* __restrict__ twf, const double* __restrict__ lamx,
                                                    const double* __restrict__ lamy, const double* __restrict__ lamz,
-                                                   double norm) {
+                                                   double norm, const double* __restrict__ dtp = nullptr,
+                                                   double hg = 0.0) {
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
   const int N = P.n;
@@ -342,9 +346,10 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T
   if (SOLVE) {
     // res holds the z spectrum of column (l, m = o); o indexes y modes here
     const int l = l0 + ll;
+    const double hc = hg != 0.0 ? hg * dtp[0] : 0.0;
     for (int t = lane; t < N; t += team) {
       double lam = (l < nl ? lamx[l] : 0.0) + lamy[o] + lamz[t];
-      double f = (lam != 0.0) ? norm / lam : 0.0;
+      double f = hg != 0.0 ? norm / (1.0 - hc * lam) : ((lam != 0.0) ? norm / lam : 0.0);
       res[t].x = (T)((double)res[t].x * f);
       res[t].y = (T)((double)res[t].y * f);
     }
@@ -365,8 +370,9 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T
 template <typename T, int DIR, bool SOLVE>
 __global__ void __launch_bounds__(256) k_fft_lines(FftPlan P, cpx<T>* data, int nl, int64_t lstride, int64_t ostride,
                                                    int L, const double* twd, const float* twf, const double* lamx,
-                                                   const double* lamy, const double* lamz, double norm) {
-  fft_lines_body<T, DIR, SOLVE>(blockIdx, P, data, nl, lstride, ostride, L, twd, twf, lamx, lamy, lamz, norm);
+                                                   const double* lamy, const double* lamz, double norm,
+                                                   const double* dtp, double hg) {
+  fft_lines_body<T, DIR, SOLVE>(blockIdx, P, data, nl, lstride, ostride, L, twd, twf, lamx, lamy, lamz, norm, dtp, hg);
 }
 
 // Batched y transforms (SOLVE = false) or periodic-z spectral solve (SOLVE = true).
@@ -539,6 +545,93 @@ __global__ void __launch_bounds__(256) k_thomas(GridP g, cpx<T>* __restrict__ sp
   }
 }
 
+// Crank-Nicolson in all directions, wall-bounded z (Eq. onestar_imp3d): after FFTs in x and
+// y, every (l, m) column holds the tridiagonal system with rows a_k, b_k - c (lamx(l) +
+// lamy(m)), c_k (c = gamma nu dt / 2; a, b, c the CN-z rows of the component, wall folds
+// included) and is solved by the Thomas algorithm in FP64.  The pivots depend on dt, so the
+// factorisation runs here, per column, alongside the forward sweep.  Same LDS staging as
+// k_thomas: tc columns of the flattened (m, l) index per block, two threads per column (real
+// and imaginary parts; each keeps its own copy of the normalised super-diagonal), nrow rows
+// solved (nz for u and v, nz - 1 for w, whose last plane is the wall face and stays zero).
+template <typename T>
+__global__ void __launch_bounds__(256) k_helm3d_z(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ ra_g,
+                                                  const double* __restrict__ rb_g, const double* __restrict__ rc_g,
+                                                  const double* __restrict__ lamx, const double* __restrict__ lamy,
+                                                  const double* __restrict__ dtp, double hg, double norm, int nrow,
+                                                  int tc) {
+  extern __shared__ double hsm3[];
+  const int nxh = g.nx / 2 + 1;
+  const int64_t ncol = (int64_t)g.nxp * g.ny;
+  const int n = g.nz;
+  const int64_t col0 = (int64_t)blockIdx.x * tc;
+  const int cw = (int)(ncol - col0 < tc ? ncol - col0 : tc);
+  cpx<T>* x = spec + col0;
+  double* fx = hsm3;                        // [n][tc][re, im]
+  double* fc = hsm3 + 2 * (size_t)n * tc;   // [n][tc][c' of the re thread, c' of the im thread]
+  double* rows = fc + 2 * (size_t)n * tc;   // a, b, c
+  for (int e = threadIdx.x; e < nrow; e += blockDim.x) {
+    rows[e] = ra_g[e];
+    rows[n + e] = rb_g[e];
+    rows[2 * n + e] = rc_g[e];
+  }
+  constexpr int TB = 8;
+  const int total = n * tc;
+  for (int e0 = 0; e0 < total; e0 += TB * (int)blockDim.x) {
+    cpx<T> v[TB];
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      const int k = e / tc, q = e % tc;
+      v[b] = x[(e < total && q < cw) ? (int64_t)k * ncol + q : 0];
+    }
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
+      if (e < total) {
+        fx[2 * e] = (double)v[b].x * norm;
+        fx[2 * e + 1] = (double)v[b].y * norm;
+      }
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 2 * cw) {
+    const int q = t >> 1, r = t & 1;
+    const int64_t cidx = col0 + q;
+    const int l = (int)(cidx % g.nxp), m = (int)(cidx / g.nxp);
+    if (l < nxh) {
+      const int fs = 2 * tc;
+      double* f = fx + 2 * q + r;
+      double* cq = fc + 2 * q + r;
+      const double shift = hg * dtp[0] * (lamx[l] + lamy[m]);
+      const double* ra = rows;
+      const double* rb = rows + n;
+      const double* rc = rows + 2 * n;
+      double cprev = 0.0, d = 0.0;
+#pragma unroll 4
+      for (int k = 0; k < nrow; ++k) {
+        const double a = ra[k];
+        const double rp = 1.0 / ((rb[k] - shift) - a * cprev);
+        d = (f[k * fs] - a * d) * rp;
+        cprev = rc[k] * rp;
+        f[k * fs] = d;
+        cq[k * fs] = cprev;
+      }
+      double xv = d;
+#pragma unroll 4
+      for (int k = nrow - 2; k >= 0; --k) {
+        xv = f[k * fs] - cq[k * fs] * xv;
+        f[k * fs] = xv;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * tc; e += blockDim.x) {
+    const int k = e / tc, q = e % tc;
+    if (q < cw) x[(int64_t)k * ncol + q] = {(T)fx[2 * e], (T)fx[2 * e + 1]};
+  }
+}
+
 // ============================================================================ bulk
 // s = (U_b - <u*>) / <q>, <.> the dzf-weighted volume mean; stored in dt[1].  One block:
 // strided partial sums per thread, then a fixed-order tree (deterministic).
@@ -621,49 +714,64 @@ static void fwd_x(Ctx& c, int mode, const T* us, const T* vs, const T* ws, const
                        c.t.hfac + 4 * c.g.nz, c.t.dzf, c.g.nz, c.cfg.ubulk, (double)c.g.sxy, c.cfg.lz);
 }
 
+// y transforms of the spectrum buffer (DIR -1 forward, +1 inverse)
+template <typename T, int DIR>
+static void ffty(Ctx& c, const char* name) {
+  const int nxh = c.g.nx / 2 + 1;
+  const int ny = c.g.ny, nz = c.g.nz;
+  const double spec_bytes = (double)nxh * ny * nz * 2 * sizeof(T);
+  const FftPlan P = make_plan(ny);
+  const int L = lines_per_block(ny);
+  dim3 grid((nxh + L - 1) / L, nz);
+  const size_t sh = 2 * (size_t)L * (ny + 1) * sizeof(cpx<T>);
+  LES_LAUNCH(c, name, 2 * spec_bytes, (k_fft_lines<T, DIR, false>), grid, dim3(256), sh, P, (cpx<T>*)c.spec, nxh,
+             (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0,
+             nullptr, 0.0);
+}
+
+// periodic z: FFT, divide by the operator's eigenvalue, inverse FFT (hg = 0: Poisson)
+template <typename T>
+static void fftz_solve(Ctx& c, const char* name, double hg) {
+  const int nxh = c.g.nx / 2 + 1;
+  const int ny = c.g.ny, nz = c.g.nz;
+  const double spec_bytes = (double)nxh * ny * nz * 2 * sizeof(T);
+  const FftPlan P = make_plan(nz);
+  const int L = lines_per_block(nz);
+  dim3 grid((nxh + L - 1) / L, ny);
+  const size_t sh = 2 * (size_t)L * (nz + 1) * sizeof(cpx<T>);
+  const double norm = 1.0 / ((double)c.g.nx * ny * nz);
+  LES_LAUNCH(c, name, 2 * spec_bytes, (k_fft_lines<T, -1, true>), grid, dim3(256), sh, P, (cpx<T>*)c.spec, nxh,
+             (int64_t)c.g.nxp * ny, (int64_t)c.g.nxp, L, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy, c.t.lamz, norm,
+             c.t.dt, hg);
+}
+
+// columns per block of the LDS-staged z solves: the largest power of two <= 32 whose LDS
+// (32 bytes per entry and the rows) stays within 64 KB
+static int zsolve_columns(int nz) {
+  int tc = 32;
+  while (tc > 2 && (size_t)nz * (32 * tc + 24) > 65536) tc /= 2;
+  return tc;
+}
+
 template <typename T>
 static void spectral_solve(Ctx& c) {
   const int nxh = c.g.nx / 2 + 1;
   const int ny = c.g.ny, nz = c.g.nz;
   cpx<T>* sp = (cpx<T>*)c.spec;
   const double spec_bytes = (double)nxh * ny * nz * 2 * sizeof(T);
-  // y transform
-  {
-    const FftPlan P = make_plan(ny);
-    const int L = lines_per_block(ny);
-    dim3 grid((nxh + L - 1) / L, nz);
-    const size_t sh = 2 * (size_t)L * (ny + 1) * sizeof(cpx<T>);
-    LES_LAUNCH(c, "ffty_fwd", 2 * spec_bytes, (k_fft_lines<T, -1, false>), grid, dim3(256), sh, P, sp, nxh, (int64_t)c.g.nxp,
-                       (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
-  }
+  ffty<T, -1>(c, "ffty_fwd");
   if (c.cfg.zbc == LES_ZBC_PERIODIC) {
-    const FftPlan P = make_plan(nz);
-    const int L = lines_per_block(nz);
-    dim3 grid((nxh + L - 1) / L, ny);
-    const size_t sh = 2 * (size_t)L * (nz + 1) * sizeof(cpx<T>);
-    const double norm = 1.0 / ((double)c.g.nx * ny * nz);
-    LES_LAUNCH(c, "fftz_solve", 2 * spec_bytes, (k_fft_lines<T, -1, true>), grid, dim3(256), sh, P, sp, nxh, (int64_t)c.g.nxp * ny,
-                       (int64_t)c.g.nxp, L, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy, c.t.lamz, norm);
+    fftz_solve<T>(c, "fftz_solve", 0.0);
   } else {
     const int64_t ncol = (int64_t)c.g.nxp * ny;
-    // columns per block: the largest power of two <= 32 whose LDS (32 bytes per entry and
-    // the rows) stays within 64 KB
-    int tc = 32;
-    while (tc > 2 && (size_t)nz * (32 * tc + 24) > 65536) tc /= 2;
+    const int tc = zsolve_columns(nz);
     const size_t sh = (size_t)nz * (32 * tc + 24);
     const double norm = 1.0 / ((double)c.g.nx * ny);
     LES_LAUNCH(c, "thomas_z", 2 * spec_bytes + (double)nxh * (ny / 2 + 1) * nz * 16, (k_thomas<T>),
                dim3((unsigned)((ncol + tc - 1) / tc)), dim3(256), sh, c.g, sp, c.t.pa, c.t.pb, c.t.pc,
                (const double2*)c.t.pfac, norm, tc);
   }
-  {
-    const FftPlan P = make_plan(ny);
-    const int L = lines_per_block(ny);
-    dim3 grid((nxh + L - 1) / L, nz);
-    const size_t sh = 2 * (size_t)L * (ny + 1) * sizeof(cpx<T>);
-    LES_LAUNCH(c, "ffty_inv", 2 * spec_bytes, (k_fft_lines<T, 1, false>), grid, dim3(256), sh, P, sp, nxh, (int64_t)c.g.nxp,
-                       (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0);
-  }
+  ffty<T, 1>(c, "ffty_inv");
 }
 
 template <typename T>
@@ -677,6 +785,39 @@ static void inv_x(Ctx& c, T* out) {
   LES_LAUNCH(c, "irfftx", spec_bytes + (double)c.g.sxy * c.g.nz * sizeof(T), (k_irfftx<T>), dim3(nblk), dim3(256), sh,
              c.g, P, (const cpx<T>*)c.spec, out,
                      c.t.twx, c.t.twx_f, pb);
+}
+
+// Crank-Nicolson in all directions (Eq. onestar_imp3d): each predicted component in u*, v*,
+// w* (right-hand side of the Helmholtz system, wall-model flux included) is transformed in x
+// and y through the spectrum buffer, solved per wavenumber pair in z (Thomas in FP64 at
+// walls, FFT when z is periodic) and transformed back in place.
+template <typename T>
+void launch_helmholtz_3d(Ctx& c, int stage) {
+  static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
+  const double hg = G[stage] * c.cfg.nu / 2.0;
+  const int n = c.g.nz;
+  const double spec_bytes = (double)(c.g.nx / 2 + 1) * c.g.ny * n * 2 * sizeof(T);
+  T* comp[3] = {(T*)c.us, (T*)c.vs, (T*)c.wsf};
+  for (int a = 0; a < 3; ++a) {
+    fwd_x<T>(c, 1, nullptr, nullptr, nullptr, comp[a], 1.0, false);
+    ffty<T, -1>(c, "h3d_ffty_fwd");
+    if (c.cfg.zbc == LES_ZBC_PERIODIC) {
+      fftz_solve<T>(c, "h3d_fftz_solve", hg);
+    } else {
+      const int64_t ncol = (int64_t)c.g.nxp * c.g.ny;
+      const int tc = zsolve_columns(n);
+      const size_t sh = (size_t)n * (32 * tc + 24);
+      const double* hf = c.t.hfac;
+      const double* ra = hf + (a < 2 ? 6 : 7) * n;
+      const double* rb = hf + (a < 2 ? 8 : 10) * n;
+      const double* rc = hf + (a < 2 ? 9 : 11) * n;
+      LES_LAUNCH(c, "h3d_thomas_z", 2 * spec_bytes, (k_helm3d_z<T>), dim3((unsigned)((ncol + tc - 1) / tc)), dim3(256),
+                 sh, c.g, (cpx<T>*)c.spec, ra, rb, rc, c.t.lamx, c.t.lamy, c.t.dt, hg,
+                 1.0 / ((double)c.g.nx * c.g.ny), a < 2 ? n : n - 1, tc);
+    }
+    ffty<T, 1>(c, "h3d_ffty_inv");
+    inv_x<T>(c, comp[a]);
+  }
 }
 
 template <typename T>
@@ -725,7 +866,8 @@ int fft_lines_per_block(int n) { return lines_per_block(n); }
   template void launch_poisson_rhs_fwd<T>(Ctx&, const T*, const T*, const T*, double, int); \
   template void launch_poisson_solve_spectral<T>(Ctx&);                                      \
   template void launch_poisson_inverse<T>(Ctx&, T*);                                         \
-  template void launch_poisson_field<T>(Ctx&, T*);
+  template void launch_poisson_field<T>(Ctx&, T*);                                          \
+  template void launch_helmholtz_3d<T>(Ctx&, int);
 INST(double)
 INST(float)
 

@@ -52,12 +52,17 @@ struct Nb {
   T p0, pip, pjp, pkp;
 };
 
-// R_i = -d(u_i u_j)/dx_j + d(2 nu_t S_ij)/dx_j + nu L u_i (explicit) or with L_xx + L_yy
-// only (CN in z); u* = u + dt (alpha R^k + beta R^{k-1} - gamma G p), or with CN in z the
-// Helmholtz right-hand side u** - gamma nu dt/2 L_zz u^k where
-// u** = u + dt (alpha R^k + beta R^{k-1} - gamma G p) + gamma nu dt L_zz u^k.
+// Viscous treatment of the predictor: explicit (Eq. onestar_exp), Crank-Nicolson in z
+// (Eq. twostar_imp1d) or in all directions (Eq. twostar_imp3d).
+enum { VISC_EXPLICIT = LES_VISC_EXPLICIT, VISC_CN_Z = LES_VISC_CN_Z, VISC_CN_3D = LES_VISC_CN_3D };
+
+// R_i = -d(u_i u_j)/dx_j + d(2 nu_t S_ij)/dx_j + nu L u_i (explicit), with L_xx + L_yy only
+// (CN in z) or without viscous part (CN in all directions); u* = u + dt (alpha R^k +
+// beta R^{k-1} - gamma G p), or the Helmholtz right-hand side u** - gamma nu dt/2 L' u^k with
+// u** = u + dt (alpha R^k + beta R^{k-1} - gamma G p) + gamma nu dt L' u^k, L' = L_zz (CN in
+// z) or the full Laplacian (CN in all directions).
 // One cell (plane k) from its neighbourhood b and, when use_rprev, R^{k-1} (rup, rvp, rwp).
-template <typename T, bool IMPLICIT>
+template <typename T, int MODE>
 __device__ __forceinline__ void predictor_cell(const Nb<T>& b, const GridP& g, int k, T dt, double alpha,
                                                double beta, double gamma, bool use_rprev, T rup, T rvp, T rwp,
                                                T& Ru_out, T& Rv_out, T& Rw_out, T& uo, T& vo, T& wo) {
@@ -99,7 +104,8 @@ __device__ __forceinline__ void predictor_cell(const Nb<T>& b, const GridP& g, i
     lz = ((b.ukp - b.u0) * rdzc - (b.u0 - b.ukm) * rdzcm) * rdzf;
   }
   const T lzu = lz;
-  T Ru = -ax + sx + nu * (IMPLICIT ? lx : lx + lz);
+  const T lxu = lx;
+  T Ru = -ax + sx + nu * (MODE == VISC_EXPLICIT ? lx + lz : (MODE == VISC_CN_Z ? lx : (T)0));
   // ---------------- v-momentum at (i, j+1/2, k)
   {
     const T fyx_r = h * (b.v0 + b.vip) * (h * (b.u0 + b.ujp));
@@ -125,7 +131,8 @@ __device__ __forceinline__ void predictor_cell(const Nb<T>& b, const GridP& g, i
     lz = ((b.vkp - b.v0) * rdzc - (b.v0 - b.vkm) * rdzcm) * rdzf;
   }
   const T lzv = lz;
-  T Rv = -ay + sy + nu * (IMPLICIT ? lx : lx + lz);
+  const T lxv = lx;
+  T Rv = -ay + sy + nu * (MODE == VISC_EXPLICIT ? lx + lz : (MODE == VISC_CN_Z ? lx : (T)0));
   // ---------------- w-momentum at (i, j, k+1/2)
   {
     const T fzx_r = h * (b.w0 + b.wip) * (h * (b.u0 + b.ukp));
@@ -151,7 +158,8 @@ __device__ __forceinline__ void predictor_cell(const Nb<T>& b, const GridP& g, i
     lz = ((b.wkp - b.w0) * rdzfp - (b.w0 - b.wkm) * rdzf) * rdzc;
   }
   const T lzw = lz;
-  T Rw = -az + sz + nu * (IMPLICIT ? lx : lx + lz);
+  const T lxw = lx;
+  T Rw = -az + sz + nu * (MODE == VISC_EXPLICIT ? lx + lz : (MODE == VISC_CN_Z ? lx : (T)0));
   const T ta = (T)alpha, tb = (T)beta, tg = (T)gamma;
   T iu = ta * Ru, iv = ta * Rv, iw = ta * Rw;
   if (use_rprev) {
@@ -166,74 +174,22 @@ __device__ __forceinline__ void predictor_cell(const Nb<T>& b, const GridP& g, i
   Rv_out = Rv;
   Rw_out = Rw;
   const bool wall_face = (g.zbc != LES_ZBC_PERIODIC) && (k == g.nz);
-  if (IMPLICIT) {
+  if (MODE == VISC_CN_Z) {
     const T cg = tg * nu, ch = tg * nu * dt / two;
     uo = (b.u0 + dt * (iu + cg * lzu)) - ch * lzu;
     vo = (b.v0 + dt * (iv + cg * lzv)) - ch * lzv;
     wo = wall_face ? (T)0 : (b.w0 + dt * (iw + cg * lzw)) - ch * lzw;
+  } else if (MODE == VISC_CN_3D) {
+    const T cg = tg * nu, ch = tg * nu * dt / two;
+    const T lu = lxu + lzu, lv = lxv + lzv, lw = lxw + lzw;
+    uo = (b.u0 + dt * (iu + cg * lu)) - ch * lu;
+    vo = (b.v0 + dt * (iv + cg * lv)) - ch * lv;
+    wo = wall_face ? (T)0 : (b.w0 + dt * (iw + cg * lw)) - ch * lw;
   } else {
     uo = b.u0 + dt * iu;
     vo = b.v0 + dt * iv;
     wo = wall_face ? (T)0 : b.w0 + dt * iw;
   }
-}
-
-// Point version: one thread per cell, neighbours read from global memory (batched boxes).
-template <typename T, bool IMPLICIT>
-__device__ __forceinline__ void predictor_body(dim3 bid, GridP g, const T* __restrict__ u, const T* __restrict__ v,
-                                               const T* __restrict__ w, const T* __restrict__ p,
-                                               const T* __restrict__ nut, const double* __restrict__ coef,
-                                               T* __restrict__ ru, T* __restrict__ rv, T* __restrict__ rw,
-                                               T* __restrict__ us, T* __restrict__ vs, T* __restrict__ ws,
-                                               const double* __restrict__ dtp, double alpha, double beta,
-                                               double gamma, int use_rprev, int write_r) {
-  const int i = bid.x * blockDim.x + threadIdx.x;
-  const int j = bid.y * blockDim.y + threadIdx.y;
-  const int k = IMPLICIT ? bid.z : bid.z + 1;
-  if (i >= g.nx || j >= g.ny) return;
-  const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx);
-  const int jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
-  const int kp = k + 1, km = k - 1;
-#define U(kk, jj, ii) u[idx3(g, kk, jj, ii)]
-#define V(kk, jj, ii) v[idx3(g, kk, jj, ii)]
-#define W(kk, jj, ii) w[idx3(g, kk, jj, ii)]
-#define NU(kk, jj, ii) nut_at(nut, coef, g, kk, jj, ii)
-  Nb<T> b;
-  b.u0 = U(k, j, i), b.uip = U(k, j, ip), b.uim = U(k, j, im), b.ujp = U(k, jp, i), b.ujm = U(k, jm, i);
-  b.ukp = U(kp, j, i), b.ukm = U(km, j, i), b.ujp_im = U(k, jp, im), b.ukp_im = U(kp, j, im);
-  b.v0 = V(k, j, i), b.vip = V(k, j, ip), b.vim = V(k, j, im), b.vjp = V(k, jp, i), b.vjm = V(k, jm, i);
-  b.vkp = V(kp, j, i), b.vkm = V(km, j, i), b.vjm_ip = V(k, jm, ip), b.vkp_jm = V(kp, jm, i);
-  b.w0 = W(k, j, i), b.wip = W(k, j, ip), b.wim = W(k, j, im), b.wjp = W(k, jp, i), b.wjm = W(k, jm, i);
-  b.wkp = W(kp, j, i), b.wkm = W(km, j, i), b.wkm_ip = W(km, j, ip), b.wkm_jp = W(km, jp, i);
-  b.n0 = NU(k, j, i), b.nip = NU(k, j, ip), b.nim = NU(k, j, im), b.njp = NU(k, jp, i), b.njm = NU(k, jm, i);
-  b.nkp = NU(kp, j, i), b.nkm = NU(km, j, i);
-  b.n_jp_ip = NU(k, jp, ip), b.n_jm_ip = NU(k, jm, ip), b.n_kp_ip = NU(kp, j, ip), b.n_km_ip = NU(km, j, ip);
-  b.n_jp_im = NU(k, jp, im), b.n_kp_jp = NU(kp, jp, i), b.n_km_jp = NU(km, jp, i), b.n_kp_im = NU(kp, j, im);
-  b.n_kp_jm = NU(kp, jm, i);
-  b.p0 = p[idx3(g, k, j, i)], b.pip = p[idx3(g, k, j, ip)], b.pjp = p[idx3(g, k, jp, i)];
-  b.pkp = p[idx3(g, kp, j, i)];
-#undef U
-#undef V
-#undef W
-#undef NU
-  const int64_t c0 = idx3(g, k, j, i);
-  T rup = (T)0, rvp = (T)0, rwp = (T)0;
-  if (use_rprev) {
-    rup = ru[c0];
-    rvp = rv[c0];
-    rwp = rw[c0];
-  }
-  T Ru, Rv, Rw, uo, vo, wo;
-  predictor_cell<T, IMPLICIT>(b, g, k, (T)dtp[0], alpha, beta, gamma, use_rprev != 0, rup, rvp, rwp, Ru, Rv, Rw, uo,
-                              vo, wo);
-  if (write_r) {
-    ru[c0] = Ru;
-    rv[c0] = Rv;
-    rw[c0] = Rw;
-  }
-  us[c0] = uo;
-  vs[c0] = vo;
-  ws[c0] = wo;
 }
 
 // z-marching predictor: a 32 x 8 tile walks a chunk of kc planes.  A ring of three planes of
@@ -246,7 +202,7 @@ constexpr int TX = 32, TY = 8, NT = TX * TY;
 constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY, NL = (N1 + NT - 1) / NT;
 }  // namespace zmarch
 
-template <typename T, bool IMPLICIT>
+template <typename T, int MODE>
 __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, const T* __restrict__ u,
                                                   const T* __restrict__ v, const T* __restrict__ w,
                                                   const T* __restrict__ p, const T* __restrict__ nut,
@@ -254,7 +210,8 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
                                                   T* __restrict__ rv, T* __restrict__ rw, T* __restrict__ us,
                                                   T* __restrict__ vs, T* __restrict__ ws,
                                                   const double* __restrict__ dtp, double alpha, double beta,
-                                                  double gamma, int use_rprev, int write_r, int kc, int chunk) {
+                                                  double gamma, int use_rprev, int write_r, int kc, int chunk,
+                                                  const double* __restrict__ tau, int wallmodel) {
   using namespace zmarch;
   __shared__ T ring[3][5][N1];   // [plane slot][u v w nu p][tile + 1 halo]
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
@@ -333,8 +290,17 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
         rwp = rw[c0];
       }
       T Ru, Rv, Rw, uo, vo, wo;
-      predictor_cell<T, IMPLICIT>(b, g, k, dt, alpha, beta, gamma, use_rprev != 0, rup, rvp, rwp, Ru, Rv, Rw, uo,
-                                  vo, wo);
+      predictor_cell<T, MODE>(b, g, k, dt, alpha, beta, gamma, use_rprev != 0, rup, rvp, rwp, Ru, Rv, Rw, uo, vo,
+                              wo);
+      if (MODE == VISC_CN_3D && wallmodel && (k == 1 || k == g.nz)) {
+        // wall-model rows: the lagged wall stress enters as a known flux (as in CN in z)
+        const double ch = gamma * g.nu * dtp[0] / 2.0;
+        const int64_t cj = (int64_t)j * g.nx + i;
+        const int b0 = k == 1 ? 0 : 2;
+        const double rz = 1.0 / g.dzf[k];
+        uo = (T)((double)uo + ch * (-(tau[b0 * sxy + cj] / g.nu) * rz));
+        vo = (T)((double)vo + ch * (-(tau[(b0 + 1) * sxy + cj] / g.nu) * rz));
+      }
       if (write_r) {
         ru[c0] = Ru;
         rv[c0] = Rv;
@@ -348,7 +314,7 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
   }
 }
 
-template <typename T, bool IMPLICIT>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) k_predictor(GridP g, const T* __restrict__ u,
                                                                         const T* __restrict__ v,
                                                                         const T* __restrict__ w,
@@ -361,17 +327,19 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) k_predictor(GridP
                                                                         const double* __restrict__ dtp,
                                                                         double alpha, double beta, double gamma,
                                                                         int use_rprev, int write_r, double* hfac,
-                                                                        int wallmodel, int kc) {
+                                                                        int wallmodel, int kc,
+                                                                        const double* __restrict__ tau) {
   const dim3 bid = xcd_tile(blockIdx, gridDim);
-  if (IMPLICIT && bid.z == 0) {
+  if (MODE != VISC_EXPLICIT && bid.z == 0) {
     __shared__ double fz[2][kMaxNz + 2];   // metric copies of the factorisation
     if (bid.x == 0 && bid.y == 0)
       helmholtz_factor_body(g, hfac, dtp, gamma, wallmodel, fz[0], fz[1], threadIdx.y * blockDim.x + threadIdx.x,
                             blockDim.x * blockDim.y);
     return;
   }
-  predictor_zm_body<T, IMPLICIT>(bid, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta, gamma,
-                                 use_rprev, write_r, kc, IMPLICIT ? (int)bid.z - 1 : (int)bid.z);
+  predictor_zm_body<T, MODE>(bid, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta, gamma,
+                             use_rprev, write_r, kc, MODE != VISC_EXPLICIT ? (int)bid.z - 1 : (int)bid.z, tau,
+                             wallmodel);
 }
 
 // Batched predictor (explicit viscous terms): one launch over all boxes of a batch, the same
@@ -382,9 +350,10 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) kb_predictor(Batc
   int box;
   const dim3 bid = batch_bid(m, BK_PRED, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
-  predictor_zm_body<T, false>(bid, d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w, (const T*)d.p,
-                              (const T*)d.nut, d.coef, (T*)d.ru, (T*)d.rv, (T*)d.rw, (T*)d.us, (T*)d.vs, (T*)d.wsf,
-                              d.dt, alpha, beta, gamma, use_rprev, write_r, d.pkc, (int)bid.z);
+  predictor_zm_body<T, VISC_EXPLICIT>(bid, d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w, (const T*)d.p,
+                                      (const T*)d.nut, d.coef, (T*)d.ru, (T*)d.rv, (T*)d.rw, (T*)d.us, (T*)d.vs,
+                                      (T*)d.wsf, d.dt, alpha, beta, gamma, use_rprev, write_r, d.pkc, (int)bid.z,
+                                      nullptr, 0);
 }
 
 template <typename T>
@@ -395,16 +364,18 @@ void launch_predictor(Ctx& c, int stage) {
   using namespace zmarch;
   const int kc = c.pred_kc;
   const unsigned nch = (unsigned)((c.g.nz + kc - 1) / kc);
-  const dim3 grid((c.g.nx + TX - 1) / TX, (c.g.ny + TY - 1) / TY, nch + (c.cfg.implicit_z ? 1 : 0));
+  const int mode = c.cfg.implicit_z;   // VISC_* (validated at init)
+  const dim3 grid((c.g.nx + TX - 1) / TX, (c.g.ny + TY - 1) / TY, nch + (mode != VISC_EXPLICIT ? 1 : 0));
   const int use_rprev = stage > 0;
   const int write_r = stage < 2;
-  auto f = c.cfg.implicit_z ? k_predictor<T, true> : k_predictor<T, false>;
+  auto f = mode == VISC_CN_3D ? k_predictor<T, VISC_CN_3D>
+                              : (mode == VISC_CN_Z ? k_predictor<T, VISC_CN_Z> : k_predictor<T, VISC_EXPLICIT>);
   const double pts = (double)c.g.sxy * c.g.nz;
   const double words = 8 + 3 * use_rprev + 3 * write_r;
   LES_LAUNCH(c, "predictor", words * pts * sizeof(T), f, grid, dim3(TX, TY), 0, c.g, (const T*)c.u, (const T*)c.v,
              (const T*)c.w, (const T*)c.p, (const T*)c.nut, c.t.coef, (T*)c.ru, (T*)c.rv, (T*)c.rw, (T*)c.us,
              (T*)c.vs, (T*)c.wsf, c.t.dt, A[stage], B[stage], G, use_rprev, write_r, c.t.hfac,
-             c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, kc);
+             c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, kc, c.t.tau);
 }
 
 // ============================================================================ CN in z
@@ -432,6 +403,10 @@ __device__ void helmholtz_factor_body(const GridP& g, double* hfac, const double
   double* qv = hfac + 4 * n;
   double* a_uv = hfac + 6 * n;
   double* a_w = hfac + 7 * n;
+  double* b_uv = hfac + 8 * n;    // diagonal and super-diagonal of the rows (CN in all
+  double* c_uv = hfac + 9 * n;    // directions shifts the diagonal per wavenumber pair)
+  double* b_w = hfac + 10 * n;
+  double* c_w = hfac + 11 * n;
   if (tid == 0) {
     double cprev = 0.0, dp = 0.0;
     for (int kk = 1; kk <= n; ++kk) {
@@ -446,13 +421,15 @@ __device__ void helmholtz_factor_body(const GridP& g, double* hfac, const double
       const double r = 1.0 / (b - a * cprev);
       rp_uv[kk - 1] = r;
       a_uv[kk - 1] = a;
+      b_uv[kk - 1] = b;
+      c_uv[kk - 1] = cc;
       cprev = cc * r;
       cp_uv[kk - 1] = cprev;
       // forward sweep of q = H^-1 1 (bulk-forcing profile, no-slip rows) alongside
       dp = (1.0 - a * dp) * r;
       qv[kk - 1] = dp;
     }
-    if (!wallmodel) {
+    if (g.zbc == LES_ZBC_NOSLIP) {
       for (int kk = n - 1; kk >= 1; --kk) qv[kk - 1] = qv[kk - 1] - cp_uv[kk - 1] * qv[kk];
     } else {
       for (int kk = 0; kk < n; ++kk) qv[kk] = 1.0;
@@ -471,6 +448,8 @@ __device__ void helmholtz_factor_body(const GridP& g, double* hfac, const double
       const double r = 1.0 / (b - a * cprev);
       rp_w[kk - 1] = r;
       a_w[kk - 1] = a;
+      b_w[kk - 1] = b;
+      c_w[kk - 1] = cc;
       cprev = cc * r;
       cp_w[kk - 1] = cprev;
     }
@@ -628,9 +607,14 @@ __device__ __forceinline__ void correct_body(dim3 bid, GridP g, const T* __restr
   else wn = ws[c0] - gdt * ((phz - ph) * (T)(1.0 / g.dzc[k]));
   T pn = p[c0] + ph;
   if (implicit) {
+    // Eq. p_update_imp1d (L_zz) or Eq. p_update_imp3d (full Laplacian)
     const T phm = phi[idx3(g, km, j, i)];
-    const T lz = ((phz - ph) * (T)(1.0 / g.dzc[k]) - (ph - phm) * (T)(1.0 / g.dzc[k - 1])) * (T)(1.0 / g.dzf[k]);
-    pn = pn - (T)(gamma * g.nu * dtp[0] / 2.0) * lz;
+    T lap = ((phz - ph) * (T)(1.0 / g.dzc[k]) - (ph - phm) * (T)(1.0 / g.dzc[k - 1])) * (T)(1.0 / g.dzf[k]);
+    if (implicit == 2) {
+      const T phxm = phi[idx3(g, k, j, wrap_m(i, g.nx))], phym = phi[idx3(g, k, wrap_m(j, g.ny), i)];
+      lap = (phx - (T)2 * ph + phxm) * (T)(g.rdx * g.rdx) + (phy - (T)2 * ph + phym) * (T)(g.rdy * g.rdy) + lap;
+    }
+    pn = pn - (T)(gamma * g.nu * dtp[0] / 2.0) * lap;
   }
   u[c0] = un;
   v[c0] = vn;
@@ -852,13 +836,16 @@ void launch_dt(Ctx& c, double cfl) {
   const int nblk = 512;
   LES_LAUNCH(c, "cfl_partial", 4.0 * c.g.sxy * c.g.nz * sizeof(T), k_cfl_partial<T>, dim3(nblk), dim3(256), 0, c.g, (const T*)c.u, (const T*)c.v,
                      (const T*)c.w, (const T*)c.nut, c.t.coef, c.t.red);
+  // viscous limit: z term dropped with CN in z; with CN in all directions only the explicit
+  // SGS viscosity limits (molecular viscosity passed as 0)
   double sinv = 1.0 / (c.g.dx * c.g.dx) + 1.0 / (c.g.dy * c.g.dy);
-  if (!c.cfg.implicit_z) {
+  if (c.cfg.implicit_z != VISC_CN_Z) {
     double dmin = 1e300;
     for (int k = 1; k <= c.g.nz; ++k) dmin = std::min(dmin, c.dzf[k]);
     sinv += 1.0 / (dmin * dmin);
   }
-  LES_LAUNCH(c, "cfl_final", 0, k_cfl_final, dim3(1), dim3(256), 0, c.t.red, nblk, c.t.dt, cfl, c.cfg.nu, sinv);
+  const double nuv = c.cfg.implicit_z == VISC_CN_3D ? 0.0 : c.cfg.nu;
+  LES_LAUNCH(c, "cfl_final", 0, k_cfl_final, dim3(1), dim3(256), 0, c.t.red, nblk, c.t.dt, cfl, nuv, sinv);
 }
 
 __global__ void k_set_dt(double* dtp, double dt) {

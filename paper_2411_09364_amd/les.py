@@ -14,6 +14,7 @@ LES_OK, LES_EINVAL, LES_ENOMEM, LES_EDEVICE, LES_ENOTSUP, LES_ENONFINITE, LES_ES
 ZBC_PERIODIC, ZBC_NOSLIP, ZBC_WALLMODEL = 0, 1, 2
 SGS_NONE, SGS_SMAG, SGS_SMAG_VD, SGS_DSM, SGS_MLP = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
+VISC_EXPLICIT, VISC_CN_Z, VISC_CN_3D = 0, 1, 2
 FIELD_U, FIELD_V, FIELD_W, FIELD_P, FIELD_WORKSPACE, FIELD_NUT, FIELD_CS, FIELD_TAUW, FIELD_ZGRID = range(9)
 ABI_VERSION = 1
 

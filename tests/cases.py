@@ -21,7 +21,8 @@ def make_pair(nx, ny, nz, lx, ly, lz, **kw):
     case = oracle.Case(nx, ny, nz, lx, ly, lz, **kw)
     g = oracle.Grid(case)
     cfg = les.make_config(nx, ny, nz, lx, ly, lz, zbc=case.zbc, beta=case.beta, nu=case.nu,
-                          sgs=case.sgs, cs=case.cs, implicit_z=int(case.implicit_z),
+                          sgs=case.sgs, cs=case.cs,
+                          implicit_z=2 if case.implicit_3d else int(case.implicit_z),
                           precision=precision, ubulk=case.ubulk, h_wm=case.h_wm,
                           kappa=case.kappa, bconst=case.bconst)
     return case, g, cfg

@@ -38,7 +38,8 @@ def _init(**kw):
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=30), -4), (dict(ny=1022), -4), (dict(nx=2048), -4), (dict(nz=20), -4),
     (dict(lx=-1.0), -1), (dict(nu=0.0), -1), (dict(zbc=7), -1), (dict(sgs=9), -1),
-    (dict(implicit_z=1), -4), (dict(precision=3), -1), (dict(zbc=1, nz=3), -1),
+    (dict(implicit_z=1), -4), (dict(implicit_z=3), -1), (dict(implicit_z=-1), -1),
+    (dict(precision=3), -1), (dict(zbc=1, nz=3), -1),
     (dict(zbc=2, nz=16, beta=1.0, h_wm=5.0), -1), (dict(cs=-0.1), -1), (dict(beta=float("nan")), -1),
 ])
 def test_invalid_configurations_rejected(kw, status):
@@ -63,6 +64,15 @@ def test_valid_configurations_and_layout():
     with pytest.raises(les.LesError) as e:
         les.les_bind(ctx, les.FIELD_U, 8)          # misaligned pointer, checked on the host
     assert e.value.status == les.LES_EINVAL
+    les.les_free(ctx)
+
+
+@pytest.mark.parametrize("zbc", [0, 1, 2])
+def test_cn_in_all_directions_accepted_for_every_z_condition(zbc):
+    from paper_2411_09364_amd import les
+    kw = dict(zbc=zbc, nz=16) if zbc else {}
+    ctx = _init(implicit_z=les.VISC_CN_3D, sgs=les.SGS_DSM, **kw)
+    assert les.les_layout(ctx, les.FIELD_WORKSPACE).bytes > 0
     les.les_free(ctx)
 
 

@@ -136,6 +136,19 @@ SUBSTEP_CASES = [
     ("wm explicit dsm radix3",
      dict(nx=96, ny=48, nz=12, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=5e-5,
           sgs=SGS_DSM, ubulk=1.0), "channel", 3),
+    # Crank-Nicolson in all directions: periodic (FFT in z), no-slip and wall-model channels
+    ("cn-3d periodic dsm",
+     dict(nx=24, ny=24, nz=24, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, nu=2e-2, sgs=SGS_DSM, implicit_3d=True),
+     "iso", 3),
+    ("cn-3d noslip bulk no model",
+     dict(nx=32, ny=12, nz=16, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_NOSLIP, beta=1.2, nu=1e-2,
+          sgs=SGS_NONE, implicit_3d=True, ubulk=1.0), "channel", 6),
+    ("cn-3d wm dsm bulk",
+     dict(nx=48, ny=24, nz=20, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=5e-4,
+          sgs=SGS_DSM, implicit_3d=True, ubulk=1.0), "channel", 3),
+    ("cn-3d noslip vd radix3 rect",
+     dict(nx=96, ny=48, nz=12, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_NOSLIP, beta=1.5, nu=2e-3,
+          sgs=SGS_SMAG_VD, cs=0.1), "channel", 3),
 ]
 
 
@@ -175,9 +188,12 @@ def test_substeps_match_oracle(les, name, cfgd, kind, nsub):
     solver.close()
 
 
-def test_time_step_matches_oracle(les):
+@pytest.mark.parametrize("visc", ["cn-z", "cn-3d", "cn-3d no model"])
+def test_time_step_matches_oracle(les, visc):
+    extra = dict(implicit_z=True) if visc == "cn-z" else dict(implicit_3d=True)
+    sgs = SGS_NONE if visc.endswith("no model") else SGS_DSM
     case, g, cfg = make_pair(nx=48, ny=24, nz=20, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL,
-                             beta=1.5, nu=5e-5, sgs=SGS_DSM, implicit_z=True, ubulk=1.0)
+                             beta=1.5, nu=5e-5, sgs=sgs, ubulk=1.0, **extra)
     u, v, w = initial_fields(case, g, 3, "channel")
     st = S.initial_state(case, g, u, v, w)
     solver = les.Solver(cfg)
@@ -196,6 +212,8 @@ MIXED_CASES = [
           sgs=SGS_DSM, ubulk=1.0), "channel"),
     ("mixed periodic dsm", dict(nx=32, ny=32, nz=32, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, nu=1e-3,
                                 sgs=SGS_DSM), "iso"),
+    ("mixed cn-3d wm dsm", dict(nx=48, ny=24, nz=20, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL,
+                                beta=1.5, nu=5e-4, sgs=SGS_DSM, implicit_3d=True, ubulk=1.0), "channel"),
 ]
 
 
