@@ -201,6 +201,9 @@ size_t carve(Ctx& c, char* base) {
   c.spec = take(nxp * f.ny * n * 2 * E);
   // factor pairs of the z systems of every (l, m <= ny/2) column (walls only)
   t.pfac = (double*)take(f.zbc == LES_ZBC_PERIODIC ? 0 : nxp * (f.ny / 2 + 1) * n * 2 * 8);
+  // per-substep factor pairs of the Helmholtz z systems (CN in all directions, walls)
+  t.hfac3 = (double2*)take(f.zbc != LES_ZBC_PERIODIC && f.implicit_z == LES_VISC_CN_3D
+                               ? 2 * nxp * (f.ny / 2 + 1) * n * 16 : 0);
   return off;
 }
 

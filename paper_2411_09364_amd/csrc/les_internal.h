@@ -73,6 +73,8 @@ struct Tables {
   float* twx_f;     // float copies
   float* twy_f;
   float* twz_f;
+  double2* hfac3;   // CN in all directions, walls: per-substep z factor pairs, u/v rows then w rows,
+                    //   each [nz][ny/2+1][nxp]
   double* hfac;     // 12*nz: CN factorisation: c', 1/pivot for u/v rows and for w rows, the
                     //   flow-rate profile q, unused, sub-diagonals (u/v, w), diagonals and
                     //   super-diagonals (u/v, w)

@@ -394,8 +394,7 @@ __global__ void __launch_bounds__(256) kb_fft_lines(BatchMap m) {
 // per wavenumber pair), once per grid: the Poisson matrix depends on the geometry only, so
 // c'_k = c_k / p_k and 1/p_k, p_k = b_k + lambda_x(l) + lambda_y(m) - a_k c'_{k-1}, are kept
 // in the workspace ([k][m][l] pairs, FP64) for m <= ny/2; mode ny - m has the same
-// eigenvalue and reads the pairs of m.  The singular (0, 0) column is factorised where it is
-// solved.
+// eigenvalue and reads the pairs of m.
 __global__ void __launch_bounds__(256) k_thomas_factor(GridP g, const double* __restrict__ pa,
                                                        const double* __restrict__ pb, const double* __restrict__ pc,
                                                        const double* __restrict__ lamx,
@@ -405,16 +404,20 @@ __global__ void __launch_bounds__(256) k_thomas_factor(GridP g, const double* __
   const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (col >= ncol) return;
   const int l = (int)(col % g.nxp), m = (int)(col / g.nxp);
-  if ((l == 0 && m == 0) || l >= nxh) return;
+  if (l >= nxh) return;
   const double lam = lamx[l] + lamy[m];
+  // the singular (0, 0) column pins its last unknown: rows 0..nz-2 factorised, the last row
+  // stored as (0, 0) so that the solve returns x = 0 there
+  const int nr = col == 0 ? g.nz - 1 : g.nz;
   double cprev = 0.0;
-  for (int k = 0; k < g.nz; ++k) {
+  for (int k = 0; k < nr; ++k) {
     const double a = pa[k];
     const double rr = 1.0 / ((pb[k] + lam) - a * cprev);
     const double cc = pc[k] * rr;
     pfac[(int64_t)k * ncol + col] = make_double2(cc, rr);
     cprev = cc;
   }
+  if (nr < g.nz) pfac[(int64_t)nr * ncol + col] = make_double2(0.0, 0.0);
 }
 
 void launch_thomas_factor(Ctx& c) {
@@ -423,212 +426,171 @@ void launch_thomas_factor(Ctx& c) {
                      c.t.pb, c.t.pc, c.t.lamx, c.t.lamy, (double2*)c.t.pfac);
 }
 
-// FP64 Thomas solve along z for every (l, m) column with the stored factors, staged through
-// LDS: a block takes TC consecutive columns of the flattened (m, l) index (contiguous in each
-// plane); all threads load the nz x TC complex right-hand sides (scaled by the transform
-// normalisation, held in double) with their factor pairs, two threads per column (real and
-// imaginary parts) run the forward and back substitution from LDS, all threads store.  The
-// singular (0, 0) column has its last unknown pinned to zero, the first nz-1 rows solved and
-// the dzf-weighted mean removed.
-template <typename T>
-__global__ void __launch_bounds__(256) k_thomas(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ pa,
-                                                const double* __restrict__ pb, const double* __restrict__ pc,
-                                                const double2* __restrict__ pfac, double norm, int tc) {
-  extern __shared__ double tsm[];
-  const int nxh = g.nx / 2 + 1;
-  const int64_t ncol = (int64_t)g.nxp * g.ny;   // flattened (m, l) over the padded rows
-  const int n = g.nz;
-  const int64_t col0 = (int64_t)blockIdx.x * tc;
-  const int cw = (int)(ncol - col0 < tc ? ncol - col0 : tc);
-  cpx<T>* x = spec + col0;
-  const int64_t nfac = (int64_t)g.nxp * (g.ny / 2 + 1);   // factor pairs per plane
-  double* fx = tsm;                        // [n][tc][re, im]
-  double* fc = tsm + 2 * (size_t)n * tc;   // [n][tc][c', 1/pivot]
-  double* rows = fc + 2 * (size_t)n * tc;  // a, b, c of the rows
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    rows[e] = pa[e];
-    rows[n + e] = pb[e];
-    rows[2 * n + e] = pc[e];
+// FP64 z solves of every (l, m) column with the stored factors, by segmented scans.  A
+// column gives two chains (real and imaginary parts), and there are only a few tens of
+// thousands of chains of nz rows: a plain Thomas sweep per chain leaves most of the chip
+// idle behind its dependent chain.  Both sweeps are first-order linear recurrences,
+//   forward d_k = r_k f_k + alpha_k d_{k-1} (alpha_k = -a_k r_k, r_k = 1/pivot),
+//   back    x_k = d_k - c'_k x_{k+1},
+// so each chain is cut into segments of S rows, one thread per segment.  A thread runs the
+// recurrence over its segment from a zero start while carrying the product of its
+// coefficients; the segment end values are combined in order through LDS (the start value of
+// segment p is a short fold over segments 0..p-1), and every row is corrected by product x
+// start.  Same for the back sweep from the top.  Threads: CG consecutive chains (adjacent in
+// memory, so each row load of a segment group is contiguous) times the segments.  Rows are
+// held in registers, loaded once and stored once.  ZERO (Poisson): the pinned (0, 0) column
+// has its own factor pairs (last row zero); its dzf-weighted mean is removed here and its
+// imaginary part set to zero.  Rows nrow..nz-1 are left as they are (the wall face of w in
+// the Helmholtz solves).
+template <typename T, int S, bool ZERO>
+__global__ void __launch_bounds__(1024) k_thomas_scan(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ pa,
+                                                      const double2* __restrict__ pfac, double norm, int nrow) {
+  constexpr int CG = 32;
+  __shared__ double E[32][CG], G[32][CG];
+  const int cl = (int)threadIdx.x % CG, p = (int)threadIdx.x / CG, P = (int)blockDim.x / CG;
+  const int n = nrow, nxh = g.nx / 2 + 1;
+  const int64_t ncol = (int64_t)g.nxp * g.ny, ncol2 = 2 * ncol;
+  const int64_t c2 = (int64_t)blockIdx.x * CG + cl;
+  const int64_t col = c2 >> 1;
+  const int l = (int)(col % g.nxp), m = (int)(col / g.nxp);
+  const bool ok = c2 < ncol2 && l < nxh;
+  const int mm = m <= g.ny / 2 ? m : g.ny - m;   // mode ny - m uses the pairs of m
+  const int64_t nfac = (int64_t)g.nxp * (g.ny / 2 + 1);
+  const double2* fp = pfac + (ok ? (int64_t)mm * g.nxp + l : 0);
+  T* x = reinterpret_cast<T*>(spec) + (ok ? c2 : 0);
+  const int k0 = p * S;
+  double v[S];
+  double2 fc[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const int k = k0 + j;
+    const bool in = ok && k < n;
+    v[j] = in ? (double)x[(int64_t)k * ncol2] * norm : 0.0;
+    fc[j] = in ? fp[(int64_t)k * nfac] : make_double2(0.0, 0.0);
   }
-  // loads in batches of TB per thread, all issued before their LDS stores
-  constexpr int TB = 8;
-  const int total = n * tc;
-  for (int e0 = 0; e0 < total; e0 += TB * (int)blockDim.x) {
-    cpx<T> v[TB];
-    double2 w[TB];
+  // forward: local recurrence from zero, product of the alphas
+  double dl = 0.0, pr = 1.0;
 #pragma unroll
-    for (int b = 0; b < TB; ++b) {
-      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
-      const int k = e / tc, q = e % tc;
-      const int64_t o = (e < total && q < cw) ? (int64_t)k * ncol + q : 0;
-      v[b] = x[o];
-      const int64_t cc = col0 + (e < total && q < cw ? q : 0);
-      const int64_t m = cc / g.nxp;
-      const int64_t mm = m <= g.ny / 2 ? m : g.ny - m;   // mode ny - m uses the pairs of m
-      w[b] = pfac[((e < total && q < cw) ? (int64_t)k * nfac : 0) + mm * g.nxp + cc % g.nxp];
+  for (int j = 0; j < S; ++j) {
+    const int k = k0 + j;
+    if (k < n) {
+      const double al = -pa[k] * fc[j].y;
+      dl = fc[j].y * v[j] + al * dl;
+      pr = al * pr;
+      v[j] = dl;
     }
+  }
+  E[p][cl] = dl;
+  G[p][cl] = pr;
+  __syncthreads();
+  double D = 0.0;
+  for (int q = 0; q < p; ++q) D = E[q][cl] + G[q][cl] * D;
+  pr = 1.0;
 #pragma unroll
-    for (int b = 0; b < TB; ++b) {
-      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
-      if (e < total) {
-        fx[2 * e] = (double)v[b].x * norm;
-        fx[2 * e + 1] = (double)v[b].y * norm;
-        fc[2 * e] = w[b].x;
-        fc[2 * e + 1] = w[b].y;
-      }
+  for (int j = 0; j < S; ++j) {
+    const int k = k0 + j;
+    if (k < n) {
+      pr *= -pa[k] * fc[j].y;
+      v[j] += pr * D;
+    }
+  }
+  // back: local recurrence from zero above the segment, product of the -c'
+  double xl = 0.0, ps = 1.0;
+#pragma unroll
+  for (int j = S - 1; j >= 0; --j) {
+    const int k = k0 + j;
+    if (k < n) {
+      xl = v[j] - fc[j].x * xl;
+      ps = -fc[j].x * ps;
+      v[j] = xl;
     }
   }
   __syncthreads();
-  const double* ra = rows;           // sub-diagonal
-  const double* rb = rows + n;       // diagonal without the eigenvalues
-  const double* rc = rows + 2 * n;   // super-diagonal
-  const int t = threadIdx.x;
-  if (t < 2 * cw) {
-    const int q = t >> 1, r = t & 1;
-    const int64_t cidx = col0 + q;
-    const int fs = 2 * tc;
-    double* f = fx + 2 * q + r;   // row k at f[k fs]
-    const double* cf = fc + 2 * q;   // row k: c' at cf[k fs], 1/pivot at cf[k fs + 1]
-    if ((int)(cidx % g.nxp) >= nxh) {
-      // padding column of a row: not a mode, left as it is
-    } else if (cidx == 0) {
-      if (r == 0) {
-        // singular column: its own factorisation (last unknown pinned), in the c' slots
-        double* cq = fc + 2 * q;
-        const int nn = n - 1;
-        double cprev = 0.0, dprev = 0.0;
-        for (int k = 0; k < nn; ++k) {
-          const double a = ra[k];
-          const double piv = rb[k] - a * cprev;
-          const double cc = rc[k] / piv;
-          const double d = (f[k * fs] - a * dprev) / piv;
-          f[k * fs] = d;
-          cq[k * fs] = cc;
-          cprev = cc;
-          dprev = d;
-        }
-        double xn = dprev;
-        for (int k = nn - 2; k >= 0; --k) {
-          xn = f[k * fs] - cq[k * fs] * xn;
-          f[k * fs] = xn;
-        }
-        f[(n - 1) * fs] = 0.0;
-        double sw = 0.0, sd = 0.0;
-        for (int k = 0; k < n; ++k) {
-          sw += f[k * fs] * g.dzf[k + 1];
-          sd += g.dzf[k + 1];
-        }
-        const double mean = sw / sd;
-        for (int k = 0; k < n; ++k) f[k * fs] -= mean;
-      } else {
-        for (int k = 0; k < n; ++k) f[k * fs] = 0.0;
-      }
-    } else {
-      double d = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < n; ++k) {
-        d = (f[k * fs] - ra[k] * d) * cf[k * fs + 1];
-        f[k * fs] = d;
-      }
-      double xv = d;
-#pragma unroll 8
-      for (int k = n - 2; k >= 0; --k) {
-        xv = f[k * fs] - cf[k * fs] * xv;
-        f[k * fs] = xv;
-      }
+  E[p][cl] = xl;
+  G[p][cl] = ps;
+  __syncthreads();
+  double X = 0.0;
+  for (int q = P - 1; q > p; --q) X = E[q][cl] + G[q][cl] * X;
+  ps = 1.0;
+#pragma unroll
+  for (int j = S - 1; j >= 0; --j) {
+    const int k = k0 + j;
+    if (k < n) {
+      ps *= -fc[j].x;
+      v[j] += ps * X;
     }
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < n * tc; e += blockDim.x) {
-    const int k = e / tc, q = e % tc;
-    if (q < cw) x[(int64_t)k * ncol + q] = {(T)fx[2 * e], (T)fx[2 * e + 1]};
+  if (ZERO && blockIdx.x == 0) {
+    // zero mode: chains 0 (real part) and 1 (imaginary part) of this block
+    double sw = 0.0, sd = 0.0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int k = k0 + j;
+      if (k < n) {
+        sw += v[j] * g.dzf[k + 1];
+        sd += g.dzf[k + 1];
+      }
+    }
+    __syncthreads();
+    if (cl == 0) {
+      E[p][0] = sw;
+      G[p][0] = sd;
+    }
+    __syncthreads();
+    if (cl == 0) {
+      double tw = 0.0, td = 0.0;
+      for (int q = 0; q < P; ++q) {
+        tw += E[q][0];
+        td += G[q][0];
+      }
+      const double mean = tw / td;
+#pragma unroll
+      for (int j = 0; j < S; ++j) v[j] -= mean;
+    } else if (cl == 1) {
+#pragma unroll
+      for (int j = 0; j < S; ++j) v[j] = 0.0;
+    }
+  }
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int k = k0 + j;
+      if (k < n) x[(int64_t)k * ncol2] = (T)v[j];
+    }
   }
 }
 
 // Crank-Nicolson in all directions, wall-bounded z (Eq. onestar_imp3d): after FFTs in x and
 // y, every (l, m) column holds the tridiagonal system with rows a_k, b_k - c (lamx(l) +
 // lamy(m)), c_k (c = gamma nu dt / 2; a, b, c the CN-z rows of the component, wall folds
-// included) and is solved by the Thomas algorithm in FP64.  The pivots depend on dt, so the
-// factorisation runs here, per column, alongside the forward sweep.  Same LDS staging as
-// k_thomas: tc columns of the flattened (m, l) index per block, two threads per column (real
-// and imaginary parts; each keeps its own copy of the normalised super-diagonal), nrow rows
-// solved (nz for u and v, nz - 1 for w, whose last plane is the wall face and stays zero).
-template <typename T>
-__global__ void __launch_bounds__(256) k_helm3d_z(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ ra_g,
-                                                  const double* __restrict__ rb_g, const double* __restrict__ rc_g,
-                                                  const double* __restrict__ lamx, const double* __restrict__ lamy,
-                                                  const double* __restrict__ dtp, double hg, double norm, int nrow,
-                                                  int tc) {
-  extern __shared__ double hsm3[];
-  const int nxh = g.nx / 2 + 1;
-  const int64_t ncol = (int64_t)g.nxp * g.ny;
-  const int n = g.nz;
-  const int64_t col0 = (int64_t)blockIdx.x * tc;
-  const int cw = (int)(ncol - col0 < tc ? ncol - col0 : tc);
-  cpx<T>* x = spec + col0;
-  double* fx = hsm3;                        // [n][tc][re, im]
-  double* fc = hsm3 + 2 * (size_t)n * tc;   // [n][tc][c' of the re thread, c' of the im thread]
-  double* rows = fc + 2 * (size_t)n * tc;   // a, b, c
-  for (int e = threadIdx.x; e < nrow; e += blockDim.x) {
-    rows[e] = ra_g[e];
-    rows[n + e] = rb_g[e];
-    rows[2 * n + e] = rc_g[e];
-  }
-  constexpr int TB = 8;
-  const int total = n * tc;
-  for (int e0 = 0; e0 < total; e0 += TB * (int)blockDim.x) {
-    cpx<T> v[TB];
-#pragma unroll
-    for (int b = 0; b < TB; ++b) {
-      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
-      const int k = e / tc, q = e % tc;
-      v[b] = x[(e < total && q < cw) ? (int64_t)k * ncol + q : 0];
-    }
-#pragma unroll
-    for (int b = 0; b < TB; ++b) {
-      const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
-      if (e < total) {
-        fx[2 * e] = (double)v[b].x * norm;
-        fx[2 * e + 1] = (double)v[b].y * norm;
-      }
-    }
-  }
-  __syncthreads();
-  const int t = threadIdx.x;
-  if (t < 2 * cw) {
-    const int q = t >> 1, r = t & 1;
-    const int64_t cidx = col0 + q;
-    const int l = (int)(cidx % g.nxp), m = (int)(cidx / g.nxp);
-    if (l < nxh) {
-      const int fs = 2 * tc;
-      double* f = fx + 2 * q + r;
-      double* cq = fc + 2 * q + r;
-      const double shift = hg * dtp[0] * (lamx[l] + lamy[m]);
-      const double* ra = rows;
-      const double* rb = rows + n;
-      const double* rc = rows + 2 * n;
-      double cprev = 0.0, d = 0.0;
-#pragma unroll 4
-      for (int k = 0; k < nrow; ++k) {
-        const double a = ra[k];
-        const double rp = 1.0 / ((rb[k] - shift) - a * cprev);
-        d = (f[k * fs] - a * d) * rp;
-        cprev = rc[k] * rp;
-        f[k * fs] = d;
-        cq[k * fs] = cprev;
-      }
-      double xv = d;
-#pragma unroll 4
-      for (int k = nrow - 2; k >= 0; --k) {
-        xv = f[k * fs] - cq[k * fs] * xv;
-        f[k * fs] = xv;
-      }
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < n * tc; e += blockDim.x) {
-    const int k = e / tc, q = e % tc;
-    if (q < cw) x[(int64_t)k * ncol + q] = {(T)fx[2 * e], (T)fx[2 * e + 1]};
+// included), solved in FP64.  The pivots depend on dt, so the factor pairs (c', 1/pivot) of
+// this substep are formed here, once for the u/v rows and once for the w rows, for m <=
+// ny/2 (mode ny - m has the same eigenvalue); the solves are k_thomas_scan.  One thread per
+// (column, row set).
+__global__ void __launch_bounds__(256) k_helm3d_factor(GridP g, const double* __restrict__ hfac,
+                                                       const double* __restrict__ lamx,
+                                                       const double* __restrict__ lamy,
+                                                       const double* __restrict__ dtp, double hg,
+                                                       double2* __restrict__ fac) {
+  const int nxh = g.nx / 2 + 1, n = g.nz;
+  const int64_t nfac = (int64_t)g.nxp * (g.ny / 2 + 1);
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= 2 * nfac) return;
+  const int w = t >= nfac;
+  const int64_t col = w ? t - nfac : t;
+  const int l = (int)(col % g.nxp), m = (int)(col / g.nxp);
+  if (l >= nxh) return;
+  const double shift = hg * dtp[0] * (lamx[l] + lamy[m]);
+  const double* ra = hfac + (w ? 7 : 6) * n;
+  const double* rb = hfac + (w ? 10 : 8) * n;
+  const double* rc = hfac + (w ? 11 : 9) * n;
+  double2* f = fac + (w ? (int64_t)n * nfac : 0) + col;
+  const int nr = w ? n - 1 : n;
+  double cprev = 0.0;
+  for (int k = 0; k < nr; ++k) {
+    const double r = 1.0 / ((rb[k] - shift) - ra[k] * cprev);
+    cprev = rc[k] * r;
+    f[(int64_t)k * nfac] = make_double2(cprev, r);
   }
 }
 
@@ -745,14 +707,6 @@ static void fftz_solve(Ctx& c, const char* name, double hg) {
              c.t.dt, hg);
 }
 
-// columns per block of the LDS-staged z solves: the largest power of two <= 32 whose LDS
-// (32 bytes per entry and the rows) stays within 64 KB
-static int zsolve_columns(int nz) {
-  int tc = 32;
-  while (tc > 2 && (size_t)nz * (32 * tc + 24) > 65536) tc /= 2;
-  return tc;
-}
-
 template <typename T>
 static void spectral_solve(Ctx& c) {
   const int nxh = c.g.nx / 2 + 1;
@@ -763,13 +717,19 @@ static void spectral_solve(Ctx& c) {
   if (c.cfg.zbc == LES_ZBC_PERIODIC) {
     fftz_solve<T>(c, "fftz_solve", 0.0);
   } else {
-    const int64_t ncol = (int64_t)c.g.nxp * ny;
-    const int tc = zsolve_columns(nz);
-    const size_t sh = (size_t)nz * (32 * tc + 24);
+    // segments of 8 rows (16 beyond 256 planes): at most 32 segments of 32 chains per block
+    const int64_t nchain = 2 * (int64_t)c.g.nxp * ny;
+    const int S = nz <= 256 ? 8 : 16;
+    const int P = (nz + S - 1) / S;
+    const dim3 grid((unsigned)((nchain + 31) / 32)), block(32 * P);
     const double norm = 1.0 / ((double)c.g.nx * ny);
-    LES_LAUNCH(c, "thomas_z", 2 * spec_bytes + (double)nxh * (ny / 2 + 1) * nz * 16, (k_thomas<T>),
-               dim3((unsigned)((ncol + tc - 1) / tc)), dim3(256), sh, c.g, sp, c.t.pa, c.t.pb, c.t.pc,
-               (const double2*)c.t.pfac, norm, tc);
+    const double bytes = 2 * spec_bytes + (double)nxh * (ny / 2 + 1) * nz * 16;
+    if (S == 8)
+      LES_LAUNCH(c, "thomas_z", bytes, (k_thomas_scan<T, 8, true>), grid, block, 0, c.g, sp, c.t.pa,
+                 (const double2*)c.t.pfac, norm, nz);
+    else
+      LES_LAUNCH(c, "thomas_z", bytes, (k_thomas_scan<T, 16, true>), grid, block, 0, c.g, sp, c.t.pa,
+                 (const double2*)c.t.pfac, norm, nz);
   }
   ffty<T, 1>(c, "ffty_inv");
 }
@@ -798,22 +758,31 @@ void launch_helmholtz_3d(Ctx& c, int stage) {
   const int n = c.g.nz;
   const double spec_bytes = (double)(c.g.nx / 2 + 1) * c.g.ny * n * 2 * sizeof(T);
   T* comp[3] = {(T*)c.us, (T*)c.vs, (T*)c.wsf};
+  const int64_t nfac = (int64_t)c.g.nxp * (c.g.ny / 2 + 1);
+  const int64_t nchain = 2 * (int64_t)c.g.nxp * c.g.ny;
+  const double norm = 1.0 / ((double)c.g.nx * c.g.ny);
+  if (c.cfg.zbc != LES_ZBC_PERIODIC)
+    LES_LAUNCH(c, "h3d_factor", 2.0 * nfac * n * 16, k_helm3d_factor, dim3((unsigned)((2 * nfac + 255) / 256)), dim3(256),
+               0, c.g, c.t.hfac, c.t.lamx, c.t.lamy, c.t.dt, hg, (double2*)c.t.hfac3);
   for (int a = 0; a < 3; ++a) {
     fwd_x<T>(c, 1, nullptr, nullptr, nullptr, comp[a], 1.0, false);
     ffty<T, -1>(c, "h3d_ffty_fwd");
     if (c.cfg.zbc == LES_ZBC_PERIODIC) {
       fftz_solve<T>(c, "h3d_fftz_solve", hg);
     } else {
-      const int64_t ncol = (int64_t)c.g.nxp * c.g.ny;
-      const int tc = zsolve_columns(n);
-      const size_t sh = (size_t)n * (32 * tc + 24);
-      const double* hf = c.t.hfac;
-      const double* ra = hf + (a < 2 ? 6 : 7) * n;
-      const double* rb = hf + (a < 2 ? 8 : 10) * n;
-      const double* rc = hf + (a < 2 ? 9 : 11) * n;
-      LES_LAUNCH(c, "h3d_thomas_z", 2 * spec_bytes, (k_helm3d_z<T>), dim3((unsigned)((ncol + tc - 1) / tc)), dim3(256),
-                 sh, c.g, (cpx<T>*)c.spec, ra, rb, rc, c.t.lamx, c.t.lamy, c.t.dt, hg,
-                 1.0 / ((double)c.g.nx * c.g.ny), a < 2 ? n : n - 1, tc);
+      const int nrow = a < 2 ? n : n - 1;
+      const int S = nrow <= 256 ? 8 : 16;
+      const int P = (nrow + S - 1) / S;
+      const dim3 grid((unsigned)((nchain + 31) / 32)), block(32 * P);
+      const double* ra = c.t.hfac + (a < 2 ? 6 : 7) * n;
+      const double2* fac = (const double2*)c.t.hfac3 + (a < 2 ? 0 : (int64_t)n * nfac);
+      const double bytes = 2 * spec_bytes + (double)nfac * n * 16;
+      if (S == 8)
+        LES_LAUNCH(c, "h3d_thomas_z", bytes, (k_thomas_scan<T, 8, false>), grid, block, 0, c.g, (cpx<T>*)c.spec, ra,
+                   fac, norm, nrow);
+      else
+        LES_LAUNCH(c, "h3d_thomas_z", bytes, (k_thomas_scan<T, 16, false>), grid, block, 0, c.g, (cpx<T>*)c.spec,
+                   ra, fac, norm, nrow);
     }
     ffty<T, 1>(c, "h3d_ffty_inv");
     inv_x<T>(c, comp[a]);

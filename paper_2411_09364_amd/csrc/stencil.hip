@@ -509,17 +509,42 @@ __global__ void __launch_bounds__(256) k_helmholtz(GridP g, T* __restrict__ us, 
       col[0] += c * (-(tau[(comp == 0 ? 0 : 1) * s + col0 + q] / g.nu) / g.dzf[1]);
       col[(n - 1) * hc] += c * (-(tau[(comp == 0 ? 2 : 3) * s + col0 + q] / g.nu) / g.dzf[n]);
     }
+    // rows in chunks of CH, every LDS read of a chunk issued before its chain
+    constexpr int CH = 8;
     double dp = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < m; ++k) {
-      dp = (col[k * hc] - av[k] * dp) * rp[k];
-      col[k * hc] = dp;
+    for (int k0 = 0; k0 < m; k0 += CH) {
+      double fv[CH], a8[CH], r8[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const int k = k0 + j < m ? k0 + j : m - 1;
+        fv[j] = col[k * hc];
+        a8[j] = av[k];
+        r8[j] = rp[k];
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        if (k0 + j < m) {
+          dp = (fv[j] - a8[j] * dp) * r8[j];
+          col[(k0 + j) * hc] = dp;
+        }
+      }
     }
     double xn = dp;
-#pragma unroll 8
-    for (int k = m - 2; k >= 0; --k) {
-      xn = col[k * hc] - cp[k] * xn;
-      col[k * hc] = xn;
+    for (int k1 = m - 2; k1 >= 0; k1 -= CH) {
+      double fv[CH], c8[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const int k = k1 - j >= 0 ? k1 - j : 0;
+        fv[j] = col[k * hc];
+        c8[j] = cp[k];
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        if (k1 - j >= 0) {
+          xn = fv[j] - c8[j] * xn;
+          col[(k1 - j) * hc] = xn;
+        }
+      }
     }
   }
   __syncthreads();

@@ -40,6 +40,11 @@ POISSON_CASES = [
     dict(nx=16, ny=16, nz=16, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, zbc=ZBC_PERIODIC),
     dict(nx=24, ny=32, nz=48, lx=1.0, ly=2.0, lz=3.0, zbc=ZBC_PERIODIC),
     dict(nx=256, ny=8, nz=5, lx=1.0, ly=1.0, lz=1.0, zbc=ZBC_NOSLIP, beta=1.2),
+    # z solves in segments: a single partial segment, a ragged last segment, and the
+    # 16-row segments used beyond 256 planes
+    dict(nx=16, ny=6, nz=4, lx=1.0, ly=1.0, lz=2.0, zbc=ZBC_NOSLIP, beta=1.5),
+    dict(nx=32, ny=16, nz=100, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5),
+    dict(nx=8, ny=8, nz=300, lx=1.0, ly=1.0, lz=2.0, zbc=ZBC_NOSLIP, beta=1.5),
 ]
 
 
