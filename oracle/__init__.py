@@ -5,7 +5,7 @@ check and the benchmark's CPU-baseline leg may import it; the library and its
 Python binding never do, and it shares no code with them.  Every function
 cites the passage of the paper (Xiao et al., "CaLES: A GPU-accelerated solver
 for large-eddy simulation of wall-bounded flows", arXiv 2411.09364) that it
-follows.  Where the paper is silent the reading taken is named R1..R27 in the
+follows.  Where the paper is silent the reading taken is named R1..R34 in the
 docstring of the function that uses it.
 
 Modules
@@ -16,6 +16,7 @@ Modules
   poisson   eigenfunction-expansion Poisson solve (Sec. 2.2, Eq. poi)
   substep   RK3 predictor, CN-z, projection, pressure update, bulk forcing, dt (Alg. 1)
   mlp       learned Smagorinsky-coefficient closure (forward, backward, Adam, BF16 rounding)
+  stats     long-run channel statistics, C_f and Re_tau, batch means, Eqs. eps_f and error
 
 Parity unpinned (no paper value or closed form fixes them; listed also in the
 design notes): the tanh map (R1), arithmetic two-point averages on the
@@ -24,6 +25,6 @@ stretched grid (R3), the filter width definition used by the static model
 """
 from .case import Case
 from .grid import Grid
-from . import ops, bc, sgs, poisson, substep, mlp
+from . import ops, bc, sgs, poisson, substep, mlp, stats
 
-__all__ = ["Case", "Grid", "ops", "bc", "sgs", "poisson", "substep", "mlp"]
+__all__ = ["Case", "Grid", "ops", "bc", "sgs", "poisson", "substep", "mlp", "stats"]
