@@ -194,6 +194,24 @@ def kernel_report(les, ctx, nsteps, workload):
     return kernels, roof
 
 
+def statistics_report(les, ctx, nsamples=20):
+    """Per-sample cost of the long-run statistics (plane sums of u, v, w, p and nu_t of the
+    current state added to the running sums), timed with HIP events like the kernels."""
+    les.les_stats_reset(ctx)
+    les.les_timing(ctx, True)
+    for _ in range(nsamples):
+        les.les_stats_sample(ctx)
+    les.les_timing(ctx, False)
+    rep = les.les_timing_report(ctx)
+    les.les_stats_reset(ctx)
+    p, f = rep["stats_partial"], rep["stats_final"]
+    gbps = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+    return {"sample_us": round(1e3 * (p["ms"] + f["ms"]) / nsamples, 3),
+            "partial_us": round(1e3 * p["ms"] / p["count"], 3), "final_us": round(1e3 * f["ms"] / f["count"], 3),
+            "alg_bytes_per_sample": p["bytes"] / p["count"], "GBps": round(gbps, 1),
+            "frac": round(gbps / HBM_PEAK_GBS, 4)}
+
+
 def learned_closure(les, torch, cfgd, solver, steps, warmup, use_graph):
     """Same workload with the learned closure: the network is trained on the GPU from
     dynamic-model pairs sampled from the plain solver's current state (400 Adam steps on
@@ -329,6 +347,7 @@ def solver_line(args, torch, cfgd):
     value = cells * 3 * args.steps / el / 1e6
     # per-kernel pass: same steps without the graph, every launch bracketed by HIP events
     kernels, roof = kernel_report(les, ctx, max(1, min(args.steps, 10)), cfgd["name"])
+    stats = statistics_report(les, ctx)
     diag, status = solver.diag()
     out = {
         "metric": METRIC,
@@ -350,6 +369,7 @@ def solver_line(args, torch, cfgd):
         "substep_roofline": substep_roofline(value, cfgd),
         "kernels": kernels,
         "state_check": {"max_div": diag.max_div, "ubulk": diag.ubulk, "nonfinite": int(diag.nonfinite)},
+        "statistics": stats,
     }
     if not args.no_learned and cfgd["sgs"] == 3 and args.config == "c2":
         out["learned_closure"] = learned_closure(les, torch, cfgd, solver, args.steps, args.warmup, use_graph)

@@ -171,6 +171,48 @@ les_status les_read(les_ctx* ctx, int field, void* dst);
 /* Synchronise and compute diagnostics. */
 les_status les_diag(les_ctx* ctx, les_diag_t* out);
 
+/* ---------------------------------------------------------------- statistics
+ * Long-run statistics of a channel run (Sec. 4.2 channel cases: mean velocity, resolved
+ * Reynolds stresses, u_tau, Re_tau = u_tau h / nu with h = lz/2, C_f = tau_w / (u_b^2 / 2) and
+ * its standard uncertainty; Eq. error for profile errors).  A sample is the plane (x-y) sums
+ * of the current state, added on the device to running sums; products are taken where their
+ * staggered factors meet: u v on the (x, y) edge, u w on the (x, z) edge and v w on the (y, z)
+ * edge at the top face of each cell, each factor the two-point mean onto that edge; w, w^2 and
+ * the products with w belong to the top face of cell k.  tau_w is the time mean of the
+ * plane-mean streamwise wall stress over both walls (wall model: its stress; no-slip:
+ * nu du/dz from the ghosts; 0 with periodic z); u_b is the dzf-weighted mean of the mean
+ * velocity profile.  The uncertainty of C_f is plain batch means over the per-sample series:
+ * nbatch equal consecutive batches (the oldest samples beyond nbatch * floor(len / nbatch)
+ * dropped), std of the batch means (n - 1 norm) / sqrt(nbatch), times 2 / u_b^2. */
+#define LES_STATS_NPROF 11
+#define LES_STATS_SERIES_MAX 65536   /* samples kept in the wall-stress series */
+/* profile rows of les_stats_read: means, then covariances (mean product minus product of
+ * the means of the two edge factors) */
+enum { LES_STAT_U = 0, LES_STAT_V, LES_STAT_W, LES_STAT_P, LES_STAT_NUT, LES_STAT_UU, LES_STAT_VV, LES_STAT_WW,
+       LES_STAT_UV, LES_STAT_UW, LES_STAT_VW };
+
+typedef struct {
+  int64_t samples;       /* samples accumulated since les_stats_reset                    */
+  int64_t series_len;    /* samples in the wall-stress series (<= LES_STATS_SERIES_MAX)   */
+  double tau_w, u_tau, re_tau;
+  double u_b;
+  double c_f, c_f_sigma; /* c_f_sigma NaN with fewer than 2 batches or samples < nbatch   */
+} les_stats_t;
+
+/* Clear the running sums (enqueued; also done at les_bind of the workspace). */
+les_status les_stats_reset(les_ctx* ctx);
+/* Add the current state as one sample (enqueued; two kernels). */
+les_status les_stats_sample(les_ctx* ctx);
+/* Synchronise, copy the sums to the host and finalise: out, and when profiles is not NULL
+ * the host array profiles[LES_STATS_NPROF][nz] (rows LES_STAT_*). */
+les_status les_stats_read(les_ctx* ctx, int32_t nbatch, les_stats_t* out, double* profiles);
+/* Host only.  Relative profile error of Eq. error over [z0, z1]: phi and ref known at the n
+ * increasing points z, both taken piecewise linear between them; the integrals are exact for
+ * that interpolant.  LES_EINVAL for n < 2, non-increasing z, z1 <= z0 or a zero reference
+ * integral. */
+les_status les_profile_error(const double* z, const double* phi, const double* ref, int32_t n, double z0,
+                             double z1, double* eps);
+
 /* ---------------------------------------------------------------- learned closure
  * Not in the paper, which motivates SGS closures trained on data produced by the LES solver
  * itself (Sec. 1).  Network: 7 -> 64 -> 64 -> 1 with SiLU, output clipped at zero, giving the

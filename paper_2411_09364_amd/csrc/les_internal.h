@@ -85,6 +85,8 @@ struct Tables {
   double* utau;     // 4*nx*ny Newton state
   double* dsm_part; // 2*nz*nblk_xy*4 plane partial sums (LM, MM) per tile and wave
   double* pfac;     // walls: (c', 1/pivot) of the (l, m <= ny/2) z systems, [nz][ny/2+1][nxp] pairs
+  double* stats;    // statistics: header[8], sums [11][nz], wall-stress series [cap][2]
+  double* stats_part; // per-block plane partials of one sample [nz+1][nblk][11]
   int64_t red_n;
   int nblk_xy;      // number of x-y tiles used by plane reductions
 };
@@ -162,6 +164,12 @@ void launch_mlp_grad(hipStream_t st, const float* P, const float* x, const float
 void launch_mlp_adam(hipStream_t st, float* P, const float* g, float* m, float* v, int step, float lr);
 void launch_mlp_normalize(hipStream_t st, const float* xr, int64_t n, const double* lo, const double* hi, float* x);
 void launch_set_dt(Ctx& c, double dt);
+int stats_blocks(int64_t sxy);
+int64_t stats_words(int nz);
+int64_t stats_part_words(int nz, int64_t sxy);
+void launch_stats_reset(Ctx& c);
+template <typename T> void launch_stats_sample(Ctx& c);
+void stats_finalize(const Ctx& c, const double* st, int nbatch, les_stats_t* out, double* prof);
 
 // Kernel launch on the context stream.  With timing enabled the launch is bracketed by
 // two HIP events and tagged with its algorithmic byte count (minimum HBM traffic of the

@@ -40,6 +40,17 @@ class LesDiag(ctypes.Structure):
                 ("nonfinite", ctypes.c_int64), ("mlp_flagged", ctypes.c_int64)]
 
 
+class LesStats(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int64), ("series_len", ctypes.c_int64), ("tau_w", ctypes.c_double),
+                ("u_tau", ctypes.c_double), ("re_tau", ctypes.c_double), ("u_b", ctypes.c_double),
+                ("c_f", ctypes.c_double), ("c_f_sigma", ctypes.c_double)]
+
+
+STATS_NPROF = 11
+STATS_SERIES_MAX = 65536
+STAT_NAMES = ("U", "V", "W", "P", "NUT", "uu", "vv", "ww", "uv", "uw", "vw")
+
+
 class LesError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{msg} (status {status})")
@@ -86,6 +97,11 @@ def _load():
         "les_batch_diag": [vp, i32, ctypes.POINTER(LesDiag)],
         "les_batch_free": [vp],
         "les_timing_report": [vp, ctypes.c_char_p, ctypes.c_size_t],
+        "les_stats_reset": [vp],
+        "les_stats_sample": [vp],
+        "les_stats_read": [vp, i32, ctypes.POINTER(LesStats), vp],
+        "les_profile_error": [ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32, dbl, dbl,
+                              ctypes.POINTER(dbl)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -114,7 +130,8 @@ def exported_symbols():
             "les_timing", "les_timing_report", "les_batch_init", "les_batch_layout", "les_batch_offset",
             "les_batch_bind", "les_batch_nut", "les_batch_dt", "les_batch_set_dt", "les_batch_substep",
             "les_batch_step", "les_batch_autotune", "les_batch_read", "les_batch_diag",
-            "les_batch_last_error", "les_batch_free"]
+            "les_batch_last_error", "les_batch_free", "les_stats_reset", "les_stats_sample", "les_stats_read",
+            "les_profile_error"]
 
 
 def make_config(nx, ny, nz, lx, ly, lz, zbc=ZBC_PERIODIC, beta=0.0, nu=1e-3, sgs=SGS_NONE, cs=0.17,
@@ -278,6 +295,29 @@ class Mlp:
         return self.loss
 
 
+def les_stats_reset(ctx):
+    _check(ctx, LIB.les_stats_reset(ctx), "les_stats_reset")
+
+
+def les_stats_sample(ctx):
+    _check(ctx, LIB.les_stats_sample(ctx), "les_stats_sample")
+
+
+def les_stats_read(ctx, nbatch, profiles_ptr=None):
+    out = LesStats()
+    _check(ctx, LIB.les_stats_read(ctx, nbatch, ctypes.byref(out), ctypes.c_void_p(profiles_ptr)), "les_stats_read")
+    return out
+
+
+def les_profile_error(z, phi, ref, z0, z1):
+    import numpy as np
+    z, phi, ref = (np.ascontiguousarray(a, dtype=np.float64) for a in (z, phi, ref))
+    p = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    eps = ctypes.c_double(0.0)
+    _check(None, LIB.les_profile_error(p(z), p(phi), p(ref), len(z), z0, z1, ctypes.byref(eps)), "les_profile_error")
+    return eps.value
+
+
 def les_timing(ctx, enable):
     _check(ctx, LIB.les_timing(ctx, 1 if enable else 0), "les_timing")
 
@@ -396,6 +436,20 @@ class Solver:
 
     def diag(self):
         return les_diag(self.ctx)
+
+    def stats_reset(self):
+        les_stats_reset(self.ctx)
+
+    def stats_sample(self):
+        les_stats_sample(self.ctx)
+
+    def stats(self, nbatch=8):
+        """(scalars dict, profiles dict of host arrays [nz]) of the accumulated statistics."""
+        import numpy as np
+        prof = np.zeros((STATS_NPROF, self.cfg.nz))
+        out = les_stats_read(self.ctx, nbatch, prof.ctypes.data)
+        sc = {f: getattr(out, f) for f, _ in LesStats._fields_}
+        return sc, {name: prof[q] for q, name in enumerate(STAT_NAMES)}
 
     def mlp_bind(self, mlp, lo, hi):
         les_mlp_bind(self.ctx, mlp.params.data_ptr(), lo, hi)

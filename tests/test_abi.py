@@ -89,3 +89,21 @@ def test_library_grid_matches_oracle_grid():
     assert np.allclose(buf[:25], g.zf, rtol=0, atol=1e-15)
     assert np.allclose(buf[25:], g.zc, rtol=0, atol=1e-15)
     les.les_free(ctx)
+
+
+def test_profile_error_host_function_matches_oracle():
+    """les_profile_error is host code (no GPU): Eq. error against the oracle's reading on a
+    stretched point set, and its argument checks."""
+    import numpy as np
+    from paper_2411_09364_amd import les
+    from oracle import stats as ST
+    rng = np.random.default_rng(9)
+    z = np.sort(rng.uniform(0.0, 1.2, 33))
+    ref = 1.0 + np.sin(2.0 * z)
+    phi = ref + 0.03 * rng.standard_normal(z.size)
+    e = les.les_profile_error(z, phi, ref, 0.1, 1.0)
+    assert abs(e - ST.eps_phi(z, phi, ref, 0.1, 1.0)) < 1e-15
+    with pytest.raises(les.LesError):
+        les.les_profile_error(z[::-1], phi, ref, 0.1, 1.0)
+    with pytest.raises(les.LesError):
+        les.les_profile_error(z, phi, ref, 1.0, 0.1)
