@@ -42,6 +42,66 @@ __device__ inline dim3 xcd_tile(dim3 bid, dim3 grid) {
   return dim3(tt % grid.x, tt / grid.x, bid.z);
 }
 
+// Segmented-scan solve of tridiagonal chains with known factors (Thomas sweeps written as
+// first-order linear recurrences: forward d_k = r_k f_k + alpha_k d_{k-1}, alpha_k = -a_k r_k,
+// r_k = 1/pivot; back x_k = d_k - c'_k x_{k+1}).  The CG chains of a block are cut into
+// segments of S rows, thread (cl, p) holding rows k0 = p S .. k0 + S - 1 (< n) of chain cl in
+// v.  Each sweep runs over the segment from a zero start while carrying the product of its
+// coefficients; the segment end values are folded in order through E, G ([segments][CG] in
+// LDS) and every row is corrected by product x start value.  R(j), A(j), C(j) give r, a and
+// c' of row k0 + j.  Contains barriers: every thread of the block calls it.
+template <int S, int CG, class RF, class AF, class CF>
+__device__ __forceinline__ void seg_scan_solve(double (&v)[S], int k0, int n, int p, int P, int cl,
+                                               double (*E)[CG], double (*G)[CG], const RF& R, const AF& A,
+                                               const CF& C) {
+  double dl = 0.0, pr = 1.0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    if (k0 + j < n) {
+      const double al = -A(j) * R(j);
+      dl = R(j) * v[j] + al * dl;
+      pr = al * pr;
+      v[j] = dl;
+    }
+  }
+  E[p][cl] = dl;
+  G[p][cl] = pr;
+  __syncthreads();
+  double D = 0.0;
+  for (int q = 0; q < p; ++q) D = E[q][cl] + G[q][cl] * D;
+  pr = 1.0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    if (k0 + j < n) {
+      pr *= -A(j) * R(j);
+      v[j] += pr * D;
+    }
+  }
+  double xl = 0.0, ps = 1.0;
+#pragma unroll
+  for (int j = S - 1; j >= 0; --j) {
+    if (k0 + j < n) {
+      xl = v[j] - C(j) * xl;
+      ps = -C(j) * ps;
+      v[j] = xl;
+    }
+  }
+  __syncthreads();
+  E[p][cl] = xl;
+  G[p][cl] = ps;
+  __syncthreads();
+  double X = 0.0;
+  for (int q = P - 1; q > p; --q) X = E[q][cl] + G[q][cl] * X;
+  ps = 1.0;
+#pragma unroll
+  for (int j = S - 1; j >= 0; --j) {
+    if (k0 + j < n) {
+      ps *= -C(j);
+      v[j] += ps * X;
+    }
+  }
+}
+
 __device__ inline int wrap_p(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 __device__ inline int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 

@@ -426,19 +426,12 @@ void launch_thomas_factor(Ctx& c) {
                      c.t.pb, c.t.pc, c.t.lamx, c.t.lamy, (double2*)c.t.pfac);
 }
 
-// FP64 z solves of every (l, m) column with the stored factors, by segmented scans.  A
-// column gives two chains (real and imaginary parts), and there are only a few tens of
-// thousands of chains of nz rows: a plain Thomas sweep per chain leaves most of the chip
-// idle behind its dependent chain.  Both sweeps are first-order linear recurrences,
-//   forward d_k = r_k f_k + alpha_k d_{k-1} (alpha_k = -a_k r_k, r_k = 1/pivot),
-//   back    x_k = d_k - c'_k x_{k+1},
-// so each chain is cut into segments of S rows, one thread per segment.  A thread runs the
-// recurrence over its segment from a zero start while carrying the product of its
-// coefficients; the segment end values are combined in order through LDS (the start value of
-// segment p is a short fold over segments 0..p-1), and every row is corrected by product x
-// start.  Same for the back sweep from the top.  Threads: CG consecutive chains (adjacent in
-// memory, so each row load of a segment group is contiguous) times the segments.  Rows are
-// held in registers, loaded once and stored once.  ZERO (Poisson): the pinned (0, 0) column
+// FP64 z solves of every (l, m) column with the stored factors, by segmented scans
+// (seg_scan_solve).  A column gives two chains (real and imaginary parts), and there are only
+// a few tens of thousands of chains of nz rows: a plain Thomas sweep per chain leaves most of
+// the chip idle behind its dependent chain.  Threads: CG consecutive chains (adjacent in
+// memory, so each row load of a segment group is contiguous) times the segments of S rows.
+// Rows are held in registers, loaded once and stored once.  ZERO (Poisson): the pinned (0, 0) column
 // has its own factor pairs (last row zero); its dzf-weighted mean is removed here and its
 // imaginary part set to zero.  Rows nrow..nz-1 are left as they are (the wall face of w in
 // the Helmholtz solves).
@@ -468,58 +461,8 @@ __global__ void __launch_bounds__(1024) k_thomas_scan(GridP g, cpx<T>* __restric
     v[j] = in ? (double)x[(int64_t)k * ncol2] * norm : 0.0;
     fc[j] = in ? fp[(int64_t)k * nfac] : make_double2(0.0, 0.0);
   }
-  // forward: local recurrence from zero, product of the alphas
-  double dl = 0.0, pr = 1.0;
-#pragma unroll
-  for (int j = 0; j < S; ++j) {
-    const int k = k0 + j;
-    if (k < n) {
-      const double al = -pa[k] * fc[j].y;
-      dl = fc[j].y * v[j] + al * dl;
-      pr = al * pr;
-      v[j] = dl;
-    }
-  }
-  E[p][cl] = dl;
-  G[p][cl] = pr;
-  __syncthreads();
-  double D = 0.0;
-  for (int q = 0; q < p; ++q) D = E[q][cl] + G[q][cl] * D;
-  pr = 1.0;
-#pragma unroll
-  for (int j = 0; j < S; ++j) {
-    const int k = k0 + j;
-    if (k < n) {
-      pr *= -pa[k] * fc[j].y;
-      v[j] += pr * D;
-    }
-  }
-  // back: local recurrence from zero above the segment, product of the -c'
-  double xl = 0.0, ps = 1.0;
-#pragma unroll
-  for (int j = S - 1; j >= 0; --j) {
-    const int k = k0 + j;
-    if (k < n) {
-      xl = v[j] - fc[j].x * xl;
-      ps = -fc[j].x * ps;
-      v[j] = xl;
-    }
-  }
-  __syncthreads();
-  E[p][cl] = xl;
-  G[p][cl] = ps;
-  __syncthreads();
-  double X = 0.0;
-  for (int q = P - 1; q > p; --q) X = E[q][cl] + G[q][cl] * X;
-  ps = 1.0;
-#pragma unroll
-  for (int j = S - 1; j >= 0; --j) {
-    const int k = k0 + j;
-    if (k < n) {
-      ps *= -fc[j].x;
-      v[j] += ps * X;
-    }
-  }
+  seg_scan_solve<S, CG>(v, k0, n, p, P, cl, E, G, [&](int j) { return fc[j].y; }, [&](int j) { return pa[k0 + j]; },
+                        [&](int j) { return fc[j].x; });
   if (ZERO && blockIdx.x == 0) {
     // zero mode: chains 0 (real part) and 1 (imaginary part) of this block
     double sw = 0.0, sd = 0.0;

@@ -258,10 +258,23 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
   const int i = i0 + tx, j = j0 + ty;
   const bool inside = i < g.nx && j < g.ny;
   const T dt = (T)dtp[0];
+  // R_prev of the own cell, loaded one plane ahead
+  T rpn[3] = {(T)0, (T)0, (T)0};
+  auto fetch_r = [&](int k) {
+    if (use_rprev && inside && k <= ke) {
+      const int64_t c = idx3(g, k, j, i);
+      rpn[0] = ru[c];
+      rpn[1] = rv[c];
+      rpn[2] = rw[c];
+    }
+  };
+  fetch_r(kb);
   for (int k = kb; k <= ke; ++k) {
     commit(k + 1);
     __syncthreads();
     if (k + 2 <= ke + 1) fetch(k + 2);
+    const T rup = rpn[0], rvp = rpn[1], rwp = rpn[2];
+    fetch_r(k + 1);
     if (inside) {
       const int sm = (k - 1) % 3, s0 = k % 3, sp = (k + 1) % 3;
       const int x = tx + 1, y = ty + 1;
@@ -283,12 +296,6 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
       b.n_kp_jm = A(3, sp, -1, 0);
       b.p0 = A(4, s0, 0, 0), b.pip = A(4, s0, 0, 1), b.pjp = A(4, s0, 1, 0), b.pkp = A(4, sp, 0, 0);
       const int64_t c0 = idx3(g, k, j, i);
-      T rup = (T)0, rvp = (T)0, rwp = (T)0;
-      if (use_rprev) {
-        rup = ru[c0];
-        rvp = rv[c0];
-        rwp = rw[c0];
-      }
       T Ru, Rv, Rw, uo, vo, wo;
       predictor_cell<T, MODE>(b, g, k, dt, alpha, beta, gamma, use_rprev != 0, rup, rvp, rwp, Ru, Rv, Rw, uo, vo,
                               wo);
