@@ -84,3 +84,35 @@ def dsm_nut_check(case, g, st, nut, rel=1e-12):
     allow = rel * ref + bound
     ratio = float(np.max(diff / allow))
     return ratio <= 1.0, ratio, float(np.max(bound) / ref) if ref > 0 else 0.0
+
+
+def poisson_condition(g):
+    """Condition number lambda_max / lambda_min of the discrete Poisson operator D G of the
+    grid (Sec. 2.2): lambda_max bounded by Gershgorin (4/dx^2 + 4/dy^2 + the largest z row
+    sum), lambda_min the smallest nonzero magnitude among the first x and y Fourier modes and
+    the z operator's eigenvalues (Neumann at walls, periodic otherwise)."""
+    n = g.nz
+    lx = (2.0 - 2.0 * np.cos(2.0 * np.pi / g.nx)) / g.dx ** 2
+    ly = (2.0 - 2.0 * np.cos(2.0 * np.pi / g.ny)) / g.dy ** 2
+    A = np.zeros((n, n))
+    for k in range(1, n + 1):
+        lo = 1.0 / (g.dzc[k - 1] * g.dzf[k])
+        up = 1.0 / (g.dzc[k] * g.dzf[k])
+        r = k - 1
+        A[r, r] = -(lo + up)
+        A[r, (r - 1) % n] += lo
+        A[r, (r + 1) % n] += up
+    if not g.periodic_z:
+        A[0, n - 1] = A[n - 1, 0] = 0.0
+        A[0, 0] += 1.0 / (g.dzc[0] * g.dzf[1])
+        A[n - 1, n - 1] += 1.0 / (g.dzc[n] * g.dzf[n])
+    ev = np.abs(np.linalg.eigvals(A))
+    lz = np.min(ev[ev > 1e-9 * np.max(ev)])
+    lmax = 4.0 / g.dx ** 2 + 4.0 / g.dy ** 2 + np.max(np.sum(np.abs(A), axis=1))
+    return lmax / min(lx, ly, lz)
+
+
+def pressure_tolerance(g):
+    """FP64 tolerance of the mean-free pressure: the Poisson solve amplifies rounding by up to
+    the operator's condition number, so max(1e-12, 4 eps kappa)."""
+    return max(1e-12, 4.0 * UNIT_ROUNDOFF * 2.0 * poisson_condition(g))

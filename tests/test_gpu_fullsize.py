@@ -1,9 +1,11 @@
 """GPU checks at the benchmark sizes, in the launch configuration the benchmark times
 (device time step slot, three substeps replayed from one hipGraph).
 
-  channel 256 x 128 x 96 FP64 (dynamic model, wall model, CN in z): one full step against
-      the oracle element by element (FP64 1e-12 on the state; the dynamic-model nu_t within
-      the propagated rounding bound of its plane coefficient);
+  channel 256 x 128 x 96 FP64 (dynamic model, wall model, CN in z, and CN in all
+      directions): one full step against the oracle element by element (FP64 1e-12 on u, v,
+      w; the mean-free p within 4 eps times the condition number of the discrete Poisson
+      operator, 8.9e-11 on this stretched grid; the dynamic-model nu_t within the propagated
+      rounding bound of its plane coefficient);
   the same grid's Poisson solve: residual of D G phi = f evaluated by the oracle's operators;
   channel 1024 x 512 x 256 mixed precision: one step, properties that hold at any size
       (divergence at float32 level, flow rate, finite state) and the FP64 library run of the
@@ -19,7 +21,8 @@ import pytest
 from oracle import substep as S, ops as OO
 from oracle.case import ZBC_PERIODIC, ZBC_WALLMODEL, SGS_DSM
 from synth import box_ensemble, isotropic_field
-from tests.cases import make_pair, initial_fields, rel_err, mean_free, say, dsm_nut_check, round32
+from tests.cases import (make_pair, initial_fields, rel_err, mean_free, say, dsm_nut_check, round32,
+                         pressure_tolerance)
 
 pytestmark = pytest.mark.gpu
 TWO_PI = 2 * np.pi
@@ -52,15 +55,45 @@ def test_channel_full_size_step_matches_oracle(les):
     gu, gv, gw, gp = solver.fields()
     errs = dict(u=rel_err(gu, st.u, I), v=rel_err(gv, st.v, I), w=rel_err(gw, st.w, I),
                 p=rel_err(mean_free(gp, g), mean_free(st.p, g), I))
-    say("  " + " ".join(f"{a}={b:.2e}" for a, b in errs.items()))
+    ptol = pressure_tolerance(g)
+    say("  " + " ".join(f"{a}={b:.2e}" for a, b in errs.items()) + f" (p tolerance {ptol:.1e})")
     for a, e in errs.items():
-        assert e < 1e-12, (a, e)
+        assert e < (ptol if a == "p" else 1e-12), (a, e)
     ok, ratio, bnd = dsm_nut_check(case, g, st, solver.eddy_viscosity())
     say(f"  nu_t vs allowance: worst ratio {ratio:.3f} (c_s rounding bound {bnd:.2e})")
     assert ok
     d, status = solver.diag()
     assert status == 0 and d.nonfinite == 0
     assert abs(d.ubulk - 1.0) < 1e-13
+    solver.close()
+
+
+def test_channel_full_size_cn_all_directions_matches_oracle(les):
+    """The same channel with Crank-Nicolson in all directions (three Helmholtz solves per
+    substep), one graph-replayed step against the oracle."""
+    say("full-size channel step 256x128x96, CN in all directions")
+    cfgd = dict(CHANNEL, implicit_z=False, implicit_3d=True)
+    case, g, cfg = make_pair(**cfgd)
+    u, v, w = initial_fields(case, g, 2, "channel")
+    st = S.initial_state(case, g, u, v, w)
+    dt = S.time_step(case, g, st, cfl=0.5)
+    solver = les.Solver(cfg)
+    solver.set_state(u, v, w)
+    solver.nut()
+    solver.set_dt(dt)
+    les.les_step(solver.ctx, True)
+    for k in range(3):
+        st = S.substep(case, g, st, k, dt)
+    I = slice(1, g.nz + 1)
+    gu, gv, gw, gp = solver.fields()
+    errs = dict(u=rel_err(gu, st.u, I), v=rel_err(gv, st.v, I), w=rel_err(gw, st.w, I),
+                p=rel_err(mean_free(gp, g), mean_free(st.p, g), I))
+    ptol = pressure_tolerance(g)
+    say("  " + " ".join(f"{a}={b:.2e}" for a, b in errs.items()) + f" (p tolerance {ptol:.1e})")
+    for a, e in errs.items():
+        assert e < (ptol if a == "p" else 1e-12), (a, e)
+    ok, ratio, bnd = dsm_nut_check(case, g, st, solver.eddy_viscosity())
+    assert ok, ratio
     solver.close()
 
 
