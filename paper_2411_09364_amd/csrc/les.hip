@@ -198,7 +198,8 @@ size_t carve(Ctx& c, char* base) {
   c.phi = take(F * E);
   const size_t rq = f.precision == LES_MIXED ? 16 : 8;
   const size_t nxp = ((size_t)(f.nx / 2 + 1) + rq - 1) / rq * rq;
-  c.spec = take(nxp * f.ny * n * 2 * E);
+  // one spectrum buffer; three with CN in all directions (the components are solved together)
+  c.spec = take(nxp * f.ny * n * 2 * E * (f.implicit_z == LES_VISC_CN_3D ? 3 : 1));
   // factor pairs of the z systems of every (l, m <= ny/2) column (walls only)
   t.pfac = (double*)take(f.zbc == LES_ZBC_PERIODIC ? 0 : nxp * (f.ny / 2 + 1) * n * 2 * 8);
   // long-run statistics: running sums and series, per-sample partials

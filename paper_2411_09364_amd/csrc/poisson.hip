@@ -436,14 +436,15 @@ void launch_thomas_factor(Ctx& c) {
 // imaginary part set to zero.  Rows nrow..nz-1 are left as they are (the wall face of w in
 // the Helmholtz solves).
 template <typename T, int S, bool ZERO>
-__global__ void __launch_bounds__(1024) k_thomas_scan(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ pa,
-                                                      const double2* __restrict__ pfac, double norm, int nrow) {
+__device__ __forceinline__ void thomas_scan_body(unsigned bx, GridP g, cpx<T>* __restrict__ spec,
+                                                 const double* __restrict__ pa, const double2* __restrict__ pfac,
+                                                 double norm, int nrow) {
   constexpr int CG = 32;
   __shared__ double E[32][CG], G[32][CG];
   const int cl = (int)threadIdx.x % CG, p = (int)threadIdx.x / CG, P = (int)blockDim.x / CG;
   const int n = nrow, nxh = g.nx / 2 + 1;
   const int64_t ncol = (int64_t)g.nxp * g.ny, ncol2 = 2 * ncol;
-  const int64_t c2 = (int64_t)blockIdx.x * CG + cl;
+  const int64_t c2 = (int64_t)bx * CG + cl;
   const int64_t col = c2 >> 1;
   const int l = (int)(col % g.nxp), m = (int)(col / g.nxp);
   const bool ok = c2 < ncol2 && l < nxh;
@@ -463,7 +464,7 @@ __global__ void __launch_bounds__(1024) k_thomas_scan(GridP g, cpx<T>* __restric
   }
   seg_scan_solve<S, CG>(v, k0, n, p, P, cl, E, G, [&](int j) { return fc[j].y; }, [&](int j) { return pa[k0 + j]; },
                         [&](int j) { return fc[j].x; });
-  if (ZERO && blockIdx.x == 0) {
+  if (ZERO && bx == 0) {
     // zero mode: chains 0 (real part) and 1 (imaginary part) of this block
     double sw = 0.0, sd = 0.0;
 #pragma unroll
@@ -501,6 +502,53 @@ __global__ void __launch_bounds__(1024) k_thomas_scan(GridP g, cpx<T>* __restric
       if (k < n) x[(int64_t)k * ncol2] = (T)v[j];
     }
   }
+}
+
+template <typename T, int S, bool ZERO>
+__global__ void __launch_bounds__(1024) k_thomas_scan(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ pa,
+                                                      const double2* __restrict__ pfac, double norm, int nrow) {
+  thomas_scan_body<T, S, ZERO>(blockIdx.x, g, spec, pa, pfac, norm, nrow);
+}
+
+// ---------------------------------------------------------------- three components at once
+// The Helmholtz solves of CN in all directions transform u*, v* and w* through three spectrum
+// buffers (cstride apart), so each stage is one launch over all components (blockIdx.y or z).
+template <typename T>
+__global__ void __launch_bounds__(256) k_rfftx3(GridP g, FftPlan P, const T* us, const T* vs, const T* ws,
+                                                cpx<T>* spec, int64_t cstride, const double* twd, const float* twf,
+                                                int npair_blk) {
+  const int comp = blockIdx.y;
+  const T* f = comp == 0 ? us : (comp == 1 ? vs : ws);
+  rfftx_body<T, 1>(dim3(blockIdx.x), g, P, nullptr, nullptr, nullptr, f, spec + comp * cstride, twd, twf, nullptr,
+                   1.0, npair_blk, nullptr);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_irfftx3(GridP g, FftPlan P, const cpx<T>* spec, int64_t cstride, T* us,
+                                                 T* vs, T* ws, const double* twd, const float* twf, int npair_blk) {
+  const int comp = blockIdx.y;
+  T* f = comp == 0 ? us : (comp == 1 ? vs : ws);
+  irfftx_body<T>(dim3(blockIdx.x), g, P, spec + comp * cstride, f, twd, twf, npair_blk);
+}
+
+template <typename T, int DIR, bool SOLVE>
+__global__ void __launch_bounds__(256) k_fft_lines3(FftPlan P, cpx<T>* data, int64_t cstride, int nl, int64_t lstride,
+                                                    int64_t ostride, int L, const double* twd, const float* twf,
+                                                    const double* lamx, const double* lamy, const double* lamz,
+                                                    double norm, const double* dtp, double hg) {
+  fft_lines_body<T, DIR, SOLVE>(dim3(blockIdx.x, blockIdx.y), P, data + blockIdx.z * cstride, nl, lstride, ostride, L,
+                                twd, twf, lamx, lamy, lamz, norm, dtp, hg);
+}
+
+// component blockIdx.y: u and v take the u/v rows and factors, w the w rows (nz - 1 unknowns)
+template <typename T, int S>
+__global__ void __launch_bounds__(1024) k_thomas_scan3(GridP g, cpx<T>* __restrict__ spec, int64_t cstride,
+                                                       const double* __restrict__ a_uv, const double* __restrict__ a_w,
+                                                       const double2* __restrict__ fac_uv,
+                                                       const double2* __restrict__ fac_w, double norm) {
+  const int comp = blockIdx.y;
+  thomas_scan_body<T, S, false>(blockIdx.x, g, spec + comp * cstride, comp < 2 ? a_uv : a_w,
+                                comp < 2 ? fac_uv : fac_w, norm, comp < 2 ? g.nz : g.nz - 1);
 }
 
 // Crank-Nicolson in all directions, wall-bounded z (Eq. onestar_imp3d): after FFTs in x and
@@ -692,45 +740,75 @@ static void inv_x(Ctx& c, T* out) {
                      c.t.twx, c.t.twx_f, pb);
 }
 
-// Crank-Nicolson in all directions (Eq. onestar_imp3d): each predicted component in u*, v*,
-// w* (right-hand side of the Helmholtz system, wall-model flux included) is transformed in x
-// and y through the spectrum buffer, solved per wavenumber pair in z (Thomas in FP64 at
-// walls, FFT when z is periodic) and transformed back in place.
+// Crank-Nicolson in all directions (Eq. onestar_imp3d): the predicted components u*, v*, w*
+// (right-hand sides of the Helmholtz systems, wall-model flux included) are transformed in x
+// and y into three spectrum buffers, solved per wavenumber pair in z (Thomas in FP64 at
+// walls, FFT when z is periodic) and transformed back in place; one launch per stage.
 template <typename T>
 void launch_helmholtz_3d(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
   const double hg = G[stage] * c.cfg.nu / 2.0;
-  const int n = c.g.nz;
-  const double spec_bytes = (double)(c.g.nx / 2 + 1) * c.g.ny * n * 2 * sizeof(T);
-  T* comp[3] = {(T*)c.us, (T*)c.vs, (T*)c.wsf};
-  const int64_t nfac = (int64_t)c.g.nxp * (c.g.ny / 2 + 1);
-  const int64_t nchain = 2 * (int64_t)c.g.nxp * c.g.ny;
-  const double norm = 1.0 / ((double)c.g.nx * c.g.ny);
+  const int n = c.g.nz, nx = c.g.nx, ny = c.g.ny, nxh = nx / 2 + 1;
+  const double spec_bytes = (double)nxh * ny * n * 2 * sizeof(T);
+  const int64_t cstride = (int64_t)c.g.nxp * ny * n;   // complex values per component
+  cpx<T>* sp = (cpx<T>*)c.spec;
+  const int64_t nfac = (int64_t)c.g.nxp * (ny / 2 + 1);
+  const double norm_xy = 1.0 / ((double)nx * ny);
   if (c.cfg.zbc != LES_ZBC_PERIODIC)
     LES_LAUNCH(c, "h3d_factor", 2.0 * nfac * n * 16, k_helm3d_factor, dim3((unsigned)((2 * nfac + 255) / 256)), dim3(256),
                0, c.g, c.t.hfac, c.t.lamx, c.t.lamy, c.t.dt, hg, (double2*)c.t.hfac3);
-  for (int a = 0; a < 3; ++a) {
-    fwd_x<T>(c, 1, nullptr, nullptr, nullptr, comp[a], 1.0, false);
-    ffty<T, -1>(c, "h3d_ffty_fwd");
-    if (c.cfg.zbc == LES_ZBC_PERIODIC) {
-      fftz_solve<T>(c, "h3d_fftz_solve", hg);
-    } else {
-      const int nrow = a < 2 ? n : n - 1;
-      const int S = nrow <= 256 ? 8 : 16;
-      const int P = (nrow + S - 1) / S;
-      const dim3 grid((unsigned)((nchain + 31) / 32)), block(32 * P);
-      const double* ra = c.t.hfac + (a < 2 ? 6 : 7) * n;
-      const double2* fac = (const double2*)c.t.hfac3 + (a < 2 ? 0 : (int64_t)n * nfac);
-      const double bytes = 2 * spec_bytes + (double)nfac * n * 16;
-      if (S == 8)
-        LES_LAUNCH(c, "h3d_thomas_z", bytes, (k_thomas_scan<T, 8, false>), grid, block, 0, c.g, (cpx<T>*)c.spec, ra,
-                   fac, norm, nrow);
-      else
-        LES_LAUNCH(c, "h3d_thomas_z", bytes, (k_thomas_scan<T, 16, false>), grid, block, 0, c.g, (cpx<T>*)c.spec,
-                   ra, fac, norm, nrow);
-    }
-    ffty<T, 1>(c, "h3d_ffty_inv");
-    inv_x<T>(c, comp[a]);
+  // forward x of the three components
+  {
+    const FftPlan P = make_plan(nx);
+    const int pb = pairs_per_block(nx);
+    const int64_t npairs = (int64_t)n * (ny / 2);
+    const size_t sh = 2 * (size_t)pb * nx * sizeof(cpx<T>);
+    LES_LAUNCH(c, "h3d_rfftx", 3 * (spec_bytes + (double)c.g.sxy * n * sizeof(T)), (k_rfftx3<T>),
+               dim3((unsigned)((npairs + pb - 1) / pb), 3), dim3(256), sh, c.g, P, (const T*)c.us, (const T*)c.vs,
+               (const T*)c.wsf, sp, cstride, c.t.twx, c.t.twx_f, pb);
+  }
+  const FftPlan Py = make_plan(ny);
+  const int Ly = lines_per_block(ny);
+  const size_t shy = 2 * (size_t)Ly * (ny + 1) * sizeof(cpx<T>);
+  const dim3 gy((nxh + Ly - 1) / Ly, n, 3);
+  LES_LAUNCH(c, "h3d_ffty_fwd", 6 * spec_bytes, (k_fft_lines3<T, -1, false>), gy, dim3(256), shy, Py, sp, cstride, nxh,
+             (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, Ly, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0,
+             nullptr, 0.0);
+  if (c.cfg.zbc == LES_ZBC_PERIODIC) {
+    const FftPlan Pz = make_plan(n);
+    const int Lz = lines_per_block(n);
+    const size_t shz = 2 * (size_t)Lz * (n + 1) * sizeof(cpx<T>);
+    LES_LAUNCH(c, "h3d_fftz_solve", 6 * spec_bytes, (k_fft_lines3<T, -1, true>), dim3((nxh + Lz - 1) / Lz, ny, 3),
+               dim3(256), shz, Pz, sp, cstride, nxh, (int64_t)c.g.nxp * ny, (int64_t)c.g.nxp, Lz, c.t.twz, c.t.twz_f,
+               c.t.lamx, c.t.lamy, c.t.lamz, 1.0 / ((double)nx * ny * n), c.t.dt, hg);
+  } else {
+    const int64_t nchain = 2 * (int64_t)c.g.nxp * ny;
+    const int S = n <= 256 ? 8 : 16;
+    const int P = (n + S - 1) / S;
+    const dim3 grid((unsigned)((nchain + 31) / 32), 3), block(32 * P);
+    const double* a_uv = c.t.hfac + 6 * n;
+    const double* a_w = c.t.hfac + 7 * n;
+    const double2* f_uv = (const double2*)c.t.hfac3;
+    const double2* f_w = f_uv + (int64_t)n * nfac;
+    const double bytes = 6 * spec_bytes + 3.0 * nfac * n * 16;
+    if (S == 8)
+      LES_LAUNCH(c, "h3d_thomas_z", bytes, (k_thomas_scan3<T, 8>), grid, block, 0, c.g, sp, cstride, a_uv, a_w, f_uv,
+                 f_w, norm_xy);
+    else
+      LES_LAUNCH(c, "h3d_thomas_z", bytes, (k_thomas_scan3<T, 16>), grid, block, 0, c.g, sp, cstride, a_uv, a_w, f_uv,
+                 f_w, norm_xy);
+  }
+  LES_LAUNCH(c, "h3d_ffty_inv", 6 * spec_bytes, (k_fft_lines3<T, 1, false>), gy, dim3(256), shy, Py, sp, cstride, nxh,
+             (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, Ly, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0,
+             nullptr, 0.0);
+  {
+    const FftPlan P = make_plan(nx);
+    const int pb = pairs_per_block(nx);
+    const int64_t npairs = (int64_t)n * (ny / 2);
+    const size_t sh = 2 * (size_t)pb * nx * sizeof(cpx<T>);
+    LES_LAUNCH(c, "h3d_irfftx", 3 * (spec_bytes + (double)c.g.sxy * n * sizeof(T)), (k_irfftx3<T>),
+               dim3((unsigned)((npairs + pb - 1) / pb), 3), dim3(256), sh, c.g, P, (const cpx<T>*)sp, cstride,
+               (T*)c.us, (T*)c.vs, (T*)c.wsf, c.t.twx, c.t.twx_f, pb);
   }
 }
 
