@@ -172,7 +172,7 @@ les_status les_read(les_ctx* ctx, int field, void* dst);
 les_status les_diag(les_ctx* ctx, les_diag_t* out);
 
 /* ---------------------------------------------------------------- statistics
- * Long-run statistics of a channel run (Sec. 4.2 channel cases: mean velocity, resolved
+ * Long-run statistics of a channel run (Secs. 4.2 and 4.3 channel cases: mean velocity, resolved
  * Reynolds stresses, u_tau, Re_tau = u_tau h / nu with h = lz/2, C_f = tau_w / (u_b^2 / 2) and
  * its standard uncertainty; Eq. error for profile errors).  A sample is the plane (x-y) sums
  * of the current state, added on the device to running sums; products are taken where their

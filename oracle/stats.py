@@ -1,4 +1,4 @@
-"""Long-run statistics of a channel run (Sec. 4.2 channel cases: mean velocity, resolved
+"""Long-run statistics of a channel run (Secs. 4.2 and 4.3 channel cases: mean velocity, resolved
 Reynolds stresses, friction velocity, friction Reynolds number Re_tau = u_tau h / nu and
 skin friction C_f = tau_w / (rho u_b^2 / 2); Eq. eps_f and Eq. error for the errors against
 a reference; the standard uncertainty of C_f by batch means).  Test infrastructure only.

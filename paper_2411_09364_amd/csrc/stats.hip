@@ -1,4 +1,4 @@
-// Long-run statistics of a channel run (Sec. 4.2 channel cases): per-sample plane sums of
+// Long-run statistics of a channel run (Secs. 4.2 and 4.3 channel cases): per-sample plane sums of
 // the mean-velocity and resolved-stress quantities accumulated on the device, the per-sample
 // plane-mean wall stress kept as a series, and the host finalisation into profiles,
 // tau_w, u_tau, Re_tau, C_f with its batch-means uncertainty and the profile error of

@@ -1,4 +1,4 @@
-"""GPU statistics (Sec. 4.2 channel statistics) against the oracle.  The device plane sums of
+"""GPU statistics (Secs. 4.2 and 4.3 channel statistics) against the oracle.  The device plane sums of
 each sample equal the oracle's sums of the same fields read back, and the whole pipeline
 (substeps, samples, finalisation) equals the oracle's own run.  Sums of the same terms in
 another order differ by rounding of the order eps log2(terms) times the sum of |term|, so

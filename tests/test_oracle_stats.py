@@ -1,4 +1,4 @@
-"""Pins of the statistics oracle (Sec. 4.2 channel statistics, Eqs. eps_f and error):
+"""Pins of the statistics oracle (Secs. 4.2 and 4.3 channel statistics, Eqs. eps_f and error):
 closed forms for uniform and sinusoidal fields, the discrete laminar Poiseuille wall stress,
 bulk velocity and skin friction on a uniform grid, exact batch-means cases, and the profile
 error of a constant offset."""
