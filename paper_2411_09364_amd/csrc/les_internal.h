@@ -181,6 +181,7 @@ struct Ctx {
   int dsm_kc = 8;         // planes per z chunk of the fused dynamic-model kernel
   int mlp_kc = 8;         // planes per z chunk of the learned-closure inference kernel
   int pred_kc = 8;        // planes per z chunk of the z-marching predictor
+  int bulk_nblk = 0;      // forward-x flow-rate partials awaiting the shift (spectral_solve forms it)
   // learned closure
   float* mlp_params = nullptr;   // caller-owned float32 parameters (les_mlp_bind)
   double mlp_lo[7], mlp_hi[7];    // feature ranges for min-max scaling

@@ -588,10 +588,22 @@ __global__ void __launch_bounds__(256) k_helm3d_factor(GridP g, const double* __
 // ============================================================================ bulk
 // s = (U_b - <u*>) / <q>, <.> the dzf-weighted volume mean; stored in dt[1].  One block:
 // strided partial sums per thread, then a fixed-order tree (deterministic).
-__global__ void __launch_bounds__(256) k_bulk_final(const double* part, int nblk, double* dtp, const double* q,
-                                                    const double* dzf, int nz, double ubulk, double cells_xy,
-                                                    double lz) {
-  __shared__ double sm[3][256];
+struct BulkArgs {
+  const double* part;
+  int nblk;
+  double* dtp;
+  const double* q;
+  const double* dzf;
+  int nz;
+  double ubulk, cells_xy, lz;
+};
+
+// sm: 3 x 256 doubles of LDS (the dynamic buffer of the transform it runs beside)
+__device__ __forceinline__ void bulk_final_body(const BulkArgs& a_, double (*sm)[256]) {
+  const double* part = a_.part;
+  const int nblk = a_.nblk, nz = a_.nz;
+  const double* q = a_.q;
+  const double* dzf = a_.dzf;
   double a = 0.0, b = 0.0, d = 0.0;
   for (int i = threadIdx.x; i < nblk; i += 256) a += part[i];
   for (int k = threadIdx.x; k < nz; k += 256) {
@@ -608,9 +620,24 @@ __global__ void __launch_bounds__(256) k_bulk_final(const double* part, int nblk
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double mean = sm[0][0] / (cells_xy * lz);
-    dtp[1] = (ubulk - mean) / (sm[1][0] / sm[2][0]);
+    const double mean = sm[0][0] / (a_.cells_xy * a_.lz);
+    a_.dtp[1] = (a_.ubulk - mean) / (sm[1][0] / sm[2][0]);
   }
+}
+
+// Forward y transform with the flow-rate shift folded in: block (0, 0), dispatched first,
+// forms s from the forward-x partials while the others transform (plane = blockIdx.y - 1).
+template <typename T>
+__global__ void __launch_bounds__(256) k_ffty_bulk(FftPlan P, cpx<T>* data, int nl, int64_t lstride, int64_t ostride,
+                                                   int L, const double* twd, const float* twf, const double* lamx,
+                                                   const double* lamy, const double* lamz, BulkArgs ba) {
+  if (blockIdx.y == 0) {
+    extern __shared__ unsigned char smem_raw[];
+    if (blockIdx.x == 0) bulk_final_body(ba, reinterpret_cast<double(*)[256]>(smem_raw));
+    return;
+  }
+  fft_lines_body<T, -1, false>(dim3(blockIdx.x, blockIdx.y - 1), P, data, nl, lstride, ostride, L, twd, twf, lamx,
+                               lamy, lamz, 1.0);
 }
 
 // ghost planes of a cell-centred scalar (Neumann walls or periodic copies)
@@ -664,9 +691,8 @@ static void fwd_x(Ctx& c, int mode, const T* us, const T* vs, const T* ws, const
   else
     LES_LAUNCH(c, "rfftx", in_bytes + spec_bytes, (k_rfftx<T, 1>), dim3(nblk), dim3(256), sh, c.g, P, us, vs, ws, fin,
                        (cpx<T>*)c.spec, c.t.twx, c.t.twx_f, c.t.dt, gamma, pb, bp);
-  if (bulk)
-    LES_LAUNCH(c, "bulk_final", 0, k_bulk_final, dim3(1), dim3(256), 0, c.t.bulk, (int)nblk, c.t.dt,
-                       c.t.hfac + 4 * c.g.nz, c.t.dzf, c.g.nz, c.cfg.ubulk, (double)c.g.sxy, c.cfg.lz);
+  // the flow-rate shift is formed by an extra block of the forward y transform that follows
+  c.bulk_nblk = bulk ? (int)nblk : 0;
 }
 
 // y transforms of the spectrum buffer (DIR -1 forward, +1 inverse)
@@ -706,7 +732,19 @@ static void spectral_solve(Ctx& c) {
   const int ny = c.g.ny, nz = c.g.nz;
   cpx<T>* sp = (cpx<T>*)c.spec;
   const double spec_bytes = (double)nxh * ny * nz * 2 * sizeof(T);
-  ffty<T, -1>(c, "ffty_fwd");
+  if (c.bulk_nblk > 0) {
+    const FftPlan P = make_plan(ny);
+    const int L = lines_per_block(ny);
+    dim3 grid((nxh + L - 1) / L, nz + 1);
+    const size_t sh = std::max(2 * (size_t)L * (ny + 1) * sizeof(cpx<T>), 3 * 256 * sizeof(double));
+    const BulkArgs ba{c.t.bulk, c.bulk_nblk, c.t.dt, c.t.hfac + 4 * nz, c.t.dzf, nz, c.cfg.ubulk, (double)c.g.sxy,
+                      c.cfg.lz};
+    LES_LAUNCH(c, "ffty_fwd", 2 * spec_bytes, (k_ffty_bulk<T>), grid, dim3(256), sh, P, sp, nxh, (int64_t)c.g.nxp,
+               (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, ba);
+    c.bulk_nblk = 0;
+  } else {
+    ffty<T, -1>(c, "ffty_fwd");
+  }
   if (c.cfg.zbc == LES_ZBC_PERIODIC) {
     fftz_solve<T>(c, "fftz_solve", 0.0);
   } else {
