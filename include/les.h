@@ -185,7 +185,8 @@ les_status les_diag(les_ctx* ctx, les_diag_t* out);
  * nbatch equal consecutive batches (the oldest samples beyond nbatch * floor(len / nbatch)
  * dropped), std of the batch means (n - 1 norm) / sqrt(nbatch), times 2 / u_b^2. */
 #define LES_STATS_NPROF 11
-#define LES_STATS_SERIES_MAX 65536   /* samples kept in the wall-stress series */
+#define LES_STATS_SERIES_MAX 65536   /* the wall-stress series keeps the first this many samples;
+                                        the running sums take every sample */
 /* profile rows of les_stats_read: means, then covariances (mean product minus product of
  * the means of the two edge factors) */
 enum { LES_STAT_U = 0, LES_STAT_V, LES_STAT_W, LES_STAT_P, LES_STAT_NUT, LES_STAT_UU, LES_STAT_VV, LES_STAT_WW,
