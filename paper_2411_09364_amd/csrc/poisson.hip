@@ -127,6 +127,74 @@ __device__ cpx<R>* stockham(cpx<R>* src, cpx<R>* dst, const FftPlan& P, const R*
   return src;
 }
 
+// In-place Stockham for long strided lines, where the line groups of the ping-pong form are
+// too narrow to fill a cache line: one LDS buffer holds twice the lines.  Each stage first
+// reads every butterfly of the thread into registers (at most PPT / RAD of them, PPT = the
+// points per thread that the launch guarantees), then, after a barrier, writes the outputs
+// over the same buffer.
+template <typename R, int DIR, int RAD, int BPT>
+__device__ inline void stage_ip(cpx<R>* buf, int N, int Ns, const R* tw, int lane, int team) {
+  const int nb = N / RAD, ts = N / (Ns * RAD);
+  cpx<R> v[BPT][RAD];
+#pragma unroll
+  for (int t = 0; t < BPT; ++t) {
+    const int b = lane + t * team;
+    if (b < nb) {
+      const int k = b % Ns;
+      v[t][0] = buf[b];
+#pragma unroll
+      for (int q = 1; q < RAD; ++q) v[t][q] = twiddle<R, DIR>(buf[b + q * nb], tw, q * k * ts);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < BPT; ++t) {
+    const int b = lane + t * team;
+    if (b < nb) {
+      const int k = b % Ns;
+      const int o = (b / Ns) * Ns * RAD + k;
+      if (RAD == 2) {
+        const cpx<R> v0 = v[t][0], v1 = v[t][1];
+        buf[o] = {v0.x + v1.x, v0.y + v1.y};
+        buf[o + Ns] = {v0.x - v1.x, v0.y - v1.y};
+      } else if (RAD == 4) {
+        const cpx<R> v0 = v[t][0], v1 = v[t][1], v2 = v[t][2], v3 = v[t][3];
+        const cpx<R> s02 = {v0.x + v2.x, v0.y + v2.y}, d02 = {v0.x - v2.x, v0.y - v2.y};
+        const cpx<R> s13 = {v1.x + v3.x, v1.y + v3.y}, d13 = {v1.x - v3.x, v1.y - v3.y};
+        const cpx<R> jd = {-(R)DIR * d13.y, (R)DIR * d13.x};   // DIR * i * d13
+        buf[o] = {s02.x + s13.x, s02.y + s13.y};
+        buf[o + Ns] = {d02.x + jd.x, d02.y + jd.y};
+        buf[o + 2 * Ns] = {s02.x - s13.x, s02.y - s13.y};
+        buf[o + 3 * Ns] = {d02.x - jd.x, d02.y - jd.y};
+      } else {
+        const R h3 = (R)0.86602540378443864676;
+        const cpx<R> v0 = v[t][0], v1 = v[t][1], v2 = v[t][RAD - 1];
+        const cpx<R> s12 = {v1.x + v2.x, v1.y + v2.y}, d12 = {v1.x - v2.x, v1.y - v2.y};
+        const cpx<R> m = {v0.x - (R)0.5 * s12.x, v0.y - (R)0.5 * s12.y};
+        const cpx<R> jd = {-(R)DIR * h3 * d12.y, (R)DIR * h3 * d12.x};
+        buf[o] = {v0.x + s12.x, v0.y + s12.y};
+        buf[o + Ns] = {m.x + jd.x, m.y + jd.y};
+        buf[o + 2 * Ns] = {m.x - jd.x, m.y - jd.y};
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int DIR, int PPT>
+__device__ cpx<R>* stockham_ip(cpx<R>* buf, const FftPlan& P, const R* __restrict__ tw, int lane, int team) {
+  const int N = P.n;
+  int Ns = 1;
+  for (int s = 0; s < P.nst; ++s) {
+    const int r = P.rad[s];
+    if (r == 4) stage_ip<R, DIR, 4, (PPT + 3) / 4>(buf, N, Ns, tw, lane, team);
+    else if (r == 2) stage_ip<R, DIR, 2, (PPT + 1) / 2>(buf, N, Ns, tw, lane, team);
+    else stage_ip<R, DIR, 3, (PPT + 2) / 3>(buf, N, Ns, tw, lane, team);
+    Ns *= r;
+  }
+  return buf;
+}
+
 template <typename T>
 __device__ inline const T* twsel(const double* d, const float* f);
 template <>
@@ -304,7 +372,7 @@ __global__ void __launch_bounds__(256) kb_irfftx(BatchMap m) {
 // is the Laplacian when hg = 0 (Poisson; the zero mode is set to 0), else the Helmholtz
 // operator 1 - hg dt lam of Crank-Nicolson in all directions (hg = gamma nu / 2, dt from
 // the device slot).
-template <typename T, int DIR, bool SOLVE>
+template <typename T, int DIR, bool SOLVE, int PPT = 0>
 __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T>* __restrict__ data, int nl, int64_t lstride,
                                                    int64_t ostride, int L, const double* __restrict__ twd,
                                                    const float* __restrict__ twf, const double* __restrict__ lamx,
@@ -342,7 +410,9 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T
   const int team = blockDim.x / L;
   const int ll = threadIdx.x / team, lane = threadIdx.x % team;
   const T* tw = twsel<T>(twd, twf);
-  cpx<T>* res = stockham<T, DIR>(A + ll * NP, B + ll * NP, P, tw, lane, team);
+  cpx<T>* res;
+  if constexpr (PPT > 0) res = stockham_ip<T, DIR, PPT>(A + ll * NP, P, tw, lane, team);
+  else res = stockham<T, DIR>(A + ll * NP, B + ll * NP, P, tw, lane, team);
   if (SOLVE) {
     // res holds the z spectrum of column (l, m = o); o indexes y modes here
     const int l = l0 + ll;
@@ -354,8 +424,12 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T
       res[t].y = (T)((double)res[t].y * f);
     }
     __syncthreads();
-    cpx<T>* other = (res == A + ll * NP) ? B + ll * NP : A + ll * NP;
-    res = stockham<T, 1>(res, other, P, tw, lane, team);
+    if constexpr (PPT > 0) {
+      res = stockham_ip<T, 1, PPT>(res, P, tw, lane, team);
+    } else {
+      cpx<T>* other = (res == A + ll * NP) ? B + ll * NP : A + ll * NP;
+      res = stockham<T, 1>(res, other, P, tw, lane, team);
+    }
   }
   // every team's result lies in the same buffer (A or B)
   cpx<T>* R = (res == A + ll * NP) ? A : B;
@@ -367,12 +441,13 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T
   }
 }
 
-template <typename T, int DIR, bool SOLVE>
+template <typename T, int DIR, bool SOLVE, int PPT = 0>
 __global__ void __launch_bounds__(256) k_fft_lines(FftPlan P, cpx<T>* data, int nl, int64_t lstride, int64_t ostride,
                                                    int L, const double* twd, const float* twf, const double* lamx,
                                                    const double* lamy, const double* lamz, double norm,
                                                    const double* dtp, double hg) {
-  fft_lines_body<T, DIR, SOLVE>(blockIdx, P, data, nl, lstride, ostride, L, twd, twf, lamx, lamy, lamz, norm, dtp, hg);
+  fft_lines_body<T, DIR, SOLVE, PPT>(blockIdx, P, data, nl, lstride, ostride, L, twd, twf, lamx, lamy, lamz, norm, dtp,
+                                     hg);
 }
 
 // Batched y transforms (SOLVE = false) or periodic-z spectral solve (SOLVE = true).
@@ -531,13 +606,13 @@ __global__ void __launch_bounds__(256) k_irfftx3(GridP g, FftPlan P, const cpx<T
   irfftx_body<T>(dim3(blockIdx.x), g, P, spec + comp * cstride, f, twd, twf, npair_blk);
 }
 
-template <typename T, int DIR, bool SOLVE>
+template <typename T, int DIR, bool SOLVE, int PPT = 0>
 __global__ void __launch_bounds__(256) k_fft_lines3(FftPlan P, cpx<T>* data, int64_t cstride, int nl, int64_t lstride,
                                                     int64_t ostride, int L, const double* twd, const float* twf,
                                                     const double* lamx, const double* lamy, const double* lamz,
                                                     double norm, const double* dtp, double hg) {
-  fft_lines_body<T, DIR, SOLVE>(dim3(blockIdx.x, blockIdx.y), P, data + blockIdx.z * cstride, nl, lstride, ostride, L,
-                                twd, twf, lamx, lamy, lamz, norm, dtp, hg);
+  fft_lines_body<T, DIR, SOLVE, PPT>(dim3(blockIdx.x, blockIdx.y), P, data + blockIdx.z * cstride, nl, lstride, ostride,
+                                     L, twd, twf, lamx, lamy, lamz, norm, dtp, hg);
 }
 
 // component blockIdx.y: u and v take the u/v rows and factors, w the w rows (nz - 1 unknowns)
@@ -627,7 +702,7 @@ __device__ __forceinline__ void bulk_final_body(const BulkArgs& a_, double (*sm)
 
 // Forward y transform with the flow-rate shift folded in: block (0, 0), dispatched first,
 // forms s from the forward-x partials while the others transform (plane = blockIdx.y - 1).
-template <typename T>
+template <typename T, int PPT = 0>
 __global__ void __launch_bounds__(256) k_ffty_bulk(FftPlan P, cpx<T>* data, int nl, int64_t lstride, int64_t ostride,
                                                    int L, const double* twd, const float* twf, const double* lamx,
                                                    const double* lamy, const double* lamz, BulkArgs ba) {
@@ -636,8 +711,8 @@ __global__ void __launch_bounds__(256) k_ffty_bulk(FftPlan P, cpx<T>* data, int 
     if (blockIdx.x == 0) bulk_final_body(ba, reinterpret_cast<double(*)[256]>(smem_raw));
     return;
   }
-  fft_lines_body<T, -1, false>(dim3(blockIdx.x, blockIdx.y - 1), P, data, nl, lstride, ostride, L, twd, twf, lamx,
-                               lamy, lamz, 1.0);
+  fft_lines_body<T, -1, false, PPT>(dim3(blockIdx.x, blockIdx.y - 1), P, data, nl, lstride, ostride, L, twd, twf,
+                                    lamx, lamy, lamz, 1.0);
 }
 
 // ghost planes of a cell-centred scalar (Neumann walls or periodic copies)
@@ -675,6 +750,23 @@ static int lines_per_block(int n) {
   return std::min(L, 32);
 }
 
+// Line groups of the single-field strided transforms: the ping-pong form (two buffers of
+// L <= 1024 / n lines), unless its row segments of L consecutive l stay under 64 bytes (long
+// lines); then the in-place form with up to four times the lines (L n <= 4096, one buffer
+// within 64 KB), ppt = L n / 256 points per thread rounded up to 8 or 16.
+struct LineShape {
+  int L, ppt;      // ppt 0: ping-pong
+  size_t sh;       // dynamic LDS bytes
+};
+static LineShape line_shape(int n, size_t esz) {
+  const int Lpp = lines_per_block(n);
+  if ((size_t)Lpp * esz >= 64 || n > 4096) return {Lpp, 0, 2 * (size_t)Lpp * (n + 1) * esz};
+  int L = Lpp;
+  while (L < 32 && (size_t)(2 * L) * n <= 4096 && (size_t)(2 * L) * (n + 1) * esz <= 65536) L *= 2;
+  const int ppt = L * n / 256 <= 8 ? 8 : 16;
+  return {L, ppt, (size_t)L * (n + 1) * esz};
+}
+
 template <typename T>
 static void fwd_x(Ctx& c, int mode, const T* us, const T* vs, const T* ws, const T* fin, double gamma, bool bulk) {
   const FftPlan P = make_plan(c.g.nx);
@@ -696,18 +788,28 @@ static void fwd_x(Ctx& c, int mode, const T* us, const T* vs, const T* ws, const
 }
 
 // y transforms of the spectrum buffer (DIR -1 forward, +1 inverse)
+template <typename T, int DIR, bool SOLVE>
+static decltype(&k_fft_lines<T, DIR, SOLVE, 0>) lines_kernel(int ppt) {
+  return ppt == 0 ? k_fft_lines<T, DIR, SOLVE, 0> : (ppt == 8 ? k_fft_lines<T, DIR, SOLVE, 8> : k_fft_lines<T, DIR, SOLVE, 16>);
+}
+template <typename T, int DIR, bool SOLVE>
+static decltype(&k_fft_lines3<T, DIR, SOLVE, 0>) lines3_kernel(int ppt) {
+  return ppt == 0 ? k_fft_lines3<T, DIR, SOLVE, 0>
+                  : (ppt == 8 ? k_fft_lines3<T, DIR, SOLVE, 8> : k_fft_lines3<T, DIR, SOLVE, 16>);
+}
+
 template <typename T, int DIR>
 static void ffty(Ctx& c, const char* name) {
   const int nxh = c.g.nx / 2 + 1;
   const int ny = c.g.ny, nz = c.g.nz;
   const double spec_bytes = (double)nxh * ny * nz * 2 * sizeof(T);
   const FftPlan P = make_plan(ny);
-  const int L = lines_per_block(ny);
+  const LineShape ls = line_shape(ny, sizeof(cpx<T>));
+  const int L = ls.L;
   dim3 grid((nxh + L - 1) / L, nz);
-  const size_t sh = 2 * (size_t)L * (ny + 1) * sizeof(cpx<T>);
-  LES_LAUNCH(c, name, 2 * spec_bytes, (k_fft_lines<T, DIR, false>), grid, dim3(256), sh, P, (cpx<T>*)c.spec, nxh,
-             (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0,
-             nullptr, 0.0);
+  LES_LAUNCH(c, name, 2 * spec_bytes, (lines_kernel<T, DIR, false>(ls.ppt)), grid, dim3(256), ls.sh, P,
+             (cpx<T>*)c.spec, nxh, (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy,
+             c.t.lamz, 1.0, nullptr, 0.0);
 }
 
 // periodic z: FFT, divide by the operator's eigenvalue, inverse FFT (hg = 0: Poisson)
@@ -717,13 +819,13 @@ static void fftz_solve(Ctx& c, const char* name, double hg) {
   const int ny = c.g.ny, nz = c.g.nz;
   const double spec_bytes = (double)nxh * ny * nz * 2 * sizeof(T);
   const FftPlan P = make_plan(nz);
-  const int L = lines_per_block(nz);
+  const LineShape ls = line_shape(nz, sizeof(cpx<T>));
+  const int L = ls.L;
   dim3 grid((nxh + L - 1) / L, ny);
-  const size_t sh = 2 * (size_t)L * (nz + 1) * sizeof(cpx<T>);
   const double norm = 1.0 / ((double)c.g.nx * ny * nz);
-  LES_LAUNCH(c, name, 2 * spec_bytes, (k_fft_lines<T, -1, true>), grid, dim3(256), sh, P, (cpx<T>*)c.spec, nxh,
-             (int64_t)c.g.nxp * ny, (int64_t)c.g.nxp, L, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy, c.t.lamz, norm,
-             c.t.dt, hg);
+  LES_LAUNCH(c, name, 2 * spec_bytes, (lines_kernel<T, -1, true>(ls.ppt)), grid, dim3(256), ls.sh, P,
+             (cpx<T>*)c.spec, nxh, (int64_t)c.g.nxp * ny, (int64_t)c.g.nxp, L, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy,
+             c.t.lamz, norm, c.t.dt, hg);
 }
 
 template <typename T>
@@ -734,12 +836,14 @@ static void spectral_solve(Ctx& c) {
   const double spec_bytes = (double)nxh * ny * nz * 2 * sizeof(T);
   if (c.bulk_nblk > 0) {
     const FftPlan P = make_plan(ny);
-    const int L = lines_per_block(ny);
+    const LineShape ls = line_shape(ny, sizeof(cpx<T>));
+    const int L = ls.L;
     dim3 grid((nxh + L - 1) / L, nz + 1);
-    const size_t sh = std::max(2 * (size_t)L * (ny + 1) * sizeof(cpx<T>), 3 * 256 * sizeof(double));
+    const size_t sh = std::max(ls.sh, 3 * 256 * sizeof(double));
     const BulkArgs ba{c.t.bulk, c.bulk_nblk, c.t.dt, c.t.hfac + 4 * nz, c.t.dzf, nz, c.cfg.ubulk, (double)c.g.sxy,
                       c.cfg.lz};
-    LES_LAUNCH(c, "ffty_fwd", 2 * spec_bytes, (k_ffty_bulk<T>), grid, dim3(256), sh, P, sp, nxh, (int64_t)c.g.nxp,
+    auto kern = ls.ppt == 0 ? k_ffty_bulk<T, 0> : (ls.ppt == 8 ? k_ffty_bulk<T, 8> : k_ffty_bulk<T, 16>);
+    LES_LAUNCH(c, "ffty_fwd", 2 * spec_bytes, kern, grid, dim3(256), sh, P, sp, nxh, (int64_t)c.g.nxp,
                (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, ba);
     c.bulk_nblk = 0;
   } else {
@@ -806,19 +910,20 @@ void launch_helmholtz_3d(Ctx& c, int stage) {
                (const T*)c.wsf, sp, cstride, c.t.twx, c.t.twx_f, pb);
   }
   const FftPlan Py = make_plan(ny);
-  const int Ly = lines_per_block(ny);
-  const size_t shy = 2 * (size_t)Ly * (ny + 1) * sizeof(cpx<T>);
+  const LineShape lsy = line_shape(ny, sizeof(cpx<T>));
+  const int Ly = lsy.L;
   const dim3 gy((nxh + Ly - 1) / Ly, n, 3);
-  LES_LAUNCH(c, "h3d_ffty_fwd", 6 * spec_bytes, (k_fft_lines3<T, -1, false>), gy, dim3(256), shy, Py, sp, cstride, nxh,
-             (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, Ly, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0,
-             nullptr, 0.0);
+  LES_LAUNCH(c, "h3d_ffty_fwd", 6 * spec_bytes, (lines3_kernel<T, -1, false>(lsy.ppt)), gy, dim3(256), lsy.sh, Py, sp,
+             cstride, nxh, (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, Ly, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy,
+             c.t.lamz, 1.0, nullptr, 0.0);
   if (c.cfg.zbc == LES_ZBC_PERIODIC) {
     const FftPlan Pz = make_plan(n);
-    const int Lz = lines_per_block(n);
-    const size_t shz = 2 * (size_t)Lz * (n + 1) * sizeof(cpx<T>);
-    LES_LAUNCH(c, "h3d_fftz_solve", 6 * spec_bytes, (k_fft_lines3<T, -1, true>), dim3((nxh + Lz - 1) / Lz, ny, 3),
-               dim3(256), shz, Pz, sp, cstride, nxh, (int64_t)c.g.nxp * ny, (int64_t)c.g.nxp, Lz, c.t.twz, c.t.twz_f,
-               c.t.lamx, c.t.lamy, c.t.lamz, 1.0 / ((double)nx * ny * n), c.t.dt, hg);
+    const LineShape lsz = line_shape(n, sizeof(cpx<T>));
+    const int Lz = lsz.L;
+    LES_LAUNCH(c, "h3d_fftz_solve", 6 * spec_bytes, (lines3_kernel<T, -1, true>(lsz.ppt)),
+               dim3((nxh + Lz - 1) / Lz, ny, 3), dim3(256), lsz.sh, Pz, sp, cstride, nxh, (int64_t)c.g.nxp * ny,
+               (int64_t)c.g.nxp, Lz, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0 / ((double)nx * ny * n),
+               c.t.dt, hg);
   } else {
     const int64_t nchain = 2 * (int64_t)c.g.nxp * ny;
     const int S = n <= 256 ? 8 : 16;
@@ -836,9 +941,9 @@ void launch_helmholtz_3d(Ctx& c, int stage) {
       LES_LAUNCH(c, "h3d_thomas_z", bytes, (k_thomas_scan3<T, 16>), grid, block, 0, c.g, sp, cstride, a_uv, a_w, f_uv,
                  f_w, norm_xy);
   }
-  LES_LAUNCH(c, "h3d_ffty_inv", 6 * spec_bytes, (k_fft_lines3<T, 1, false>), gy, dim3(256), shy, Py, sp, cstride, nxh,
-             (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, Ly, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0,
-             nullptr, 0.0);
+  LES_LAUNCH(c, "h3d_ffty_inv", 6 * spec_bytes, (lines3_kernel<T, 1, false>(lsy.ppt)), gy, dim3(256), lsy.sh, Py, sp,
+             cstride, nxh, (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, Ly, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy,
+             c.t.lamz, 1.0, nullptr, 0.0);
   {
     const FftPlan P = make_plan(nx);
     const int pb = pairs_per_block(nx);

@@ -45,6 +45,9 @@ POISSON_CASES = [
     dict(nx=16, ny=6, nz=4, lx=1.0, ly=1.0, lz=2.0, zbc=ZBC_NOSLIP, beta=1.5),
     dict(nx=32, ny=16, nz=100, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5),
     dict(nx=8, ny=8, nz=300, lx=1.0, ly=1.0, lz=2.0, zbc=ZBC_NOSLIP, beta=1.5),
+    # long strided lines: the in-place transform with wide line groups (y, and z periodic)
+    dict(nx=16, ny=512, nz=6, lx=1.0, ly=4.0, lz=2.0, zbc=ZBC_NOSLIP, beta=1.2),
+    dict(nx=8, ny=8, nz=384, lx=1.0, ly=1.0, lz=3.0, zbc=ZBC_PERIODIC),
 ]
 
 
