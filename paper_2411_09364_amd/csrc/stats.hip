@@ -43,7 +43,8 @@ __global__ void __launch_bounds__(256) k_stats_partial(GridP g, const T* __restr
     const int64_t base = (int64_t)kk * sxy;
     const T cf = (T)coef[kk];
     for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-      const int i = (int)(r % g.nx), j = (int)(r / g.nx);
+      const int rr = (int)r;   // in-plane index (nx ny < 2^31)
+      const int i = rr % g.nx, j = rr / g.nx;
       const int64_t c = base + r;
       const int64_t cip = base + (int64_t)j * g.nx + wrap_p(i, g.nx);
       const int64_t cjp = base + (int64_t)wrap_p(j, g.ny) * g.nx + i;

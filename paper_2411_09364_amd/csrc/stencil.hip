@@ -780,12 +780,24 @@ __device__ __forceinline__ void cfl_partial_body(int b, int nb, GridP g, const T
   __shared__ double sm[2][256];
   double mc = 0.0, mn = 0.0;
   const int64_t total = (int64_t)g.nz * g.sxy;
-  for (int64_t e = b * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)nb * blockDim.x) {
-    const int k = (int)(e / g.sxy) + 1;
-    const int64_t c = (int64_t)k * g.sxy + e % g.sxy;
+  // the flattened interior index advances by a fixed stride: its plane and in-plane offset
+  // are stepped along instead of divided out per element
+  const int64_t step = (int64_t)nb * blockDim.x;
+  int64_t e = b * (int64_t)blockDim.x + threadIdx.x;
+  int k = (int)(e / g.sxy) + 1;
+  int64_t r = e % g.sxy;
+  const int64_t dk = step / g.sxy, dr = step % g.sxy;
+  for (; e < total; e += step) {
+    const int64_t c = (int64_t)k * g.sxy + r;
     const double a = fabs((double)u[c]) * g.rdx + fabs((double)v[c]) * g.rdy + fabs((double)w[c]) / g.dzf[k];
     mc = fmax(mc, a);
     mn = fmax(mn, coef[k] * (double)nut[c]);
+    k += (int)dk;
+    r += dr;
+    if (r >= g.sxy) {
+      r -= g.sxy;
+      ++k;
+    }
   }
   sm[0][threadIdx.x] = mc;
   sm[1][threadIdx.x] = mn;
