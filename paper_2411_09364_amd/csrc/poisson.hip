@@ -222,8 +222,8 @@ __device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, const FftPlan& P, 
     const int64_t gp = (int64_t)bid.x * npair_blk + p;
     cpx<T> z = {(T)0, (T)0};
     if (gp < npairs) {
-      const int k = (int)(gp / nyh) + 1;
-      const int j0 = 2 * (int)(gp % nyh);
+      const int k = (int)gp / nyh + 1;
+      const int j0 = 2 * ((int)gp % nyh);
       T fv[2];
       for (int r = 0; r < 2; ++r) {
         const int j = j0 + r;
@@ -264,8 +264,8 @@ __device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, const FftPlan& P, 
   // res points into A or B for team p (same parity for all teams)
   const int64_t gp = (int64_t)bid.x * npair_blk + p;
   if (gp >= npairs) return;
-  const int k = (int)(gp / nyh);
-  const int j0 = 2 * (int)(gp % nyh);
+  const int k = (int)gp / nyh;
+  const int j0 = 2 * ((int)gp % nyh);
   cpx<T>* s0 = spec + ((int64_t)k * g.ny + j0) * g.nxp;
   cpx<T>* s1 = s0 + g.nxp;
   for (int l = lane; l < nxh; l += team) {
@@ -314,8 +314,8 @@ __device__ __forceinline__ void irfftx_body(dim3 bid, GridP g, const FftPlan& P,
       const int p = e / nx, l = e % nx;
       const int64_t gp = (int64_t)bid.x * npair_blk + p;
       const bool ok = e < total && gp < npairs;
-      const int64_t k = ok ? gp / nyh : 0;
-      const int j0 = ok ? 2 * (int)(gp % nyh) : 0;
+      const int64_t k = ok ? (int)gp / nyh : 0;   // pair indices fit 32 bits
+      const int j0 = ok ? 2 * ((int)gp % nyh) : 0;
       const int ls = l < nxh ? l : nx - l;
       const cpx<T>* s0 = spec + (k * g.ny + j0) * g.nxp;
       va[b] = s0[ls];
@@ -342,8 +342,8 @@ __device__ __forceinline__ void irfftx_body(dim3 bid, GridP g, const FftPlan& P,
   cpx<T>* res = stockham<T, 1>(A + p * nx, B + p * nx, P, tw, lane, team);
   const int64_t gp = (int64_t)bid.x * npair_blk + p;
   if (gp >= npairs) return;
-  const int k = (int)(gp / nyh) + 1;
-  const int j0 = 2 * (int)(gp % nyh);
+  const int k = (int)gp / nyh + 1;
+  const int j0 = 2 * ((int)gp % nyh);
   for (int i = lane; i < nx; i += team) {
     out[idx3(g, k, j0, i)] = res[i].x;
     out[idx3(g, k, j0 + 1, i)] = res[i].y;
