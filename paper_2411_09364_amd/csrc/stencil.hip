@@ -78,7 +78,7 @@ __device__ __forceinline__ void predictor_cell(const Nb<T>& b, const GridP& g, i
   const T nu = (T)g.nu;
   const T h = (T)0.5, q = (T)0.25, two = (T)2;
   // ---------------- u-momentum at (i+1/2, j, k)
-  T ax, ay, az, sx, sy, sz, lx, ly, lz;
+  T ax, ay, az, sx, sy, sz, lx, lz;
   {
     const T fxx_r = (h * (b.u0 + b.uip)) * (h * (b.u0 + b.uip));
     const T fxx_l = (h * (b.uim + b.u0)) * (h * (b.uim + b.u0));
