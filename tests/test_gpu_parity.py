@@ -157,6 +157,9 @@ SUBSTEP_CASES = [
     ("cn-3d noslip vd radix3 rect",
      dict(nx=96, ny=48, nz=12, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_NOSLIP, beta=1.5, nu=2e-3,
           sgs=SGS_SMAG_VD, cs=0.1), "channel", 3),
+    ("cn-3d wm fewest planes h_wm",
+     dict(nx=16, ny=8, nz=4, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.0, nu=1e-3,
+          sgs=SGS_SMAG_VD, cs=0.1, h_wm=0.6, implicit_3d=True, ubulk=1.0), "channel", 3),
 ]
 
 
@@ -222,6 +225,8 @@ MIXED_CASES = [
                                 sgs=SGS_DSM), "iso"),
     ("mixed cn-3d wm dsm", dict(nx=48, ny=24, nz=20, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL,
                                 beta=1.5, nu=5e-4, sgs=SGS_DSM, implicit_3d=True, ubulk=1.0), "channel"),
+    ("mixed cn-3d periodic", dict(nx=24, ny=24, nz=24, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, nu=2e-2,
+                                  sgs=SGS_SMAG, implicit_3d=True), "iso"),
 ]
 
 
