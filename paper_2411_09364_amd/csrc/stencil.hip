@@ -335,9 +335,9 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) k_predictor(GridP
                                                                         double alpha, double beta, double gamma,
                                                                         int use_rprev, int write_r, double* hfac,
                                                                         int wallmodel, int kc,
-                                                                        const double* __restrict__ tau) {
+                                                                        const double* __restrict__ tau, int fslice) {
   const dim3 bid = xcd_tile(blockIdx, gridDim);
-  if (MODE != VISC_EXPLICIT && bid.z == 0) {
+  if (MODE != VISC_EXPLICIT && fslice && bid.z == 0) {
     __shared__ double fz[2][kMaxNz + 2];   // metric copies of the factorisation
     if (bid.x == 0 && bid.y == 0)
       helmholtz_factor_body(g, hfac, dtp, gamma, wallmodel, fz[0], fz[1], threadIdx.y * blockDim.x + threadIdx.x,
@@ -345,8 +345,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) k_predictor(GridP
     return;
   }
   predictor_zm_body<T, MODE>(bid, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta, gamma,
-                             use_rprev, write_r, kc, MODE != VISC_EXPLICIT ? (int)bid.z - 1 : (int)bid.z, tau,
-                             wallmodel);
+                             use_rprev, write_r, kc, (int)bid.z - fslice, tau, wallmodel);
 }
 
 // Batched predictor (explicit viscous terms): one launch over all boxes of a batch, the same
@@ -372,7 +371,10 @@ void launch_predictor(Ctx& c, int stage) {
   const int kc = c.pred_kc;
   const unsigned nch = (unsigned)((c.g.nz + kc - 1) / kc);
   const int mode = c.cfg.implicit_z;   // VISC_* (validated at init)
-  const dim3 grid((c.g.nx + TX - 1) / TX, (c.g.ny + TY - 1) / TY, nch + (mode != VISC_EXPLICIT ? 1 : 0));
+  // the Helmholtz rows are needed with walls only (periodic z solves by FFT): the extra z slice
+  // that factorises them exists then
+  const int fslice = mode != VISC_EXPLICIT && c.cfg.zbc != LES_ZBC_PERIODIC ? 1 : 0;
+  const dim3 grid((c.g.nx + TX - 1) / TX, (c.g.ny + TY - 1) / TY, nch + fslice);
   const int use_rprev = stage > 0;
   const int write_r = stage < 2;
   auto f = mode == VISC_CN_3D ? k_predictor<T, VISC_CN_3D>
@@ -382,7 +384,7 @@ void launch_predictor(Ctx& c, int stage) {
   LES_LAUNCH(c, "predictor", words * pts * sizeof(T), f, grid, dim3(TX, TY), 0, c.g, (const T*)c.u, (const T*)c.v,
              (const T*)c.w, (const T*)c.p, (const T*)c.nut, c.t.coef, (T*)c.ru, (T*)c.rv, (T*)c.rw, (T*)c.us,
              (T*)c.vs, (T*)c.wsf, c.t.dt, A[stage], B[stage], G, use_rprev, write_r, c.t.hfac,
-             c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, kc, c.t.tau);
+             c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, kc, c.t.tau, fslice);
 }
 
 // ============================================================================ CN in z
