@@ -10,6 +10,12 @@ z = lz.  Wall treatment:
   wall-model stress is the boundary condition of the wall-parallel velocity);
   nu_t odd about the wall (R12), so the SGS flux through the wall is zero and the wall
   stress is carried by the viscous term alone.
+With walls in y as well (square duct, Sec. 4.4; R35) the two ghost rows of grid.py follow
+the same rules with the roles of the components exchanged: v = 0 on the wall faces (row
+ny - 1 and ghost row ny + 1; ghost row ny, beyond the wall, is set to 0 and never read),
+u and w odd (no-slip) or from the y-wall stresses, p even, nu_t odd.  z ghost planes are
+filled first on every stored row, then the y ghost rows on every stored plane, so the
+corner values come from the y rule.
 """
 import math
 
@@ -24,9 +30,35 @@ def periodic_z(a, nz):
     a[nz + 1] = a[1]
 
 
-def fill_velocity(case, g, u, v, w, tau=None):
+def fill_velocity(case, g, u, v, w, tau=None, tauy=None):
     """Ghost planes of u, v, w (Alg. 2, lines 1, 2 and 4).  tau = (tx_bot, ty_bot, tx_top,
-    ty_top) from wall_stress() is required for the wall-model case."""
+    ty_top) from wall_stress() is required for the wall-model case, and with y walls tauy =
+    (tx_lo, tz_lo, tx_hi, tz_hi) from wall_stress_y()."""
+    _fill_velocity_z(case, g, u, v, w, tau)
+    if g.ywalls:
+        _fill_velocity_y(case, g, u, v, w, tauy)
+
+
+def _fill_velocity_y(case, g, u, v, w, tauy):
+    """y ghost rows (R35): row ny above y = ly, row ny + 1 below y = 0."""
+    ny = g.ny
+    v[:, ny - 1] = 0.0
+    v[:, ny] = 0.0
+    v[:, ny + 1] = 0.0
+    if case.zbc == ZBC_WALLMODEL:
+        txl, tzl, txh, tzh = tauy
+        u[:, ny + 1] = u[:, 0] - g.dy * txl / case.nu
+        w[:, ny + 1] = w[:, 0] - g.dy * tzl / case.nu
+        u[:, ny] = u[:, ny - 1] - g.dy * txh / case.nu
+        w[:, ny] = w[:, ny - 1] - g.dy * tzh / case.nu
+    else:
+        u[:, ny + 1] = -u[:, 0]
+        w[:, ny + 1] = -w[:, 0]
+        u[:, ny] = -u[:, ny - 1]
+        w[:, ny] = -w[:, ny - 1]
+
+
+def _fill_velocity_z(case, g, u, v, w, tau):
     nz = g.nz
     if case.zbc == ZBC_PERIODIC:
         for a in (u, v, w):
@@ -58,6 +90,9 @@ def fill_scalar(case, g, p):
     else:
         p[0] = p[1]
         p[nz + 1] = p[nz]
+    if g.ywalls:
+        p[:, g.ny + 1] = p[:, 0]
+        p[:, g.ny] = p[:, g.ny - 1]
 
 
 def fill_nut(case, g, nut):
@@ -68,21 +103,30 @@ def fill_nut(case, g, nut):
     else:
         nut[0] = -nut[1]
         nut[nz + 1] = -nut[nz]
+    if g.ywalls:
+        nut[:, g.ny + 1] = -nut[:, 0]
+        nut[:, g.ny] = -nut[:, g.ny - 1]
 
 
-def strain_ghosts(case, g, u, v):
+def strain_ghosts(case, g, u, v, w):
     """Velocity ghosts used only to evaluate the strain rate for the SGS model.
     With the wall model the wall-normal derivative in the first layer is one-sided
     (Sec. 2.2): the ghost is the linear extrapolation, in z, of the first two interior
     values, so the central difference at the wall edge equals (u_2 - u_1)/dzc_1.
-    Otherwise the ordinary ghosts are used.  Returns modified copies."""
-    u2, v2 = u.copy(), v.copy()
+    With y walls u and w get the same extrapolation in y (uniform dy), after the z one.
+    Otherwise the ordinary ghosts are used.  Returns modified copies (u, v, w)."""
+    u2, v2, w2 = u.copy(), v.copy(), w.copy()
     if case.zbc == ZBC_WALLMODEL:
         nz = g.nz
         for a in (u2, v2):
             a[0] = a[1] - g.dzc[0] * (a[2] - a[1]) / g.dzc[1]
             a[nz + 1] = a[nz] + g.dzc[nz] * (a[nz] - a[nz - 1]) / g.dzc[nz - 1]
-    return u2, v2
+        if g.ywalls:
+            ny = g.ny
+            for a in (u2, w2):
+                a[:, ny + 1] = a[:, 0] - (a[:, 1] - a[:, 0])
+                a[:, ny] = a[:, ny - 1] + (a[:, ny - 1] - a[:, ny - 2])
+    return u2, v2, w2
 
 
 # ---------------------------------------------------------------- log-law wall model
@@ -177,7 +221,82 @@ def wall_stress(case, g, u, v, utau_prev):
             utau[key] = ut
             out.append(tau)
     txb, tyb, txt, tyt = out
+    if g.ywalls:
+        # R35: the y ghost rows carry no z-wall stress, and the v row on the wall face
+        # y = ly has no wall-parallel velocity
+        for a in out:
+            a[g.ny:] = 0.0
+        tyb[g.ny - 1] = 0.0
+        tyt[g.ny - 1] = 0.0
     return (txb, tyb, txt, tyt), utau, itmax
+
+
+def _wm_rows(case, g):
+    """y-wall counterpart of _wm_planes (uniform dy, R35): (row, next row inward, weight,
+    height) for the wall at y = 0 and the wall at y = ly."""
+    ny = g.ny
+    yc = g.yc
+    if case.h_wm <= 0.0:
+        return (0, 1, 0.0, yc[0]), (ny - 1, ny - 2, 0.0, g.ly - yc[ny - 1])
+    h = case.h_wm
+    jb = max(j for j in range(0, ny - 1) if yc[j] <= h)
+    tb = (h - yc[jb]) / (yc[jb + 1] - yc[jb])
+    jt = min(j for j in range(1, ny) if g.ly - yc[j] <= h)
+    d_lo, d_hi = g.ly - yc[jt], g.ly - yc[jt - 1]
+    tt = (h - d_lo) / (d_hi - d_lo)
+    return (jb, jb + 1, tb, h), (jt, jt - 1, tt, h)
+
+
+def wall_stress_y(case, g, u, w, utau_prev):
+    """Wall-model stresses on the walls y = 0 and y = ly (square duct, Sec. 4.4; R35): the
+    rule of wall_stress() with z replaced by y and v by w.  For each wall and each wall-
+    parallel component (u at (i+1/2, k), w at (i, k+1/2)), at its own face points of the
+    interior planes: interpolate u and w linearly in y to h_wm, bring the other component
+    to the same point by the mean of its four surrounding faces (x and z neighbours), take
+    U = sqrt(u^2 + w^2), solve for u_tau and set tau = u_tau^2 (component) / U.  w on the
+    z wall faces (k = 0 and nz) has no stress.  Returns ((tx_lo, tz_lo, tx_hi, tz_hi) each
+    (nz + 2, nx) with zero ghost planes, utau dict, max iteration count)."""
+    lo, hi = _wm_rows(case, g)
+    n = g.nz
+    out, utau, itmax = [], {}, 0
+    for name, (j0, j1, t, h) in (("ylo", lo), ("yhi", hi)):
+        ui = (1.0 - t) * u[:, j0] + t * u[:, j1]          # (nz + 2, nx)
+        wi = (1.0 - t) * w[:, j0] + t * w[:, j1]
+        w_at_u = np.zeros_like(ui)
+        u_at_w = np.zeros_like(ui)
+        for k in range(1, n + 1):
+            w_at_u[k] = 0.25 * (wi[k] + xp(wi[k]) + wi[k - 1] + xp(wi[k - 1]))
+            u_at_w[k] = 0.25 * (ui[k] + xm(ui[k]) + ui[k + 1] + xm(ui[k + 1]))
+        for comp, a, b in (("x", ui, w_at_u), ("z", wi, u_at_w)):
+            key = name + comp
+            prev = utau_prev[key] if (utau_prev is not None and key in utau_prev) else np.zeros_like(a)
+            U = np.sqrt(a * a + b * b)
+            ut, its = newton_utau_array(U, h, case.nu, case.kappa, case.bconst, prev)
+            itmax = max(itmax, its)
+            safe = np.where(U > 0.0, U, 1.0)
+            tau = np.where(U > 0.0, ut * ut * a / safe, 0.0)
+            tau[0] = 0.0
+            tau[n + 1] = 0.0
+            if comp == "z":
+                tau[n] = 0.0
+            utau[key] = ut
+            out.append(tau)
+    return tuple(out), utau, itmax
+
+
+def noslip_wall_stress_y(case, g, u, w):
+    """y-wall counterpart of noslip_wall_stress (R35): nu du/dy and nu dw/dy at the walls
+    y = 0 and y = ly from the no-slip ghost rows, (tx_lo, tz_lo, tx_hi, tz_hi) each
+    (nz + 2, nx), zero on the z ghost planes and, for w, on the z wall faces."""
+    ny, n = g.ny, g.nz
+    out = [case.nu * (u[:, 0] - u[:, ny + 1]) / g.dy, case.nu * (w[:, 0] - w[:, ny + 1]) / g.dy,
+           case.nu * (u[:, ny - 1] - u[:, ny]) / g.dy, case.nu * (w[:, ny - 1] - w[:, ny]) / g.dy]
+    for q, a in enumerate(out):
+        a[0] = 0.0
+        a[n + 1] = 0.0
+        if q % 2 == 1 and not g.periodic_z:
+            a[n] = 0.0
+    return tuple(out)
 
 
 def noslip_wall_stress(case, g, u, v):

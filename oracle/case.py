@@ -2,6 +2,7 @@
 from dataclasses import dataclass
 
 ZBC_PERIODIC, ZBC_NOSLIP, ZBC_WALLMODEL = 0, 1, 2
+YBC_PERIODIC, YBC_WALL = 0, 1   # y walls take the z walls' treatment (duct, Sec. 4.4)
 SGS_NONE, SGS_SMAG, SGS_SMAG_VD, SGS_DSM, SGS_MLP = 0, 1, 2, 3, 4
 
 
@@ -25,6 +26,11 @@ class Case:
     kappa: float = 0.41
     bconst: float = 5.2
     advection: bool = True     # False only in tests that isolate the viscous operator
+    ybc: int = YBC_PERIODIC    # YBC_WALL: walls at y = 0 and y = ly as well (square duct)
+
+    def __post_init__(self):
+        if self.ybc == YBC_WALL and (self.zbc == ZBC_PERIODIC or self.implicit_3d or self.sgs > SGS_SMAG_VD):
+            raise ValueError("y walls need walls in z, no CN in y and a static eddy-viscosity model")
 
     @property
     def zperiodic(self):
@@ -33,3 +39,7 @@ class Case:
     @property
     def walls(self):
         return self.zbc != ZBC_PERIODIC
+
+    @property
+    def ywalls(self):
+        return self.ybc == YBC_WALL

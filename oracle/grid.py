@@ -2,7 +2,13 @@
 solver's non-uniform direction, which the paper calls y).  Test infrastructure only.
 
 Indices: cells i = 0..nx-1, j = 0..ny-1 (periodic), k = 1..nz with ghost planes
-k = 0 and k = nz + 1.  zf[k] is the top face of cell k (zf[0] = 0, zf[nz] = lz),
+k = 0 and k = nz + 1.  With walls in y as well (the square duct of Sec. 4.4) the arrays
+carry two ghost rows, stored after the interior ones: row ny is the ghost above y = ly and
+row ny + 1 the ghost below y = 0.  Row ny + 1 is where the periodic index j - 1 of row 0
+lands, so the periodic difference operators give the wall-bounded ones on every interior
+row once the ghost rows hold the boundary values; nys = ny + 2 is the stored row count.
+The y spacing is uniform; v at row j sits at (j + 1) dy, so row ny - 1 of v is the wall
+face y = ly and the ghost row ny + 1 is the wall face y = 0.  zf[k] is the top face of cell k (zf[0] = 0, zf[nz] = lz),
 zc[k] the centre, dzf[k] = zf[k] - zf[k-1] the cell height, dzc[k] = zc[k+1] - zc[k]
 the distance between centres k and k+1 (k = 0..nz).
 """
@@ -39,6 +45,9 @@ class Grid:
         self.dx = case.lx / nx
         self.dy = case.ly / ny
         self.periodic_z = case.zperiodic
+        self.ywalls = case.ywalls
+        self.nys = ny + 2 if self.ywalls else ny
+        self.yc = np.array([(j + 0.5) * self.dy for j in range(ny)])
         if case.beta > 0.0 and not case.zperiodic:
             zf = tanh_faces(nz, case.lz, case.beta)
         else:

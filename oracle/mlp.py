@@ -143,7 +143,7 @@ def raw_features(case, g, u, v, w, s, utau_walls):
     to the nearer wall, u_tau that wall's friction velocity; 0 with periodic z) and
     Delta/delta with delta = 1.  s: centre strain (S11, S22, S33, S12, S13, S23) with the
     SGS-strain ghosts; the rotation uses the same ghosts."""
-    us, vs = bc.strain_ghosts(case, g, u, v)
+    us, vs, _ = bc.strain_ghosts(case, g, u, v, w)
     o12, o13, o23 = rotation_centre(g, us, vs, w)
     s11, s22, s33, s12, s13, s23 = s
     S = np.stack([np.stack([s11, s12, s13], -1), np.stack([s12, s22, s23], -1),

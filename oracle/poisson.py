@@ -7,12 +7,28 @@ and gradient of ops.py with G.n = 0 on walls (Neumann) or periodic z.  The discr
 eigenvalues of the periodic second difference are
     lambda_x(l) = -(4/dx^2) sin^2(pi l / nx),  lambda_y(m) likewise.
 Normalisation (R20): forward transform unscaled, inverse scaled by 1/N (numpy.fft).
+
+With walls in y (square duct, Sec. 4.4) y is a Neumann direction like wall-bounded z: the
+eigenvectors of its second difference with zero flux through both walls are the cosines
+cos(pi m (j + 1/2) / ny), m = 0..ny-1, with eigenvalues -(4/dy^2) sin^2(pi m / (2 ny)); the
+expansion is written out with that matrix (R37).
 """
 import numpy as np
 
 
 def eigenvalues(n, h):
     return np.array([-(4.0 / h ** 2) * np.sin(np.pi * l / n) ** 2 for l in range(n)])
+
+
+def neumann_eigenvalues(n, h):
+    """Eigenvalues of the cell-centred second difference with zero flux at both ends."""
+    return np.array([-(4.0 / h ** 2) * np.sin(np.pi * m / (2.0 * n)) ** 2 for m in range(n)])
+
+
+def cosine_basis(n):
+    """C[m, j] = cos(pi m (j + 1/2) / n): the eigenvectors of the Neumann second difference
+    (orthogonal; squared norms n for m = 0 and n / 2 otherwise)."""
+    return np.array([[np.cos(np.pi * m * (j + 0.5) / n) for j in range(n)] for m in range(n)])
 
 
 def z_coefficients(g):
@@ -84,6 +100,8 @@ def solve(g, f):
     sum_k f_hat dzf_k = 0), and the dzf-weighted mean of phi is then removed.
     Periodic z: 3-D FFT and division by lambda_x + lambda_y + lambda_z, with the
     (0, 0, 0) mode set to zero."""
+    if getattr(g, "ywalls", False):
+        return _solve_duct(g, f)
     nz, ny, nx = f.shape
     lx = eigenvalues(nx, g.dx)
     ly = eigenvalues(ny, g.dy)
@@ -106,3 +124,29 @@ def solve(g, f):
     dzf = g.dzf[1:nz + 1]
     mean = np.sum(phi * dzf[:, None, None]) / (np.sum(dzf) * nx * ny)
     return phi - mean
+
+
+def _solve_duct(g, f):
+    """Walls in y and z (R37): FFT in x, cosine expansion in y, then for every pair (l, m)
+    the z system (A_z + lambda_x(l) + lambda_y(m)) phi_hat = f_hat by Thomas, the singular
+    (0, 0) system pinned as in solve(), the dzf-weighted mean removed.  f has the stored
+    rows (nz, ny + 2, nx); only rows 0..ny-1 are read, and the result's ghost rows are 0."""
+    nz, nx, ny = g.nz, g.nx, g.ny
+    fi = f[:, :ny, :]
+    C = cosine_basis(ny)
+    norm = np.array([1.0 / ny] + [2.0 / ny] * (ny - 1))       # inverse of the squared norms
+    fx = np.fft.fft(fi, axis=2)
+    fh = np.einsum("mj,kjl->kml", C, fx)
+    lam = neumann_eigenvalues(ny, g.dy)[:, None] + eigenvalues(nx, g.dx)[None, :]
+    a, b, c = z_coefficients(g)
+    ph = thomas_columns(a, b, c, lam, fh)
+    x = np.zeros(nz, dtype=np.complex128)
+    x[:nz - 1] = thomas(a[:nz - 1], b[:nz - 1], c[:nz - 1], fh[:nz - 1, 0, 0])
+    ph[:, 0, 0] = x
+    py = np.einsum("mj,kml->kjl", C * norm[:, None], ph)
+    phi_i = np.real(np.fft.ifft(py, axis=2))
+    dzf = g.dzf[1:nz + 1]
+    mean = np.sum(phi_i * dzf[:, None, None]) / (np.sum(dzf) * nx * ny)
+    out = np.zeros((nz, g.nys, nx))
+    out[:, :ny] = phi_i - mean
+    return out

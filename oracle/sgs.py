@@ -15,8 +15,8 @@ from .ops import centre_strain, strain_magnitude, xm, xp, ym, yp
 def model_strain(case, g, u, v, w):
     """S_ij at cell centres with the SGS-strain ghosts (one-sided wall-normal derivative
     in the first layer when the wall model is on, Sec. 2.2)."""
-    us, vs = bc.strain_ghosts(case, g, u, v)
-    return centre_strain(g, us, vs, w)
+    us, vs, ws = bc.strain_ghosts(case, g, u, v, w)
+    return centre_strain(g, us, vs, ws)
 
 
 def smagorinsky(case, g, u, v, w, utau_walls=None):
@@ -28,13 +28,49 @@ def smagorinsky(case, g, u, v, w, utau_walls=None):
     smag = strain_magnitude(s)
     delta = g.delta()[:, None, None]
     damp = np.ones((g.nz, 1, 1))
-    if case.sgs == SGS_SMAG_VD and case.zbc != ZBC_PERIODIC:
+    if case.sgs == SGS_SMAG_VD and g.ywalls:
+        damp = duct_damping(case, g, utau_walls)[:, :, None]
+    elif case.sgs == SGS_SMAG_VD and case.zbc != ZBC_PERIODIC:
         zc = g.zc[1:g.nz + 1]
         lower = zc <= 0.5 * g.lz
         dist = np.where(lower, zc, g.lz - zc)
         ut = np.where(lower, utau_walls[0], utau_walls[1])
         damp = (1.0 - np.exp(-dist * ut / case.nu / 25.0))[:, None, None]
     return (case.cs * delta * damp) ** 2 * smag
+
+
+def duct_damping(case, g, utau_walls):
+    """R36: van Driest factor with four walls, per (k, j) (nz, nys): y* is the smallest of
+    d_w u_tau,w / nu over the four walls w (d_w the distance to wall w): the nearest wall in
+    its own wall units, a rule that needs no tie-break where two walls are equally far.
+    utau_walls = (z bottom, z top, y = 0, y = ly).  Ghost rows get 1 (their values are
+    replaced by the ghost rule)."""
+    n, ny = g.nz, g.ny
+    out = np.ones((n, g.nys))
+    for k in range(1, n + 1):
+        zc = g.zc[k]
+        for j in range(ny):
+            yc = g.yc[j]
+            ys = min(zc * utau_walls[0], (g.lz - zc) * utau_walls[1], yc * utau_walls[2],
+                     (g.ly - yc) * utau_walls[3]) / case.nu
+            out[k - 1, j] = 1.0 - np.exp(-ys / 25.0)
+    return out
+
+
+def duct_friction_velocity(g, tau, tauy):
+    """R36: per-wall friction velocity sqrt(|(<tau_1>, <tau_2>)|) for the four duct walls,
+    each component averaged over its own points on that wall that are not wall faces: z
+    walls over rows j < ny (the v stress over j < ny - 1), y walls over planes 1..nz (the w
+    stress over faces 1..nz - 1).  Returns (z bottom, z top, y = 0, y = ly)."""
+    ny, n = g.ny, g.nz
+    txb, tyb, txt, tyt = tau
+    txl, tzl, txh, tzh = tauy
+    m = lambda a, sl: float(np.mean(a[sl]))
+    zb = np.sqrt(np.hypot(m(txb, slice(0, ny)), m(tyb, slice(0, ny - 1))))
+    zt = np.sqrt(np.hypot(m(txt, slice(0, ny)), m(tyt, slice(0, ny - 1))))
+    yl = np.sqrt(np.hypot(m(txl, slice(1, n + 1)), m(tzl, slice(1, n))))
+    yh = np.sqrt(np.hypot(m(txh, slice(1, n + 1)), m(tzh, slice(1, n))))
+    return zb, zt, yl, yh
 
 
 def friction_velocity(tau):
@@ -201,15 +237,23 @@ def dynamic_smagorinsky(case, g, u, v, w):
     return cs[:, None, None] * (g.delta() ** 2)[:, None, None] * smag, cs
 
 
-def eddy_viscosity(case, g, u, v, w, tau=None):
-    """nu_t on the interior planes for the configured model (SGS_NONE gives zeros)."""
+def eddy_viscosity(case, g, u, v, w, tau=None, tauy=None):
+    """nu_t on the interior planes for the configured model (SGS_NONE gives zeros).
+    With y walls (square duct) only SGS_NONE, SGS_SMAG and SGS_SMAG_VD are defined here."""
+    if g.ywalls and case.sgs not in (SGS_SMAG, SGS_SMAG_VD) and case.sgs != 0:
+        raise NotImplementedError("duct: only the static models")
     if case.sgs in (SGS_SMAG, SGS_SMAG_VD):
         ut = None
         if case.sgs == SGS_SMAG_VD and case.zbc != ZBC_PERIODIC:
             if tau is None:
                 tau = bc.noslip_wall_stress(case, g, u, v)
-            ut = friction_velocity(tau)
+            if g.ywalls:
+                if tauy is None:
+                    tauy = bc.noslip_wall_stress_y(case, g, u, w)
+                ut = duct_friction_velocity(g, tau, tauy)
+            else:
+                ut = friction_velocity(tau)
         return smagorinsky(case, g, u, v, w, ut), None
     if case.sgs == SGS_DSM:
         return dynamic_smagorinsky(case, g, u, v, w)
-    return np.zeros((g.nz, g.ny, g.nx)), None
+    return np.zeros((g.nz, g.nys, g.nx)), None

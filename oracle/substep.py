@@ -8,6 +8,9 @@ State at a substep boundary (all float64, ghost planes valid, Alg. 2):
                     previous substep (unused when beta_k = 0, i.e. on the first substep)
   utau            : dict of per-face friction velocities (wall model's Newton guess)
   tau             : wall stresses (tx_bot, ty_bot, tx_top, ty_top) (wall model)
+  tauy            : y-wall stresses (tx_lo, tz_lo, tx_hi, tz_hi) (wall model with y walls)
+With walls in y (square duct, Sec. 4.4) the arrays carry the ghost rows of grid.py,
+(nz + 2, ny + 2, nx); v on the wall face row ny - 1 stays zero.
   cs              : dynamic coefficient per plane (dynamic model), else None
 """
 import numpy as np
@@ -22,11 +25,12 @@ GAMMA = tuple(a + b for a, b in zip(ALPHA, BETA))
 
 
 class State:
-    def __init__(self, u, v, w, p, nut=None, rprev=None, utau=None, tau=None, cs=None):
+    def __init__(self, u, v, w, p, nut=None, rprev=None, utau=None, tau=None, cs=None, tauy=None):
         self.u, self.v, self.w, self.p = u, v, w, p
         self.nut = np.zeros_like(p) if nut is None else nut
         self.rprev = rprev
         self.utau, self.tau, self.cs = utau, tau, cs
+        self.tauy = tauy
 
     def copy(self):
         cp = lambda x: None if x is None else x.copy()
@@ -35,7 +39,8 @@ class State:
                      None if self.rprev is None else tuple(r.copy() for r in self.rprev),
                      None if self.utau is None else {k: x.copy() for k, x in self.utau.items()},
                      None if self.tau is None else tuple(t.copy() for t in self.tau),
-                     cp(self.cs))
+                     cp(self.cs),
+                     None if self.tauy is None else tuple(t.copy() for t in self.tauy))
 
 
 # ---------------------------------------------------------------- boundary sequence
@@ -43,13 +48,20 @@ def apply_bc_and_model(case, g, st):
     """Alg. 2 followed by the eddy viscosity (Alg. 1, first and last substep lines):
     periodic/no-slip ghosts, then the wall stress, then the wall-model ghosts, then nu_t
     with its ghost planes.  Modifies st in place."""
-    bc.fill_velocity(case, g, st.u, st.v, st.w, tau=_zero_tau(g) if case.zbc == ZBC_WALLMODEL else None)
+    wm = case.zbc == ZBC_WALLMODEL
+    bc.fill_velocity(case, g, st.u, st.v, st.w, tau=_zero_tau(g) if wm else None,
+                     tauy=_zero_tauy(g) if wm and g.ywalls else None)
     bc.fill_scalar(case, g, st.p)
-    if case.zbc == ZBC_WALLMODEL:
-        st.tau, st.utau, _ = bc.wall_stress(case, g, st.u, st.v, st.utau)
-        bc.fill_velocity(case, g, st.u, st.v, st.w, tau=st.tau)
-    nut, cs = sgs.eddy_viscosity(case, g, st.u, st.v, st.w,
-                                 tau=st.tau if case.zbc == ZBC_WALLMODEL else None)
+    if wm:
+        # both wall models read interior values and wall faces only (R35)
+        st.tau, utz, _ = bc.wall_stress(case, g, st.u, st.v, st.utau)
+        if g.ywalls:
+            st.tauy, uty, _ = bc.wall_stress_y(case, g, st.u, st.w, st.utau)
+            utz = {**utz, **uty}
+        st.utau = utz
+        bc.fill_velocity(case, g, st.u, st.v, st.w, tau=st.tau, tauy=st.tauy)
+    nut, cs = sgs.eddy_viscosity(case, g, st.u, st.v, st.w, tau=st.tau if wm else None,
+                                 tauy=st.tauy if wm else None)
     st.nut = np.zeros_like(st.p)
     st.nut[1:g.nz + 1] = nut
     bc.fill_nut(case, g, st.nut)
@@ -57,7 +69,12 @@ def apply_bc_and_model(case, g, st):
 
 
 def _zero_tau(g):
-    z = np.zeros((g.ny, g.nx))
+    z = np.zeros((g.nys, g.nx))
+    return (z, z, z, z)
+
+
+def _zero_tauy(g):
+    z = np.zeros((g.nz + 2, g.nx))
     return (z, z, z, z)
 
 
@@ -109,6 +126,8 @@ def predictor(case, g, st, k, dt):
         elif case.implicit_3d:
             incr = incr + c * case.nu * laplacian(g, vel, comp)
         out.append(vel[I] + dt * incr)
+    if g.ywalls:
+        out[1][:, g.ny - 1] = 0.0       # v on the wall face y = ly is not advanced
     return tuple(out), r
 
 
@@ -263,6 +282,8 @@ def project(case, g, st, ustar, k, dt):
         bc.fill_velocity(case, g, us, vs, ws)
     else:
         ws[0] = ws[n] = ws[n + 1] = 0.0
+    if g.ywalls:
+        vs[:, g.ny - 1:] = 0.0          # wall faces (rows ny - 1 and ny + 1) and row ny
     f = ops.divergence(g, us, vs, ws) / (gk * dt)
     phi = np.zeros_like(st.p)
     phi[I] = poisson.solve(g, f)
@@ -274,6 +295,8 @@ def project(case, g, st, ustar, k, dt):
     w[I] = ws[I] - gk * dt * gz
     if case.zbc != ZBC_PERIODIC:
         w[n] = 0.0
+    if g.ywalls:
+        v[:, g.ny - 1] = 0.0
     p = st.p.copy()
     p[I] = st.p[I] + phi[I]
     if case.implicit_z:
@@ -288,7 +311,7 @@ def bulk_velocity(g, u):
     """Volume mean of u, sum(u dzf) / (nx ny lz)."""
     n = g.nz
     dzf = g.dzf[1:n + 1]
-    return np.sum(u[1:n + 1] * dzf[:, None, None]) / (g.nx * g.ny * np.sum(dzf))
+    return np.sum(u[1:n + 1, :g.ny] * dzf[:, None, None]) / (g.nx * g.ny * np.sum(dzf))
 
 
 def bulk_profile(case, g, k, dt):
@@ -336,7 +359,7 @@ def substep(case, g, st, k, dt):
         ustar = helmholtz_3d(case, g, st, ustar, k, dt)
     u, v, w, p, _ = project(case, g, st, ustar, k, dt)
     force_bulk(case, g, u, k, dt)
-    new = State(u, v, w, p, rprev=r, utau=st.utau, tau=st.tau)
+    new = State(u, v, w, p, rprev=r, utau=st.utau, tau=st.tau, tauy=st.tauy)
     apply_bc_and_model(case, g, new)
     return new
 
@@ -359,9 +382,10 @@ def time_step(case, g, st, cfl=0.5, visc_safety=0.95):
     Returns min of the two."""
     n = g.nz
     I = slice(1, n + 1)
+    J = slice(0, g.ny)
     dzf = g.dzf[I][:, None, None]
-    conv = np.max(np.abs(st.u[I]) / g.dx + np.abs(st.v[I]) / g.dy + np.abs(st.w[I]) / dzf)
-    numax = (0.0 if case.implicit_3d else case.nu) + max(0.0, float(np.max(st.nut[I])))
+    conv = np.max(np.abs(st.u[I, J]) / g.dx + np.abs(st.v[I, J]) / g.dy + np.abs(st.w[I, J]) / dzf)
+    numax = (0.0 if case.implicit_3d else case.nu) + max(0.0, float(np.max(st.nut[I, J])))
     s = 1.0 / g.dx ** 2 + 1.0 / g.dy ** 2
     if not case.implicit_z:
         s += 1.0 / np.min(g.dzf[I]) ** 2

@@ -79,6 +79,25 @@ def channel_field(nx, ny, nz, zc, seed, ubulk=1.0, noise=0.1, half_height=1.0):
     return u, v, w
 
 
+def duct_field(nx, ny, nz, zc, ly, lz, seed, ubulk=1.0, noise=0.1):
+    """Square-duct start: u = 2.25 U_b (1 - (2y/ly - 1)^2)(1 - (2z/lz - 1)^2) plus seeded
+    uniform noise, v = w = noise, on the duct layout with two ghost rows in y (rows ny, ny+1,
+    left zero); v on the wall face row ny - 1 and w on the wall face plane nz are zero.
+    zc holds the cell-centre heights of planes 0..nz+1."""
+    rng = _rng(seed)
+    shape = (nz + 2, ny + 2, nx)
+    u, v, w = np.zeros(shape), np.zeros(shape), np.zeros(shape)
+    y = (np.arange(ny) + 0.5) * (ly / ny)
+    z = np.asarray(zc, dtype=np.float64)[1:nz + 1]
+    prof = 2.25 * ubulk * (1.0 - (2.0 * z / lz - 1.0) ** 2)[:, None] * (1.0 - (2.0 * y / ly - 1.0) ** 2)[None, :]
+    u[1:nz + 1, :ny] = prof[:, :, None] + noise * ubulk * (2.0 * rng.random((nz, ny, nx)) - 1.0)
+    v[1:nz + 1, :ny] = noise * ubulk * (2.0 * rng.random((nz, ny, nx)) - 1.0)
+    w[1:nz + 1, :ny] = noise * ubulk * (2.0 * rng.random((nz, ny, nx)) - 1.0)
+    v[:, ny - 1] = 0.0
+    w[nz] = 0.0
+    return u, v, w
+
+
 def uniform_shear_field(nx, ny, nz, zc, shear, z0=0.0):
     """u = shear (z - z0) at the u positions, v = w = 0."""
     u, v, w = _empty(nx, ny, nz), _empty(nx, ny, nz), _empty(nx, ny, nz)
