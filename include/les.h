@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LES_ABI_VERSION 1
+#define LES_ABI_VERSION 2
 
 typedef enum {
   LES_OK = 0,
@@ -60,6 +60,9 @@ typedef enum {
 } les_status;
 
 enum { LES_ZBC_PERIODIC = 0, LES_ZBC_NOSLIP = 1, LES_ZBC_WALLMODEL = 2 };
+/* y boundaries (les_config.ybc): periodic, or walls at y = 0 and y = ly with the z walls'
+   treatment (no-slip or the wall model): the square duct of Sec. 4.4. */
+enum { LES_YBC_PERIODIC = 0, LES_YBC_WALL = 1 };
 enum { LES_SGS_NONE = 0, LES_SGS_SMAG = 1, LES_SGS_SMAG_VD = 2, LES_SGS_DSM = 3, LES_SGS_MLP = 4 };
 enum { LES_FP64 = 0, LES_MIXED = 1 };
 /* Viscous-term treatment (les_config.implicit_z). */
@@ -70,7 +73,7 @@ typedef struct les_ctx les_ctx;   /* opaque, owned by the library */
 /* Problem description.  Plain data, copied by les_init. */
 typedef struct {
   int32_t abi_version;  /* must be LES_ABI_VERSION                                        */
-  int32_t nx, ny, nz;   /* cells; nx, ny even, of the form 2^a or 3 * 2^a, 8..1024;
+  int32_t nx, ny, nz;   /* cells; nx, ny even, of the form 2^a, 3 * 2^a, 5 * 2^a or 15 * 2^a, 8..1024;
                            4 <= nz <= 512 (wall-bounded) or, when z is periodic, of that form   */
   double lx, ly, lz;    /* box lengths (> 0)                                             */
   int32_t zbc;          /* LES_ZBC_*                                                     */
@@ -88,6 +91,13 @@ typedef struct {
   double ubulk;         /* > 0: constant flow rate (bulk velocity) in x; 0: off          */
   double h_wm;          /* wall-model height; 0 = first off-wall cell centre            */
   double kappa, bconst; /* log-law constants (Eq. wm); 0 selects 0.41 and 5.2            */
+  int32_t ybc;          /* LES_YBC_*.  LES_YBC_WALL (square duct, Sec. 4.4) needs wall-bounded
+                           z, explicit viscous terms or CN in z, and LES_SGS_NONE, _SMAG or
+                           _SMAG_VD; fields then carry two ghost rows in y, stored after the
+                           interior rows: dims [nz+2][ny+2][nx], row ny above y = ly, row ny+1
+                           below y = 0 (where the periodic index j - 1 of row 0 lands).  v on
+                           row ny - 1 is the wall face y = ly and stays zero.  Statistics,
+                           the learned closure and batches are not available for ducts. */
 } les_config;
 
 /* Bindable and readable buffers. */
@@ -96,14 +106,18 @@ enum {
   LES_FIELD_WORKSPACE = 4,  /* scratch + internal state (RK history, |S|, spectra, ...) */
   LES_FIELD_NUT = 5,        /* readable only: eddy viscosity at cell centres, field layout */
   LES_FIELD_CS = 6,         /* readable only: per-plane model coefficient, double[nz]      */
-  LES_FIELD_TAUW = 7,       /* readable only: wall stress, double[4][ny][nx]:
-                               tau_x bottom, tau_y bottom, tau_x top, tau_y top            */
-  LES_FIELD_ZGRID = 8       /* readable only, host memory: double zf[nz+1], zc[nz+2]       */
+  LES_FIELD_TAUW = 7,       /* readable only: wall stress, double[4][ny'][nx] (ny' = the stored
+                               rows): tau_x bottom, tau_y bottom, tau_x top, tau_y top     */
+  LES_FIELD_ZGRID = 8,      /* readable only, host memory: double zf[nz+1], zc[nz+2]       */
+  LES_FIELD_TAUWY = 9       /* readable only, ducts with the wall model: y-wall stress,
+                               double[4][nz+2][nx]: tau_x at y = 0, tau_z at y = 0, tau_x at
+                               y = ly, tau_z at y = ly (zero on the ghost planes and, for
+                               tau_z, on the wall face k = nz)                              */
 };
 
 typedef struct {
   int64_t nx, ny, nz;        /* interior cells                                     */
-  int64_t dims[3];           /* [nz+2, ny, nx] for fields                          */
+  int64_t dims[3];           /* [nz+2, ny, nx] for fields ([nz+2, ny+2, nx] for ducts) */
   int64_t elem_bytes;        /* 8 (double) or 4 (float) for fields                 */
   int64_t bytes;             /* total bytes required for the requested buffer      */
 } les_layout_t;

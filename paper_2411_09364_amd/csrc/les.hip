@@ -20,6 +20,7 @@ const double kPi = 3.14159265358979323846;
 bool fft_size_ok(int n) {
   if (n < 4 || n > 1024) return false;
   int m = n;
+  if (m % 5 == 0) m /= 5;
   if (m % 3 == 0) m /= 3;
   while (m % 2 == 0) m /= 2;
   return m == 1;
@@ -112,10 +113,19 @@ void build_grid(Ctx& c) {
   c.lamx.resize(f.nx / 2 + 1);
   for (int l = 0; l <= f.nx / 2; ++l) c.lamx[l] = eig(f.nx, dx, l);
   c.lamy.resize(f.ny);
-  // y modes m and ny - m share their eigenvalue exactly (mirrored), so their z systems and
-  // factors coincide
-  for (int m = 0; m <= f.ny / 2; ++m) c.lamy[m] = eig(f.ny, dy, m);
-  for (int m = f.ny / 2 + 1; m < f.ny; ++m) c.lamy[m] = c.lamy[f.ny - m];
+  if (f.ybc == LES_YBC_WALL) {
+    // walls in y: the cosine modes of the zero-flux second difference,
+    // -(4/dy^2) sin^2(pi m / (2 ny)), m = 0..ny-1
+    for (int m = 0; m < f.ny; ++m) {
+      const double s = std::sin(kPi * m / (2.0 * f.ny));
+      c.lamy[m] = -(4.0 / (dy * dy)) * s * s;
+    }
+  } else {
+    // y modes m and ny - m share their eigenvalue exactly (mirrored), so their z systems and
+    // factors coincide
+    for (int m = 0; m <= f.ny / 2; ++m) c.lamy[m] = eig(f.ny, dy, m);
+    for (int m = f.ny / 2 + 1; m < f.ny; ++m) c.lamy[m] = c.lamy[f.ny - m];
+  }
   c.lamz.assign(n, 0.0);
   if (f.zbc == LES_ZBC_PERIODIC)
     for (int q = 0; q < n; ++q) c.lamz[q] = eig(n, f.lz / n, q);
@@ -129,6 +139,12 @@ void build_grid(Ctx& c) {
   tw(f.nx, c.twx);
   tw(f.ny, c.twy);
   tw(n, c.twz);
+  // cosine transform (ducts): cos, sin of pi m / (2 ny)
+  c.twc.resize(2 * f.ny);
+  for (int m = 0; m < f.ny; ++m) {
+    c.twc[2 * m] = std::cos(kPi * m / (2.0 * f.ny));
+    c.twc[2 * m + 1] = std::sin(kPi * m / (2.0 * f.ny));
+  }
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -138,7 +154,7 @@ size_t carve(Ctx& c, char* base) {
   const les_config& f = c.cfg;
   const int n = f.nz;
   const size_t F = c.field_elems, E = c.elem;
-  const int64_t sxy = (int64_t)f.nx * f.ny;
+  const int64_t sxy = c.g.sxy;   // stored rows (ghost rows of ducts included)
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -173,6 +189,12 @@ size_t carve(Ctx& c, char* base) {
   t.bulk = (double*)take((size_t)std::max<int64_t>(npairs, 1) * 8);
   t.tau = (double*)take(4 * sxy * 8);
   t.utau = (double*)take(4 * sxy * 8);
+  const bool duct = f.ybc == LES_YBC_WALL;
+  t.tauy = (double*)take(duct ? 4 * (size_t)(n + 2) * f.nx * 8 : 0);
+  t.utauy = (double*)take(duct ? 4 * (size_t)(n + 2) * f.nx * 8 : 0);
+  t.vd4 = (double*)take(4 * 8);
+  t.twc = (double*)take(2 * f.ny * 8);
+  t.twc_f = (float*)take(2 * f.ny * 4);
   // plane partial sums (LM, MM): one per wave of each x-y tile of the fused dynamic-model
   // kernel (32 x 8 cells, 4 waves)
   t.nblk_xy = ((f.nx + 31) / 32) * ((f.ny + 7) / 8);
@@ -200,8 +222,8 @@ size_t carve(Ctx& c, char* base) {
   const size_t nxp = ((size_t)(f.nx / 2 + 1) + rq - 1) / rq * rq;
   // one spectrum buffer; three with CN in all directions (the components are solved together)
   c.spec = take(nxp * f.ny * n * 2 * E * (f.implicit_z == LES_VISC_CN_3D ? 3 : 1));
-  // factor pairs of the z systems of every (l, m <= ny/2) column (walls only)
-  t.pfac = (double*)take(f.zbc == LES_ZBC_PERIODIC ? 0 : nxp * (f.ny / 2 + 1) * n * 2 * 8);
+  // factor pairs of the z systems of every (l, m) column with its own factors (walls only)
+  t.pfac = (double*)take(f.zbc == LES_ZBC_PERIODIC ? 0 : nxp * factor_modes(c.g) * n * 2 * 8);
   // long-run statistics: running sums and series, per-sample partials
   t.stats = (double*)take(8 * stats_words(n));
   t.stats_part = (double*)take(8 * stats_part_words(n, (int64_t)f.nx * f.ny));
@@ -209,6 +231,21 @@ size_t carve(Ctx& c, char* base) {
   t.hfac3 = (double2*)take(f.zbc != LES_ZBC_PERIODIC && f.implicit_z == LES_VISC_CN_3D
                                ? 2 * nxp * (f.ny / 2 + 1) * n * 16 : 0);
   return off;
+}
+
+// After an update of u, v, w, p (Alg. 2, then Alg. 1's last line): the wall stresses from the
+// interior values, the wall-model ghosts, the y ghost rows of ducts, and the eddy viscosity
+// with its ghosts.  Both wall models read interior values and wall faces only, so the stale
+// y ghost rows they see do not matter.
+template <typename T>
+void boundary_and_model(Ctx& c) {
+  if (c.cfg.zbc == LES_ZBC_WALLMODEL) {
+    launch_wallmodel<T>(c);
+    if (c.g.ywall) launch_wallmodel_y<T>(c);
+  }
+  if (c.g.ywall) launch_bc_fill_y<T>(c, (T*)c.u, (T*)c.v, (T*)c.w, (T*)c.p);
+  launch_eddy_viscosity<T>(c);
+  if (c.g.ywall) launch_fill_y_scalar<T>(c, (T*)c.nut, -1.0);
 }
 
 template <typename T>
@@ -221,8 +258,7 @@ les_status substep_body(Ctx& c, int stage) {
   launch_poisson_solve_spectral<T>(c);
   launch_poisson_inverse<T>(c, (T*)c.phi);
   launch_correct<T>(c, stage);
-  if (c.cfg.zbc == LES_ZBC_WALLMODEL) launch_wallmodel<T>(c);
-  launch_eddy_viscosity<T>(c);
+  boundary_and_model<T>(c);
   return check_launch(c, "les_substep");
 }
 
@@ -279,6 +315,16 @@ les_status les_init(const les_config* cfg, void* hip_stream, les_ctx** out) {
   if (!(std::isfinite(f.ubulk) && f.ubulk >= 0.0)) return LES_EINVAL;
   if (!(std::isfinite(f.h_wm) && f.h_wm >= 0.0)) return LES_EINVAL;
   if (!(std::isfinite(f.kappa) && f.kappa >= 0.0) || !std::isfinite(f.bconst)) return LES_EINVAL;
+  if (f.ybc != LES_YBC_PERIODIC && f.ybc != LES_YBC_WALL) return LES_EINVAL;
+  if (f.ybc == LES_YBC_WALL) {
+    // square duct: walls in z as well, no implicit y solve, the static models
+    if (f.zbc == LES_ZBC_PERIODIC || f.implicit_z == LES_VISC_CN_3D || f.sgs > LES_SGS_SMAG_VD || f.ny < 4)
+      return LES_ENOTSUP;
+    if (f.zbc == LES_ZBC_WALLMODEL && f.h_wm > 0.0) {
+      const double dy = f.ly / f.ny;
+      if (f.h_wm < 0.5 * dy || f.h_wm > (f.ny / 2 - 0.5) * dy) return LES_EINVAL;
+    }
+  }
   les_ctx* h = new (std::nothrow) les_ctx();
   if (!h) return LES_ENOMEM;
   Ctx& c = h->c;
@@ -287,7 +333,8 @@ les_status les_init(const les_config* cfg, void* hip_stream, les_ctx** out) {
   if (c.cfg.bconst == 0.0) c.cfg.bconst = 5.2;
   c.stream = (hipStream_t)hip_stream;
   c.elem = f.precision == LES_MIXED ? 4 : 8;
-  c.field_elems = (size_t)(f.nz + 2) * f.ny * f.nx;
+  const int nys = f.ybc == LES_YBC_WALL ? f.ny + 2 : f.ny;
+  c.field_elems = (size_t)(f.nz + 2) * nys * f.nx;
   build_grid(c);
   if (f.zbc == LES_ZBC_WALLMODEL && f.h_wm > 0.0) {
     if (f.h_wm < c.zc[1] || f.h_wm > c.zc[f.nz / 2]) {
@@ -300,7 +347,9 @@ les_status les_init(const les_config* cfg, void* hip_stream, les_ctx** out) {
   g.ny = f.ny;
   g.nz = f.nz;
   g.zbc = f.zbc;
-  g.sxy = (int64_t)f.nx * f.ny;
+  g.ywall = f.ybc == LES_YBC_WALL ? 1 : 0;
+  g.nys = nys;
+  g.sxy = (int64_t)f.nx * nys;
   // 128-byte spectrum rows: 8 double or 16 float complex values
   const int rq = f.precision == LES_MIXED ? 16 : 8;
   g.nxp = ((f.nx / 2 + 1) + rq - 1) / rq * rq;
@@ -324,7 +373,7 @@ les_status les_layout(const les_ctx* ctx, int field, les_layout_t* out) {
   out->ny = f.ny;
   out->nz = f.nz;
   out->dims[0] = f.nz + 2;
-  out->dims[1] = f.ny;
+  out->dims[1] = c.g.nys;
   out->dims[2] = f.nx;
   out->elem_bytes = (int64_t)c.elem;
   switch (field) {
@@ -340,7 +389,12 @@ les_status les_layout(const les_ctx* ctx, int field, les_layout_t* out) {
       out->elem_bytes = 8;
       return LES_OK;
     case LES_FIELD_TAUW:
-      out->bytes = 8LL * 4 * f.nx * f.ny;
+      out->bytes = 8LL * 4 * c.g.sxy;
+      out->elem_bytes = 8;
+      return LES_OK;
+    case LES_FIELD_TAUWY:
+      if (f.ybc != LES_YBC_WALL) return LES_EINVAL;
+      out->bytes = 8LL * 4 * (f.nz + 2) * f.nx;
       out->elem_bytes = 8;
       return LES_OK;
     case LES_FIELD_ZGRID:
@@ -383,6 +437,8 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       for (double x : c.twy) c.twy_f_host.push_back((float)x);
       c.twz_f_host.clear();
       for (double x : c.twz) c.twz_f_host.push_back((float)x);
+      c.twc_f_host.clear();
+      for (double x : c.twc) c.twc_f_host.push_back((float)x);
       c.coef_host.assign(n + 2, 0.0);
       if (f.sgs == LES_SGS_MLP && c.mlp_params != nullptr) c.coef_host = c.delta2;
       if (f.sgs == LES_SGS_SMAG || f.sgs == LES_SGS_SMAG_VD)
@@ -409,6 +465,8 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       if ((s = up(c.t.twx_f, c.twx_f_host.data(), c.twx_f_host.size() * 4)) != LES_OK) return s;
       if ((s = up(c.t.twy_f, c.twy_f_host.data(), c.twy_f_host.size() * 4)) != LES_OK) return s;
       if ((s = up(c.t.twz_f, c.twz_f_host.data(), c.twz_f_host.size() * 4)) != LES_OK) return s;
+      if ((s = up(c.t.twc, c.twc.data(), c.twc.size() * 8)) != LES_OK) return s;
+      if ((s = up(c.t.twc_f, c.twc_f_host.data(), c.twc_f_host.size() * 4)) != LES_OK) return s;
       if ((s = up(c.t.hfac, c.hfac_host.data(), c.hfac_host.size() * 8)) != LES_OK) return s;
       // learned closure: the first evaluation runs the dynamic model (fallback coefficients)
       static const int cnt_init[2] = {0, 1};
@@ -441,12 +499,12 @@ les_status les_nut(les_ctx* ctx) {
   if (s != LES_OK) return s;
   if (c.cfg.precision == LES_MIXED) {
     launch_bc_fill<float>(c, (float*)c.u, (float*)c.v, (float*)c.w, (float*)c.p);
-    if (c.cfg.zbc == LES_ZBC_WALLMODEL) launch_wallmodel<float>(c);
-    launch_eddy_viscosity<float>(c);
+    if (c.g.ywall) launch_bc_fill_y<float>(c, (float*)c.u, (float*)c.v, (float*)c.w, (float*)c.p);
+    boundary_and_model<float>(c);
   } else {
     launch_bc_fill<double>(c, (double*)c.u, (double*)c.v, (double*)c.w, (double*)c.p);
-    if (c.cfg.zbc == LES_ZBC_WALLMODEL) launch_wallmodel<double>(c);
-    launch_eddy_viscosity<double>(c);
+    if (c.g.ywall) launch_bc_fill_y<double>(c, (double*)c.u, (double*)c.v, (double*)c.w, (double*)c.p);
+    boundary_and_model<double>(c);
   }
   s = check_launch(c, "les_nut");
   if (s == LES_OK) c.initialised = true;
@@ -550,6 +608,11 @@ les_status les_read(les_ctx* ctx, int field, void* dst) {
     case LES_FIELD_TAUW:
       return check_hip(c, hipMemcpyAsync(dst, c.t.tau, 8 * 4 * c.g.sxy, hipMemcpyDeviceToDevice, c.stream),
                        "read tau");
+    case LES_FIELD_TAUWY:
+      if (f.ybc != LES_YBC_WALL) return fail(&c, LES_EINVAL, "no y walls");
+      return check_hip(c, hipMemcpyAsync(dst, c.t.tauy, 8 * 4 * (size_t)(f.nz + 2) * f.nx, hipMemcpyDeviceToDevice,
+                                         c.stream),
+                       "read tauy");
   }
   return fail(&c, LES_EINVAL, "field is not readable");
 }
@@ -557,6 +620,7 @@ les_status les_read(les_ctx* ctx, int field, void* dst) {
 les_status les_stats_reset(les_ctx* ctx) {
   if (!ctx) return LES_EINVAL;
   Ctx& c = ctx->c;
+  if (c.g.ywall) return fail(&c, LES_ENOTSUP, "plane statistics are defined for channels only");
   if (!c.ws) return fail(&c, LES_ESTATE, "workspace not bound");
   launch_stats_reset(c);
   return check_launch(c, "les_stats_reset");
@@ -565,6 +629,7 @@ les_status les_stats_reset(les_ctx* ctx) {
 les_status les_stats_sample(les_ctx* ctx) {
   if (!ctx) return LES_EINVAL;
   Ctx& c = ctx->c;
+  if (c.g.ywall) return fail(&c, LES_ENOTSUP, "plane statistics are defined for channels only");
   les_status s = ready(c, false);
   if (s != LES_OK) return s;
   if (c.cfg.precision == LES_MIXED) launch_stats_sample<float>(c);
@@ -575,6 +640,7 @@ les_status les_stats_sample(les_ctx* ctx) {
 les_status les_stats_read(les_ctx* ctx, int32_t nbatch, les_stats_t* out, double* profiles) {
   if (!ctx || !out) return LES_EINVAL;
   Ctx& c = ctx->c;
+  if (c.g.ywall) return fail(&c, LES_ENOTSUP, "plane statistics are defined for channels only");
   if (!c.ws) return fail(&c, LES_ESTATE, "workspace not bound");
   std::vector<double> host((size_t)stats_words(c.cfg.nz));
   les_status s = check_hip(c, hipMemcpyAsync(host.data(), c.t.stats, host.size() * 8, hipMemcpyDeviceToHost, c.stream),
@@ -608,11 +674,12 @@ les_status les_diag(les_ctx* ctx, les_diag_t* out) {
   if ((s = check_hip(c, hipStreamSynchronize(c.stream), "diag sync")) != LES_OK) return s;
   std::memset(out, 0, sizeof(*out));
   out->max_div = h[0];
-  out->ubulk = h[1] / ((double)c.g.sxy * c.cfg.lz);
+  const double cells_xy = (double)c.g.nx * c.g.ny;   // interior cells per plane
+  out->ubulk = h[1] / (cells_xy * c.cfg.lz);
   out->max_vel = h[2];
   out->nonfinite = (int64_t)h[3];
-  out->tauw_mean[0] = h[4] / (double)c.g.sxy;
-  out->tauw_mean[1] = h[5] / (double)c.g.sxy;
+  out->tauw_mean[0] = h[4] / cells_xy;
+  out->tauw_mean[1] = h[5] / cells_xy;
   out->dt = dt;
   out->mlp_flagged = cnt[1];
   return out->nonfinite ? LES_ENONFINITE : LES_OK;

@@ -17,7 +17,9 @@ namespace les {
 struct GridP {
   int nx, ny, nz;
   int zbc;            // LES_ZBC_*
-  int64_t sxy;        // nx * ny
+  int ywall;          // walls in y as well (square duct): two ghost rows after the interior
+  int nys;            // stored rows per plane: ny, or ny + 2 with y walls
+  int64_t sxy;        // plane stride nx * nys; the interior cells of a plane are its first nx * ny
   int nxp;            // row stride of the spectrum (complex values): nx/2+1 rounded up to 128 bytes
   double dx, dy, rdx, rdy;
   double lz, nu;
@@ -28,7 +30,7 @@ struct GridP {
 };
 
 __host__ __device__ inline int64_t idx3(const GridP& g, int k, int j, int i) {
-  return ((int64_t)k * g.ny + j) * g.nx + i;
+  return ((int64_t)k * g.nys + j) * g.nx + i;
 }
 // XCD-aware tile order.  Workgroups are dispatched to the 8 XCDs in turn by linear index;
 // when a plane holds a multiple of 8 tiles, XCD x gets the contiguous band of tiles
@@ -103,6 +105,8 @@ __device__ __forceinline__ void seg_scan_solve(double (&v)[S], int k0, int n, in
 }
 
 __device__ inline int wrap_p(int i, int n) { return i + 1 == n ? 0 : i + 1; }
+// y modes with their own z factors: m <= ny/2 (periodic y), every m (ducts)
+__host__ __device__ inline int factor_modes(const GridP& g) { return g.ywall ? g.ny : g.ny / 2 + 1; }
 __device__ inline int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 
 // Radix plan of an LDS Stockham FFT (radix 3 first, then 4s, then a 2).
@@ -141,10 +145,16 @@ struct Tables {
   double* dt;       // [0] time step; [1] bulk shift s; [2..] scratch scalars
   double* red;      // reduction partials (size red_n)
   double* bulk;     // flow-rate partial sums, one per forward-x block
-  double* tau;      // 4*nx*ny wall stresses
-  double* utau;     // 4*nx*ny Newton state
+  double* tau;      // 4*sxy wall stresses of the z walls
+  double* utau;     // 4*sxy Newton state
+  double* tauy;     // ducts: 4*(nz+2)*nx stresses of the y walls (tau_x, tau_z at y = 0, then y = ly)
+  double* utauy;    // ducts: their Newton state
+  double* vd4;      // ducts, van Driest: friction velocity of the z bottom, z top, y = 0, y = ly walls
+  double* twc;      // ducts: 2*ny cos, sin of pi m / (2 ny), the cosine transform's twiddles
+  float* twc_f;
   double* dsm_part; // 2*nz*nblk_xy*4 plane partial sums (LM, MM) per tile and wave
-  double* pfac;     // walls: (c', 1/pivot) of the (l, m <= ny/2) z systems, [nz][ny/2+1][nxp] pairs
+  double* pfac;     // walls: (c', 1/pivot) of the (l, m) z systems, [nz][nm][nxp] pairs with
+                    //   nm = ny/2+1 (periodic y: m and ny - m share them) or ny (ducts)
   double* stats;    // statistics: header[8], sums [11][nz], wall-stress series [cap][2]
   double* stats_part; // per-block plane partials of one sample [nz+1][nblk][11]
   int64_t red_n;
@@ -158,9 +168,9 @@ struct Ctx {
   GridP g;               // device metric pointers filled at workspace bind
   // host copies of the tables
   std::vector<double> zf, zc, dzf, dzc, delta2, pa, pb, pc, lamx, lamy, lamz;
-  std::vector<double> twx, twy, twz;
+  std::vector<double> twx, twy, twz, twc;
   // host staging of uploaded tables (kept alive for the asynchronous copies)
-  std::vector<float> twx_f_host, twy_f_host, twz_f_host;
+  std::vector<float> twx_f_host, twy_f_host, twz_f_host, twc_f_host;
   std::vector<double> coef_host, hfac_host;
   // bound buffers
   void* u = nullptr;
@@ -169,7 +179,7 @@ struct Ctx {
   void* p = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  size_t field_elems = 0;   // (nz+2)*ny*nx
+  size_t field_elems = 0;   // (nz+2)*nys*nx
   size_t elem = 8;          // storage bytes
   // workspace carving (byte offsets into ws)
   Tables t{};
@@ -212,6 +222,10 @@ template <typename T> void launch_poisson_inverse(Ctx& c, T* phi_out);
 template <typename T> void launch_correct(Ctx& c, int stage);
 template <typename T> void launch_bc_fill(Ctx& c, T* u, T* v, T* w, T* p);
 template <typename T> void launch_wallmodel(Ctx& c);
+// ducts: y-wall model, y ghost rows of u, v, w, p (Alg. 2) and of the eddy viscosity
+template <typename T> void launch_wallmodel_y(Ctx& c);
+template <typename T> void launch_bc_fill_y(Ctx& c, T* u, T* v, T* w, T* p);
+template <typename T> void launch_fill_y_scalar(Ctx& c, T* f, double sign);
 template <typename T> void launch_eddy_viscosity(Ctx& c);
 template <typename T> void launch_dt(Ctx& c, double cfl);
 template <typename T> void launch_poisson_field(Ctx& c, T* f);

@@ -30,6 +30,10 @@ FftPlan make_plan(int n) {
   p.n = n;
   int m = n;
   int s = 0;
+  if (m % 5 == 0) {
+    p.rad[s++] = 5;
+    m /= 5;
+  }
   if (m % 3 == 0) {
     p.rad[s++] = 3;
     m /= 3;
@@ -109,6 +113,43 @@ __device__ inline void stage3(const cpx<R>* src, cpx<R>* dst, int N, int Ns, con
   }
 }
 
+// radix 5: with t1 = v1 + v4, t2 = v2 + v3, t3 = v1 - v4, t4 = v2 - v3 (c_q, s_q the cosine
+// and sine of 2 pi q / 5): X1,4 = v0 + c1 t1 + c2 t2 +- DIR i (s1 t3 + s2 t4),
+// X2,3 = v0 + c2 t1 + c1 t2 +- DIR i (s2 t3 - s1 t4), X0 = v0 + t1 + t2
+template <typename R, int DIR>
+__device__ inline void bfly5(const cpx<R> v[5], cpx<R> out[5]) {
+  const R c1 = (R)0.30901699437494742410, c2 = (R)-0.80901699437494742410;
+  const R s1 = (R)0.95105651629515357212, s2 = (R)0.58778525229247312917;
+  const cpx<R> t1 = {v[1].x + v[4].x, v[1].y + v[4].y}, t2 = {v[2].x + v[3].x, v[2].y + v[3].y};
+  const cpx<R> t3 = {v[1].x - v[4].x, v[1].y - v[4].y}, t4 = {v[2].x - v[3].x, v[2].y - v[3].y};
+  const cpx<R> a1 = {v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+  const cpx<R> a2 = {v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+  const cpx<R> b1 = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
+  const cpx<R> b2 = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
+  const cpx<R> j1 = {-(R)DIR * b1.y, (R)DIR * b1.x}, j2 = {-(R)DIR * b2.y, (R)DIR * b2.x};   // DIR i b
+  out[0] = {v[0].x + t1.x + t2.x, v[0].y + t1.y + t2.y};
+  out[1] = {a1.x + j1.x, a1.y + j1.y};
+  out[4] = {a1.x - j1.x, a1.y - j1.y};
+  out[2] = {a2.x + j2.x, a2.y + j2.y};
+  out[3] = {a2.x - j2.x, a2.y - j2.y};
+}
+
+template <typename R, int DIR>
+__device__ inline void stage5(const cpx<R>* src, cpx<R>* dst, int N, int Ns, const R* tw, int lane, int team) {
+  const int nb = N / 5, ts = N / (Ns * 5);
+  for (int b = lane; b < nb; b += team) {
+    const int k = b % Ns;
+    cpx<R> v[5], o5[5];
+    v[0] = src[b];
+#pragma unroll
+    for (int q = 1; q < 5; ++q) v[q] = twiddle<R, DIR>(src[b + q * nb], tw, q * k * ts);
+    bfly5<R, DIR>(v, o5);
+    const int o = (b / Ns) * Ns * 5 + k;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) dst[o + q * Ns] = o5[q];
+  }
+}
+
 template <typename R, int DIR>
 __device__ cpx<R>* stockham(cpx<R>* src, cpx<R>* dst, const FftPlan& P, const R* __restrict__ tw, int lane, int team) {
   const int N = P.n;
@@ -117,7 +158,8 @@ __device__ cpx<R>* stockham(cpx<R>* src, cpx<R>* dst, const FftPlan& P, const R*
     const int r = P.rad[s];
     if (r == 4) stage4<R, DIR>(src, dst, N, Ns, tw, lane, team);
     else if (r == 2) stage2<R, DIR>(src, dst, N, Ns, tw, lane, team);
-    else stage3<R, DIR>(src, dst, N, Ns, tw, lane, team);
+    else if (r == 3) stage3<R, DIR>(src, dst, N, Ns, tw, lane, team);
+    else stage5<R, DIR>(src, dst, N, Ns, tw, lane, team);
     __syncthreads();
     cpx<R>* t = src;
     src = dst;
@@ -166,6 +208,11 @@ __device__ inline void stage_ip(cpx<R>* buf, int N, int Ns, const R* tw, int lan
         buf[o + Ns] = {d02.x + jd.x, d02.y + jd.y};
         buf[o + 2 * Ns] = {s02.x - s13.x, s02.y - s13.y};
         buf[o + 3 * Ns] = {d02.x - jd.x, d02.y - jd.y};
+      } else if (RAD == 5) {
+        cpx<R> o5[5];
+        bfly5<R, DIR>(v[t], o5);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) buf[o + q * Ns] = o5[q];
       } else {
         const R h3 = (R)0.86602540378443864676;
         const cpx<R> v0 = v[t][0], v1 = v[t][1], v2 = v[t][RAD - 1];
@@ -189,7 +236,8 @@ __device__ cpx<R>* stockham_ip(cpx<R>* buf, const FftPlan& P, const R* __restric
     const int r = P.rad[s];
     if (r == 4) stage_ip<R, DIR, 4, (PPT + 3) / 4>(buf, N, Ns, tw, lane, team);
     else if (r == 2) stage_ip<R, DIR, 2, (PPT + 1) / 2>(buf, N, Ns, tw, lane, team);
-    else stage_ip<R, DIR, 3, (PPT + 2) / 3>(buf, N, Ns, tw, lane, team);
+    else if (r == 3) stage_ip<R, DIR, 3, (PPT + 2) / 3>(buf, N, Ns, tw, lane, team);
+    else stage_ip<R, DIR, 5, (PPT + 4) / 5>(buf, N, Ns, tw, lane, team);
     Ns *= r;
   }
   return buf;
@@ -230,7 +278,7 @@ __device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, const FftPlan& P, 
         const int64_t c = idx3(g, k, j, i);
         if (MODE == 0) {
           const T d = (us[c] - us[idx3(g, k, j, wrap_m(i, nx))]) * (T)g.rdx +
-                      (vs[c] - vs[idx3(g, k, wrap_m(j, g.ny), i)]) * (T)g.rdy +
+                      (vs[c] - ((g.ywall && j == 0) ? (T)0 : vs[idx3(g, k, wrap_m(j, g.ny), i)])) * (T)g.rdy +
                       (ws[c] - ((k == 1 && g.zbc == LES_ZBC_PERIODIC) ? ws[idx3(g, g.nz, j, i)] : ws[c - g.sxy])) *
                           (T)(1.0 / g.dzf[k]);
           fv[r] = d * scale;
@@ -372,13 +420,25 @@ __global__ void __launch_bounds__(256) kb_irfftx(BatchMap m) {
 // is the Laplacian when hg = 0 (Poisson; the zero mode is set to 0), else the Helmholtz
 // operator 1 - hg dt lam of Crank-Nicolson in all directions (hg = gamma nu / 2, dt from
 // the device slot).
-template <typename T, int DIR, bool SOLVE, int PPT = 0>
+//
+// DCT = 1 (ducts, walls in y): the lines are transformed by the cosine expansion of the
+// zero-flux second difference instead, X_m = sum_t x_t cos(pi m (t + 1/2) / N) (DIR = -1)
+// and its unnormalised inverse y_t = X_0 + 2 sum_{m >= 1} X_m cos(pi m (t + 1/2) / N) (DIR =
+// +1, so that a forward-inverse pair multiplies by N, like the FFT pair), each through one
+// complex FFT of length N of the same line (the lines are complex, and the transforms are
+// linear, so real and imaginary parts go through together): forward, the line is loaded
+// in the order x_0, x_2, .., x_{N-2}, x_{N-1}, .., x_3, x_1 and X_m = (W_m V_m + conj(W_m)
+// V_{N-m}) / 2 with W_m = exp(-i pi m / (2N)) and V its FFT; inverse, V_m = conj(W_m) (X_m -
+// i X_{N-m}) (X_N = 0) before the inverse FFT, whose output is stored back in the permuted
+// order.  twc holds (cos, sin)(pi m / (2N)).
+template <typename T, int DIR, bool SOLVE, int PPT = 0, int DCT = 0>
 __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T>* __restrict__ data, int nl, int64_t lstride,
                                                    int64_t ostride, int L, const double* __restrict__ twd,
                                                    const float* __restrict__ twf, const double* __restrict__ lamx,
                                                    const double* __restrict__ lamy, const double* __restrict__ lamz,
                                                    double norm, const double* __restrict__ dtp = nullptr,
-                                                   double hg = 0.0) {
+                                                   double hg = 0.0, const double* __restrict__ twcd = nullptr,
+                                                   const float* __restrict__ twcf = nullptr) {
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
   const int N = P.n;
@@ -403,13 +463,38 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
-      if (e < total) A[(e % L) * NP + e / L] = v[b];
+      if (e < total) {
+        const int t = e / L;
+        // forward cosine transform: even points first, then odd points in reverse
+        const int pos = (DCT && DIR < 0) ? ((t & 1) ? N - 1 - (t >> 1) : (t >> 1)) : t;
+        A[(e % L) * NP + pos] = v[b];
+      }
     }
   }
   __syncthreads();
   const int team = blockDim.x / L;
   const int ll = threadIdx.x / team, lane = threadIdx.x % team;
   const T* tw = twsel<T>(twd, twf);
+  const T* twc = DCT ? twsel<T>(twcd, twcf) : nullptr;
+  if (DCT && DIR > 0) {
+    // inverse cosine transform: V_m = conj(W_m) (X_m - i X_{N-m}), pairs (m, N - m) in place
+    cpx<T>* X = A + ll * NP;
+    for (int m = lane; m <= N / 2; m += team) {
+      const cpx<T> a = X[m];
+      const cpx<T> b = m == 0 ? cpx<T>{(T)0, (T)0} : X[N - m];
+      {
+        const T c = twc[2 * m], sn = twc[2 * m + 1];
+        const T zx = a.x + b.y, zy = a.y - b.x;
+        X[m] = {c * zx - sn * zy, sn * zx + c * zy};
+      }
+      if (m > 0 && 2 * m != N) {
+        const T c = twc[2 * (N - m)], sn = twc[2 * (N - m) + 1];
+        const T zx = b.x + a.y, zy = b.y - a.x;
+        X[N - m] = {c * zx - sn * zy, sn * zx + c * zy};
+      }
+    }
+    __syncthreads();
+  }
   cpx<T>* res;
   if constexpr (PPT > 0) res = stockham_ip<T, DIR, PPT>(A + ll * NP, P, tw, lane, team);
   else res = stockham<T, DIR>(A + ll * NP, B + ll * NP, P, tw, lane, team);
@@ -437,17 +522,30 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T
   for (int e = threadIdx.x; e < L * N; e += blockDim.x) {
     const int t = e / L, l2 = e % L;
     const int l = l0 + l2;
-    if (l < nl) base[(int64_t)t * lstride + l] = R[l2 * NP + t];
+    if (l >= nl) continue;
+    if (DCT && DIR < 0) {
+      // X_t = (W_t V_t + conj(W_t) V_{N-t}) / 2
+      const cpx<T> a = R[l2 * NP + t], b = R[l2 * NP + (t == 0 ? 0 : N - t)];
+      const T c = twc[2 * t], sn = twc[2 * t + 1];
+      const T xr = (c * a.x + sn * a.y) + (c * b.x - sn * b.y);
+      const T xi = (c * a.y - sn * a.x) + (c * b.y + sn * b.x);
+      base[(int64_t)t * lstride + l] = {(T)0.5 * xr, (T)0.5 * xi};
+    } else if (DCT) {
+      base[(int64_t)t * lstride + l] = R[l2 * NP + ((t & 1) ? N - 1 - (t >> 1) : (t >> 1))];
+    } else {
+      base[(int64_t)t * lstride + l] = R[l2 * NP + t];
+    }
   }
 }
 
-template <typename T, int DIR, bool SOLVE, int PPT = 0>
+template <typename T, int DIR, bool SOLVE, int PPT = 0, int DCT = 0>
 __global__ void __launch_bounds__(256) k_fft_lines(FftPlan P, cpx<T>* data, int nl, int64_t lstride, int64_t ostride,
                                                    int L, const double* twd, const float* twf, const double* lamx,
                                                    const double* lamy, const double* lamz, double norm,
-                                                   const double* dtp, double hg) {
-  fft_lines_body<T, DIR, SOLVE, PPT>(blockIdx, P, data, nl, lstride, ostride, L, twd, twf, lamx, lamy, lamz, norm, dtp,
-                                     hg);
+                                                   const double* dtp, double hg, const double* twcd,
+                                                   const float* twcf) {
+  fft_lines_body<T, DIR, SOLVE, PPT, DCT>(blockIdx, P, data, nl, lstride, ostride, L, twd, twf, lamx, lamy, lamz, norm,
+                                          dtp, hg, twcd, twcf);
 }
 
 // Batched y transforms (SOLVE = false) or periodic-z spectral solve (SOLVE = true).
@@ -475,7 +573,7 @@ __global__ void __launch_bounds__(256) k_thomas_factor(GridP g, const double* __
                                                        const double* __restrict__ lamx,
                                                        const double* __restrict__ lamy, double2* __restrict__ pfac) {
   const int nxh = g.nx / 2 + 1;
-  const int64_t ncol = (int64_t)g.nxp * (g.ny / 2 + 1);   // m <= ny/2; l >= nx/2+1 are padding
+  const int64_t ncol = (int64_t)g.nxp * factor_modes(g);   // l >= nx/2+1 are padding
   const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (col >= ncol) return;
   const int l = (int)(col % g.nxp), m = (int)(col / g.nxp);
@@ -496,7 +594,7 @@ __global__ void __launch_bounds__(256) k_thomas_factor(GridP g, const double* __
 }
 
 void launch_thomas_factor(Ctx& c) {
-  const int64_t ncol = (int64_t)c.g.nxp * (c.g.ny / 2 + 1);
+  const int64_t ncol = (int64_t)c.g.nxp * factor_modes(c.g);
   hipLaunchKernelGGL(k_thomas_factor, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, c.stream, c.g, c.t.pa,
                      c.t.pb, c.t.pc, c.t.lamx, c.t.lamy, (double2*)c.t.pfac);
 }
@@ -523,8 +621,9 @@ __device__ __forceinline__ void thomas_scan_body(unsigned bx, GridP g, cpx<T>* _
   const int64_t col = c2 >> 1;
   const int l = (int)(col % g.nxp), m = (int)(col / g.nxp);
   const bool ok = c2 < ncol2 && l < nxh;
-  const int mm = m <= g.ny / 2 ? m : g.ny - m;   // mode ny - m uses the pairs of m
-  const int64_t nfac = (int64_t)g.nxp * (g.ny / 2 + 1);
+  // periodic y: mode ny - m uses the pairs of m; ducts: every m has its own
+  const int mm = (g.ywall || m <= g.ny / 2) ? m : g.ny - m;
+  const int64_t nfac = (int64_t)g.nxp * factor_modes(g);
   const double2* fp = pfac + (ok ? (int64_t)mm * g.nxp + l : 0);
   T* x = reinterpret_cast<T*>(spec) + (ok ? c2 : 0);
   const int k0 = p * S;
@@ -702,17 +801,18 @@ __device__ __forceinline__ void bulk_final_body(const BulkArgs& a_, double (*sm)
 
 // Forward y transform with the flow-rate shift folded in: block (0, 0), dispatched first,
 // forms s from the forward-x partials while the others transform (plane = blockIdx.y - 1).
-template <typename T, int PPT = 0>
+template <typename T, int PPT = 0, int DCT = 0>
 __global__ void __launch_bounds__(256) k_ffty_bulk(FftPlan P, cpx<T>* data, int nl, int64_t lstride, int64_t ostride,
                                                    int L, const double* twd, const float* twf, const double* lamx,
-                                                   const double* lamy, const double* lamz, BulkArgs ba) {
+                                                   const double* lamy, const double* lamz, BulkArgs ba,
+                                                   const double* twcd, const float* twcf) {
   if (blockIdx.y == 0) {
     extern __shared__ unsigned char smem_raw[];
     if (blockIdx.x == 0) bulk_final_body(ba, reinterpret_cast<double(*)[256]>(smem_raw));
     return;
   }
-  fft_lines_body<T, -1, false, PPT>(dim3(blockIdx.x, blockIdx.y - 1), P, data, nl, lstride, ostride, L, twd, twf,
-                                    lamx, lamy, lamz, 1.0);
+  fft_lines_body<T, -1, false, PPT, DCT>(dim3(blockIdx.x, blockIdx.y - 1), P, data, nl, lstride, ostride, L, twd, twf,
+                                         lamx, lamy, lamz, 1.0, nullptr, 0.0, twcd, twcf);
 }
 
 // ghost planes of a cell-centred scalar (Neumann walls or periodic copies)
@@ -788,9 +888,10 @@ static void fwd_x(Ctx& c, int mode, const T* us, const T* vs, const T* ws, const
 }
 
 // y transforms of the spectrum buffer (DIR -1 forward, +1 inverse)
-template <typename T, int DIR, bool SOLVE>
-static decltype(&k_fft_lines<T, DIR, SOLVE, 0>) lines_kernel(int ppt) {
-  return ppt == 0 ? k_fft_lines<T, DIR, SOLVE, 0> : (ppt == 8 ? k_fft_lines<T, DIR, SOLVE, 8> : k_fft_lines<T, DIR, SOLVE, 16>);
+template <typename T, int DIR, bool SOLVE, int DCT = 0>
+static decltype(&k_fft_lines<T, DIR, SOLVE, 0, DCT>) lines_kernel(int ppt) {
+  return ppt == 0 ? k_fft_lines<T, DIR, SOLVE, 0, DCT>
+                  : (ppt == 8 ? k_fft_lines<T, DIR, SOLVE, 8, DCT> : k_fft_lines<T, DIR, SOLVE, 16, DCT>);
 }
 template <typename T, int DIR, bool SOLVE>
 static decltype(&k_fft_lines3<T, DIR, SOLVE, 0>) lines3_kernel(int ppt) {
@@ -807,9 +908,11 @@ static void ffty(Ctx& c, const char* name) {
   const LineShape ls = line_shape(ny, sizeof(cpx<T>));
   const int L = ls.L;
   dim3 grid((nxh + L - 1) / L, nz);
-  LES_LAUNCH(c, name, 2 * spec_bytes, (lines_kernel<T, DIR, false>(ls.ppt)), grid, dim3(256), ls.sh, P,
-             (cpx<T>*)c.spec, nxh, (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy,
-             c.t.lamz, 1.0, nullptr, 0.0);
+  // ducts: the cosine transform of the wall-bounded y direction
+  auto kern = c.g.ywall ? lines_kernel<T, DIR, false, 1>(ls.ppt) : lines_kernel<T, DIR, false, 0>(ls.ppt);
+  LES_LAUNCH(c, name, 2 * spec_bytes, kern, grid, dim3(256), ls.sh, P, (cpx<T>*)c.spec, nxh, (int64_t)c.g.nxp,
+             (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, 1.0, nullptr, 0.0, c.t.twc,
+             c.t.twc_f);
 }
 
 // periodic z: FFT, divide by the operator's eigenvalue, inverse FFT (hg = 0: Poisson)
@@ -825,7 +928,7 @@ static void fftz_solve(Ctx& c, const char* name, double hg) {
   const double norm = 1.0 / ((double)c.g.nx * ny * nz);
   LES_LAUNCH(c, name, 2 * spec_bytes, (lines_kernel<T, -1, true>(ls.ppt)), grid, dim3(256), ls.sh, P,
              (cpx<T>*)c.spec, nxh, (int64_t)c.g.nxp * ny, (int64_t)c.g.nxp, L, c.t.twz, c.t.twz_f, c.t.lamx, c.t.lamy,
-             c.t.lamz, norm, c.t.dt, hg);
+             c.t.lamz, norm, c.t.dt, hg, (const double*)nullptr, (const float*)nullptr);
 }
 
 template <typename T>
@@ -840,11 +943,12 @@ static void spectral_solve(Ctx& c) {
     const int L = ls.L;
     dim3 grid((nxh + L - 1) / L, nz + 1);
     const size_t sh = std::max(ls.sh, 3 * 256 * sizeof(double));
-    const BulkArgs ba{c.t.bulk, c.bulk_nblk, c.t.dt, c.t.hfac + 4 * nz, c.t.dzf, nz, c.cfg.ubulk, (double)c.g.sxy,
-                      c.cfg.lz};
-    auto kern = ls.ppt == 0 ? k_ffty_bulk<T, 0> : (ls.ppt == 8 ? k_ffty_bulk<T, 8> : k_ffty_bulk<T, 16>);
+    const BulkArgs ba{c.t.bulk, c.bulk_nblk, c.t.dt, c.t.hfac + 4 * nz, c.t.dzf, nz, c.cfg.ubulk,
+                      (double)c.g.nx * c.g.ny, c.cfg.lz};
+    auto kern = c.g.ywall ? (ls.ppt == 0 ? k_ffty_bulk<T, 0, 1> : (ls.ppt == 8 ? k_ffty_bulk<T, 8, 1> : k_ffty_bulk<T, 16, 1>))
+                          : (ls.ppt == 0 ? k_ffty_bulk<T, 0, 0> : (ls.ppt == 8 ? k_ffty_bulk<T, 8, 0> : k_ffty_bulk<T, 16, 0>));
     LES_LAUNCH(c, "ffty_fwd", 2 * spec_bytes, kern, grid, dim3(256), sh, P, sp, nxh, (int64_t)c.g.nxp,
-               (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, ba);
+               (int64_t)c.g.nxp * ny, L, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy, c.t.lamz, ba, c.t.twc, c.t.twc_f);
     c.bulk_nblk = 0;
   } else {
     ffty<T, -1>(c, "ffty_fwd");
@@ -858,7 +962,7 @@ static void spectral_solve(Ctx& c) {
     const int P = (nz + S - 1) / S;
     const dim3 grid((unsigned)((nchain + 31) / 32)), block(32 * P);
     const double norm = 1.0 / ((double)c.g.nx * ny);
-    const double bytes = 2 * spec_bytes + (double)nxh * (ny / 2 + 1) * nz * 16;
+    const double bytes = 2 * spec_bytes + (double)nxh * factor_modes(c.g) * nz * 16;
     if (S == 8)
       LES_LAUNCH(c, "thomas_z", bytes, (k_thomas_scan<T, 8, true>), grid, block, 0, c.g, sp, c.t.pa,
                  (const double2*)c.t.pfac, norm, nz);
@@ -978,6 +1082,7 @@ void launch_poisson_field(Ctx& c, T* f) {
   inv_x<T>(c, f);
   LES_LAUNCH(c, "scalar_ghosts", 4.0 * c.g.sxy * sizeof(T), k_scalar_ghosts<T>, dim3((unsigned)((c.g.sxy + 255) / 256)),
              dim3(256), 0, c.g, f);
+  if (c.g.ywall) launch_fill_y_scalar<T>(c, f, 1.0);
 }
 
 // ============================================================================ batch launchers

@@ -11,7 +11,12 @@
 //
 // Strain ghosts: with the wall model, wall-parallel velocity ghosts for the strain are the
 // linear extrapolation in z of the first two interior values (one-sided wall-normal
-// derivative in the first layer, Sec. 2.2); otherwise the stored ghosts are used.
+// derivative in the first layer, Sec. 2.2), and in a duct those of u and w in y as well;
+// otherwise the stored ghosts are used.
+//
+// Ducts (walls in y too, Sec. 4.4): the van Driest factor takes y* as the smallest of
+// d_w u_tau,w / nu over the four walls and is folded into the stored field (|S| D^2), so
+// the plane coefficient stays (C_s Delta_k)^2.
 #include "les_internal.h"
 #include "mlp_core.h"
 
@@ -26,7 +31,7 @@ struct VelView {
   const T* w;
 };
 
-// u or v at (k, j, i) with the strain ghost rule.
+// u or v at (k, j, i) with the z strain ghost rule.
 template <typename T>
 __device__ inline T sval(const GridP& g, const T* f, int k, int j, int i) {
   if (g.zbc == LES_ZBC_WALLMODEL) {
@@ -43,15 +48,31 @@ __device__ inline T sval(const GridP& g, const T* f, int k, int j, int i) {
   return f[idx3(g, k, j, i)];
 }
 
+// u or w of a duct with the wall model on a y ghost row: the linear extrapolation in y of the
+// first two interior rows (uniform dy), taken after the z rule (zr: apply it, for u).
+template <typename T>
+__device__ inline T sval_y(const GridP& g, const T* f, int k, int j, int i, bool zr) {
+  auto at = [&](int jj) { return zr ? sval(g, f, k, jj, i) : f[idx3(g, k, jj, i)]; };
+  if (g.ywall && g.zbc == LES_ZBC_WALLMODEL && j >= g.ny) {
+    if (j == g.ny + 1) {
+      const T a0 = at(0), a1 = at(1);
+      return a0 - (a1 - a0);
+    }
+    const T a0 = at(g.ny - 1), a1 = at(g.ny - 2);
+    return a0 + (a0 - a1);
+  }
+  return at(j);
+}
+
 // Strain rate at the centre of cell (k, j, i): s[0..5] = S11 S22 S33 S12 S13 S23.
 template <typename T>
 __device__ inline void centre_strain(const GridP& g, const T* u, const T* v, const T* w, int k, int j, int i, T s[6]) {
-  const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx), jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
+  const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx), jp = wrap_p(j, g.nys), jm = wrap_m(j, g.nys);
   const T rdx = (T)g.rdx, rdy = (T)g.rdy, h = (T)0.5, q = (T)0.25;
   const T rdzc = (T)(1.0 / g.dzc[k]), rdzcm = (T)(1.0 / g.dzc[k - 1]);
-#define US(kk, jj, ii) sval(g, u, kk, jj, ii)
+#define US(kk, jj, ii) sval_y(g, u, kk, jj, ii, true)
 #define VS(kk, jj, ii) sval(g, v, kk, jj, ii)
-#define W(kk, jj, ii) w[idx3(g, kk, jj, ii)]
+#define W(kk, jj, ii) sval_y(g, w, kk, jj, ii, false)
   const T u0 = US(k, j, i), uim = US(k, j, im), ujp = US(k, jp, i), ujm = US(k, jm, i);
   const T ujp_im = US(k, jp, im), ujm_im = US(k, jm, im);
   const T v0 = VS(k, j, i), vjm = VS(k, jm, i), vip = VS(k, j, ip), vim = VS(k, j, im);
@@ -104,14 +125,90 @@ __device__ inline void store_nut(const GridP& g, T* nut, int k, int j, int i, T 
 // ============================================================================ |S|
 template <typename T>
 __global__ void __launch_bounds__(256) k_strain_mag(GridP g, const T* __restrict__ u, const T* __restrict__ v,
-                                                    const T* __restrict__ w, T* __restrict__ nut) {
+                                                    const T* __restrict__ w, T* __restrict__ nut,
+                                                    const double* __restrict__ vd4, double ly) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = blockIdx.z + 1;
   if (i >= g.nx || j >= g.ny) return;
   T s[6];
   centre_strain(g, u, v, w, k, j, i, s);
-  store_nut(g, nut, k, j, i, strain_mag(s));
+  T val = strain_mag(s);
+  if (vd4 != nullptr) {
+    // duct van Driest factor (four walls): y* the smallest d_w u_tau,w / nu
+    const double zc = g.zc[k], yc = (j + 0.5) * g.dy;
+    const double ys = fmin(fmin(zc * vd4[0], (g.lz - zc) * vd4[1]), fmin(yc * vd4[2], (ly - yc) * vd4[3])) / g.nu;
+    const double d = 1.0 - exp(-ys / 25.0);
+    val = (T)((double)val * (d * d));
+  }
+  store_nut(g, nut, k, j, i, val);
+}
+
+// Friction velocities of the four duct walls for the van Driest factor: sqrt(|(<tau_1>,
+// <tau_2>)|) per wall, each component averaged over its own points on that wall that are not
+// wall faces (z walls: rows j < ny, the v stress over j < ny - 1; y walls: planes 1..nz, the w
+// stress over faces 1..nz-1).  Stresses from the wall models, or nu times the wall-normal
+// difference across the no-slip ghosts.  One block, fixed-order sums; vd4 = (z bottom, z
+// top, y = 0, y = ly).
+template <typename T>
+__global__ void __launch_bounds__(256) k_vd_duct(GridP g, const T* u, const T* v, const T* w, const double* tau,
+                                                 const double* tauy, int wallmodel, double* vd4) {
+  __shared__ double sm[8][256];
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int n = g.nz, ny = g.ny, nx = g.nx;
+  const int64_t s = g.sxy, sy = (int64_t)(n + 2) * nx;
+  for (int64_t c = threadIdx.x; c < (int64_t)nx * ny; c += blockDim.x) {
+    const bool vrow = c < (int64_t)nx * (ny - 1);   // v rows off the wall face y = ly
+    if (wallmodel) {
+      a[0] += tau[c];
+      a[2] += tau[2 * s + c];
+      if (vrow) {
+        a[1] += tau[s + c];
+        a[3] += tau[3 * s + c];
+      }
+    } else {
+      a[0] += g.nu * ((double)u[s + c] - (double)u[c]) / g.dzc[0];
+      a[2] += g.nu * ((double)u[(int64_t)n * s + c] - (double)u[(int64_t)(n + 1) * s + c]) / g.dzc[n];
+      if (vrow) {
+        a[1] += g.nu * ((double)v[s + c] - (double)v[c]) / g.dzc[0];
+        a[3] += g.nu * ((double)v[(int64_t)n * s + c] - (double)v[(int64_t)(n + 1) * s + c]) / g.dzc[n];
+      }
+    }
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)nx * n; e += blockDim.x) {
+    const int k = (int)(e / nx) + 1, i = (int)(e % nx);
+    const bool wface = k < n;   // w faces off the wall face k = nz
+    if (wallmodel) {
+      const int64_t o = (int64_t)k * nx + i;
+      a[4] += tauy[o];
+      a[6] += tauy[2 * sy + o];
+      if (wface) {
+        a[5] += tauy[sy + o];
+        a[7] += tauy[3 * sy + o];
+      }
+    } else {
+      a[4] += g.nu * ((double)u[idx3(g, k, 0, i)] - (double)u[idx3(g, k, ny + 1, i)]) / g.dy;
+      a[6] += g.nu * ((double)u[idx3(g, k, ny - 1, i)] - (double)u[idx3(g, k, ny, i)]) / g.dy;
+      if (wface) {
+        a[5] += g.nu * ((double)w[idx3(g, k, 0, i)] - (double)w[idx3(g, k, ny + 1, i)]) / g.dy;
+        a[7] += g.nu * ((double)w[idx3(g, k, ny - 1, i)] - (double)w[idx3(g, k, ny, i)]) / g.dy;
+      }
+    }
+  }
+  for (int q = 0; q < 8; ++q) sm[q][threadIdx.x] = a[q];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int q = 0; q < 8; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double cz = (double)nx * ny, cv = (double)nx * (ny - 1), cy = (double)nx * n, cw = (double)nx * (n - 1);
+    vd4[0] = sqrt(hypot(sm[0][0] / cz, sm[1][0] / cv));
+    vd4[1] = sqrt(hypot(sm[2][0] / cz, sm[3][0] / cv));
+    vd4[2] = sqrt(hypot(sm[4][0] / cy, sm[5][0] / cw));
+    vd4[3] = sqrt(hypot(sm[6][0] / cy, sm[7][0] / cw));
+  }
 }
 
 // van Driest coefficient: plane-mean wall stresses -> u_tau per wall -> coef[k].
@@ -298,9 +395,9 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   for (int r = 0; r < NL; ++r) {
     const int e = tid + r * NT;
     const int rx = e % RX2, ry = e / RX2;
-    int i = (i0 - 2 + rx) % g.nx, j = (j0 - 2 + ry) % g.ny;
+    int i = (i0 - 2 + rx) % g.nx, j = (j0 - 2 + ry) % g.nys;
     if (i < 0) i += g.nx;
-    if (j < 0) j += g.ny;
+    if (j < 0) j += g.nys;
     lofs[r] = e < N2 ? j * g.nx + i : 0;
   }
   // velocity of one plane held in registers between its fetch and its commit to LDS, so that
@@ -626,13 +723,13 @@ __global__ void k_mlp_prep(GridP g, const double* part, double* dtp, int* cnt) {
 template <typename T>
 __device__ inline void centre_rotation(const GridP& g, const T* u, const T* v, const T* w, int k, int j, int i,
                                        double o[3]) {
-  const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx), jp = wrap_p(j, g.ny), jm = wrap_m(j, g.ny);
+  const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx), jp = wrap_p(j, g.nys), jm = wrap_m(j, g.nys);
   const double rdx = g.rdx, rdy = g.rdy, rdzc = 1.0 / g.dzc[k], rdzcm = 1.0 / g.dzc[k - 1];
   auto U = [&](int kk, int jj, int ii) { return (double)sval(g, u, kk, jj, ii); };
   auto V = [&](int kk, int jj, int ii) { return (double)sval(g, v, kk, jj, ii); };
   auto W = [&](int kk, int jj, int ii) { return (double)w[idx3(g, kk, jj, ii)]; };
   auto r12 = [&](int jj, int ii) {
-    return 0.5 * ((U(k, wrap_p(jj, g.ny), ii) - U(k, jj, ii)) * rdy - (V(k, jj, wrap_p(ii, g.nx)) - V(k, jj, ii)) * rdx);
+    return 0.5 * ((U(k, wrap_p(jj, g.nys), ii) - U(k, jj, ii)) * rdy - (V(k, jj, wrap_p(ii, g.nx)) - V(k, jj, ii)) * rdx);
   };
   o[0] = 0.25 * (r12(j, i) + r12(j, im) + r12(jm, i) + r12(jm, im));
   auto r13 = [&](int kk, int ii, double rz) {
@@ -640,7 +737,7 @@ __device__ inline void centre_rotation(const GridP& g, const T* u, const T* v, c
   };
   o[1] = 0.25 * (r13(k, i, rdzc) + r13(k, im, rdzc) + r13(k - 1, i, rdzcm) + r13(k - 1, im, rdzcm));
   auto r23 = [&](int kk, int jj, double rz) {
-    return 0.5 * ((V(kk + 1, jj, i) - V(kk, jj, i)) * rz - (W(kk, wrap_p(jj, g.ny), i) - W(kk, jj, i)) * rdy);
+    return 0.5 * ((V(kk + 1, jj, i) - V(kk, jj, i)) * rz - (W(kk, wrap_p(jj, g.nys), i) - W(kk, jj, i)) * rdy);
   };
   o[2] = 0.25 * (r23(k, j, rdzc) + r23(k, jm, rdzc) + r23(k - 1, j, rdzcm) + r23(k - 1, jm, rdzcm));
   (void)ip;
@@ -749,9 +846,9 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
   int lofs[NL];
   for (int r = 0; r < NL; ++r) {
     const int e = tid + r * tiled::NT;
-    int ii = (i0 - 1 + e % RX) % g.nx, jj = (j0 - 1 + e / RX) % g.ny;
+    int ii = (i0 - 1 + e % RX) % g.nx, jj = (j0 - 1 + e / RX) % g.nys;
     if (ii < 0) ii += g.nx;
-    if (jj < 0) jj += g.ny;
+    if (jj < 0) jj += g.nys;
     lofs[r] = e < N1 ? jj * g.nx + ii : 0;
   }
   const int64_t sxy = g.sxy;
@@ -914,11 +1011,15 @@ void launch_eddy_viscosity(Ctx& c) {
   Launch3 L = point_launch(g, g.nz);
   const int model = c.cfg.sgs;
   if (model == LES_SGS_NONE) return;
-  const double pts = (double)g.sxy * g.nz;
+  const double pts = (double)g.nx * g.ny * g.nz;
   if (model == LES_SGS_SMAG || model == LES_SGS_SMAG_VD) {
+    const bool duct_vd = g.ywall && model == LES_SGS_SMAG_VD;
+    if (duct_vd)
+      LES_LAUNCH(c, "vd_duct", 0, k_vd_duct<T>, dim3(1), dim3(256), 0, g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
+                 c.t.tau, c.t.tauy, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.vd4);
     LES_LAUNCH(c, "strain_mag", 4 * pts * sizeof(T), k_strain_mag<T>, L.grid, L.block, 0, g, (const T*)c.u, (const T*)c.v,
-                       (const T*)c.w, (T*)c.nut);
-    if (model == LES_SGS_SMAG_VD && c.cfg.zbc != LES_ZBC_PERIODIC)
+                       (const T*)c.w, (T*)c.nut, duct_vd ? (const double*)c.t.vd4 : nullptr, c.cfg.ly);
+    if (model == LES_SGS_SMAG_VD && c.cfg.zbc != LES_ZBC_PERIODIC && !g.ywall)
       LES_LAUNCH(c, "vd_coef", 0, k_vd_coef<T>, dim3(1), dim3(256), 0, g, (const T*)c.u, (const T*)c.v, c.t.tau,
                          c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.cfg.cs, c.t.coef);
     return;

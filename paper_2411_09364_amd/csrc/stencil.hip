@@ -222,9 +222,10 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
   int lofs[NL];
   for (int r = 0; r < NL; ++r) {
     const int e = tid + r * NT;
-    int ii = (i0 - 1 + e % RX) % g.nx, jj = (j0 - 1 + e / RX) % g.ny;
+    // rows wrap over the stored rows: a duct's ghost rows sit where j = -1 and j = ny land
+    int ii = (i0 - 1 + e % RX) % g.nx, jj = (j0 - 1 + e / RX) % g.nys;
     if (ii < 0) ii += g.nx;
-    if (jj < 0) jj += g.ny;
+    if (jj < 0) jj += g.nys;
     lofs[r] = e < N1 ? jj * g.nx + ii : 0;
   }
   T rg[NL][5];
@@ -314,7 +315,7 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
         rw[c0] = Rw;
       }
       us[c0] = uo;
-      vs[c0] = vo;
+      vs[c0] = (g.ywall && j == g.ny - 1) ? (T)0 : vo;   // v on the duct's wall face y = ly
       ws[c0] = wo;
     }
     __syncthreads();
@@ -631,11 +632,11 @@ __device__ __forceinline__ void correct_body(dim3 bid, GridP g, const T* __restr
   const T gdt = (T)(gamma * dtp[0]);
   const T ph = phi[c0];
   const T phx = phi[idx3(g, k, j, wrap_p(i, g.nx))];
-  const T phy = phi[idx3(g, k, wrap_p(j, g.ny), i)];
+  const T phy = phi[idx3(g, k, wrap_p(j, g.nys), i)];
   const T phz = phi[idx3(g, kp, j, i)];
   T un = us[c0] - gdt * ((phx - ph) * (T)g.rdx);
   if (qprof != nullptr) un = un + (T)(dtp[1] * qprof[k - 1]);
-  const T vn = vs[c0] - gdt * ((phy - ph) * (T)g.rdy);
+  const T vn = (g.ywall && j == g.ny - 1) ? (T)0 : vs[c0] - gdt * ((phy - ph) * (T)g.rdy);
   T wn;
   if (!per && k == n) wn = (T)0;
   else wn = ws[c0] - gdt * ((phz - ph) * (T)(1.0 / g.dzc[k]));
@@ -645,7 +646,7 @@ __device__ __forceinline__ void correct_body(dim3 bid, GridP g, const T* __restr
     const T phm = phi[idx3(g, km, j, i)];
     T lap = ((phz - ph) * (T)(1.0 / g.dzc[k]) - (ph - phm) * (T)(1.0 / g.dzc[k - 1])) * (T)(1.0 / g.dzf[k]);
     if (implicit == 2) {
-      const T phxm = phi[idx3(g, k, j, wrap_m(i, g.nx))], phym = phi[idx3(g, k, wrap_m(j, g.ny), i)];
+      const T phxm = phi[idx3(g, k, j, wrap_m(i, g.nx))], phym = phi[idx3(g, k, wrap_m(j, g.nys), i)];
       lap = (phx - (T)2 * ph + phxm) * (T)(g.rdx * g.rdx) + (phy - (T)2 * ph + phym) * (T)(g.rdy * g.rdy) + lap;
     }
     pn = pn - (T)(gamma * g.nu * dtp[0] / 2.0) * lap;
@@ -719,7 +720,7 @@ __global__ void k_wallmodel(GridP g, T* u, T* v, double* tau, double* utau, int 
                             int kt0, int kt1, double tt, double ht, double kappa, double bconst) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int which = blockIdx.y;  // 0 bot-x, 1 bot-y, 2 top-x, 3 top-y
-  if (c >= g.sxy) return;
+  if (c >= (int64_t)g.nx * g.ny) return;   // interior rows (a duct's ghost rows carry no stress)
   const int i = (int)(c % g.nx), j = (int)(c / g.nx);
   const bool top = which >= 2;
   const bool isx = (which & 1) == 0;
@@ -731,18 +732,19 @@ __global__ void k_wallmodel(GridP g, T* u, T* v, double* tau, double* utau, int 
   double a, b;
   if (isx) {
     a = at(u, j, i);
-    const int ip = wrap_p(i, g.nx), jm = wrap_m(j, g.ny);
+    const int ip = wrap_p(i, g.nx), jm = wrap_m(j, g.nys);
     b = 0.25 * (at(v, j, i) + at(v, j, ip) + at(v, jm, i) + at(v, jm, ip));
   } else {
     a = at(v, j, i);
-    const int im = wrap_m(i, g.nx), jp = wrap_p(j, g.ny);
+    const int im = wrap_m(i, g.nx), jp = wrap_p(j, g.nys);
     b = 0.25 * (at(u, j, i) + at(u, j, im) + at(u, jp, i) + at(u, jp, im));
   }
   const double U = sqrt(a * a + b * b);
   const int64_t o = (int64_t)which * g.sxy + c;
   const double x = wm_newton(U, h, g.nu, kappa, bconst, utau[o]);
   utau[o] = x;
-  const double tw = U > 0.0 ? x * x * a / U : 0.0;
+  // the v row on a duct's wall face y = ly has no wall-parallel velocity
+  const double tw = (U > 0.0 && !(g.ywall && !isx && j == g.ny - 1)) ? x * x * a / U : 0.0;
   tau[o] = tw;
   T* f = isx ? u : v;
   const int n = g.nz;
@@ -773,6 +775,133 @@ void launch_wallmodel(Ctx& c) {
                      kb1, tb, hb, kt0, kt1, tt, ht, c.cfg.kappa, c.cfg.bconst);
 }
 
+// ============================================================================ duct: y walls
+// The square duct (Sec. 4.4) keeps two ghost rows per plane after the interior rows: row ny
+// above y = ly and row ny + 1 below y = 0, where the wrapped index j - 1 of row 0 lands, so
+// the y-periodic stencils read the boundary values there.  Rules (Alg. 2 with the z walls'
+// treatment in y): v = 0 on both wall faces (row ny - 1 and ghost row ny + 1; row ny is
+// never read and is set to 0), u and w odd (no-slip) or from the y-wall stresses (the
+// viscous flux nu (u_0 - u_ghost)/dy equals the stress), p even.  One thread per (k, i),
+// every stored plane k = 0..nz+1, run after the z ghost planes so that the corners follow
+// the y rule.
+template <typename T>
+__global__ void k_bc_fill_y(GridP g, T* u, T* v, T* w, T* p, const double* tauy, int wallmodel) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= g.nx) return;
+  const int ny = g.ny;
+  const int64_t lo = idx3(g, k, ny + 1, i), hi = idx3(g, k, ny, i);
+  const int64_t j0 = idx3(g, k, 0, i), j1 = idx3(g, k, ny - 1, i);
+  v[j1] = (T)0;
+  v[hi] = (T)0;
+  v[lo] = (T)0;
+  if (wallmodel) {
+    const int64_t s = (int64_t)(g.nz + 2) * g.nx, o = (int64_t)k * g.nx + i;
+    u[lo] = (T)((double)u[j0] - g.dy * tauy[o] / g.nu);
+    w[lo] = (T)((double)w[j0] - g.dy * tauy[s + o] / g.nu);
+    u[hi] = (T)((double)u[j1] - g.dy * tauy[2 * s + o] / g.nu);
+    w[hi] = (T)((double)w[j1] - g.dy * tauy[3 * s + o] / g.nu);
+  } else {
+    u[lo] = -u[j0];
+    w[lo] = -w[j0];
+    u[hi] = -u[j1];
+    w[hi] = -w[j1];
+  }
+  p[lo] = p[j0];
+  p[hi] = p[j1];
+}
+
+template <typename T>
+void launch_bc_fill_y(Ctx& c, T* u, T* v, T* w, T* p) {
+  LES_LAUNCH(c, "bc_fill_y", 14.0 * c.g.nx * (c.g.nz + 2) * sizeof(T), k_bc_fill_y<T>,
+             dim3((unsigned)((c.g.nx + 63) / 64), (unsigned)(c.g.nz + 2)), dim3(64), 0, c.g, u, v, w, p, c.t.tauy,
+             c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0);
+}
+
+// y ghost rows of a cell-centred scalar: even (sign 1: pressure, pressure correction) or odd
+// (sign -1: the eddy-viscosity field, R12 in y), every stored plane.
+template <typename T>
+__global__ void k_fill_y_scalar(GridP g, T* f, T sign) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= g.nx) return;
+  f[idx3(g, k, g.ny + 1, i)] = sign * f[idx3(g, k, 0, i)];
+  f[idx3(g, k, g.ny, i)] = sign * f[idx3(g, k, g.ny - 1, i)];
+}
+
+template <typename T>
+void launch_fill_y_scalar(Ctx& c, T* f, double sign) {
+  LES_LAUNCH(c, "fill_y", 4.0 * c.g.nx * (c.g.nz + 2) * sizeof(T), k_fill_y_scalar<T>,
+             dim3((unsigned)((c.g.nx + 63) / 64), (unsigned)(c.g.nz + 2)), dim3(64), 0, c.g, f, (T)sign);
+}
+
+// Wall model on the y walls: the z-wall rule with y and z exchanged.  One thread per (wall,
+// component, k, i): u (at (i+1/2, k)) and w (at (i, k+1/2)) interpolated in y to h_wm, the
+// other component brought to the point by its four-face mean (x and z neighbours), Newton for
+// u_tau, tau = u_tau^2 (component)/U.  w on the z wall face k = nz carries no stress; the
+// ghost rows are written afterwards from tau (k_bc_fill_y).  tauy: [4][nz+2][nx] (tau_x at
+// y = 0, tau_z at y = 0, tau_x at y = ly, tau_z at y = ly), ghost planes left at zero.
+template <typename T>
+__global__ void k_wallmodel_y(GridP g, const T* u, const T* w, double* tauy, double* utauy, int jb0, int jb1,
+                              double tb, double hb, int jt0, int jt1, double tt, double ht, double kappa,
+                              double bconst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y + 1;
+  const int which = blockIdx.z;   // 0 lo-x, 1 lo-z, 2 hi-x, 3 hi-z
+  if (i >= g.nx) return;
+  const bool top = which >= 2;
+  const bool isx = (which & 1) == 0;
+  const int j0 = top ? jt0 : jb0, j1 = top ? jt1 : jb1;
+  const double t = top ? tt : tb, h = top ? ht : hb;
+  auto at = [&](const T* f, int kk, int ii) {
+    return (1.0 - t) * (double)f[idx3(g, kk, j0, ii)] + t * (double)f[idx3(g, kk, j1, ii)];
+  };
+  const int64_t o = (int64_t)which * (g.nz + 2) * g.nx + (int64_t)k * g.nx + i;
+  if (!isx && k == g.nz) {
+    tauy[o] = 0.0;
+    return;
+  }
+  double a, b;
+  if (isx) {
+    a = at(u, k, i);
+    const int ip = wrap_p(i, g.nx);
+    b = 0.25 * (at(w, k, i) + at(w, k, ip) + at(w, k - 1, i) + at(w, k - 1, ip));
+  } else {
+    a = at(w, k, i);
+    const int im = wrap_m(i, g.nx);
+    b = 0.25 * (at(u, k, i) + at(u, k, im) + at(u, k + 1, i) + at(u, k + 1, im));
+  }
+  const double U = sqrt(a * a + b * b);
+  const double x = wm_newton(U, h, g.nu, kappa, bconst, utauy[o]);
+  utauy[o] = x;
+  tauy[o] = U > 0.0 ? x * x * a / U : 0.0;
+}
+
+template <typename T>
+void launch_wallmodel_y(Ctx& c) {
+  const int ny = c.g.ny;
+  const double dy = c.g.dy;
+  auto yc = [&](int j) { return (j + 0.5) * dy; };
+  int jb0 = 0, jb1 = 1, jt0 = ny - 1, jt1 = ny - 2;
+  double tb = 0.0, tt = 0.0, hb = yc(0), ht = c.cfg.ly - yc(ny - 1);
+  if (c.cfg.h_wm > 0.0) {
+    const double h = c.cfg.h_wm;
+    for (int j = 0; j < ny - 1; ++j)
+      if (yc(j) <= h) jb0 = j;
+    jb1 = jb0 + 1;
+    tb = (h - yc(jb0)) / (yc(jb1) - yc(jb0));
+    for (int j = ny - 1; j >= 1; --j)
+      if (c.cfg.ly - yc(j) <= h) jt0 = j;
+    jt1 = jt0 - 1;
+    const double lo = c.cfg.ly - yc(jt0), hi = c.cfg.ly - yc(jt1);
+    tt = (h - lo) / (hi - lo);
+    hb = ht = h;
+  }
+  LES_LAUNCH(c, "wallmodel_y", (double)c.g.nx * c.g.nz * (8.0 * sizeof(T) + 4 * 3 * 8.0), k_wallmodel_y<T>,
+             dim3((unsigned)((c.g.nx + 63) / 64), (unsigned)c.g.nz, 4), dim3(64), 0, c.g, (const T*)c.u, (const T*)c.w,
+             c.t.tauy, c.t.utauy, jb0, jb1, tb, hb, jt0, jt1, tt, ht, c.cfg.kappa, c.cfg.bconst);
+}
+
 // ============================================================================ time step
 // Block maxima of |u|/dx + |v|/dy + |w|/dzf and of nu_t, reduced in a fixed order by a
 // single block which then writes dt (R22 reading of the paper's time-step rule).
@@ -781,14 +910,16 @@ __device__ __forceinline__ void cfl_partial_body(int b, int nb, GridP g, const T
                                                  const T* nut, const double* coef, double* part) {
   __shared__ double sm[2][256];
   double mc = 0.0, mn = 0.0;
-  const int64_t total = (int64_t)g.nz * g.sxy;
+  // interior cells: the first nxy of every plane (a duct's ghost rows follow them)
+  const int64_t nxy = (int64_t)g.nx * g.ny;
+  const int64_t total = (int64_t)g.nz * nxy;
   // the flattened interior index advances by a fixed stride: its plane and in-plane offset
   // are stepped along instead of divided out per element
   const int64_t step = (int64_t)nb * blockDim.x;
   int64_t e = b * (int64_t)blockDim.x + threadIdx.x;
-  int k = (int)(e / g.sxy) + 1;
-  int64_t r = e % g.sxy;
-  const int64_t dk = step / g.sxy, dr = step % g.sxy;
+  int k = (int)(e / nxy) + 1;
+  int64_t r = e % nxy;
+  const int64_t dk = step / nxy, dr = step % nxy;
   for (; e < total; e += step) {
     const int64_t c = (int64_t)k * g.sxy + r;
     const double a = fabs((double)u[c]) * g.rdx + fabs((double)v[c]) * g.rdy + fabs((double)w[c]) / g.dzf[k];
@@ -796,8 +927,8 @@ __device__ __forceinline__ void cfl_partial_body(int b, int nb, GridP g, const T
     mn = fmax(mn, coef[k] * (double)nut[c]);
     k += (int)dk;
     r += dr;
-    if (r >= g.sxy) {
-      r -= g.sxy;
+    if (r >= nxy) {
+      r -= nxy;
       ++k;
     }
   }
@@ -912,16 +1043,17 @@ __global__ void __launch_bounds__(256) k_diag_partial(GridP g, const T* u, const
   __shared__ double sm[6][256];
   double md = 0.0, su = 0.0, mv = 0.0, nf = 0.0, tb = 0.0, tt = 0.0;
   const bool per = g.zbc == LES_ZBC_PERIODIC;
-  const int64_t total = (int64_t)g.nz * g.sxy;
+  const int64_t nxy = (int64_t)g.nx * g.ny;   // interior cells of a plane (stored first)
+  const int64_t total = (int64_t)g.nz * nxy;
   const int64_t chunk = (total + DIAG_BLOCKS - 1) / DIAG_BLOCKS;
   const int64_t e0 = blockIdx.x * chunk, e1 = e0 + chunk < total ? e0 + chunk : total;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const int k = (int)(e / g.sxy) + 1;
-    const int64_t r = e % g.sxy;
+    const int k = (int)(e / nxy) + 1;
+    const int64_t r = e % nxy;
     const int i = (int)(r % g.nx), j = (int)(r / g.nx);
     const int64_t c = (int64_t)k * g.sxy + r;
     const double d = ((double)u[c] - (double)u[idx3(g, k, j, wrap_m(i, g.nx))]) * g.rdx +
-                     ((double)v[c] - (double)v[idx3(g, k, wrap_m(j, g.ny), i)]) * g.rdy +
+                     ((double)v[c] - (double)v[idx3(g, k, wrap_m(j, g.nys), i)]) * g.rdy +
                      ((double)w[c] - (double)w[c - g.sxy]) / g.dzf[k];
     md = fmax(md, fabs(d));
     su += (double)u[c] * g.dzf[k];
@@ -930,8 +1062,8 @@ __global__ void __launch_bounds__(256) k_diag_partial(GridP g, const T* u, const
       nf += 1.0;
   }
   if (!per && tau != nullptr) {
-    const int64_t pc = (g.sxy + DIAG_BLOCKS - 1) / DIAG_BLOCKS;
-    const int64_t r0 = blockIdx.x * pc, r1 = r0 + pc < g.sxy ? r0 + pc : g.sxy;
+    const int64_t pc = (nxy + DIAG_BLOCKS - 1) / DIAG_BLOCKS;
+    const int64_t r0 = blockIdx.x * pc, r1 = r0 + pc < nxy ? r0 + pc : nxy;
     for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
       tb += tau[r];
       tt += tau[2 * g.sxy + r];
@@ -1011,6 +1143,9 @@ template void batch_dt<double>(hipStream_t, const BatchMap&, int, int, double);
   template void launch_correct<T>(Ctx&, int);                    \
   template void launch_bc_fill<T>(Ctx&, T*, T*, T*, T*);         \
   template void launch_wallmodel<T>(Ctx&);                       \
+  template void launch_wallmodel_y<T>(Ctx&);                     \
+  template void launch_bc_fill_y<T>(Ctx&, T*, T*, T*, T*);       \
+  template void launch_fill_y_scalar<T>(Ctx&, T*, double);       \
   template void launch_dt<T>(Ctx&, double);                      \
   template void launch_diag<T>(Ctx&, double*);
 INST(double)

@@ -15,8 +15,9 @@ ZBC_PERIODIC, ZBC_NOSLIP, ZBC_WALLMODEL = 0, 1, 2
 SGS_NONE, SGS_SMAG, SGS_SMAG_VD, SGS_DSM, SGS_MLP = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 VISC_EXPLICIT, VISC_CN_Z, VISC_CN_3D = 0, 1, 2
-FIELD_U, FIELD_V, FIELD_W, FIELD_P, FIELD_WORKSPACE, FIELD_NUT, FIELD_CS, FIELD_TAUW, FIELD_ZGRID = range(9)
-ABI_VERSION = 1
+FIELD_U, FIELD_V, FIELD_W, FIELD_P, FIELD_WORKSPACE, FIELD_NUT, FIELD_CS, FIELD_TAUW, FIELD_ZGRID, FIELD_TAUWY = range(10)
+YBC_PERIODIC, YBC_WALL = 0, 1
+ABI_VERSION = 2
 
 
 class LesConfig(ctypes.Structure):
@@ -26,7 +27,7 @@ class LesConfig(ctypes.Structure):
                 ("nu", ctypes.c_double), ("sgs", ctypes.c_int32), ("cs", ctypes.c_double),
                 ("implicit_z", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("ubulk", ctypes.c_double), ("h_wm", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("bconst", ctypes.c_double)]
+                ("bconst", ctypes.c_double), ("ybc", ctypes.c_int32)]
 
 
 class LesLayout(ctypes.Structure):
@@ -135,9 +136,9 @@ def exported_symbols():
 
 
 def make_config(nx, ny, nz, lx, ly, lz, zbc=ZBC_PERIODIC, beta=0.0, nu=1e-3, sgs=SGS_NONE, cs=0.17,
-                implicit_z=0, precision=FP64, ubulk=0.0, h_wm=0.0, kappa=0.41, bconst=5.2):
+                implicit_z=0, precision=FP64, ubulk=0.0, h_wm=0.0, kappa=0.41, bconst=5.2, ybc=YBC_PERIODIC):
     return LesConfig(ABI_VERSION, nx, ny, nz, lx, ly, lz, zbc, beta, nu, sgs, cs, int(implicit_z),
-                     precision, ubulk, h_wm, kappa, bconst)
+                     precision, ubulk, h_wm, kappa, bconst, int(ybc))
 
 
 def _check(ctx, st, what):
@@ -337,7 +338,8 @@ def les_free(ctx):
 class Solver:
     """One context with torch-allocated fields and workspace on its own stream.
 
-    Fields are torch tensors of shape (nz + 2, ny, nx) in the context's storage type.
+    Fields are torch tensors of shape (nz + 2, ny, nx) in the context's storage type
+    ((nz + 2, ny + 2, nx) for ducts: two ghost rows after the interior rows).
     """
 
     def __init__(self, cfg, device="cuda"):
@@ -348,7 +350,7 @@ class Solver:
         self.ctx = les_init(cfg, self.stream.cuda_stream)
         lay = les_layout(self.ctx, FIELD_U)
         self.dtype = torch.float64 if lay.elem_bytes == 8 else torch.float32
-        self.shape = (cfg.nz + 2, cfg.ny, cfg.nx)
+        self.shape = tuple(int(d) for d in lay.dims)   # (nz + 2, ny [+ 2 ghost rows for ducts], nx)
         with torch.cuda.stream(self.stream):
             self.u, self.v, self.w, self.p = (torch.zeros(self.shape, dtype=self.dtype, device=device)
                                               for _ in range(4))
@@ -413,8 +415,16 @@ class Solver:
 
     def wall_stress(self):
         torch = self.torch
-        out = torch.empty((4, self.cfg.ny, self.cfg.nx), dtype=torch.float64, device=self.u.device)
+        out = torch.empty((4, self.shape[1], self.cfg.nx), dtype=torch.float64, device=self.u.device)
         les_read(self.ctx, FIELD_TAUW, out.data_ptr())
+        self.synchronize()
+        return out.cpu().numpy()
+
+    def wall_stress_y(self):
+        """Ducts with the wall model: (4, nz + 2, nx) stresses of the y walls."""
+        torch = self.torch
+        out = torch.empty((4, self.cfg.nz + 2, self.cfg.nx), dtype=torch.float64, device=self.u.device)
+        les_read(self.ctx, FIELD_TAUWY, out.data_ptr())
         self.synchronize()
         return out.cpu().numpy()
 

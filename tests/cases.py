@@ -6,7 +6,7 @@ import numpy as np
 
 import oracle
 from oracle import substep as S
-from synth import isotropic_field, channel_field, random_state
+from synth import isotropic_field, channel_field, duct_field, random_state
 
 
 def say(*a):
@@ -24,7 +24,7 @@ def make_pair(nx, ny, nz, lx, ly, lz, **kw):
                           sgs=case.sgs, cs=case.cs,
                           implicit_z=2 if case.implicit_3d else int(case.implicit_z),
                           precision=precision, ubulk=case.ubulk, h_wm=case.h_wm,
-                          kappa=case.kappa, bconst=case.bconst)
+                          kappa=case.kappa, bconst=case.bconst, ybc=case.ybc)
     return case, g, cfg
 
 
@@ -34,9 +34,15 @@ def initial_fields(case, g, seed, kind):
         return isotropic_field(case.nx, seed=seed, k0=4.0)
     if kind == "channel":
         return channel_field(case.nx, case.ny, case.nz, g.zc, seed=seed)
-    u, v, w, _ = random_state(case.nx, case.ny, case.nz, seed)
+    if kind == "duct":
+        return duct_field(case.nx, case.ny, case.nz, g.zc, case.ly, case.lz, seed=seed)
+    u, v, w, _ = random_state(case.nx, g.nys, case.nz, seed)
     if case.walls:
         w[case.nz] = 0.0
+    if case.ywalls:
+        for a in (u, v, w):
+            a[:, case.ny:] = 0.0
+        v[:, case.ny - 1] = 0.0
     return u, v, w
 
 
@@ -49,7 +55,7 @@ def mean_free(p, g):
     n = g.nz
     I = slice(1, n + 1)
     dzf = g.dzf[I]
-    m = np.sum(p[I] * dzf[:, None, None]) / (np.sum(dzf) * g.nx * g.ny)
+    m = np.sum(p[I, :g.ny] * dzf[:, None, None]) / (np.sum(dzf) * g.nx * g.ny)
     q = p.copy()
     q[I] -= m
     return q
@@ -89,11 +95,12 @@ def dsm_nut_check(case, g, st, nut, rel=1e-12):
 def poisson_condition(g):
     """Condition number lambda_max / lambda_min of the discrete Poisson operator D G of the
     grid (Sec. 2.2): lambda_max bounded by Gershgorin (4/dx^2 + 4/dy^2 + the largest z row
-    sum), lambda_min the smallest nonzero magnitude among the first x and y Fourier modes and
-    the z operator's eigenvalues (Neumann at walls, periodic otherwise)."""
+    sum), lambda_min the smallest nonzero magnitude among the first x and y modes (cosine in
+    y for ducts) and the z operator's eigenvalues (Neumann at walls, periodic otherwise)."""
     n = g.nz
     lx = (2.0 - 2.0 * np.cos(2.0 * np.pi / g.nx)) / g.dx ** 2
-    ly = (2.0 - 2.0 * np.cos(2.0 * np.pi / g.ny)) / g.dy ** 2
+    # first cosine mode with walls in y (square duct), first Fourier mode otherwise
+    ly = (2.0 - 2.0 * np.cos((1.0 if g.ywalls else 2.0) * np.pi / g.ny)) / g.dy ** 2
     A = np.zeros((n, n))
     for k in range(1, n + 1):
         lo = 1.0 / (g.dzc[k - 1] * g.dzf[k])

@@ -36,7 +36,7 @@ def _init(**kw):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(nx=30), -4), (dict(ny=1022), -4), (dict(nx=2048), -4), (dict(nz=20), -4),
+    (dict(nx=14), -4), (dict(nx=50), -4), (dict(ny=1022), -4), (dict(nx=2048), -4), (dict(nz=22), -4),
     (dict(lx=-1.0), -1), (dict(nu=0.0), -1), (dict(zbc=7), -1), (dict(sgs=9), -1),
     (dict(implicit_z=1), -4), (dict(implicit_z=3), -1), (dict(implicit_z=-1), -1),
     (dict(precision=3), -1), (dict(zbc=1, nz=3), -1),
@@ -73,6 +73,40 @@ def test_cn_in_all_directions_accepted_for_every_z_condition(zbc):
     kw = dict(zbc=zbc, nz=16) if zbc else {}
     ctx = _init(implicit_z=les.VISC_CN_3D, sgs=les.SGS_DSM, **kw)
     assert les.les_layout(ctx, les.FIELD_WORKSPACE).bytes > 0
+    les.les_free(ctx)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(ybc=1), -4),                                              # y walls need z walls
+    (dict(ybc=1, zbc=1, nz=16, implicit_z=2), -4),                  # no CN in y
+    (dict(ybc=1, zbc=1, nz=16, sgs=3), -4),                         # static models only
+    (dict(ybc=1, zbc=2, nz=16, h_wm=0.9), -1),                      # h_wm beyond the duct's middle row
+    (dict(ybc=2, zbc=1, nz=16), -1),
+])
+def test_duct_configurations_rejected(kw, status):
+    from paper_2411_09364_amd import les
+    with pytest.raises(les.LesError) as e:
+        _init(**kw)
+    assert e.value.status == status
+
+
+def test_duct_layout_has_two_ghost_rows():
+    from paper_2411_09364_amd import les
+    ctx = _init(nx=16, ny=12, nz=10, zbc=les.ZBC_WALLMODEL, ybc=les.YBC_WALL, sgs=les.SGS_SMAG_VD,
+                h_wm=0.2, implicit_z=1)
+    lay = les.les_layout(ctx, les.FIELD_U)
+    assert (lay.dims[0], lay.dims[1], lay.dims[2]) == (12, 14, 16)
+    assert lay.bytes == 12 * 14 * 16 * 8
+    assert les.les_layout(ctx, les.FIELD_TAUW).bytes == 4 * 14 * 16 * 8
+    assert les.les_layout(ctx, les.FIELD_TAUWY).bytes == 4 * 12 * 16 * 8
+    with pytest.raises(les.LesError) as e:
+        les.les_stats_reset(ctx)
+    assert e.value.status == les.LES_ENOTSUP
+    les.les_free(ctx)
+    ctx = _init()
+    with pytest.raises(les.LesError) as e:
+        les.les_layout(ctx, les.FIELD_TAUWY)
+    assert e.value.status == les.LES_EINVAL
     les.les_free(ctx)
 
 
