@@ -44,6 +44,11 @@ CONFIGS = {
     "f1": dict(name="channel 256x128x96 fp64 DSM+WM CN in x, y and z", nx=256, ny=128, nz=96,
                lx=2 * 3.141592653589793, ly=3.141592653589793, lz=2.0, zbc=2, beta=1.5, nu=5e-5, sgs=3, cs=0.17,
                implicit_z=2, precision=0, ubulk=1.0, init="channel", seed=2, dtype="f64"),
+    # square duct of Sec. 4.4 (Table duct, 512 x 80 x 80, AR = 1, SM): walls with the wall model on y and z
+    # (h_wm = 0.1 h), uniform spacing, Re_b = 40000 (nu = 5e-5), C_s = 0.18 with van Driest damping
+    "f2": dict(name="square duct 512x80x80 fp64 Smagorinsky+van Driest, WM on four walls, explicit", nx=512, ny=80,
+               nz=80, lx=12.8, ly=2.0, lz=2.0, zbc=2, beta=0.0, nu=5e-5, sgs=2, cs=0.18, implicit_z=0, precision=0,
+               ubulk=1.0, h_wm=0.1, ybc=1, init="duct", seed=7, dtype="f64"),
     "c5": dict(name="64 isotropic boxes 32^3/48^3/64^3/96^3 fp32 DSM explicit, batched", nbox=64, seed=5,
                dtype="f32"),
 }
@@ -73,14 +78,17 @@ def make_solver(cfgd):
     from paper_2411_09364_amd import les
     cfg = les.make_config(cfgd["nx"], cfgd["ny"], cfgd["nz"], cfgd["lx"], cfgd["ly"], cfgd["lz"],
                           zbc=cfgd["zbc"], beta=cfgd["beta"], nu=cfgd["nu"], sgs=cfgd["sgs"], cs=cfgd["cs"],
-                          implicit_z=cfgd["implicit_z"], precision=cfgd["precision"], ubulk=cfgd["ubulk"])
+                          implicit_z=cfgd["implicit_z"], precision=cfgd["precision"], ubulk=cfgd["ubulk"],
+                          h_wm=cfgd.get("h_wm", 0.0), ybc=cfgd.get("ybc", 0))
     return les, les.Solver(cfg)
 
 
 def initial_fields(cfgd, zc):
-    from synth import isotropic_field, channel_field
+    from synth import isotropic_field, channel_field, duct_field
     if cfgd["init"] == "iso":
         return isotropic_field(cfgd["nx"], seed=cfgd["seed"], k0=4.0)
+    if cfgd["init"] == "duct":
+        return duct_field(cfgd["nx"], cfgd["ny"], cfgd["nz"], zc, cfgd["ly"], cfgd["lz"], seed=cfgd["seed"])
     return channel_field(cfgd["nx"], cfgd["ny"], cfgd["nz"], zc, seed=cfgd["seed"])
 
 
@@ -97,7 +105,7 @@ def cpu_baseline(cfgd, budget_s):
     case = oracle.Case(cfgd["nx"], cfgd["ny"], cfgd["nz"], cfgd["lx"], cfgd["ly"], cfgd["lz"], zbc=cfgd["zbc"],
                        beta=cfgd["beta"], nu=cfgd["nu"], sgs=cfgd["sgs"], cs=cfgd["cs"],
                        implicit_z=cfgd["implicit_z"] == 1, implicit_3d=cfgd["implicit_z"] == 2,
-                       ubulk=cfgd["ubulk"])
+                       ubulk=cfgd["ubulk"], h_wm=cfgd.get("h_wm", 0.0), ybc=cfgd.get("ybc", 0))
     g = oracle.Grid(case)
     u, v, w = initial_fields(cfgd, g.zc)
     st = S.initial_state(case, g, u, v, w)
@@ -369,7 +377,7 @@ def solver_line(args, torch, cfgd):
     # per-kernel pass: same steps without the graph, every launch bracketed by HIP events
     kernels, roof = kernel_report(les, ctx, max(1, min(args.steps, 10)), cfgd["name"], cells,
                                   cfgd["precision"] == 0)
-    stats = statistics_report(les, ctx)
+    stats = statistics_report(les, ctx) if not cfgd.get("ybc") else None   # plane statistics: channels
     diag, status = solver.diag()
     out = {
         "metric": METRIC,
@@ -385,8 +393,8 @@ def solver_line(args, torch, cfgd):
         "dtype": cfgd["dtype"],
         "data": "synthetic",
         "config": {"workload": cfgd["name"], "grid": [cfgd["nx"], cfgd["ny"], cfgd["nz"]],
-                   "substeps_per_step": 3, "graph": use_graph, "closure": "dynamic Smagorinsky"
-                   if cfgd["sgs"] == 3 else "Smagorinsky"},
+                   "substeps_per_step": 3, "graph": use_graph,
+                   "closure": {3: "dynamic Smagorinsky", 2: "Smagorinsky + van Driest"}.get(cfgd["sgs"], "Smagorinsky")},
         "roofline": roof,
         "substep_roofline": substep_roofline(value, cfgd),
         "kernels": kernels,
@@ -398,7 +406,7 @@ def solver_line(args, torch, cfgd):
     solver.close()
     if args.config == "c3":
         out["precision_check"] = precision_check(les, torch, cfgd, args.compare_steps)
-    if not args.no_cpu_baseline and args.config in ("c1", "c2", "f1"):
+    if not args.no_cpu_baseline and args.config in ("c1", "c2", "f1", "f2"):
         out["cpu_baseline"] = cpu_baseline(cfgd, args.cpu_seconds)
     return out
 

@@ -148,16 +148,21 @@ __global__ void __launch_bounds__(256) k_strain_mag(GridP g, const T* __restrict
 // <tau_2>)|) per wall, each component averaged over its own points on that wall that are not
 // wall faces (z walls: rows j < ny, the v stress over j < ny - 1; y walls: planes 1..nz, the w
 // stress over faces 1..nz-1).  Stresses from the wall models, or nu times the wall-normal
-// difference across the no-slip ghosts.  One block, fixed-order sums; vd4 = (z bottom, z
-// top, y = 0, y = ly).
+// difference across the no-slip ghosts.  Stage 1: VD_BLOCKS blocks, each a fixed-order tree
+// of its strided share into 8 partials (part[b][8]); stage 2: one block sums them in block
+// order and writes vd4 = (z bottom, z top, y = 0, y = ly).
+constexpr int VD_BLOCKS = 64;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_vd_duct(GridP g, const T* u, const T* v, const T* w, const double* tau,
-                                                 const double* tauy, int wallmodel, double* vd4) {
+__global__ void __launch_bounds__(256) k_vd_duct_partial(GridP g, const T* u, const T* v, const T* w,
+                                                         const double* tau, const double* tauy, int wallmodel,
+                                                         double* part) {
   __shared__ double sm[8][256];
   double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int n = g.nz, ny = g.ny, nx = g.nx;
   const int64_t s = g.sxy, sy = (int64_t)(n + 2) * nx;
-  for (int64_t c = threadIdx.x; c < (int64_t)nx * ny; c += blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t c = t0; c < (int64_t)nx * ny; c += stride) {
     const bool vrow = c < (int64_t)nx * (ny - 1);   // v rows off the wall face y = ly
     if (wallmodel) {
       a[0] += tau[c];
@@ -175,7 +180,7 @@ __global__ void __launch_bounds__(256) k_vd_duct(GridP g, const T* u, const T* v
       }
     }
   }
-  for (int64_t e = threadIdx.x; e < (int64_t)nx * n; e += blockDim.x) {
+  for (int64_t e = t0; e < (int64_t)nx * n; e += stride) {
     const int k = (int)(e / nx) + 1, i = (int)(e % nx);
     const bool wface = k < n;   // w faces off the wall face k = nz
     if (wallmodel) {
@@ -202,13 +207,20 @@ __global__ void __launch_bounds__(256) k_vd_duct(GridP g, const T* u, const T* v
       for (int q = 0; q < 8; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double cz = (double)nx * ny, cv = (double)nx * (ny - 1), cy = (double)nx * n, cw = (double)nx * (n - 1);
-    vd4[0] = sqrt(hypot(sm[0][0] / cz, sm[1][0] / cv));
-    vd4[1] = sqrt(hypot(sm[2][0] / cz, sm[3][0] / cv));
-    vd4[2] = sqrt(hypot(sm[4][0] / cy, sm[5][0] / cw));
-    vd4[3] = sqrt(hypot(sm[6][0] / cy, sm[7][0] / cw));
-  }
+  if (threadIdx.x < 8) part[blockIdx.x * 8 + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+__global__ void k_vd_duct_final(GridP g, const double* part, double* vd4) {
+  if (threadIdx.x != 0) return;
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < VD_BLOCKS; ++b)
+    for (int q = 0; q < 8; ++q) a[q] += part[b * 8 + q];
+  const double nx = g.nx, ny = g.ny, n = g.nz;
+  const double cz = nx * ny, cv = nx * (ny - 1), cy = nx * n, cw = nx * (n - 1);
+  vd4[0] = sqrt(hypot(a[0] / cz, a[1] / cv));
+  vd4[1] = sqrt(hypot(a[2] / cz, a[3] / cv));
+  vd4[2] = sqrt(hypot(a[4] / cy, a[5] / cw));
+  vd4[3] = sqrt(hypot(a[6] / cy, a[7] / cw));
 }
 
 // van Driest coefficient: plane-mean wall stresses -> u_tau per wall -> coef[k].
@@ -1014,9 +1026,12 @@ void launch_eddy_viscosity(Ctx& c) {
   const double pts = (double)g.nx * g.ny * g.nz;
   if (model == LES_SGS_SMAG || model == LES_SGS_SMAG_VD) {
     const bool duct_vd = g.ywall && model == LES_SGS_SMAG_VD;
-    if (duct_vd)
-      LES_LAUNCH(c, "vd_duct", 0, k_vd_duct<T>, dim3(1), dim3(256), 0, g, (const T*)c.u, (const T*)c.v, (const T*)c.w,
-                 c.t.tau, c.t.tauy, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.vd4);
+    if (duct_vd) {
+      static_assert(VD_BLOCKS * 8 <= 4096, "partials fit the reduction area");
+      LES_LAUNCH(c, "vd_duct", 0, k_vd_duct_partial<T>, dim3(VD_BLOCKS), dim3(256), 0, g, (const T*)c.u,
+                 (const T*)c.v, (const T*)c.w, c.t.tau, c.t.tauy, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
+      LES_LAUNCH(c, "vd_duct_final", 0, k_vd_duct_final, dim3(1), dim3(64), 0, g, c.t.red, c.t.vd4);
+    }
     LES_LAUNCH(c, "strain_mag", 4 * pts * sizeof(T), k_strain_mag<T>, L.grid, L.block, 0, g, (const T*)c.u, (const T*)c.v,
                        (const T*)c.w, (T*)c.nut, duct_vd ? (const double*)c.t.vd4 : nullptr, c.cfg.ly);
     if (model == LES_SGS_SMAG_VD && c.cfg.zbc != LES_ZBC_PERIODIC && !g.ywall)
