@@ -83,9 +83,17 @@ def friction_velocity(tau):
 
 
 # ---------------------------------------------------------------- dynamic model
-def _filter_xy(q):
-    """Trapezoidal box filter (1/4, 1/2, 1/4) in x then y (R7, uniform weights, Sec. 2.2)."""
+def _filter_xy(q, g=None, centred_y=True):
+    """Trapezoidal box filter (1/4, 1/2, 1/4) in x then y (R7, uniform weights, Sec. 2.2).
+    With y walls (duct, R38) the y pass of a y-centred quantity uses the index-space
+    extrapolation of R9 in the ghost rows, which makes it the identity on the first and last
+    rows; a quantity on y faces (v) keeps its true wall values (zero ghost rows)."""
     q = 0.25 * xm(q) + 0.5 * q + 0.25 * xp(q)
+    if g is not None and g.ywalls and centred_y:
+        ny = g.ny
+        q = q.copy()
+        q[..., ny + 1, :] = 2.0 * q[..., 0, :] - q[..., 1, :]
+        q[..., ny, :] = 2.0 * q[..., ny - 1, :] - q[..., ny - 2, :]
     return 0.25 * ym(q) + 0.5 * q + 0.25 * yp(q)
 
 
@@ -104,9 +112,9 @@ def _pad_z_centre(case, q):
     return out
 
 
-def test_filter_centre(case, q):
+def test_filter_centre(case, q, g=None, centred_y=True):
     """3-D test filter of a z-centred quantity on the interior planes (nz, ny, nx)."""
-    qp = _pad_z_centre(case, _filter_xy(q))
+    qp = _pad_z_centre(case, _filter_xy(q, g, centred_y))
     return 0.25 * qp[:-2] + 0.5 * qp[1:-1] + 0.25 * qp[2:]
 
 
@@ -118,9 +126,9 @@ def test_filter_velocity(case, g, u, v, w):
     n = g.nz
     I = slice(1, n + 1)
     uf, vf, wf = np.zeros_like(u), np.zeros_like(v), np.zeros_like(w)
-    uf[I] = test_filter_centre(case, u[I])
-    vf[I] = test_filter_centre(case, v[I])
-    wxy = _filter_xy(w)
+    uf[I] = test_filter_centre(case, u[I], g)
+    vf[I] = test_filter_centre(case, v[I], g, centred_y=False)
+    wxy = _filter_xy(w, g)
     wf[I] = 0.25 * wxy[0:n] + 0.5 * wxy[1:n + 1] + 0.25 * wxy[2:n + 2]
     if case.zbc == ZBC_PERIODIC:
         bc.fill_velocity(case, g, uf, vf, wf)
@@ -133,6 +141,16 @@ def test_filter_velocity(case, g, u, v, w):
         else:
             uf[0], uf[n + 1] = -uf[1], -uf[n]
             vf[0], vf[n + 1] = -vf[1], -vf[n]
+    if g.ywalls:
+        # duct (R38): v~ vanishes on the y wall faces; the y ghost rows of u~ and w~ follow
+        # the strain ghost rule (odd with no-slip, extrapolated by strain_ghosts() with the
+        # wall model), after the z ghost planes
+        ny = g.ny
+        vf[:, ny - 1:] = 0.0
+        if case.zbc != ZBC_WALLMODEL:
+            for a in (uf, wf):
+                a[:, ny + 1] = -a[:, 0]
+                a[:, ny] = -a[:, ny - 1]
     return uf, vf, wf
 
 
@@ -153,7 +171,7 @@ def dynamic_coefficient(case, g, u, v, w):
     wc = 0.5 * (w[I] + w[Im])
     s = model_strain(case, g, u, v, w)
     smag = strain_magnitude(s)
-    F = lambda q: test_filter_centre(case, q)
+    F = lambda q: test_filter_centre(case, q, g)
     vel = (uc, vc, wc)
     fvel = [F(q) for q in vel]
     pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]   # order of s: 11 22 33 12 13 23
@@ -161,9 +179,7 @@ def dynamic_coefficient(case, g, u, v, w):
     st = model_strain(case, g, uf, vf, wf)
     stmag = strain_magnitude(st)
     delta2 = (g.delta() ** 2)[:, None, None]
-    alpha2 = np.full((n, 1, 1), 4.0)
-    if case.zbc != ZBC_PERIODIC:
-        alpha2[0] = alpha2[n - 1] = 4.0 ** (2.0 / 3.0)
+    alpha2 = _alpha2(case, g)
     lm = np.zeros_like(smag)
     mm = np.zeros_like(smag)
     for c, (a, b) in enumerate(pairs):
@@ -175,6 +191,11 @@ def dynamic_coefficient(case, g, u, v, w):
     if case.zbc == ZBC_PERIODIC:
         slm = np.full(n, lm.sum())
         smm = np.full(n, mm.sum())
+    elif g.ywalls:
+        slm = lm.sum(axis=2)          # duct (R38): x lines, the only homogeneous direction
+        smm = mm.sum(axis=2)
+        slm[:, g.ny:] = 0.0
+        smm[:, g.ny:] = 0.0
     else:
         slm = lm.sum(axis=(1, 2))
         smm = mm.sum(axis=(1, 2))
@@ -199,7 +220,7 @@ def coefficient_rounding_scale(case, g, u, v, w):
     wc = 0.5 * (w[I] + w[Im])
     s = model_strain(case, g, u, v, w)
     smag = strain_magnitude(s)
-    F = lambda q: test_filter_centre(case, q)
+    F = lambda q: test_filter_centre(case, q, g)
     vel = (uc, vc, wc)
     fvel = [F(q) for q in vel]
     pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
@@ -207,9 +228,7 @@ def coefficient_rounding_scale(case, g, u, v, w):
     st = model_strain(case, g, uf, vf, wf)
     stmag = strain_magnitude(st)
     delta2 = (g.delta() ** 2)[:, None, None]
-    alpha2 = np.full((n, 1, 1), 4.0)
-    if case.zbc != ZBC_PERIODIC:
-        alpha2[0] = alpha2[n - 1] = 4.0 ** (2.0 / 3.0)
+    alpha2 = _alpha2(case, g)
     a = np.zeros_like(smag)
     b = np.zeros_like(smag)
     lm = np.zeros_like(smag)
@@ -225,23 +244,44 @@ def coefficient_rounding_scale(case, g, u, v, w):
         b += wgt * 2.0 * np.abs(M) * Ma
         lm += wgt * L * M
         mm += wgt * M * M
-    ax = None if case.zbc == ZBC_PERIODIC else (1, 2)
-    sa, sb, slm, smm = (np.broadcast_to(q.sum(axis=ax), (n,)) for q in (a, b, lm, mm))
+    if g.ywalls:
+        sa, sb, slm, smm = (q.sum(axis=2) for q in (a, b, lm, mm))
+    else:
+        ax = None if case.zbc == ZBC_PERIODIC else (1, 2)
+        sa, sb, slm, smm = (np.broadcast_to(q.sum(axis=ax), (n,)) for q in (a, b, lm, mm))
     cs = np.where(smm > 0.0, np.maximum(slm / np.where(smm > 0.0, smm, 1.0), 0.0), 0.0)
     return np.where(smm > 0.0, (sa + cs * sb) / np.where(smm > 0.0, smm, 1.0), 0.0)
 
 
+def _alpha2(case, g):
+    """alpha^2 per cell (n, rows, 1): 4 for the 3-D test filter; 4^(2/3) where the filter is
+    2-D (the first off-wall layer of one wall pair, R9); 2^(2/3) where it is 1-D (a duct's
+    corner cells, first off-wall in y and z, R38)."""
+    n = g.nz
+    dims = np.full((n, g.nys, 1), 3)
+    if case.zbc != ZBC_PERIODIC:
+        dims[0] -= 1
+        dims[n - 1] -= 1
+    if g.ywalls:
+        dims[:, 0] -= 1
+        dims[:, g.ny - 1] -= 1
+    table = {3: 4.0, 2: 4.0 ** (2.0 / 3.0), 1: 2.0 ** (2.0 / 3.0)}
+    return np.vectorize(table.get)(dims).astype(np.float64)
+
+
 def dynamic_smagorinsky(case, g, u, v, w):
-    """Eq. dsmag: nu_t = c_s Delta^2 |S|.  Returns (nu_t, c_s)."""
+    """Eq. dsmag: nu_t = c_s Delta^2 |S|.  Returns (nu_t, c_s); c_s per plane, or per x line
+    (nz, ny + 2) in a duct."""
     cs, smag, _, _ = dynamic_coefficient(case, g, u, v, w)
-    return cs[:, None, None] * (g.delta() ** 2)[:, None, None] * smag, cs
+    c3 = cs[:, :, None] if cs.ndim == 2 else cs[:, None, None]
+    return c3 * (g.delta() ** 2)[:, None, None] * smag, cs
 
 
 def eddy_viscosity(case, g, u, v, w, tau=None, tauy=None):
     """nu_t on the interior planes for the configured model (SGS_NONE gives zeros).
-    With y walls (square duct) only SGS_NONE, SGS_SMAG and SGS_SMAG_VD are defined here."""
-    if g.ywalls and case.sgs not in (SGS_SMAG, SGS_SMAG_VD) and case.sgs != 0:
-        raise NotImplementedError("duct: only the static models")
+    With y walls (square duct) the learned closure is not defined here."""
+    if g.ywalls and case.sgs > SGS_DSM:
+        raise NotImplementedError("duct: the static and dynamic models")
     if case.sgs in (SGS_SMAG, SGS_SMAG_VD):
         ut = None
         if case.sgs == SGS_SMAG_VD and case.zbc != ZBC_PERIODIC:

@@ -1,4 +1,4 @@
-"""Pins of the square-duct oracle (Sec. 4.4: walls in y and z, periodic x; R35-R37).
+"""Pins of the square-duct oracle (Sec. 4.4: walls in y and z, periodic x; R35-R38).
 
 - The duct Poisson solve against the dense matrix of the oracle's own divergence and
   gradient with the Neumann ghost rows (brute force on a tiny grid) and against single
@@ -7,7 +7,9 @@
 - The discrete laminar duct flow, solved directly, is a fixed point of the substep.
 - Exchanging y and z on a square duct with uniform spacing maps a state to another state,
   and the substep commutes with that exchange: every y-wall rule must equal its z-wall
-  counterpart (ghost rows, wall model, van Driest, Poisson, forcing).
+  counterpart (ghost rows, wall model, van Driest, Poisson, forcing, and for the dynamic
+  model the test filter's wall rows, alpha at the walls and corners, and the averages along
+  x lines, whose coefficients must form a symmetric (z, y) array).
 - The y-wall model on a profile u(y) returns the log-law stress at the interpolated
   velocity, found by bisection.
 """
@@ -18,7 +20,7 @@ import pytest
 
 import oracle
 from oracle import bc, ops, poisson, substep as S
-from oracle.case import ZBC_NOSLIP, ZBC_WALLMODEL, YBC_WALL, SGS_NONE, SGS_SMAG, SGS_SMAG_VD
+from oracle.case import ZBC_NOSLIP, ZBC_WALLMODEL, YBC_WALL, SGS_NONE, SGS_SMAG, SGS_SMAG_VD, SGS_DSM
 from synth import duct_field
 
 
@@ -142,7 +144,8 @@ def _swap(g, u, v, w, p):
 
 
 @pytest.mark.parametrize("zbc,sgs,h_wm", [(ZBC_NOSLIP, SGS_SMAG_VD, 0.0), (ZBC_WALLMODEL, SGS_SMAG_VD, 0.0),
-                                          (ZBC_WALLMODEL, SGS_SMAG, 0.45)])
+                                          (ZBC_WALLMODEL, SGS_SMAG, 0.45), (ZBC_NOSLIP, SGS_DSM, 0.0),
+                                          (ZBC_WALLMODEL, SGS_DSM, 0.45)])
 def test_substep_commutes_with_exchanging_y_and_z(zbc, sgs, h_wm):
     case, g = _duct(nx=6, ny=6, nz=6, lx=2.0, ly=2.0, lz=2.0, zbc=zbc, nu=2e-3, sgs=sgs, cs=0.12,
                     ubulk=1.0, h_wm=h_wm)
@@ -164,6 +167,13 @@ def test_substep_commutes_with_exchanging_y_and_z(zbc, sgs, h_wm):
             scale = max(np.max(np.abs(b[I, J])), 1e-300)
             assert np.max(np.abs(a[I, J] - b[I, J])) < 1e-12 * max(scale, 1.0), k
         assert np.max(np.abs(st.v[:, g.ny - 1])) == 0.0
+        tn = _swap(g, st.nut, st.nut, st.nut, st.nut)[0]
+        assert np.max(np.abs(tn[I, J] - st.nut[I, J])) < 1e-12 * np.max(np.abs(st.nut[I, J])), k
+        if sgs == SGS_DSM:
+            # x-line coefficients: line (k, j) goes to line (j + 1, k - 1)
+            cs = st.cs[:, :g.ny]
+            assert cs.shape == (g.nz, g.ny) and np.max(cs) > 0.0
+            assert np.max(np.abs(cs - cs.T)) < 1e-10 * np.max(cs), k
     if zbc == ZBC_WALLMODEL:
         # the y-wall stress at (k, i) equals the z-wall stress at (j = k - 1, i)
         txb = st.tau[0][:g.ny]
