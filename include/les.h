@@ -92,8 +92,9 @@ typedef struct {
   double h_wm;          /* wall-model height; 0 = first off-wall cell centre            */
   double kappa, bconst; /* log-law constants (Eq. wm); 0 selects 0.41 and 5.2            */
   int32_t ybc;          /* LES_YBC_*.  LES_YBC_WALL (square duct, Sec. 4.4) needs wall-bounded
-                           z, explicit viscous terms or CN in z, and LES_SGS_NONE, _SMAG or
-                           _SMAG_VD; fields then carry two ghost rows in y, stored after the
+                           z, explicit viscous terms or CN in z, and a model other than the
+                           learned one (the dynamic coefficient is then averaged along x
+                           lines, the only homogeneous direction); fields then carry two ghost rows in y, stored after the
                            interior rows: dims [nz+2][ny+2][nx], row ny above y = ly, row ny+1
                            below y = 0 (where the periodic index j - 1 of row 0 lands).  v on
                            row ny - 1 is the wall face y = ly and stays zero.  Statistics,
@@ -105,7 +106,8 @@ enum {
   LES_FIELD_U = 0, LES_FIELD_V = 1, LES_FIELD_W = 2, LES_FIELD_P = 3,
   LES_FIELD_WORKSPACE = 4,  /* scratch + internal state (RK history, |S|, spectra, ...) */
   LES_FIELD_NUT = 5,        /* readable only: eddy viscosity at cell centres, field layout */
-  LES_FIELD_CS = 6,         /* readable only: per-plane model coefficient, double[nz]      */
+  LES_FIELD_CS = 6,         /* readable only: per-plane model coefficient, double[nz]
+                               (ducts: per x line, double[nz][ny])                         */
   LES_FIELD_TAUW = 7,       /* readable only: wall stress, double[4][ny'][nx] (ny' = the stored
                                rows): tau_x bottom, tau_y bottom, tau_x top, tau_y top     */
   LES_FIELD_ZGRID = 8,      /* readable only, host memory: double zf[nz+1], zc[nz+2]       */

@@ -167,7 +167,7 @@ size_t carve(Ctx& c, char* base) {
   t.dzc = (double*)take((n + 2) * 8);
   t.delta2 = (double*)take((n + 2) * 8);
   t.coef = (double*)take((n + 2) * 8);
-  t.cs = (double*)take(n * 8);
+  t.cs = (double*)take((f.ybc == LES_YBC_WALL ? (size_t)n * f.ny : n) * 8);   // per plane, or per x line
   t.pa = (double*)take(n * 8);
   t.pb = (double*)take(n * 8);
   t.pc = (double*)take(n * 8);
@@ -209,7 +209,8 @@ size_t carve(Ctx& c, char* base) {
     c.mlp_kc = chunk(768);
     c.pred_kc = chunk(512);   // z-marching predictor: two blocks per CU (FP64)
   }
-  t.dsm_part = (double*)take((size_t)2 * n * t.nblk_xy * 4 * 8);
+  // ducts: one partial per x line and x tile, [nz][ny][nx/32]
+  t.dsm_part = (double*)take(std::max((size_t)2 * n * t.nblk_xy * 4, (size_t)2 * n * f.ny * ((f.nx + 31) / 32)) * 8);
   c.ru = take(F * E);
   c.rv = take(F * E);
   c.rw = take(F * E);
@@ -318,7 +319,7 @@ les_status les_init(const les_config* cfg, void* hip_stream, les_ctx** out) {
   if (f.ybc != LES_YBC_PERIODIC && f.ybc != LES_YBC_WALL) return LES_EINVAL;
   if (f.ybc == LES_YBC_WALL) {
     // square duct: walls in z as well, no implicit y solve, the static models
-    if (f.zbc == LES_ZBC_PERIODIC || f.implicit_z == LES_VISC_CN_3D || f.sgs > LES_SGS_SMAG_VD || f.ny < 4)
+    if (f.zbc == LES_ZBC_PERIODIC || f.implicit_z == LES_VISC_CN_3D || f.sgs > LES_SGS_DSM || f.ny < 4)
       return LES_ENOTSUP;
     if (f.zbc == LES_ZBC_WALLMODEL && f.h_wm > 0.0) {
       const double dy = f.ly / f.ny;
@@ -385,7 +386,7 @@ les_status les_layout(const les_ctx* ctx, int field, les_layout_t* out) {
       out->elem_bytes = 1;
       return LES_OK;
     case LES_FIELD_CS:
-      out->bytes = 8LL * f.nz;
+      out->bytes = 8LL * f.nz * (f.ybc == LES_YBC_WALL ? f.ny : 1);
       out->elem_bytes = 8;
       return LES_OK;
     case LES_FIELD_TAUW:
@@ -441,6 +442,7 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       for (double x : c.twc) c.twc_f_host.push_back((float)x);
       c.coef_host.assign(n + 2, 0.0);
       if (f.sgs == LES_SGS_MLP && c.mlp_params != nullptr) c.coef_host = c.delta2;
+      if (f.sgs == LES_SGS_DSM && f.ybc == LES_YBC_WALL) c.coef_host = c.delta2;   // field c_s(j, k) |S|
       if (f.sgs == LES_SGS_SMAG || f.sgs == LES_SGS_SMAG_VD)
         for (int k = 0; k <= n + 1; ++k) {
           const double d = std::pow((f.lx / f.nx) * (f.ly / f.ny) * c.dzf[k], 1.0 / 3.0);
@@ -604,7 +606,9 @@ les_status les_read(les_ctx* ctx, int field, void* dst) {
       else launch_read_nut<double>(c, (double*)dst);
       return check_launch(c, "les_read");
     case LES_FIELD_CS:
-      return check_hip(c, hipMemcpyAsync(dst, c.t.cs, 8 * f.nz, hipMemcpyDeviceToDevice, c.stream), "read cs");
+      return check_hip(c, hipMemcpyAsync(dst, c.t.cs, 8 * (size_t)f.nz * (f.ybc == LES_YBC_WALL ? f.ny : 1),
+                                         hipMemcpyDeviceToDevice, c.stream),
+                       "read cs");
     case LES_FIELD_TAUW:
       return check_hip(c, hipMemcpyAsync(dst, c.t.tau, 8 * 4 * c.g.sxy, hipMemcpyDeviceToDevice, c.stream),
                        "read tau");

@@ -372,7 +372,12 @@ __device__ inline int ring3(int q) {
   return ((q % 3) + 3) % 3;
 }
 
-template <typename T>
+// YW (ducts, walls in y too): the y pass of the test filter is the identity on the first and
+// last rows for y-centred quantities (u, w and the 15 cell quantities), v~ vanishes on and
+// beyond the y wall faces, the y ghost rows of u~ and w~ follow the strain ghost rule, alpha^2
+// counts the filter's dimensions per cell, and the partial sums are per x line (one per row
+// of each wave: 32 lanes) instead of per wave.
+template <typename T, bool YW = false>
 __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP g, const T* __restrict__ u,
                                                const T* __restrict__ v, const T* __restrict__ w,
                                                T* __restrict__ nut, double* __restrict__ part, int kc,
@@ -404,6 +409,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   };
   // in-plane offsets of the thread's halo-2 load points (tiles may exceed the grid: wrap)
   int lofs[NL];
+  int lrow[NL];   // global row of the load point before the wrap (ducts)
   for (int r = 0; r < NL; ++r) {
     const int e = tid + r * NT;
     const int rx = e % RX2, ry = e / RX2;
@@ -411,6 +417,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     if (i < 0) i += g.nx;
     if (j < 0) j += g.nys;
     lofs[r] = e < N2 ? j * g.nx + i : 0;
+    lrow[r] = j0 - 2 + ry;
   }
   // velocity of one plane held in registers between its fetch and its commit to LDS, so that
   // the global loads of plane p + 2 overlap the work on plane p (strain ghost rule applied at
@@ -436,6 +443,14 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
         } else {
           ra[r] = u[bw + lofs[r]];
           rb[r] = v[bw + lofs[r]];
+        }
+        if (YW && wm && (lrow[r] == -1 || lrow[r] == g.ny)) {
+          // duct: strain ghosts of u and w on the y ghost rows, extrapolated in y
+          const int64_t o0 = bw + (lofs[r] % g.nx) + (int64_t)(lrow[r] < 0 ? 0 : g.ny - 1) * g.nx;
+          const int64_t o1 = o0 + (lrow[r] < 0 ? g.nx : -g.nx);
+          const T a0 = u[o0], a1 = u[o1], c0 = w[o0], c1 = w[o1];
+          ra[r] = a0 - (a1 - a0);
+          rc[r] = c0 - (c1 - c0);
         }
       }
     }
@@ -475,17 +490,35 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     for (int r = 0; r < NH; ++r) {
       const int e = tid + r * NT;
       if (e < N1) {
+        const int jr = j0 - 2 + hy[r];   // global row of the point
+        const bool yedge = YW && (jr == 0 || jr == g.ny - 1);
         for (int c = 0; c < 3; ++c) {
           T pl = (T)0;
           for (int dy = -1; dy <= 1; ++dy) {
             const T* rr = &vel[sl][c][(hy[r] + dy) * RX2 + hx[r]];
             const T row = W0 * rr[-1] + W1 * rr[0] + W0 * rr[1];
-            pl = pl + (dy == 0 ? W1 : W0) * row;
+            const T wy = (yedge && c != 1) ? (dy == 0 ? (T)1 : (T)0) : (dy == 0 ? W1 : W0);
+            pl = pl + wy * row;
           }
+          if (YW && c == 1 && (jr >= g.ny - 1 || jr < 0)) pl = (T)0;   // v~ on and beyond the y walls
           if (put) ut[so][c][e] = G1[r][c] + zw(q - 1, c, 2) * pl;
           G1[r][c] = G2[r][c] + zw(q, c, 1) * pl;
           G2[r][c] = zw(q + 1, c, 0) * pl;
         }
+      }
+    }
+  };
+  // ducts: the y ghost rows of u~ and w~ of plane q by the strain ghost rule (extrapolated
+  // with the wall model, odd with no-slip), from the completed rows next to them
+  auto fix_rows = [&](int q) {
+    const int sl = ring3<T>(q);
+    for (int e = tid; e < N1; e += NT) {
+      const int jr = j0 - 1 + e / RX1;
+      if (jr != -1 && jr != g.ny) continue;
+      const int d = jr < 0 ? RX1 : -RX1;   // one row inward
+      for (int c = 0; c < 3; c += 2) {
+        const T a0 = ut[sl][c][e + d];
+        ut[sl][c][e] = wm ? a0 - (ut[sl][c][e + 2 * d] - a0) : -a0;
       }
     }
   };
@@ -520,10 +553,12 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     __syncthreads();
     // x-y filter of the 15 quantities at the thread's own cell (R1 coords tx+1, ty+1)
     for (int a = 0; a < 15; ++a) qC[a] = (T)0;
+    const bool yedge = YW && (j0 + ty == 0 || j0 + ty == g.ny - 1);
 #pragma unroll 1
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
-        const T wxy = (dy == 0 ? W1 : W0) * (dx == 0 ? W1 : W0);
+        const T wy = yedge ? (dy == 0 ? (T)1 : (T)0) : (dy == 0 ? W1 : W0);
+        const T wxy = wy * (dx == 0 ? W1 : W0);
         const int e = (ty + 1 + dy) * RX1 + tx + 1 + dx;
         const T uc = qb[0][e], vc = qb[1][e], wc = qb[2][e];
         const T val[15] = {uc, vc, wc, uc * uc, vc * vc, wc * wc, uc * vc, uc * wc, vc * wc,
@@ -569,7 +604,10 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       const T stm = sqrt((T)2 * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2]) +
                          (T)4 * (st[3] * st[3] + st[4] * st[4] + st[5] * st[5]));
       const bool wall_layer = !per && (k == 1 || k == nz);
-      const T alpha2 = wall_layer ? (T)2.5198420997897464 : (T)4;
+      const bool wall_row = YW && (j == 0 || j == g.ny - 1);
+      // 3-D, 2-D or (duct corners) 1-D test filter: 4, 4^(2/3), 2^(2/3)
+      const T alpha2 = (wall_layer && wall_row) ? (T)1.5874010519681994
+                                                : ((wall_layer || wall_row) ? (T)2.5198420997897464 : (T)4);
       const T d2 = (T)g.delta2[pk];
       // z pass of the test filter, one quantity at a time
       auto Fz = [&](int a) { return W0 * lo[a] + W1 * mid[a] + W0 * hi[a]; };
@@ -582,6 +620,20 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
         lm += wgt2 * (double)L * (double)M;
         mm += wgt2 * (double)M * (double)M;
       }
+    }
+    if (YW) {
+      // x-line sums: a row of the tile is 32 lanes of one wave; partials [k][j][tile x]
+      for (int off = 16; off > 0; off >>= 1) {
+        lm += __shfl_down(lm, off, 32);
+        mm += __shfl_down(mm, off, 32);
+      }
+      const int jrow = j0 + ty;
+      if (tx == 0 && jrow < g.ny) {
+        const int64_t o = (((int64_t)(k - 1) * g.ny + jrow) * gdx + bid.x) * 2;
+        part[o] = lm;
+        part[o + 1] = mm;
+      }
+      return;
     }
     // wave sums in a fixed order (shuffle tree); the waves' partials go out per plane and
     // are summed over (tile, wave) in a fixed order by the plane reduction
@@ -619,6 +671,10 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       qB[a] = qC[a];
     }
     stage(p);
+    if (YW) {
+      fix_rows(p);
+      __syncthreads();
+    }
     const int k = p - 1;
     if (k >= kb && k <= ke) {
       if (!per && k == 1) {
@@ -639,10 +695,39 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   }
 }
 
-template <typename T>
+template <typename T, bool YW = false>
 __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
                                                    int kc, const int* gate) {
-  dsm_fused_body<T>(xcd_tile(blockIdx, gridDim), gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
+  dsm_fused_body<T, YW>(xcd_tile(blockIdx, gridDim), gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
+}
+
+// Ducts: c_s per x line (j, k) from the tile partials [k][j][tile x], summed in tile order,
+// clipped at zero (0 where <M M> = 0); one thread per line.
+__global__ void __launch_bounds__(256) k_dsm_reduce_lines(GridP g, const double* part, int ntx, double* cs) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.nz * g.ny) return;
+  double a = 0.0, b = 0.0;
+  for (int t = 0; t < ntx; ++t) {
+    a += part[((int64_t)e * ntx + t) * 2];
+    b += part[((int64_t)e * ntx + t) * 2 + 1];
+  }
+  cs[e] = b > 0.0 ? fmax(a / b, 0.0) : 0.0;
+}
+
+// Ducts: the stored field becomes c_s(j, k) |S| (the plane factor coef[k] = Delta_k^2), the
+// ghost planes taking the coefficient of their neighbour plane; one thread per stored cell
+// of the interior rows (the ghost rows are refilled afterwards).
+template <typename T>
+__global__ void __launch_bounds__(256) k_nut_lines(GridP g, T* nut, const double* cs) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nxy = (int64_t)g.nx * g.ny;
+  if (e >= (int64_t)(g.nz + 2) * nxy) return;
+  const int k = (int)(e / nxy);
+  const int64_t r = e % nxy;
+  const int j = (int)(r / g.nx);
+  const int kk = k < 1 ? 1 : (k > g.nz ? g.nz : k);
+  const int64_t c = (int64_t)k * g.sxy + r;
+  nut[c] = (T)((double)nut[c] * cs[(int64_t)(kk - 1) * g.ny + j]);
 }
 
 // Batched dynamic model (and its plane / volume reduction) over all boxes of a batch.
@@ -1049,6 +1134,18 @@ void launch_eddy_viscosity(Ctx& c) {
     }
     const int kc = c.dsm_kc;
     dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + fused::TY - 1) / fused::TY, (g.nz + kc - 1) / kc);
+    if (g.ywall) {
+      // ducts: coefficients along x lines
+      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), (k_dsm_fused<T, true>), grid, dim3(fused::TX, fused::TY), 0, g,
+                 (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.t.dsm_part, kc, (const int*)nullptr);
+      const int nl = g.nz * g.ny;
+      LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce_lines, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, g,
+                 c.t.dsm_part, (int)grid.x, c.t.cs);
+      const int64_t ns = (int64_t)(g.nz + 2) * g.nx * g.ny;
+      LES_LAUNCH(c, "nut_lines", 2.0 * ns * sizeof(T), k_nut_lines<T>, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0,
+                 g, (T*)c.nut, (const double*)c.t.cs);
+      return;
+    }
     LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, fused::TY), 0, g,
                (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.t.dsm_part, kc, gate);
     const int ntile = (int)(grid.x * grid.y) * fused::WV;

@@ -407,8 +407,10 @@ class Solver:
         return out.double().cpu().numpy()
 
     def coefficient(self):
+        """Dynamic coefficient per plane (nz,), or per x line (nz, ny) for ducts."""
         torch = self.torch
-        out = torch.empty(self.cfg.nz, dtype=torch.float64, device=self.u.device)
+        shape = (self.cfg.nz, self.cfg.ny) if self.cfg.ybc == YBC_WALL else (self.cfg.nz,)
+        out = torch.empty(shape, dtype=torch.float64, device=self.u.device)
         les_read(self.ctx, FIELD_CS, out.data_ptr())
         self.synchronize()
         return out.cpu().numpy()

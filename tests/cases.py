@@ -72,8 +72,9 @@ UNIT_ROUNDOFF = 2.0 ** -53
 
 
 def dsm_nut_check(case, g, st, nut, rel=1e-12):
-    """Compare a dynamic-model nu_t with the oracle's plane by plane: the allowed difference
-    on plane k is rel * max|nu_t| plus the propagated rounding bound of c_s(k)
+    """Compare a dynamic-model nu_t with the oracle's plane by plane (x line by x line in a
+    duct): the allowed difference on plane k is rel * max|nu_t| plus the propagated rounding
+    bound of c_s(k)
     (oracle.sgs.coefficient_rounding_scale) times Delta_k^2 max|S| on that plane.
     Returns (ok, worst ratio of difference to allowance, largest bound-only allowance
     relative to max|nu_t|)."""
@@ -85,8 +86,14 @@ def dsm_nut_check(case, g, st, nut, rel=1e-12):
     smag = strain_magnitude(sgs.model_strain(case, g, st.u, st.v, st.w))
     ref = np.max(np.abs(st.nut[I]))
     d2 = g.delta() ** 2
-    diff = np.max(np.abs(nut[I] - st.nut[I]), axis=(1, 2))
-    bound = CS_ROUNDING_K * UNIT_ROUNDOFF * scale * d2 * np.max(smag, axis=(1, 2))
+    if g.ywalls:
+        # ducts: one coefficient per x line (k, j); interior rows
+        J = slice(0, g.ny)
+        diff = np.max(np.abs(nut[I, J] - st.nut[I, J]), axis=2)
+        bound = CS_ROUNDING_K * UNIT_ROUNDOFF * scale[:, J] * d2[:, None] * np.max(smag[:, J], axis=2)
+    else:
+        diff = np.max(np.abs(nut[I] - st.nut[I]), axis=(1, 2))
+        bound = CS_ROUNDING_K * UNIT_ROUNDOFF * scale * d2 * np.max(smag, axis=(1, 2))
     allow = rel * ref + bound
     ratio = float(np.max(diff / allow))
     return ratio <= 1.0, ratio, float(np.max(bound) / ref) if ref > 0 else 0.0

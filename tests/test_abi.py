@@ -79,7 +79,7 @@ def test_cn_in_all_directions_accepted_for_every_z_condition(zbc):
 @pytest.mark.parametrize("kw,status", [
     (dict(ybc=1), -4),                                              # y walls need z walls
     (dict(ybc=1, zbc=1, nz=16, implicit_z=2), -4),                  # no CN in y
-    (dict(ybc=1, zbc=1, nz=16, sgs=3), -4),                         # static models only
+    (dict(ybc=1, zbc=1, nz=16, sgs=4), -4),                         # no learned closure
     (dict(ybc=1, zbc=2, nz=16, h_wm=0.9), -1),                      # h_wm beyond the duct's middle row
     (dict(ybc=2, zbc=1, nz=16), -1),
 ])
