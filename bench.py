@@ -49,6 +49,10 @@ CONFIGS = {
     "f2": dict(name="square duct 512x80x80 fp64 Smagorinsky+van Driest, WM on four walls, explicit", nx=512, ny=80,
                nz=80, lx=12.8, ly=2.0, lz=2.0, zbc=2, beta=0.0, nu=5e-5, sgs=2, cs=0.18, implicit_z=0, precision=0,
                ubulk=1.0, h_wm=0.1, ybc=1, init="duct", seed=7, dtype="f64"),
+    # the same duct with the dynamic model (Table duct, DSM rows): coefficients along x lines
+    "f2d": dict(name="square duct 512x80x80 fp64 dynamic Smagorinsky, WM on four walls, explicit", nx=512, ny=80,
+                nz=80, lx=12.8, ly=2.0, lz=2.0, zbc=2, beta=0.0, nu=5e-5, sgs=3, cs=0.18, implicit_z=0, precision=0,
+                ubulk=1.0, h_wm=0.1, ybc=1, init="duct", seed=7, dtype="f64"),
     "c5": dict(name="64 isotropic boxes 32^3/48^3/64^3/96^3 fp32 DSM explicit, batched", nbox=64, seed=5,
                dtype="f32"),
 }
@@ -406,7 +410,7 @@ def solver_line(args, torch, cfgd):
     solver.close()
     if args.config == "c3":
         out["precision_check"] = precision_check(les, torch, cfgd, args.compare_steps)
-    if not args.no_cpu_baseline and args.config in ("c1", "c2", "f1", "f2"):
+    if not args.no_cpu_baseline and args.config in ("c1", "c2", "f1", "f2", "f2d"):
         out["cpu_baseline"] = cpu_baseline(cfgd, args.cpu_seconds)
     return out
 
