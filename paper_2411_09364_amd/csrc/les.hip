@@ -84,6 +84,12 @@ void build_grid(Ctx& c) {
   c.dzc.assign(n + 2, 0.0);
   for (int k = 0; k <= n; ++k) c.dzc[k] = c.zc[k + 1] - c.zc[k];
   c.dzc[n + 1] = c.dzc[n];
+  c.rdzf.assign(n + 2, 0.0);
+  c.rdzc.assign(n + 2, 0.0);
+  for (int k = 0; k <= n + 1; ++k) {
+    c.rdzf[k] = 1.0 / c.dzf[k];
+    c.rdzc[k] = 1.0 / c.dzc[k];
+  }
   const double dx = f.lx / f.nx, dy = f.ly / f.ny;
   c.delta2.assign(n + 2, 0.0);
   for (int k = 0; k <= n + 1; ++k) {
@@ -166,6 +172,8 @@ size_t carve(Ctx& c, char* base) {
   t.dzf = (double*)take((n + 2) * 8);
   t.dzc = (double*)take((n + 2) * 8);
   t.delta2 = (double*)take((n + 2) * 8);
+  t.rdzf = (double*)take((n + 2) * 8);
+  t.rdzc = (double*)take((n + 2) * 8);
   t.coef = (double*)take((n + 2) * 8);
   t.cs = (double*)take((f.ybc == LES_YBC_WALL ? (size_t)n * f.ny : n) * 8);   // per plane, or per x line
   t.pa = (double*)take(n * 8);
@@ -424,6 +432,8 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       g.dzf = c.t.dzf;
       g.dzc = c.t.dzc;
       g.delta2 = c.t.delta2;
+      g.rdzf = c.t.rdzf;
+      g.rdzc = c.t.rdzc;
       const les_config& f = c.cfg;
       const int n = f.nz;
       les_status s = check_hip(c, hipMemsetAsync(ptr, 0, c.ws_bytes, c.stream), "zero workspace");
@@ -454,6 +464,8 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       if ((s = up(c.t.dzf, c.dzf.data(), (n + 2) * 8)) != LES_OK) return s;
       if ((s = up(c.t.dzc, c.dzc.data(), (n + 2) * 8)) != LES_OK) return s;
       if ((s = up(c.t.delta2, c.delta2.data(), (n + 2) * 8)) != LES_OK) return s;
+      if ((s = up(c.t.rdzf, c.rdzf.data(), (n + 2) * 8)) != LES_OK) return s;
+      if ((s = up(c.t.rdzc, c.rdzc.data(), (n + 2) * 8)) != LES_OK) return s;
       if ((s = up(c.t.coef, c.coef_host.data(), (n + 2) * 8)) != LES_OK) return s;
       if ((s = up(c.t.pa, c.pa.data(), n * 8)) != LES_OK) return s;
       if ((s = up(c.t.pb, c.pb.data(), n * 8)) != LES_OK) return s;

@@ -27,6 +27,8 @@ struct GridP {
   const double* dzf;  // [nz+2]
   const double* dzc;  // [nz+1]
   const double* delta2;  // [nz+2] filter width squared per plane (ghosts copy neighbours)
+  const double* rdzf;    // [nz+2] 1 / dzf, correctly rounded on the host (no division per wave)
+  const double* rdzc;    // [nz+2] 1 / dzc
 };
 
 __host__ __device__ inline int64_t idx3(const GridP& g, int k, int j, int i) {
@@ -123,6 +125,8 @@ struct Tables {
   double* dzf;      // nz+2
   double* dzc;      // nz+1 (padded)
   double* delta2;   // nz+2
+  double* rdzf;     // nz+2: 1 / dzf
+  double* rdzc;     // nz+2: 1 / dzc
   double* coef;     // nz+2: nu_t = coef[k] * nut_field (see les.cpp)
   double* cs;       // nz: dynamic coefficient per plane
   double* pa;       // nz: Poisson z rows (lower)
@@ -167,7 +171,7 @@ struct Ctx {
   hipStream_t stream;
   GridP g;               // device metric pointers filled at workspace bind
   // host copies of the tables
-  std::vector<double> zf, zc, dzf, dzc, delta2, pa, pb, pc, lamx, lamy, lamz;
+  std::vector<double> zf, zc, dzf, dzc, delta2, pa, pb, pc, lamx, lamy, lamz, rdzf, rdzc;
   std::vector<double> twx, twy, twz, twc;
   // host staging of uploaded tables (kept alive for the asynchronous copies)
   std::vector<float> twx_f_host, twy_f_host, twz_f_host, twc_f_host;

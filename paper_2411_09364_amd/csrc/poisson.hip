@@ -280,7 +280,7 @@ __device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, const FftPlan& P, 
           const T d = (us[c] - us[idx3(g, k, j, wrap_m(i, nx))]) * (T)g.rdx +
                       (vs[c] - ((g.ywall && j == 0) ? (T)0 : vs[idx3(g, k, wrap_m(j, g.ny), i)])) * (T)g.rdy +
                       (ws[c] - ((k == 1 && g.zbc == LES_ZBC_PERIODIC) ? ws[idx3(g, g.nz, j, i)] : ws[c - g.sxy])) *
-                          (T)(1.0 / g.dzf[k]);
+                          (T)g.rdzf[k];
           fv[r] = d * scale;
           if (bulk_part) bsum += (double)us[c] * g.dzf[k];
         } else {

@@ -69,7 +69,7 @@ template <typename T>
 __device__ inline void centre_strain(const GridP& g, const T* u, const T* v, const T* w, int k, int j, int i, T s[6]) {
   const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx), jp = wrap_p(j, g.nys), jm = wrap_m(j, g.nys);
   const T rdx = (T)g.rdx, rdy = (T)g.rdy, h = (T)0.5, q = (T)0.25;
-  const T rdzc = (T)(1.0 / g.dzc[k]), rdzcm = (T)(1.0 / g.dzc[k - 1]);
+  const T rdzc = (T)g.rdzc[k], rdzcm = (T)g.rdzc[k - 1];
 #define US(kk, jj, ii) sval_y(g, u, kk, jj, ii, true)
 #define VS(kk, jj, ii) sval(g, v, kk, jj, ii)
 #define W(kk, jj, ii) sval_y(g, w, kk, jj, ii, false)
@@ -79,7 +79,7 @@ __device__ inline void centre_strain(const GridP& g, const T* u, const T* v, con
   const T vjm_ip = VS(k, jm, ip), vjm_im = VS(k, jm, im);
   s[0] = (u0 - uim) * rdx;
   s[1] = (v0 - vjm) * rdy;
-  s[2] = (W(k, j, i) - W(k - 1, j, i)) * (T)(1.0 / g.dzf[k]);
+  s[2] = (W(k, j, i) - W(k - 1, j, i)) * (T)g.rdzf[k];
   const T e_a = h * ((ujp - u0) * rdy + (vip - v0) * rdx);           // (j, i)
   const T e_b = h * ((ujp_im - uim) * rdy + (v0 - vim) * rdx);       // (j, i-1)
   const T e_c = h * ((u0 - ujm) * rdy + (vjm_ip - vjm) * rdx);       // (j-1, i)
@@ -528,7 +528,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   auto stage = [&](int p) {
     const int pq = phys(p);
     const int sm = ring3<T>(p - 1), s0 = ring3<T>(p), sp = ring3<T>(p + 1);
-    const T rdzf = (T)(1.0 / g.dzf[pq]), rdzc = (T)(1.0 / g.dzc[pq]), rdzcm = (T)(1.0 / g.dzc[pq - 1]);
+    const T rdzf = (T)g.rdzf[pq], rdzc = (T)g.rdzc[pq], rdzcm = (T)g.rdzc[pq - 1];
     const bool own = p >= kb && p <= ke;
 #pragma unroll 1
     for (int e = tid; e < N1; e += NT) {
@@ -600,7 +600,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
         return ut[sl][c][(y + dy) * RX1 + x + dx];
       };
       T st[6];
-      strain_from<T>(A, rdx, rdy, (T)(1.0 / g.dzf[pk]), (T)(1.0 / g.dzc[pk]), (T)(1.0 / g.dzc[pk - 1]), st);
+      strain_from<T>(A, rdx, rdy, (T)g.rdzf[pk], (T)g.rdzc[pk], (T)g.rdzc[pk - 1], st);
       const T stm = sqrt((T)2 * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2]) +
                          (T)4 * (st[3] * st[3] + st[4] * st[4] + st[5] * st[5]));
       const bool wall_layer = !per && (k == 1 || k == nz);

@@ -71,10 +71,10 @@ __device__ __forceinline__ void predictor_cell(const Nb<T>& b, const GridP& g, i
 #pragma clang fp contract(on)
   const int kp = k + 1, km = k - 1;
   const T rdx = (T)g.rdx, rdy = (T)g.rdy;
-  const T rdzf = (T)(1.0 / g.dzf[k]);
-  const T rdzc = (T)(1.0 / g.dzc[k]);
-  const T rdzcm = (T)(1.0 / g.dzc[km]);
-  const T rdzfp = (T)(1.0 / g.dzf[kp]);
+  const T rdzf = (T)g.rdzf[k];
+  const T rdzc = (T)g.rdzc[k];
+  const T rdzcm = (T)g.rdzc[km];
+  const T rdzfp = (T)g.rdzf[kp];
   const T nu = (T)g.nu;
   const T h = (T)0.5, q = (T)0.25, two = (T)2;
   // ---------------- u-momentum at (i+1/2, j, k)
@@ -639,12 +639,12 @@ __device__ __forceinline__ void correct_body(dim3 bid, GridP g, const T* __restr
   const T vn = (g.ywall && j == g.ny - 1) ? (T)0 : vs[c0] - gdt * ((phy - ph) * (T)g.rdy);
   T wn;
   if (!per && k == n) wn = (T)0;
-  else wn = ws[c0] - gdt * ((phz - ph) * (T)(1.0 / g.dzc[k]));
+  else wn = ws[c0] - gdt * ((phz - ph) * (T)g.rdzc[k]);
   T pn = p[c0] + ph;
   if (implicit) {
     // Eq. p_update_imp1d (L_zz) or Eq. p_update_imp3d (full Laplacian)
     const T phm = phi[idx3(g, km, j, i)];
-    T lap = ((phz - ph) * (T)(1.0 / g.dzc[k]) - (ph - phm) * (T)(1.0 / g.dzc[k - 1])) * (T)(1.0 / g.dzf[k]);
+    T lap = ((phz - ph) * (T)g.rdzc[k] - (ph - phm) * (T)g.rdzc[k - 1]) * (T)g.rdzf[k];
     if (implicit == 2) {
       const T phxm = phi[idx3(g, k, j, wrap_m(i, g.nx))], phym = phi[idx3(g, k, wrap_m(j, g.nys), i)];
       lap = (phx - (T)2 * ph + phxm) * (T)(g.rdx * g.rdx) + (phy - (T)2 * ph + phym) * (T)(g.rdy * g.rdy) + lap;
