@@ -10,6 +10,9 @@
   channel 1024 x 512 x 256 mixed precision: one step, properties that hold at any size
       (divergence at float32 level, flow rate, finite state) and the FP64 library run of the
       same step within 1e-5 (the FP64 path is oracle-checked above and at small sizes);
+  square duct 512 x 80 x 80 FP64 (the paper's Table duct mesh, wall model on four walls,
+      Smagorinsky with van Driest damping, and the dynamic model with x-line averages): one
+      full step against the oracle element by element, ghost rows included;
   64-box ensemble (32^3 .. 96^3, FP32): one batched step replayed from the graph, a sample of
       two boxes of every size against the oracle within the mixed tolerance;
   degenerate states: fluid at rest stays at rest with a zero dynamic coefficient, a uniform
@@ -19,7 +22,7 @@ import numpy as np
 import pytest
 
 from oracle import substep as S, ops as OO
-from oracle.case import ZBC_PERIODIC, ZBC_WALLMODEL, SGS_DSM
+from oracle.case import ZBC_PERIODIC, ZBC_WALLMODEL, SGS_DSM, SGS_SMAG_VD, YBC_WALL
 from synth import box_ensemble, isotropic_field
 from tests.cases import (make_pair, initial_fields, rel_err, mean_free, say, dsm_nut_check, round32,
                          pressure_tolerance)
@@ -28,6 +31,10 @@ pytestmark = pytest.mark.gpu
 TWO_PI = 2 * np.pi
 CHANNEL = dict(nx=256, ny=128, nz=96, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=5e-5,
                sgs=SGS_DSM, cs=0.17, implicit_z=True, ubulk=1.0)
+
+
+DUCT = dict(nx=512, ny=80, nz=80, lx=12.8, ly=2.0, lz=2.0, zbc=ZBC_WALLMODEL, beta=0.0, nu=5e-5, cs=0.18,
+            ubulk=1.0, h_wm=0.1, ybc=YBC_WALL)
 
 
 @pytest.fixture(scope="module")
@@ -215,4 +222,42 @@ def test_degenerate_states(les, kind):
     assert np.max(np.abs(gw[I] - w[I])) < 1e-14
     assert np.all(solver.coefficient() == 0.0)
     assert np.max(np.abs(solver.eddy_viscosity()[I])) == 0.0
+    solver.close()
+
+
+@pytest.mark.parametrize("sgs", [SGS_SMAG_VD, SGS_DSM], ids=["smag-vd", "dsm"])
+def test_duct_full_size_step_matches_oracle(les, sgs):
+    say("full-size duct step 512x80x80, sgs", sgs)
+    case, g, cfg = make_pair(sgs=sgs, **DUCT)
+    u, v, w = initial_fields(case, g, 7, "duct")
+    st = S.initial_state(case, g, u, v, w)
+    dt = S.time_step(case, g, st, cfl=0.5)
+    solver = les.Solver(cfg)
+    solver.set_state(u, v, w)
+    solver.nut()
+    solver.set_dt(dt)
+    les.les_step(solver.ctx, True)   # graph replay of the three substeps
+    for k in range(3):
+        st = S.substep(case, g, st, k, dt)
+    I, J = slice(1, g.nz + 1), slice(0, g.ny)
+    gu, gv, gw, gp = solver.fields()
+    errs = dict(u=rel_err(gu, st.u, I), v=rel_err(gv, st.v, I), w=rel_err(gw, st.w, I),
+                p=np.max(np.abs(mean_free(gp, g)[I, J] - mean_free(st.p, g)[I, J])) / np.max(np.abs(mean_free(st.p, g)[I, J])))
+    tz, ty = solver.wall_stress(), solver.wall_stress_y()
+    errs["tau"] = max(max(rel_err(tz[q], st.tau[q], slice(None)) for q in range(4)),
+                      max(rel_err(ty[q], st.tauy[q], slice(None)) for q in range(4)))
+    nut = solver.eddy_viscosity()
+    if sgs == SGS_DSM:
+        ok, ratio, bnd = dsm_nut_check(case, g, st, nut)
+        say(f"  nu_t vs allowance: worst ratio {ratio:.3f} (c_s rounding bound {bnd:.2e})")
+        assert ok
+    else:
+        errs["nut"] = rel_err(nut, st.nut, I)
+    ptol = pressure_tolerance(g)
+    say("  " + " ".join(f"{a}={b:.2e}" for a, b in errs.items()) + f" (p tolerance {ptol:.1e})")
+    for a, e in errs.items():
+        assert e < (ptol if a == "p" else 1e-12), (a, e)
+    d, status = solver.diag()
+    assert status == 0 and d.nonfinite == 0
+    assert abs(d.ubulk - 1.0) < 1e-13 and d.max_div < 1e-10
     solver.close()
