@@ -308,8 +308,11 @@ def traffic_entry(kernel, launches_bytes, workload):
         return None
     try:
         data = json.load(open(path))
+        # entries are keyed by kernel (the default channel) or by "kernel @ workload"
         ent = data.get(kernel)
         if not ent or ent.get("workload", CONFIGS["c2"]["name"]) != workload:
+            ent = data.get(f"{kernel} @ {workload}")
+        if not ent or ent.get("workload") != workload:
             return None
         src = os.path.join(ROOT, "paper_2411_09364_amd", "csrc", ent["source"])
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()

@@ -177,3 +177,27 @@ def test_duct_mixed_precision(les, name, cfgd, kind):
         for a, e in errs.items():
             assert e < 1e-5, (k, a, e)
     solver.close()
+
+
+@pytest.mark.parametrize("zbc,sgs", [(ZBC_NOSLIP, SGS_DSM), (ZBC_WALLMODEL, SGS_SMAG_VD)], ids=["noslip dsm", "wm vd"])
+def test_duct_fluid_at_rest_stays_at_rest(les, zbc, sgs):
+    """Degenerate case: no flow, no forcing.  Every stress, coefficient and pressure stays
+    exactly zero (the wall models' Newton returns u_tau = 0 at U = 0, the dynamic model's
+    <M M> = 0 gives c_s = 0)."""
+    say("duct at rest", zbc, sgs)
+    case, g, cfg = make_pair(nx=16, ny=12, nz=10, lx=3.2, ly=2.0, lz=2.0, zbc=zbc, nu=1e-3, sgs=sgs, ybc=YBC_WALL)
+    solver = les.Solver(cfg)
+    z = np.zeros((g.nz + 2, g.nys, g.nx))
+    solver.set_state(z, z, z)
+    solver.nut()
+    solver.set_dt(1e-2)
+    for k in range(3):
+        solver.substep(k)
+    for a in solver.fields():
+        assert np.all(a == 0.0)
+    assert np.all(solver.eddy_viscosity() == 0.0)
+    if zbc == ZBC_WALLMODEL:
+        assert np.all(solver.wall_stress() == 0.0) and np.all(solver.wall_stress_y() == 0.0)
+    if sgs == SGS_DSM:
+        assert np.all(solver.coefficient() == 0.0)
+    solver.close()
