@@ -740,6 +740,7 @@ les_status les_mlp_sample(les_ctx* ctx, uint64_t seed, int64_t n, float* x, floa
   if (s != LES_OK) return s;
   if (c.cfg.sgs != LES_SGS_DSM && c.cfg.sgs != LES_SGS_MLP)
     return fail(&c, LES_ESTATE, "sampling needs the dynamic-model coefficient (sgs = DSM)");
+  if (c.g.ywall) return fail(&c, LES_ENOTSUP, "the learned closure's features are defined for channels only");
   if (n <= 0 || !x || !y) return fail(&c, LES_EINVAL, "bad sample buffers");
   if (c.cfg.precision == LES_MIXED) launch_mlp_sample<float>(c, seed, n, x, y);
   else launch_mlp_sample<double>(c, seed, n, x, y);
