@@ -21,6 +21,13 @@ Readings (the paper names the quantities, not their discrete form):
   R34  Eq. error integrates over y/h in [0.1, 1]; the profiles are known at their own points,
        so phi - phi_ref and phi_ref are taken piecewise linear between those points and the
        integrals are exact for that interpolant, clipped to [z0, z1].
+  R39  Square duct (Sec. 4.4): x is the only homogeneous direction, so the sums run along x
+       lines and the profiles are (z, y) cross-sections; the products sit on the same edges as
+       in R32, and a covariance subtracts the product of the means of its two edge factors
+       (the two-point means of the neighbouring lines' means).  tau_w is the perimeter mean
+       of the streamwise wall stress: each wall's mean (over x and its own direction, the y
+       walls weighted by dzf) weighted by the wall's length in the cross-section; u_b is the
+       area mean of U; h = L_z / 2 (half the side of the square).
 """
 import numpy as np
 
@@ -51,6 +58,42 @@ def plane_sums(case, g, st):
     return out
 
 
+def line_sums(case, g, st):
+    """Duct (R39): sums over i of the quantities of R32, array [11][nz][ny] (row order
+    QUANTITIES); line (k, j) is interior plane k + 1 (for w, uw, vw: face k + 1), row j."""
+    n, ny = g.nz, g.ny
+    out = np.zeros((len(QUANTITIES), n, ny))
+    for kk in range(1, n + 1):
+        u, v, w = st.u[kk], st.v[kk], st.w[kk]
+        u_up, v_up = st.u[kk + 1], st.v[kk + 1]
+        u_xy = 0.5 * (u + np.roll(u, -1, axis=0))      # row j + 1 of the stored rows (ghost at the top)
+        v_xy = 0.5 * (v + np.roll(v, -1, axis=1))
+        u_xz = 0.5 * (u + u_up)
+        w_xz = 0.5 * (w + np.roll(w, -1, axis=1))
+        v_yz = 0.5 * (v + v_up)
+        w_yz = 0.5 * (w + np.roll(w, -1, axis=0))
+        vals = (u, v, w, st.p[kk], st.nut[kk], u * u, v * v, w * w, u_xy * v_xy, u_xz * w_xz, v_yz * w_yz)
+        for q, a in enumerate(vals):
+            out[q, kk - 1] = np.sum(a[:ny], axis=1)
+    return out
+
+
+def perimeter_wall_stress(case, g, st):
+    """Duct (R39): perimeter mean of the streamwise wall stress of one state."""
+    n, ny = g.nz, g.ny
+    if case.zbc == ZBC_WALLMODEL:
+        txb, _, txt, _ = st.tau
+        txl, _, txh, _ = st.tauy
+    else:
+        txb, _, txt, _ = bc.noslip_wall_stress(case, g, st.u, st.v)
+        txl, _, txh, _ = bc.noslip_wall_stress_y(case, g, st.u, st.w)
+    dzf = g.dzf[1:n + 1][:, None]
+    zb, zt = float(np.mean(txb[:ny])), float(np.mean(txt[:ny]))
+    yl = float(np.sum(txl[1:n + 1] * dzf) / (g.nx * g.lz))
+    yh = float(np.sum(txh[1:n + 1] * dzf) / (g.nx * g.lz))
+    return (g.ly * (zb + zt) + g.lz * (yl + yh)) / (2.0 * (g.ly + g.lz))
+
+
 def wall_stress_sample(case, g, st):
     """Plane means of the streamwise wall stress at the bottom and top walls (R32): the wall
     model's stress, or nu du/dz from the no-slip ghosts; (0, 0) with periodic z."""
@@ -68,12 +111,17 @@ class Accumulator:
 
     def __init__(self, g):
         self.samples = 0
-        self.sums = np.zeros((len(QUANTITIES), g.nz))
+        self.sums = np.zeros((len(QUANTITIES), g.nz, g.ny) if g.ywalls else (len(QUANTITIES), g.nz))
         self.series = []
 
     def add(self, case, g, st):
-        self.sums += plane_sums(case, g, st)
-        self.series.append(wall_stress_sample(case, g, st))
+        if g.ywalls:
+            self.sums += line_sums(case, g, st)
+            t = perimeter_wall_stress(case, g, st)
+            self.series.append((t, t))
+        else:
+            self.sums += plane_sums(case, g, st)
+            self.series.append(wall_stress_sample(case, g, st))
         self.samples += 1
 
 
@@ -90,7 +138,10 @@ def batch_means_sigma(x, nb):
 
 def finalize(case, g, acc, nb=8):
     """Profiles (dict of the means U, V, W, P, NUT and covariances uu, vv, ww, uv, uw, vw, each
-    [nz]) and scalars (dict: samples, tau_w, u_tau, re_tau, u_b, c_f, c_f_sigma)."""
+    [nz]; [nz][ny] cross-sections for a duct) and scalars (dict: samples, tau_w, u_tau, re_tau,
+    u_b, c_f, c_f_sigma)."""
+    if g.ywalls:
+        return _finalize_duct(case, g, acc, nb)
     n = g.nz
     N = acc.samples * g.nx * g.ny
     m = {q: acc.sums[i] / N for i, q in enumerate(QUANTITIES)}
@@ -106,6 +157,35 @@ def finalize(case, g, acc, nb=8):
             "vw": m["vw"] - 0.5 * (V + Vup) * W}
     dzf = g.dzf[1:n + 1]
     u_b = float(np.sum(U * dzf) / np.sum(dzf))
+    ser = np.array(acc.series) if acc.series else np.zeros((0, 2))
+    tw_series = 0.5 * (ser[:, 0] + ser[:, 1]) if len(ser) else np.zeros(0)
+    tau_w = float(np.mean(tw_series)) if len(tw_series) else 0.0
+    u_tau = float(np.sqrt(max(tau_w, 0.0)))
+    h = 0.5 * case.lz
+    sc = {"samples": acc.samples, "tau_w": tau_w, "u_tau": u_tau, "re_tau": u_tau * h / case.nu, "u_b": u_b,
+          "c_f": 2.0 * tau_w / (u_b * u_b) if u_b != 0.0 else float("nan"),
+          "c_f_sigma": 2.0 * batch_means_sigma(tw_series, nb) / (u_b * u_b) if u_b != 0.0 else float("nan")}
+    return prof, sc
+
+
+def _finalize_duct(case, g, acc, nb):
+    """R39: cross-section profiles and perimeter-averaged wall quantities of a duct."""
+    n, ny = g.nz, g.ny
+    N = acc.samples * g.nx
+    m = {q: acc.sums[i] / N for i, q in enumerate(QUANTITIES)}
+    U, V, W = m["u"], m["v"], m["w"]
+    # neighbour lines' means (row j + 1, plane k + 1); beyond the last row or plane the factor
+    # they multiply is zero (v on the y wall face, w on the z wall face), any value will do
+    Ujp = np.concatenate([U[:, 1:], U[:, -1:]], axis=1)
+    Ukp = np.concatenate([U[1:], U[-1:]], axis=0)
+    Vkp = np.concatenate([V[1:], V[-1:]], axis=0)
+    Wjp = np.concatenate([W[:, 1:], W[:, -1:]], axis=1)
+    prof = {"U": U, "V": V, "W": W, "P": m["p"], "NUT": m["nut"],
+            "uu": m["uu"] - U * U, "vv": m["vv"] - V * V, "ww": m["ww"] - W * W,
+            "uv": m["uv"] - 0.5 * (U + Ujp) * V, "uw": m["uw"] - 0.5 * (U + Ukp) * W,
+            "vw": m["vw"] - 0.5 * (V + Vkp) * 0.5 * (W + Wjp)}
+    dzf = g.dzf[1:n + 1][:, None]
+    u_b = float(np.sum(U * dzf) / (ny * np.sum(dzf)))
     ser = np.array(acc.series) if acc.series else np.zeros((0, 2))
     tw_series = 0.5 * (ser[:, 0] + ser[:, 1]) if len(ser) else np.zeros(0)
     tau_w = float(np.mean(tw_series)) if len(tw_series) else 0.0

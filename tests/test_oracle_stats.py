@@ -125,3 +125,63 @@ def test_profile_error_linear_difference():
 
 def test_eps_f():
     assert ST.eps_f(0.0060, 0.0050) == pytest.approx(0.2, abs=1e-15)
+
+
+def test_duct_laminar_perimeter_stress_balances_the_driving_gradient():
+    """R39: for the discrete laminar duct flow nu (L_yy + L_zz) u = -G (solved directly, no-slip)
+    the wall fluxes telescope: the perimeter-mean wall stress times the perimeter equals
+    G times the cross-section area, tau_w = G ly lz / (2 (ly + lz)), to roundoff; u_b is the
+    area mean, so C_f = 2 tau_w / u_b^2."""
+    from oracle.case import YBC_WALL
+    from tests.test_oracle_duct import _laminar_duct
+    G = 0.7
+    case = Case(4, 8, 6, 1.0, 2.0, 1.5, zbc=ZBC_NOSLIP, ybc=YBC_WALL, beta=1.2, nu=0.05)
+    g = Grid(case)
+    prof = _laminar_duct(case, g, G)
+    u = np.zeros((g.nz + 2, g.nys, g.nx))
+    u[1:g.nz + 1, :g.ny] = prof[:, :, None]
+    v, w = np.zeros_like(u), np.zeros_like(u)
+    from oracle import bc
+    bc.fill_velocity(case, g, u, v, w)
+    acc = ST.Accumulator(g)
+    for _ in range(3):
+        acc.add(case, g, _state(g, u, v, w))
+    prof_out, sc = ST.finalize(case, g, acc)
+    tau = G * case.ly * case.lz / (2.0 * (case.ly + case.lz))
+    assert abs(sc["tau_w"] - tau) < 1e-13 * tau
+    dzf = g.dzf[1:g.nz + 1]
+    ub = np.sum(prof * dzf[:, None]) / (g.ny * np.sum(dzf))
+    assert abs(sc["u_b"] - ub) < 1e-14 * ub
+    assert abs(sc["c_f"] - 2.0 * tau / ub ** 2) < 1e-13 * sc["c_f"]
+    assert np.allclose(prof_out["U"], prof, rtol=0, atol=1e-14)
+    for q in ("uu", "vv", "ww", "uv", "uw", "vw"):   # steady: no fluctuations (cancellation of U^2)
+        assert np.max(np.abs(prof_out[q])) < 1e-14 * np.max(prof) ** 2, q
+
+
+def test_duct_streamwise_fluctuation_closed_forms():
+    """R39: u = U(k, j) + a sin(2 pi x / Lx), w = b sin(2 pi x / Lx) on their points:
+    <u'u'> = a^2/2 and <w'w'> = b^2/2 on every line, <u'w'> = a b cos(pi / nx) / 2 on the
+    interior (x, z) edges, and the cross-section means are the line means."""
+    from oracle.case import YBC_WALL
+    nx, ny, nz = 12, 6, 5
+    case = Case(nx, ny, nz, 1.0, 2.0, 2.0, zbc=ZBC_NOSLIP, ybc=YBC_WALL)
+    g = Grid(case)
+    a, b = 0.3, 0.2
+    xu = (np.arange(nx) + 1.0) / nx
+    xw = (np.arange(nx) + 0.5) / nx
+    rng = np.random.default_rng(4)
+    Ucs = rng.uniform(0.5, 1.5, (nz, ny))
+    u = np.zeros((nz + 2, g.nys, nx))
+    w = np.zeros_like(u)
+    u[1:nz + 1, :ny] = Ucs[:, :, None] + a * np.sin(2 * np.pi * xu)[None, None, :]
+    w[1:nz, :ny] = b * np.sin(2 * np.pi * xw)[None, None, :]
+    v = np.zeros_like(u)
+    acc = ST.Accumulator(g)
+    acc.add(case, g, _state(g, u, v, w))
+    prof, _ = ST.finalize(case, g, acc)
+    assert np.allclose(prof["U"], Ucs, rtol=0, atol=1e-14)
+    assert np.allclose(prof["uu"], a * a / 2, rtol=0, atol=1e-14)
+    assert np.allclose(prof["ww"][:nz - 1], b * b / 2, rtol=0, atol=1e-14)
+    assert np.allclose(prof["ww"][nz - 1], 0.0, atol=1e-15)
+    assert np.allclose(prof["uw"][:nz - 1], a * b * np.cos(np.pi / nx) / 2, rtol=0, atol=1e-14)
+    assert np.allclose(prof["uv"], 0.0, atol=1e-15) and np.allclose(prof["vw"], 0.0, atol=1e-15)
