@@ -97,8 +97,8 @@ typedef struct {
                            lines, the only homogeneous direction); fields then carry two ghost rows in y, stored after the
                            interior rows: dims [nz+2][ny+2][nx], row ny above y = ly, row ny+1
                            below y = 0 (where the periodic index j - 1 of row 0 lands).  v on
-                           row ny - 1 is the wall face y = ly and stays zero.  Statistics,
-                           the learned closure and batches are not available for ducts. */
+                           row ny - 1 is the wall face y = ly and stays zero.  The learned
+                           closure and batches are not available for ducts. */
 } les_config;
 
 /* Bindable and readable buffers. */
@@ -221,7 +221,12 @@ les_status les_stats_reset(les_ctx* ctx);
 /* Add the current state as one sample (enqueued; two kernels). */
 les_status les_stats_sample(les_ctx* ctx);
 /* Synchronise, copy the sums to the host and finalise: out, and when profiles is not NULL
- * the host array profiles[LES_STATS_NPROF][nz] (rows LES_STAT_*). */
+ * the host array profiles[LES_STATS_NPROF][nz] (rows LES_STAT_*).
+ * Ducts (Sec. 4.4): the sums run along x lines, so profiles is [LES_STATS_NPROF][nz][ny]
+ * (cross-sections); a covariance subtracts the product of the two edge factors' means, each
+ * the two-point mean of the neighbouring lines' means; tau_w is the perimeter mean of the
+ * streamwise wall stress (each wall's mean, the y walls' weighted by dzf, weighted by the
+ * wall's length); u_b the area mean of U; Re_tau uses h = lz / 2. */
 les_status les_stats_read(les_ctx* ctx, int32_t nbatch, les_stats_t* out, double* profiles);
 /* Host only.  Relative profile error of Eq. error over [z0, z1]: phi and ref known at the n
  * increasing points z, both taken piecewise linear between them; the integrals are exact for

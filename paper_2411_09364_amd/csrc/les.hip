@@ -234,7 +234,7 @@ size_t carve(Ctx& c, char* base) {
   // factor pairs of the z systems of every (l, m) column with its own factors (walls only)
   t.pfac = (double*)take(f.zbc == LES_ZBC_PERIODIC ? 0 : nxp * factor_modes(c.g) * n * 2 * 8);
   // long-run statistics: running sums and series, per-sample partials
-  t.stats = (double*)take(8 * stats_words(n));
+  t.stats = (double*)take(8 * stats_words(c.g));
   t.stats_part = (double*)take(8 * stats_part_words(n, (int64_t)f.nx * f.ny));
   // per-substep factor pairs of the Helmholtz z systems (CN in all directions, walls)
   t.hfac3 = (double2*)take(f.zbc != LES_ZBC_PERIODIC && f.implicit_z == LES_VISC_CN_3D
@@ -636,7 +636,6 @@ les_status les_read(les_ctx* ctx, int field, void* dst) {
 les_status les_stats_reset(les_ctx* ctx) {
   if (!ctx) return LES_EINVAL;
   Ctx& c = ctx->c;
-  if (c.g.ywall) return fail(&c, LES_ENOTSUP, "plane statistics are defined for channels only");
   if (!c.ws) return fail(&c, LES_ESTATE, "workspace not bound");
   launch_stats_reset(c);
   return check_launch(c, "les_stats_reset");
@@ -645,7 +644,6 @@ les_status les_stats_reset(les_ctx* ctx) {
 les_status les_stats_sample(les_ctx* ctx) {
   if (!ctx) return LES_EINVAL;
   Ctx& c = ctx->c;
-  if (c.g.ywall) return fail(&c, LES_ENOTSUP, "plane statistics are defined for channels only");
   les_status s = ready(c, false);
   if (s != LES_OK) return s;
   if (c.cfg.precision == LES_MIXED) launch_stats_sample<float>(c);
@@ -656,9 +654,8 @@ les_status les_stats_sample(les_ctx* ctx) {
 les_status les_stats_read(les_ctx* ctx, int32_t nbatch, les_stats_t* out, double* profiles) {
   if (!ctx || !out) return LES_EINVAL;
   Ctx& c = ctx->c;
-  if (c.g.ywall) return fail(&c, LES_ENOTSUP, "plane statistics are defined for channels only");
   if (!c.ws) return fail(&c, LES_ESTATE, "workspace not bound");
-  std::vector<double> host((size_t)stats_words(c.cfg.nz));
+  std::vector<double> host((size_t)stats_words(c.g));
   les_status s = check_hip(c, hipMemcpyAsync(host.data(), c.t.stats, host.size() * 8, hipMemcpyDeviceToHost, c.stream),
                            "read statistics");
   if (s != LES_OK) return s;

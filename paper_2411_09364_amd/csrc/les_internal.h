@@ -244,7 +244,7 @@ void launch_mlp_adam(hipStream_t st, float* P, const float* g, float* m, float* 
 void launch_mlp_normalize(hipStream_t st, const float* xr, int64_t n, const double* lo, const double* hi, float* x);
 void launch_set_dt(Ctx& c, double dt);
 int stats_blocks(int64_t sxy);
-int64_t stats_words(int nz);
+int64_t stats_words(const GridP& g);
 int64_t stats_part_words(int nz, int64_t sxy);
 void launch_stats_reset(Ctx& c);
 template <typename T> void launch_stats_sample(Ctx& c);

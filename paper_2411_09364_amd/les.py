@@ -456,9 +456,11 @@ class Solver:
         les_stats_sample(self.ctx)
 
     def stats(self, nbatch=8):
-        """(scalars dict, profiles dict of host arrays [nz]) of the accumulated statistics."""
+        """(scalars dict, profiles dict of host arrays [nz], or [nz][ny] cross-sections for
+        ducts) of the accumulated statistics."""
         import numpy as np
-        prof = np.zeros((STATS_NPROF, self.cfg.nz))
+        shape = (STATS_NPROF, self.cfg.nz, self.cfg.ny) if self.cfg.ybc == YBC_WALL else (STATS_NPROF, self.cfg.nz)
+        prof = np.zeros(shape)
         out = les_stats_read(self.ctx, nbatch, prof.ctypes.data)
         sc = {f: getattr(out, f) for f, _ in LesStats._fields_}
         return sc, {name: prof[q] for q, name in enumerate(STAT_NAMES)}

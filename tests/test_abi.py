@@ -99,9 +99,6 @@ def test_duct_layout_has_two_ghost_rows():
     assert lay.bytes == 12 * 14 * 16 * 8
     assert les.les_layout(ctx, les.FIELD_TAUW).bytes == 4 * 14 * 16 * 8
     assert les.les_layout(ctx, les.FIELD_TAUWY).bytes == 4 * 12 * 16 * 8
-    with pytest.raises(les.LesError) as e:
-        les.les_stats_reset(ctx)
-    assert e.value.status == les.LES_ENOTSUP
     les.les_free(ctx)
     ctx = _init()
     with pytest.raises(les.LesError) as e:

@@ -1,4 +1,5 @@
-"""GPU statistics (Secs. 4.2 and 4.3 channel statistics) against the oracle.  The device plane sums of
+"""GPU statistics (Secs. 4.2 and 4.3 channel statistics; the square duct of Sec. 4.4 with x-line
+sums and the perimeter-mean wall stress) against the oracle.  The device plane sums of
 each sample equal the oracle's sums of the same fields read back, and the whole pipeline
 (substeps, samples, finalisation) equals the oracle's own run.  Sums of the same terms in
 another order differ by rounding of the order eps log2(terms) times the sum of |term|, so
@@ -9,7 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import substep as S, stats as ST
-from oracle.case import ZBC_NOSLIP, ZBC_WALLMODEL, ZBC_PERIODIC, SGS_SMAG_VD, SGS_SMAG, SGS_DSM
+from oracle.case import ZBC_NOSLIP, ZBC_WALLMODEL, ZBC_PERIODIC, SGS_SMAG_VD, SGS_SMAG, SGS_DSM, YBC_WALL
 from oracle.substep import State
 from tests.cases import make_pair, initial_fields, say, round32
 
@@ -30,13 +31,15 @@ def les():
 def _gpu_state(solver, case):
     u, v, w, p = solver.fields()
     tau = tuple(solver.wall_stress()) if case.zbc == ZBC_WALLMODEL else None
-    return State(u, v, w, p, nut=solver.eddy_viscosity(), tau=tau)
+    tauy = tuple(solver.wall_stress_y()) if case.zbc == ZBC_WALLMODEL and case.ywalls else None
+    return State(u, v, w, p, nut=solver.eddy_viscosity(), tau=tau, tauy=tauy)
 
 
 def _abs_state(st):
     """Absolute values of a state: its plane sums bound the sums of |term| of every quantity
     (|(a + b)/2| <= (|a| + |b|)/2), the scale of the rounding error of a plane sum."""
-    return State(np.abs(st.u), np.abs(st.v), np.abs(st.w), np.abs(st.p), nut=np.abs(st.nut), tau=st.tau)
+    return State(np.abs(st.u), np.abs(st.v), np.abs(st.w), np.abs(st.p), nut=np.abs(st.nut), tau=st.tau,
+                 tauy=st.tauy)
 
 
 def _compare(prof, sc, oprof, osc, absprof, tol):
@@ -69,7 +72,7 @@ def _abs_profiles(case, g, states):
     acc = ST.Accumulator(g)
     for st in states:
         acc.add(case, g, _abs_state(st))
-    N = acc.samples * g.nx * g.ny
+    N = acc.samples * g.nx * (1 if g.ywalls else g.ny)   # x lines in a duct, planes otherwise
     names = ("U", "V", "W", "P", "NUT", "uu", "vv", "ww", "uv", "uw", "vw")
     return {nm: acc.sums[q] / N for q, nm in enumerate(names)}
 
@@ -82,6 +85,13 @@ CASES = [
     ("periodic smag", dict(nx=24, ny=24, nz=24, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, nu=1e-3, sgs=SGS_SMAG), "iso", 0),
     ("mixed wm dsm", dict(nx=48, ny=24, nz=20, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=5e-5,
                           sgs=SGS_DSM, ubulk=1.0), "channel", 1),
+    # square duct: x-line sums (cross-section profiles), perimeter-mean wall stress
+    ("duct wm dsm", dict(nx=40, ny=20, nz=12, lx=4.0, ly=2.0, lz=2.0, zbc=ZBC_WALLMODEL, nu=1e-4, sgs=SGS_DSM,
+                         ubulk=1.0, ybc=YBC_WALL, h_wm=0.3), "duct", 0),
+    ("duct noslip vd stretched", dict(nx=16, ny=12, nz=10, lx=3.2, ly=2.0, lz=2.0, zbc=ZBC_NOSLIP, beta=1.3,
+                                      nu=2e-3, sgs=SGS_SMAG_VD, cs=0.12, ubulk=1.0, ybc=YBC_WALL), "duct", 0),
+    ("mixed duct wm vd", dict(nx=40, ny=20, nz=12, lx=4.0, ly=2.0, lz=2.0, zbc=ZBC_WALLMODEL, nu=1e-4,
+                              sgs=SGS_SMAG_VD, cs=0.1, ubulk=1.0, ybc=YBC_WALL), "duct", 1),
 ]
 
 
