@@ -238,8 +238,9 @@ def statistics_report(les, ctx, nsamples=20):
     rep = les.les_timing_report(ctx)
     les.les_stats_reset(ctx)
     p, f = rep["stats_partial"], rep["stats_final"]
+    wall_ms = rep["stats_wall"]["ms"] if "stats_wall" in rep else 0.0   # ducts: the four walls' stresses
     gbps = p["bytes"] / (p["ms"] * 1e-3) / 1e9
-    return {"sample_us": round(1e3 * (p["ms"] + f["ms"]) / nsamples, 3),
+    return {"sample_us": round(1e3 * (p["ms"] + f["ms"] + wall_ms) / nsamples, 3),
             "partial_us": round(1e3 * p["ms"] / p["count"], 3), "final_us": round(1e3 * f["ms"] / f["count"], 3),
             "alg_bytes_per_sample": p["bytes"] / p["count"], "GBps": round(gbps, 1),
             "frac": round(gbps / HBM_PEAK_GBS, 4)}
@@ -384,7 +385,7 @@ def solver_line(args, torch, cfgd):
     # per-kernel pass: same steps without the graph, every launch bracketed by HIP events
     kernels, roof = kernel_report(les, ctx, max(1, min(args.steps, 10)), cfgd["name"], cells,
                                   cfgd["precision"] == 0)
-    stats = statistics_report(les, ctx) if not cfgd.get("ybc") else None   # plane statistics: channels
+    stats = statistics_report(les, ctx)
     diag, status = solver.diag()
     out = {
         "metric": METRIC,

@@ -5,7 +5,7 @@ check and the benchmark's CPU-baseline leg may import it; the library and its
 Python binding never do, and it shares no code with them.  Every function
 cites the passage of the paper (Xiao et al., "CaLES: A GPU-accelerated solver
 for large-eddy simulation of wall-bounded flows", arXiv 2411.09364) that it
-follows.  Where the paper is silent the reading taken is named R1..R38 in the
+follows.  Where the paper is silent the reading taken is named R1..R39 in the
 docstring of the function that uses it.
 
 Modules
