@@ -89,6 +89,11 @@ SUBSTEP_CASES = [
                                   sgs=SGS_DSM), "duct"),
     ("wm dsm cn-z h_wm", dict(nx=24, ny=16, nz=16, lx=6.4, ly=2.0, lz=2.0, zbc=ZBC_WALLMODEL, nu=1e-4, sgs=SGS_DSM,
                               h_wm=0.3, implicit_z=True), "duct"),
+    # the smallest duct: four rows and four planes (every row and plane next to a wall)
+    ("fewest cells wm dsm", dict(nx=8, ny=4, nz=4, lx=1.0, ly=2.0, lz=2.0, zbc=ZBC_WALLMODEL, nu=1e-3, sgs=SGS_DSM),
+     "duct"),
+    ("fewest cells noslip vd radix3", dict(nx=12, ny=6, nz=4, lx=1.0, ly=2.0, lz=2.0, zbc=ZBC_NOSLIP, nu=1e-2,
+                                           sgs=SGS_SMAG_VD, cs=0.12), "duct"),
 ]
 
 
