@@ -60,7 +60,7 @@ class LesError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIBPATH):
-        raise ImportError(f"HIP library not built: {LIBPATH} (run __graft_entry__.build())")
+        raise ImportError(f"HIP library not built: {LIBPATH} (run python paper_2411_09364_amd/build.py)")
     lib = ctypes.CDLL(LIBPATH)
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     sig = {
