@@ -73,8 +73,9 @@ typedef struct les_ctx les_ctx;   /* opaque, owned by the library */
 /* Problem description.  Plain data, copied by les_init. */
 typedef struct {
   int32_t abi_version;  /* must be LES_ABI_VERSION                                        */
-  int32_t nx, ny, nz;   /* cells; nx, ny even, of the form 2^a, 3 * 2^a, 5 * 2^a or 15 * 2^a, 8..1024;
-                           4 <= nz <= 512 (wall-bounded) or, when z is periodic, of that form   */
+  int32_t nx, ny, nz;   /* cells; nx, ny even, of the form 2^a, 3 * 2^a, 5 * 2^a or
+                           15 * 2^a, 4..1024; 4 <= nz <= 512 (wall-bounded) or, when z is
+                           periodic, of that form                                          */
   double lx, ly, lz;    /* box lengths (> 0)                                             */
   int32_t zbc;          /* LES_ZBC_*                                                     */
   double beta;          /* tanh wall clustering (wall-bounded z); 0 = uniform            */
@@ -92,13 +93,14 @@ typedef struct {
   double h_wm;          /* wall-model height; 0 = first off-wall cell centre            */
   double kappa, bconst; /* log-law constants (Eq. wm); 0 selects 0.41 and 5.2            */
   int32_t ybc;          /* LES_YBC_*.  LES_YBC_WALL (square duct, Sec. 4.4) needs wall-bounded
-                           z, explicit viscous terms or CN in z, and a model other than the
-                           learned one (the dynamic coefficient is then averaged along x
-                           lines, the only homogeneous direction); fields then carry two ghost rows in y, stored after the
-                           interior rows: dims [nz+2][ny+2][nx], row ny above y = ly, row ny+1
-                           below y = 0 (where the periodic index j - 1 of row 0 lands).  v on
-                           row ny - 1 is the wall face y = ly and stays zero.  The learned
-                           closure and batches are not available for ducts. */
+                           z, uniform y, explicit viscous terms or CN in z, and a model other
+                           than the learned one (the dynamic coefficient is then averaged
+                           along x lines, the only homogeneous direction).  Fields then
+                           carry two ghost rows in y after the interior rows: dims
+                           [nz+2][ny+2][nx], row ny above y = ly, row ny+1 below y = 0
+                           (where the periodic index j - 1 of row 0 lands).  v on row
+                           ny - 1 is the wall face y = ly and stays zero.  Batches are not
+                           available for ducts. */
 } les_config;
 
 /* Bindable and readable buffers. */
