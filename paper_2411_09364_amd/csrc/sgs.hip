@@ -210,11 +210,22 @@ __global__ void __launch_bounds__(256) k_vd_duct_partial(GridP g, const T* u, co
   if (threadIdx.x < 8) part[blockIdx.x * 8 + threadIdx.x] = sm[threadIdx.x][0];
 }
 
+// sums of q-strided block partials (nq per block, VD_BLOCKS = 64 blocks: one lane each) by a
+// fixed-order shuffle tree within one wave; lane 0 holds the totals
+__device__ inline void wave_block_sums(const double* part, int nq, double* a) {
+  const int lane = threadIdx.x & 63;
+  for (int q = 0; q < nq; ++q) {
+    double x = lane < VD_BLOCKS ? part[lane * nq + q] : 0.0;
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    a[q] = x;
+  }
+}
+
 __global__ void k_vd_duct_final(GridP g, const double* part, double* vd4) {
+  static_assert(VD_BLOCKS <= 64, "one lane per block partial");
+  double a[8];
+  wave_block_sums(part, 8, a);
   if (threadIdx.x != 0) return;
-  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int b = 0; b < VD_BLOCKS; ++b)
-    for (int q = 0; q < 8; ++q) a[q] += part[b * 8 + q];
   const double nx = g.nx, ny = g.ny, n = g.nz;
   const double cz = nx * ny, cv = nx * (ny - 1), cy = nx * n, cw = nx * (n - 1);
   vd4[0] = sqrt(hypot(a[0] / cz, a[1] / cv));
@@ -224,15 +235,18 @@ __global__ void k_vd_duct_final(GridP g, const double* part, double* vd4) {
 }
 
 // van Driest coefficient: plane-mean wall stresses -> u_tau per wall -> coef[k].
-// tau = wall-model stresses, or (no-slip) nu (u_1 - u_0)/dzc_0 from the ghosts.
+// tau = wall-model stresses, or (no-slip) nu (u_1 - u_0)/dzc_0 from the ghosts.  Stage 1:
+// VD_BLOCKS blocks of fixed-order partials of the four plane sums (part[b][4]); stage 2, one
+// block: the sums in block order, u_tau per wall, then coef[k] for every plane.
 template <typename T>
-__global__ void k_vd_coef(GridP g, const T* u, const T* v, const double* tau, int wallmodel, double cs,
-                          double* coef) {
+__global__ void __launch_bounds__(256) k_vd_coef_partial(GridP g, const T* u, const T* v, const double* tau,
+                                                         int wallmodel, double* part) {
   __shared__ double sm[4][256];
   double a[4] = {0, 0, 0, 0};
   const int64_t s = g.sxy;
   const int n = g.nz;
-  for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < s; c += stride) {
     if (wallmodel) {
       for (int q = 0; q < 4; ++q) a[q] += tau[q * s + c];
     } else {
@@ -249,20 +263,31 @@ __global__ void k_vd_coef(GridP g, const T* u, const T* v, const double* tau, in
       for (int q = 0; q < 4; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + st];
     __syncthreads();
   }
+  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) k_vd_coef_final(GridP g, const double* part, double cs,
+                                                       double* coef) {
+  __shared__ double ut[2];
+  const int n = g.nz;
+  double a[4];
+  if (threadIdx.x < 64) wave_block_sums(part, 4, a);
   if (threadIdx.x == 0) {
-    const double ub = sqrt(hypot(sm[0][0] / s, sm[1][0] / s));
-    const double ut = sqrt(hypot(sm[2][0] / s, sm[3][0] / s));
-    for (int k = 1; k <= n; ++k) {
-      const double zc = g.zc[k];
-      const bool lower = zc <= 0.5 * g.lz;
-      const double d = lower ? zc : g.lz - zc;
-      const double utk = lower ? ub : ut;
-      const double damp = 1.0 - exp(-d * utk / g.nu / 25.0);
-      const double f = cs * sqrt(g.delta2[k]) * damp;
-      coef[k] = f * f;
-    }
-    coef[0] = coef[1];
-    coef[n + 1] = coef[n];
+    const double s = (double)g.sxy;
+    ut[0] = sqrt(hypot(a[0] / s, a[1] / s));
+    ut[1] = sqrt(hypot(a[2] / s, a[3] / s));
+  }
+  __syncthreads();
+  for (int k = threadIdx.x + 1; k <= n; k += blockDim.x) {
+    const double zc = g.zc[k];
+    const bool lower = zc <= 0.5 * g.lz;
+    const double d = lower ? zc : g.lz - zc;
+    const double utk = lower ? ut[0] : ut[1];
+    const double damp = 1.0 - exp(-d * utk / g.nu / 25.0);
+    const double f = cs * sqrt(g.delta2[k]) * damp;
+    coef[k] = f * f;
+    if (k == 1) coef[0] = f * f;
+    if (k == n) coef[n + 1] = f * f;
   }
 }
 
@@ -1119,9 +1144,11 @@ void launch_eddy_viscosity(Ctx& c) {
     }
     LES_LAUNCH(c, "strain_mag", 4 * pts * sizeof(T), k_strain_mag<T>, L.grid, L.block, 0, g, (const T*)c.u, (const T*)c.v,
                        (const T*)c.w, (T*)c.nut, duct_vd ? (const double*)c.t.vd4 : nullptr, c.cfg.ly);
-    if (model == LES_SGS_SMAG_VD && c.cfg.zbc != LES_ZBC_PERIODIC && !g.ywall)
-      LES_LAUNCH(c, "vd_coef", 0, k_vd_coef<T>, dim3(1), dim3(256), 0, g, (const T*)c.u, (const T*)c.v, c.t.tau,
-                         c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.cfg.cs, c.t.coef);
+    if (model == LES_SGS_SMAG_VD && c.cfg.zbc != LES_ZBC_PERIODIC && !g.ywall) {
+      LES_LAUNCH(c, "vd_coef", 0, k_vd_coef_partial<T>, dim3(VD_BLOCKS), dim3(256), 0, g, (const T*)c.u,
+                 (const T*)c.v, c.t.tau, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
+      LES_LAUNCH(c, "vd_coef_final", 0, k_vd_coef_final, dim3(1), dim3(256), 0, g, c.t.red, c.cfg.cs, c.t.coef);
+    }
     return;
   }
   if (model == LES_SGS_DSM || model == LES_SGS_MLP) {

@@ -61,6 +61,12 @@ class LesError(RuntimeError):
 def _load():
     if not os.path.exists(LIBPATH):
         raise ImportError(f"HIP library not built: {LIBPATH} (run python paper_2411_09364_amd/build.py)")
+    # torch brings its own HIP runtime; loading it first lets the library resolve to that same
+    # runtime, so that the two share devices, streams and memory
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIBPATH)
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     sig = {
