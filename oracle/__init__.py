@@ -5,7 +5,7 @@ check and the benchmark's CPU-baseline leg may import it; the library and its
 Python binding never do, and it shares no code with them.  Every function
 cites the passage of the paper (Xiao et al., "CaLES: A GPU-accelerated solver
 for large-eddy simulation of wall-bounded flows", arXiv 2411.09364) that it
-follows.  Where the paper is silent the reading taken is named R1..R39 in the
+follows.  Where the paper is silent the reading taken is named R1..R40 in the
 docstring of the function that uses it.
 
 Modules
@@ -21,9 +21,9 @@ Modules
 The square duct of Sec. 4.4 (walls in y and z, periodic x) runs through the same
 modules: two ghost rows in y (grid.py), the y-wall rules and wall model (bc.py, R35),
 the four-wall van Driest factor (sgs.py, R36), the cosine expansion in y (poisson.py,
-R37) and the dynamic model's y filter rules and x-line averages (sgs.py, R38);
-tests/test_oracle_duct.py pins them (dense Poisson solve, laminar fixed point, exchange of
-y and z).
+R37), the dynamic model's y filter rules and x-line averages (sgs.py, R38) and the
+learned closure's four-wall y+ input (mlp.py, R40); tests/test_oracle_duct.py pins them
+(dense Poisson solve, laminar fixed point, exchange of y and z, closed-form shear inputs).
 
 Parity unpinned (no paper value or closed form fixes them; listed also in the
 design notes): the tanh map (R1), arithmetic two-point averages on the

@@ -29,8 +29,8 @@ class Case:
     ybc: int = YBC_PERIODIC    # YBC_WALL: walls at y = 0 and y = ly as well (square duct)
 
     def __post_init__(self):
-        if self.ybc == YBC_WALL and (self.zbc == ZBC_PERIODIC or self.implicit_3d or self.sgs > SGS_DSM):
-            raise ValueError("y walls need walls in z, no CN in y and a Smagorinsky-type model")
+        if self.ybc == YBC_WALL and (self.zbc == ZBC_PERIODIC or self.implicit_3d):
+            raise ValueError("y walls need walls in z and no CN in y")
 
     @property
     def zperiodic(self):

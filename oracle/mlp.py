@@ -142,9 +142,12 @@ def raw_features(case, g, u, v, w, s, utau_walls):
     n = sqrt(S_ij S_ij + O_ij O_ij) (zero where n = 0), then y+ = d u_tau/nu (d the distance
     to the nearer wall, u_tau that wall's friction velocity; 0 with periodic z) and
     Delta/delta with delta = 1.  s: centre strain (S11, S22, S33, S12, S13, S23) with the
-    SGS-strain ghosts; the rotation uses the same ghosts."""
-    us, vs, _ = bc.strain_ghosts(case, g, u, v, w)
-    o12, o13, o23 = rotation_centre(g, us, vs, w)
+    SGS-strain ghosts; the rotation uses the same ghosts.
+    R40 (square duct): y+ is the smallest d_w u_tau,w / nu over the four walls, the rule of
+    the van Driest factor (R36), with utau_walls = (z bottom, z top, y = 0, y = ly); the
+    features of the interior rows are returned, shape (nz, ny, nx, 7)."""
+    us, vs, ws = bc.strain_ghosts(case, g, u, v, w)
+    o12, o13, o23 = rotation_centre(g, us, vs, ws)
     s11, s22, s33, s12, s13, s23 = s
     S = np.stack([np.stack([s11, s12, s13], -1), np.stack([s12, s22, s23], -1),
                   np.stack([s13, s23, s33], -1)], -2)
@@ -163,6 +166,16 @@ def raw_features(case, g, u, v, w, s, utau_walls):
     f[..., 2] = tr(S2 @ Sh)
     f[..., 3] = tr(O2 @ Sh)
     f[..., 4] = tr(O2 @ S2)
+    f[..., 6] = g.delta()[:, None, None]
+    if g.ywalls:
+        f = f[:, :g.ny]
+        zc = g.zc[1:g.nz + 1][:, None]
+        yc = g.yc[None, :]
+        ut = utau_walls
+        dz_plus = np.minimum(zc * ut[0], (g.lz - zc) * ut[1])
+        dy_plus = np.minimum(yc * ut[2], (g.ly - yc) * ut[3])
+        f[..., 5] = (np.minimum(dz_plus, dy_plus) / case.nu)[:, :, None]
+        return f
     if case.zperiodic:
         yplus = np.zeros(g.nz)
     else:
@@ -171,7 +184,6 @@ def raw_features(case, g, u, v, w, s, utau_walls):
         dist = np.where(lower, zc, g.lz - zc)
         yplus = dist * np.where(lower, utau_walls[0], utau_walls[1]) / case.nu
     f[..., 5] = yplus[:, None, None]
-    f[..., 6] = g.delta()[:, None, None]
     return f
 
 
@@ -188,14 +200,17 @@ def out_of_range(fn, margin=0.05):
 def mlp_eddy_viscosity(case, g, u, v, w, params, lo, hi, cs_fallback, utau_walls,
                        emulate_bf16=True):
     """Learned closure: nu_t = max(0, MLP(x)) Delta^2 |S| (R26 clip), with flagged points
-    taking the fallback coefficient of their plane (R27).  Returns (nu_t, flags)."""
+    taking the fallback coefficient of their plane (R27), or of their x line in a duct
+    (cs_fallback (nz, ny) or wider, R38).  Returns (nu_t, flags) on the interior rows."""
     from .sgs import model_strain
     from .ops import strain_magnitude
     s = model_strain(case, g, u, v, w)
-    smag = strain_magnitude(s)
+    smag = strain_magnitude(s)[:, :g.ny]
     fn = normalise(raw_features(case, g, u, v, w, s, utau_walls), lo, hi)
     flags = out_of_range(fn)
     y, _ = forward(params, fn.reshape(-1, 7), emulate_bf16)
     c = np.maximum(y.reshape(smag.shape), 0.0)
-    c = np.where(flags, np.asarray(cs_fallback)[:, None, None], c)
+    cf = np.asarray(cs_fallback)
+    cf = cf[:, :g.ny, None] if g.ywalls else cf[:, None, None]
+    c = np.where(flags, cf, c)
     return c * (g.delta() ** 2)[:, None, None] * smag, flags

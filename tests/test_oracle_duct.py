@@ -1,4 +1,4 @@
-"""Pins of the square-duct oracle (Sec. 4.4: walls in y and z, periodic x; R35-R38).
+"""Pins of the square-duct oracle (Sec. 4.4: walls in y and z, periodic x; R35-R38, R40).
 
 - The duct Poisson solve against the dense matrix of the oracle's own divergence and
   gradient with the Neumann ghost rows (brute force on a tiny grid) and against single
@@ -12,6 +12,9 @@
   x lines, whose coefficients must form a symmetric (z, y) array).
 - The y-wall model on a profile u(y) returns the log-law stress at the interpolated
   velocity, found by bisection.
+- The learned closure's inputs (R40): they commute with the exchange of y and z; a single
+  constant velocity gradient gives the closed-form invariants at every cell, wall rows
+  included; y+ at hand-worked cells takes the nearest wall in its own units.
 """
 import math
 
@@ -209,3 +212,75 @@ def test_y_wall_model_on_a_profile(h_wm):
         assert np.max(np.abs(tau[1:g.nz + 1] - ut * ut)) < 1e-10 * ut * ut, name
         assert np.all(tau[0] == 0.0) and np.all(tau[g.nz + 1] == 0.0)
     assert np.all(tauy[1] == 0.0) and np.all(tauy[3] == 0.0)
+
+
+# ---------------------------------------------------------------- learned closure inputs (R40)
+def _features(case, g, st, ut4):
+    from oracle import mlp as OM, sgs as OS
+    s6 = OS.model_strain(case, g, st.u, st.v, st.w)
+    return OM.raw_features(case, g, st.u, st.v, st.w, s6, ut4)
+
+
+@pytest.mark.parametrize("zbc", [ZBC_NOSLIP, ZBC_WALLMODEL])
+def test_learned_inputs_commute_with_exchanging_y_and_z(zbc):
+    """The invariants are unchanged by the reflection that exchanges y and z, and y+ follows
+    the walls: the inputs of the exchanged state, with the friction velocities of the y and
+    z walls exchanged, are the transposed (z, y) inputs of the original one."""
+    case, g = _duct(nx=6, ny=6, nz=6, lx=2.0, ly=2.0, lz=2.0, zbc=zbc, nu=2e-3, sgs=SGS_DSM)
+    u, v, w = duct_field(g.nx, g.ny, g.nz, g.zc, 2.0, 2.0, seed=5, noise=0.3)
+    st = S.initial_state(case, g, u, v, w)
+    su, sv, sw, _ = _swap(g, st.u, st.v, st.w, st.p)
+    st2 = S.initial_state(case, g, su, sv, sw)
+    ut4 = (0.031, 0.047, 0.053, 0.029)
+    f = _features(case, g, st, ut4)
+    f2 = _features(case, g, st2, (ut4[2], ut4[3], ut4[0], ut4[1]))
+    assert f.shape == (g.nz, g.ny, g.nx, 7)
+    scale = np.max(np.abs(f), axis=(0, 1, 2))
+    assert np.all(scale[:6] > 0.0)
+    d = np.abs(f2.transpose(1, 0, 2, 3) - f)
+    assert np.all(np.max(d, axis=(0, 1, 2)) <= 1e-12 * np.maximum(scale, 1.0))
+
+
+@pytest.mark.parametrize("grad", ["dudz", "dudy", "dwdy"])
+def test_learned_inputs_of_a_single_velocity_gradient(grad):
+    """A flow with one constant off-diagonal gradient G has S and Omega with entries +-G/2 in
+    one pair, n = |G|, so the five invariants are (1/2, -1/2, 0, 0, -1/8) at every cell whose
+    stencil sees the linear field, the wall rows included (the y strain ghosts of R9 extend
+    u and w linearly; the z ones extend u and v).  w = b y vanishes on the z-wall faces, so
+    its check leaves out the first and last planes."""
+    case, g = _duct(nx=4, ny=8, nz=6, lx=1.0, ly=2.0, lz=1.5, zbc=ZBC_WALLMODEL, beta=1.2, nu=1e-3,
+                    sgs=SGS_DSM)
+    n = g.nz
+    u, v, w = (np.zeros((n + 2, g.nys, g.nx)) for _ in range(3))
+    zc = g.zc[1:n + 1][:, None, None]
+    yc = g.yc[None, :, None]
+    if grad == "dudz":
+        u[1:n + 1, :g.ny] = 0.7 * zc + 0.0 * yc
+    elif grad == "dudy":
+        u[1:n + 1, :g.ny] = -1.3 * yc + 0.0 * zc
+    else:
+        w[1:n, :g.ny] = 0.9 * yc + 0.0 * g.zf[1:n][:, None, None]
+    st = S.initial_state(case, g, u, v, w)
+    f = _features(case, g, st, (0.05, 0.05, 0.05, 0.05))
+    ks = slice(1, n - 1) if grad == "dwdy" else slice(0, n)
+    ref = np.array([0.5, -0.5, 0.0, 0.0, -0.125])
+    assert np.max(np.abs(f[ks, :, :, :5] - ref)) < 1e-12
+
+
+def test_learned_y_plus_takes_the_nearest_wall_in_its_own_units():
+    """R40: y+ = min over the four walls of d_w u_tau,w / nu; with friction velocities
+    (1, 2, 3, 4) (z bottom, z top, y = 0, y = ly) on a uniform 8 x 8 section of side 2
+    (spacing 1/4), checked at cells worked by hand."""
+    case, g = _duct(nx=4, ny=8, nz=8, lx=1.0, ly=2.0, lz=2.0, zbc=ZBC_WALLMODEL, nu=0.5, sgs=SGS_DSM)
+    u, v, w = duct_field(g.nx, g.ny, g.nz, g.zc, 2.0, 2.0, seed=3)
+    st = S.initial_state(case, g, u, v, w)
+    f = _features(case, g, st, (1.0, 2.0, 3.0, 4.0))[..., 5]
+    assert np.all(f == f[:, :, :1])
+    # (plane, row): distances (z bottom, z top, y = 0, y = ly) -> the smallest product / nu
+    cases = {(0, 7): 0.125 * 1.0 / 0.5,                 # z bottom 1/8 x 1 beats y = ly 1/8 x 4
+             (4, 7): 0.125 * 4.0 / 0.5,                 # mid-height: y = ly, 1/8 x 4 = 1/2
+             (7, 3): 0.125 * 2.0 / 0.5,                 # z top 1/8 x 2
+             (3, 0): 0.125 * 3.0 / 0.5,                 # y = 0, 1/8 x 3 beats z bottom 7/8 x 1
+             (1, 1): 0.375 * 1.0 / 0.5}                 # z bottom 3/8 x 1 beats y = 0 3/8 x 3
+    for (k, j), val in cases.items():
+        assert abs(f[k, j, 0] - val) < 1e-14, (k, j, f[k, j, 0], val)
