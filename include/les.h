@@ -93,9 +93,9 @@ typedef struct {
   double h_wm;          /* wall-model height; 0 = first off-wall cell centre            */
   double kappa, bconst; /* log-law constants (Eq. wm); 0 selects 0.41 and 5.2            */
   int32_t ybc;          /* LES_YBC_*.  LES_YBC_WALL (square duct, Sec. 4.4) needs wall-bounded
-                           z, uniform y, explicit viscous terms or CN in z, and a model other
-                           than the learned one (the dynamic coefficient is then averaged
-                           along x lines, the only homogeneous direction).  Fields then
+                           z, uniform y, and explicit viscous terms or CN in z (the dynamic
+                           coefficient is then averaged along x lines, the only homogeneous
+                           direction, and the learned closure falls back per x line).  Fields then
                            carry two ghost rows in y after the interior rows: dims
                            [nz+2][ny+2][nx], row ny above y = ly, row ny+1 below y = 0
                            (where the periodic index j - 1 of row 0 lands).  v on row
@@ -243,8 +243,9 @@ les_status les_profile_error(const double* z, const double* phi, const double* r
  * coefficient c of nu_t = c Delta^2 |S| (the role c_s plays in Eq. dsmag).  Inputs per cell:
  * tr(S^2), tr(O^2), tr(S^3), tr(O^2 S), tr(O^2 S^2) of S/n and O/n (S strain, O rotation,
  * n = sqrt(S_ij S_ij + O_ij O_ij)), y+ = d u_tau/nu (d distance to the nearer wall, u_tau from
- * that wall's plane-mean stress; 0 when z is periodic) and Delta (channel half-height 1),
- * each min-max scaled with the training ranges lo, hi.
+ * that wall's plane-mean stress; 0 when z is periodic; in a duct the smallest d_w u_tau,w/nu
+ * over the four walls, each u_tau,w from its wall's mean stress, as in the van Driest factor)
+ * and Delta (channel half-height 1), each min-max scaled with the training ranges lo, hi.
  * Parameters: 4737 floats, W1[64][7] | b1[64] | W2[64][64] | b2[64] | W3[64] | b3, float32
  * master copy in caller-owned device memory.  W1, W2 and the inputs of the two 64-wide
  * products are rounded to bfloat16 (nearest-even) for the matrix cores, accumulation is
@@ -253,14 +254,15 @@ les_status les_profile_error(const double* z, const double* phi, const double* r
 /* Use the network for nu_t (context created with sgs = LES_SGS_MLP; until this is called such
  * a context runs the dynamic model).  params must stay valid; lo, hi: host double[7], copied.
  * Points whose scaled inputs leave [-0.05, 1.05] take the dynamic-model coefficient of their
- * plane instead; the dynamic model is re-evaluated (on the device, without host round trip)
+ * plane (of their x line in a duct) instead; the dynamic model is re-evaluated (on the device, without host round trip)
  * in every nu_t evaluation that follows one in which a point fell back. */
 les_status les_mlp_bind(les_ctx* ctx, const float* params_dev, const double* lo, const double* hi);
 
-/* Training pairs from the current state: sample s sits at the cell drawn by SplitMix64 from
- * (seed, s); x_raw_dev (float[n][7]) receives its raw (unscaled) inputs and y_dev (float[n])
- * the dynamic-model coefficient of its plane (context with sgs = DSM, after les_nut or a
- * substep). */
+/* Training pairs from the current state: sample s sits at interior cell
+ * e = SplitMix64(seed ^ SplitMix64(s)) mod (nz ny nx), in [k][j][i] order; x_raw_dev
+ * (float[n][7]) receives its raw (unscaled) inputs and y_dev (float[n]) the dynamic-model
+ * coefficient of its plane, or of its x line in a duct (context with sgs = DSM, after les_nut
+ * or a substep). */
 les_status les_mlp_sample(les_ctx* ctx, uint64_t seed, int64_t n_samples, float* x_raw_dev, float* y_dev);
 
 /* The functions below need no context; they enqueue on hip_stream (NULL = default). */

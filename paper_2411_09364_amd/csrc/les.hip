@@ -326,8 +326,8 @@ les_status les_init(const les_config* cfg, void* hip_stream, les_ctx** out) {
   if (!(std::isfinite(f.kappa) && f.kappa >= 0.0) || !std::isfinite(f.bconst)) return LES_EINVAL;
   if (f.ybc != LES_YBC_PERIODIC && f.ybc != LES_YBC_WALL) return LES_EINVAL;
   if (f.ybc == LES_YBC_WALL) {
-    // square duct: walls in z as well, no implicit y solve, the static models
-    if (f.zbc == LES_ZBC_PERIODIC || f.implicit_z == LES_VISC_CN_3D || f.sgs > LES_SGS_DSM || f.ny < 4)
+    // square duct: walls in z as well, no implicit y solve
+    if (f.zbc == LES_ZBC_PERIODIC || f.implicit_z == LES_VISC_CN_3D || f.ny < 4)
       return LES_ENOTSUP;
     if (f.zbc == LES_ZBC_WALLMODEL && f.h_wm > 0.0) {
       const double dy = f.ly / f.ny;
@@ -452,7 +452,8 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       for (double x : c.twc) c.twc_f_host.push_back((float)x);
       c.coef_host.assign(n + 2, 0.0);
       if (f.sgs == LES_SGS_MLP && c.mlp_params != nullptr) c.coef_host = c.delta2;
-      if (f.sgs == LES_SGS_DSM && f.ybc == LES_YBC_WALL) c.coef_host = c.delta2;   // field c_s(j, k) |S|
+      if ((f.sgs == LES_SGS_DSM || f.sgs == LES_SGS_MLP) && f.ybc == LES_YBC_WALL)
+        c.coef_host = c.delta2;   // field c_s(j, k) |S|
       if (f.sgs == LES_SGS_SMAG || f.sgs == LES_SGS_SMAG_VD)
         for (int k = 0; k <= n + 1; ++k) {
           const double d = std::pow((f.lx / f.nx) * (f.ly / f.ny) * c.dzf[k], 1.0 / 3.0);
@@ -737,7 +738,6 @@ les_status les_mlp_sample(les_ctx* ctx, uint64_t seed, int64_t n, float* x, floa
   if (s != LES_OK) return s;
   if (c.cfg.sgs != LES_SGS_DSM && c.cfg.sgs != LES_SGS_MLP)
     return fail(&c, LES_ESTATE, "sampling needs the dynamic-model coefficient (sgs = DSM)");
-  if (c.g.ywall) return fail(&c, LES_ENOTSUP, "the learned closure's features are defined for channels only");
   if (n <= 0 || !x || !y) return fail(&c, LES_EINVAL, "bad sample buffers");
   if (c.cfg.precision == LES_MIXED) launch_mlp_sample<float>(c, seed, n, x, y);
   else launch_mlp_sample<double>(c, seed, n, x, y);

@@ -727,8 +727,10 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) k_dsm_fused(GridP
 }
 
 // Ducts: c_s per x line (j, k) from the tile partials [k][j][tile x], summed in tile order,
-// clipped at zero (0 where <M M> = 0); one thread per line.
-__global__ void __launch_bounds__(256) k_dsm_reduce_lines(GridP g, const double* part, int ntx, double* cs) {
+// clipped at zero (0 where <M M> = 0); one thread per line.  gate: as in k_dsm_fused.
+__global__ void __launch_bounds__(256) k_dsm_reduce_lines(GridP g, const double* part, int ntx, double* cs,
+                                                          const int* gate) {
+  if (gate != nullptr && gate[0] == 0) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= g.nz * g.ny) return;
   double a = 0.0, b = 0.0;
@@ -823,33 +825,35 @@ __global__ void __launch_bounds__(256) k_wall_mean_partial(GridP g, const T* u, 
 }
 
 // Stage 2: friction velocity of each wall, u_tau = sqrt(|(<tau_x>, <tau_y>)|), stored in
-// dt[2] (bottom) and dt[3] (top); also rotates the learned closure's fallback counters:
+// dt[2] (bottom) and dt[3] (top) (skipped without partials: ducts take the four-wall values
+// of the van Driest reduction); also rotates the learned closure's fallback counters:
 // cnt[0] = points that fell back in the previous evaluation (gate of the dynamic-model
 // fallback), cnt[1] = 0.
 __global__ void k_mlp_prep(GridP g, const double* part, double* dtp, int* cnt) {
   if (threadIdx.x != 0) return;
+  if (cnt != nullptr) {
+    cnt[0] = cnt[1];
+    cnt[1] = 0;
+  }
+  if (part == nullptr) return;
   double a[4] = {0, 0, 0, 0};
   for (int b = 0; b < WM_BLOCKS; ++b)
     for (int q = 0; q < 4; ++q) a[q] += part[b * 4 + q];
   const double s = (double)g.sxy;
   dtp[2] = sqrt(hypot(a[0] / s, a[1] / s));
   dtp[3] = sqrt(hypot(a[2] / s, a[3] / s));
-  if (cnt != nullptr) {
-    cnt[0] = cnt[1];
-    cnt[1] = 0;
-  }
 }
 
 // Rotation tensor at the cell centre (edges, then the four-edge mean, like the strain),
-// with the strain ghost rule: o[0..2] = O12, O13, O23.
+// with the strain ghost rules (z, and y in a duct): o[0..2] = O12, O13, O23.
 template <typename T>
 __device__ inline void centre_rotation(const GridP& g, const T* u, const T* v, const T* w, int k, int j, int i,
                                        double o[3]) {
   const int ip = wrap_p(i, g.nx), im = wrap_m(i, g.nx), jp = wrap_p(j, g.nys), jm = wrap_m(j, g.nys);
   const double rdx = g.rdx, rdy = g.rdy, rdzc = 1.0 / g.dzc[k], rdzcm = 1.0 / g.dzc[k - 1];
-  auto U = [&](int kk, int jj, int ii) { return (double)sval(g, u, kk, jj, ii); };
+  auto U = [&](int kk, int jj, int ii) { return (double)sval_y(g, u, kk, jj, ii, true); };
   auto V = [&](int kk, int jj, int ii) { return (double)sval(g, v, kk, jj, ii); };
-  auto W = [&](int kk, int jj, int ii) { return (double)w[idx3(g, kk, jj, ii)]; };
+  auto W = [&](int kk, int jj, int ii) { return (double)sval_y(g, w, kk, jj, ii, false); };
   auto r12 = [&](int jj, int ii) {
     return 0.5 * ((U(k, wrap_p(jj, g.nys), ii) - U(k, jj, ii)) * rdy - (V(k, jj, wrap_p(ii, g.nx)) - V(k, jj, ii)) * rdx);
   };
@@ -900,22 +904,29 @@ struct MlpNorm {
   double lo[7], inv[7];   // scaled input = (raw - lo) * inv, inv = 1 / (hi - lo)
 };
 
+// y+ of cell (k, j): the distance to the nearer z wall in that wall's units (ut[0] bottom,
+// ut[1] top); in a duct the smallest d_w u_tau,w over the four walls (ut[2] at y = 0, ut[3]
+// at y = ly), the van Driest rule; 0 with periodic z.
+__device__ inline double cell_yplus(const GridP& g, int k, int j, const double* ut, double ly) {
+  if (g.zbc == LES_ZBC_PERIODIC) return 0.0;
+  const double zc = g.zc[k];
+  if (g.ywall) {
+    const double yc = (j + 0.5) * g.dy;
+    return fmin(fmin(zc * ut[0], (g.lz - zc) * ut[1]), fmin(yc * ut[2], (ly - yc) * ut[3])) / g.nu;
+  }
+  const bool lower = zc <= 0.5 * g.lz;
+  return (lower ? zc : g.lz - zc) * (lower ? ut[0] : ut[1]) / g.nu;
+}
+
 template <typename T>
 __device__ inline void cell_features(const GridP& g, const T* u, const T* v, const T* w, int k, int j, int i,
-                                     const double* dtp, double f[7], T s6[6]) {
+                                     const double* ut, double ly, double f[7], T s6[6]) {
   centre_strain(g, u, v, w, k, j, i, s6);
   double s[6];
   for (int a = 0; a < 6; ++a) s[a] = (double)s6[a];
   double o[3];
   centre_rotation(g, u, v, w, k, j, i, o);
-  double yplus = 0.0;
-  if (g.zbc != LES_ZBC_PERIODIC) {
-    const double zc = g.zc[k];
-    const bool lower = zc <= 0.5 * g.lz;
-    const double d = lower ? zc : g.lz - zc;
-    yplus = d * (lower ? dtp[2] : dtp[3]) / g.nu;
-  }
-  raw_features(s, o, yplus, sqrt(g.delta2[k]), f);
+  raw_features(s, o, cell_yplus(g, k, j, ut, ly), sqrt(g.delta2[k]), f);
 }
 
 // Fused inference, z-marching over a chunk of planes per 32 x 8 tile (like the dynamic
@@ -924,17 +935,19 @@ __device__ inline void cell_features(const GridP& g, const T* u, const T* v, con
 // of its cell (diagonal at the centre, off-diagonal terms as four-edge means, so S and O are
 // its symmetric and antisymmetric parts), the seven scaled inputs, and each wave of 64 cells
 // runs the network on the matrix cores.  c = max(0, MLP) or, for a cell whose scaled inputs
-// leave [-0.05, 1.05], the dynamic coefficient of its plane (counted); stores c |S|.
+// leave [-0.05, 1.05], the dynamic coefficient of its plane, or of its x line in a duct
+// (YW), counted; stores c |S|.
 namespace tiled {
 constexpr int TX = 32, TY = 8, NT = TX * TY;
 constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY;
 }  // namespace tiled
 
-template <typename T>
+template <typename T, bool YW>
 __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict__ u, const T* __restrict__ v,
                                                  const T* __restrict__ w, T* __restrict__ nut,
                                                  const float* __restrict__ P, MlpNorm nm, const double* __restrict__ cs,
-                                                 const double* __restrict__ dtp, int* __restrict__ cnt, int kc) {
+                                                 const double* __restrict__ ut, double ly, int* __restrict__ cnt,
+                                                 int kc) {
   using namespace mlp;
   using tiled::TX;
   using tiled::TY;
@@ -966,12 +979,20 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
   // loads of plane k + 2 overlap the work on plane k (strain ghost rule applied at fetch)
   constexpr int NL = (N1 + tiled::NT - 1) / tiled::NT;
   int lofs[NL];
+  int yg[NL];   // ducts: 0, or the offset to the first interior row next to a y ghost row (+-nx)
   for (int r = 0; r < NL; ++r) {
     const int e = tid + r * tiled::NT;
-    int ii = (i0 - 1 + e % RX) % g.nx, jj = (j0 - 1 + e / RX) % g.nys;
+    const int lrow = j0 - 1 + e / RX;
+    int ii = (i0 - 1 + e % RX) % g.nx, jj = lrow % g.nys;
     if (ii < 0) ii += g.nx;
     if (jj < 0) jj += g.nys;
     lofs[r] = e < N1 ? jj * g.nx + ii : 0;
+    yg[r] = 0;
+    if (YW && wm && e < N1 && (lrow == -1 || lrow == g.ny)) {
+      // strain ghost of u and w on a y ghost row: 2 a0 - a1 from the two rows next to it
+      lofs[r] = (lrow < 0 ? 0 : g.ny - 1) * g.nx + ii;
+      yg[r] = lrow < 0 ? g.nx : -g.nx;
+    }
   }
   const int64_t sxy = g.sxy;
   T ra[NL], rb[NL], rc[NL];
@@ -995,6 +1016,14 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
         } else {
           ra[r] = u[bw + lofs[r]];
           rb[r] = v[bw + lofs[r]];
+        }
+        if (YW && yg[r] != 0) {
+          // lofs points at the interior row next to the ghost row: u and w extrapolated in y
+          // (in the z ghost planes these corner values are not used); v is 0 on the wall face
+          const T a1 = u[bw + lofs[r] + yg[r]], c1 = w[bw + lofs[r] + yg[r]];
+          ra[r] = u[bw + lofs[r]] - (a1 - u[bw + lofs[r]]);
+          rc[r] = rc[r] - (c1 - rc[r]);
+          rb[r] = (T)0;
         }
       }
     }
@@ -1055,8 +1084,13 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
     double yplus = 0.0;
     if (!per) {
       const double zc = g.zc[pk];
-      const bool lower = zc <= 0.5 * g.lz;
-      yplus = (lower ? zc : g.lz - zc) * (lower ? dtp[2] : dtp[3]) / g.nu;
+      if (YW) {
+        const double yc = (j + 0.5) * g.dy;
+        yplus = fmin(fmin(zc * ut[0], (g.lz - zc) * ut[1]), fmin(yc * ut[2], (ly - yc) * ut[3])) / g.nu;
+      } else {
+        const bool lower = zc <= 0.5 * g.lz;
+        yplus = (lower ? zc : g.lz - zc) * (lower ? ut[0] : ut[1]) / g.nu;
+      }
     }
     double f[7];
     raw_features(s, o, yplus, sqrt(g.delta2[pk]), f);
@@ -1087,7 +1121,7 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
       const T smag = strain_mag(s6);
       double c = yv > 0.0f ? (double)yv : 0.0;
       if (flag) {
-        c = cs[pk - 1];
+        c = YW ? cs[(int64_t)(pk - 1) * g.ny + j] : cs[pk - 1];
         ++flagged;
       }
       store_nut(g, nut, pk, j, i, (T)c * smag);
@@ -1100,8 +1134,9 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
   }
 }
 
-// Training pairs: sample s sits at the cell hashed from (seed, s) (SplitMix64); x gets
-// its seven raw features, y the dynamic coefficient of its plane.
+// Training pairs: sample s sits at the interior cell hashed from (seed, s) (SplitMix64); x
+// gets its seven raw features, y the dynamic coefficient of its plane (of its x line in a
+// duct).
 __device__ inline uint64_t splitmix64(uint64_t z) {
   z += 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -1110,20 +1145,21 @@ __device__ inline uint64_t splitmix64(uint64_t z) {
 }
 
 template <typename T>
-__global__ void k_mlp_sample(GridP g, const T* u, const T* v, const T* w, const double* cs, const double* dtp,
-                             uint64_t seed, int64_t n, float* x, float* y) {
+__global__ void k_mlp_sample(GridP g, const T* u, const T* v, const T* w, const double* cs, const double* ut,
+                             double ly, uint64_t seed, int64_t n, float* x, float* y) {
   const int64_t sidx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (sidx >= n) return;
-  const uint64_t ncell = (uint64_t)g.nz * (uint64_t)g.sxy;
+  const uint64_t nxy = (uint64_t)g.nx * (uint64_t)g.ny;
+  const uint64_t ncell = (uint64_t)g.nz * nxy;
   const uint64_t e = splitmix64(seed ^ splitmix64((uint64_t)sidx)) % ncell;
-  const int k = (int)(e / (uint64_t)g.sxy) + 1;
-  const int64_t r = (int64_t)(e % (uint64_t)g.sxy);
+  const int k = (int)(e / nxy) + 1;
+  const int64_t r = (int64_t)(e % nxy);
   const int j = (int)(r / g.nx), i = (int)(r % g.nx);
   double f[7];
   T s6[6];
-  cell_features(g, u, v, w, k, j, i, dtp, f, s6);
+  cell_features(g, u, v, w, k, j, i, ut, ly, f, s6);
   for (int a = 0; a < 7; ++a) x[sidx * 7 + a] = (float)f[a];
-  y[sidx] = (float)cs[k - 1];
+  y[sidx] = (float)(g.ywall ? cs[(int64_t)(k - 1) * g.ny + j] : cs[k - 1]);
 }
 
 // ============================================================================ launcher
@@ -1155,19 +1191,42 @@ void launch_eddy_viscosity(Ctx& c) {
     const bool learned = model == LES_SGS_MLP && c.mlp_params != nullptr;
     const int* gate = learned ? c.mlp_cnt : nullptr;
     if (learned) {
-      LES_LAUNCH(c, "wall_mean", 0, k_wall_mean_partial<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
-                 (const T*)c.v, c.t.tau, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
-      LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, c.t.red, c.t.dt, c.mlp_cnt);
+      if (g.ywall) {
+        // ducts: the four walls' friction velocities of the van Driest reduction
+        LES_LAUNCH(c, "vd_duct", 0, k_vd_duct_partial<T>, dim3(VD_BLOCKS), dim3(256), 0, g, (const T*)c.u,
+                   (const T*)c.v, (const T*)c.w, c.t.tau, c.t.tauy, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
+        LES_LAUNCH(c, "vd_duct_final", 0, k_vd_duct_final, dim3(1), dim3(64), 0, g, c.t.red, c.t.vd4);
+        LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, (const double*)nullptr, c.t.dt, c.mlp_cnt);
+      } else {
+        LES_LAUNCH(c, "wall_mean", 0, k_wall_mean_partial<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
+                   (const T*)c.v, c.t.tau, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
+        LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, c.t.red, c.t.dt, c.mlp_cnt);
+      }
     }
     const int kc = c.dsm_kc;
     dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + fused::TY - 1) / fused::TY, (g.nz + kc - 1) / kc);
+    MlpNorm nm;
+    if (learned) {
+      for (int a = 0; a < 7; ++a) {
+        nm.lo[a] = c.mlp_lo[a];
+        nm.inv[a] = 1.0 / (c.mlp_hi[a] - c.mlp_lo[a]);
+      }
+    }
+    const int mkc = c.mlp_kc;
+    const dim3 tgrid((g.nx + tiled::TX - 1) / tiled::TX, (g.ny + tiled::TY - 1) / tiled::TY, (g.nz + mkc - 1) / mkc);
     if (g.ywall) {
       // ducts: coefficients along x lines
       LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), (k_dsm_fused<T, true>), grid, dim3(fused::TX, fused::TY), 0, g,
-                 (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.t.dsm_part, kc, (const int*)nullptr);
+                 (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.t.dsm_part, kc, gate);
       const int nl = g.nz * g.ny;
       LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce_lines, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, g,
-                 c.t.dsm_part, (int)grid.x, c.t.cs);
+                 c.t.dsm_part, (int)grid.x, c.t.cs, gate);
+      if (learned) {
+        LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), (k_mlp_nut<T, true>), tgrid, dim3(tiled::TX, tiled::TY), 0, g,
+                   (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm, c.t.cs,
+                   (const double*)c.t.vd4, c.cfg.ly, c.mlp_cnt, mkc);
+        return;
+      }
       const int64_t ns = (int64_t)(g.nz + 2) * g.nx * g.ny;
       LES_LAUNCH(c, "nut_lines", 2.0 * ns * sizeof(T), k_nut_lines<T>, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0,
                  g, (T*)c.nut, (const double*)c.t.cs);
@@ -1179,16 +1238,9 @@ void launch_eddy_viscosity(Ctx& c) {
     LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs,
                learned ? nullptr : c.t.coef, gate);
     if (learned) {
-      MlpNorm nm;
-      for (int a = 0; a < 7; ++a) {
-        nm.lo[a] = c.mlp_lo[a];
-        nm.inv[a] = 1.0 / (c.mlp_hi[a] - c.mlp_lo[a]);
-      }
-      const int mkc = c.mlp_kc;
-      dim3 tgrid((g.nx + tiled::TX - 1) / tiled::TX, (g.ny + tiled::TY - 1) / tiled::TY, (g.nz + mkc - 1) / mkc);
-      LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), k_mlp_nut<T>, tgrid, dim3(tiled::TX, tiled::TY), 0, g,
-                 (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm, c.t.cs, c.t.dt, c.mlp_cnt,
-                 mkc);
+      LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), (k_mlp_nut<T, false>), tgrid, dim3(tiled::TX, tiled::TY), 0, g,
+                 (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm, c.t.cs,
+                 (const double*)(c.t.dt + 2), c.cfg.ly, c.mlp_cnt, mkc);
     }
   }
 }
@@ -1207,11 +1259,20 @@ template void batch_eddy_viscosity<double>(hipStream_t, const BatchMap&, const i
 template <typename T>
 void launch_mlp_sample(Ctx& c, uint64_t seed, int64_t n, float* x, float* y) {
   const GridP& g = c.g;
-  LES_LAUNCH(c, "wall_mean", 0, k_wall_mean_partial<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
-             (const T*)c.v, c.t.tau, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
-  LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, c.t.red, c.t.dt, (int*)nullptr);
+  const int wm = c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0;
+  const double* ut = c.t.dt + 2;
+  if (g.ywall) {
+    LES_LAUNCH(c, "vd_duct", 0, k_vd_duct_partial<T>, dim3(VD_BLOCKS), dim3(256), 0, g, (const T*)c.u, (const T*)c.v,
+               (const T*)c.w, c.t.tau, c.t.tauy, wm, c.t.red);
+    LES_LAUNCH(c, "vd_duct_final", 0, k_vd_duct_final, dim3(1), dim3(64), 0, g, c.t.red, c.t.vd4);
+    ut = c.t.vd4;
+  } else {
+    LES_LAUNCH(c, "wall_mean", 0, k_wall_mean_partial<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
+               (const T*)c.v, c.t.tau, wm, c.t.red);
+    LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, c.t.red, c.t.dt, (int*)nullptr);
+  }
   LES_LAUNCH(c, "mlp_sample", 0, k_mlp_sample<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g, (const T*)c.u,
-             (const T*)c.v, (const T*)c.w, c.t.cs, c.t.dt, seed, n, x, y);
+             (const T*)c.v, (const T*)c.w, c.t.cs, ut, c.cfg.ly, seed, n, x, y);
 }
 template void launch_mlp_sample<double>(Ctx&, uint64_t, int64_t, float*, float*);
 template void launch_mlp_sample<float>(Ctx&, uint64_t, int64_t, float*, float*);

@@ -79,7 +79,6 @@ def test_cn_in_all_directions_accepted_for_every_z_condition(zbc):
 @pytest.mark.parametrize("kw,status", [
     (dict(ybc=1), -4),                                              # y walls need z walls
     (dict(ybc=1, zbc=1, nz=16, implicit_z=2), -4),                  # no CN in y
-    (dict(ybc=1, zbc=1, nz=16, sgs=4), -4),                         # no learned closure
     (dict(ybc=1, zbc=2, nz=16, h_wm=0.9), -1),                      # h_wm beyond the duct's middle row
     (dict(ybc=2, zbc=1, nz=16), -1),
 ])
@@ -88,6 +87,13 @@ def test_duct_configurations_rejected(kw, status):
     with pytest.raises(les.LesError) as e:
         _init(**kw)
     assert e.value.status == status
+
+
+def test_duct_learned_closure_accepted():
+    from paper_2411_09364_amd import les
+    ctx = _init(ybc=1, zbc=2, nz=16, sgs=les.SGS_MLP)
+    assert les.les_layout(ctx, les.FIELD_CS).bytes == 8 * 16 * 32   # per x line (nz, ny)
+    les.les_free(ctx)
 
 
 def test_duct_layout_has_two_ghost_rows():
