@@ -148,10 +148,13 @@ def initial_params(seed):
 def feature_range(torch, xr):
     """Scaling range of the raw features: the sample min/max widened by a quarter of the
     span on each side (inputs beyond it, with the 5 % margin, fall back to the dynamic
-    model)."""
+    model), and by at least 1e-5 of the value's size: the samples are float32, so an input
+    that is constant over the grid (Delta on a uniform grid) differs from the kernels' FP64
+    value by float32 rounding."""
+    import numpy as np
     lo = xr.min(dim=0).values.double().cpu().numpy()
     hi = xr.max(dim=0).values.double().cpu().numpy()
-    pad = 0.25 * (hi - lo) + 1e-12
+    pad = 0.25 * (hi - lo) + 1e-5 * np.maximum(1.0, np.maximum(np.abs(lo), np.abs(hi)))
     return lo - pad, hi + pad
 
 
@@ -263,10 +266,7 @@ def learned_closure(les, torch, cfgd, solver, steps, warmup, use_graph):
         loss = mlp.train_step(x, yr, 3e-3 if it < 300 else 1e-3)
     solver.synchronize()
     train_s = time.perf_counter() - t0
-    cfg = les.make_config(cfgd["nx"], cfgd["ny"], cfgd["nz"], cfgd["lx"], cfgd["ly"], cfgd["lz"], zbc=cfgd["zbc"],
-                          beta=cfgd["beta"], nu=cfgd["nu"], sgs=les.SGS_MLP, cs=cfgd["cs"],
-                          implicit_z=cfgd["implicit_z"], precision=cfgd["precision"], ubulk=cfgd["ubulk"])
-    s2 = les.Solver(cfg)
+    _, s2 = make_solver(dict(cfgd, sgs=les.SGS_MLP))
     zf, zc = s2.zgrid()
     u, v, w = initial_fields(cfgd, zc)
     s2.set_state(u, v, w)
@@ -296,7 +296,7 @@ def learned_closure(les, torch, cfgd, solver, steps, warmup, use_graph):
            "ms_per_step": round(el / steps * 1e3, 4), "train_loss": float(loss.item()),
            "train_seconds": round(train_s, 3), "fallback_points_last_eval": int(d.mlp_flagged),
            "nut_kernel_us": {k: round(1e3 * v["ms"] / v["count"], 2) for k, v in rep.items()
-                             if k.startswith("mlp") or k.startswith("dsm")}}
+                             if k.startswith(("mlp", "dsm", "vd_duct"))}}
     s2.close()
     return out
 
@@ -409,7 +409,7 @@ def solver_line(args, torch, cfgd):
         "state_check": {"max_div": diag.max_div, "ubulk": diag.ubulk, "nonfinite": int(diag.nonfinite)},
         "statistics": stats,
     }
-    if not args.no_learned and cfgd["sgs"] == 3 and args.config == "c2":
+    if not args.no_learned and cfgd["sgs"] == 3 and args.config in ("c2", "f2d"):
         out["learned_closure"] = learned_closure(les, torch, cfgd, solver, args.steps, args.warmup, use_graph)
     solver.close()
     if args.config == "c3":
