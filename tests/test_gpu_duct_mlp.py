@@ -100,7 +100,9 @@ def test_duct_fused_inference_matches_oracle(env, zbc, narrow, precision):
     lo, hi = f.min(axis=0), f.max(axis=0)
     if narrow:
         hi[5] = np.median(f[:, 5])
-    hi = np.where(hi > lo, hi, lo + 1.0)
+    # an input constant over the grid up to rounding (Delta on a uniform grid) gets a unit
+    # span: a span of rounding size would turn last-bit differences into O(1) inputs
+    hi = np.where(hi - lo > 1e-9 * np.maximum(1.0, np.abs(hi)), hi, lo + 1.0)
     p = OM.init_params(21)
     p["b3"][:] = 0.03
     ref, flags = OM.mlp_eddy_viscosity(case_d, g, st.u, st.v, st.w, p, lo, hi, st.cs, ut, emulate_bf16=True)
@@ -192,7 +194,9 @@ def test_duct_learned_closure_gains_over_constant_coefficient(env):
     torch.cuda.synchronize()
     xn = xr.cpu().numpy().astype(np.float64)
     lo, hi = xn.min(axis=0), xn.max(axis=0)
-    hi = np.where(hi > lo, hi, lo + 1.0)
+    # an input constant over the grid up to rounding (Delta on a uniform grid) gets a unit
+    # span: a span of rounding size would turn last-bit differences into O(1) inputs
+    hi = np.where(hi - lo > 1e-9 * np.maximum(1.0, np.abs(hi)), hi, lo + 1.0)
     x = torch.empty_like(xr)
     xhn = torch.empty_like(xhr)
     les.les_mlp_normalize(solver.stream.cuda_stream, xr.data_ptr(), xr.shape[0], lo, hi, x.data_ptr())

@@ -16,13 +16,17 @@
   64-box ensemble (32^3 .. 96^3, FP32): one batched step replayed from the graph, a sample of
       two boxes of every size against the oracle within the mixed tolerance;
   degenerate states: fluid at rest stays at rest with a zero dynamic coefficient, a uniform
-      flow stays uniform.
+      flow stays uniform;
+  the learned closure's fused inference on the channel and the duct grids above against the
+      oracle's network with its bfloat16 rounding points, every cell (float32 level at the
+      median, single bfloat16 flips at most), with the cells farthest from the walls falling
+      back to the dynamic coefficient (counts equal).
 """
 import numpy as np
 import pytest
 
 from oracle import substep as S, ops as OO
-from oracle.case import ZBC_PERIODIC, ZBC_WALLMODEL, SGS_DSM, SGS_SMAG_VD, YBC_WALL
+from oracle.case import ZBC_PERIODIC, ZBC_WALLMODEL, SGS_DSM, SGS_SMAG_VD, SGS_MLP, YBC_WALL
 from synth import box_ensemble, isotropic_field
 from tests.cases import (make_pair, initial_fields, rel_err, mean_free, say, dsm_nut_check, round32,
                          pressure_tolerance)
@@ -260,4 +264,43 @@ def test_duct_full_size_step_matches_oracle(les, sgs):
     d, status = solver.diag()
     assert status == 0 and d.nonfinite == 0
     assert abs(d.ubulk - 1.0) < 1e-13 and d.max_div < 1e-10
+    solver.close()
+
+
+@pytest.mark.parametrize("which", ["channel", "duct"])
+def test_full_size_learned_inference_matches_oracle(les, which):
+    from oracle import mlp as OM, sgs as OS
+    say("full-size learned inference,", which)
+    base = CHANNEL if which == "channel" else DUCT
+    case_d, g, _ = make_pair(**dict(base, sgs=SGS_DSM))
+    _, _, cfg_m = make_pair(**dict(base, sgs=SGS_MLP))
+    u, v, w = initial_fields(case_d, g, 11, which)
+    st = S.initial_state(case_d, g, u, v, w)
+    ut = OS.duct_friction_velocity(g, st.tau, st.tauy) if g.ywalls else OS.friction_velocity(st.tau)
+    s6 = OS.model_strain(case_d, g, st.u, st.v, st.w)
+    f = OM.raw_features(case_d, g, st.u, st.v, st.w, s6, ut).reshape(-1, 7)
+    lo, hi = f.min(axis=0), f.max(axis=0)
+    hi[5] = np.quantile(f[:, 5], 0.8)          # the cells farthest from the walls fall back
+    # an input constant over the grid up to rounding (Delta on a uniform grid) gets a unit
+    # span: a span of rounding size would turn last-bit differences into O(1) inputs
+    hi = np.where(hi - lo > 1e-9 * np.maximum(1.0, np.abs(hi)), hi, lo + 1.0)
+    del f, s6
+    p = OM.init_params(21)
+    p["b3"][:] = 0.03
+    ref, flags = OM.mlp_eddy_viscosity(case_d, g, st.u, st.v, st.w, p, lo, hi, st.cs, ut, emulate_bf16=True)
+    solver = les.Solver(cfg_m)
+    solver.set_state(u, v, w)
+    mlp = les.Mlp(OM.flatten(p), stream=solver.stream)
+    solver.mlp_bind(mlp, lo, hi)
+    solver.nut()
+    nut = solver.eddy_viscosity()[1:g.nz + 1, :g.ny]
+    d, status = solver.diag()
+    scale = np.max(np.abs(ref))
+    diff = np.abs(nut - ref)
+    say(f"  flagged {int(flags.sum())} of {flags.size} (gpu {d.mlp_flagged}); |diff|/max: median "
+        f"{np.median(diff) / scale:.2e}, max {diff.max() / scale:.2e}, above 1e-4: {int(np.sum(diff > 1e-4 * scale))}")
+    assert status == 0
+    assert 0 < int(flags.sum()) < flags.size and d.mlp_flagged == int(flags.sum())
+    assert np.median(diff) <= 2e-6 * scale
+    assert diff.max() <= 2e-3 * scale
     solver.close()
