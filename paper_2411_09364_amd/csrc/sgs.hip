@@ -1058,8 +1058,8 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
       const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
       return vel[sl][c][(y + dy) * RX + x + dx];
     };
-    const T rdx = (T)g.rdx, rdy = (T)g.rdy, rdzf = (T)(1.0 / g.dzf[pk]);
-    const T rdzc = (T)(1.0 / g.dzc[pk]), rdzcm = (T)(1.0 / g.dzc[pk - 1]);
+    const T rdx = (T)g.rdx, rdy = (T)g.rdy, rdzf = (T)g.rdzf[pk];
+    const T rdzc = (T)g.rdzc[pk], rdzcm = (T)g.rdzc[pk - 1];
     const T q4 = (T)0.25, h = (T)0.5;
     // velocity-gradient tensor at the centre
     const T a11 = (A(0, 0, 0, 0) - A(0, 0, 0, -1)) * rdx;
