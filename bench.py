@@ -2,18 +2,23 @@
 
 A step is one full RK3 time step of the hot path: the device-side time-step reduction
 and three substeps (predictor, CN-z Helmholtz solves, Poisson solve, projection, flow-rate
-forcing, wall model, dynamic eddy viscosity), replayed from a hipGraph.  The metric is
-grid points x substeps per second (Mpts.substeps/s).
+forcing, wall model, eddy viscosity), replayed from a hipGraph.  The metric is grid
+points x substeps per second (Mpts.substeps/s), for the plain method (dynamic
+Smagorinsky) and for the learned closure on the same grid.
 
-Default workload: turbulent channel 256 x 128 x 96 (x, y periodic; z wall-bounded, tanh
-stretching beta = 1.5), Lx = 2 pi, Ly = pi, Lz = 2, FP64, Re_b = 40000 (nu = 5e-5 with
-U_b = 1, h = 1), dynamic Smagorinsky, log-law wall model at the first off-wall cell,
-Crank-Nicolson in z, constant flow rate; initial field laminar Poiseuille plus 10 %
-seeded uniform noise (synthetic).
+Default workload (--config c4): turbulent channel 512 x 256 x 128 (x, y periodic; z
+wall-bounded, tanh stretching beta = 1.5), Lx = 2 pi, Ly = pi, Lz = 2, FP64, Re_b = 40000
+(nu = 5e-5 with U_b = 1, h = 1), log-law wall model at the first off-wall cell,
+Crank-Nicolson in z, constant flow rate; initial field laminar Poiseuille plus 10 % seeded
+uniform noise (synthetic), projected onto discretely divergence-free fields.  `value` is
+the dynamic-Smagorinsky throughput; the learned closure (trained on the GPU from
+dynamic-model samples of the same run) is timed on the same state and reported beside it.
+Each throughput is the median of five timed runs of --steps steps.
 
 Printed: one JSON line with the throughput, the roofline of the dominant kernel (HIP
 events on the library's stream, algorithmic bytes per launch from the library) and the
-CPU oracle timed on a bounded sample of the same workload.
+CPU oracle timed on a bounded sample of the same workload (in a child process whose
+thread count is fixed and measured).
 """
 import argparse
 import hashlib
@@ -57,15 +62,21 @@ CONFIGS = {
                dtype="f32"),
 }
 
+def note(msg):
+    """Progress line on stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="c4", choices=sorted(CONFIGS))
+    ap.add_argument("--runs", type=int, default=5, help="timed runs of --steps steps; the median is reported")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--compare-steps", type=int, default=100,
                     help="c3: steps of the mixed vs FP64 comparison; c4: steps of the mean-profile comparison")
@@ -75,6 +86,8 @@ def parse():
     ap.add_argument("--epochs", type=int, default=5, help="c4: training epochs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (calibration of HBM counters)")
+    ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)     # child process of cpu_baseline
+    ap.add_argument("--fft-workers", type=int, default=0, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -96,16 +109,21 @@ def initial_fields(cfgd, zc):
     return channel_field(cfgd["nx"], cfgd["ny"], cfgd["nz"], zc, seed=cfgd["seed"])
 
 
-def cpu_baseline(cfgd, budget_s):
-    """The CPU oracle as it stands, one thread, on the same workload: substeps from the
-    same seeded initial field until about budget_s seconds have been spent (at least one)."""
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=1)
-    except Exception:
-        limiter = None
+def cpu_leg(key, budget_s, fft_workers):
+    """Child-process body of cpu_baseline: oracle substeps of workload `key` from its seeded
+    initial state until about budget_s seconds have been spent (at least one), timed by the
+    wall clock and by this process's CPU time.  With fft_workers > 0 the oracle's numpy FFT
+    calls are routed to scipy.fft with that many workers (same transforms, threaded)."""
+    import numpy as np
+    if fft_workers > 0:
+        import scipy.fft as sf
+        for name in ("fft", "ifft", "fft2", "ifft2", "fftn", "ifftn"):
+            def routed(*a, _f=getattr(sf, name), **kw):
+                return _f(*a, workers=fft_workers, **kw)
+            setattr(np.fft, name, routed)
     import oracle
     from oracle import substep as S
+    cfgd = CONFIGS[key]
     case = oracle.Case(cfgd["nx"], cfgd["ny"], cfgd["nz"], cfgd["lx"], cfgd["ly"], cfgd["lz"], zbc=cfgd["zbc"],
                        beta=cfgd["beta"], nu=cfgd["nu"], sgs=cfgd["sgs"], cs=cfgd["cs"],
                        implicit_z=cfgd["implicit_z"] == 1, implicit_3d=cfgd["implicit_z"] == 2,
@@ -114,20 +132,45 @@ def cpu_baseline(cfgd, budget_s):
     u, v, w = initial_fields(cfgd, g.zc)
     st = S.initial_state(case, g, u, v, w)
     dt = S.time_step(case, g, st, cfl=0.5)
-    t0 = time.perf_counter()
+    del u, v, w
+    t0, c0 = time.perf_counter(), time.process_time()
     n = 0
     while True:
         st = S.substep(case, g, st, n % 3, dt)
         n += 1
         if time.perf_counter() - t0 >= budget_s or n >= 30:
             break
-    el = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
+    el, cpu = time.perf_counter() - t0, time.process_time() - c0
     cells = cfgd["nx"] * cfgd["ny"] * cfgd["nz"]
-    return {"value": cells * n / el / 1e6, "unit": "Mpts·substeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} oracle substep(s) of the full {cfgd['nx']}x{cfgd['ny']}x{cfgd['nz']} workload "
-                      f"in {el:.1f} s, numpy float64, 1 thread"}
+    return {"substeps": n, "seconds": el, "cpu_seconds": cpu, "value": cells * n / el / 1e6}
+
+
+def cpu_baseline(key, budget_s, fft_workers=0):
+    """The CPU oracle as it stands on the same workload, in a child process started with one
+    thread for OpenMP and BLAS (numpy's elementwise work and FFTs are single-threaded), or
+    with its FFTs on fft_workers scipy threads.  `cores` is what the child used: its CPU time
+    over its wall time, rounded up."""
+    import math
+    import subprocess
+    env = dict(os.environ)
+    threads = max(1, fft_workers)
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+        env[var] = "1"
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", key, "--cpu-seconds", str(budget_s),
+           "--fft-workers", str(fft_workers)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=max(600.0, 20 * budget_s))
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle timing failed: {r.stderr[-2000:]}")
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    cfgd = CONFIGS[key]
+    used = res["cpu_seconds"] / res["seconds"]
+    cores = max(1, math.ceil(used - 0.05))
+    fft = f", FFTs on {fft_workers} scipy.fft workers" if fft_workers else ""
+    return {"value": res["value"], "unit": "Mpts·substeps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{res['substeps']} oracle substep(s) of the full {cfgd['nx']}x{cfgd['ny']}x{cfgd['nz']} "
+                      f"workload in {res['seconds']:.1f} s, numpy float64{fft} (child process, "
+                      f"OMP/BLAS threads 1; CPU time / wall time {used:.2f}; {os.cpu_count()} host threads)",
+            "threads_requested": threads, "cpu_utilisation": round(used, 3)}
 
 
 def initial_params(seed):
@@ -162,6 +205,24 @@ def run_steps(les, s, n, use_graph=True):
     for _ in range(n):
         les.les_dt(s.ctx, 0.5, sync=False)
         les.les_step(s.ctx, use_graph)
+
+
+def timed_runs(les, s, args, use_graph):
+    """--runs timed runs of --steps steps each (after --warmup untimed steps), each bracketed
+    by stream synchronisation; returns (median seconds per run, all run seconds)."""
+    import statistics
+    import torch
+    run_steps(les, s, args.warmup, use_graph)
+    s.synchronize()
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(max(1, args.runs)):
+        t0 = time.perf_counter()
+        run_steps(les, s, args.steps, use_graph)
+        s.synchronize()
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
+    return statistics.median(runs), runs
 
 
 def copy_state(torch, dst, src):
@@ -249,7 +310,7 @@ def statistics_report(les, ctx, nsamples=20):
             "frac": round(gbps / HBM_PEAK_GBS, 4)}
 
 
-def learned_closure(les, torch, cfgd, solver, steps, warmup, use_graph):
+def learned_closure(les, torch, cfgd, solver, args, use_graph):
     """Same workload with the learned closure: the network is trained on the GPU from
     dynamic-model pairs sampled from the plain solver's current state (400 Adam steps on
     2^16 samples), bound to a second context started from the same initial field, and the
@@ -274,26 +335,17 @@ def learned_closure(les, torch, cfgd, solver, steps, warmup, use_graph):
     s2.nut()
     ctx = s2.ctx
 
-    def step(graph):
-        les.les_dt(ctx, 0.5, sync=False)
-        les.les_step(ctx, graph)
-
-    for _ in range(warmup):
-        step(use_graph)
-    s2.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step(use_graph)
-    s2.synchronize()
-    el = time.perf_counter() - t0
+    el, runs = timed_runs(les, s2, args, use_graph)
+    steps = args.steps
     les.les_timing(ctx, True)
-    step(False)
+    run_steps(les, s2, 1, False)
     les.les_timing(ctx, False)
     rep = les.les_timing_report(ctx)
     d, _ = s2.diag()
     cells = cfgd["nx"] * cfgd["ny"] * cfgd["nz"]
     out = {"value": round(cells * 3 * steps / el / 1e6, 3), "unit": "Mpts·substeps/s",
-           "ms_per_step": round(el / steps * 1e3, 4), "train_loss": float(loss.item()),
+           "ms_per_step": round(el / steps * 1e3, 4), "timed_runs_s": [round(r, 5) for r in runs],
+           "train_loss": float(loss.item()),
            "train_seconds": round(train_s, 3), "fallback_points_last_eval": int(d.mlp_flagged),
            "nut_kernel_us": {k: round(1e3 * v["ms"] / v["count"], 2) for k, v in rep.items()
                              if k.startswith(("mlp", "dsm", "vd_duct"))}}
@@ -372,14 +424,7 @@ def solver_line(args, torch, cfgd):
     ctx = solver.ctx
     use_graph = not args.no_graph
     cells = cfgd["nx"] * cfgd["ny"] * cfgd["nz"]
-    run_steps(les, solver, args.warmup, use_graph)
-    solver.synchronize()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run_steps(les, solver, args.steps, use_graph)
-    solver.synchronize()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el, runs = timed_runs(les, solver, args, use_graph)
     ms_per_step = el / args.steps * 1e3
     value = cells * 3 * args.steps / el / 1e6
     # per-kernel pass: same steps without the graph, every launch bracketed by HIP events
@@ -403,6 +448,7 @@ def solver_line(args, torch, cfgd):
         "config": {"workload": cfgd["name"], "grid": [cfgd["nx"], cfgd["ny"], cfgd["nz"]],
                    "substeps_per_step": 3, "graph": use_graph,
                    "closure": {3: "dynamic Smagorinsky", 2: "Smagorinsky + van Driest"}.get(cfgd["sgs"], "Smagorinsky")},
+        "timed_runs_s": [round(r, 5) for r in runs],
         "roofline": roof,
         "substep_roofline": substep_roofline(value, cfgd),
         "kernels": kernels,
@@ -410,17 +456,24 @@ def solver_line(args, torch, cfgd):
         "statistics": stats,
     }
     if not args.no_learned and cfgd["sgs"] == 3 and args.config in ("c2", "f2d"):
-        out["learned_closure"] = learned_closure(les, torch, cfgd, solver, args.steps, args.warmup, use_graph)
+        out["learned_closure"] = learned_closure(les, torch, cfgd, solver, args, use_graph)
     solver.close()
     if args.config == "c3":
         out["precision_check"] = precision_check(les, torch, cfgd, args.compare_steps)
-    if not args.no_cpu_baseline and args.config in ("c1", "c2", "f1", "f2", "f2d"):
-        out["cpu_baseline"] = cpu_baseline(cfgd, args.cpu_seconds)
+    if not args.no_cpu_baseline and args.config in ("c1", "c2", "c3", "f1", "f2", "f2d"):
+        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds)
     return out
 
 
-def learned_line(args, torch):
-    """Learned closure against the dynamic model on the 512 x 256 x 128 channel.
+# Matrix-core work of the learned closure per cell: 2 (7 * 64 + 64 * 64 + 64) flops (the first
+# layer's 7 inputs are padded to 16 on the matrix cores, not counted); dense BF16 peak of the
+# MI355X matrix cores in TFLOP/s.
+MLP_FLOPS_PER_CELL = 2 * (7 * 64 + 64 * 64 + 64)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def c4_line(args, torch):
+    """Dynamic Smagorinsky against the learned closure on the 512 x 256 x 128 channel.
     1. Dynamic-model run from the seeded laminar-plus-noise field for `spinup` steps.
     2. Training pairs (raw features, dynamic c_s of the cell's plane) sampled on the GPU at
        `snapshots` states 10 steps apart, `per_snapshot` cells each; the batches interleave
@@ -429,9 +482,13 @@ def learned_line(args, torch):
     4. On the last dynamic-model state: the learned and the dynamic eddy viscosity of the
        same velocity; the learned closure's effective plane coefficient
        c_eff(k) = c_s(k) <nu_t,learned>(k) / <nu_t,dynamic>(k) against c_s(k).
-    5. Throughput of both closures from that state (graph-replayed steps).
-    6. Both runs restarted from that state for `compare_steps` steps: plane-mean streamwise
-       velocity profiles compared."""
+    5. Throughput of both closures from that state (graph-replayed steps, median of --runs
+       timed runs each); `value` is the dynamic model's.
+    6. Per-kernel HIP-event timing of both; roofline of the dynamic run's dominant kernel,
+       matrix-core rate of the learned closure's inference kernel.
+    7. Both runs restarted from the state of step 4 for `compare_steps` steps: plane-mean
+       streamwise velocity profiles compared.
+    8. The CPU oracle on a bounded sample of the same workload."""
     import numpy as np
     cfgd = CONFIGS["c4"]
     use_graph = not args.no_graph
@@ -441,10 +498,12 @@ def learned_line(args, torch):
     sd.set_state(u, v, w)
     sd.nut()
     del u, v, w
+    note(f"c4: {args.spinup} dynamic-model steps")
     t0 = time.perf_counter()
     run_steps(les, sd, args.spinup, use_graph)
     sd.synchronize()
     spin_s = time.perf_counter() - t0
+    note(f"c4: spin-up {spin_s:.1f} s; sampling {args.snapshots} snapshots")
     xs, ys = [], []
     for q in range(args.snapshots):
         run_steps(les, sd, 10, use_graph)
@@ -460,6 +519,7 @@ def learned_line(args, torch):
     Xn = torch.empty_like(X)
     les.les_mlp_normalize(sd.stream.cuda_stream, X.data_ptr(), X.shape[0], lo, hi, Xn.data_ptr())
     mlp = les.Mlp(initial_params(5), stream=sd.stream)
+    note("c4: training")
     B = 1 << 16
     nb = X.shape[0] // B
     total = args.epochs * nb
@@ -503,16 +563,16 @@ def learned_line(args, torch):
     cells = cfgd["nx"] * cfgd["ny"] * cfgd["nz"]
     thr = {}
     for name, s in (("dynamic", sd), ("learned", sm)):
-        run_steps(les, s, args.warmup, use_graph)
-        s.synchronize()
-        t0 = time.perf_counter()
-        run_steps(les, s, args.steps, use_graph)
-        s.synchronize()
-        el = time.perf_counter() - t0
-        thr[name] = (cells * 3 * args.steps / el / 1e6, el / args.steps * 1e3)
-    kernels, roof = kernel_report(les, sm.ctx, max(1, min(args.steps, 10)), cfgd["name"], cells,
-                                  cfgd["precision"] == 0)
+        note(f"c4: timing the {name} closure")
+        el, runs = timed_runs(les, s, args, use_graph)
+        thr[name] = (cells * 3 * args.steps / el / 1e6, el / args.steps * 1e3, runs)
+    nrep = max(1, min(args.steps, 10))
+    kernels, roof = kernel_report(les, sd.ctx, nrep, cfgd["name"], cells, cfgd["precision"] == 0)
+    kernels_m, _ = kernel_report(les, sm.ctx, nrep, cfgd["name"] + " learned", cells, cfgd["precision"] == 0)
+    mlp_us = kernels_m["mlp_nut"]["avg_us"]
+    mlp_tflops = cells * MLP_FLOPS_PER_CELL / (mlp_us * 1e-6) / 1e12
     # mean-profile comparison from the same state
+    note("c4: mean-profile comparison")
     torch.cuda.synchronize()
     for s in (sd, sm):
         with torch.cuda.stream(s.stream):
@@ -527,37 +587,56 @@ def learned_line(args, torch):
     prof_err = float((pm - pd).abs().max().item()) / cfgd["ubulk"]
     d1, _ = sd.diag()
     d2, _ = sm.diag()
+    value = thr["dynamic"][0]
     out = {
         "metric": METRIC,
-        "value": round(thr["learned"][0], 3),
+        "value": round(value, 3),
         "unit": "Mpts·substeps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(thr["learned"][1], 4),
+        "ms_per_step": round(thr["dynamic"][1], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": cfgd["dtype"],
         "data": "synthetic",
         "config": {"workload": cfgd["name"], "grid": [cfgd["nx"], cfgd["ny"], cfgd["nz"]],
-                   "substeps_per_step": 3, "graph": use_graph, "closure": "learned (BF16 MFMA) with dynamic fallback"},
+                   "substeps_per_step": 3, "graph": use_graph,
+                   "closure": "dynamic Smagorinsky (value); learned closure beside it (learned_closure)"},
+        "timed_runs_s": [round(r, 5) for r in thr["dynamic"][2]],
         "roofline": roof,
-        "substep_roofline": substep_roofline(thr["learned"][0], cfgd),
+        "substep_roofline": substep_roofline(value, cfgd),
         "kernels": kernels,
-        "dynamic_value": round(thr["dynamic"][0], 3),
-        "dynamic_ms_per_step": round(thr["dynamic"][1], 4),
-        "training": {"spinup_steps": args.spinup, "spinup_seconds": round(spin_s, 2), "snapshots": args.snapshots,
-                     "samples": nb * B, "epochs": args.epochs, "adam_steps": total,
-                     "seconds": round(train_s, 2), "final_batch_mse": final_loss, "target_variance": target_var},
-        "coefficient_error": {"plane_coefficient_rel_l2": coef_err, "plane_nut_rel_l2": nut_plane_err,
-                              "pointwise_nut_rel_rms": nut_point_err, "fallback_points": flagged},
-        "mean_profile": {"steps": args.compare_steps, "max_abs_diff_over_ub": prof_err,
-                         "max_div": [d1.max_div, d2.max_div], "ubulk": [d1.ubulk, d2.ubulk],
-                         "nonfinite": [int(d1.nonfinite), int(d2.nonfinite)]},
+        "learned_closure": {
+            "value": round(thr["learned"][0], 3), "unit": "Mpts·substeps/s",
+            "ms_per_step": round(thr["learned"][1], 4),
+            "timed_runs_s": [round(r, 5) for r in thr["learned"][2]],
+            "ratio_to_dynamic": round(thr["learned"][0] / value, 4),
+            "substep_roofline": substep_roofline(thr["learned"][0], cfgd),
+            "mlp_nut": {"bound": "mfma", "avg_launch_us": round(mlp_us, 3),
+                        "alg_flops_per_cell": MLP_FLOPS_PER_CELL,
+                        "achieved": round(mlp_tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(mlp_tflops / MFMA_BF16_PEAK_TFLOPS, 4)},
+            "kernels": kernels_m,
+            "training": {"spinup_steps": args.spinup, "spinup_seconds": round(spin_s, 2),
+                         "snapshots": args.snapshots, "samples": nb * B, "epochs": args.epochs,
+                         "adam_steps": total, "seconds": round(train_s, 2), "final_batch_mse": final_loss,
+                         "target_variance": target_var},
+            "coefficient_error": {"plane_coefficient_rel_l2": coef_err, "plane_nut_rel_l2": nut_plane_err,
+                                  "pointwise_nut_rel_rms": nut_point_err, "fallback_points": flagged},
+            "mean_profile": {"steps": args.compare_steps, "max_abs_diff_over_ub": prof_err,
+                             "max_div": [d1.max_div, d2.max_div], "ubulk": [d1.ubulk, d2.ubulk],
+                             "nonfinite": [int(d1.nonfinite), int(d2.nonfinite)]},
+        },
     }
     sd.close()
     sm.close()
+    if not args.no_cpu_baseline:
+        note("c4: CPU oracle (one thread, then threaded FFTs)")
+        out["cpu_baseline"] = cpu_baseline("c4", args.cpu_seconds)
+        workers = min(16, os.cpu_count() or 1)
+        out["cpu_baseline_fft_threads"] = cpu_baseline("c4", args.cpu_seconds, fft_workers=workers)
     return out
 
 
@@ -637,6 +716,10 @@ def batch_line(args, torch):
 
 def main():
     args = parse()
+    if args.cpu_leg is not None:
+        # child process of cpu_baseline: the oracle only, no GPU
+        print(json.dumps(cpu_leg(args.cpu_leg, args.cpu_seconds, args.fft_workers)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not "
               f"built in this library", file=sys.stderr)
@@ -657,7 +740,7 @@ def main():
     if args.config == "c5":
         out = batch_line(args, torch)
     elif args.config == "c4":
-        out = learned_line(args, torch)
+        out = c4_line(args, torch)
     else:
         out = solver_line(args, torch, CONFIGS[args.config])
     print(json.dumps(out), flush=True)

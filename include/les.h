@@ -134,7 +134,7 @@ typedef struct {
   double tauw_mean[2];       /* plane-mean tau_x at bottom / top wall (wall model)   */
   double dt;                 /* current time step in the device slot                 */
   int64_t nonfinite;         /* count of non-finite values in u, v, w, p             */
-  int64_t mlp_flagged;       /* learned closure: points that fell back last call     */
+  int64_t mlp_flagged;       /* learned closure: points that fell back in the last nu_t evaluation */
 } les_diag_t;
 
 /* Validate cfg, compute the grid metrics and solver tables on the host, and create a
@@ -254,9 +254,9 @@ les_status les_profile_error(const double* z, const double* phi, const double* r
 /* Use the network for nu_t (context created with sgs = LES_SGS_MLP; until this is called such
  * a context runs the dynamic model).  params must stay valid; lo, hi: host double[7], copied.
  * Points whose scaled inputs leave [-0.05, 1.05] take the dynamic-model coefficient of their
- * plane (of their x line in a duct) instead; the dynamic model is re-evaluated (on the
- * device, without host round trip) in every nu_t evaluation that follows one in which a
- * point fell back.  A range not much wider than the rounding of its input (an input constant
+ * plane (of their x line in a duct) instead, computed from the same velocity: the dynamic
+ * model runs (on the device, without host round trip) in every nu_t evaluation in which a
+ * point falls back, and only then.  A range not much wider than the rounding of its input (an input constant
  * over the grid, such as Delta on a uniform grid) makes the scaled input rounding noise:
  * give such an input a span of order one. */
 les_status les_mlp_bind(les_ctx* ctx, const float* params_dev, const double* lo, const double* hi);

@@ -483,8 +483,8 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       if ((s = up(c.t.twc, c.twc.data(), c.twc.size() * 8)) != LES_OK) return s;
       if ((s = up(c.t.twc_f, c.twc_f_host.data(), c.twc_f_host.size() * 4)) != LES_OK) return s;
       if ((s = up(c.t.hfac, c.hfac_host.data(), c.hfac_host.size() * 8)) != LES_OK) return s;
-      // learned closure: the first evaluation runs the dynamic model (fallback coefficients)
-      static const int cnt_init[2] = {0, 1};
+      // learned closure: fallback counters (cleared again by every evaluation)
+      static const int cnt_init[2] = {0, 0};
       if ((s = up(c.mlp_cnt, cnt_init, sizeof(cnt_init))) != LES_OK) return s;
       if (f.zbc != LES_ZBC_PERIODIC) {
         launch_thomas_factor(c);
@@ -717,7 +717,7 @@ les_status les_mlp_bind(les_ctx* ctx, const float* params, const double* lo, con
   les_status s = check_hip(c, hipMemcpyAsync(c.t.coef, c.delta2.data(), (c.cfg.nz + 2) * 8, hipMemcpyHostToDevice,
                                              c.stream), "mlp coef");
   if (s != LES_OK) return s;
-  static const int cnt_init[2] = {0, 1};
+  static const int cnt_init[2] = {0, 0};
   s = check_hip(c, hipMemcpyAsync(c.mlp_cnt, cnt_init, sizeof(cnt_init), hipMemcpyHostToDevice, c.stream), "mlp cnt");
   if (s != LES_OK) return s;
   if (c.graph_exec) {

@@ -570,7 +570,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       qb[1][e] = (T)0.5 * (A(1, 0, 0, 0) + A(1, 0, -1, 0));
       qb[2][e] = (T)0.5 * (A(2, 0, 0, 0) + A(2, -1, 0, 0));
       for (int a = 0; a < 6; ++a) qb[3 + a][e] = sm_ * s[a];
-      if (own && x >= 2 && x <= TX + 1 && y >= 2 && y <= TY + 1) {
+      if (nut != nullptr && own && x >= 2 && x <= TX + 1 && y >= 2 && y <= TY + 1) {
         const int i = i0 + x - 2, j = j0 + y - 2;
         if (i < g.nx && j < g.ny) store_nut(g, nut, p, j, i, sm_);
       }
@@ -826,13 +826,12 @@ __global__ void __launch_bounds__(256) k_wall_mean_partial(GridP g, const T* u, 
 
 // Stage 2: friction velocity of each wall, u_tau = sqrt(|(<tau_x>, <tau_y>)|), stored in
 // dt[2] (bottom) and dt[3] (top) (skipped without partials: ducts take the four-wall values
-// of the van Driest reduction); also rotates the learned closure's fallback counters:
-// cnt[0] = points that fell back in the previous evaluation (gate of the dynamic-model
-// fallback), cnt[1] = 0.
+// of the van Driest reduction); also clears the learned closure's fallback counter cnt[1]
+// (points of this evaluation that fall back; the inference kernel adds to it).
 __global__ void k_mlp_prep(GridP g, const double* part, double* dtp, int* cnt) {
   if (threadIdx.x != 0) return;
   if (cnt != nullptr) {
-    cnt[0] = cnt[1];
+    cnt[0] = 0;
     cnt[1] = 0;
   }
   if (part == nullptr) return;
@@ -934,9 +933,10 @@ __device__ inline void cell_features(const GridP& g, const T* u, const T* v, con
 // applied on wall ghost planes).  Per plane each thread forms the velocity-gradient tensor
 // of its cell (diagonal at the centre, off-diagonal terms as four-edge means, so S and O are
 // its symmetric and antisymmetric parts), the seven scaled inputs, and each wave of 64 cells
-// runs the network on the matrix cores.  c = max(0, MLP) or, for a cell whose scaled inputs
-// leave [-0.05, 1.05], the dynamic coefficient of its plane, or of its x line in a duct
-// (YW), counted; stores c |S|.
+// runs the network on the matrix cores.  Stores c |S| with c = max(0, MLP); a cell whose
+// scaled inputs leave [-0.05, 1.05] is counted and stores -|S| instead, a mark that
+// k_mlp_fallback replaces by the dynamic coefficient of its plane (of its x line in a duct,
+// YW) times |S| once the dynamic model of the same state has run (c |S| >= 0 elsewhere).
 namespace tiled {
 constexpr int TX = 32, TY = 8, NT = TX * TY;
 constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY;
@@ -945,7 +945,7 @@ constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY;
 template <typename T, bool YW>
 __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict__ u, const T* __restrict__ v,
                                                  const T* __restrict__ w, T* __restrict__ nut,
-                                                 const float* __restrict__ P, MlpNorm nm, const double* __restrict__ cs,
+                                                 const float* __restrict__ P, MlpNorm nm,
                                                  const double* __restrict__ ut, double ly, int* __restrict__ cnt,
                                                  int kc) {
   using namespace mlp;
@@ -1119,12 +1119,9 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
     const float yv = qq == 0 ? out.y[0] : (qq == 1 ? out.y[1] : (qq == 2 ? out.y[2] : out.y[3]));
     if (inside) {
       const T smag = strain_mag(s6);
-      double c = yv > 0.0f ? (double)yv : 0.0;
-      if (flag) {
-        c = YW ? cs[(int64_t)(pk - 1) * g.ny + j] : cs[pk - 1];
-        ++flagged;
-      }
-      store_nut(g, nut, pk, j, i, (T)c * smag);
+      const T c = yv > 0.0f ? (T)yv : (T)0;
+      if (flag) ++flagged;
+      store_nut(g, nut, pk, j, i, flag ? -smag : c * smag);
     }
     __syncthreads();
   }
@@ -1132,6 +1129,26 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
     for (int off = 32; off > 0; off >>= 1) flagged += __shfl_down(flagged, off, 64);
     if (lane == 0 && flagged) atomicAdd(&cnt[1], flagged);
   }
+}
+
+// Fallback of the learned closure: the cells k_mlp_nut marked (negative stored value -|S|)
+// take the dynamic coefficient of their plane (of their x line in a duct) computed from the
+// same velocity, c_s |S|, ghost planes included.  Runs only when the current evaluation
+// flagged a cell (gate = its counter); one thread per interior cell.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mlp_fallback(GridP g, T* __restrict__ nut, const double* __restrict__ cs,
+                                                      const int* __restrict__ gate) {
+  if (gate[0] == 0) return;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nxy = (int64_t)g.nx * g.ny;
+  if (e >= (int64_t)g.nz * nxy) return;
+  const int k = (int)(e / nxy) + 1;
+  const int64_t r = e % nxy;
+  const int j = (int)(r / g.nx), i = (int)(r % g.nx);
+  const T val = nut[idx3(g, k, j, i)];
+  if (!(val < (T)0)) return;
+  const double c = g.ywall ? cs[(int64_t)(k - 1) * g.ny + j] : cs[k - 1];
+  store_nut(g, nut, k, j, i, (T)c * -val);
 }
 
 // Training pairs: sample s sits at the interior cell hashed from (seed, s) (SplitMix64); x
@@ -1189,58 +1206,62 @@ void launch_eddy_viscosity(Ctx& c) {
   }
   if (model == LES_SGS_DSM || model == LES_SGS_MLP) {
     const bool learned = model == LES_SGS_MLP && c.mlp_params != nullptr;
-    const int* gate = learned ? c.mlp_cnt : nullptr;
+    // learned closure: the network runs first; the dynamic model of the same velocity runs
+    // only if that evaluation flagged a cell (gate = its fallback counter), without storing
+    // |S|, and k_mlp_fallback then fills the flagged cells from its coefficients
+    const int* gate = learned ? c.mlp_cnt + 1 : nullptr;
+    T* dsm_nut = learned ? nullptr : (T*)c.nut;
+    const int kc = c.dsm_kc;
+    dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + fused::TY - 1) / fused::TY, (g.nz + kc - 1) / kc);
     if (learned) {
+      MlpNorm nm;
+      for (int a = 0; a < 7; ++a) {
+        nm.lo[a] = c.mlp_lo[a];
+        nm.inv[a] = 1.0 / (c.mlp_hi[a] - c.mlp_lo[a]);
+      }
+      const int mkc = c.mlp_kc;
+      const dim3 tgrid((g.nx + tiled::TX - 1) / tiled::TX, (g.ny + tiled::TY - 1) / tiled::TY, (g.nz + mkc - 1) / mkc);
       if (g.ywall) {
         // ducts: the four walls' friction velocities of the van Driest reduction
         LES_LAUNCH(c, "vd_duct", 0, k_vd_duct_partial<T>, dim3(VD_BLOCKS), dim3(256), 0, g, (const T*)c.u,
                    (const T*)c.v, (const T*)c.w, c.t.tau, c.t.tauy, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
         LES_LAUNCH(c, "vd_duct_final", 0, k_vd_duct_final, dim3(1), dim3(64), 0, g, c.t.red, c.t.vd4);
         LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, (const double*)nullptr, c.t.dt, c.mlp_cnt);
+        LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), (k_mlp_nut<T, true>), tgrid, dim3(tiled::TX, tiled::TY), 0, g,
+                   (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm,
+                   (const double*)c.t.vd4, c.cfg.ly, c.mlp_cnt, mkc);
       } else {
         LES_LAUNCH(c, "wall_mean", 0, k_wall_mean_partial<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
                    (const T*)c.v, c.t.tau, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
         LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, c.t.red, c.t.dt, c.mlp_cnt);
+        LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), (k_mlp_nut<T, false>), tgrid, dim3(tiled::TX, tiled::TY), 0, g,
+                   (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm,
+                   (const double*)(c.t.dt + 2), c.cfg.ly, c.mlp_cnt, mkc);
       }
     }
-    const int kc = c.dsm_kc;
-    dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + fused::TY - 1) / fused::TY, (g.nz + kc - 1) / kc);
-    MlpNorm nm;
-    if (learned) {
-      for (int a = 0; a < 7; ++a) {
-        nm.lo[a] = c.mlp_lo[a];
-        nm.inv[a] = 1.0 / (c.mlp_hi[a] - c.mlp_lo[a]);
-      }
-    }
-    const int mkc = c.mlp_kc;
-    const dim3 tgrid((g.nx + tiled::TX - 1) / tiled::TX, (g.ny + tiled::TY - 1) / tiled::TY, (g.nz + mkc - 1) / mkc);
     if (g.ywall) {
       // ducts: coefficients along x lines
       LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), (k_dsm_fused<T, true>), grid, dim3(fused::TX, fused::TY), 0, g,
-                 (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.t.dsm_part, kc, gate);
+                 (const T*)c.u, (const T*)c.v, (const T*)c.w, dsm_nut, c.t.dsm_part, kc, gate);
       const int nl = g.nz * g.ny;
       LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce_lines, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, g,
                  c.t.dsm_part, (int)grid.x, c.t.cs, gate);
-      if (learned) {
-        LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), (k_mlp_nut<T, true>), tgrid, dim3(tiled::TX, tiled::TY), 0, g,
-                   (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm, c.t.cs,
-                   (const double*)c.t.vd4, c.cfg.ly, c.mlp_cnt, mkc);
-        return;
+      if (!learned) {
+        const int64_t ns = (int64_t)(g.nz + 2) * g.nx * g.ny;
+        LES_LAUNCH(c, "nut_lines", 2.0 * ns * sizeof(T), k_nut_lines<T>, dim3((unsigned)((ns + 255) / 256)), dim3(256),
+                   0, g, (T*)c.nut, (const double*)c.t.cs);
       }
-      const int64_t ns = (int64_t)(g.nz + 2) * g.nx * g.ny;
-      LES_LAUNCH(c, "nut_lines", 2.0 * ns * sizeof(T), k_nut_lines<T>, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0,
-                 g, (T*)c.nut, (const double*)c.t.cs);
-      return;
+    } else {
+      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, fused::TY), 0, g,
+                 (const T*)c.u, (const T*)c.v, (const T*)c.w, dsm_nut, c.t.dsm_part, kc, gate);
+      const int ntile = (int)(grid.x * grid.y) * fused::WV;
+      LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs,
+                 learned ? nullptr : c.t.coef, gate);
     }
-    LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, fused::TY), 0, g,
-               (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.t.dsm_part, kc, gate);
-    const int ntile = (int)(grid.x * grid.y) * fused::WV;
-    LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs,
-               learned ? nullptr : c.t.coef, gate);
     if (learned) {
-      LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), (k_mlp_nut<T, false>), tgrid, dim3(tiled::TX, tiled::TY), 0, g,
-                 (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm, c.t.cs,
-                 (const double*)(c.t.dt + 2), c.cfg.ly, c.mlp_cnt, mkc);
+      const int64_t ni = (int64_t)g.nz * g.nx * g.ny;
+      LES_LAUNCH(c, "mlp_fallback", 0, k_mlp_fallback<T>, dim3((unsigned)((ni + 255) / 256)), dim3(256), 0, g,
+                 (T*)c.nut, (const double*)c.t.cs, (const int*)gate);
     }
   }
 }

@@ -204,6 +204,73 @@ def test_fused_inference_matches_oracle(env, narrow):
     solver.close()
 
 
+def test_fallback_takes_the_current_coefficients(env):
+    """The fallback of a flagged cell is the dynamic coefficient of the state being evaluated
+    (R27), also in the first evaluation that flags anything after evaluations that flagged
+    nothing.  The y+ range is set so that its extreme values of the initial state sit just
+    inside the 5 % margin: the first evaluation flags no cell, and as the friction velocities
+    change over the substeps cells at one end leave the range.  After every substep the
+    library's eddy viscosity is compared with the oracle's learned closure evaluated on the
+    library's own state, whose fallback is the oracle's dynamic coefficient of that state."""
+    from tests.cases import CS_ROUNDING_K, UNIT_ROUNDOFF
+    from oracle.ops import strain_magnitude
+    les, torch = env
+    case_d, g, _ = _channel(env, SGS_DSM)
+    _, _, cfg_m = _channel(env, SGS_MLP)
+    u, v, w = initial_fields(case_d, g, 9, "channel")
+    st = S.initial_state(case_d, g, u, v, w)
+    ut0 = OS.friction_velocity(st.tau)
+    f = OM.raw_features(case_d, g, st.u, st.v, st.w, OS.model_strain(case_d, g, st.u, st.v, st.w), ut0)
+    f = f.reshape(-1, 7)
+    lo, hi = f.min(axis=0), f.max(axis=0)
+    hi = np.where(hi > lo, hi, lo + 1.0)
+    a, b, e = lo[5], hi[5], 1e-9
+    span = (b - a) / (1.1 - 2 * e)
+    lo[5] = a + span * (0.05 - e)
+    hi[5] = lo[5] + span
+    p = OM.init_params(21)
+    p["b3"][:] = 0.03
+    solver = les.Solver(cfg_m)
+    solver.set_state(u, v, w)
+    mlp = les.Mlp(OM.flatten(p), stream=solver.stream)
+    solver.mlp_bind(mlp, lo, hi)
+    solver.nut()
+    n = g.nz
+    I = slice(1, n + 1)
+    counts = []
+    for sub in range(7):
+        if sub > 0:
+            if (sub - 1) % 3 == 0:
+                solver.dt(0.5)
+            solver.substep((sub - 1) % 3)
+        gu, gv, gw, _ = solver.fields()
+        tau = solver.wall_stress()
+        ut = OS.friction_velocity(tuple(tau[q] for q in range(4)))
+        cs, _, _, _ = OS.dynamic_coefficient(case_d, g, gu, gv, gw)
+        ref, flags = OM.mlp_eddy_viscosity(case_d, g, gu, gv, gw, p, lo, hi, cs, ut, emulate_bf16=True)
+        nut = solver.eddy_viscosity()[I]
+        d, _ = solver.diag()
+        scale = np.max(np.abs(ref))
+        diff = np.abs(nut - ref)
+        counts.append(int(flags.sum()))
+        say(f"substep {sub}: flagged {counts[-1]} (gpu {d.mlp_flagged}), median {np.median(diff) / scale:.2e} "
+            f"max {diff.max() / scale:.2e}")
+        assert d.mlp_flagged == counts[-1]
+        assert np.median(diff) <= 2e-6 * scale
+        assert diff.max() <= 2e-3 * scale
+        if counts[-1]:
+            # flagged cells: the dynamic coefficient of this state, within its rounding bound
+            rs = OS.coefficient_rounding_scale(case_d, g, gu, gv, gw)
+            smag = strain_magnitude(OS.model_strain(case_d, g, gu, gv, gw))
+            allow = 1e-12 * scale + CS_ROUNDING_K * UNIT_ROUNDOFF * (rs * g.delta() ** 2)[:, None, None] * smag
+            assert np.all(diff[flags] <= allow[flags]), float(np.max(diff[flags] / allow[flags]))
+        if sub > 0 and counts[-1] and counts[-2] == 0:
+            break
+    assert counts[0] == 0
+    assert any(c > 0 for c in counts[1:]), counts
+    solver.close()
+
+
 def test_learned_closure_gains_over_constant_coefficient(env):
     """Train on dynamic-model coefficients produced by the GPU solver itself (channel, dynamic
     Smagorinsky + wall model + CN-z, six snapshots); on held-out cells of the same snapshots
