@@ -154,16 +154,17 @@ def test_filter_velocity(case, g, u, v, w):
     return uf, vf, wf
 
 
-def dynamic_coefficient(case, g, u, v, w):
-    """Dynamic procedure (Eqs. cs, lij, mij; Sec. 2.2 test-filter paragraph).
+PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))   # order of s: 11 22 33 12 13 23
+
+
+def germano_tensors(case, g, u, v, w):
+    """Steps 1-5 of the dynamic procedure (Eqs. lij, mij; Sec. 2.2 test-filter paragraph):
     1. velocities averaged to cell centres; 2. S_ij and |S| at centres;
     3. L_ij = F(uc_i uc_j) - F(uc_i) F(uc_j);
     4. S~_ij from the test-filtered staggered velocity with the same strain routine;
     5. M_ij = 2 Delta^2 [F(|S| S_ij) - alpha^2 |S~| S~_ij] with alpha^2 = 4 (alpha = 2 in
-       3-D) and alpha^2 = 4^(2/3) on the first off-wall layers (alpha = 4^(1/3));
-    6. c_s = <L_ij M_ij>/<M_ij M_ij> over each x-y plane (over the whole box when z is
-       periodic), clipped at zero; R10: c_s = 0 where <M M> = 0.
-    Returns (c_s per plane (nz,), |S| (nz, ny, nx), sum LM per plane, sum MM per plane)."""
+       3-D) and alpha^2 = 4^(2/3) on the first off-wall layers (alpha = 4^(1/3)).
+    Returns (L, M, |S|): L and M lists of six (nz, rows, nx) arrays in the order of PAIRS."""
     n = g.nz
     I, Im = slice(1, n + 1), slice(0, n)
     uc = 0.5 * (u[I] + xm(u[I]))
@@ -174,20 +175,32 @@ def dynamic_coefficient(case, g, u, v, w):
     F = lambda q: test_filter_centre(case, q, g)
     vel = (uc, vc, wc)
     fvel = [F(q) for q in vel]
-    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]   # order of s: 11 22 33 12 13 23
     uf, vf, wf = test_filter_velocity(case, g, u, v, w)
     st = model_strain(case, g, uf, vf, wf)
     stmag = strain_magnitude(st)
     delta2 = (g.delta() ** 2)[:, None, None]
     alpha2 = _alpha2(case, g)
+    L, M = [], []
+    for c, (a, b) in enumerate(PAIRS):
+        L.append(F(vel[a] * vel[b]) - fvel[a] * fvel[b])
+        M.append(2.0 * delta2 * (F(smag * s[c]) - alpha2 * stmag * st[c]))
+    return L, M, smag
+
+
+def dynamic_coefficient(case, g, u, v, w):
+    """Dynamic procedure (Eqs. cs, lij, mij; Sec. 2.2 test-filter paragraph): L_ij and M_ij
+    from germano_tensors, then
+    6. c_s = <L_ij M_ij>/<M_ij M_ij> over each x-y plane (over the whole box when z is
+       periodic), clipped at zero; R10: c_s = 0 where <M M> = 0.
+    Returns (c_s per plane (nz,), |S| (nz, ny, nx), sum LM per plane, sum MM per plane)."""
+    n = g.nz
+    L, M, smag = germano_tensors(case, g, u, v, w)
     lm = np.zeros_like(smag)
     mm = np.zeros_like(smag)
-    for c, (a, b) in enumerate(pairs):
-        L = F(vel[a] * vel[b]) - fvel[a] * fvel[b]
-        M = 2.0 * delta2 * (F(smag * s[c]) - alpha2 * stmag * st[c])
+    for c, (a, b) in enumerate(PAIRS):
         wgt = 1.0 if a == b else 2.0          # symmetric tensors: off-diagonals twice
-        lm += wgt * L * M
-        mm += wgt * M * M
+        lm += wgt * L[c] * M[c]
+        mm += wgt * M[c] * M[c]
     if case.zbc == ZBC_PERIODIC:
         slm = np.full(n, lm.sum())
         smm = np.full(n, mm.sum())

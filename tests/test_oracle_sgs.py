@@ -245,17 +245,122 @@ def _bruteforce_cs(case, g, u, v, w):
                         mm[k] += M * M
     if per:
         tl, tm = lm.sum(), mm.sum()
-        return np.full(nz, max(0.0, tl / tm) if tm > 0 else 0.0)
-    return np.array([max(0.0, lm[k] / mm[k]) if mm[k] > 0 else 0.0 for k in range(1, nz + 1)])
+        return np.full(nz, max(0.0, tl / tm) if tm > 0 else 0.0), np.full(nz, tl), np.full(nz, tm)
+    cs = np.array([max(0.0, lm[k] / mm[k]) if mm[k] > 0 else 0.0 for k in range(1, nz + 1)])
+    return cs, lm[1:], mm[1:]
 
 
 @pytest.mark.parametrize("zbc", [ZBC_PERIODIC, ZBC_NOSLIP, ZBC_WALLMODEL])
 def test_dsm_matches_plain_loops(zbc):
+    """The unclipped plane sums <L M> and <M M> (the volume sums when z is periodic) and the
+    clipped c_s of the vectorised oracle equal the plain loops.  The periodic field (seed 103)
+    has <L M> > 0, so its coefficient is not clipped away."""
     case = Case(5, 4, 6, 1.0, 1.3, 2.0, zbc=zbc, beta=1.1 if zbc else 0.0, nu=1e-3, sgs=SGS_DSM)
     g = Grid(case)
-    u, v, w, _ = random_state(5, 4, 6, 99)
-    u[1:7] += 2.0 * np.linspace(0, 1, 6)[:, None, None]    # some mean shear
+    u, v, w, _ = random_state(5, 4, 6, 103 if zbc == ZBC_PERIODIC else 99)
+    if zbc != ZBC_PERIODIC:
+        u[1:7] += 2.0 * np.linspace(0, 1, 6)[:, None, None]    # some mean shear
     u, v, w = _ghosted(case, g, u, v, w)
     cs, _, slm, smm = sgs.dynamic_coefficient(case, g, u, v, w)
-    ref = _bruteforce_cs(case, g, u, v, w)
+    ref, rlm, rmm = _bruteforce_cs(case, g, u, v, w)
+    assert np.allclose(slm, rlm, rtol=1e-11, atol=1e-14 * np.max(np.abs(rlm)))
+    assert np.allclose(smm, rmm, rtol=1e-11, atol=0)
     assert np.allclose(cs, ref, rtol=1e-11, atol=1e-15)
+    if zbc == ZBC_PERIODIC:
+        assert cs[0] > 0.0
+    else:
+        assert np.any(slm < 0) and np.any(cs > 0)
+
+
+# ------------------------------------------------------------------ closed forms of the filter and of L, M
+def _mode_phase(g, a, b, c):
+    """Phase 2 pi (a i/nx + b j/ny + c k/nz) of the cell-centred index grid (nz, ny, nx)."""
+    k, j, i = np.meshgrid(np.arange(1, g.nz + 1), np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    return 2 * np.pi * (a * i / g.nx + b * j / g.ny + c * k / g.nz)
+
+
+def _transfer(g, a, b, c):
+    """Transfer function of the (1/4, 1/2, 1/4) tensor-product filter on the mode (a, b, c):
+    1/2 + cos(theta)/2 = cos^2(theta/2) per direction."""
+    return (np.cos(np.pi * a / g.nx) * np.cos(np.pi * b / g.ny) * np.cos(np.pi * c / g.nz)) ** 2
+
+
+@pytest.mark.parametrize("mode", [(1, 0, 0), (0, 2, 0), (0, 0, 3), (2, 1, 1), (3, 2, 5)])
+def test_test_filter_transfer_function(mode):
+    """R7 pinned by its transfer function: on a triply periodic grid every Fourier mode is an
+    eigenfunction of the test filter with eigenvalue prod cos^2(pi m_d / N_d), for the
+    cell-centred quantities and for each staggered velocity component."""
+    case = Case(8, 6, 10, 1.0, 1.0, 1.0, zbc=ZBC_PERIODIC, sgs=SGS_DSM)
+    g = Grid(case)
+    ph = _mode_phase(g, *mode) + 0.3
+    q = np.cos(ph)
+    T = _transfer(g, *mode)
+    assert np.allclose(sgs.test_filter_centre(case, q, g), T * q, rtol=0, atol=1e-14)
+    u = np.zeros((g.nz + 2, g.ny, g.nx))
+    v, w = u.copy(), u.copy()
+    I = slice(1, g.nz + 1)
+    u[I], v[I], w[I] = np.cos(ph + 0.1), np.sin(ph), np.cos(ph - 0.7)
+    u, v, w = _ghosted(case, g, u, v, w)
+    uf, vf, wf = sgs.test_filter_velocity(case, g, u, v, w)
+    for f, a in ((uf, u), (vf, v), (wf, w)):
+        assert np.allclose(f[I], T * a[I], rtol=0, atol=1e-14)
+
+
+def test_leonard_tensor_closed_form():
+    """Eq. lij on two Fourier modes.  With centre velocities uc = A cos(p1), vc = B cos(p2)
+    and wc = 0 (u, v on their faces shifted by half a cell), products of modes are sums of
+    modes, so with T the filter's transfer function:
+      L11 = A^2/2 [1 - T(m1)^2 + (T(2 m1) - T(m1)^2) cos 2 p1],
+      L12 = AB/2 [T(m1 + m2) cos(p1 + p2) + T(m1 - m2) cos(p1 - p2)] - AB T(m1) T(m2) cos p1 cos p2,
+      L13 = L23 = L33 = 0."""
+    case = Case(8, 6, 10, 1.0, 1.3, 0.7, zbc=ZBC_PERIODIC, sgs=SGS_DSM)
+    g = Grid(case)
+    m1, m2 = (1, 1, 0), (2, 0, 1)
+    A, B = 1.3, -0.6
+    p1, p2 = _mode_phase(g, *m1) + 0.2, _mode_phase(g, *m2) - 0.4
+    u = np.zeros((g.nz + 2, g.ny, g.nx))
+    v, w = u.copy(), u.copy()
+    I = slice(1, g.nz + 1)
+    # u[i] sits half a cell in x after the centre, v[j] half a cell in y after it
+    ax, by = np.pi * m1[0] / g.nx, np.pi * m2[1] / g.ny
+    u[I] = A / np.cos(ax) * np.cos(p1 + ax)
+    v[I] = B / np.cos(by) * np.cos(p2 + by)
+    u, v, w = _ghosted(case, g, u, v, w)
+    L, _, _ = sgs.germano_tensors(case, g, u, v, w)
+    T = lambda m: _transfer(g, *m)
+    add = tuple(a + b for a, b in zip(m1, m2))
+    sub = tuple(a - b for a, b in zip(m1, m2))
+    dbl = tuple(2 * a for a in m1)
+    l11 = 0.5 * A * A * (1 - T(m1) ** 2 + (T(dbl) - T(m1) ** 2) * np.cos(2 * p1))
+    l12 = (0.5 * A * B * (T(add) * np.cos(p1 + p2) + T(sub) * np.cos(p1 - p2))
+           - A * B * T(m1) * T(m2) * np.cos(p1) * np.cos(p2))
+    l22 = 0.5 * B * B * (1 - T(m2) ** 2 + (T(tuple(2 * a for a in m2)) - T(m2) ** 2) * np.cos(2 * p2))
+    assert np.allclose(L[0], l11, rtol=0, atol=1e-14)
+    assert np.allclose(L[1], l22, rtol=0, atol=1e-14)
+    assert np.allclose(L[3], l12, rtol=0, atol=1e-14)
+    for c in (2, 4, 5):
+        assert np.all(L[c] == 0.0)
+
+
+@pytest.mark.parametrize("s0", [1.7, -0.8])
+def test_model_tensor_plane_sums_on_uniform_shear(s0):
+    """Eq. mij on u = S0 z (v = w = 0) between walls with uniform spacing and the wall model's
+    one-sided strain ghosts: every linear profile passes the test filter unchanged (its z
+    pass is the identity on the first layers, R9, and exact in between), so
+    S~ = S = S0/2 in the 13 slot, |S| = |S~| = |S0| and
+      M13 = 2 Delta^2 (1 - alpha^2) |S0| S0 / 2,  every other M_ij = 0,
+    giving <M M>_k = 2 nx ny Delta_k^4 (1 - alpha_k^2)^2 S0^4 with alpha^2 = 4 inside and
+    4^(2/3) on the first off-wall layers (2-D filter), and <L M>_k = 0 (M11 = 0 where
+    L11 = F(u^2) - F(u)^2 is not)."""
+    case = Case(6, 4, 8, 1.5, 0.9, 2.0, zbc=ZBC_WALLMODEL, beta=0.0, nu=1e-3, sgs=SGS_DSM)
+    g = Grid(case)
+    u, v, w = uniform_shear_field(6, 4, 8, g.zc, s0)
+    u, v, w = _ghosted(case, g, u, v, w)
+    _, _, slm, smm = sgs.dynamic_coefficient(case, g, u, v, w)
+    n = g.nz
+    alpha2 = np.full(n, 4.0)
+    alpha2[0] = alpha2[n - 1] = 4.0 ** (2.0 / 3.0)
+    d2 = (g.dx * g.dy * g.dzf[1:n + 1]) ** (2.0 / 3.0)
+    ref = 2.0 * g.nx * g.ny * d2 ** 2 * (1.0 - alpha2) ** 2 * s0 ** 4
+    assert np.allclose(smm, ref, rtol=1e-12, atol=0)
+    assert np.all(slm == 0.0)
