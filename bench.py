@@ -129,7 +129,7 @@ def cpu_leg(key, budget_s, fft_workers):
                        implicit_z=cfgd["implicit_z"] == 1, implicit_3d=cfgd["implicit_z"] == 2,
                        ubulk=cfgd["ubulk"], h_wm=cfgd.get("h_wm", 0.0), ybc=cfgd.get("ybc", 0))
     g = oracle.Grid(case)
-    u, v, w = initial_fields(cfgd, g.zc)
+    u, v, w = S.initial_projection(case, g, *initial_fields(cfgd, g.zc))
     st = S.initial_state(case, g, u, v, w)
     dt = S.time_step(case, g, st, cfl=0.5)
     del u, v, w
@@ -331,6 +331,7 @@ def learned_closure(les, torch, cfgd, solver, args, use_graph):
     zf, zc = s2.zgrid()
     u, v, w = initial_fields(cfgd, zc)
     s2.set_state(u, v, w)
+    s2.project()
     s2.mlp_bind(mlp, lo, hi)
     s2.nut()
     ctx = s2.ctx
@@ -390,6 +391,7 @@ def precision_check(les, torch, cfgd, steps):
     u, v, w = (a.astype(np.float32).astype(np.float64) for a in (u, v, w))
     for s in (s64, s32):
         s.set_state(u, v, w)
+        s.project()
         s.nut()
     del u, v, w
     secs = {}
@@ -419,6 +421,7 @@ def solver_line(args, torch, cfgd):
     zf, zc = solver.zgrid()
     u, v, w = initial_fields(cfgd, zc)
     solver.set_state(u, v, w)
+    solver.project()
     solver.nut()
     del u, v, w
     ctx = solver.ctx
@@ -496,6 +499,7 @@ def c4_line(args, torch):
     zf, zc = sd.zgrid()
     u, v, w = initial_fields(cfgd, zc)
     sd.set_state(u, v, w)
+    sd.project()
     sd.nut()
     del u, v, w
     note(f"c4: {args.spinup} dynamic-model steps")
@@ -651,8 +655,19 @@ def batch_line(args, torch):
     ens = box_ensemble(cfgd["nbox"], seed=cfgd["seed"])
     cfgs = [les.make_config(e["n"], e["n"], e["n"], two_pi, two_pi, two_pi, zbc=0, nu=e["nu"], sgs=3, cs=0.17,
                             implicit_z=0, precision=1) for e in ens]
+    # initial fields made discretely divergence-free by the library's projection, one
+    # single-box context per box size
+    projector, init = {}, []
+    for e, cfg in zip(ens, cfgs):
+        if e["n"] not in projector:
+            projector[e["n"]] = les.Solver(cfg)
+        s = projector[e["n"]]
+        s.set_state(*isotropic_field(e["n"], seed=e["seed"], k0=e["k0"]))
+        s.project()
+        init.append(s.fields()[:3])
+    for s in projector.values():
+        s.close()
     b = les.Batch(cfgs)
-    init = [isotropic_field(e["n"], seed=e["seed"], k0=e["k0"]) for e in ens]
 
     def load():
         for i, (u, v, w) in enumerate(init):

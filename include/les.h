@@ -182,6 +182,15 @@ les_status les_step(les_ctx* ctx, int use_graph);
  * filled.  Uses the workspace. */
 les_status les_poisson(les_ctx* ctx, void* f_inout);
 
+/* Initial fields: make the bound velocity discretely divergence-free by one projection with
+ * the substep's own operators (Eq. poi and Eq. correc without the time factor gamma_k dt):
+ * phi solves D G phi = D u with zero flux through walls (or periodic z), then u -= G phi, the
+ * wall faces of w (and of v in a duct) staying zero.  With a constant flow rate (ubulk > 0) u
+ * is then shifted uniformly so that its volume mean (sum u dzf / (nx ny lz)) is ubulk.  Only
+ * interior values change.  Enqueued; uses the workspace (spectrum, pressure correction); call
+ * les_nut afterwards (les_substep returns LES_ESTATE until then). */
+les_status les_project(les_ctx* ctx);
+
 /* Copy a readable quantity (LES_FIELD_NUT, _CS, _TAUW to device memory dst; _ZGRID to
  * host memory dst).  Enqueued, except _ZGRID which is immediate. */
 les_status les_read(les_ctx* ctx, int field, void* dst);

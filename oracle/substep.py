@@ -364,6 +364,39 @@ def substep(case, g, st, k, dt):
     return new
 
 
+def initial_projection(case, g, u, v, w):
+    """Initial fields made discretely divergence-free by one projection with the substep's
+    operators (Eq. poi and Eq. correc without the time factor): phi solves D(G phi) = D u with
+    zero flux through walls (or periodic z), u <- u - G phi, the wall faces of w (and of v in a
+    duct) at rest.  With a constant flow rate u is then shifted uniformly so that its volume
+    mean is U_b (Sec. 4.2 forcing target).  Returns new interior-valued (u, v, w) in the
+    ghosted layout (ghost planes zero, to be filled by initial_state)."""
+    n = g.nz
+    I = slice(1, n + 1)
+    us, vs, ws = u.copy(), v.copy(), w.copy()
+    if case.zbc == ZBC_PERIODIC:
+        bc.fill_velocity(case, g, us, vs, ws)
+    else:
+        ws[0] = ws[n] = ws[n + 1] = 0.0
+    if g.ywalls:
+        vs[:, g.ny - 1:] = 0.0
+    phi = np.zeros_like(us)
+    phi[I] = poisson.solve(g, ops.divergence(g, us, vs, ws))
+    bc.fill_scalar(case, g, phi)
+    gx, gy, gz = ops.gradient(g, phi)
+    ou, ov, ow = np.zeros_like(u), np.zeros_like(v), np.zeros_like(w)
+    ou[I], ov[I], ow[I] = us[I] - gx, vs[I] - gy, ws[I] - gz
+    if case.zbc != ZBC_PERIODIC:
+        ow[n] = 0.0
+    if g.ywalls:
+        ov[:, g.ny - 1:] = 0.0
+        for a in (ou, ow):
+            a[:, g.ny:] = 0.0
+    if case.ubulk > 0.0:
+        ou[I, :g.ny] += case.ubulk - bulk_velocity(g, ou)
+    return ou, ov, ow
+
+
 def initial_state(case, g, u, v, w, p=None):
     """Alg. 1 lines 1-2: take the initial velocity (and pressure), fill ghosts, compute nu_t."""
     st = State(u.copy(), v.copy(), w.copy(), np.zeros_like(u) if p is None else p.copy())

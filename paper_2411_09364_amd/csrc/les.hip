@@ -602,6 +602,17 @@ les_status les_poisson(les_ctx* ctx, void* f) {
   return check_launch(c, "les_poisson");
 }
 
+les_status les_project(les_ctx* ctx) {
+  if (!ctx) return LES_EINVAL;
+  Ctx& c = ctx->c;
+  les_status s = ready(c, false);
+  if (s != LES_OK) return s;
+  if (c.cfg.precision == LES_MIXED) launch_project<float>(c);
+  else launch_project<double>(c);
+  c.initialised = false;   // the eddy viscosity and ghosts of the new velocity come from les_nut
+  return check_launch(c, "les_project");
+}
+
 les_status les_read(les_ctx* ctx, int field, void* dst) {
   if (!ctx) return LES_EINVAL;
   Ctx& c = ctx->c;

@@ -233,6 +233,7 @@ template <typename T> void launch_fill_y_scalar(Ctx& c, T* f, double sign);
 template <typename T> void launch_eddy_viscosity(Ctx& c);
 template <typename T> void launch_dt(Ctx& c, double cfl);
 template <typename T> void launch_poisson_field(Ctx& c, T* f);
+template <typename T> void launch_project(Ctx& c);
 template <typename T> void launch_read_nut(Ctx& c, T* dst);
 template <typename T> void launch_diag(Ctx& c, double* out_dev);
 template <typename T> void launch_mlp_sample(Ctx& c, uint64_t seed, int64_t n, float* x, float* y);

@@ -263,7 +263,8 @@ __device__ __forceinline__ void rfftx_body(dim3 bid, GridP g, const FftPlan& P, 
   const int nx = g.nx, nxh = nx / 2 + 1, nyh = g.ny / 2;
   cpx<T>* B = A + npair_blk * nx;
   const int64_t npairs = (int64_t)g.nz * nyh;
-  const T scale = MODE == 0 ? (T)(1.0 / (gamma * dtp[0])) : (T)1;
+  // gamma = 0: the plain divergence (initial projection), no time factor
+  const T scale = (MODE == 0 && gamma > 0.0) ? (T)(1.0 / (gamma * dtp[0])) : (T)1;
   double bsum = 0.0;
   for (int e = threadIdx.x; e < npair_blk * nx; e += blockDim.x) {
     const int p = e / nx, i = e % nx;
@@ -1085,6 +1086,92 @@ void launch_poisson_field(Ctx& c, T* f) {
   if (c.g.ywall) launch_fill_y_scalar<T>(c, f, 1.0);
 }
 
+// ============================================================================ initial projection
+// One projection of the bound velocity with the substep's operators (Eqs. poi, correc without
+// the time factor): phi solves D G phi = D u, u -= G phi; with a constant flow rate the
+// streamwise velocity is then shifted uniformly so that its volume mean is U_b.  The interior
+// cells are cut into PROJ_BLOCKS contiguous chunks, one block each, so that the flow-rate sum
+// runs in a fixed order.
+constexpr int PROJ_BLOCKS = 64;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_project_correct(GridP g, T* __restrict__ u, T* __restrict__ v,
+                                                         T* __restrict__ w, const T* __restrict__ phi,
+                                                         double* __restrict__ part) {
+  __shared__ double red[256];
+  const int64_t nxy = (int64_t)g.nx * g.ny;
+  const int64_t total = (int64_t)g.nz * nxy;
+  const int64_t chunk = (total + PROJ_BLOCKS - 1) / PROJ_BLOCKS;
+  const int64_t e0 = blockIdx.x * chunk, e1 = e0 + chunk < total ? e0 + chunk : total;
+  const bool walls = g.zbc != LES_ZBC_PERIODIC;
+  double su = 0.0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int k = (int)(e / nxy) + 1;
+    const int64_t r = e % nxy;
+    const int i = (int)(r % g.nx), j = (int)(r / g.nx);
+    const int64_t c = idx3(g, k, j, i);
+    const T ph = phi[c];
+    const T un = u[c] - (phi[idx3(g, k, j, wrap_p(i, g.nx))] - ph) * (T)g.rdx;
+    u[c] = un;
+    // the y wall face y = ly of a duct (row ny - 1) and the z wall face on top stay at rest
+    v[c] = (g.ywall && j == g.ny - 1) ? (T)0 : v[c] - (phi[idx3(g, k, wrap_p(j, g.nys), i)] - ph) * (T)g.rdy;
+    w[c] = (walls && k == g.nz) ? (T)0 : w[c] - (phi[c + g.sxy] - ph) * (T)g.rdzc[k];
+    su += (double)un * g.dzf[k];
+  }
+  red[threadIdx.x] = su;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// u += U_b - <u> on every interior cell; each block sums the chunk partials in block order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_project_shift(GridP g, T* __restrict__ u, const double* __restrict__ part,
+                                                       double ubulk, double lz) {
+  __shared__ double shift;
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int b = 0; b < PROJ_BLOCKS; ++b) a += part[b];
+    shift = ubulk - a / ((double)g.nx * g.ny * lz);
+  }
+  __syncthreads();
+  const T s = (T)shift;
+  const int64_t nxy = (int64_t)g.nx * g.ny;
+  const int64_t total = (int64_t)g.nz * nxy;
+  const int64_t chunk = (total + PROJ_BLOCKS - 1) / PROJ_BLOCKS;
+  const int64_t e0 = blockIdx.x * chunk, e1 = e0 + chunk < total ? e0 + chunk : total;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int k = (int)(e / nxy) + 1;
+    const int64_t r = e % nxy;
+    u[(int64_t)k * g.sxy + r] += s;
+  }
+}
+
+template <typename T>
+void launch_project(Ctx& c) {
+  T* u = (T*)c.u;
+  T* v = (T*)c.v;
+  T* w = (T*)c.w;
+  T* phi = (T*)c.phi;
+  launch_bc_fill<T>(c, u, v, w, (T*)c.p);   // wall faces of w (and the periodic copies)
+  if (c.g.ywall) launch_bc_fill_y<T>(c, u, v, w, (T*)c.p);
+  fwd_x<T>(c, 0, u, v, w, nullptr, 0.0, false);
+  spectral_solve<T>(c);
+  inv_x<T>(c, phi);
+  LES_LAUNCH(c, "scalar_ghosts", 4.0 * c.g.sxy * sizeof(T), k_scalar_ghosts<T>, dim3((unsigned)((c.g.sxy + 255) / 256)),
+             dim3(256), 0, c.g, phi);
+  if (c.g.ywall) launch_fill_y_scalar<T>(c, phi, 1.0);
+  const double cells = (double)c.g.nx * c.g.ny * c.g.nz;
+  LES_LAUNCH(c, "project_correct", 7.0 * cells * sizeof(T), k_project_correct<T>, dim3(PROJ_BLOCKS), dim3(256), 0,
+             c.g, u, v, w, (const T*)phi, c.t.red);
+  if (c.cfg.ubulk > 0.0)
+    LES_LAUNCH(c, "project_shift", 2.0 * cells * sizeof(T), k_project_shift<T>, dim3(PROJ_BLOCKS), dim3(256), 0, c.g,
+               u, (const double*)c.t.red, c.cfg.ubulk, c.cfg.lz);
+}
+
 // ============================================================================ batch launchers
 template <typename T>
 void batch_poisson(hipStream_t st, const BatchMap& m, const int* totals, size_t sh_x, size_t sh_y, size_t sh_z,
@@ -1107,6 +1194,7 @@ int fft_lines_per_block(int n) { return lines_per_block(n); }
   template void launch_poisson_solve_spectral<T>(Ctx&);                                      \
   template void launch_poisson_inverse<T>(Ctx&, T*);                                         \
   template void launch_poisson_field<T>(Ctx&, T*);                                          \
+  template void launch_project<T>(Ctx&);                                                     \
   template void launch_helmholtz_3d<T>(Ctx&, int);
 INST(double)
 INST(float)

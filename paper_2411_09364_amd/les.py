@@ -79,6 +79,7 @@ def _load():
         "les_substep": [vp, i32],
         "les_step": [vp, i32],
         "les_poisson": [vp, vp],
+        "les_project": [vp],
         "les_read": [vp, i32, vp],
         "les_diag": [vp, ctypes.POINTER(LesDiag)],
         "les_mlp_bind": [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
@@ -131,7 +132,7 @@ LIB = _load()
 def exported_symbols():
     """Names of the ABI functions the binding resolves (all must exist in the library)."""
     return ["les_init", "les_layout", "les_bind", "les_nut", "les_dt", "les_set_dt", "les_substep",
-            "les_step", "les_poisson", "les_read", "les_diag", "les_mlp_bind", "les_mlp_sample",
+            "les_step", "les_poisson", "les_project", "les_read", "les_diag", "les_mlp_bind", "les_mlp_sample",
             "les_mlp_normalize", "les_mlp_forward", "les_mlp_workspace_bytes", "les_mlp_grad",
             "les_mlp_adam", "les_mlp_train_step", "les_free", "les_strerror", "les_last_error",
             "les_timing", "les_timing_report", "les_batch_init", "les_batch_layout", "les_batch_offset",
@@ -196,6 +197,10 @@ def les_step(ctx, use_graph=False):
 
 def les_poisson(ctx, ptr):
     _check(ctx, LIB.les_poisson(ctx, ctypes.c_void_p(ptr)), "les_poisson")
+
+
+def les_project(ctx):
+    _check(ctx, LIB.les_project(ctx), "les_project")
 
 
 def les_read(ctx, field, ptr):
@@ -380,6 +385,10 @@ class Solver:
                 else:
                     dst.copy_(torch.as_tensor(src, dtype=self.dtype))
         self.stream.synchronize()
+
+    def project(self):
+        """Initial projection of the bound velocity (les_project); call nut() afterwards."""
+        les_project(self.ctx)
 
     def nut(self):
         les_nut(self.ctx)

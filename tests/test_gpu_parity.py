@@ -51,6 +51,8 @@ POISSON_CASES = [
     # long strided lines: the in-place transform with wide line groups (y, and z periodic)
     dict(nx=16, ny=512, nz=6, lx=1.0, ly=4.0, lz=2.0, zbc=ZBC_NOSLIP, beta=1.2),
     dict(nx=8, ny=8, nz=384, lx=1.0, ly=1.0, lz=3.0, zbc=ZBC_PERIODIC),
+    # the longest x rows the library accepts (the 134M-cell channel's row length)
+    dict(nx=1024, ny=8, nz=6, lx=2 * TWO_PI, ly=np.pi / 4, lz=2.0, zbc=ZBC_NOSLIP, beta=1.5),
 ]
 
 
@@ -163,6 +165,9 @@ SUBSTEP_CASES = [
     ("cn-3d periodic long z",
      dict(nx=8, ny=8, nz=768, lx=1.0, ly=1.0, lz=12.0, nu=5e-2, sgs=SGS_SMAG, implicit_3d=True),
      "random", 3),
+    ("wm cn-z dsm 1024-point rows",
+     dict(nx=1024, ny=8, nz=6, lx=2 * TWO_PI, ly=np.pi / 4, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=5e-5,
+          sgs=SGS_DSM, implicit_z=True, ubulk=1.0), "channel", 3),
     ("cn-3d wm fewest planes h_wm",
      dict(nx=16, ny=8, nz=4, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.0, nu=1e-3,
           sgs=SGS_SMAG_VD, cs=0.1, h_wm=0.6, implicit_3d=True, ubulk=1.0), "channel", 3),
@@ -236,6 +241,10 @@ MIXED_CASES = [
                                 beta=1.5, nu=5e-4, sgs=SGS_DSM, implicit_3d=True, ubulk=1.0), "channel"),
     ("mixed cn-3d periodic", dict(nx=24, ny=24, nz=24, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, nu=2e-2,
                                   sgs=SGS_SMAG, implicit_3d=True), "iso"),
+    # the 134M-cell channel's row length (1024-point x transforms in float)
+    ("mixed 1024-point rows dsm wm explicit",
+     dict(nx=1024, ny=8, nz=6, lx=2 * TWO_PI, ly=np.pi / 4, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=1.6e-5,
+          sgs=SGS_DSM, ubulk=1.0), "channel"),
 ]
 
 
@@ -262,4 +271,43 @@ def test_mixed_precision_substeps(les, name, cfgd, kind):
         say(f"  substep {k}: " + " ".join(f"{a}={b:.2e}" for a, b in errs.items()))
         for a, e in errs.items():
             assert e < 1e-5, (k, a, e)
+    solver.close()
+
+
+PROJECT_CASES = [
+    ("iso", dict(nx=24, ny=24, nz=24, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, sgs=SGS_SMAG), "iso", 0),
+    ("channel wm", dict(nx=96, ny=24, nz=20, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=5e-5,
+                        sgs=SGS_DSM, implicit_z=True, ubulk=1.0), "channel", 0),
+    ("channel mixed", dict(nx=48, ny=24, nz=20, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5,
+                           nu=1.6e-5, sgs=SGS_DSM, ubulk=1.0), "channel", 1),
+]
+
+
+@pytest.mark.parametrize("name,cfgd,kind,precision", PROJECT_CASES, ids=[c[0] for c in PROJECT_CASES])
+def test_initial_projection_matches_oracle(les, name, cfgd, kind, precision):
+    """les_project against oracle.substep.initial_projection on the same seeded field, then
+    the library's own divergence check (les_diag) on the projected state."""
+    say("projection case", name)
+    case, g, cfg = make_pair(precision=precision, **dict(cfgd))
+    u, v, w = initial_fields(case, g, 5, kind)
+    if precision:
+        u, v, w = round32(u, v, w)
+    ru, rv, rw = S.initial_projection(case, g, u, v, w)
+    solver = les.Solver(cfg)
+    solver.set_state(u, v, w)
+    solver.project()
+    solver.nut()
+    gu, gv, gw, _ = solver.fields()
+    I = slice(1, g.nz + 1)
+    tol = 1e-5 if precision else 1e-12
+    errs = dict(u=rel_err(gu, ru, I), v=rel_err(gv, rv, I), w=rel_err(gw, rw, I))
+    d, _ = solver.diag()
+    say("  " + " ".join(f"{a}={b:.2e}" for a, b in errs.items()) + f" max|Du|={d.max_div:.2e} U_b={d.ubulk!r}")
+    for a, e in errs.items():
+        assert e < tol, (a, e)
+    umax = max(np.max(np.abs(ru[I])), np.max(np.abs(rw[I])))
+    hmin = min(g.dx, g.dy, np.min(g.dzf[I]))
+    assert d.max_div <= (1e-5 if precision else 1e-12) * umax / hmin
+    if case.ubulk > 0:
+        assert abs(d.ubulk - case.ubulk) <= (1e-6 if precision else 1e-13)
     solver.close()

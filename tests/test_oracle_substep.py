@@ -313,3 +313,61 @@ def test_pressure_update_fully_implicit_identity():
     lhs = p[I] - st.p[I] - phi[I]
     assert np.max(np.abs(lhs + 0.5 * case.nu * div)) < 1e-12 * max(1.0, np.max(np.abs(div)))
     assert np.max(np.abs(div)) > 1e-3          # the identity is not trivially zero
+
+
+# ------------------------------------------------------------------ initial projection
+@pytest.mark.parametrize("kind", ["iso", "channel", "duct"])
+def test_initial_projection(kind):
+    """The initial fields' projection: the result is discretely divergence-free (to the
+    Poisson solve's rounding), has the prescribed flow rate, leaves an already
+    divergence-free field unchanged up to the flow-rate shift (projecting twice equals
+    projecting once), and removes a gradient: the removed part is orthogonal to the result,
+    sum(u_new . (u - u_new)) dV = 0, since D u_new = 0 and (u - u_new) = G phi."""
+    from oracle import ops
+    from oracle.case import YBC_WALL
+    from synth import isotropic_field, channel_field, duct_field
+    if kind == "iso":
+        case = Case(12, 12, 12, 2 * np.pi, 2 * np.pi, 2 * np.pi, nu=1e-3)
+        g = Grid(case)
+        u, v, w = isotropic_field(12, seed=1)
+    elif kind == "channel":
+        case = Case(16, 8, 10, 2 * np.pi, np.pi, 2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=5e-4, ubulk=1.0)
+        g = Grid(case)
+        u, v, w = channel_field(16, 8, 10, g.zc, seed=2)
+    else:
+        case = Case(12, 8, 6, 3.0, 2.0, 2.0, zbc=ZBC_WALLMODEL, nu=5e-4, ubulk=1.0, ybc=YBC_WALL)
+        g = Grid(case)
+        u, v, w = duct_field(12, 8, 6, g.zc, 2.0, 2.0, seed=3)
+    pu, pv, pw = S.initial_projection(case, g, u, v, w)
+    n = g.nz
+    I, J = slice(1, n + 1), slice(0, g.ny)
+
+    def div(a, b, c):
+        a, b, c = a.copy(), b.copy(), c.copy()
+        if case.zbc == ZBC_PERIODIC:
+            for f in (a, b, c):
+                f[0], f[n + 1] = f[n], f[1]
+        if g.ywalls:
+            b[:, g.ny + 1] = 0.0
+        return ops.divergence(g, a, b, c)[:, J]
+
+    scale = max(np.max(np.abs(pu[I])), np.max(np.abs(pw[I])))
+    hmin = min(g.dx, g.dy, np.min(g.dzf[I]))
+    assert np.max(np.abs(div(pu, pv, pw))) <= 1e-12 * scale / hmin
+    assert np.max(np.abs(div(u, v, w))) > 1e-3 * scale / hmin       # the input was not
+    if case.ubulk > 0:
+        assert abs(S.bulk_velocity(g, pu) - case.ubulk) <= 1e-14
+    qu, qv, qw = S.initial_projection(case, g, pu, pv, pw)
+    for a, b in ((qu, pu), (qv, pv), (qw, pw)):
+        assert np.max(np.abs(a[I, J] - b[I, J])) <= 1e-12 * scale
+    # orthogonality of the removed gradient (volume weights dx dy dzf at u, v; dzc at w)
+    dzf = g.dzf[I][:, None, None]
+    dzc = g.dzc[1:n + 1][:, None, None]
+    # u - u_new = G phi minus the uniform flow-rate shift; G phi has zero mean in periodic x
+    ru = u[I, J] - pu[I, J]
+    if case.ubulk > 0:
+        ru = ru - (ru * dzf).sum() / (dzf.sum() * g.nx * g.ny)
+    rv, rw = v[I, J] - pv[I, J], w[I, J] - pw[I, J]
+    inner = (np.sum(pu[I, J] * ru * dzf) + np.sum(pv[I, J] * rv * dzf) + np.sum(pw[I, J] * rw * dzc))
+    norm = np.sum(pu[I, J] ** 2 * dzf) + np.sum(pv[I, J] ** 2 * dzf) + np.sum(pw[I, J] ** 2 * dzc)
+    assert abs(inner) <= 1e-12 * norm
