@@ -216,56 +216,6 @@ def dynamic_coefficient(case, g, u, v, w):
     return cs, smag, slm, smm
 
 
-def coefficient_rounding_scale(case, g, u, v, w):
-    """First-order size of the rounding error of c_s(k), in units of the unit roundoff.
-    c_s = <L M>/<M M> is built from differences that cancel: L_ij = F(uc_i uc_j) -
-    F(uc_i) F(uc_j) and M_ij = 2 Delta^2 (F(|S| S_ij) - alpha^2 |S~| S~_ij).  A relative
-    perturbation of size u in each term of those differences moves the plane sums by at most
-      u A_k,  A_k = sum w [(|F(uc_i uc_j)| + |F(uc_i) F(uc_j)|) |M_ij| + |L_ij| Ma_ij],
-      u B_k,  B_k = 2 sum w |M_ij| Ma_ij,   Ma_ij = 2 Delta^2 (|F(|S| S_ij)| + alpha^2 |S~ S~_ij|),
-    so |delta c_s(k)| <~ u (A_k + c_s(k) B_k) / <M M>_k (clipped or not).  Returns
-    (A_k + c_s B_k) / <M M>_k per plane (0 where <M M> = 0); an error-analysis aid for
-    comparing two implementations, not part of the model."""
-    n = g.nz
-    I, Im = slice(1, n + 1), slice(0, n)
-    uc = 0.5 * (u[I] + xm(u[I]))
-    vc = 0.5 * (v[I] + ym(v[I]))
-    wc = 0.5 * (w[I] + w[Im])
-    s = model_strain(case, g, u, v, w)
-    smag = strain_magnitude(s)
-    F = lambda q: test_filter_centre(case, q, g)
-    vel = (uc, vc, wc)
-    fvel = [F(q) for q in vel]
-    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
-    uf, vf, wf = test_filter_velocity(case, g, u, v, w)
-    st = model_strain(case, g, uf, vf, wf)
-    stmag = strain_magnitude(st)
-    delta2 = (g.delta() ** 2)[:, None, None]
-    alpha2 = _alpha2(case, g)
-    a = np.zeros_like(smag)
-    b = np.zeros_like(smag)
-    lm = np.zeros_like(smag)
-    mm = np.zeros_like(smag)
-    for c, (i, j) in enumerate(pairs):
-        fuu, fufu = F(vel[i] * vel[j]), fvel[i] * fvel[j]
-        fss, sts = F(smag * s[c]), alpha2 * stmag * st[c]
-        L = fuu - fufu
-        M = 2.0 * delta2 * (fss - sts)
-        Ma = 2.0 * delta2 * (np.abs(fss) + np.abs(sts))
-        wgt = 1.0 if i == j else 2.0
-        a += wgt * ((np.abs(fuu) + np.abs(fufu)) * np.abs(M) + np.abs(L) * Ma)
-        b += wgt * 2.0 * np.abs(M) * Ma
-        lm += wgt * L * M
-        mm += wgt * M * M
-    if g.ywalls:
-        sa, sb, slm, smm = (q.sum(axis=2) for q in (a, b, lm, mm))
-    else:
-        ax = None if case.zbc == ZBC_PERIODIC else (1, 2)
-        sa, sb, slm, smm = (np.broadcast_to(q.sum(axis=ax), (n,)) for q in (a, b, lm, mm))
-    cs = np.where(smm > 0.0, np.maximum(slm / np.where(smm > 0.0, smm, 1.0), 0.0), 0.0)
-    return np.where(smm > 0.0, (sa + cs * sb) / np.where(smm > 0.0, smm, 1.0), 0.0)
-
-
 def _alpha2(case, g):
     """alpha^2 per cell (n, rows, 1): 4 for the 3-D test filter; 4^(2/3) where the filter is
     2-D (the first off-wall layer of one wall pair, R9); 2^(2/3) where it is 1-D (a duct's

@@ -65,38 +65,25 @@ def round32(*arrs):
     return tuple(np.asarray(a, dtype=np.float32).astype(np.float64) for a in arrs)
 
 
-# Constant of the first-order rounding bound of the dynamic coefficient: covers the 27-term
-# test-filter sums and the depth of the plane sums (pairwise on the CPU, tree on the GPU).
-CS_ROUNDING_K = 64.0
 UNIT_ROUNDOFF = 2.0 ** -53
 
 
 def dsm_nut_check(case, g, st, nut, rel=1e-12):
-    """Compare a dynamic-model nu_t with the oracle's plane by plane (x line by x line in a
-    duct): the allowed difference on plane k is rel * max|nu_t| plus the propagated rounding
-    bound of c_s(k)
-    (oracle.sgs.coefficient_rounding_scale) times Delta_k^2 max|S| on that plane.
-    Returns (ok, worst ratio of difference to allowance, largest bound-only allowance
-    relative to max|nu_t|)."""
-    from oracle import sgs
-    from oracle.ops import strain_magnitude
+    """Compare a dynamic-model nu_t with the oracle's cell by cell: the allowed difference is
+    rel * max|nu_t| plus the derived rounding bound of two float64 evaluations of the model
+    in different orders (tests/dsm_bound.py, from the oracle state's velocity).
+    Returns (ok, worst ratio of difference to allowance, largest bound relative to
+    max|nu_t|)."""
+    from tests.dsm_bound import nut_difference_bound
     n = g.nz
     I = slice(1, n + 1)
-    scale = sgs.coefficient_rounding_scale(case, g, st.u, st.v, st.w)
-    smag = strain_magnitude(sgs.model_strain(case, g, st.u, st.v, st.w))
-    ref = np.max(np.abs(st.nut[I]))
-    d2 = g.delta() ** 2
-    if g.ywalls:
-        # ducts: one coefficient per x line (k, j); interior rows
-        J = slice(0, g.ny)
-        diff = np.max(np.abs(nut[I, J] - st.nut[I, J]), axis=2)
-        bound = CS_ROUNDING_K * UNIT_ROUNDOFF * scale[:, J] * d2[:, None] * np.max(smag[:, J], axis=2)
-    else:
-        diff = np.max(np.abs(nut[I] - st.nut[I]), axis=(1, 2))
-        bound = CS_ROUNDING_K * UNIT_ROUNDOFF * scale * d2 * np.max(smag, axis=(1, 2))
-    allow = rel * ref + bound
+    bound, _, _ = nut_difference_bound(case, g, st.u, st.v, st.w)
+    J = slice(0, g.ny)
+    ref = np.max(np.abs(st.nut[I, J]))
+    diff = np.abs(nut[I, J] - st.nut[I, J])
+    allow = rel * ref + bound[:, J]
     ratio = float(np.max(diff / allow))
-    return ratio <= 1.0, ratio, float(np.max(bound) / ref) if ref > 0 else 0.0
+    return ratio <= 1.0, ratio, float(np.max(bound[:, J]) / ref) if ref > 0 else 0.0
 
 
 def poisson_condition(g):
