@@ -637,9 +637,10 @@ def c4_line(args, torch):
     sd.close()
     sm.close()
     if not args.no_cpu_baseline:
-        note("c4: CPU oracle (one thread, then threaded FFTs)")
+        note("c4: CPU oracle, one thread")
         out["cpu_baseline"] = cpu_baseline("c4", args.cpu_seconds)
         workers = min(16, os.cpu_count() or 1)
+        note(f"c4: CPU oracle, FFTs on {workers} threads")
         out["cpu_baseline_fft_threads"] = cpu_baseline("c4", args.cpu_seconds, fft_workers=workers)
     return out
 

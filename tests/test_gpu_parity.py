@@ -261,20 +261,42 @@ def test_mixed_precision_substeps(les, name, cfgd, kind):
     solver.set_dt(dt)
     I = slice(1, g.nz + 1)
     for k in range(3):
-        # each substep from the same (float32-representable) state on both sides
+        # the float32 path stores u* in float32: the oracle's own pressure response to that one
+        # rounding of u*, dp_round, scales the pressure's tolerance (below)
+        dp_round = _pressure_rounding_response(case, g, st, k, dt)
         st = S.substep(case, g, st, k, dt)
         solver.substep(k)
         gu, gv, gw, gp = solver.fields()
         umax2 = max(np.max(np.abs(st.u[I])), np.max(np.abs(st.v[I])), np.max(np.abs(st.w[I]))) ** 2
         pref = mean_free(st.p, g)[I]
         dpa = np.max(np.abs(mean_free(gp, g)[I] - pref))
-        dp = dpa / umax2
-        errs = dict(u=rel_err(gu, st.u, I), v=rel_err(gv, st.v, I), w=rel_err(gw, st.w, I), p=dp)
+        errs = dict(u=rel_err(gu, st.u, I), v=rel_err(gv, st.v, I), w=rel_err(gw, st.w, I))
+        ptol = max(1e-5 * umax2, 30.0 * dp_round)
         say(f"  substep {k}: " + " ".join(f"{a}={b:.2e}" for a, b in errs.items()) +
-            f" p/max|p|={dpa / np.max(np.abs(pref)):.2e}")
+            f" p={dpa / umax2:.2e} (|u|^2 scale) p/max|p|={dpa / np.max(np.abs(pref)):.2e}"
+            f" p/(rounding response)={dpa / max(dp_round, 1e-300):.1f} ptol/|u|^2={ptol / umax2:.2e}")
         for a, e in errs.items():
             assert e < 1e-5, (k, a, e)
+        assert dpa <= ptol, (k, "p", dpa, ptol)
     solver.close()
+
+
+def _pressure_rounding_response(case, g, st, k, dt):
+    """Largest change of the oracle's mean-free pressure after substep k when u* (the predictor's
+    and Helmholtz solves' output, the input of Eq. poi) is rounded once to float32.  The pressure
+    increment is the Poisson solution of D u* / (gamma_k dt): float32 rounding of u* enters it
+    divided by gamma_k dt and amplified by the operator's conditioning (long rows, fine wall
+    cells), so the pressure of the float32 path is compared on this scale: 30 times it, the
+    rounding budget of the stencil, transform and correction chain that the velocities meet."""
+    ustar, _ = S.predictor(case, g, st, k, dt)
+    if case.implicit_z:
+        ustar = S.helmholtz_z(case, g, st, ustar, k, dt)
+    elif case.implicit_3d:
+        ustar = S.helmholtz_3d(case, g, st, ustar, k, dt)
+    pa = S.project(case, g, st, ustar, k, dt)[3]
+    pb = S.project(case, g, st, round32(*ustar), k, dt)[3]
+    I = slice(1, g.nz + 1)
+    return float(np.max(np.abs(mean_free(pb, g)[I] - mean_free(pa, g)[I])))
 
 
 PROJECT_CASES = [
