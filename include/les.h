@@ -300,6 +300,20 @@ les_status les_mlp_grad(void* hip_stream, const float* params_dev, const float* 
 les_status les_mlp_adam(void* hip_stream, float* params_dev, const float* grad_dev, float* m_dev, float* v_dev,
                         int step, float lr);
 
+/* For callers that cannot allocate device memory (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation): les_mlp_grad without a workspace argument.  The
+ * per-block partial gradients live in a static device array of the library,
+ * LES_MLP_NOALLOC_MAX_SAMPLES / 256 * 4738 floats (4.6 MiB), one per device, held until the
+ * process ends; its address is looked up on the first call on each device, with the stream's
+ * device current (a stream of another device: LES_EINVAL).  n above
+ * LES_MLP_NOALLOC_MAX_SAMPLES returns LES_EINVAL with a message in les_last_error(NULL).
+ * Results are bitwise those of les_mlp_grad for the same inputs.  Nothing is allocated.  All
+ * calls on one device share the array: calls that overlap on one device (other streams,
+ * other threads) race and must be ordered by the caller. */
+#define LES_MLP_NOALLOC_MAX_SAMPLES 65536
+les_status les_mlp_grad_noalloc(void* hip_stream, const float* params_dev, const float* x_dev, const float* y_dev,
+                                int64_t n, float* grad_dev, float* loss_dev);
+
 /* les_mlp_grad followed by les_mlp_adam. */
 les_status les_mlp_train_step(void* hip_stream, float* params_dev, const float* x_dev, const float* y_dev,
                               int64_t n, void* workspace_dev, float* grad_dev, float* m_dev, float* v_dev,
@@ -356,6 +370,8 @@ les_status les_batch_free(les_batch* b);
 les_status les_free(les_ctx* ctx);
 
 const char* les_strerror(les_status s);
+/* Description of the context's last error.  With ctx NULL: the calling thread's last error of
+ * les_mlp_grad_noalloc if it has failed on this thread, else "null context". */
 const char* les_last_error(const les_ctx* ctx);
 
 #ifdef __cplusplus

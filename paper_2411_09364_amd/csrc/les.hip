@@ -298,7 +298,13 @@ const char* les_strerror(les_status s) {
   return "unknown status";
 }
 
-const char* les_last_error(const les_ctx* ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+// last error of a context-free call that reports one (les_mlp_grad_noalloc), per thread
+static thread_local std::string t_free_err;
+
+const char* les_last_error(const les_ctx* ctx) {
+  if (ctx) return ctx->c.err.c_str();
+  return t_free_err.empty() ? "null context" : t_free_err.c_str();
+}
 
 les_status les_init(const les_config* cfg, void* hip_stream, les_ctx** out) {
   if (!out) return LES_EINVAL;
@@ -784,6 +790,44 @@ les_status les_mlp_grad(void* stream, const float* params, const float* x, const
                         float* grad, float* loss) {
   if (!params || !x || !y || !ws || !grad || n <= 0) return LES_EINVAL;
   launch_mlp_grad((hipStream_t)stream, params, x, y, n, (float*)ws, grad, loss);
+  return mlp_status();
+}
+
+les_status les_mlp_grad_noalloc(void* stream, const float* params, const float* x, const float* y, int64_t n,
+                                float* grad, float* loss) {
+  if (!params || !x || !y || !grad || n <= 0) {
+    t_free_err = "les_mlp_grad_noalloc: null pointer or n <= 0";
+    return LES_EINVAL;
+  }
+  if (n > LES_MLP_NOALLOC_MAX_SAMPLES) {
+    t_free_err = "les_mlp_grad_noalloc: n = " + std::to_string(n) + " exceeds LES_MLP_NOALLOC_MAX_SAMPLES = " +
+                 std::to_string(LES_MLP_NOALLOC_MAX_SAMPLES) + "; use les_mlp_grad with a workspace";
+    return LES_EINVAL;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    t_free_err = "les_mlp_grad_noalloc: no current device";
+    return LES_EDEVICE;
+  }
+  if (stream != nullptr) {
+    hipDevice_t sdev = -1;
+    if (hipStreamGetDevice((hipStream_t)stream, &sdev) != hipSuccess) {
+      t_free_err = "les_mlp_grad_noalloc: cannot query the stream's device";
+      return LES_EDEVICE;
+    }
+    if (sdev != dev) {
+      t_free_err = "les_mlp_grad_noalloc: the stream belongs to device " + std::to_string(sdev) + " but device " +
+                   std::to_string(dev) + " is current";
+      return LES_EINVAL;
+    }
+  }
+  float* part = nullptr;
+  const hipError_t e = mlp_scratch_ptr(dev, &part);
+  if (e != hipSuccess) {
+    t_free_err = std::string("les_mlp_grad_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e);
+    return LES_EDEVICE;
+  }
+  launch_mlp_grad((hipStream_t)stream, params, x, y, n, part, grad, loss);
   return mlp_status();
 }
 

@@ -242,6 +242,10 @@ void launch_mlp_forward(hipStream_t st, const float* P, const float* x, int64_t 
 void launch_mlp_grad(hipStream_t st, const float* P, const float* x, const float* t, int64_t n, float* part,
                      float* grad, float* loss);
 void launch_mlp_adam(hipStream_t st, float* P, const float* g, float* m, float* v, int step, float lr);
+// blocks of k_mlp_grad at the largest sample count of the allocation-free gradient
+constexpr int MLP_NOALLOC_BLOCKS = LES_MLP_NOALLOC_MAX_SAMPLES / 256;
+// device address of this device's partial-gradient array (looked up on first use per device)
+hipError_t mlp_scratch_ptr(int device, float** out);
 void launch_mlp_normalize(hipStream_t st, const float* xr, int64_t n, const double* lo, const double* hi, float* x);
 void launch_set_dt(Ctx& c, double dt);
 int stats_blocks(int64_t sxy);

@@ -15,6 +15,8 @@
 // Parameter vector (float32, 4737): W1[64][7] | b1[64] | W2[64][64] | b2[64] | W3[64] | b3.
 #include "mlp_core.h"
 
+#include <mutex>
+
 namespace les {
 namespace mlp {
 
@@ -255,6 +257,33 @@ void launch_mlp_grad(hipStream_t st, const float* P, const float* x, const float
   hipLaunchKernelGGL(mlp::k_mlp_grad, dim3((unsigned)nb), dim3(mlp::NT), 0, st, P, x, t, n, part);
   hipLaunchKernelGGL(mlp::k_mlp_reduce, dim3((mlp::NPARAM + 1 + 255) / 256), dim3(256), 0, st, part, (int)nb, n, grad,
                      loss);
+}
+
+// ---------------------------------------------------------------- gradient without a workspace
+// The block partials of k_mlp_grad live in a file-scope device array instead of a caller
+// workspace.  Each device holds its own copy; its address is looked up once per device with
+// that device current and kept here.  Host code never passes the array's name to a kernel: in
+// host code that name is a stand-in, not a device address.
+static __device__ __align__(256) float scratch[MLP_NOALLOC_BLOCKS * (mlp::NPARAM + 1)];
+static_assert(MLP_NOALLOC_BLOCKS * mlp::NT >= LES_MLP_NOALLOC_MAX_SAMPLES, "one chunk per block up to the limit");
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t mlp_scratch_ptr(int device, float** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = static_cast<float*>(p);
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
 }
 
 void launch_mlp_adam(hipStream_t st, float* P, const float* g, float* m, float* v, int step, float lr) {

@@ -87,6 +87,7 @@ def _load():
         "les_mlp_normalize": [vp, vp, ctypes.c_int64, ctypes.POINTER(dbl), ctypes.POINTER(dbl), vp],
         "les_mlp_forward": [vp, vp, vp, ctypes.c_int64, vp],
         "les_mlp_grad": [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp],
+        "les_mlp_grad_noalloc": [vp, vp, vp, vp, ctypes.c_int64, vp, vp],
         "les_mlp_adam": [vp, vp, vp, vp, vp, i32, ctypes.c_float],
         "les_mlp_train_step": [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp, i32, ctypes.c_float, vp],
         "les_free": [vp],
@@ -134,7 +135,7 @@ def exported_symbols():
     return ["les_init", "les_layout", "les_bind", "les_nut", "les_dt", "les_set_dt", "les_substep",
             "les_step", "les_poisson", "les_project", "les_read", "les_diag", "les_mlp_bind", "les_mlp_sample",
             "les_mlp_normalize", "les_mlp_forward", "les_mlp_workspace_bytes", "les_mlp_grad",
-            "les_mlp_adam", "les_mlp_train_step", "les_free", "les_strerror", "les_last_error",
+            "les_mlp_grad_noalloc", "les_mlp_adam", "les_mlp_train_step", "les_free", "les_strerror", "les_last_error",
             "les_timing", "les_timing_report", "les_batch_init", "les_batch_layout", "les_batch_offset",
             "les_batch_bind", "les_batch_nut", "les_batch_dt", "les_batch_set_dt", "les_batch_substep",
             "les_batch_step", "les_batch_autotune", "les_batch_read", "les_batch_diag",
@@ -245,6 +246,16 @@ def les_mlp_grad(stream, params_ptr, x_ptr, y_ptr, n, ws_ptr, grad_ptr, loss_ptr
     vp = ctypes.c_void_p
     _check(None, LIB.les_mlp_grad(vp(stream), vp(params_ptr), vp(x_ptr), vp(y_ptr), n, vp(ws_ptr), vp(grad_ptr),
                                   vp(loss_ptr)), "les_mlp_grad")
+
+
+MLP_NOALLOC_MAX_SAMPLES = 65536
+
+
+def les_mlp_grad_noalloc(stream, params_ptr, x_ptr, y_ptr, n, grad_ptr, loss_ptr):
+    vp = ctypes.c_void_p
+    st = LIB.les_mlp_grad_noalloc(vp(stream), vp(params_ptr), vp(x_ptr), vp(y_ptr), n, vp(grad_ptr), vp(loss_ptr))
+    if st != LES_OK:
+        raise LesError(st, f"les_mlp_grad_noalloc: {LIB.les_last_error(None).decode()}")
 
 
 def les_mlp_adam(stream, params_ptr, grad_ptr, m_ptr, v_ptr, step, lr):
