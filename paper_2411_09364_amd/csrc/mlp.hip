@@ -48,12 +48,14 @@ __global__ void __launch_bounds__(NT) k_mlp_forward(const float* __restrict__ P,
 __global__ void __launch_bounds__(NT) k_mlp_grad(const float* __restrict__ P, const float* __restrict__ x,
                                                  const float* __restrict__ t, int64_t n, float* __restrict__ part) {
   __shared__ Weights W;
+  __shared__ unsigned short w2t[H * LD2];             // W2^T, rows padded like W2
   __shared__ unsigned short xs[WAVES][64 * FP];
-  __shared__ unsigned short tr[WAVES][2][H * 64];   // transposes: [0] dz2b or dz1b, [1] h1b
+  __shared__ unsigned short tr[WAVES][2][H * LD2];  // transposes: [0] dz2b or dz1b, [1] h1b (rows padded)
   __shared__ float acc[NPARAM + 1];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int r16 = lane % 16, g4 = 4 * (lane / 16);
   load_weights(P, W, tid, NT);
+  for (int e = tid; e < H * H; e += NT) w2t[(e % H) * LD2 + e / H] = f2bf(P[P_W2 + e]);
   for (int e = tid; e < NPARAM + 1; e += NT) acc[e] = 0.f;
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
   f4 gW2[4][4], gW1[4];
@@ -104,7 +106,7 @@ __global__ void __launch_bounds__(NT) k_mlp_grad(const float* __restrict__ P, co
     for (int kb = 0; kb < 4; ++kb)
       for (int sb = 0; sb < 4; ++sb) {
         f4 d = zero;
-        for (int a = 0; a < 4; ++a) d = mfma(lds4(&W.w2t[(16 * kb + r16) * H + 16 * a + g4]), dz2b[a][sb], d);
+        for (int a = 0; a < 4; ++a) d = mfma(lds4(&w2t[(16 * kb + r16) * LD2 + 16 * a + g4]), dz2b[a][sb], d);
         float z[4];
         for (int i = 0; i < 4; ++i) {
           z[i] = d[i] * dsilu(o.z1[kb][sb][i]);
@@ -120,8 +122,8 @@ __global__ void __launch_bounds__(NT) k_mlp_grad(const float* __restrict__ P, co
         const s4 v0 = dz2b[a][sb], v1 = o.h1b[a][sb];
         const short e0[4] = {v0.x, v0.y, v0.z, v0.w}, e1[4] = {v1.x, v1.y, v1.z, v1.w};
         for (int i = 0; i < 4; ++i) {
-          T0[(16 * a + g4 + i) * 64 + 16 * sb + r16] = (unsigned short)e0[i];
-          T1[(16 * a + g4 + i) * 64 + 16 * sb + r16] = (unsigned short)e1[i];
+          T0[(16 * a + g4 + i) * LD2 + 16 * sb + r16] = (unsigned short)e0[i];
+          T1[(16 * a + g4 + i) * LD2 + 16 * sb + r16] = (unsigned short)e1[i];
         }
       }
     __syncthreads();
@@ -129,7 +131,7 @@ __global__ void __launch_bounds__(NT) k_mlp_grad(const float* __restrict__ P, co
     for (int a = 0; a < 4; ++a)
       for (int kb = 0; kb < 4; ++kb)
         for (int sb = 0; sb < 4; ++sb)
-          gW2[a][kb] = mfma(lds4(&T0[(16 * a + r16) * 64 + 16 * sb + g4]), lds4(&T1[(16 * kb + r16) * 64 + 16 * sb + g4]),
+          gW2[a][kb] = mfma(lds4(&T0[(16 * a + r16) * LD2 + 16 * sb + g4]), lds4(&T1[(16 * kb + r16) * LD2 + 16 * sb + g4]),
                             gW2[a][kb]);
     __syncthreads();
     // dW1(h, f) += sum_s dz1b(h, s) xb(s, f)
@@ -137,7 +139,7 @@ __global__ void __launch_bounds__(NT) k_mlp_grad(const float* __restrict__ P, co
       for (int sb = 0; sb < 4; ++sb) {
         const s4 v0 = dz1b[a][sb];
         const short e0[4] = {v0.x, v0.y, v0.z, v0.w};
-        for (int i = 0; i < 4; ++i) T0[(16 * a + g4 + i) * 64 + 16 * sb + r16] = (unsigned short)e0[i];
+        for (int i = 0; i < 4; ++i) T0[(16 * a + g4 + i) * LD2 + 16 * sb + r16] = (unsigned short)e0[i];
       }
     __syncthreads();
     for (int a = 0; a < 4; ++a)
@@ -148,7 +150,7 @@ __global__ void __launch_bounds__(NT) k_mlp_grad(const float* __restrict__ P, co
         B.y = (short)xw[(16 * sb + g4 + 1) * FP + r16];
         B.z = (short)xw[(16 * sb + g4 + 2) * FP + r16];
         B.w = (short)xw[(16 * sb + g4 + 3) * FP + r16];
-        gW1[a] = mfma(lds4(&T0[(16 * a + r16) * 64 + 16 * sb + g4]), B, gW1[a]);
+        gW1[a] = mfma(lds4(&T0[(16 * a + r16) * LD2 + 16 * sb + g4]), B, gW1[a]);
       }
     __syncthreads();
   }

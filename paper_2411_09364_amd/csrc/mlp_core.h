@@ -56,12 +56,14 @@ __device__ inline s4 pack4(float a, float b, float c, float d) {
   return r;
 }
 
-// Weights staged once per block: bf16 W1 (padded to 16 features), W2 and W2^T; float32
-// biases and output layer.
-struct Weights {
+// Weights staged once per block: bf16 W1 (padded to 16 features) and W2; float32 biases and
+// output layer.  W2 rows are padded to LD2 = 72 halfwords: with 128-byte rows the 16 rows a
+// matrix-core operand read touches (one per lane of a 16-lane group) would all start in one
+// LDS bank; 144-byte rows spread them over the 32 banks.
+constexpr int LD2 = H + 8;
+struct alignas(16) Weights {
   unsigned short w1[H * FP];
-  unsigned short w2[H * H];
-  unsigned short w2t[H * H];
+  unsigned short w2[H * LD2];
   float b1[H], b2[H], w3[H];
   float b3;
 };
@@ -71,12 +73,7 @@ __device__ void load_weights(const float* __restrict__ P, Weights& W, int tid, i
     const int r = e / FP, f = e % FP;
     W.w1[e] = f < F ? f2bf(P[P_W1 + r * F + f]) : (unsigned short)0;
   }
-  for (int e = tid; e < H * H; e += nthr) {
-    const int r = e / H, c = e % H;
-    const unsigned short b = f2bf(P[P_W2 + e]);
-    W.w2[e] = b;
-    W.w2t[c * H + r] = b;
-  }
+  for (int e = tid; e < H * H; e += nthr) W.w2[(e / H) * LD2 + e % H] = f2bf(P[P_W2 + e]);
   for (int e = tid; e < H; e += nthr) {
     W.b1[e] = P[P_B1 + e];
     W.b2[e] = P[P_B2 + e];
@@ -99,18 +96,16 @@ struct Fwd {
 template <bool KEEP>
 __device__ void forward_wave(const Weights& W, const unsigned short* xb, int lane, Fwd& o) {
   const int r16 = lane % 16, g4 = 4 * (lane / 16);
-  const f4 zero = {0.f, 0.f, 0.f, 0.f};
-  // layer 1: Z1^T(16a.., 16sb..) = W1 tile a  x  X^T tile sb
+  // layer 1: Z1^T(16a.., 16sb..) = W1 tile a  x  X^T tile sb, the accumulator starting at the
+  // bias of the lane's four rows
   for (int a = 0; a < 4; ++a) {
     const s4 A = lds4(&W.w1[(16 * a + r16) * FP + g4]);
+    const f4 bias = *reinterpret_cast<const f4*>(&W.b1[16 * a + g4]);
     for (int sb = 0; sb < 4; ++sb) {
       const s4 B = lds4(&xb[(16 * sb + r16) * FP + g4]);
-      f4 z = mfma(A, B, zero);
+      const f4 z = mfma(A, B, bias);
       float h[4];
-      for (int i = 0; i < 4; ++i) {
-        z[i] += W.b1[16 * a + g4 + i];
-        h[i] = silu(z[i]);
-      }
+      for (int i = 0; i < 4; ++i) h[i] = silu(z[i]);
       if (KEEP) o.z1[a][sb] = z;
       o.h1b[a][sb] = pack4(h[0], h[1], h[2], h[3]);
     }
@@ -120,14 +115,15 @@ __device__ void forward_wave(const Weights& W, const unsigned short* xb, int lan
   // four lane groups
   float py[4] = {0.f, 0.f, 0.f, 0.f};
   for (int a = 0; a < 4; ++a) {
+    const f4 bias = *reinterpret_cast<const f4*>(&W.b2[16 * a + g4]);
+    const f4 w3 = *reinterpret_cast<const f4*>(&W.w3[16 * a + g4]);
     for (int sb = 0; sb < 4; ++sb) {
-      f4 z = zero;
-      for (int kb = 0; kb < 4; ++kb) z = mfma(lds4(&W.w2[(16 * a + r16) * H + 16 * kb + g4]), o.h1b[kb][sb], z);
+      f4 z = bias;
+      for (int kb = 0; kb < 4; ++kb) z = mfma(lds4(&W.w2[(16 * a + r16) * LD2 + 16 * kb + g4]), o.h1b[kb][sb], z);
       f4 h;
       for (int i = 0; i < 4; ++i) {
-        z[i] += W.b2[16 * a + g4 + i];
         h[i] = silu(z[i]);
-        py[sb] += W.w3[16 * a + g4 + i] * h[i];
+        py[sb] += w3[i] * h[i];
       }
       if (KEEP) {
         o.z2[a][sb] = z;

@@ -1139,16 +1139,18 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_mlp_fallback(GridP g, T* __restrict__ nut, const double* __restrict__ cs,
                                                       const int* __restrict__ gate) {
   if (gate[0] == 0) return;
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nxy = (int64_t)g.nx * g.ny;
-  if (e >= (int64_t)g.nz * nxy) return;
-  const int k = (int)(e / nxy) + 1;
-  const int64_t r = e % nxy;
-  const int j = (int)(r / g.nx), i = (int)(r % g.nx);
-  const T val = nut[idx3(g, k, j, i)];
-  if (!(val < (T)0)) return;
-  const double c = g.ywall ? cs[(int64_t)(k - 1) * g.ny + j] : cs[k - 1];
-  store_nut(g, nut, k, j, i, (T)c * -val);
+  const int64_t ncell = (int64_t)g.nz * nxy;
+  // grid-stride: the launch is small, so that it costs little when no cell fell back
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ncell; e += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e / nxy) + 1;
+    const int64_t r = e % nxy;
+    const int j = (int)(r / g.nx), i = (int)(r % g.nx);
+    const T val = nut[idx3(g, k, j, i)];
+    if (!(val < (T)0)) continue;
+    const double c = g.ywall ? cs[(int64_t)(k - 1) * g.ny + j] : cs[k - 1];
+    store_nut(g, nut, k, j, i, (T)c * -val);
+  }
 }
 
 // Training pairs: sample s sits at the interior cell hashed from (seed, s) (SplitMix64); x
@@ -1260,7 +1262,8 @@ void launch_eddy_viscosity(Ctx& c) {
     }
     if (learned) {
       const int64_t ni = (int64_t)g.nz * g.nx * g.ny;
-      LES_LAUNCH(c, "mlp_fallback", 0, k_mlp_fallback<T>, dim3((unsigned)((ni + 255) / 256)), dim3(256), 0, g,
+      LES_LAUNCH(c, "mlp_fallback", 0, k_mlp_fallback<T>, dim3((unsigned)std::min<int64_t>(1024, (ni + 255) / 256)),
+                 dim3(256), 0, g,
                  (T*)c.nut, (const double*)c.t.cs, (const int*)gate);
     }
   }
