@@ -852,16 +852,16 @@ static int lines_per_block(int n) {
 }
 
 // Line groups of the single-field strided transforms: the ping-pong form (two buffers of
-// L <= 1024 / n lines), unless its row segments of L consecutive l stay under 64 bytes (long
-// lines); then the in-place form with up to four times the lines (L n <= 4096, one buffer
-// within 64 KB), ppt = L n / 256 points per thread rounded up to 8 or 16.
+// L <= 1024 / n lines), unless its row segments of L consecutive l stay under 128 bytes (one
+// cache line; long lines); then the in-place form with up to four times the lines (L n <=
+// 4096, one buffer within 64 KB), ppt = L n / 256 points per thread rounded up to 8 or 16.
 struct LineShape {
   int L, ppt;      // ppt 0: ping-pong
   size_t sh;       // dynamic LDS bytes
 };
 static LineShape line_shape(int n, size_t esz) {
   const int Lpp = lines_per_block(n);
-  if ((size_t)Lpp * esz >= 64 || n > 4096) return {Lpp, 0, 2 * (size_t)Lpp * (n + 1) * esz};
+  if ((size_t)Lpp * esz >= 128 || n > 4096) return {Lpp, 0, 2 * (size_t)Lpp * (n + 1) * esz};
   int L = Lpp;
   while (L < 32 && (size_t)(2 * L) * n <= 4096 && (size_t)(2 * L) * (n + 1) * esz <= 65536) L *= 2;
   const int ppt = L * n / 256 <= 8 ? 8 : 16;
