@@ -31,6 +31,45 @@ struct GridP {
   const double* rdzc;    // [nz+2] 1 / dzc
 };
 
+// Read of a table that no kernel writes while the reading kernel runs (grid metrics, plane
+// coefficients, the time-step slot), through the constant address space: with a uniform
+// index it becomes a scalar load, which does not wait behind the vector loads in flight.
+template <typename T>
+__device__ inline T ro_load(const T* p, int64_t i) {
+  typedef const __attribute__((address_space(4))) T* cptr;
+  return ((cptr)p)[i];
+}
+
+// Loads from one stored plane of a field through a raw buffer resource: the resource (scalar
+// registers) holds the plane's base address, each lane a 32-bit element offset, so a load
+// point costs one VGPR instead of a 64-bit pointer; offsets past the plane read 0.
+template <typename T>
+struct PlaneLoader {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ PlaneLoader(const T* base, int64_t plane, int64_t sxy)
+      : r(__builtin_amdgcn_make_buffer_rsrc((void*)(base + plane * sxy), (short)0, (int)(sxy * (int64_t)sizeof(T)),
+                                            0x00020000)) {}
+  __device__ T operator()(int off) const;
+};
+template <>
+__device__ inline double PlaneLoader<double>::operator()(int off) const {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off * 8, 0, 0));
+}
+template <>
+__device__ inline float PlaneLoader<float>::operator()(int off) const {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off * 4, 0, 0));
+}
+
+// Workgroup barrier that orders LDS only: it waits for the wave's LDS operations, not for
+// its global loads and stores, so loads issued before it stay in flight.  For kernels whose
+// threads exchange data through LDS only (each global location a thread reads is written by
+// no other thread of the launch while it runs).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __host__ __device__ inline int64_t idx3(const GridP& g, int k, int j, int i) {
   return ((int64_t)k * g.nys + j) * g.nx + i;
 }

@@ -445,31 +445,23 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     lrow[r] = j0 - 2 + ry;
   }
   // velocity of one plane held in registers between its fetch and its commit to LDS, so that
-  // the global loads of plane p + 2 overlap the work on plane p (strain ghost rule applied at
-  // fetch on wall ghost planes)
+  // the global loads of plane p + 2 overlap the work on plane p: the loads are raw and
+  // unconditional (points past the halo read offset 0 and are not committed).  Strain ghosts
+  // of the wall model on the wall ghost planes are formed at the commit, from the thread's own
+  // LDS entries of the two planes next to the wall.
   T ra[NL], rb[NL], rc[NL];
   auto fetch = [&](int q) {
     const int pq = phys(q);
-    const bool gb = wm && pq == 0, gt = wm && pq == nz + 1;
-    const int64_t bw = (int64_t)pq * sxy;
+    const PlaneLoader<T> lu(u, pq, sxy), lv(v, pq, sxy), lw(w, pq, sxy);
     for (int r = 0; r < NL; ++r) {
-      if (tid + r * NT < N2) {
-        rc[r] = w[bw + lofs[r]];
-        if (gb) {
-          const T a1 = u[sxy + lofs[r]], a2 = u[2 * sxy + lofs[r]];
-          const T b1 = v[sxy + lofs[r]], b2 = v[2 * sxy + lofs[r]];
-          ra[r] = a1 - (T)g.dzc[0] * ((a2 - a1) / (T)g.dzc[1]);
-          rb[r] = b1 - (T)g.dzc[0] * ((b2 - b1) / (T)g.dzc[1]);
-        } else if (gt) {
-          const T a1 = u[nz * sxy + lofs[r]], a0 = u[(nz - 1) * sxy + lofs[r]];
-          const T b1 = v[nz * sxy + lofs[r]], b0 = v[(nz - 1) * sxy + lofs[r]];
-          ra[r] = a1 + (T)g.dzc[nz] * ((a1 - a0) / (T)g.dzc[nz - 1]);
-          rb[r] = b1 + (T)g.dzc[nz] * ((b1 - b0) / (T)g.dzc[nz - 1]);
-        } else {
-          ra[r] = u[bw + lofs[r]];
-          rb[r] = v[bw + lofs[r]];
-        }
-        if (YW && wm && (lrow[r] == -1 || lrow[r] == g.ny)) {
+      ra[r] = lu(lofs[r]);
+      rb[r] = lv(lofs[r]);
+      rc[r] = lw(lofs[r]);
+    }
+    if (YW && wm) {
+      const int64_t bw = (int64_t)pq * sxy;
+      for (int r = 0; r < NL; ++r) {
+        if (tid + r * NT < N2 && (lrow[r] == -1 || lrow[r] == g.ny)) {
           // duct: strain ghosts of u and w on the y ghost rows, extrapolated in y
           const int64_t o0 = bw + (lofs[r] % g.nx) + (int64_t)(lrow[r] < 0 ? 0 : g.ny - 1) * g.nx;
           const int64_t o1 = o0 + (lrow[r] < 0 ? g.nx : -g.nx);
@@ -482,6 +474,26 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   };
   auto commit = [&](int q) {
     const int sl = ring3<T>(q);
+    const int pq = phys(q);
+    if (wm && (pq == 0 || pq == nz + 1)) {
+      // u, v ghosts: linear extrapolation in z of the first two interior values (the planes
+      // 1, 2 or nz, nz - 1, already committed by this thread to its own entries)
+      const bool bot = pq == 0;
+      const int s1 = ring3<T>(bot ? q + 1 : q - 1), s2 = ring3<T>(bot ? q + 2 : q - 2);
+      const T ca = (T)ro_load(g.dzc, bot ? 0 : nz), cb = (T)ro_load(g.dzc, bot ? 1 : nz - 1);
+      for (int r = 0; r < NL; ++r) {
+        const int e = tid + r * NT;
+        if (e < N2) {
+          const T b1 = vel[s1][1][e], b2 = vel[s2][1][e];
+          rb[r] = bot ? b1 - ca * ((b2 - b1) / cb) : b1 + ca * ((b1 - b2) / cb);
+          // ducts: u on a y ghost row keeps its y extrapolation of the stored plane (corner rule)
+          if (!(YW && (lrow[r] == -1 || lrow[r] == g.ny))) {
+            const T a1 = vel[s1][0][e], a2 = vel[s2][0][e];
+            ra[r] = bot ? a1 - ca * ((a2 - a1) / cb) : a1 + ca * ((a1 - a2) / cb);
+          }
+        }
+      }
+    }
     for (int r = 0; r < NL; ++r) {
       const int e = tid + r * NT;
       if (e < N2) {
@@ -553,11 +565,28 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   auto stage = [&](int p) {
     const int pq = phys(p);
     const int sm = ring3<T>(p - 1), s0 = ring3<T>(p), sp = ring3<T>(p + 1);
-    const T rdzf = (T)g.rdzf[pq], rdzc = (T)g.rdzc[pq], rdzcm = (T)g.rdzc[pq - 1];
+    const T rdzf = (T)ro_load(g.rdzf, pq), rdzc = (T)ro_load(g.rdzc, pq), rdzcm = (T)ro_load(g.rdzc, pq - 1);
     const bool own = p >= kb && p <= ke;
+    // pass 0: the thread's own cell (it also stores |S| there); pass 1: the 2 (TX + TY) + 4
+    // halo points, on the first threads
 #pragma unroll 1
-    for (int e = tid; e < N1; e += NT) {
-      const int x = e % RX1 + 1, y = e / RX1 + 1;
+    for (int pass = 0; pass < 2; ++pass) {
+      int x, y;
+      if (pass == 0) {
+        x = tx + 2;
+        y = ty + 2;
+      } else {
+        const int h = tid;
+        if (h >= 2 * (RX1 + TY)) break;
+        if (h < 2 * RX1) {
+          x = h % RX1 + 1;
+          y = h < RX1 ? 1 : RY1;
+        } else {
+          x = (h - 2 * RX1) < TY ? 1 : RX1;
+          y = (h - 2 * RX1) % TY + 2;
+        }
+      }
+      const int e = (y - 1) * RX1 + x - 1;
       auto A = [&](int c, int dz, int dy, int dx) -> T {
         const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
         return vel[sl][c][(y + dy) * RX2 + x + dx];
@@ -570,12 +599,12 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       qb[1][e] = (T)0.5 * (A(1, 0, 0, 0) + A(1, 0, -1, 0));
       qb[2][e] = (T)0.5 * (A(2, 0, 0, 0) + A(2, -1, 0, 0));
       for (int a = 0; a < 6; ++a) qb[3 + a][e] = sm_ * s[a];
-      if (nut != nullptr && own && x >= 2 && x <= TX + 1 && y >= 2 && y <= TY + 1) {
-        const int i = i0 + x - 2, j = j0 + y - 2;
+      if (pass == 0 && nut != nullptr && own) {
+        const int i = i0 + tx, j = j0 + ty;
         if (i < g.nx && j < g.ny) store_nut(g, nut, p, j, i, sm_);
       }
     }
-    __syncthreads();
+    lds_barrier();
     // x-y filter of the 15 quantities at the thread's own cell (R1 coords tx+1, ty+1)
     for (int a = 0; a < 15; ++a) qC[a] = (T)0;
     const bool yedge = YW && (j0 + ty == 0 || j0 + ty == g.ny - 1);
@@ -596,7 +625,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     const int pk = phys(k);
     // wall ghosts of the filtered velocity (strain ghost rule): fill the free ring slot
     if (!per && (k == 1 || k == nz)) {
-      __syncthreads();   // the free slot may still be read by the previous plane's output
+      lds_barrier();   // the free slot may still be read by the previous plane's output
       const int sg = ring3<T>(k == 1 ? 0 : nz + 1);
       const int s1 = ring3<T>(k == 1 ? 1 : nz), s2 = ring3<T>(k == 1 ? 2 : nz - 1);
       for (int e = tid; e < N1; e += NT) {
@@ -604,8 +633,8 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
           const T a1 = ut[s1][c][e], a2 = ut[s2][c][e];
           T gh;
           if (wm) {
-            gh = k == 1 ? a1 - (T)g.dzc[0] * ((a2 - a1) / (T)g.dzc[1])
-                        : a1 + (T)g.dzc[nz] * ((a1 - a2) / (T)g.dzc[nz - 1]);
+            gh = k == 1 ? a1 - (T)ro_load(g.dzc, 0) * ((a2 - a1) / (T)ro_load(g.dzc, 1))
+                        : a1 + (T)ro_load(g.dzc, nz) * ((a1 - a2) / (T)ro_load(g.dzc, nz - 1));
           } else {
             gh = -a1;
           }
@@ -613,7 +642,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
         }
         ut[sg][2][e] = (T)0;
       }
-      __syncthreads();
+      lds_barrier();
     }
     double lm = 0.0, mm = 0.0;
     const int i = i0 + tx, j = j0 + ty;
@@ -625,7 +654,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
         return ut[sl][c][(y + dy) * RX1 + x + dx];
       };
       T st[6];
-      strain_from<T>(A, rdx, rdy, (T)g.rdzf[pk], (T)g.rdzc[pk], (T)g.rdzc[pk - 1], st);
+      strain_from<T>(A, rdx, rdy, (T)ro_load(g.rdzf, pk), (T)ro_load(g.rdzc, pk), (T)ro_load(g.rdzc, pk - 1), st);
       const T stm = sqrt((T)2 * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2]) +
                          (T)4 * (st[3] * st[3] + st[4] * st[4] + st[5] * st[5]));
       const bool wall_layer = !per && (k == 1 || k == nz);
@@ -633,7 +662,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       // 3-D, 2-D or (duct corners) 1-D test filter: 4, 4^(2/3), 2^(2/3)
       const T alpha2 = (wall_layer && wall_row) ? (T)1.5874010519681994
                                                 : ((wall_layer || wall_row) ? (T)2.5198420997897464 : (T)4);
-      const T d2 = (T)g.delta2[pk];
+      const T d2 = (T)ro_load(g.delta2, pk);
       // z pass of the test filter, one quantity at a time
       auto Fz = [&](int a) { return W0 * lo[a] + W1 * mid[a] + W0 * hi[a]; };
       const T F0 = Fz(0), F1 = Fz(1), F2 = Fz(2);
@@ -676,20 +705,34 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   // of plane p + 2 are issued right after and complete under the work on plane p
   const int pstart = per ? kb - 1 : max(kb - 1, 1);
   const int pend = per ? ke + 1 : min(ke + 1, nz);
-  fetch(pstart - 1);
-  commit(pstart - 1);
-  fetch(pstart);
-  commit(pstart);
-  fetch(pstart + 1);
-  __syncthreads();
+  if (wm && pstart == 1) {
+    // the bottom ghost plane is formed from planes 1 and 2: those are committed first (plane 2
+    // is fetched again for the loop's first commit)
+    fetch(1);
+    commit(1);
+    fetch(2);
+    commit(2);
+    fetch(0);
+    commit(0);
+    fetch(2);
+  } else {
+    fetch(pstart - 1);
+    commit(pstart - 1);
+    fetch(pstart);
+    commit(pstart);
+    fetch(pstart + 1);
+  }
+  lds_barrier();
   for (int r = 0; r < NH; ++r)
     for (int c = 0; c < 3; ++c) G2[r][c] = (T)0;
   filter_xy(pstart - 1, false);
   filter_xy(pstart, false);
+  // threads exchange data through LDS only (the stored |S| and partial sums are read by later
+  // launches): the barriers leave global loads in flight
   for (int p = pstart; p <= pend; ++p) {
     commit(p + 1);
-    __syncthreads();
-    if (p + 2 <= pend + 1) fetch(p + 2);
+    lds_barrier();
+    fetch(min(p + 2, pend + 1));   // the last one reloads plane pend + 1 and is not committed
     filter_xy(p + 1, true);
     for (int a = 0; a < 15; ++a) {
       qA[a] = qB[a];
@@ -698,7 +741,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     stage(p);
     if (YW) {
       fix_rows(p);
-      __syncthreads();
+      lds_barrier();
     }
     const int k = p - 1;
     if (k >= kb && k <= ke) {
@@ -995,33 +1038,26 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
     }
   }
   const int64_t sxy = g.sxy;
+  // raw unconditional loads (points past the halo read offset 0 and are not committed), so
+  // that nothing waits for them before their commit one plane later; the wall model's strain
+  // ghosts on the wall ghost planes are formed at the commit from the thread's own LDS entries
+  // of the two planes next to the wall
   T ra[NL], rb[NL], rc[NL];
   auto fetch = [&](int q) {
     const int pq = phys(q);
-    const bool gb = wm && pq == 0, gt = wm && pq == nz + 1;
-    const int64_t bw = (int64_t)pq * sxy;
+    const PlaneLoader<T> lu(u, pq, sxy), lv(v, pq, sxy), lw(w, pq, sxy);
     for (int r = 0; r < NL; ++r) {
-      if (tid + r * tiled::NT < N1) {
-        rc[r] = w[bw + lofs[r]];
-        if (gb) {
-          const T a1 = u[sxy + lofs[r]], a2 = u[2 * sxy + lofs[r]];
-          const T b1 = v[sxy + lofs[r]], b2 = v[2 * sxy + lofs[r]];
-          ra[r] = a1 - (T)g.dzc[0] * ((a2 - a1) / (T)g.dzc[1]);
-          rb[r] = b1 - (T)g.dzc[0] * ((b2 - b1) / (T)g.dzc[1]);
-        } else if (gt) {
-          const T a1 = u[nz * sxy + lofs[r]], a0 = u[(nz - 1) * sxy + lofs[r]];
-          const T b1 = v[nz * sxy + lofs[r]], b0 = v[(nz - 1) * sxy + lofs[r]];
-          ra[r] = a1 + (T)g.dzc[nz] * ((a1 - a0) / (T)g.dzc[nz - 1]);
-          rb[r] = b1 + (T)g.dzc[nz] * ((b1 - b0) / (T)g.dzc[nz - 1]);
-        } else {
-          ra[r] = u[bw + lofs[r]];
-          rb[r] = v[bw + lofs[r]];
-        }
-        if (YW && yg[r] != 0) {
+      ra[r] = lu(lofs[r]);
+      rb[r] = lv(lofs[r]);
+      rc[r] = lw(lofs[r]);
+    }
+    if (YW) {
+      for (int r = 0; r < NL; ++r) {
+        if (yg[r] != 0) {
           // lofs points at the interior row next to the ghost row: u and w extrapolated in y
           // (in the z ghost planes these corner values are not used); v is 0 on the wall face
-          const T a1 = u[bw + lofs[r] + yg[r]], c1 = w[bw + lofs[r] + yg[r]];
-          ra[r] = u[bw + lofs[r]] - (a1 - u[bw + lofs[r]]);
+          const T a1 = lu(lofs[r] + yg[r]), c1 = lw(lofs[r] + yg[r]);
+          ra[r] = ra[r] - (a1 - ra[r]);
           rc[r] = rc[r] - (c1 - rc[r]);
           rb[r] = (T)0;
         }
@@ -1030,6 +1066,21 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
   };
   auto commit = [&](int q) {
     const int sl = slot(q);
+    const int pq = phys(q);
+    if (wm && (pq == 0 || pq == nz + 1)) {
+      const bool bot = pq == 0;
+      const int s1 = slot(bot ? q + 1 : q - 1), s2 = slot(bot ? q + 2 : q - 2);
+      const T ca = (T)ro_load(g.dzc, bot ? 0 : nz), cb = (T)ro_load(g.dzc, bot ? 1 : nz - 1);
+      for (int r = 0; r < NL; ++r) {
+        const int e = tid + r * tiled::NT;
+        if (e < N1 && !(YW && yg[r] != 0)) {
+          const T a1 = vel[s1][0][e], a2 = vel[s2][0][e];
+          const T b1 = vel[s1][1][e], b2 = vel[s2][1][e];
+          ra[r] = bot ? a1 - ca * ((a2 - a1) / cb) : a1 + ca * ((a1 - a2) / cb);
+          rb[r] = bot ? b1 - ca * ((b2 - b1) / cb) : b1 + ca * ((b1 - b2) / cb);
+        }
+      }
+    }
     for (int r = 0; r < NL; ++r) {
       const int e = tid + r * tiled::NT;
       if (e < N1) {
@@ -1039,18 +1090,31 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
       }
     }
   };
-  fetch(kb - 1);
-  commit(kb - 1);
-  fetch(kb);
-  commit(kb);
-  fetch(kb + 1);
+  if (wm && kb == 1) {
+    // the bottom ghost plane is formed from planes 1 and 2: those are committed first (plane 2
+    // is fetched again for the loop's first commit)
+    fetch(1);
+    commit(1);
+    fetch(2);
+    commit(2);
+    fetch(0);
+    commit(0);
+    fetch(2);
+  } else {
+    fetch(kb - 1);
+    commit(kb - 1);
+    fetch(kb);
+    commit(kb);
+    fetch(kb + 1);
+  }
   int flagged = 0;
   const int i = i0 + tx, j = j0 + ty;
   const bool inside = i < g.nx && j < g.ny;
+  // threads exchange data through LDS only: the barriers leave global loads in flight
   for (int k = kb; k <= ke; ++k) {
     commit(k + 1);
-    __syncthreads();
-    if (k + 2 <= ke + 1) fetch(k + 2);
+    lds_barrier();
+    fetch(min(k + 2, ke + 1));   // the last one reloads plane ke + 1 and is not committed
     const int pk = phys(k);
     const int sm = slot(k - 1), s0 = slot(k), sp = slot(k + 1);
     const int x = tx + 1, y = ty + 1;
@@ -1058,8 +1122,8 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
       const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
       return vel[sl][c][(y + dy) * RX + x + dx];
     };
-    const T rdx = (T)g.rdx, rdy = (T)g.rdy, rdzf = (T)g.rdzf[pk];
-    const T rdzc = (T)g.rdzc[pk], rdzcm = (T)g.rdzc[pk - 1];
+    const T rdx = (T)g.rdx, rdy = (T)g.rdy, rdzf = (T)ro_load(g.rdzf, pk);
+    const T rdzc = (T)ro_load(g.rdzc, pk), rdzcm = (T)ro_load(g.rdzc, pk - 1);
     const T q4 = (T)0.25, h = (T)0.5;
     // velocity-gradient tensor at the centre
     const T a11 = (A(0, 0, 0, 0) - A(0, 0, 0, -1)) * rdx;
@@ -1083,17 +1147,18 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
                          0.5 * ((double)dvdz - (double)dwdy)};
     double yplus = 0.0;
     if (!per) {
-      const double zc = g.zc[pk];
+      const double zc = ro_load(g.zc, pk);
       if (YW) {
         const double yc = (j + 0.5) * g.dy;
-        yplus = fmin(fmin(zc * ut[0], (g.lz - zc) * ut[1]), fmin(yc * ut[2], (ly - yc) * ut[3])) / g.nu;
+        yplus = fmin(fmin(zc * ro_load(ut, 0), (g.lz - zc) * ro_load(ut, 1)),
+                     fmin(yc * ro_load(ut, 2), (ly - yc) * ro_load(ut, 3))) / g.nu;
       } else {
         const bool lower = zc <= 0.5 * g.lz;
-        yplus = (lower ? zc : g.lz - zc) * (lower ? ut[0] : ut[1]) / g.nu;
+        yplus = (lower ? zc : g.lz - zc) * (lower ? ro_load(ut, 0) : ro_load(ut, 1)) / g.nu;
       }
     }
     double f[7];
-    raw_features(s, o, yplus, sqrt(g.delta2[pk]), f);
+    raw_features(s, o, yplus, sqrt(ro_load(g.delta2, pk)), f);
     bool flag = false;
     for (int a = 0; a < 7; ++a) {
       const double xn = (f[a] - nm.lo[a]) * nm.inv[a];
@@ -1123,7 +1188,7 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
       if (flag) ++flagged;
       store_nut(g, nut, pk, j, i, flag ? -smag : c * smag);
     }
-    __syncthreads();
+    lds_barrier();   // the ring slot of plane k - 1 is refilled next
   }
   if (cnt != nullptr) {
     for (int off = 32; off > 0; off >>= 1) flagged += __shfl_down(flagged, off, 64);

@@ -4,6 +4,8 @@
 // p_update_imp1d; Eq. wm with the coupling of Sec. 2.2; Alg. 2).
 #include "les_internal.h"
 
+#include <type_traits>
+
 namespace les {
 
 constexpr int kMaxNz = 512;   // largest wall-bounded nz accepted by les_init
@@ -71,10 +73,10 @@ __device__ __forceinline__ void predictor_cell(const Nb<T>& b, const GridP& g, i
 #pragma clang fp contract(on)
   const int kp = k + 1, km = k - 1;
   const T rdx = (T)g.rdx, rdy = (T)g.rdy;
-  const T rdzf = (T)g.rdzf[k];
-  const T rdzc = (T)g.rdzc[k];
-  const T rdzcm = (T)g.rdzc[km];
-  const T rdzfp = (T)g.rdzf[kp];
+  const T rdzf = (T)ro_load(g.rdzf, k);
+  const T rdzc = (T)ro_load(g.rdzc, k);
+  const T rdzcm = (T)ro_load(g.rdzc, km);
+  const T rdzfp = (T)ro_load(g.rdzf, kp);
   const T nu = (T)g.nu;
   const T h = (T)0.5, q = (T)0.25, two = (T)2;
   // ---------------- u-momentum at (i+1/2, j, k)
@@ -202,7 +204,9 @@ constexpr int TX = 32, TY = 8, NT = TX * TY;
 constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY, NL = (N1 + NT - 1) / NT;
 }  // namespace zmarch
 
-template <typename T, int MODE>
+// RW: bit 0 reads R^{k-1} (substeps 1, 2), bit 1 writes R^k (substeps 0, 1); compile-time so
+// that the loop holds no branch around a global load or store.
+template <typename T, int MODE, int RW>
 __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, const T* __restrict__ u,
                                                   const T* __restrict__ v, const T* __restrict__ w,
                                                   const T* __restrict__ p, const T* __restrict__ nut,
@@ -210,9 +214,10 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
                                                   T* __restrict__ rv, T* __restrict__ rw, T* __restrict__ us,
                                                   T* __restrict__ vs, T* __restrict__ ws,
                                                   const double* __restrict__ dtp, double alpha, double beta,
-                                                  double gamma, int use_rprev, int write_r, int kc, int chunk,
+                                                  double gamma, int kc, int chunk,
                                                   const double* __restrict__ tau, int wallmodel) {
   using namespace zmarch;
+  constexpr bool use_rprev = (RW & 1) != 0, write_r = (RW & 2) != 0;
   __shared__ T ring[3][5][N1];   // [plane slot][u v w nu p][tile + 1 halo]
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   const int i0 = bid.x * TX, j0 = bid.y * TY;
@@ -228,27 +233,33 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
     if (jj < 0) jj += g.nys;
     lofs[r] = e < N1 ? jj * g.nx + ii : 0;
   }
+  // Raw loads only, issued unconditionally (points beyond the halo read the plane's first
+  // value and are not committed), so that nothing waits for them before the commit one plane
+  // later; the plane coefficient of nu_t is applied at the commit.
   T rg[NL][5];
   auto fetch = [&](int q) {   // planes 0 .. nz+1 are stored (ghosts included)
     const int64_t base = (int64_t)q * sxy;
-    const T cq = (T)coef[q];
     for (int r = 0; r < NL; ++r) {
-      if (tid + r * NT < N1) {
-        const int64_t o = base + lofs[r];
-        rg[r][0] = u[o];
-        rg[r][1] = v[o];
-        rg[r][2] = w[o];
-        rg[r][3] = cq * nut[o];
-        rg[r][4] = p[o];
-      }
+      const int64_t o = base + lofs[r];
+      rg[r][0] = u[o];
+      rg[r][1] = v[o];
+      rg[r][2] = w[o];
+      rg[r][3] = nut[o];
+      rg[r][4] = p[o];
     }
   };
   auto commit = [&](int q) {
     const int sl = q % 3;
+    const T cq = (T)ro_load(coef, q);
     for (int r = 0; r < NL; ++r) {
       const int e = tid + r * NT;
-      if (e < N1)
-        for (int f = 0; f < 5; ++f) ring[sl][f][e] = rg[r][f];
+      if (e < N1) {
+        ring[sl][0][e] = rg[r][0];
+        ring[sl][1][e] = rg[r][1];
+        ring[sl][2][e] = rg[r][2];
+        ring[sl][3][e] = cq * rg[r][3];
+        ring[sl][4][e] = rg[r][4];
+      }
     }
   };
   fetch(kb - 1);
@@ -258,12 +269,15 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
   fetch(kb + 1);
   const int i = i0 + tx, j = j0 + ty;
   const bool inside = i < g.nx && j < g.ny;
-  const T dt = (T)dtp[0];
-  // R_prev of the own cell, loaded one plane ahead
+  const T dt = (T)ro_load(dtp, 0);
+  // R_prev of the own cell, loaded one plane ahead and unconditionally within the substep:
+  // the plane after the chunk reads the chunk's last plane (not used), threads outside the
+  // grid read the ghost plane 0, which no thread writes
   T rpn[3] = {(T)0, (T)0, (T)0};
+  const int64_t rcell = inside ? (int64_t)j * g.nx + i : -1;
   auto fetch_r = [&](int k) {
-    if (use_rprev && inside && k <= ke) {
-      const int64_t c = idx3(g, k, j, i);
+    if constexpr (use_rprev) {
+      const int64_t c = rcell < 0 ? 0 : (int64_t)min(k, ke) * sxy + rcell;
       rpn[0] = ru[c];
       rpn[1] = rv[c];
       rpn[2] = rw[c];
@@ -272,10 +286,10 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
   fetch_r(kb);
   for (int k = kb; k <= ke; ++k) {
     commit(k + 1);
-    __syncthreads();
-    if (k + 2 <= ke + 1) fetch(k + 2);
+    // the ring is the only data threads exchange: global loads in flight stay in flight
+    lds_barrier();
+    fetch(min(k + 2, ke + 1));   // past the chunk: a plane that exists, not committed
     const T rup = rpn[0], rvp = rpn[1], rwp = rpn[2];
-    fetch_r(k + 1);
     if (inside) {
       const int sm = (k - 1) % 3, s0 = k % 3, sp = (k + 1) % 3;
       const int x = tx + 1, y = ty + 1;
@@ -298,18 +312,18 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
       b.p0 = A(4, s0, 0, 0), b.pip = A(4, s0, 0, 1), b.pjp = A(4, s0, 1, 0), b.pkp = A(4, sp, 0, 0);
       const int64_t c0 = idx3(g, k, j, i);
       T Ru, Rv, Rw, uo, vo, wo;
-      predictor_cell<T, MODE>(b, g, k, dt, alpha, beta, gamma, use_rprev != 0, rup, rvp, rwp, Ru, Rv, Rw, uo, vo,
+      predictor_cell<T, MODE>(b, g, k, dt, alpha, beta, gamma, use_rprev, rup, rvp, rwp, Ru, Rv, Rw, uo, vo,
                               wo);
       if (MODE == VISC_CN_3D && wallmodel && (k == 1 || k == g.nz)) {
         // wall-model rows: the lagged wall stress enters as a known flux (as in CN in z)
-        const double ch = gamma * g.nu * dtp[0] / 2.0;
+        const double ch = gamma * g.nu * ro_load(dtp, 0) / 2.0;
         const int64_t cj = (int64_t)j * g.nx + i;
         const int b0 = k == 1 ? 0 : 2;
         const double rz = 1.0 / g.dzf[k];
         uo = (T)((double)uo + ch * (-(tau[b0 * sxy + cj] / g.nu) * rz));
         vo = (T)((double)vo + ch * (-(tau[(b0 + 1) * sxy + cj] / g.nu) * rz));
       }
-      if (write_r) {
+      if constexpr (write_r) {
         ru[c0] = Ru;
         rv[c0] = Rv;
         rw[c0] = Rw;
@@ -318,11 +332,12 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
       vs[c0] = (g.ywall && j == g.ny - 1) ? (T)0 : vo;   // v on the duct's wall face y = ly
       ws[c0] = wo;
     }
-    __syncthreads();
+    fetch_r(k + 1);   // after this plane's use of rpn: no copy waits for the loads
+    lds_barrier();    // the ring slot of plane k - 1 is refilled next
   }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int RW>
 __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) k_predictor(GridP g, const T* __restrict__ u,
                                                                         const T* __restrict__ v,
                                                                         const T* __restrict__ w,
@@ -334,7 +349,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) k_predictor(GridP
                                                                         T* __restrict__ vs, T* __restrict__ ws,
                                                                         const double* __restrict__ dtp,
                                                                         double alpha, double beta, double gamma,
-                                                                        int use_rprev, int write_r, double* hfac,
+                                                                        double* hfac,
                                                                         int wallmodel, int kc,
                                                                         const double* __restrict__ tau, int fslice) {
   const dim3 bid = xcd_tile(blockIdx, gridDim);
@@ -345,22 +360,22 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) k_predictor(GridP
                             blockDim.x * blockDim.y);
     return;
   }
-  predictor_zm_body<T, MODE>(bid, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta, gamma,
-                             use_rprev, write_r, kc, (int)bid.z - fslice, tau, wallmodel);
+  predictor_zm_body<T, MODE, RW>(bid, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta, gamma,
+                                 kc, (int)bid.z - fslice, tau, wallmodel);
 }
 
 // Batched predictor (explicit viscous terms): one launch over all boxes of a batch, the same
 // z-marching body per box.
-template <typename T>
+template <typename T, int RW>
 __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) kb_predictor(BatchMap m, double alpha, double beta,
-                                                                         double gamma, int use_rprev, int write_r) {
+                                                                         double gamma) {
   int box;
   const dim3 bid = batch_bid(m, BK_PRED, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
-  predictor_zm_body<T, VISC_EXPLICIT>(bid, d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w, (const T*)d.p,
-                                      (const T*)d.nut, d.coef, (T*)d.ru, (T*)d.rv, (T*)d.rw, (T*)d.us, (T*)d.vs,
-                                      (T*)d.wsf, d.dt, alpha, beta, gamma, use_rprev, write_r, d.pkc, (int)bid.z,
-                                      nullptr, 0);
+  predictor_zm_body<T, VISC_EXPLICIT, RW>(bid, d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w,
+                                          (const T*)d.p, (const T*)d.nut, d.coef, (T*)d.ru, (T*)d.rv, (T*)d.rw,
+                                          (T*)d.us, (T*)d.vs, (T*)d.wsf, d.dt, alpha, beta, gamma, d.pkc, (int)bid.z,
+                                          nullptr, 0);
 }
 
 template <typename T>
@@ -378,13 +393,19 @@ void launch_predictor(Ctx& c, int stage) {
   const dim3 grid((c.g.nx + TX - 1) / TX, (c.g.ny + TY - 1) / TY, nch + fslice);
   const int use_rprev = stage > 0;
   const int write_r = stage < 2;
-  auto f = mode == VISC_CN_3D ? k_predictor<T, VISC_CN_3D>
-                              : (mode == VISC_CN_Z ? k_predictor<T, VISC_CN_Z> : k_predictor<T, VISC_EXPLICIT>);
+  // R^k written by substeps 0 and 1, R^{k-1} read by substeps 1 and 2
+  auto pick = [&](auto m) {
+    constexpr int M = decltype(m)::value;
+    return stage == 0 ? k_predictor<T, M, 2> : (stage == 1 ? k_predictor<T, M, 3> : k_predictor<T, M, 1>);
+  };
+  auto f = mode == VISC_CN_3D ? pick(std::integral_constant<int, VISC_CN_3D>())
+                              : (mode == VISC_CN_Z ? pick(std::integral_constant<int, VISC_CN_Z>())
+                                                   : pick(std::integral_constant<int, VISC_EXPLICIT>()));
   const double pts = (double)c.g.sxy * c.g.nz;
   const double words = 8 + 3 * use_rprev + 3 * write_r;
   LES_LAUNCH(c, "predictor", words * pts * sizeof(T), f, grid, dim3(TX, TY), 0, c.g, (const T*)c.u, (const T*)c.v,
              (const T*)c.w, (const T*)c.p, (const T*)c.nut, c.t.coef, (T*)c.ru, (T*)c.rv, (T*)c.rw, (T*)c.us,
-             (T*)c.vs, (T*)c.wsf, c.t.dt, A[stage], B[stage], G, use_rprev, write_r, c.t.hfac,
+             (T*)c.vs, (T*)c.wsf, c.t.dt, A[stage], B[stage], G, c.t.hfac,
              c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, kc, c.t.tau, fslice);
 }
 
@@ -1113,8 +1134,8 @@ template <typename T>
 void batch_predictor(hipStream_t st, const BatchMap& m, int total, int stage) {
   static const double A[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
   static const double B[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
-  hipLaunchKernelGGL(kb_predictor<T>, dim3(total), dim3(32, 8), 0, st, m, A[stage], B[stage], A[stage] + B[stage],
-                     stage > 0 ? 1 : 0, stage < 2 ? 1 : 0);
+  auto f = stage == 0 ? kb_predictor<T, 2> : (stage == 1 ? kb_predictor<T, 3> : kb_predictor<T, 1>);
+  hipLaunchKernelGGL(f, dim3(total), dim3(32, 8), 0, st, m, A[stage], B[stage], A[stage] + B[stage]);
 }
 template <typename T>
 void batch_correct(hipStream_t st, const BatchMap& m, int total, int stage) {
