@@ -213,9 +213,22 @@ size_t carve(Ctx& c, char* base) {
       const int64_t want = ((int64_t)n * t.nblk_xy + slots - 1) / slots;
       return (int)std::max<int64_t>(std::min<int64_t>(8, n), std::min<int64_t>(n, want));
     };
+    // the fewest chunks that make the launch a whole number of rounds (at least one), when
+    // their length stays at 8 planes or more; else as above
+    auto chunk_rounds = [&](int64_t slots) {
+      for (int64_t nch = 1; nch <= n; ++nch) {
+        const int64_t blocks = nch * t.nblk_xy;
+        if (blocks < slots || blocks % slots != 0) continue;
+        const int64_t kc = (n + nch - 1) / nch;
+        if (kc < std::min<int64_t>(8, n)) break;
+        return (int)kc;
+      }
+      return chunk(slots);
+    };
     c.dsm_kc = chunk(512);
     c.mlp_kc = chunk(768);
-    c.pred_kc = chunk(512);   // z-marching predictor: two blocks per CU (FP64)
+    // z-marching predictor: three blocks per CU in FP64, four in FP32
+    c.pred_kc = chunk_rounds(f.precision == LES_MIXED ? 1024 : 768);
   }
   // ducts: one partial per x line and x tile, [nz][ny][nx/32]
   t.dsm_part = (double*)take(std::max((size_t)2 * n * t.nblk_xy * 4, (size_t)2 * n * f.ny * ((f.nx + 31) / 32)) * 8);

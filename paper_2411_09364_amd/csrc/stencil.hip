@@ -238,14 +238,13 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
   // later; the plane coefficient of nu_t is applied at the commit.
   T rg[NL][5];
   auto fetch = [&](int q) {   // planes 0 .. nz+1 are stored (ghosts included)
-    const int64_t base = (int64_t)q * sxy;
+    const PlaneLoader<T> lu(u, q, sxy), lv(v, q, sxy), lw(w, q, sxy), ln(nut, q, sxy), lp(p, q, sxy);
     for (int r = 0; r < NL; ++r) {
-      const int64_t o = base + lofs[r];
-      rg[r][0] = u[o];
-      rg[r][1] = v[o];
-      rg[r][2] = w[o];
-      rg[r][3] = nut[o];
-      rg[r][4] = p[o];
+      rg[r][0] = lu(lofs[r]);
+      rg[r][1] = lv(lofs[r]);
+      rg[r][2] = lw(lofs[r]);
+      rg[r][3] = ln(lofs[r]);
+      rg[r][4] = lp(lofs[r]);
     }
   };
   auto commit = [&](int q) {
@@ -338,7 +337,7 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
 }
 
 template <typename T, int MODE, int RW>
-__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) k_predictor(GridP g, const T* __restrict__ u,
+__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 3 : 4) k_predictor(GridP g, const T* __restrict__ u,
                                                                         const T* __restrict__ v,
                                                                         const T* __restrict__ w,
                                                                         const T* __restrict__ p,
