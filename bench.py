@@ -11,9 +11,12 @@ wall-bounded, tanh stretching beta = 1.5), Lx = 2 pi, Ly = pi, Lz = 2, FP64, Re_
 (nu = 5e-5 with U_b = 1, h = 1), log-law wall model at the first off-wall cell,
 Crank-Nicolson in z, constant flow rate; initial field laminar Poiseuille plus 10 % seeded
 uniform noise (synthetic), projected onto discretely divergence-free fields.  `value` is
-the dynamic-Smagorinsky throughput; the learned closure (trained on the GPU from
-dynamic-model samples of the same run) is timed on the same state and reported beside it.
-Each throughput is the median of five timed runs of --steps steps.
+the dynamic-Smagorinsky throughput on developed flow (20000 spin-up steps by default); the
+learned closure (trained on the GPU from dynamic-model samples of the same run, checked on
+later held-out snapshots) is timed on the same state and reported beside it, with its
+coefficient error and an a-posteriori comparison of mean profiles over one flow-through
+against the dynamic model and static Smagorinsky with van Driest damping.  Each throughput
+is the median of five timed runs of --steps steps.
 
 Printed: one JSON line with the throughput, the roofline of the dominant kernel (HIP
 events on the library's stream, algorithmic bytes per launch from the library) and the
@@ -78,9 +81,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--compare-steps", type=int, default=100,
-                    help="c3: steps of the mixed vs FP64 comparison; c4: steps of the mean-profile comparison")
-    ap.add_argument("--spinup", type=int, default=300, help="c4: dynamic-model steps before sampling")
+    ap.add_argument("--compare-steps", type=int, default=100, help="c3: steps of the mixed vs FP64 comparison")
+    ap.add_argument("--spinup", type=int, default=20000, help="c4: dynamic-model steps before sampling")
     ap.add_argument("--snapshots", type=int, default=20, help="c4: training snapshots")
     ap.add_argument("--per-snapshot", type=int, default=1 << 19, help="c4: samples per snapshot")
     ap.add_argument("--epochs", type=int, default=5, help="c4: training epochs")
@@ -476,22 +478,31 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
 def c4_line(args, torch):
-    """Dynamic Smagorinsky against the learned closure on the 512 x 256 x 128 channel.
-    1. Dynamic-model run from the seeded laminar-plus-noise field for `spinup` steps.
+    """Dynamic Smagorinsky against the learned closure on the 512 x 256 x 128 channel, on
+    developed flow.
+    1. Spin-up: the dynamic model from the seeded laminar-plus-noise field for `spinup` steps
+       (Courant number 0.5); the friction coefficient of each window of 1000 steps (statistics
+       sampled every 20 steps) is recorded, and the spin-up reports the relative change over
+       its last two windows (plateau check).
     2. Training pairs (raw features, dynamic c_s of the cell's plane) sampled on the GPU at
-       `snapshots` states 10 steps apart, `per_snapshot` cells each; the batches interleave
-       the snapshots.
-    3. Training on the GPU with the library's kernels (Adam, batches of 2^16, `epochs` passes).
-    4. On the last dynamic-model state: the learned and the dynamic eddy viscosity of the
-       same velocity; the learned closure's effective plane coefficient
-       c_eff(k) = c_s(k) <nu_t,learned>(k) / <nu_t,dynamic>(k) against c_s(k).
-    5. Throughput of both closures from that state (graph-replayed steps, median of --runs
+       `snapshots` states 50 steps apart, `per_snapshot` cells each.
+    3. Held-out pairs: 4 later states (a gap of 500 steps, then 50 steps apart), 2^18 cells each.
+    4. Training on the GPU with the library's kernels (Adam, batches of 2^16, `epochs` passes).
+    5. A-priori on the held-out pairs: mean-squared error of the network against the dynamic
+       coefficient, and of the best constant (the training mean) for comparison.
+    6. On the last held-out state: the learned and the dynamic eddy viscosity of the same
+       velocity; the learned closure's effective plane coefficient c_eff(k) = c_s(k)
+       <nu_t,learned>(k) / <nu_t,dynamic>(k) against c_s(k).
+    7. Throughput of both closures from that state (graph-replayed steps, median of --runs
        timed runs each); `value` is the dynamic model's.
-    6. Per-kernel HIP-event timing of both; roofline of the dynamic run's dominant kernel,
+    8. Per-kernel HIP-event timing of both; roofline of the dynamic run's dominant kernel,
        matrix-core rate of the learned closure's inference kernel.
-    7. Both runs restarted from the state of step 4 for `compare_steps` steps: plane-mean
-       streamwise velocity profiles compared.
-    8. The CPU oracle on a bounded sample of the same workload."""
+    9. A-posteriori: from the same state, the dynamic model, the learned closure and static
+       Smagorinsky with van Driest damping each advance one flow-through time L_x / U_b;
+       mean streamwise velocity profiles (statistics every 10 steps, the two halves averaged)
+       and C_f; the profile error of Eq. error over [0.1 h, h] of the learned closure and of
+       the static model against the dynamic model.
+    10. The CPU oracle on a bounded sample of the same workload."""
     import numpy as np
     cfgd = CONFIGS["c4"]
     use_graph = not args.no_graph
@@ -502,26 +513,58 @@ def c4_line(args, torch):
     sd.project()
     sd.nut()
     del u, v, w
-    note(f"c4: {args.spinup} dynamic-model steps")
+    n = cfgd["nz"]
+    cells = cfgd["nx"] * cfgd["ny"] * cfgd["nz"]
+    # 1. spin-up with the friction coefficient per window
+    note(f"c4: {args.spinup} dynamic-model steps of spin-up")
     t0 = time.perf_counter()
-    run_steps(les, sd, args.spinup, use_graph)
+    window, cf_hist, sim_t = 1000, [], 0.0
+    sd.stats_reset()
+    done = 0
+    while done < args.spinup:
+        m = min(window, args.spinup - done)
+        for _ in range(m // 20):
+            run_steps(les, sd, 20, use_graph)
+            sd.stats_sample()
+        run_steps(les, sd, m % 20, use_graph)
+        done += m
+        sc, _ = sd.stats(1)
+        d, _ = sd.diag()
+        sim_t += m * d.dt
+        cf_hist.append([done, round(sim_t, 3), sc["c_f"], sc["re_tau"]])
+        sd.stats_reset()
+        note(f"c4: spin-up {done} steps, t = {sim_t:.1f}, C_f = {sc['c_f']:.4e}, Re_tau = {sc['re_tau']:.0f}")
     sd.synchronize()
     spin_s = time.perf_counter() - t0
-    note(f"c4: spin-up {spin_s:.1f} s; sampling {args.snapshots} snapshots")
+    plateau = (abs(cf_hist[-1][2] - cf_hist[-2][2]) / abs(cf_hist[-1][2])) if len(cf_hist) > 1 else None
+    # 2. training snapshots, 3. held-out snapshots
+    note(f"c4: sampling {args.snapshots} training and 4 held-out snapshots")
     xs, ys = [], []
     for q in range(args.snapshots):
-        run_steps(les, sd, 10, use_graph)
+        run_steps(les, sd, 50, use_graph)
         x, y = sd.mlp_sample(1000 + q, args.per_snapshot)
         xs.append(x)
         ys.append(y)
+    run_steps(les, sd, 500, use_graph)
+    hx, hy = [], []
+    for q in range(4):
+        run_steps(les, sd, 50, use_graph)
+        x, y = sd.mlp_sample(5000 + q, 1 << 18)
+        hx.append(x)
+        hy.append(y)
     sd.synchronize()
     X = torch.stack(xs, 1).reshape(-1, 7).contiguous()
     Y = torch.stack(ys, 1).reshape(-1).contiguous()
-    del xs, ys
+    HX = torch.cat(hx, 0).contiguous()
+    HY = torch.cat(hy, 0).contiguous()
+    del xs, ys, hx, hy
     torch.cuda.synchronize()
     lo, hi = feature_range(torch, X)
     Xn = torch.empty_like(X)
     les.les_mlp_normalize(sd.stream.cuda_stream, X.data_ptr(), X.shape[0], lo, hi, Xn.data_ptr())
+    HXn = torch.empty_like(HX)
+    les.les_mlp_normalize(sd.stream.cuda_stream, HX.data_ptr(), HX.shape[0], lo, hi, HXn.data_ptr())
+    # 4. training
     mlp = les.Mlp(initial_params(5), stream=sd.stream)
     note("c4: training")
     B = 1 << 16
@@ -538,7 +581,17 @@ def c4_line(args, torch):
     train_s = time.perf_counter() - t0
     final_loss = float(loss.item())
     target_var = float(Y.double().var().item())
-    del X, Xn, Y
+    ymean = float(Y.double().mean().item())
+    # 5. a-priori on the held-out snapshots (the network's output clipped at zero, as in the
+    # eddy viscosity)
+    pred = mlp.forward(HXn)
+    sd.synchronize()
+    pred = pred.double().clamp(min=0.0)
+    hyd = HY.double()
+    mse_net = float(((pred - hyd) ** 2).mean().item())
+    mse_const = float(((ymean - hyd) ** 2).mean().item())
+    held_var = float(hyd.var().item())
+    del X, Xn, Y, HX, HXn, HY, pred, hyd
     cfg_m = les.make_config(cfgd["nx"], cfgd["ny"], cfgd["nz"], cfgd["lx"], cfgd["ly"], cfgd["lz"], zbc=cfgd["zbc"],
                             beta=cfgd["beta"], nu=cfgd["nu"], sgs=les.SGS_MLP, cs=cfgd["cs"],
                             implicit_z=cfgd["implicit_z"], precision=cfgd["precision"], ubulk=cfgd["ubulk"])
@@ -551,7 +604,7 @@ def c4_line(args, torch):
     sm.synchronize()
     snap = [t.clone() for t in (sd.u, sd.v, sd.w, sd.p)]
     torch.cuda.synchronize()
-    n = cfgd["nz"]
+    # 6. coefficient error on the same velocity
     nut_d = sd.eddy_viscosity()[1:n + 1]
     nut_m = sm.eddy_viscosity()[1:n + 1]
     cs_d = sd.coefficient()
@@ -564,33 +617,58 @@ def c4_line(args, torch):
     dm, _ = sm.diag()
     flagged = int(dm.mlp_flagged)
     del nut_d, nut_m
-    cells = cfgd["nx"] * cfgd["ny"] * cfgd["nz"]
+    # 7. throughput
     thr = {}
     for name, s in (("dynamic", sd), ("learned", sm)):
         note(f"c4: timing the {name} closure")
         el, runs = timed_runs(les, s, args, use_graph)
         thr[name] = (cells * 3 * args.steps / el / 1e6, el / args.steps * 1e3, runs)
+    # 8. per-kernel timing
     nrep = max(1, min(args.steps, 10))
     kernels, roof = kernel_report(les, sd.ctx, nrep, cfgd["name"], cells, cfgd["precision"] == 0)
     kernels_m, _ = kernel_report(les, sm.ctx, nrep, cfgd["name"] + " learned", cells, cfgd["precision"] == 0)
     mlp_us = kernels_m["mlp_nut"]["avg_us"]
     mlp_tflops = cells * MLP_FLOPS_PER_CELL / (mlp_us * 1e-6) / 1e12
-    # mean-profile comparison from the same state
-    note("c4: mean-profile comparison")
-    torch.cuda.synchronize()
-    for s in (sd, sm):
+    # 9. a-posteriori over one flow-through from the same state
+    _, sv = make_solver(dict(cfgd, sgs=2))
+    runs_ap = (("dynamic", sd), ("learned", sm), ("smagorinsky_van_driest", sv))
+    for s in (sd, sm, sv):
         with torch.cuda.stream(s.stream):
             for a, b in zip((s.u, s.v, s.w, s.p), snap):
                 a.copy_(b)
         s.nut()
-    for s in (sd, sm):
-        run_steps(les, s, args.compare_steps, use_graph)
-        s.synchronize()
-    pd = sd.u[1:n + 1].mean(dim=(1, 2))
-    pm = sm.u[1:n + 1].mean(dim=(1, 2))
-    prof_err = float((pm - pd).abs().max().item()) / cfgd["ubulk"]
-    d1, _ = sd.diag()
-    d2, _ = sm.diag()
+    del snap
+    dt_est = sd.dt(0.5)
+    nft = int(np.ceil(cfgd["lx"] / cfgd["ubulk"] / dt_est))
+    note(f"c4: a-posteriori comparison, {nft} steps (one flow-through) per closure")
+    prof, scal = {}, {}
+    for name, s in runs_ap:
+        s.stats_reset()
+        t0 = time.perf_counter()
+        for _ in range(nft // 10):
+            run_steps(les, s, 10, use_graph)
+            s.stats_sample()
+        sc, pr = s.stats(8)
+        d, _ = s.diag()
+        prof[name] = pr["U"]
+        scal[name] = {"c_f": sc["c_f"], "c_f_sigma": sc["c_f_sigma"], "re_tau": sc["re_tau"], "u_tau": sc["u_tau"],
+                      "max_div": d.max_div, "nonfinite": int(d.nonfinite),
+                      "seconds": round(time.perf_counter() - t0, 2)}
+    # profiles of the two halves averaged; z from the wall to the centre (h = lz / 2 = 1)
+    h = cfgd["lz"] / 2
+    half = n // 2
+    zl = np.append(zc[1:half + 1], h)
+
+    def sym(p):
+        lower = 0.5 * (p[:half] + p[::-1][:half])
+        return np.append(lower, 0.5 * (p[half - 1] + p[half]))
+
+    ref = sym(prof["dynamic"])
+    eps = {name: les.les_profile_error(zl, sym(prof[name]), ref, 0.1 * h, h)
+           for name in ("learned", "smagorinsky_van_driest")}
+    umax_diff = {name: float(np.max(np.abs(sym(prof[name]) - ref))) / cfgd["ubulk"]
+                 for name in ("learned", "smagorinsky_van_driest")}
+    sv.close()
     value = thr["dynamic"][0]
     out = {
         "metric": METRIC,
@@ -623,15 +701,19 @@ def c4_line(args, torch):
                         "achieved": round(mlp_tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(mlp_tflops / MFMA_BF16_PEAK_TFLOPS, 4)},
             "kernels": kernels_m,
-            "training": {"spinup_steps": args.spinup, "spinup_seconds": round(spin_s, 2),
-                         "snapshots": args.snapshots, "samples": nb * B, "epochs": args.epochs,
-                         "adam_steps": total, "seconds": round(train_s, 2), "final_batch_mse": final_loss,
-                         "target_variance": target_var},
+            "spinup": {"steps": args.spinup, "seconds": round(spin_s, 2), "window_steps": window,
+                       "c_f_windows": cf_hist, "last_window_rel_change": plateau},
+            "training": {"snapshots": args.snapshots, "snapshot_spacing_steps": 50, "samples": nb * B,
+                         "epochs": args.epochs, "adam_steps": total, "seconds": round(train_s, 2),
+                         "final_batch_mse": final_loss, "target_variance": target_var},
+            "held_out": {"snapshots": 4, "gap_steps": 500, "samples": 4 << 18, "mse_network": mse_net,
+                         "mse_best_constant": mse_const, "target_variance": held_var,
+                         "mse_ratio_network_to_constant": mse_net / mse_const if mse_const > 0 else None},
             "coefficient_error": {"plane_coefficient_rel_l2": coef_err, "plane_nut_rel_l2": nut_plane_err,
                                   "pointwise_nut_rel_rms": nut_point_err, "fallback_points": flagged},
-            "mean_profile": {"steps": args.compare_steps, "max_abs_diff_over_ub": prof_err,
-                             "max_div": [d1.max_div, d2.max_div], "ubulk": [d1.ubulk, d2.ubulk],
-                             "nonfinite": [int(d1.nonfinite), int(d2.nonfinite)]},
+            "a_posteriori": {"steps": nft, "flow_throughs": round(nft * dt_est * cfgd["ubulk"] / cfgd["lx"], 3),
+                             "reference": "dynamic", "profile_error_eq_error_0.1h_to_h": eps,
+                             "mean_u_max_abs_diff_over_ub": umax_diff, "closures": scal},
         },
     }
     sd.close()
