@@ -957,9 +957,9 @@ static void spectral_solve(Ctx& c) {
   if (c.cfg.zbc == LES_ZBC_PERIODIC) {
     fftz_solve<T>(c, "fftz_solve", 0.0);
   } else {
-    // segments of 8 rows (16 beyond 256 planes): at most 32 segments of 32 chains per block
+    // segments of 16 rows (8 up to 32 planes): at most 32 segments of 32 chains per block
     const int64_t nchain = 2 * (int64_t)c.g.nxp * ny;
-    const int S = nz <= 256 ? 8 : 16;
+    const int S = nz <= 32 ? 8 : 16;
     const int P = (nz + S - 1) / S;
     const dim3 grid((unsigned)((nchain + 31) / 32)), block(32 * P);
     const double norm = 1.0 / ((double)c.g.nx * ny);
