@@ -85,7 +85,7 @@ def parse():
     ap.add_argument("--spinup", type=int, default=20000, help="c4: dynamic-model steps before sampling")
     ap.add_argument("--snapshots", type=int, default=20, help="c4: training snapshots")
     ap.add_argument("--per-snapshot", type=int, default=1 << 19, help="c4: samples per snapshot")
-    ap.add_argument("--epochs", type=int, default=5, help="c4: training epochs")
+    ap.add_argument("--epochs", type=int, default=20, help="c4: training epochs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (calibration of HBM counters)")
     ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)     # child process of cpu_baseline
