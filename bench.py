@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--snapshots", type=int, default=20, help="c4: training snapshots")
     ap.add_argument("--per-snapshot", type=int, default=1 << 19, help="c4: samples per snapshot")
     ap.add_argument("--epochs", type=int, default=20, help="c4: training epochs")
+    ap.add_argument("--aposteriori", type=float, default=1.0,
+                    help="c4: flow-through times of the a-posteriori comparison (0: skipped)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (calibration of HBM counters)")
     ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)     # child process of cpu_baseline
@@ -477,6 +479,83 @@ MLP_FLOPS_PER_CELL = 2 * (7 * 64 + 64 * 64 + 64)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
+def a_posteriori(les, torch, cfgd, args, sd, sm, snap, zc, use_graph):
+    """The dynamic model, the learned closure and static Smagorinsky with van Driest damping,
+    each from the same state, for --aposteriori flow-through times L_x / U_b (with the time step
+    of that state): mean streamwise velocity profiles (statistics every 10 steps, the two halves
+    averaged) and C_f; the profile error of Eq. error over [0.1 h, h] of the learned closure and
+    of the static model against the dynamic model."""
+    import numpy as np
+    n = cfgd["nz"]
+    _, sv = make_solver(dict(cfgd, sgs=2))
+    runs_ap = (("dynamic", sd), ("learned", sm), ("smagorinsky_van_driest", sv))
+    for s in (sd, sm, sv):
+        with torch.cuda.stream(s.stream):
+            for a, b in zip((s.u, s.v, s.w, s.p), snap):
+                a.copy_(b)
+        s.nut()
+    dt_est = sd.dt(0.5)
+    nft = int(np.ceil(args.aposteriori * cfgd["lx"] / cfgd["ubulk"] / dt_est))
+    note(f"c4: a-posteriori comparison, {nft} steps ({args.aposteriori} flow-through) per closure")
+    prof, scal = {}, {}
+    for name, s in runs_ap:
+        s.stats_reset()
+        t0 = time.perf_counter()
+        for _ in range(nft // 10):
+            run_steps(les, s, 10, use_graph)
+            s.stats_sample()
+        sc, pr = s.stats(8)
+        d, _ = s.diag()
+        prof[name] = pr["U"]
+        scal[name] = {"c_f": sc["c_f"], "c_f_sigma": sc["c_f_sigma"], "re_tau": sc["re_tau"], "u_tau": sc["u_tau"],
+                      "max_div": d.max_div, "nonfinite": int(d.nonfinite),
+                      "seconds": round(time.perf_counter() - t0, 2)}
+    # profiles of the two halves averaged; z from the wall to the centre (h = lz / 2 = 1)
+    h = cfgd["lz"] / 2
+    half = n // 2
+    zl = np.append(zc[1:half + 1], h)
+
+    def sym(p):
+        lower = 0.5 * (p[:half] + p[::-1][:half])
+        return np.append(lower, 0.5 * (p[half - 1] + p[half]))
+
+    ref = sym(prof["dynamic"])
+    eps = {name: les.les_profile_error(zl, sym(prof[name]), ref, 0.1 * h, h)
+           for name in ("learned", "smagorinsky_van_driest")}
+    umax_diff = {name: float(np.max(np.abs(sym(prof[name]) - ref))) / cfgd["ubulk"]
+                 for name in ("learned", "smagorinsky_van_driest")}
+    sv.close()
+    return {"steps": nft, "flow_throughs": round(nft * dt_est * cfgd["ubulk"] / cfgd["lx"], 3),
+            "reference": "dynamic", "profile_error_eq_error_0.1h_to_h": eps,
+            "mean_u_max_abs_diff_over_ub": umax_diff, "closures": scal}
+
+
+def c4_base(args, cfgd, value, ms_per_step, runs, roof, kernels, use_graph):
+    """Fields of the C4 line common to the full run and the dynamic-model-only run."""
+    return {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mpts·substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": cfgd["dtype"],
+        "data": "synthetic",
+        "config": {"workload": cfgd["name"], "grid": [cfgd["nx"], cfgd["ny"], cfgd["nz"]],
+                   "substeps_per_step": 3, "graph": use_graph,
+                   "closure": "dynamic Smagorinsky (value)" + ("" if args.no_learned else
+                                                               "; learned closure beside it (learned_closure)")},
+        "timed_runs_s": [round(r, 5) for r in runs],
+        "roofline": roof,
+        "substep_roofline": substep_roofline(value, cfgd),
+        "kernels": kernels,
+    }
+
+
 def c4_line(args, torch):
     """Dynamic Smagorinsky against the learned closure on the 512 x 256 x 128 channel, on
     developed flow.
@@ -537,6 +616,18 @@ def c4_line(args, torch):
     sd.synchronize()
     spin_s = time.perf_counter() - t0
     plateau = (abs(cf_hist[-1][2] - cf_hist[-2][2]) / abs(cf_hist[-1][2])) if len(cf_hist) > 1 else None
+    if args.no_learned:
+        # the dynamic model alone (no sampling, training or learned closure)
+        el, runs = timed_runs(les, sd, args, use_graph)
+        value = cells * 3 * args.steps / el / 1e6
+        kernels, roof = kernel_report(les, sd.ctx, max(1, min(args.steps, 10)), cfgd["name"], cells,
+                                      cfgd["precision"] == 0)
+        out = c4_base(args, cfgd, value, el / args.steps * 1e3, runs, roof, kernels, use_graph)
+        out["spinup"] = {"steps": args.spinup, "seconds": round(spin_s, 2), "c_f_windows": cf_hist}
+        sd.close()
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline("c4", args.cpu_seconds)
+        return out
     # 2. training snapshots, 3. held-out snapshots
     note(f"c4: sampling {args.snapshots} training and 4 held-out snapshots")
     xs, ys = [], []
@@ -629,67 +720,16 @@ def c4_line(args, torch):
     kernels_m, _ = kernel_report(les, sm.ctx, nrep, cfgd["name"] + " learned", cells, cfgd["precision"] == 0)
     mlp_us = kernels_m["mlp_nut"]["avg_us"]
     mlp_tflops = cells * MLP_FLOPS_PER_CELL / (mlp_us * 1e-6) / 1e12
-    # 9. a-posteriori over one flow-through from the same state
-    _, sv = make_solver(dict(cfgd, sgs=2))
-    runs_ap = (("dynamic", sd), ("learned", sm), ("smagorinsky_van_driest", sv))
-    for s in (sd, sm, sv):
-        with torch.cuda.stream(s.stream):
-            for a, b in zip((s.u, s.v, s.w, s.p), snap):
-                a.copy_(b)
-        s.nut()
-    del snap
-    dt_est = sd.dt(0.5)
-    nft = int(np.ceil(cfgd["lx"] / cfgd["ubulk"] / dt_est))
-    note(f"c4: a-posteriori comparison, {nft} steps (one flow-through) per closure")
-    prof, scal = {}, {}
-    for name, s in runs_ap:
-        s.stats_reset()
-        t0 = time.perf_counter()
-        for _ in range(nft // 10):
-            run_steps(les, s, 10, use_graph)
-            s.stats_sample()
-        sc, pr = s.stats(8)
-        d, _ = s.diag()
-        prof[name] = pr["U"]
-        scal[name] = {"c_f": sc["c_f"], "c_f_sigma": sc["c_f_sigma"], "re_tau": sc["re_tau"], "u_tau": sc["u_tau"],
-                      "max_div": d.max_div, "nonfinite": int(d.nonfinite),
-                      "seconds": round(time.perf_counter() - t0, 2)}
-    # profiles of the two halves averaged; z from the wall to the centre (h = lz / 2 = 1)
-    h = cfgd["lz"] / 2
-    half = n // 2
-    zl = np.append(zc[1:half + 1], h)
-
-    def sym(p):
-        lower = 0.5 * (p[:half] + p[::-1][:half])
-        return np.append(lower, 0.5 * (p[half - 1] + p[half]))
-
-    ref = sym(prof["dynamic"])
-    eps = {name: les.les_profile_error(zl, sym(prof[name]), ref, 0.1 * h, h)
-           for name in ("learned", "smagorinsky_van_driest")}
-    umax_diff = {name: float(np.max(np.abs(sym(prof[name]) - ref))) / cfgd["ubulk"]
-                 for name in ("learned", "smagorinsky_van_driest")}
-    sv.close()
+    # 9. a-posteriori over --aposteriori flow-throughs from the same state
+    if args.aposteriori <= 0:
+        del snap
+        ap_out = None
+    else:
+        ap_out = a_posteriori(les, torch, cfgd, args, sd, sm, snap, zc, use_graph)
+        del snap
     value = thr["dynamic"][0]
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "Mpts·substeps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(thr["dynamic"][1], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": cfgd["dtype"],
-        "data": "synthetic",
-        "config": {"workload": cfgd["name"], "grid": [cfgd["nx"], cfgd["ny"], cfgd["nz"]],
-                   "substeps_per_step": 3, "graph": use_graph,
-                   "closure": "dynamic Smagorinsky (value); learned closure beside it (learned_closure)"},
-        "timed_runs_s": [round(r, 5) for r in thr["dynamic"][2]],
-        "roofline": roof,
-        "substep_roofline": substep_roofline(value, cfgd),
-        "kernels": kernels,
+    out = c4_base(args, cfgd, value, thr["dynamic"][1], thr["dynamic"][2], roof, kernels, use_graph)
+    out.update({
         "learned_closure": {
             "value": round(thr["learned"][0], 3), "unit": "Mpts·substeps/s",
             "ms_per_step": round(thr["learned"][1], 4),
@@ -711,11 +751,9 @@ def c4_line(args, torch):
                          "mse_ratio_network_to_constant": mse_net / mse_const if mse_const > 0 else None},
             "coefficient_error": {"plane_coefficient_rel_l2": coef_err, "plane_nut_rel_l2": nut_plane_err,
                                   "pointwise_nut_rel_rms": nut_point_err, "fallback_points": flagged},
-            "a_posteriori": {"steps": nft, "flow_throughs": round(nft * dt_est * cfgd["ubulk"] / cfgd["lx"], 3),
-                             "reference": "dynamic", "profile_error_eq_error_0.1h_to_h": eps,
-                             "mean_u_max_abs_diff_over_ub": umax_diff, "closures": scal},
+            "a_posteriori": ap_out,
         },
-    }
+    })
     sd.close()
     sm.close()
     if not args.no_cpu_baseline:
