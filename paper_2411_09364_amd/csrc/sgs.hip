@@ -344,57 +344,99 @@ __global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part,
 // ============================================================================ fused dynamic model
 // One z-marching pass per (32 x 8 tile, chunk of planes) computing |S| and the plane sums
 // of L_ij M_ij and M_ij M_ij, reading u, v, w once (halo 2) and writing |S| once.
-//   LDS: velocity ring of 3 planes on the tile + 2 halo (strain ghosts substituted),
-//        the 9 centre quantities (uc_i, |S| S_ij) of one plane on the tile + 1 halo,
-//        the test-filtered staggered velocity ring of 3 planes on the tile + 1 halo.
-//   Registers: the x-y-filtered 15 quantities of planes k-1, k, k+1 for the thread's cell.
-// The stage of plane p computes the centre quantities and the filtered velocity of p from
-// velocity planes p-1..p+1; once stage p is done the cell values of plane p-1 are final
-// (z pass of the test filter, S~ from the filtered velocity, L and M).
+//   LDS: velocity of planes p, p + 1 on the tile + 2 halo (strain ghosts substituted),
+//        the 15 filter inputs (u_i, u_i u_j, |S| S_ij at cell centres) of plane p on the
+//        tile + 1 halo, stored in pairs (one 16-byte read per pair in the filter), the
+//        test-filtered staggered velocity of two planes on the tile + 1 halo.
+//   Registers: the z pass of the test filter as running sums over the thread's cell; the
+//        upper z-edge terms of the off-diagonal strain and w of the previous plane at the
+//        thread's points, which are the lower terms of the plane above (so only planes k and
+//        k + 1 are needed to form the strain of plane k).
+// The stage of plane p forms the filter inputs of plane p from velocity planes p, p + 1 and
+// completes the filtered velocity of plane p - 1; once stage p is done the cell values of plane
+// p - 1 are final (z pass of the test filter, S~ from the filtered velocity, L and M).
 // Wall rules as in the rest of the dynamic model: on the first off-wall layers the z pass of
-// the filter is the identity (index-space extrapolation), filtered-velocity ghosts follow the
-// strain ghost rule, alpha^2 = 4^(2/3) there.
+// the filter is the identity (the index-space extrapolation of the neighbour reduces to it),
+// filtered-velocity ghosts follow the strain ghost rule, alpha^2 = 4^(2/3) there.
 namespace fused {
 constexpr int TX = 32, TY = 8, NT = TX * TY, WV = NT / 64;
 constexpr int RX2 = TX + 4, RY2 = TY + 4, N2 = RX2 * RY2;  // halo 2
 constexpr int RX1 = TX + 2, RY1 = TY + 2, N1 = RX1 * RY1;  // halo 1
+constexpr int NQ = 15;                                      // filter inputs per cell
+constexpr int NHALO = 2 * (RX1 + TY);                       // halo-1 points around the tile
 }  // namespace fused
 
-// strain at a centre from an accessor A(c, dz, dy, dx) giving component c (0 u, 1 v, 2 w)
-// at offsets relative to the cell (dz in {-1, 0, 1}: planes k-1, k, k+1; w at dz is the face
-// on top of plane k+dz).
+// Upper z-edge terms at a cell of plane k: (du/dz + dw/dx) / 2 on the x-z edges of the cell's
+// two x faces (fa: the face of u_i, fb: of u_{i-1}), (dv/dz + dw/dy) / 2 on the y-z edges of
+// its two y faces (ga, gb), all on the face between planes k and k + 1, and w on that face.
+// They are the lower edge terms of the cell above.
+template <typename T>
+struct ZEdges {
+  T fa, fb, ga, gb, w;
+};
+
+// from an accessor A(c, dz, o): component c (0 u, 1 v, 2 w) of plane k + dz (dz in {0, 1}) at
+// plane offset o; sy is one step in y, rdzc the reciprocal centre spacing above plane k
 template <typename T, typename Acc>
-__device__ inline void strain_from(const Acc& A, T rdx, T rdy, T rdzf, T rdzc, T rdzcm, T s[6]) {
+__device__ inline ZEdges<T> zedges(const Acc& A, int o, int sy, T rdx, T rdy, T rdzc) {
+  const T h = (T)0.5;
+  ZEdges<T> E;
+  const T w0 = A(2, 0, o);
+  E.fa = h * ((A(0, 1, o) - A(0, 0, o)) * rdzc + (A(2, 0, o + 1) - w0) * rdx);
+  E.fb = h * ((A(0, 1, o - 1) - A(0, 0, o - 1)) * rdzc + (w0 - A(2, 0, o - 1)) * rdx);
+  E.ga = h * ((A(1, 1, o) - A(1, 0, o)) * rdzc + (A(2, 0, o + sy) - w0) * rdy);
+  E.gb = h * ((A(1, 1, o - sy) - A(1, 0, o - sy)) * rdzc + (w0 - A(2, 0, o - sy)) * rdy);
+  E.w = w0;
+  return E;
+}
+
+// strain at a cell of plane k (Sec. 2.2: diagonal terms from face differences, off-diagonal
+// terms as means of four edge values) from the accessor over plane k, the lower edge terms P
+// (the upper terms of plane k - 1) and the cell's own upper terms E
+template <typename T, typename Acc>
+__device__ inline void strain_zm(const Acc& A, int o, int sy, T rdx, T rdy, T rdzf, const ZEdges<T>& P,
+                                 const ZEdges<T>& E, T s[6]) {
   const T h = (T)0.5, q = (T)0.25;
-  const T u0 = A(0, 0, 0, 0), uim = A(0, 0, 0, -1), ujp = A(0, 0, 1, 0), ujm = A(0, 0, -1, 0);
-  const T ujp_im = A(0, 0, 1, -1), ujm_im = A(0, 0, -1, -1);
-  const T v0 = A(1, 0, 0, 0), vjm = A(1, 0, -1, 0), vip = A(1, 0, 0, 1), vim = A(1, 0, 0, -1);
-  const T vjm_ip = A(1, 0, -1, 1), vjm_im = A(1, 0, -1, -1);
+  const T u0 = A(0, 0, o), uim = A(0, 0, o - 1), ujp = A(0, 0, o + sy), ujm = A(0, 0, o - sy);
+  const T ujp_im = A(0, 0, o + sy - 1), ujm_im = A(0, 0, o - sy - 1);
+  const T v0 = A(1, 0, o), vjm = A(1, 0, o - sy), vip = A(1, 0, o + 1), vim = A(1, 0, o - 1);
+  const T vjm_ip = A(1, 0, o - sy + 1), vjm_im = A(1, 0, o - sy - 1);
   s[0] = (u0 - uim) * rdx;
   s[1] = (v0 - vjm) * rdy;
-  s[2] = (A(2, 0, 0, 0) - A(2, -1, 0, 0)) * rdzf;
+  s[2] = (E.w - P.w) * rdzf;
   const T e_a = h * ((ujp - u0) * rdy + (vip - v0) * rdx);
   const T e_b = h * ((ujp_im - uim) * rdy + (v0 - vim) * rdx);
   const T e_c = h * ((u0 - ujm) * rdy + (vjm_ip - vjm) * rdx);
   const T e_d = h * ((uim - ujm_im) * rdy + (vjm - vjm_im) * rdx);
   s[3] = q * (e_a + e_b + e_c + e_d);
-  const T ukp = A(0, 1, 0, 0), ukm = A(0, -1, 0, 0), ukp_im = A(0, 1, 0, -1), ukm_im = A(0, -1, 0, -1);
-  const T f_a = h * ((ukp - u0) * rdzc + (A(2, 0, 0, 1) - A(2, 0, 0, 0)) * rdx);
-  const T f_b = h * ((ukp_im - uim) * rdzc + (A(2, 0, 0, 0) - A(2, 0, 0, -1)) * rdx);
-  const T f_c = h * ((u0 - ukm) * rdzcm + (A(2, -1, 0, 1) - A(2, -1, 0, 0)) * rdx);
-  const T f_d = h * ((uim - ukm_im) * rdzcm + (A(2, -1, 0, 0) - A(2, -1, 0, -1)) * rdx);
-  s[4] = q * (f_a + f_b + f_c + f_d);
-  const T vkp = A(1, 1, 0, 0), vkm = A(1, -1, 0, 0), vkp_jm = A(1, 1, -1, 0), vkm_jm = A(1, -1, -1, 0);
-  const T g_a = h * ((vkp - v0) * rdzc + (A(2, 0, 1, 0) - A(2, 0, 0, 0)) * rdy);
-  const T g_b = h * ((vkp_jm - vjm) * rdzc + (A(2, 0, 0, 0) - A(2, 0, -1, 0)) * rdy);
-  const T g_c = h * ((v0 - vkm) * rdzcm + (A(2, -1, 1, 0) - A(2, -1, 0, 0)) * rdy);
-  const T g_d = h * ((vjm - vkm_jm) * rdzcm + (A(2, -1, 0, 0) - A(2, -1, -1, 0)) * rdy);
-  s[5] = q * (g_a + g_b + g_c + g_d);
+  s[4] = q * (E.fa + E.fb + P.fa + P.fb);
+  s[5] = q * (E.ga + E.gb + P.ga + P.gb);
 }
 
+// x of another lane of the same row of 16 lanes, by a DPP lane pattern
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false));
+}
+// sum over each row of 16 lanes, a 4-level tree (partners at lane distance 1 and 2 in a quad,
+// then the mirrored half-row and row): every lane of a row holds the same bits
+__device__ inline double row_sum(double x) {
+  x = x + dpp_f64<0xB1>(x);    // quad permutation 1 0 3 2
+  x = x + dpp_f64<0x4E>(x);    // quad permutation 2 3 0 1
+  x = x + dpp_f64<0x141>(x);   // half-row mirror
+  x = x + dpp_f64<0x140>(x);   // row mirror
+  return x;
+}
+// lane L's value of x, uniform across the wave
+__device__ inline double lane_f64(double x, int L) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), L),
+                          __builtin_amdgcn_readlane(__double2loint(x), L));
+}
 template <typename T>
-__device__ inline int ring3(int q) {
-  return ((q % 3) + 3) % 3;
+__device__ inline T strain_norm(const T s[6]) {
+  return sqrt((T)2 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2]) + (T)4 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
 }
 
 // YW (ducts, walls in y too): the y pass of the test filter is the identity on the first and
@@ -410,10 +452,11 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   using namespace fused;
   if (gate != nullptr && gate[0] == 0) return;   // learned closure: no point fell back
   constexpr int NL = (N2 + NT - 1) / NT;          // halo-2 points per thread (loads)
-  constexpr int NH = (N1 + NT - 1) / NT;          // halo-1 points per thread (stage)
-  __shared__ T vel[3][3][N2];   // [slot][component][R2]
-  __shared__ T qb[9][N1];       // centre quantities of the current stage plane
-  __shared__ T ut[3][3][N1];    // filtered velocity [slot][component][R1]
+  constexpr int NH = (N1 + NT - 1) / NT;          // halo-1 points per thread (velocity filter)
+  __shared__ T vel[2][3][N2];   // [plane & 1][component][R2]
+  typedef HIP_vector_type<T, 2> T2;
+  __shared__ T2 qb[(NQ + 1) / 2][N1];   // filter inputs of the current stage plane, in pairs
+  __shared__ T ut[2][3][N1];    // filtered velocity [plane & 1][component][R1]
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   const int i0 = bid.x * TX, j0 = bid.y * TY;
   const int nz = g.nz;
@@ -432,9 +475,11 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     if (m < 0) m += nz;
     return m + 1;
   };
+  // the z spacing above plane q as the plane above sees it (they differ only across the
+  // periodic wrap, where the stored spacings at both ends are separately rounded)
+  auto rdzc_above = [&](int q) { return (T)ro_load(g.rdzc, phys(q + 1) - 1); };
   // in-plane offsets of the thread's halo-2 load points (tiles may exceed the grid: wrap)
   int lofs[NL];
-  int lrow[NL];   // global row of the load point before the wrap (ducts)
   for (int r = 0; r < NL; ++r) {
     const int e = tid + r * NT;
     const int rx = e % RX2, ry = e / RX2;
@@ -442,13 +487,12 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     if (i < 0) i += g.nx;
     if (j < 0) j += g.nys;
     lofs[r] = e < N2 ? j * g.nx + i : 0;
-    lrow[r] = j0 - 2 + ry;
   }
+  // global row of a load point before the wrap (ducts)
+  auto lrow = [&](int r) { return j0 - 2 + (tid + r * NT) / RX2; };
   // velocity of one plane held in registers between its fetch and its commit to LDS, so that
   // the global loads of plane p + 2 overlap the work on plane p: the loads are raw and
-  // unconditional (points past the halo read offset 0 and are not committed).  Strain ghosts
-  // of the wall model on the wall ghost planes are formed at the commit, from the thread's own
-  // LDS entries of the two planes next to the wall.
+  // unconditional (points past the halo read offset 0 and are not committed)
   T ra[NL], rb[NL], rc[NL];
   auto fetch = [&](int q) {
     const int pq = phys(q);
@@ -461,10 +505,10 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     if (YW && wm) {
       const int64_t bw = (int64_t)pq * sxy;
       for (int r = 0; r < NL; ++r) {
-        if (tid + r * NT < N2 && (lrow[r] == -1 || lrow[r] == g.ny)) {
+        if (tid + r * NT < N2 && (lrow(r) == -1 || lrow(r) == g.ny)) {
           // duct: strain ghosts of u and w on the y ghost rows, extrapolated in y
-          const int64_t o0 = bw + (lofs[r] % g.nx) + (int64_t)(lrow[r] < 0 ? 0 : g.ny - 1) * g.nx;
-          const int64_t o1 = o0 + (lrow[r] < 0 ? g.nx : -g.nx);
+          const int64_t o0 = bw + (lofs[r] % g.nx) + (int64_t)(lrow(r) < 0 ? 0 : g.ny - 1) * g.nx;
+          const int64_t o1 = o0 + (lrow(r) < 0 ? g.nx : -g.nx);
           const T a0 = u[o0], a1 = u[o1], c0 = w[o0], c1 = w[o1];
           ra[r] = a0 - (a1 - a0);
           rc[r] = c0 - (c1 - c0);
@@ -472,24 +516,24 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       }
     }
   };
+  auto yghost = [&](int r) { return YW && (lrow(r) == -1 || lrow(r) == g.ny); };
+  // commit plane q to its ring slot; with the wall model the top ghost plane's u, v are the
+  // linear extrapolation in z of planes nz and nz - 1 (the thread's own entries; plane nz - 1
+  // sits in the slot being replaced, read before it is overwritten)
   auto commit = [&](int q) {
-    const int sl = ring3<T>(q);
-    const int pq = phys(q);
-    if (wm && (pq == 0 || pq == nz + 1)) {
-      // u, v ghosts: linear extrapolation in z of the first two interior values (the planes
-      // 1, 2 or nz, nz - 1, already committed by this thread to its own entries)
-      const bool bot = pq == 0;
-      const int s1 = ring3<T>(bot ? q + 1 : q - 1), s2 = ring3<T>(bot ? q + 2 : q - 2);
-      const T ca = (T)ro_load(g.dzc, bot ? 0 : nz), cb = (T)ro_load(g.dzc, bot ? 1 : nz - 1);
+    const int sl = q & 1;
+    if (wm && phys(q) == nz + 1) {
+      const int s1 = (q - 1) & 1;
+      const T ca = (T)ro_load(g.dzc, nz), cb = (T)ro_load(g.dzc, nz - 1);
       for (int r = 0; r < NL; ++r) {
         const int e = tid + r * NT;
         if (e < N2) {
-          const T b1 = vel[s1][1][e], b2 = vel[s2][1][e];
-          rb[r] = bot ? b1 - ca * ((b2 - b1) / cb) : b1 + ca * ((b1 - b2) / cb);
+          const T b1 = vel[s1][1][e], b2 = vel[sl][1][e];
+          rb[r] = b1 + ca * ((b1 - b2) / cb);
           // ducts: u on a y ghost row keeps its y extrapolation of the stored plane (corner rule)
-          if (!(YW && (lrow[r] == -1 || lrow[r] == g.ny))) {
-            const T a1 = vel[s1][0][e], a2 = vel[s2][0][e];
-            ra[r] = bot ? a1 - ca * ((a2 - a1) / cb) : a1 + ca * ((a1 - a2) / cb);
+          if (!yghost(r)) {
+            const T a1 = vel[s1][0][e], a2 = vel[sl][0][e];
+            ra[r] = a1 + ca * ((a1 - a2) / cb);
           }
         }
       }
@@ -503,17 +547,9 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       }
     }
   };
-  // the thread's halo-1 points (R2 coordinates) and the x-y test filter of the velocity there:
-  // a register ring over planes p-1, p, p+1 (each plane filtered once)
-  int hx[NH], hy[NH];
-  for (int r = 0; r < NH; ++r) {
-    const int e = tid + r * NT;
-    hx[r] = e % RX1 + 1;
-    hy[r] = e / RX1 + 1;
-  }
-  // z pass by partial sums: G1 holds plane p's sum without its upper neighbour, G2 plane
-  // p + 1's lower-neighbour term; z weights per plane (lower, centre, upper) are (0, 1, 0)
-  // for u, v on the first off-wall layers and 0 for w on the top wall face
+  // z pass of the velocity filter by partial sums: G1 holds plane p's sum without its upper
+  // neighbour, G2 plane p + 1's lower-neighbour term; z weights per plane (lower, centre,
+  // upper) are (0, 1, 0) for u, v on the first off-wall layers and 0 for w on the top wall face
   T G1[NH][3], G2[NH][3];
   auto zw = [&](int q, int c, int which) -> T {
     if (!per && c == 2 && q == nz) return (T)0;
@@ -521,18 +557,20 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     return which == 1 ? W1 : W0;
   };
   // x-y filter of velocity plane q at the thread's halo-1 points, folded into the z sums;
-  // completes the filtered velocity of plane q - 1 (written to the ut ring when put != 0)
+  // completes the filtered velocity of plane q - 1 (written to its ring slot when put != 0)
   auto filter_xy = [&](int q, bool put) {
-    const int sl = ring3<T>(q), so = ring3<T>(q - 1);
+    const int sl = q & 1, so = (q - 1) & 1;
     for (int r = 0; r < NH; ++r) {
       const int e = tid + r * NT;
       if (e < N1) {
-        const int jr = j0 - 2 + hy[r];   // global row of the point
+        // the thread's halo-1 points for the velocity filter (R2 coordinates)
+        const int hx = e % RX1 + 1, hy = e / RX1 + 1;
+        const int jr = j0 - 2 + hy;   // global row of the point
         const bool yedge = YW && (jr == 0 || jr == g.ny - 1);
         for (int c = 0; c < 3; ++c) {
           T pl = (T)0;
           for (int dy = -1; dy <= 1; ++dy) {
-            const T* rr = &vel[sl][c][(hy[r] + dy) * RX2 + hx[r]];
+            const T* rr = &vel[sl][c][(hy + dy) * RX2 + hx];
             const T row = W0 * rr[-1] + W1 * rr[0] + W0 * rr[1];
             const T wy = (yedge && c != 1) ? (dy == 0 ? (T)1 : (T)0) : (dy == 0 ? W1 : W0);
             pl = pl + wy * row;
@@ -548,7 +586,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   // ducts: the y ghost rows of u~ and w~ of plane q by the strain ghost rule (extrapolated
   // with the wall model, odd with no-slip), from the completed rows next to them
   auto fix_rows = [&](int q) {
-    const int sl = ring3<T>(q);
+    const int sl = q & 1;
     for (int e = tid; e < N1; e += NT) {
       const int jr = j0 - 1 + e / RX1;
       if (jr != -1 && jr != g.ny) continue;
@@ -559,160 +597,191 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
       }
     }
   };
-  // register ring of x-y filtered quantities: A = plane k-1, B = k, C = k+1
-  T qA[15], qB[15], qC[15];
-  // ---- stage p: centre quantities and filtered velocity of plane p, then x-y filter
+  // the thread's stage points: its own cell and, on the first NHALO threads, one halo-1 point
+  // (R2 coordinates); each carries the upper z-edge terms of the previous plane
+  const int ox = tx + 2, oy = ty + 2;
+  const bool has_halo = tid < NHALO;
+  int bx = 1, by = 1;
+  if (has_halo) {
+    const int h = tid;
+    if (h < 2 * RX1) {
+      bx = h % RX1 + 1;
+      by = h < RX1 ? 1 : RY1;
+    } else {
+      bx = (h - 2 * RX1) < TY ? 1 : RX1;
+      by = (h - 2 * RX1) % TY + 2;
+    }
+  }
+  ZEdges<T> P0, P1;   // velocity: own cell, halo point
+  ZEdges<T> PT;       // filtered velocity: own cell
+  auto vacc = [](int s0, int s1) {
+    return [=](int c, int dz, int o) -> T { return vel[dz ? s1 : s0][c][o]; };
+  };
+  // running sums of the z pass of the test filter over the thread's cell: S1 holds plane p's
+  // sum without its upper neighbour, S2 plane p + 1's lower-neighbour term
+  T S1[NQ], S2[NQ], qx[NQ];
+  auto zq = [&](int q, int which) -> T {
+    if (!per && (q == 1 || q == nz)) return which == 1 ? (T)1 : (T)0;
+    return which == 1 ? W1 : W0;
+  };
+  // ---- stage p: filter inputs of plane p at the tile + 1 halo, then their x-y filter at the
+  // thread's cell (into qx)
   auto stage = [&](int p) {
     const int pq = phys(p);
-    const int sm = ring3<T>(p - 1), s0 = ring3<T>(p), sp = ring3<T>(p + 1);
-    const T rdzf = (T)ro_load(g.rdzf, pq), rdzc = (T)ro_load(g.rdzc, pq), rdzcm = (T)ro_load(g.rdzc, pq - 1);
+    const int s0 = p & 1, s1 = (p + 1) & 1;
+    const T rdzf = (T)ro_load(g.rdzf, pq), rdzc = (T)ro_load(g.rdzc, pq);
+    const T rdzn = rdzc_above(p);
+    const bool wrap = phys(p + 1) - 1 != pq;
     const bool own = p >= kb && p <= ke;
-    // pass 0: the thread's own cell (it also stores |S| there); pass 1: the 2 (TX + TY) + 4
-    // halo points, on the first threads
-#pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-      int x, y;
-      if (pass == 0) {
-        x = tx + 2;
-        y = ty + 2;
-      } else {
-        const int h = tid;
-        if (h >= 2 * (RX1 + TY)) break;
-        if (h < 2 * RX1) {
-          x = h % RX1 + 1;
-          y = h < RX1 ? 1 : RY1;
-        } else {
-          x = (h - 2 * RX1) < TY ? 1 : RX1;
-          y = (h - 2 * RX1) % TY + 2;
-        }
-      }
-      const int e = (y - 1) * RX1 + x - 1;
-      auto A = [&](int c, int dz, int dy, int dx) -> T {
-        const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
-        return vel[sl][c][(y + dy) * RX2 + x + dx];
-      };
+    const auto A = vacc(s0, s1);
+    auto point = [&](int x, int y, ZEdges<T>& P, bool store) {
+      const int o = y * RX2 + x;
+      const ZEdges<T> E = zedges<T>(A, o, RX2, rdx, rdy, rdzc);
       T s[6];
-      strain_from<T>(A, rdx, rdy, rdzf, rdzc, rdzcm, s);
-      const T sm_ = sqrt((T)2 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2]) +
-                         (T)4 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
-      qb[0][e] = (T)0.5 * (A(0, 0, 0, 0) + A(0, 0, 0, -1));
-      qb[1][e] = (T)0.5 * (A(1, 0, 0, 0) + A(1, 0, -1, 0));
-      qb[2][e] = (T)0.5 * (A(2, 0, 0, 0) + A(2, -1, 0, 0));
-      for (int a = 0; a < 6; ++a) qb[3 + a][e] = sm_ * s[a];
-      if (pass == 0 && nut != nullptr && own) {
+      strain_zm<T>(A, o, RX2, rdx, rdy, rdzf, P, E, s);
+      const T sm_ = strain_norm<T>(s);
+      const int e = (y - 1) * RX1 + x - 1;
+      const T uc = (T)0.5 * (A(0, 0, o) + A(0, 0, o - 1));
+      const T vc = (T)0.5 * (A(1, 0, o) + A(1, 0, o - RX2));
+      const T wc = (T)0.5 * (E.w + P.w);
+      qb[0][e] = T2(uc, vc);
+      qb[1][e] = T2(wc, uc * uc);
+      qb[2][e] = T2(vc * vc, wc * wc);
+      qb[3][e] = T2(uc * vc, uc * wc);
+      qb[4][e] = T2(vc * wc, sm_ * s[0]);
+      qb[5][e] = T2(sm_ * s[1], sm_ * s[2]);
+      qb[6][e] = T2(sm_ * s[3], sm_ * s[4]);
+      qb[7][e] = T2(sm_ * s[5], (T)0);
+      if (store && nut != nullptr && own) {
         const int i = i0 + tx, j = j0 + ty;
         if (i < g.nx && j < g.ny) store_nut(g, nut, p, j, i, sm_);
       }
-    }
+      if (wrap)
+        P = zedges<T>(A, o, RX2, rdx, rdy, rdzn);
+      else
+        P = E;
+    };
+    point(ox, oy, P0, true);
+    if (has_halo) point(bx, by, P1, false);
     lds_barrier();
-    // x-y filter of the 15 quantities at the thread's own cell (R1 coords tx+1, ty+1)
-    for (int a = 0; a < 15; ++a) qC[a] = (T)0;
+    // x-y filter of the 15 inputs at the thread's own cell (R1 coords tx+1, ty+1)
+    for (int a = 0; a < NQ; ++a) qx[a] = (T)0;
     const bool yedge = YW && (j0 + ty == 0 || j0 + ty == g.ny - 1);
 #pragma unroll 1
     for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll 1
       for (int dx = -1; dx <= 1; ++dx) {
         const T wy = yedge ? (dy == 0 ? (T)1 : (T)0) : (dy == 0 ? W1 : W0);
         const T wxy = wy * (dx == 0 ? W1 : W0);
         const int e = (ty + 1 + dy) * RX1 + tx + 1 + dx;
-        const T uc = qb[0][e], vc = qb[1][e], wc = qb[2][e];
-        const T val[15] = {uc, vc, wc, uc * uc, vc * vc, wc * wc, uc * vc, uc * wc, vc * wc,
-                           qb[3][e], qb[4][e], qb[5][e], qb[6][e], qb[7][e], qb[8][e]};
-        for (int a = 0; a < 15; ++a) qC[a] = qC[a] + wxy * val[a];
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+          const T2 pr = qb[a / 2][e];
+          qx[a] = qx[a] + wxy * (a % 2 ? pr.y : pr.x);
+        }
       }
   };
-  // ---- output plane k from the register ring (lo, mid, hi) and the filtered-velocity ring
-  auto output = [&](int k, const T* lo, const T* mid, const T* hi) {
+  // ---- output plane k: F holds the test-filtered inputs of its cell; the filtered velocity of
+  // planes k and k + 1 is in the ring (the top ghost plane is formed on the fly), PT holds the
+  // upper edge terms of plane k - 1
+  auto output = [&](int k, const T* F) {
     const int pk = phys(k);
-    // wall ghosts of the filtered velocity (strain ghost rule): fill the free ring slot
-    if (!per && (k == 1 || k == nz)) {
-      lds_barrier();   // the free slot may still be read by the previous plane's output
-      const int sg = ring3<T>(k == 1 ? 0 : nz + 1);
-      const int s1 = ring3<T>(k == 1 ? 1 : nz), s2 = ring3<T>(k == 1 ? 2 : nz - 1);
-      for (int e = tid; e < N1; e += NT) {
-        for (int c = 0; c < 2; ++c) {
-          const T a1 = ut[s1][c][e], a2 = ut[s2][c][e];
-          T gh;
-          if (wm) {
-            gh = k == 1 ? a1 - (T)ro_load(g.dzc, 0) * ((a2 - a1) / (T)ro_load(g.dzc, 1))
-                        : a1 + (T)ro_load(g.dzc, nz) * ((a1 - a2) / (T)ro_load(g.dzc, nz - 1));
-          } else {
-            gh = -a1;
-          }
-          ut[sg][c][e] = gh;
-        }
-        ut[sg][2][e] = (T)0;
-      }
-      lds_barrier();
-    }
     double lm = 0.0, mm = 0.0;
     const int i = i0 + tx, j = j0 + ty;
-    if (i < g.nx && j < g.ny) {
-      const int sm = ring3<T>(k - 1), s0 = ring3<T>(k), sp = ring3<T>(k + 1);
-      const int x = tx + 1, y = ty + 1;  // own cell in R1
-      auto A = [&](int c, int dz, int dy, int dx) -> T {
-        const int sl = dz < 0 ? sm : (dz > 0 ? sp : s0);
-        return ut[sl][c][(y + dy) * RX1 + x + dx];
+    const int o = (ty + 1) * RX1 + tx + 1;   // own cell in R1
+    const int sA = k & 1, sB = (k + 1) & 1;
+    const bool top = !per && k == nz;
+    const T rdzc = (T)ro_load(g.rdzc, pk), rdzf = (T)ro_load(g.rdzf, pk);
+    T st[6];
+    if (top) {
+      // strain ghost rule above the top wall, from planes nz (slot sA) and nz - 1 (slot sB)
+      const T ca = (T)ro_load(g.dzc, nz), cb = (T)ro_load(g.dzc, nz - 1);
+      const auto A = [&](int c, int dz, int oo) -> T {
+        const T a1 = ut[sA][c][oo];
+        if (dz == 0) return a1;
+        const T a2 = ut[sB][c][oo];
+        return wm ? a1 + ca * ((a1 - a2) / cb) : -a1;
       };
-      T st[6];
-      strain_from<T>(A, rdx, rdy, (T)ro_load(g.rdzf, pk), (T)ro_load(g.rdzc, pk), (T)ro_load(g.rdzc, pk - 1), st);
-      const T stm = sqrt((T)2 * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2]) +
-                         (T)4 * (st[3] * st[3] + st[4] * st[4] + st[5] * st[5]));
+      strain_zm<T>(A, o, RX1, rdx, rdy, rdzf, PT, zedges<T>(A, o, RX1, rdx, rdy, rdzc), st);
+    } else {
+      const auto A = [&](int c, int dz, int oo) -> T { return ut[dz ? sB : sA][c][oo]; };
+      const ZEdges<T> E = zedges<T>(A, o, RX1, rdx, rdy, rdzc);
+      strain_zm<T>(A, o, RX1, rdx, rdy, rdzf, PT, E, st);
+      if (phys(k + 1) - 1 != pk)
+        PT = zedges<T>(A, o, RX1, rdx, rdy, rdzc_above(k));
+      else
+        PT = E;
+    }
+    if (i < g.nx && j < g.ny) {
+      const T stm = strain_norm<T>(st);
       const bool wall_layer = !per && (k == 1 || k == nz);
       const bool wall_row = YW && (j == 0 || j == g.ny - 1);
       // 3-D, 2-D or (duct corners) 1-D test filter: 4, 4^(2/3), 2^(2/3)
       const T alpha2 = (wall_layer && wall_row) ? (T)1.5874010519681994
                                                 : ((wall_layer || wall_row) ? (T)2.5198420997897464 : (T)4);
       const T d2 = (T)ro_load(g.delta2, pk);
-      // z pass of the test filter, one quantity at a time
-      auto Fz = [&](int a) { return W0 * lo[a] + W1 * mid[a] + W0 * hi[a]; };
-      const T F0 = Fz(0), F1 = Fz(1), F2 = Fz(2);
-      const T Fa[6] = {F0, F1, F2, F0, F0, F1}, Fb[6] = {F0, F1, F2, F1, F2, F2};
+      const T Fa[6] = {F[0], F[1], F[2], F[0], F[0], F[1]}, Fb[6] = {F[0], F[1], F[2], F[1], F[2], F[2]};
       for (int c = 0; c < 6; ++c) {
-        const T L = Fz(3 + c) - Fa[c] * Fb[c];
-        const T M = (T)2 * d2 * (Fz(9 + c) - alpha2 * stm * st[c]);
+        const T L = F[3 + c] - Fa[c] * Fb[c];
+        const T M = (T)2 * d2 * (F[9 + c] - alpha2 * stm * st[c]);
         const double wgt2 = c < 3 ? 1.0 : 2.0;
         lm += wgt2 * (double)L * (double)M;
         mm += wgt2 * (double)M * (double)M;
       }
     }
+    lm = row_sum(lm);
+    mm = row_sum(mm);
     if (YW) {
-      // x-line sums: a row of the tile is 32 lanes of one wave; partials [k][j][tile x]
-      for (int off = 16; off > 0; off >>= 1) {
-        lm += __shfl_down(lm, off, 32);
-        mm += __shfl_down(mm, off, 32);
-      }
+      // x-line sums: a row of the tile is 32 lanes (two rows of 16) of one wave; partials
+      // [k][j][tile x]
+      const bool lo = (tid & 63) < 32;
+      lm = lo ? lane_f64(lm, 0) + lane_f64(lm, 16) : lane_f64(lm, 32) + lane_f64(lm, 48);
+      mm = lo ? lane_f64(mm, 0) + lane_f64(mm, 16) : lane_f64(mm, 32) + lane_f64(mm, 48);
       const int jrow = j0 + ty;
       if (tx == 0 && jrow < g.ny) {
-        const int64_t o = (((int64_t)(k - 1) * g.ny + jrow) * gdx + bid.x) * 2;
-        part[o] = lm;
-        part[o + 1] = mm;
+        const int64_t oo = (((int64_t)(k - 1) * g.ny + jrow) * gdx + bid.x) * 2;
+        part[oo] = lm;
+        part[oo + 1] = mm;
       }
       return;
     }
-    // wave sums in a fixed order (shuffle tree); the waves' partials go out per plane and
-    // are summed over (tile, wave) in a fixed order by the plane reduction
-    for (int off = 32; off > 0; off >>= 1) {
-      lm += __shfl_down(lm, off, 64);
-      mm += __shfl_down(mm, off, 64);
-    }
+    // wave sums in a fixed order (row trees, then the four rows in turn); the waves' partials
+    // go out per plane and are summed over (tile, wave) in a fixed order by the plane reduction
+    lm = ((lane_f64(lm, 0) + lane_f64(lm, 16)) + lane_f64(lm, 32)) + lane_f64(lm, 48);
+    mm = ((lane_f64(mm, 0) + lane_f64(mm, 16)) + lane_f64(mm, 32)) + lane_f64(mm, 48);
     if (tid % 64 == 0) {
-      const int64_t o = ((int64_t)(k - 1) * ntile * WV + tile * WV + tid / 64) * 2;
-      part[o] = lm;
-      part[o + 1] = mm;
+      const int64_t oo = ((int64_t)(k - 1) * ntile * WV + tile * WV + tid / 64) * 2;
+      part[oo] = lm;
+      part[oo + 1] = mm;
     }
   };
-  // ---- march: velocity plane p + 1 is committed to LDS at the top of iteration p, the loads
-  // of plane p + 2 are issued right after and complete under the work on plane p
+  // ---- prologue: planes pstart - 1 and pstart in the ring, pstart + 1 in flight
   const int pstart = per ? kb - 1 : max(kb - 1, 1);
   const int pend = per ? ke + 1 : min(ke + 1, nz);
   if (wm && pstart == 1) {
-    // the bottom ghost plane is formed from planes 1 and 2: those are committed first (plane 2
-    // is fetched again for the loop's first commit)
+    // the bottom ghost plane: u, v extrapolated linearly in z from planes 1 (in the ring) and
+    // 2 (held in registers), w and the duct's y-ghost u as stored
     fetch(1);
     commit(1);
     fetch(2);
-    commit(2);
+    T xa[NL], xb[NL];
+    for (int r = 0; r < NL; ++r) {
+      xa[r] = ra[r];
+      xb[r] = rb[r];
+    }
     fetch(0);
+    const T ca = (T)ro_load(g.dzc, 0), cb = (T)ro_load(g.dzc, 1);
+    for (int r = 0; r < NL; ++r) {
+      const int e = tid + r * NT;
+      if (e < N2) {
+        const T b1 = vel[1][1][e];
+        rb[r] = b1 - ca * ((xb[r] - b1) / cb);
+        if (!yghost(r)) {
+          const T a1 = vel[1][0][e];
+          ra[r] = a1 - ca * ((xa[r] - a1) / cb);
+        }
+      }
+    }
     commit(0);
     fetch(2);
   } else {
@@ -727,40 +796,55 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
     for (int c = 0; c < 3; ++c) G2[r][c] = (T)0;
   filter_xy(pstart - 1, false);
   filter_xy(pstart, false);
-  // threads exchange data through LDS only (the stored |S| and partial sums are read by later
-  // launches): the barriers leave global loads in flight
+  {
+    const auto A = vacc((pstart - 1) & 1, pstart & 1);
+    const T rdzn = rdzc_above(pstart - 1);
+    P0 = zedges<T>(A, oy * RX2 + ox, RX2, rdx, rdy, rdzn);
+    if (has_halo) P1 = zedges<T>(A, by * RX2 + bx, RX2, rdx, rdy, rdzn);
+  }
+  for (int a = 0; a < NQ; ++a) S2[a] = (T)0;
+  lds_barrier();   // the first commit replaces plane pstart - 1
+  // ---- march: velocity plane p + 1 is committed to LDS at the top of iteration p, the loads
+  // of plane p + 2 are issued right after and complete under the work on plane p.  Threads
+  // exchange data through LDS only (the stored |S| and partial sums are read by later
+  // launches): the barriers leave global loads in flight.
   for (int p = pstart; p <= pend; ++p) {
     commit(p + 1);
     lds_barrier();
     fetch(min(p + 2, pend + 1));   // the last one reloads plane pend + 1 and is not committed
     filter_xy(p + 1, true);
-    for (int a = 0; a < 15; ++a) {
-      qA[a] = qB[a];
-      qB[a] = qC[a];
-    }
     stage(p);
     if (YW) {
       fix_rows(p);
       lds_barrier();
     }
     const int k = p - 1;
+    if (k == kb - 1 && (per || kb > 1)) {
+      // upper edge terms of the filtered velocity below the first output plane
+      const auto A = [&](int c, int dz, int oo) -> T { return ut[dz ? (p & 1) : (k & 1)][c][oo]; };
+      PT = zedges<T>(A, (ty + 1) * RX1 + tx + 1, RX1, rdx, rdy, rdzc_above(k));
+    }
     if (k >= kb && k <= ke) {
       if (!per && k == 1) {
-        T ext[15];
-        for (int a = 0; a < 15; ++a) ext[a] = (T)2 * qB[a] - qC[a];
-        output(k, ext, qB, qC);
-      } else {
-        output(k, qA, qB, qC);
+        // below the bottom wall: the strain ghost rule from planes 1 and 2, w~ = 0 on the wall
+        const T ca = (T)ro_load(g.dzc, 0), cb = (T)ro_load(g.dzc, 1);
+        const auto A = [&](int c, int dz, int oo) -> T {
+          if (dz) return ut[1][c][oo];
+          if (c == 2) return (T)0;
+          const T a1 = ut[1][c][oo], a2 = ut[0][c][oo];
+          return wm ? a1 - ca * ((a2 - a1) / cb) : -a1;
+        };
+        PT = zedges<T>(A, (ty + 1) * RX1 + tx + 1, RX1, rdx, rdy, (T)ro_load(g.rdzc, 0));
       }
+      for (int a = 0; a < NQ; ++a) S1[a] = S1[a] + zq(k, 2) * qx[a];
+      output(k, S1);
+    }
+    for (int a = 0; a < NQ; ++a) {
+      S1[a] = S2[a] + zq(p, 1) * qx[a];
+      S2[a] = zq(p + 1, 0) * qx[a];
     }
   }
-  if (!per && ke == nz) {
-    // plane nz: the stage of nz + 1 does not exist; its z neighbour is extrapolated
-    // (plane nz - 1 is always staged: pstart <= kb - 1 <= nz - 1)
-    T ext[15];
-    for (int a = 0; a < 15; ++a) ext[a] = (T)2 * qC[a] - qB[a];
-    output(nz, qB, qC, ext);
-  }
+  if (!per && ke == nz) output(nz, S1);   // the z pass is the identity on the top layer
 }
 
 template <typename T, bool YW = false>

@@ -225,9 +225,9 @@ def _depth(n):
 def plane_sum_depth(case, g):
     """Depth of the summation trees of the plane (x-line, volume) sums: the oracle's numpy
     reduction (pairwise along the contiguous axis: at most log2(n) + 20 levels, plus one level
-    per row when the outer axes are not merged) and the kernel's (64-lane shuffle tree, each
-    thread's strided share of the per-wave partials of 32 x 8 tiles, a 256-thread block
-    tree); the larger."""
+    per row when the outer axes are not merged) and the kernel's (16-lane row trees, then the
+    four rows of a wave added in turn, each thread's strided share of the per-wave partials
+    of 32 x 8 tiles, a 256-thread block tree); the larger."""
     nx, ny, nz = g.nx, g.ny, g.nz
     ntile = ((nx + 31) // 32) * ((ny + 7) // 8)
     if g.ywalls:
@@ -235,10 +235,10 @@ def plane_sum_depth(case, g):
         d_gpu = 5 + (nx + 31) // 32
     elif case.zbc == ZBC_PERIODIC:
         d_or = nz * ny + _depth(nx) + 20
-        d_gpu = 6 + (nz * ntile * 4 + 255) // 256 + 8
+        d_gpu = 7 + (nz * ntile * 4 + 255) // 256 + 8
     else:
         d_or = ny + _depth(nx) + 20
-        d_gpu = 6 + (ntile * 4 + 255) // 256 + 8
+        d_gpu = 7 + (ntile * 4 + 255) // 256 + 8
     return max(d_or, d_gpu)
 
 
