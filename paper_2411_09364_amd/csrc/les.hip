@@ -188,7 +188,7 @@ size_t carve(Ctx& c, char* base) {
   t.twx_f = (float*)take(2 * f.nx * 4);
   t.twy_f = (float*)take(2 * f.ny * 4);
   t.twz_f = (float*)take(2 * n * 4);
-  t.hfac = (double*)take(12 * n * 8);
+  t.hfac = (double*)take(14 * n * 8);
   t.dt = (double*)take(16 * 8);
   c.mlp_cnt = (int*)take(2 * sizeof(int));
   t.red_n = 4096;
@@ -478,7 +478,7 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
           const double d = std::pow((f.lx / f.nx) * (f.ly / f.ny) * c.dzf[k], 1.0 / 3.0);
           c.coef_host[k] = (f.cs * d) * (f.cs * d);
         }
-      c.hfac_host.assign(12 * n, 0.0);
+      c.hfac_host.assign(14 * n, 0.0);
       for (int k = 0; k < n; ++k) c.hfac_host[4 * n + k] = 1.0;
       if ((s = up(c.t.zc, c.zc.data(), (n + 2) * 8)) != LES_OK) return s;
       if ((s = up(c.t.dzf, c.dzf.data(), (n + 2) * 8)) != LES_OK) return s;

@@ -215,10 +215,14 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
                                                   T* __restrict__ vs, T* __restrict__ ws,
                                                   const double* __restrict__ dtp, double alpha, double beta,
                                                   double gamma, int kc, int chunk,
-                                                  const double* __restrict__ tau, int wallmodel) {
+                                                  const double* __restrict__ tau, int wallmodel,
+                                                  const double* __restrict__ hfw,
+                                                  T (&ring)[3][5][zmarch::N1]) {
+  // ring: [plane slot][u v w nu p][tile + 1 halo]
   using namespace zmarch;
   constexpr bool use_rprev = (RW & 1) != 0, write_r = (RW & 2) != 0;
-  __shared__ T ring[3][5][N1];   // [plane slot][u v w nu p][tile + 1 halo]
+  // CN in z: the thread's running elimination values of u, v, w, kept in LDS
+  __shared__ double ecar[MODE == VISC_CN_Z ? 3 : 1][NT];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   const int i0 = bid.x * TX, j0 = bid.y * TY;
   const int kb = 1 + chunk * kc;
@@ -283,6 +287,14 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
     }
   };
   fetch_r(kb);
+  // CN in z with walls (FP64): the forward elimination of the z systems runs here, along the
+  // march, from a zero start at the chunk's first row (the back substitution adds the
+  // contribution of the rows below the chunk)
+  if constexpr (MODE == VISC_CN_Z) {
+    ecar[0][tid] = 0.0;
+    ecar[1][tid] = 0.0;
+    ecar[2][tid] = 0.0;
+  }
   for (int k = kb; k <= ke; ++k) {
     commit(k + 1);
     // the ring is the only data threads exchange: global loads in flight stay in flight
@@ -322,6 +334,32 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
         uo = (T)((double)uo + ch * (-(tau[b0 * sxy + cj] / g.nu) * rz));
         vo = (T)((double)vo + ch * (-(tau[(b0 + 1) * sxy + cj] / g.nu) * rz));
       }
+      if constexpr (MODE == VISC_CN_Z) {
+        if (hfw != nullptr) {
+          double fu = (double)uo, fv = (double)vo;
+          if (wallmodel && (k == 1 || k == g.nz)) {
+            // wall-model rows: the lagged wall stress enters as a known flux
+            const double ch = gamma * g.nu * ro_load(dtp, 0) / 2.0;
+            const int64_t cj = (int64_t)j * g.nx + i;
+            const int b0 = k == 1 ? 0 : 2;
+            const double dz = ro_load(g.dzf, k);
+            fu += ch * (-(tau[b0 * sxy + cj] / g.nu) / dz);
+            fv += ch * (-(tau[(b0 + 1) * sxy + cj] / g.nu) / dz);
+          }
+          const int n = g.nz, r = k - 1;
+          const double eu = (fu - ro_load(hfw, 6 * n + r) * ecar[0][tid]) * ro_load(hfw, n + r);
+          const double ev = (fv - ro_load(hfw, 6 * n + r) * ecar[1][tid]) * ro_load(hfw, n + r);
+          ecar[0][tid] = eu;
+          ecar[1][tid] = ev;
+          uo = (T)eu;
+          vo = (T)ev;
+          if (k < n) {   // w rows: the faces 1 .. nz - 1
+            const double ew = ((double)wo - ro_load(hfw, 7 * n + r) * ecar[2][tid]) * ro_load(hfw, 3 * n + r);
+            ecar[2][tid] = ew;
+            wo = (T)ew;
+          }
+        }
+      }
       if constexpr (write_r) {
         ru[c0] = Ru;
         rv[c0] = Rv;
@@ -350,17 +388,21 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 3 : 4) k_predictor(GridP
                                                                         double alpha, double beta, double gamma,
                                                                         double* hfac,
                                                                         int wallmodel, int kc,
-                                                                        const double* __restrict__ tau, int fslice) {
+                                                                        const double* __restrict__ tau, int fslice,
+                                                                        const double* __restrict__ hfw) {
   const dim3 bid = xcd_tile(blockIdx, gridDim);
+  __shared__ T ring[3][5][zmarch::N1];
+  static_assert(sizeof(ring) >= 2 * (kMaxNz + 2) * sizeof(double), "factorisation scratch");
   if (MODE != VISC_EXPLICIT && fslice && bid.z == 0) {
-    __shared__ double fz[2][kMaxNz + 2];   // metric copies of the factorisation
+    // metric copies of the factorisation in the ring's memory
+    double* fz = reinterpret_cast<double*>(&ring[0][0][0]);
     if (bid.x == 0 && bid.y == 0)
-      helmholtz_factor_body(g, hfac, dtp, gamma, wallmodel, fz[0], fz[1], threadIdx.y * blockDim.x + threadIdx.x,
-                            blockDim.x * blockDim.y);
+      helmholtz_factor_body(g, hfac, dtp, gamma, wallmodel, fz, fz + kMaxNz + 2,
+                            threadIdx.y * blockDim.x + threadIdx.x, blockDim.x * blockDim.y);
     return;
   }
   predictor_zm_body<T, MODE, RW>(bid, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta, gamma,
-                                 kc, (int)bid.z - fslice, tau, wallmodel);
+                                 kc, (int)bid.z - fslice, tau, wallmodel, hfw, ring);
 }
 
 // Batched predictor (explicit viscous terms): one launch over all boxes of a batch, the same
@@ -371,10 +413,144 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) kb_predictor(Batc
   int box;
   const dim3 bid = batch_bid(m, BK_PRED, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
+  __shared__ T ring[3][5][zmarch::N1];
   predictor_zm_body<T, VISC_EXPLICIT, RW>(bid, d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w,
                                           (const T*)d.p, (const T*)d.nut, d.coef, (T*)d.ru, (T*)d.rv, (T*)d.rw,
                                           (T*)d.us, (T*)d.vs, (T*)d.wsf, d.dt, alpha, beta, gamma, d.pkc, (int)bid.z,
-                                          nullptr, 0);
+                                          nullptr, 0, nullptr, ring);
+}
+
+// CN in z with walls, FP64: the predictor eliminates along its z march and a streaming
+// kernel substitutes back (the z chunks of the march fixed up through the products of the
+// elimination's row multipliers); the chunk corrections are held per thread for at most
+// HZ_MAXCH chunks.  Otherwise the staged solve below runs after the predictor.
+constexpr int HZ_MAXCH = 8;
+template <typename T>
+bool hz_fused(const Ctx& c) {
+  return sizeof(T) == 8 && c.cfg.implicit_z == VISC_CN_Z && c.cfg.zbc != LES_ZBC_PERIODIC &&
+         (c.g.nz + c.pred_kc - 1) / c.pred_kc <= HZ_MAXCH;
+}
+
+// Factorisation of the substep's z systems in one block of 1024 threads, ahead of the
+// predictor: one thread per row (u/v rows on threads 0..511, w rows on 512..1023), with the
+// recurrences of the Thomas factorisation taken as prefix scans (Hillis-Steele, log2 nz
+// levels):
+//   pivots p_k = b_k - a_k c_{k-1} / p_{k-1}: the ratio x_k / y_k of the first column of the
+//     product M_k ... M_0, M_k = [[b_k, -a_k c_{k-1}], [1, 0]] (each partial product rescaled
+//     by a power of two, which leaves the ratio unchanged);
+//   products pp_k of the elimination's row multipliers -a_j r_j from the first row of each
+//     chunk of kc rows (the weight of the value below a chunk in each eliminated row);
+//   flow-rate profile q = H^-1 1 of the u rows (no-slip walls; 1 otherwise): forward
+//     d_k = r_k - a_k r_k d_{k-1}, back q_k = d_k - c'_k q_{k+1}, both affine recurrences.
+// Rows, layout and the row arithmetic as helmholtz_factor_body; the pivots, products and q
+// agree with its sequential sweeps up to rounding.
+constexpr int HZF_T = 512;   // threads per system (>= kMaxNz)
+__global__ void __launch_bounds__(1024) k_hz_factor(GridP g, double* __restrict__ hfac,
+                                                    const double* __restrict__ dtp, double gamma, int wallmodel,
+                                                    int kc) {
+  static_assert(HZF_T >= kMaxNz, "one thread per row");
+  __shared__ double sc[2][4][HZF_T];   // per system: scan values (up to a 2 x 2 matrix per row)
+  const int n = g.nz;
+  const int sys = (int)threadIdx.x / HZF_T, k = (int)threadIdx.x % HZF_T;   // 0: u/v, 1: w
+  const int rows = sys == 0 ? n : n - 1;
+  const bool row = k < rows;
+  const double c = gamma * g.nu * dtp[0] / 2.0;
+  // the row (a, b, cc) and the super-diagonal of the row below
+  auto coeffs = [&](int kk, double& a, double& b, double& cc) {   // kk = 1 .. rows
+    if (sys == 0) {
+      double lo = 1.0 / (g.dzc[kk - 1] * g.dzf[kk]);
+      double up = 1.0 / (g.dzc[kk] * g.dzf[kk]);
+      double dg = -(lo + up);
+      if (kk == 1) dg += wallmodel ? lo : -lo;
+      if (kk == n) dg += wallmodel ? up : -up;
+      if (kk == 1) lo = 0.0;
+      if (kk == n) up = 0.0;
+      a = -c * lo, b = 1.0 - c * dg, cc = -c * up;
+    } else {
+      const int m = n - 1;
+      double lo = 1.0 / (g.dzf[kk] * g.dzc[kk]);
+      double up = 1.0 / (g.dzf[kk + 1] * g.dzc[kk]);
+      const double dg = -(lo + up);
+      if (kk == 1) lo = 0.0;
+      if (kk == m) up = 0.0;
+      a = -c * lo, b = 1.0 - c * dg, cc = -c * up;
+    }
+  };
+  double a = 0.0, b = 1.0, cc = 0.0, cbelow = 0.0;
+  if (row) {
+    coeffs(k + 1, a, b, cc);
+    if (k > 0) {
+      double a1, b1;
+      coeffs(k, a1, b1, cbelow);
+    }
+    hfac[(sys == 0 ? 6 : 7) * n + k] = a;
+    hfac[(sys == 0 ? 8 : 10) * n + k] = b;
+    hfac[(sys == 0 ? 9 : 11) * n + k] = cc;
+  }
+  double (*S)[HZF_T] = sc[sys];
+  // ---- pivots: inclusive scan of 2 x 2 matrix products (window product on the left)
+  double m00 = b, m01 = -a * cbelow, m10 = 1.0, m11 = 0.0;
+  for (int d = 1; d < n; d <<= 1) {   // levels: uniform across the block
+    S[0][k] = m00, S[1][k] = m01, S[2][k] = m10, S[3][k] = m11;
+    __syncthreads();
+    if (k >= d && row) {
+      const double q00 = S[0][k - d], q01 = S[1][k - d], q10 = S[2][k - d], q11 = S[3][k - d];
+      double r00 = m00 * q00 + m01 * q10, r01 = m00 * q01 + m01 * q11;
+      double r10 = m10 * q00 + m11 * q10, r11 = m10 * q01 + m11 * q11;
+      const double big = fmax(fmax(fabs(r00), fabs(r01)), fmax(fabs(r10), fabs(r11)));
+      int e;
+      (void)frexp(big, &e);
+      m00 = ldexp(r00, -e), m01 = ldexp(r01, -e), m10 = ldexp(r10, -e), m11 = ldexp(r11, -e);
+    }
+    __syncthreads();
+  }
+  const double r = m10 / m00;   // 1 / pivot
+  const double cpk = cc * r;
+  if (row) {
+    hfac[(sys == 0 ? 1 : 3) * n + k] = r;
+    hfac[(sys == 0 ? 0 : 2) * n + k] = cpk;
+  }
+  // ---- chunk products of -a r (segmented inclusive product scan)
+  double pp = -a * r;
+  const int seg0 = (k / kc) * kc;
+  for (int d = 1; d < kc; d <<= 1) {
+    S[0][k] = pp;
+    __syncthreads();
+    if (k - d >= seg0 && row) pp = pp * S[0][k - d];
+    __syncthreads();
+  }
+  if (row) hfac[(sys == 0 ? 12 : 13) * n + k] = pp;
+  // ---- flow-rate profile of the u/v system: 1 unless both walls are no-slip
+  if (g.zbc != LES_ZBC_NOSLIP) {   // uniform across the block
+    if (sys == 0 && row) hfac[4 * n + k] = 1.0;
+    return;
+  }
+  // every thread takes part in the scans' barriers; the w system's values are not stored
+  // forward affine scan x -> al + be x, a window's map applied after the one below it
+  double al = r, be = -a * r;
+  for (int d = 1; d < n; d <<= 1) {
+    S[0][k] = al, S[1][k] = be;
+    __syncthreads();
+    if (k >= d && row) {
+      const double al2 = S[0][k - d], be2 = S[1][k - d];
+      al = al + be * al2;
+      be = be * be2;
+    }
+    __syncthreads();
+  }
+  // back affine scan from the top row: q_k = d_k - c'_k q_{k+1}
+  double bl = al, bb = k == rows - 1 ? 0.0 : -cpk;
+  for (int d = 1; d < n; d <<= 1) {
+    S[0][k] = bl, S[1][k] = bb;
+    __syncthreads();
+    if (k + d < rows && row) {
+      const double bl2 = S[0][k + d], bb2 = S[1][k + d];
+      bl = bl + bb * bl2;
+      bb = bb * bb2;
+    }
+    __syncthreads();
+  }
+  if (sys == 0 && row) hfac[4 * n + k] = bl;
 }
 
 template <typename T>
@@ -386,9 +562,14 @@ void launch_predictor(Ctx& c, int stage) {
   const int kc = c.pred_kc;
   const unsigned nch = (unsigned)((c.g.nz + kc - 1) / kc);
   const int mode = c.cfg.implicit_z;   // VISC_* (validated at init)
-  // the Helmholtz rows are needed with walls only (periodic z solves by FFT): the extra z slice
-  // that factorises them exists then
-  const int fslice = mode != VISC_EXPLICIT && c.cfg.zbc != LES_ZBC_PERIODIC ? 1 : 0;
+  const bool fused = hz_fused<T>(c);
+  // the Helmholtz rows are needed with walls only (periodic z solves by FFT): a launch of its
+  // own factorises them ahead of a predictor that eliminates along its march, else the extra
+  // z slice of the predictor's launch does
+  const int fslice = !fused && mode != VISC_EXPLICIT && c.cfg.zbc != LES_ZBC_PERIODIC ? 1 : 0;
+  if (fused)
+    LES_LAUNCH(c, "hz_factor", 0, k_hz_factor, dim3(1), dim3(2 * HZF_T), 0, c.g, c.t.hfac, c.t.dt, G,
+               c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, kc);
   const dim3 grid((c.g.nx + TX - 1) / TX, (c.g.ny + TY - 1) / TY, nch + fslice);
   const int use_rprev = stage > 0;
   const int write_r = stage < 2;
@@ -405,7 +586,8 @@ void launch_predictor(Ctx& c, int stage) {
   LES_LAUNCH(c, "predictor", words * pts * sizeof(T), f, grid, dim3(TX, TY), 0, c.g, (const T*)c.u, (const T*)c.v,
              (const T*)c.w, (const T*)c.p, (const T*)c.nut, c.t.coef, (T*)c.ru, (T*)c.rv, (T*)c.rw, (T*)c.us,
              (T*)c.vs, (T*)c.wsf, c.t.dt, A[stage], B[stage], G, c.t.hfac,
-             c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, kc, c.t.tau, fslice);
+             c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, kc, c.t.tau, fslice,
+             fused ? (const double*)c.t.hfac : nullptr);
 }
 
 // ============================================================================ CN in z
@@ -413,7 +595,8 @@ void launch_predictor(Ctx& c, int stage) {
 // its Thomas factorisation (pivots and normalised super-diagonal) is computed once per
 // substep by three threads: u/v rows, w rows, and the flow-rate profile q = H^-1 1 of
 // the u rows (no-slip walls; 1 otherwise).  Layout of hfac: [cp_uv | rp_uv | cp_w | rp_w
-// | q | -] each nz long.
+// | q | - | a_uv | a_w | b_uv | c_uv | b_w | c_w | pp_uv | pp_w] each nz long (pp: see
+// k_hz_factor).
 // Runs in one block of nthr threads; dzf/dzc are LDS copies of the metrics.  Thread 0 runs
 // the u/v chain (and the flow-rate profile), thread 64 (thread 0 in small blocks) the w chain.
 __device__ void helmholtz_factor_body(const GridP& g, double* hfac, const double* dtp, double gamma, int wallmodel,
@@ -584,9 +767,65 @@ __global__ void __launch_bounds__(256) k_helmholtz(GridP g, T* __restrict__ us, 
   }
 }
 
+// Back substitution of the CN-z systems eliminated by the predictor (Eq. onestar_imp1d): one
+// thread per interior (j, i) column and component, marching down the rows.  The predictor's
+// chunk c left e_r = d_r - pp_r D_c in its rows, D_c the elimination value of the row below
+// the chunk; the D_c are rebuilt from the chunk tops upwards, then x_r = d_r - c'_r x_{r+1}.
+template <typename T>
+__global__ void __launch_bounds__(256) k_hz_back(GridP g, T* __restrict__ us, T* __restrict__ vs,
+                                                 T* __restrict__ ws, const double* __restrict__ hfac, int kc) {
+  __shared__ double dl[HZ_MAXCH][256];   // each thread's own chunk corrections
+  const int comp = blockIdx.y;
+  const int n = g.nz;
+  const int m = comp < 2 ? n : n - 1;
+  const int64_t s = g.sxy;
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= (int64_t)g.ny * g.nx) return;
+  T* x = (comp == 0 ? us : (comp == 1 ? vs : ws)) + s + col;   // row r at x[r s]
+  const double* cp = hfac + (comp < 2 ? 0 : 2 * n);
+  const double* pp = hfac + (comp < 2 ? 12 * n : 13 * n);
+  const int nch = (m + kc - 1) / kc;
+  double D = 0.0;
+  dl[0][threadIdx.x] = 0.0;
+  for (int ch = 1; ch < nch; ++ch) {
+    const int e = ch * kc - 1;
+    D = (double)x[(int64_t)e * s] + ro_load(pp, e) * D;
+    dl[ch][threadIdx.x] = D;
+  }
+  constexpr int B = 8;
+  double xn = 0.0;
+  for (int ch = nch - 1; ch >= 0; --ch) {
+    const int lo = ch * kc, hi = min(m, lo + kc) - 1;
+    const double Dc = dl[ch][threadIdx.x];
+    for (int r0 = hi; r0 >= lo; r0 -= B) {
+      double v[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int r = r0 - j >= lo ? r0 - j : lo;
+        v[j] = (double)x[(int64_t)r * s];
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int r = r0 - j;
+        if (r >= lo) {
+          const double d = ch > 0 ? v[j] + ro_load(pp, r) * Dc : v[j];
+          xn = r == m - 1 ? d : d - ro_load(cp, r) * xn;
+          x[(int64_t)r * s] = (T)xn;
+        }
+      }
+    }
+  }
+}
+
 template <typename T>
 void launch_helmholtz(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
+  if (hz_fused<T>(c)) {
+    const dim3 grid((unsigned)(((int64_t)c.g.ny * c.g.nx + 255) / 256), 3);
+    LES_LAUNCH(c, "helmholtz_z", 6.0 * c.g.ny * c.g.nx * c.g.nz * sizeof(T), k_hz_back<T>, grid, dim3(256), 0, c.g,
+               (T*)c.us, (T*)c.vs, (T*)c.wsf, c.t.hfac, c.pred_kc);
+    return;
+  }
   // columns per block: the largest power of two <= 64 whose rows fit 64 KB of LDS
   int hc = 64;
   while (hc > 8 && (size_t)c.g.nz * (hc + 3) * sizeof(double) > 65536) hc /= 2;
