@@ -125,7 +125,8 @@ les_status prepare(les_batch* b) {
     set(BK_RFFTX, (int)(((int64_t)nz * (ny / 2) + d.pbx - 1) / d.pbx), 1, 1);
     set(BK_FFTY, (nxh + d.ly - 1) / d.ly, nz, 1);
     set(BK_FFTZ, (nxh + d.lz - 1) / d.lz, ny, 1);
-    set(BK_DSM, (nx + 31) / 32, (ny + 7) / 8, (nz + d.kc - 1) / d.kc);
+    const int dty = dsm_tile_rows(b->prec != LES_MIXED);
+    set(BK_DSM, (nx + 31) / 32, (ny + dty - 1) / dty, (nz + d.kc - 1) / d.kc);
     set(BK_DSMRED, nz, 1, 1);
     set(BK_CFL, 64, 1, 1);
     set(BK_PRED, (nx + 31) / 32, (ny + 7) / 8, (nz + d.pkc - 1) / d.pkc);

@@ -231,7 +231,10 @@ size_t carve(Ctx& c, char* base) {
     c.pred_kc = chunk_rounds(f.precision == LES_MIXED ? 1024 : 768);
   }
   // ducts: one partial per x line and x tile, [nz][ny][nx/32]
-  t.dsm_part = (double*)take(std::max((size_t)2 * n * t.nblk_xy * 4, (size_t)2 * n * f.ny * ((f.nx + 31) / 32)) * 8);
+  // per (plane, tile, wave) of the fused dynamic-model kernel, or per (plane, row, x tile)
+  const int dty = dsm_tile_rows(f.precision != LES_MIXED);
+  const size_t dsm_waves = (size_t)((f.nx + 31) / 32) * ((f.ny + dty - 1) / dty) * (32 * dty / 64);
+  t.dsm_part = (double*)take(std::max((size_t)2 * n * dsm_waves, (size_t)2 * n * f.ny * ((f.nx + 31) / 32)) * 8);
   c.ru = take(F * E);
   c.rv = take(F * E);
   c.rw = take(F * E);

@@ -73,6 +73,10 @@ __device__ inline void lds_barrier() {
 __host__ __device__ inline int64_t idx3(const GridP& g, int k, int j, int i) {
   return ((int64_t)k * g.nys + j) * g.nx + i;
 }
+// Rows of the x-y tiles of the fused dynamic-model kernel (32 columns wide): 16 in FP64, 8 in
+// FP32.
+constexpr int dsm_tile_rows(bool fp64) { return fp64 ? 16 : 8; }
+
 // XCD-aware tile order.  Workgroups are dispatched to the 8 XCDs in turn by linear index;
 // when a plane holds a multiple of 8 tiles, XCD x gets the contiguous band of tiles
 // [x n/8, (x+1) n/8) of every plane, so tiles that are neighbours in y, and the same tile
@@ -195,7 +199,7 @@ struct Tables {
   double* vd4;      // ducts, van Driest: friction velocity of the z bottom, z top, y = 0, y = ly walls
   double* twc;      // ducts: 2*ny cos, sin of pi m / (2 ny), the cosine transform's twiddles
   float* twc_f;
-  double* dsm_part; // 2*nz*nblk_xy*4 plane partial sums (LM, MM) per tile and wave
+  double* dsm_part; // plane partial sums (LM, MM) per tile and wave of the fused dynamic model
   double* pfac;     // walls: (c', 1/pivot) of the (l, m) z systems, [nz][nm][nxp] pairs with
                     //   nm = ny/2+1 (periodic y: m and ny - m share them) or ny (ducts)
   double* stats;    // statistics: header[8], sums [11][nz], wall-stress series [cap][2]

@@ -358,12 +358,20 @@ __global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part,
 // Wall rules as in the rest of the dynamic model: on the first off-wall layers the z pass of
 // the filter is the identity (the index-space extrapolation of the neighbour reduces to it),
 // filtered-velocity ghosts follow the strain ghost rule, alpha^2 = 4^(2/3) there.
+// Tiles of 32 x 16 cells in FP64 (one 512-thread block per CU: the LDS of a block is about
+// 140 KB, and the halo is a smaller share of the tile) and 32 x 8 in FP32 (three 256-thread
+// blocks per CU).
 namespace fused {
-constexpr int TX = 32, TY = 8, NT = TX * TY, WV = NT / 64;
-constexpr int RX2 = TX + 4, RY2 = TY + 4, N2 = RX2 * RY2;  // halo 2
-constexpr int RX1 = TX + 2, RY1 = TY + 2, N1 = RX1 * RY1;  // halo 1
-constexpr int NQ = 15;                                      // filter inputs per cell
-constexpr int NHALO = 2 * (RX1 + TY);                       // halo-1 points around the tile
+constexpr int TX = 32;
+constexpr int NQ = 15;   // filter inputs per cell
+template <typename T>
+struct Tile {
+  static constexpr int TY = dsm_tile_rows(sizeof(T) == 8), NT = TX * TY, WV = NT / 64;
+  static constexpr int RX2 = TX + 4, RY2 = TY + 4, N2 = RX2 * RY2;  // halo 2
+  static constexpr int RX1 = TX + 2, RY1 = TY + 2, N1 = RX1 * RY1;  // halo 1
+  static constexpr int NHALO = 2 * (RX1 + TY);                       // halo-1 points around the tile
+  static constexpr int MINB = sizeof(T) == 8 ? 1 : 3;                // blocks per CU
+};
 }  // namespace fused
 
 // Upper z-edge terms at a cell of plane k: (du/dz + dw/dx) / 2 on the x-z edges of the cell's
@@ -449,7 +457,9 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
                                                const T* __restrict__ v, const T* __restrict__ w,
                                                T* __restrict__ nut, double* __restrict__ part, int kc,
                                                const int* __restrict__ gate) {
-  using namespace fused;
+  using TL = fused::Tile<T>;
+  constexpr int TX = fused::TX, TY = TL::TY, NT = TL::NT, WV = TL::WV, NQ = fused::NQ;
+  constexpr int RX2 = TL::RX2, N2 = TL::N2, RX1 = TL::RX1, RY1 = TL::RY1, N1 = TL::N1, NHALO = TL::NHALO;
   if (gate != nullptr && gate[0] == 0) return;   // learned closure: no point fell back
   constexpr int NL = (N2 + NT - 1) / NT;          // halo-2 points per thread (loads)
   constexpr int NH = (N1 + NT - 1) / NT;          // halo-1 points per thread (velocity filter)
@@ -848,7 +858,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
 }
 
 template <typename T, bool YW = false>
-__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
+__global__ void __launch_bounds__(fused::Tile<T>::NT, fused::Tile<T>::MINB) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
                                                    int kc, const int* gate) {
   dsm_fused_body<T, YW>(xcd_tile(blockIdx, gridDim), gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
 }
@@ -886,7 +896,7 @@ __global__ void __launch_bounds__(256) k_nut_lines(GridP g, T* nut, const double
 
 // Batched dynamic model (and its plane / volume reduction) over all boxes of a batch.
 template <typename T>
-__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) kb_dsm_fused(BatchMap m) {
+__global__ void __launch_bounds__(fused::Tile<T>::NT, fused::Tile<T>::MINB) kb_dsm_fused(BatchMap m) {
   int box;
   const dim3 bid = batch_bid(m, BK_DSM, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
@@ -894,11 +904,12 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) kb_dsm_fused(Batc
                     (T*)d.nut, d.dsm_part, d.kc, nullptr);
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256) kb_dsm_reduce(BatchMap m) {
   int box;
   const dim3 bid = batch_bid(m, BK_DSMRED, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
-  dsm_reduce_body(bid.x, d.g, d.dsm_part, d.gdim[BK_DSM][0] * d.gdim[BK_DSM][1] * fused::WV, d.cs, d.coef, nullptr);
+  dsm_reduce_body(bid.x, d.g, d.dsm_part, d.gdim[BK_DSM][0] * d.gdim[BK_DSM][1] * fused::Tile<T>::WV, d.cs, d.coef, nullptr);
 }
 
 template <typename T>
@@ -1363,7 +1374,8 @@ void launch_eddy_viscosity(Ctx& c) {
     const int* gate = learned ? c.mlp_cnt + 1 : nullptr;
     T* dsm_nut = learned ? nullptr : (T*)c.nut;
     const int kc = c.dsm_kc;
-    dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + fused::TY - 1) / fused::TY, (g.nz + kc - 1) / kc);
+    using TL = fused::Tile<T>;
+    dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + TL::TY - 1) / TL::TY, (g.nz + kc - 1) / kc);
     if (learned) {
       MlpNorm nm;
       for (int a = 0; a < 7; ++a) {
@@ -1392,7 +1404,7 @@ void launch_eddy_viscosity(Ctx& c) {
     }
     if (g.ywall) {
       // ducts: coefficients along x lines
-      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), (k_dsm_fused<T, true>), grid, dim3(fused::TX, fused::TY), 0, g,
+      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), (k_dsm_fused<T, true>), grid, dim3(fused::TX, TL::TY), 0, g,
                  (const T*)c.u, (const T*)c.v, (const T*)c.w, dsm_nut, c.t.dsm_part, kc, gate);
       const int nl = g.nz * g.ny;
       LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce_lines, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, g,
@@ -1403,9 +1415,9 @@ void launch_eddy_viscosity(Ctx& c) {
                    0, g, (T*)c.nut, (const double*)c.t.cs);
       }
     } else {
-      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, fused::TY), 0, g,
+      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, TL::TY), 0, g,
                  (const T*)c.u, (const T*)c.v, (const T*)c.w, dsm_nut, c.t.dsm_part, kc, gate);
-      const int ntile = (int)(grid.x * grid.y) * fused::WV;
+      const int ntile = (int)(grid.x * grid.y) * TL::WV;
       LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs,
                  learned ? nullptr : c.t.coef, gate);
     }
@@ -1422,8 +1434,8 @@ template <typename T>
 void batch_eddy_viscosity(hipStream_t st, const BatchMap& m, const int* totals, int any_dsm, int any_smag) {
   if (any_smag) hipLaunchKernelGGL(kb_strain_mag<T>, dim3(totals[BK_POINT]), dim3(32, 8), 0, st, m);
   if (any_dsm) {
-    hipLaunchKernelGGL(kb_dsm_fused<T>, dim3(totals[BK_DSM]), dim3(fused::TX, fused::TY), 0, st, m);
-    hipLaunchKernelGGL(kb_dsm_reduce, dim3(totals[BK_DSMRED]), dim3(256), 0, st, m);
+    hipLaunchKernelGGL(kb_dsm_fused<T>, dim3(totals[BK_DSM]), dim3(fused::TX, fused::Tile<T>::TY), 0, st, m);
+    hipLaunchKernelGGL(kb_dsm_reduce<T>, dim3(totals[BK_DSMRED]), dim3(256), 0, st, m);
   }
 }
 template void batch_eddy_viscosity<float>(hipStream_t, const BatchMap&, const int*, int, int);
