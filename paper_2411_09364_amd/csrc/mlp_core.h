@@ -82,7 +82,9 @@ __device__ void load_weights(const float* __restrict__ P, Weights& W, int tid, i
   if (tid == 0) W.b3 = P[P_B3];
 }
 
-// Forward pass of one wave over 64 samples whose bf16 features sit in xb[64][16].
+// Forward pass of one wave over 64 samples whose bf16 features sit in xb[64][XS]: XS = 16, or
+// XS = 8, where the features 8..15 of the padded input (zero) are not stored and the lanes
+// holding that half of the K operand take zeros.
 // Outputs (registers, tile (a, sb) holds hidden rows 16a + 4(l/16) + i, sample 16sb + l%16):
 // z1, h1b (bf16 of silu(z1)), z2, h2 = silu(z2), and y[sb] for sample 16sb + l%16.
 struct Fwd {
@@ -93,8 +95,9 @@ struct Fwd {
   float y[4];
 };
 
-template <bool KEEP>
+template <bool KEEP, int XS = FP>
 __device__ void forward_wave(const Weights& W, const unsigned short* xb, int lane, Fwd& o) {
+  static_assert(XS == FP || (XS == 8 && F <= 8), "input row stride");
   const int r16 = lane % 16, g4 = 4 * (lane / 16);
   // layer 1: Z1^T(16a.., 16sb..) = W1 tile a  x  X^T tile sb, the accumulator starting at the
   // bias of the lane's four rows
@@ -102,7 +105,7 @@ __device__ void forward_wave(const Weights& W, const unsigned short* xb, int lan
     const s4 A = lds4(&W.w1[(16 * a + r16) * FP + g4]);
     const f4 bias = *reinterpret_cast<const f4*>(&W.b1[16 * a + g4]);
     for (int sb = 0; sb < 4; ++sb) {
-      const s4 B = lds4(&xb[(16 * sb + r16) * FP + g4]);
+      const s4 B = (XS == FP || g4 < XS) ? lds4(&xb[(16 * sb + r16) * XS + g4]) : s4{0, 0, 0, 0};
       const f4 z = mfma(A, B, bias);
       float h[4];
       for (int i = 0; i < 4; ++i) h[i] = silu(z[i]);

@@ -1081,7 +1081,7 @@ constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY;
 }  // namespace tiled
 
 template <typename T, bool YW>
-__global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict__ u, const T* __restrict__ v,
+__global__ void __launch_bounds__(256, 4) k_mlp_nut(GridP g, const T* __restrict__ u, const T* __restrict__ v,
                                                  const T* __restrict__ w, T* __restrict__ nut,
                                                  const float* __restrict__ P, MlpNorm nm,
                                                  const double* __restrict__ ut, double ly, int* __restrict__ cnt,
@@ -1093,7 +1093,8 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
   using tiled::RY;
   using tiled::N1;
   __shared__ Weights Wt;
-  __shared__ __align__(16) unsigned short xs[WAVES][64 * FP];
+  constexpr int XS = 8;   // stored features per cell (7 and a zero): four blocks per CU in FP64
+  __shared__ __align__(16) unsigned short xs[WAVES][64 * XS];
   __shared__ T vel[3][3][N1];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   const int wave = tid / 64, lane = tid % 64;
@@ -1261,20 +1262,19 @@ __global__ void __launch_bounds__(256, 3) k_mlp_nut(GridP g, const T* __restrict
       f[a] = xn;
     }
     {
-      // seven bf16 inputs (zero-padded to 16) as two 16-byte LDS stores
+      // seven bf16 inputs and a zero as one 16-byte LDS store
       auto pk = [&](int a) -> unsigned int {
         if (!inside) return 0u;
         const fl2 pr = {(float)f[a], a + 1 < F ? (float)f[a + 1] : 0.0f};
         return __builtin_bit_cast(unsigned int, __builtin_convertvector(pr, bf2));
       };
-      uint4* dst = reinterpret_cast<uint4*>(&xs[wave][lane * FP]);
+      uint4* dst = reinterpret_cast<uint4*>(&xs[wave][lane * XS]);
       dst[0] = make_uint4(pk(0), pk(2), pk(4), pk(6));
-      dst[1] = make_uint4(0u, 0u, 0u, 0u);
     }
     // each wave reads only its own inputs: LDS operations of a wave complete in order
     __builtin_amdgcn_wave_barrier();
     Fwd out;
-    forward_wave<false>(Wt, xs[wave], lane, out);
+    forward_wave<false, XS>(Wt, xs[wave], lane, out);
     const int qq = lane >> 4;
     const float yv = qq == 0 ? out.y[0] : (qq == 1 ? out.y[1] : (qq == 2 ? out.y[2] : out.y[3]));
     if (inside) {
