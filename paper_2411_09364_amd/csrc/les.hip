@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -207,15 +208,18 @@ size_t carve(Ctx& c, char* base) {
   // kernel (32 x 8 cells, 4 waves)
   t.nblk_xy = ((f.nx + 31) / 32) * ((f.ny + 7) / 8);
   {
-    // z chunk lengths: whole rounds of resident blocks (the dynamic-model kernel holds two
-    // blocks per CU, the learned-closure inference three, on 256 CUs), at least 8 planes
+    // z chunk lengths in units of 32 x 8 tiles on 256 CUs: whole rounds of resident blocks, at
+    // least 8 planes (the dynamic model's FP64 block covers two such tiles, one block per CU;
+    // the learned-closure inference runs four blocks per CU on chunks sized for three, which
+    // measured faster than chunks for four)
     auto chunk = [&](int64_t slots) {
       const int64_t want = ((int64_t)n * t.nblk_xy + slots - 1) / slots;
       return (int)std::max<int64_t>(std::min<int64_t>(8, n), std::min<int64_t>(n, want));
     };
     // the fewest chunks that make the launch a whole number of rounds (at least one), when
-    // their length stays at 8 planes or more; else as above
-    auto chunk_rounds = [&](int64_t slots) {
+    // their length stays at 8 planes or more (0 if there are none); chunk_rounds falls back
+    // to chunk
+    auto whole_rounds = [&](int64_t slots) {
       for (int64_t nch = 1; nch <= n; ++nch) {
         const int64_t blocks = nch * t.nblk_xy;
         if (blocks < slots || blocks % slots != 0) continue;
@@ -223,12 +227,25 @@ size_t carve(Ctx& c, char* base) {
         if (kc < std::min<int64_t>(8, n)) break;
         return (int)kc;
       }
-      return chunk(slots);
+      return 0;
+    };
+    auto chunk_rounds = [&](int64_t slots) {
+      const int kc = whole_rounds(slots);
+      return kc > 0 ? kc : chunk(slots);
     };
     c.dsm_kc = chunk(512);
     c.mlp_kc = chunk(768);
-    // z-marching predictor: three blocks per CU in FP64, four in FP32
-    c.pred_kc = chunk_rounds(f.precision == LES_MIXED ? 1024 : 768);
+    // z-marching predictor: in FP64 32 x 16 tiles at one 512-thread block per CU, which fetch
+    // less halo than 32 x 8 tiles at three blocks per CU (measured faster on 3 and 17 M-cell
+    // channels), when their launch makes whole rounds; else, and in FP32, 32 x 8 tiles at three
+    // (FP64) or four (FP32) blocks per CU.  LES_PRED_TILE_ROWS (8 or 16) overrides.
+    c.pred_ty = f.precision != LES_MIXED && f.ny % 16 == 0 && whole_rounds(512) > 0 ? 16 : 8;
+    if (const char* e = std::getenv("LES_PRED_TILE_ROWS")) {
+      const int r = std::atoi(e);
+      if (r == 8 || (r == 16 && f.precision != LES_MIXED)) c.pred_ty = r;
+    }
+    // slots in units of 32 x 8 tiles: a 32 x 16 block covers two
+    c.pred_kc = chunk_rounds(c.pred_ty == 16 ? 512 : (f.precision == LES_MIXED ? 1024 : 768));
   }
   // ducts: one partial per x line and x tile, [nz][ny][nx/32]
   // per (plane, tile, wave) of the fused dynamic-model kernel, or per (plane, row, x tile)

@@ -73,8 +73,8 @@ __device__ inline void lds_barrier() {
 __host__ __device__ inline int64_t idx3(const GridP& g, int k, int j, int i) {
   return ((int64_t)k * g.nys + j) * g.nx + i;
 }
-// Rows of the x-y tiles of the fused dynamic-model kernel (32 columns wide): 16 in FP64, 8 in
-// FP32.
+// Rows of the x-y tiles of the fused dynamic-model kernel (32 columns wide): 16 in FP64 (not in
+// ducts), 8 in FP32 and in ducts.
 constexpr int dsm_tile_rows(bool fp64) { return fp64 ? 16 : 8; }
 
 // XCD-aware tile order.  Workgroups are dispatched to the 8 XCDs in turn by linear index;
@@ -238,6 +238,7 @@ struct Ctx {
   int dsm_kc = 8;         // planes per z chunk of the fused dynamic-model kernel
   int mlp_kc = 8;         // planes per z chunk of the learned-closure inference kernel
   int pred_kc = 8;        // planes per z chunk of the z-marching predictor
+  int pred_ty = 8;        // rows of the predictor's 32-wide tiles: 8 or 16
   int bulk_nblk = 0;      // forward-x flow-rate partials awaiting the shift (spectral_solve forms it)
   // learned closure
   float* mlp_params = nullptr;   // caller-owned float32 parameters (les_mlp_bind)

@@ -360,17 +360,17 @@ __global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part,
 // filtered-velocity ghosts follow the strain ghost rule, alpha^2 = 4^(2/3) there.
 // Tiles of 32 x 16 cells in FP64 (one 512-thread block per CU: the LDS of a block is about
 // 140 KB, and the halo is a smaller share of the tile) and 32 x 8 in FP32 (three 256-thread
-// blocks per CU).
+// blocks per CU) and in the duct variant (YW; two blocks per CU in FP64).
 namespace fused {
 constexpr int TX = 32;
 constexpr int NQ = 15;   // filter inputs per cell
-template <typename T>
+template <typename T, bool YW = false>
 struct Tile {
-  static constexpr int TY = dsm_tile_rows(sizeof(T) == 8), NT = TX * TY, WV = NT / 64;
+  static constexpr int TY = dsm_tile_rows(sizeof(T) == 8 && !YW), NT = TX * TY, WV = NT / 64;
   static constexpr int RX2 = TX + 4, RY2 = TY + 4, N2 = RX2 * RY2;  // halo 2
   static constexpr int RX1 = TX + 2, RY1 = TY + 2, N1 = RX1 * RY1;  // halo 1
   static constexpr int NHALO = 2 * (RX1 + TY);                       // halo-1 points around the tile
-  static constexpr int MINB = sizeof(T) == 8 ? 1 : 3;                // blocks per CU
+  static constexpr int MINB = sizeof(T) == 8 ? (YW ? 2 : 1) : 3;     // blocks per CU
 };
 }  // namespace fused
 
@@ -457,7 +457,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
                                                const T* __restrict__ v, const T* __restrict__ w,
                                                T* __restrict__ nut, double* __restrict__ part, int kc,
                                                const int* __restrict__ gate) {
-  using TL = fused::Tile<T>;
+  using TL = fused::Tile<T, YW>;
   constexpr int TX = fused::TX, TY = TL::TY, NT = TL::NT, WV = TL::WV, NQ = fused::NQ;
   constexpr int RX2 = TL::RX2, N2 = TL::N2, RX1 = TL::RX1, RY1 = TL::RY1, N1 = TL::N1, NHALO = TL::NHALO;
   if (gate != nullptr && gate[0] == 0) return;   // learned closure: no point fell back
@@ -858,7 +858,7 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
 }
 
 template <typename T, bool YW = false>
-__global__ void __launch_bounds__(fused::Tile<T>::NT, fused::Tile<T>::MINB) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
+__global__ void __launch_bounds__((fused::Tile<T, YW>::NT), (fused::Tile<T, YW>::MINB)) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
                                                    int kc, const int* gate) {
   dsm_fused_body<T, YW>(xcd_tile(blockIdx, gridDim), gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
 }
@@ -1375,7 +1375,9 @@ void launch_eddy_viscosity(Ctx& c) {
     T* dsm_nut = learned ? nullptr : (T*)c.nut;
     const int kc = c.dsm_kc;
     using TL = fused::Tile<T>;
-    dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + TL::TY - 1) / TL::TY, (g.nz + kc - 1) / kc);
+    using TLY = fused::Tile<T, true>;   // ducts
+    const int dty = g.ywall ? TLY::TY : TL::TY;
+    dim3 grid((g.nx + fused::TX - 1) / fused::TX, (g.ny + dty - 1) / dty, (g.nz + kc - 1) / kc);
     if (learned) {
       MlpNorm nm;
       for (int a = 0; a < 7; ++a) {
@@ -1404,7 +1406,7 @@ void launch_eddy_viscosity(Ctx& c) {
     }
     if (g.ywall) {
       // ducts: coefficients along x lines
-      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), (k_dsm_fused<T, true>), grid, dim3(fused::TX, TL::TY), 0, g,
+      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), (k_dsm_fused<T, true>), grid, dim3(fused::TX, TLY::TY), 0, g,
                  (const T*)c.u, (const T*)c.v, (const T*)c.w, dsm_nut, c.t.dsm_part, kc, gate);
       const int nl = g.nz * g.ny;
       LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce_lines, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, g,

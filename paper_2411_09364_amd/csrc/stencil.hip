@@ -194,19 +194,25 @@ __device__ __forceinline__ void predictor_cell(const Nb<T>& b, const GridP& g, i
   }
 }
 
-// z-marching predictor: a 32 x 8 tile walks a chunk of kc planes.  A ring of three planes of
+// z-marching predictor: a 32 x TY tile walks a chunk of kc planes.  A ring of three planes of
 // u, v, w, nu_t (coefficient applied) and p on the tile + 1 halo sits in LDS; the loads of
 // plane k + 2 are issued right after plane k + 1 is committed and complete under the work
 // on plane k.  With CN in z the first z slice of blocks holds the block that factorises the
-// substep's Helmholtz matrices (the others of that slice return at once).
+// substep's Helmholtz matrices (the others of that slice return at once), unless a launch of
+// its own has done so.  TY = 16 (FP64): one 512-thread block per CU, the halo a smaller share
+// of the loads (18 / 16 rows against 10 / 8); TY = 8: three (FP64) or four (FP32) blocks per CU.
 namespace zmarch {
-constexpr int TX = 32, TY = 8, NT = TX * TY;
-constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY, NL = (N1 + NT - 1) / NT;
+constexpr int TX = 32;
+template <int TY_>
+struct Tile {
+  static constexpr int TY = TY_, NT = TX * TY;
+  static constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY, NL = (N1 + NT - 1) / NT;
+};
 }  // namespace zmarch
 
 // RW: bit 0 reads R^{k-1} (substeps 1, 2), bit 1 writes R^k (substeps 0, 1); compile-time so
 // that the loop holds no branch around a global load or store.
-template <typename T, int MODE, int RW>
+template <typename T, int MODE, int RW, int TY>
 __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, const T* __restrict__ u,
                                                   const T* __restrict__ v, const T* __restrict__ w,
                                                   const T* __restrict__ p, const T* __restrict__ nut,
@@ -217,9 +223,10 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
                                                   double gamma, int kc, int chunk,
                                                   const double* __restrict__ tau, int wallmodel,
                                                   const double* __restrict__ hfw,
-                                                  T (&ring)[3][5][zmarch::N1]) {
+                                                  T (&ring)[3][5][zmarch::Tile<TY>::N1]) {
   // ring: [plane slot][u v w nu p][tile + 1 halo]
-  using namespace zmarch;
+  using ZT = zmarch::Tile<TY>;
+  constexpr int TX = zmarch::TX, NT = ZT::NT, RX = ZT::RX, N1 = ZT::N1, NL = ZT::NL;
   constexpr bool use_rprev = (RW & 1) != 0, write_r = (RW & 2) != 0;
   // CN in z: the thread's running elimination values of u, v, w, kept in LDS
   __shared__ double ecar[MODE == VISC_CN_Z ? 3 : 1][NT];
@@ -374,8 +381,8 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
   }
 }
 
-template <typename T, int MODE, int RW>
-__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 3 : 4) k_predictor(GridP g, const T* __restrict__ u,
+template <typename T, int MODE, int RW, int TY>
+__global__ void __launch_bounds__(32 * TY, TY == 16 ? 1 : (sizeof(T) == 8 ? 3 : 4)) k_predictor(GridP g, const T* __restrict__ u,
                                                                         const T* __restrict__ v,
                                                                         const T* __restrict__ w,
                                                                         const T* __restrict__ p,
@@ -391,7 +398,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 3 : 4) k_predictor(GridP
                                                                         const double* __restrict__ tau, int fslice,
                                                                         const double* __restrict__ hfw) {
   const dim3 bid = xcd_tile(blockIdx, gridDim);
-  __shared__ T ring[3][5][zmarch::N1];
+  __shared__ T ring[3][5][zmarch::Tile<TY>::N1];
   static_assert(sizeof(ring) >= 2 * (kMaxNz + 2) * sizeof(double), "factorisation scratch");
   if (MODE != VISC_EXPLICIT && fslice && bid.z == 0) {
     // metric copies of the factorisation in the ring's memory
@@ -401,8 +408,8 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 3 : 4) k_predictor(GridP
                             threadIdx.y * blockDim.x + threadIdx.x, blockDim.x * blockDim.y);
     return;
   }
-  predictor_zm_body<T, MODE, RW>(bid, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta, gamma,
-                                 kc, (int)bid.z - fslice, tau, wallmodel, hfw, ring);
+  predictor_zm_body<T, MODE, RW, TY>(bid, g, u, v, w, p, nut, coef, ru, rv, rw, us, vs, ws, dtp, alpha, beta,
+                                     gamma, kc, (int)bid.z - fslice, tau, wallmodel, hfw, ring);
 }
 
 // Batched predictor (explicit viscous terms): one launch over all boxes of a batch, the same
@@ -413,8 +420,8 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) kb_predictor(Batc
   int box;
   const dim3 bid = batch_bid(m, BK_PRED, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
-  __shared__ T ring[3][5][zmarch::N1];
-  predictor_zm_body<T, VISC_EXPLICIT, RW>(bid, d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w,
+  __shared__ T ring[3][5][zmarch::Tile<8>::N1];
+  predictor_zm_body<T, VISC_EXPLICIT, RW, 8>(bid, d.g, (const T*)d.u, (const T*)d.v, (const T*)d.w,
                                           (const T*)d.p, (const T*)d.nut, d.coef, (T*)d.ru, (T*)d.rv, (T*)d.rw,
                                           (T*)d.us, (T*)d.vs, (T*)d.wsf, d.dt, alpha, beta, gamma, d.pkc, (int)bid.z,
                                           nullptr, 0, nullptr, ring);
@@ -558,7 +565,6 @@ void launch_predictor(Ctx& c, int stage) {
   static const double A[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
   static const double B[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
   const double G = A[stage] + B[stage];
-  using namespace zmarch;
   const int kc = c.pred_kc;
   const unsigned nch = (unsigned)((c.g.nz + kc - 1) / kc);
   const int mode = c.cfg.implicit_z;   // VISC_* (validated at init)
@@ -570,17 +576,21 @@ void launch_predictor(Ctx& c, int stage) {
   if (fused)
     LES_LAUNCH(c, "hz_factor", 0, k_hz_factor, dim3(1), dim3(2 * HZF_T), 0, c.g, c.t.hfac, c.t.dt, G,
                c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, kc);
+  const int TX = zmarch::TX, TY = c.pred_ty;
   const dim3 grid((c.g.nx + TX - 1) / TX, (c.g.ny + TY - 1) / TY, nch + fslice);
   const int use_rprev = stage > 0;
   const int write_r = stage < 2;
   // R^k written by substeps 0 and 1, R^{k-1} read by substeps 1 and 2
-  auto pick = [&](auto m) {
-    constexpr int M = decltype(m)::value;
-    return stage == 0 ? k_predictor<T, M, 2> : (stage == 1 ? k_predictor<T, M, 3> : k_predictor<T, M, 1>);
+  auto pick = [&](auto m, auto ty) {
+    constexpr int M = decltype(m)::value, Y = decltype(ty)::value;
+    return stage == 0 ? k_predictor<T, M, 2, Y> : (stage == 1 ? k_predictor<T, M, 3, Y> : k_predictor<T, M, 1, Y>);
   };
-  auto f = mode == VISC_CN_3D ? pick(std::integral_constant<int, VISC_CN_3D>())
-                              : (mode == VISC_CN_Z ? pick(std::integral_constant<int, VISC_CN_Z>())
-                                                   : pick(std::integral_constant<int, VISC_EXPLICIT>()));
+  auto pick_ty = [&](auto m) {
+    return TY == 16 ? pick(m, std::integral_constant<int, 16>()) : pick(m, std::integral_constant<int, 8>());
+  };
+  auto f = mode == VISC_CN_3D ? pick_ty(std::integral_constant<int, VISC_CN_3D>())
+                              : (mode == VISC_CN_Z ? pick_ty(std::integral_constant<int, VISC_CN_Z>())
+                                                   : pick_ty(std::integral_constant<int, VISC_EXPLICIT>()));
   const double pts = (double)c.g.sxy * c.g.nz;
   const double words = 8 + 3 * use_rprev + 3 * write_r;
   LES_LAUNCH(c, "predictor", words * pts * sizeof(T), f, grid, dim3(TX, TY), 0, c.g, (const T*)c.u, (const T*)c.v,

@@ -213,6 +213,20 @@ def test_substeps_match_oracle(les, name, cfgd, kind, nsub):
     solver.close()
 
 
+# FP64 runs the predictor on 32 x 16 tiles when their launch makes whole rounds on the GPU
+# (the full-size grids), else on 32 x 8 tiles (these small cases); the 32 x 16 tiles, through
+# the library's override, on the same cases: CN in z with the dynamic model, explicit, CN in
+# all directions
+TILE16_CASES = [c for c in SUBSTEP_CASES
+                if c[0] in ("C2-like dsm wm cn-z bulk", "noslip vd explicit bulk", "cn-3d wm dsm bulk")]
+
+
+@pytest.mark.parametrize("name,cfgd,kind,nsub", TILE16_CASES, ids=[c[0] for c in TILE16_CASES])
+def test_substeps_predictor_16_row_tiles(les, monkeypatch, name, cfgd, kind, nsub):
+    monkeypatch.setenv("LES_PRED_TILE_ROWS", "16")   # read when the context is created
+    test_substeps_match_oracle(les, name, cfgd, kind, nsub)
+
+
 @pytest.mark.parametrize("visc", ["cn-z", "cn-3d", "cn-3d no model"])
 def test_time_step_matches_oracle(les, visc):
     extra = dict(implicit_z=True) if visc == "cn-z" else dict(implicit_3d=True)
