@@ -191,7 +191,7 @@ size_t carve(Ctx& c, char* base) {
   t.twz_f = (float*)take(2 * n * 4);
   t.hfac = (double*)take(14 * n * 8);
   t.dt = (double*)take(16 * 8);
-  c.mlp_cnt = (int*)take(2 * sizeof(int));
+  c.mlp_cnt = (int*)take(4 * sizeof(int));   // [0, 1] fallback counters, [2] wall-mean ticket
   t.red_n = 4096;
   t.red = (double*)take(t.red_n * 8);
   const int64_t npairs = (int64_t)n * (f.ny / 2);
@@ -523,7 +523,7 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
       if ((s = up(c.t.twc_f, c.twc_f_host.data(), c.twc_f_host.size() * 4)) != LES_OK) return s;
       if ((s = up(c.t.hfac, c.hfac_host.data(), c.hfac_host.size() * 8)) != LES_OK) return s;
       // learned closure: fallback counters (cleared again by every evaluation)
-      static const int cnt_init[2] = {0, 0};
+      static const int cnt_init[4] = {0, 0, 0, 0};
       if ((s = up(c.mlp_cnt, cnt_init, sizeof(cnt_init))) != LES_OK) return s;
       if (f.zbc != LES_ZBC_PERIODIC) {
         launch_thomas_factor(c);

@@ -221,11 +221,17 @@ __device__ inline void wave_block_sums(const double* part, int nq, double* a) {
   }
 }
 
-__global__ void k_vd_duct_final(GridP g, const double* part, double* vd4) {
+// cnt (learned closure, may be null): the fallback counters are cleared here, ahead of the
+// inference kernel that adds to them.
+__global__ void k_vd_duct_final(GridP g, const double* part, double* vd4, int* cnt) {
   static_assert(VD_BLOCKS <= 64, "one lane per block partial");
   double a[8];
   wave_block_sums(part, 8, a);
   if (threadIdx.x != 0) return;
+  if (cnt != nullptr) {
+    cnt[0] = 0;
+    cnt[1] = 0;
+  }
   const double nx = g.nx, ny = g.ny, n = g.nz;
   const double cz = nx * ny, cv = nx * (ny - 1), cy = nx * n, cw = nx * (n - 1);
   vd4[0] = sqrt(hypot(a[0] / cz, a[1] / cv));
@@ -296,8 +302,9 @@ __global__ void __launch_bounds__(256) k_vd_coef_final(GridP g, const double* pa
 // when z is periodic; coef[k] = c_s Delta_k^2 with ghost copies.  One block per plane:
 // strided partial sums over the tiles, then a fixed-order tree.  With periodic z every block
 // forms the total over all planes itself (same order in every block).
+template <typename T>
 __device__ __forceinline__ void dsm_reduce_body(int k, GridP g, const double* part, int ntile, double* cs,
-                                                double* coef, const int* gate) {
+                                                double* coef, const int* gate, T* fnut) {
   if (gate != nullptr && gate[0] == 0) return;
   __shared__ double sm[2][256];
   const int n = g.nz;
@@ -324,9 +331,9 @@ __device__ __forceinline__ void dsm_reduce_body(int k, GridP g, const double* pa
     }
     __syncthreads();
   }
+  const double sa = sm[0][0], sb = sm[1][0];
+  const double c = sb > 0.0 ? fmax(sa / sb, 0.0) : 0.0;
   if (threadIdx.x == 0) {
-    const double sa = sm[0][0], sb = sm[1][0];
-    const double c = sb > 0.0 ? fmax(sa / sb, 0.0) : 0.0;
     cs[k] = c;
     if (coef != nullptr) {
       coef[k + 1] = c * g.delta2[k + 1];
@@ -334,11 +341,23 @@ __device__ __forceinline__ void dsm_reduce_body(int k, GridP g, const double* pa
       if (k == n - 1) coef[per ? 0 : n + 1] = c * g.delta2[n];
     }
   }
+  if (fnut != nullptr) {
+    // learned closure: the cells of this plane that the network left to the dynamic model
+    // (stored -|S|) take c |S|
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    for (int64_t r = threadIdx.x; r < nxy; r += blockDim.x) {
+      const int j = (int)(r / g.nx), i = (int)(r % g.nx);
+      const T val = fnut[idx3(g, k + 1, j, i)];
+      if (val < (T)0) store_nut(g, fnut, k + 1, j, i, (T)c * -val);
+    }
+  }
 }
 
+// fnut (learned closure, may be null): also the fallback of the plane's flagged cells
+template <typename T>
 __global__ void __launch_bounds__(256) k_dsm_reduce(GridP g, const double* part, int ntile, double* cs,
-                                                    double* coef, const int* gate) {
-  dsm_reduce_body(blockIdx.x, g, part, ntile, cs, coef, gate);
+                                                    double* coef, const int* gate, T* fnut) {
+  dsm_reduce_body<T>(blockIdx.x, g, part, ntile, cs, coef, gate, fnut);
 }
 
 // ============================================================================ fused dynamic model
@@ -909,7 +928,8 @@ __global__ void __launch_bounds__(256) kb_dsm_reduce(BatchMap m) {
   int box;
   const dim3 bid = batch_bid(m, BK_DSMRED, blockIdx.x, box);
   const BoxDesc& d = m.desc[box];
-  dsm_reduce_body(bid.x, d.g, d.dsm_part, d.gdim[BK_DSM][0] * d.gdim[BK_DSM][1] * fused::Tile<T>::WV, d.cs, d.coef, nullptr);
+  dsm_reduce_body<T>(bid.x, d.g, d.dsm_part, d.gdim[BK_DSM][0] * d.gdim[BK_DSM][1] * fused::Tile<T>::WV, d.cs, d.coef,
+                     nullptr, (T*)nullptr);
 }
 
 template <typename T>
@@ -928,14 +948,19 @@ __global__ void __launch_bounds__(256) kb_strain_mag(BatchMap m) {
 
 // ============================================================================ learned closure
 // Plane sums of the four wall-stress components (bottom x, bottom y, top x, top y) from the
-// wall-model stresses or the no-slip viscous flux: stage 1, WM_BLOCKS blocks over
-// contiguous chunks of the plane, each a fixed-order tree.
+// wall-model stresses or the no-slip viscous flux, WM_BLOCKS blocks over contiguous chunks of
+// the plane, each a fixed-order tree; the last block to finish (a ticket counter, cleared
+// again by that block) sums the partials by a fixed-order tree and stores the friction velocity of
+// each wall, u_tau = sqrt(|(<tau_x>, <tau_y>)|), in dt[2] (bottom) and dt[3] (top).  cnt
+// (learned closure, may be null): that block also clears the fallback counters, ahead of the
+// inference kernel that adds to them.
 constexpr int WM_BLOCKS = 64;
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_wall_mean_partial(GridP g, const T* u, const T* v, const double* tau,
-                                                           int wallmodel, double* part) {
+__global__ void __launch_bounds__(256) k_wall_mean(GridP g, const T* u, const T* v, const double* tau, int wallmodel,
+                                                   double* part, double* dtp, int* cnt, unsigned* ticket) {
   __shared__ double sm[4][256];
+  __shared__ bool last;
   double a[4] = {0, 0, 0, 0};
   const int64_t s = g.sxy;
   const int n = g.nz;
@@ -959,26 +984,31 @@ __global__ void __launch_bounds__(256) k_wall_mean_partial(GridP g, const T* u, 
       for (int q = 0; q < 4; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sm[threadIdx.x][0];
-}
-
-// Stage 2: friction velocity of each wall, u_tau = sqrt(|(<tau_x>, <tau_y>)|), stored in
-// dt[2] (bottom) and dt[3] (top) (skipped without partials: ducts take the four-wall values
-// of the van Driest reduction); also clears the learned closure's fallback counter cnt[1]
-// (points of this evaluation that fall back; the inference kernel adds to it).
-__global__ void k_mlp_prep(GridP g, const double* part, double* dtp, int* cnt) {
+  if (threadIdx.x < 4) {
+    part[blockIdx.x * 4 + threadIdx.x] = sm[threadIdx.x][0];
+    __threadfence();   // the partial is visible device-wide before the ticket is taken
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == WM_BLOCKS - 1;
+  __syncthreads();
+  if (!last || threadIdx.x >= 64) return;
+  __threadfence();   // the other blocks' partials, published before their tickets
+  static_assert(WM_BLOCKS <= 64, "one lane per block partial");
+  double w[4];
+  for (int q = 0; q < 4; ++q) {   // a fixed-order shuffle tree over the block partials
+    double x = threadIdx.x < WM_BLOCKS ? part[threadIdx.x * 4 + q] : 0.0;
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    w[q] = x;
+  }
   if (threadIdx.x != 0) return;
+  const double area = (double)s;
+  dtp[2] = sqrt(hypot(w[0] / area, w[1] / area));
+  dtp[3] = sqrt(hypot(w[2] / area, w[3] / area));
   if (cnt != nullptr) {
     cnt[0] = 0;
     cnt[1] = 0;
   }
-  if (part == nullptr) return;
-  double a[4] = {0, 0, 0, 0};
-  for (int b = 0; b < WM_BLOCKS; ++b)
-    for (int q = 0; q < 4; ++q) a[q] += part[b * 4 + q];
-  const double s = (double)g.sxy;
-  dtp[2] = sqrt(hypot(a[0] / s, a[1] / s));
-  dtp[3] = sqrt(hypot(a[2] / s, a[3] / s));
+  *ticket = 0u;
 }
 
 // Rotation tensor at the cell centre (edges, then the four-edge mean, like the strain),
@@ -1355,7 +1385,8 @@ void launch_eddy_viscosity(Ctx& c) {
       static_assert(VD_BLOCKS * 8 <= 4096, "partials fit the reduction area");
       LES_LAUNCH(c, "vd_duct", 0, k_vd_duct_partial<T>, dim3(VD_BLOCKS), dim3(256), 0, g, (const T*)c.u,
                  (const T*)c.v, (const T*)c.w, c.t.tau, c.t.tauy, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
-      LES_LAUNCH(c, "vd_duct_final", 0, k_vd_duct_final, dim3(1), dim3(64), 0, g, c.t.red, c.t.vd4);
+      LES_LAUNCH(c, "vd_duct_final", 0, k_vd_duct_final, dim3(1), dim3(64), 0, g, c.t.red, c.t.vd4,
+                 (int*)nullptr);
     }
     LES_LAUNCH(c, "strain_mag", 4 * pts * sizeof(T), k_strain_mag<T>, L.grid, L.block, 0, g, (const T*)c.u, (const T*)c.v,
                        (const T*)c.w, (T*)c.nut, duct_vd ? (const double*)c.t.vd4 : nullptr, c.cfg.ly);
@@ -1390,15 +1421,14 @@ void launch_eddy_viscosity(Ctx& c) {
         // ducts: the four walls' friction velocities of the van Driest reduction
         LES_LAUNCH(c, "vd_duct", 0, k_vd_duct_partial<T>, dim3(VD_BLOCKS), dim3(256), 0, g, (const T*)c.u,
                    (const T*)c.v, (const T*)c.w, c.t.tau, c.t.tauy, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
-        LES_LAUNCH(c, "vd_duct_final", 0, k_vd_duct_final, dim3(1), dim3(64), 0, g, c.t.red, c.t.vd4);
-        LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, (const double*)nullptr, c.t.dt, c.mlp_cnt);
+        LES_LAUNCH(c, "vd_duct_final", 0, k_vd_duct_final, dim3(1), dim3(64), 0, g, c.t.red, c.t.vd4, c.mlp_cnt);
         LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), (k_mlp_nut<T, true>), tgrid, dim3(tiled::TX, tiled::TY), 0, g,
                    (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm,
                    (const double*)c.t.vd4, c.cfg.ly, c.mlp_cnt, mkc);
       } else {
-        LES_LAUNCH(c, "wall_mean", 0, k_wall_mean_partial<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
-                   (const T*)c.v, c.t.tau, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red);
-        LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, c.t.red, c.t.dt, c.mlp_cnt);
+        LES_LAUNCH(c, "wall_mean", 0, k_wall_mean<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
+                   (const T*)c.v, c.t.tau, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red, c.t.dt, c.mlp_cnt,
+                   (unsigned*)(c.mlp_cnt + 2));
         LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), (k_mlp_nut<T, false>), tgrid, dim3(tiled::TX, tiled::TY), 0, g,
                    (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm,
                    (const double*)(c.t.dt + 2), c.cfg.ly, c.mlp_cnt, mkc);
@@ -1420,10 +1450,10 @@ void launch_eddy_viscosity(Ctx& c) {
       LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, TL::TY), 0, g,
                  (const T*)c.u, (const T*)c.v, (const T*)c.w, dsm_nut, c.t.dsm_part, kc, gate);
       const int ntile = (int)(grid.x * grid.y) * TL::WV;
-      LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs,
-                 learned ? nullptr : c.t.coef, gate);
+      LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce<T>, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs,
+                 learned ? nullptr : c.t.coef, gate, learned ? (T*)c.nut : (T*)nullptr);
     }
-    if (learned) {
+    if (learned && g.ywall) {   // channels: the fallback ran with the plane coefficients
       const int64_t ni = (int64_t)g.nz * g.nx * g.ny;
       LES_LAUNCH(c, "mlp_fallback", 0, k_mlp_fallback<T>, dim3((unsigned)std::min<int64_t>(1024, (ni + 255) / 256)),
                  dim3(256), 0, g,
@@ -1451,12 +1481,12 @@ void launch_mlp_sample(Ctx& c, uint64_t seed, int64_t n, float* x, float* y) {
   if (g.ywall) {
     LES_LAUNCH(c, "vd_duct", 0, k_vd_duct_partial<T>, dim3(VD_BLOCKS), dim3(256), 0, g, (const T*)c.u, (const T*)c.v,
                (const T*)c.w, c.t.tau, c.t.tauy, wm, c.t.red);
-    LES_LAUNCH(c, "vd_duct_final", 0, k_vd_duct_final, dim3(1), dim3(64), 0, g, c.t.red, c.t.vd4);
+    LES_LAUNCH(c, "vd_duct_final", 0, k_vd_duct_final, dim3(1), dim3(64), 0, g, c.t.red, c.t.vd4,
+                 (int*)nullptr);
     ut = c.t.vd4;
   } else {
-    LES_LAUNCH(c, "wall_mean", 0, k_wall_mean_partial<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
-               (const T*)c.v, c.t.tau, wm, c.t.red);
-    LES_LAUNCH(c, "mlp_prep", 0, k_mlp_prep, dim3(1), dim3(64), 0, g, c.t.red, c.t.dt, (int*)nullptr);
+    LES_LAUNCH(c, "wall_mean", 0, k_wall_mean<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
+               (const T*)c.v, c.t.tau, wm, c.t.red, c.t.dt, (int*)nullptr, (unsigned*)(c.mlp_cnt + 2));
   }
   LES_LAUNCH(c, "mlp_sample", 0, k_mlp_sample<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g, (const T*)c.u,
              (const T*)c.v, (const T*)c.w, c.t.cs, ut, c.cfg.ly, seed, n, x, y);
