@@ -600,6 +600,18 @@ void launch_thomas_factor(Ctx& c) {
                      c.t.pb, c.t.pc, c.t.lamx, c.t.lamy, (double2*)c.t.pfac);
 }
 
+// Launch shape of the chain solves of n rows (nchain chains over all components): segments of
+// S rows (8 up to s8 rows, else 16), P segments per block, CG chains per segment: 64 (a wave
+// per segment, 512 contiguous bytes of each FP64 row) while P <= 16 and the launch still has
+// four blocks per CU, else 32 (nz <= 512).
+struct ThomasShape {
+  int S, CG, P;
+};
+inline ThomasShape thomas_shape(int n, int s8, int64_t nchain) {
+  const int S = n <= s8 ? 8 : 16, P = (n + S - 1) / S;
+  return {S, P <= 16 && nchain / 64 >= 4 * 256 ? 64 : 32, P};
+}
+
 // FP64 z solves of every (l, m) column with the stored factors, by segmented scans
 // (seg_scan_solve).  A column gives two chains (real and imaginary parts), and there are only
 // a few tens of thousands of chains of nz rows: a plain Thomas sweep per chain leaves most of
@@ -609,13 +621,15 @@ void launch_thomas_factor(Ctx& c) {
 // has its own factor pairs (last row zero); its dzf-weighted mean is removed here and its
 // imaginary part set to zero.  Rows nrow..nz-1 are left as they are (the wall face of w in
 // the Helmholtz solves).
-template <typename T, int S, bool ZERO>
+template <typename T, int S, int CG, bool ZERO>
 __device__ __forceinline__ void thomas_scan_body(unsigned bx, GridP g, cpx<T>* __restrict__ spec,
                                                  const double* __restrict__ pa, const double2* __restrict__ pfac,
                                                  double norm, int nrow) {
-  constexpr int CG = 32;
-  __shared__ double E[32][CG], G[32][CG];
-  const int cl = (int)threadIdx.x % CG, p = (int)threadIdx.x / CG, P = (int)blockDim.x / CG;
+  __shared__ double E[1024 / CG][CG], G[1024 / CG][CG];
+  // with CG a multiple of the wave size a wave holds one segment, whose a_k are then
+  // wave-uniform (scalar loads)
+  const int cl = (int)threadIdx.x % CG, P = (int)blockDim.x / CG;
+  const int p = CG % 64 == 0 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / CG) : (int)threadIdx.x / CG;
   const int n = nrow, nxh = g.nx / 2 + 1;
   const int64_t ncol = (int64_t)g.nxp * g.ny, ncol2 = 2 * ncol;
   const int64_t c2 = (int64_t)bx * CG + cl;
@@ -679,10 +693,10 @@ __device__ __forceinline__ void thomas_scan_body(unsigned bx, GridP g, cpx<T>* _
   }
 }
 
-template <typename T, int S, bool ZERO>
+template <typename T, int S, int CG, bool ZERO>
 __global__ void __launch_bounds__(1024) k_thomas_scan(GridP g, cpx<T>* __restrict__ spec, const double* __restrict__ pa,
                                                       const double2* __restrict__ pfac, double norm, int nrow) {
-  thomas_scan_body<T, S, ZERO>(blockIdx.x, g, spec, pa, pfac, norm, nrow);
+  thomas_scan_body<T, S, CG, ZERO>(blockIdx.x, g, spec, pa, pfac, norm, nrow);
 }
 
 // ---------------------------------------------------------------- three components at once
@@ -716,13 +730,13 @@ __global__ void __launch_bounds__(256) k_fft_lines3(FftPlan P, cpx<T>* data, int
 }
 
 // component blockIdx.y: u and v take the u/v rows and factors, w the w rows (nz - 1 unknowns)
-template <typename T, int S>
+template <typename T, int S, int CG>
 __global__ void __launch_bounds__(1024) k_thomas_scan3(GridP g, cpx<T>* __restrict__ spec, int64_t cstride,
                                                        const double* __restrict__ a_uv, const double* __restrict__ a_w,
                                                        const double2* __restrict__ fac_uv,
                                                        const double2* __restrict__ fac_w, double norm) {
   const int comp = blockIdx.y;
-  thomas_scan_body<T, S, false>(blockIdx.x, g, spec + comp * cstride, comp < 2 ? a_uv : a_w,
+  thomas_scan_body<T, S, CG, false>(blockIdx.x, g, spec + comp * cstride, comp < 2 ? a_uv : a_w,
                                 comp < 2 ? fac_uv : fac_w, norm, comp < 2 ? g.nz : g.nz - 1);
 }
 
@@ -957,19 +971,21 @@ static void spectral_solve(Ctx& c) {
   if (c.cfg.zbc == LES_ZBC_PERIODIC) {
     fftz_solve<T>(c, "fftz_solve", 0.0);
   } else {
-    // segments of 16 rows (8 up to 32 planes): at most 32 segments of 32 chains per block
     const int64_t nchain = 2 * (int64_t)c.g.nxp * ny;
-    const int S = nz <= 32 ? 8 : 16;
-    const int P = (nz + S - 1) / S;
-    const dim3 grid((unsigned)((nchain + 31) / 32)), block(32 * P);
+    const ThomasShape sh = thomas_shape(nz, 32, nchain);
+    const dim3 block(sh.CG * sh.P);
     const double norm = 1.0 / ((double)c.g.nx * ny);
     const double bytes = 2 * spec_bytes + (double)nxh * factor_modes(c.g) * nz * 16;
-    if (S == 8)
-      LES_LAUNCH(c, "thomas_z", bytes, (k_thomas_scan<T, 8, true>), grid, block, 0, c.g, sp, c.t.pa,
-                 (const double2*)c.t.pfac, norm, nz);
+    auto go = [&](auto kern, int64_t nb) {
+      LES_LAUNCH(c, "thomas_z", bytes, kern, dim3((unsigned)nb), block, 0, c.g, sp, c.t.pa, (const double2*)c.t.pfac,
+                 norm, nz);
+    };
+    if (sh.CG == 64)
+      sh.S == 8 ? go(k_thomas_scan<T, 8, 64, true>, (nchain + 64 - 1) / 64)
+                : go(k_thomas_scan<T, 16, 64, true>, (nchain + 64 - 1) / 64);
     else
-      LES_LAUNCH(c, "thomas_z", bytes, (k_thomas_scan<T, 16, true>), grid, block, 0, c.g, sp, c.t.pa,
-                 (const double2*)c.t.pfac, norm, nz);
+      sh.S == 8 ? go(k_thomas_scan<T, 8, 32, true>, (nchain + 32 - 1) / 32)
+                : go(k_thomas_scan<T, 16, 32, true>, (nchain + 32 - 1) / 32);
   }
   ffty<T, 1>(c, "ffty_inv");
 }
@@ -1031,20 +1047,23 @@ void launch_helmholtz_3d(Ctx& c, int stage) {
                c.t.dt, hg);
   } else {
     const int64_t nchain = 2 * (int64_t)c.g.nxp * ny;
-    const int S = n <= 256 ? 8 : 16;
-    const int P = (n + S - 1) / S;
-    const dim3 grid((unsigned)((nchain + 31) / 32), 3), block(32 * P);
+    const ThomasShape sh = thomas_shape(n, 128, 3 * nchain);
+    const dim3 block(sh.CG * sh.P);
     const double* a_uv = c.t.hfac + 6 * n;
     const double* a_w = c.t.hfac + 7 * n;
     const double2* f_uv = (const double2*)c.t.hfac3;
     const double2* f_w = f_uv + (int64_t)n * nfac;
     const double bytes = 6 * spec_bytes + 3.0 * nfac * n * 16;
-    if (S == 8)
-      LES_LAUNCH(c, "h3d_thomas_z", bytes, (k_thomas_scan3<T, 8>), grid, block, 0, c.g, sp, cstride, a_uv, a_w, f_uv,
+    auto go = [&](auto kern, int64_t nb) {
+      LES_LAUNCH(c, "h3d_thomas_z", bytes, kern, dim3((unsigned)nb, 3), block, 0, c.g, sp, cstride, a_uv, a_w, f_uv,
                  f_w, norm_xy);
+    };
+    if (sh.CG == 64)
+      sh.S == 8 ? go(k_thomas_scan3<T, 8, 64>, (nchain + 64 - 1) / 64)
+                : go(k_thomas_scan3<T, 16, 64>, (nchain + 64 - 1) / 64);
     else
-      LES_LAUNCH(c, "h3d_thomas_z", bytes, (k_thomas_scan3<T, 16>), grid, block, 0, c.g, sp, cstride, a_uv, a_w, f_uv,
-                 f_w, norm_xy);
+      sh.S == 8 ? go(k_thomas_scan3<T, 8, 32>, (nchain + 32 - 1) / 32)
+                : go(k_thomas_scan3<T, 16, 32>, (nchain + 32 - 1) / 32);
   }
   LES_LAUNCH(c, "h3d_ffty_inv", 6 * spec_bytes, (lines3_kernel<T, 1, false>(lsy.ppt)), gy, dim3(256), lsy.sh, Py, sp,
              cstride, nxh, (int64_t)c.g.nxp, (int64_t)c.g.nxp * ny, Ly, c.t.twy, c.t.twy_f, c.t.lamx, c.t.lamy,
