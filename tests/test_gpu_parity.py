@@ -53,6 +53,9 @@ POISSON_CASES = [
     dict(nx=8, ny=8, nz=384, lx=1.0, ly=1.0, lz=3.0, zbc=ZBC_PERIODIC),
     # the longest x rows the library accepts (the 134M-cell channel's row length)
     dict(nx=1024, ny=8, nz=6, lx=2 * TWO_PI, ly=np.pi / 4, lz=2.0, zbc=ZBC_NOSLIP, beta=1.5),
+    # enough chains for the z solves' 64-chain segment groups (8- and 16-row segments)
+    dict(nx=256, ny=256, nz=20, lx=TWO_PI, ly=TWO_PI, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5),
+    dict(nx=128, ny=512, nz=40, lx=TWO_PI, ly=2 * TWO_PI, lz=2.0, zbc=ZBC_NOSLIP, beta=1.2),
 ]
 
 
