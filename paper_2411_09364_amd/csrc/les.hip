@@ -235,17 +235,19 @@ size_t carve(Ctx& c, char* base) {
     };
     c.dsm_kc = chunk(512);
     c.mlp_kc = chunk(768);
-    // z-marching predictor: in FP64 32 x 16 tiles at one 512-thread block per CU, which fetch
-    // less halo than 32 x 8 tiles at three blocks per CU (measured faster on 3 and 17 M-cell
-    // channels), when their launch makes whole rounds; else, and in FP32, 32 x 8 tiles at three
-    // (FP64) or four (FP32) blocks per CU.  LES_PRED_TILE_ROWS (8 or 16) overrides.
-    c.pred_ty = f.precision != LES_MIXED && f.ny % 16 == 0 && whole_rounds(512) > 0 ? 16 : 8;
+    // z-marching predictor: 32 x 16 tiles, at one 512-thread block per CU in FP64 and two in
+    // FP32, fetch less halo than 32 x 8 tiles at three (FP64) or four (FP32) blocks per CU
+    // (measured faster on 3, 17 and 134 M-cell channels) and are taken when their launch makes
+    // whole rounds; else 32 x 8.  LES_PRED_TILE_ROWS (8 or 16) overrides.  Slots in units of
+    // 32 x 8 tiles: a 32 x 16 block covers two.
+    const bool mixed = f.precision == LES_MIXED;
+    const int slots16 = mixed ? 1024 : 512;
+    c.pred_ty = f.ny % 16 == 0 && whole_rounds(slots16) > 0 ? 16 : 8;
     if (const char* e = std::getenv("LES_PRED_TILE_ROWS")) {
       const int r = std::atoi(e);
-      if (r == 8 || (r == 16 && f.precision != LES_MIXED)) c.pred_ty = r;
+      if (r == 8 || r == 16) c.pred_ty = r;
     }
-    // slots in units of 32 x 8 tiles: a 32 x 16 block covers two
-    c.pred_kc = chunk_rounds(c.pred_ty == 16 ? 512 : (f.precision == LES_MIXED ? 1024 : 768));
+    c.pred_kc = chunk_rounds(c.pred_ty == 16 ? slots16 : (mixed ? 1024 : 768));
   }
   // ducts: one partial per x line and x tile, [nz][ny][nx/32]
   // per (plane, tile, wave) of the fused dynamic-model kernel, or per (plane, row, x tile)

@@ -382,7 +382,7 @@ __device__ __forceinline__ void predictor_zm_body(dim3 bid, const GridP& g, cons
 }
 
 template <typename T, int MODE, int RW, int TY>
-__global__ void __launch_bounds__(32 * TY, TY == 16 ? 1 : (sizeof(T) == 8 ? 3 : 4)) k_predictor(GridP g, const T* __restrict__ u,
+__global__ void __launch_bounds__(32 * TY, TY == 16 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 3 : 4)) k_predictor(GridP g, const T* __restrict__ u,
                                                                         const T* __restrict__ v,
                                                                         const T* __restrict__ w,
                                                                         const T* __restrict__ p,

@@ -298,6 +298,15 @@ def test_mixed_precision_substeps(les, name, cfgd, kind):
     solver.close()
 
 
+MIXED_TILE16_CASES = [c for c in MIXED_CASES if c[0] in ("mixed C3-like dsm wm explicit", "mixed cn-3d wm dsm")]
+
+
+@pytest.mark.parametrize("name,cfgd,kind", MIXED_TILE16_CASES, ids=[c[0] for c in MIXED_TILE16_CASES])
+def test_mixed_precision_predictor_16_row_tiles(les, monkeypatch, name, cfgd, kind):
+    monkeypatch.setenv("LES_PRED_TILE_ROWS", "16")   # read when the context is created
+    test_mixed_precision_substeps(les, name, cfgd, kind)
+
+
 def _pressure_rounding_response(case, g, st, k, dt):
     """Largest change of the oracle's mean-free pressure after substep k when u* (the predictor's
     and Helmholtz solves' output, the input of Eq. poi) is rounded once to float32.  The pressure
