@@ -448,13 +448,15 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T
   const int l0 = bid.x * L;
   const int o = bid.y;
   cpx<T>* base = data + (int64_t)o * ostride;
-  // loads in batches of four per thread, all issued before their LDS stores (out-of-range
-  // lanes read element 0 and store zero)
+  // loads in batches of LB per thread, all issued before their LDS stores (out-of-range lanes
+  // read element 0 and store zero): four, or in FP32 with the in-place form all PPT points of
+  // the thread at once (measured faster there; slower in FP64)
+  constexpr int LB = (sizeof(T) == 4 && PPT > 0) ? PPT : 4;
   const int total = L * N;
-  for (int e0 = 0; e0 < total; e0 += 4 * (int)blockDim.x) {
-    cpx<T> v[4];
+  for (int e0 = 0; e0 < total; e0 += LB * (int)blockDim.x) {
+    cpx<T> v[LB];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < LB; ++b) {
       const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
       const int t = e / L, l = l0 + e % L;
       const bool ok = e < total && l < nl;
@@ -462,7 +464,7 @@ __device__ __forceinline__ void fft_lines_body(dim3 bid, const FftPlan& P, cpx<T
       if (!ok) v[b] = cpx<T>{(T)0, (T)0};
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < LB; ++b) {
       const int e = e0 + b * (int)blockDim.x + (int)threadIdx.x;
       if (e < total) {
         const int t = e / L;

@@ -258,6 +258,14 @@ MIXED_CASES = [
                                 beta=1.5, nu=5e-4, sgs=SGS_DSM, implicit_3d=True, ubulk=1.0), "channel"),
     ("mixed cn-3d periodic", dict(nx=24, ny=24, nz=24, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, nu=2e-2,
                                   sgs=SGS_SMAG, implicit_3d=True), "iso"),
+    # long y lines in float (the 134M-cell channel's 512, and 384 with a radix-3 stage): the
+    # in-place transform on groups of 8 lines, 16 points per thread
+    ("mixed 512-point y lines dsm wm explicit",
+     dict(nx=16, ny=512, nz=6, lx=1.0, ly=4.0, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=1.6e-5, sgs=SGS_DSM,
+          ubulk=1.0), "channel"),
+    ("mixed 384-point y lines smag noslip explicit",
+     dict(nx=24, ny=384, nz=5, lx=1.0, ly=3.0, lz=2.0, zbc=ZBC_NOSLIP, beta=1.2, nu=1e-3, sgs=SGS_SMAG,
+          ubulk=1.0), "channel"),
     # the 134M-cell channel's row length (1024-point x transforms in float)
     ("mixed 1024-point rows dsm wm explicit",
      dict(nx=1024, ny=8, nz=6, lx=2 * TWO_PI, ly=np.pi / 4, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=1.6e-5,
