@@ -471,7 +471,7 @@ __device__ inline T strain_norm(const T s[6]) {
 // beyond the y wall faces, the y ghost rows of u~ and w~ follow the strain ghost rule, alpha^2
 // counts the filter's dimensions per cell, and the partial sums are per x line (one per row
 // of each wave: 32 lanes) instead of per wave.
-template <typename T, bool YW = false>
+template <typename T, bool YW = false, int ZBC = -1>
 __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP g, const T* __restrict__ u,
                                                const T* __restrict__ v, const T* __restrict__ w,
                                                T* __restrict__ nut, double* __restrict__ part, int kc,
@@ -491,8 +491,9 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   const int nz = g.nz;
   const int kb = 1 + bid.z * kc;
   const int ke = min(nz, kb + kc - 1);
-  const bool per = g.zbc == LES_ZBC_PERIODIC;
-  const bool wm = g.zbc == LES_ZBC_WALLMODEL;
+  const int zbc = ZBC < 0 ? g.zbc : ZBC;   // ZBC >= 0: the z boundary fixed at compile time
+  const bool per = zbc == LES_ZBC_PERIODIC;
+  const bool wm = zbc == LES_ZBC_WALLMODEL;
   const int ntile = gdx * gdy;
   const int tile = bid.y * gdx + bid.x;
   const T rdx = (T)g.rdx, rdy = (T)g.rdy;
@@ -876,10 +877,10 @@ __device__ __forceinline__ void dsm_fused_body(dim3 bid, int gdx, int gdy, GridP
   if (!per && ke == nz) output(nz, S1);   // the z pass is the identity on the top layer
 }
 
-template <typename T, bool YW = false>
+template <typename T, bool YW = false, int ZBC = -1>
 __global__ void __launch_bounds__((fused::Tile<T, YW>::NT), (fused::Tile<T, YW>::MINB)) k_dsm_fused(GridP g, const T* u, const T* v, const T* w, T* nut, double* part,
                                                    int kc, const int* gate) {
-  dsm_fused_body<T, YW>(xcd_tile(blockIdx, gridDim), gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
+  dsm_fused_body<T, YW, ZBC>(xcd_tile(blockIdx, gridDim), gridDim.x, gridDim.y, g, u, v, w, nut, part, kc, gate);
 }
 
 // Ducts: c_s per x line (j, k) from the tile partials [k][j][tile x], summed in tile order,
@@ -1110,7 +1111,7 @@ constexpr int TX = 32, TY = 8, NT = TX * TY;
 constexpr int RX = TX + 2, RY = TY + 2, N1 = RX * RY;
 }  // namespace tiled
 
-template <typename T, bool YW>
+template <typename T, bool YW, int ZBC = -1>
 __global__ void __launch_bounds__(256, 4) k_mlp_nut(GridP g, const T* __restrict__ u, const T* __restrict__ v,
                                                  const T* __restrict__ w, T* __restrict__ nut,
                                                  const float* __restrict__ P, MlpNorm nm,
@@ -1133,8 +1134,9 @@ __global__ void __launch_bounds__(256, 4) k_mlp_nut(GridP g, const T* __restrict
   const int nz = g.nz;
   const int kb = 1 + bid.z * kc;
   const int ke = min(nz, kb + kc - 1);
-  const bool per = g.zbc == LES_ZBC_PERIODIC;
-  const bool wm = g.zbc == LES_ZBC_WALLMODEL;
+  const int zbc = ZBC < 0 ? g.zbc : ZBC;
+  const bool per = zbc == LES_ZBC_PERIODIC;
+  const bool wm = zbc == LES_ZBC_WALLMODEL;
   load_weights(P, Wt, tid, tiled::NT);
   auto phys = [&](int q) {
     if (!per) return q;
@@ -1429,14 +1431,24 @@ void launch_eddy_viscosity(Ctx& c) {
         LES_LAUNCH(c, "wall_mean", 0, k_wall_mean<T>, dim3(WM_BLOCKS), dim3(256), 0, g, (const T*)c.u,
                    (const T*)c.v, c.t.tau, c.cfg.zbc == LES_ZBC_WALLMODEL ? 1 : 0, c.t.red, c.t.dt, c.mlp_cnt,
                    (unsigned*)(c.mlp_cnt + 2));
-        LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), (k_mlp_nut<T, false>), tgrid, dim3(tiled::TX, tiled::TY), 0, g,
+        // FP64 with the wall model: the z boundary fixed at compile time (690 -> 677 us on
+        // 512x256x128)
+        auto km = k_mlp_nut<T, false>;
+        if constexpr (sizeof(T) == 8)
+          if (g.zbc == LES_ZBC_WALLMODEL) km = k_mlp_nut<T, false, LES_ZBC_WALLMODEL>;
+        LES_LAUNCH(c, "mlp_nut", 4 * pts * sizeof(T), km, tgrid, dim3(tiled::TX, tiled::TY), 0, g,
                    (const T*)c.u, (const T*)c.v, (const T*)c.w, (T*)c.nut, c.mlp_params, nm,
                    (const double*)(c.t.dt + 2), c.cfg.ly, c.mlp_cnt, mkc);
       }
     }
     if (g.ywall) {
       // ducts: coefficients along x lines
-      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), (k_dsm_fused<T, true>), grid, dim3(fused::TX, TLY::TY), 0, g,
+      // FP64 with the wall model: the z boundary fixed at compile time (no spill; 225 -> 215 us
+      // on the 512x80x80 duct)
+      auto kfy = k_dsm_fused<T, true>;
+      if constexpr (sizeof(T) == 8)
+        if (g.zbc == LES_ZBC_WALLMODEL) kfy = k_dsm_fused<T, true, LES_ZBC_WALLMODEL>;
+      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), kfy, grid, dim3(fused::TX, TLY::TY), 0, g,
                  (const T*)c.u, (const T*)c.v, (const T*)c.w, dsm_nut, c.t.dsm_part, kc, gate);
       const int nl = g.nz * g.ny;
       LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce_lines, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, g,
@@ -1447,7 +1459,15 @@ void launch_eddy_viscosity(Ctx& c) {
                    0, g, (T*)c.nut, (const double*)c.t.cs);
       }
     } else {
-      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), k_dsm_fused<T>, grid, dim3(fused::TX, TL::TY), 0, g,
+      // FP64 channels with walls: the z boundary fixed at compile time (the wall-model build
+      // needs 238 VGPRs instead of 255 and ran 674 -> 603 us on 512x256x128; in FP32, and
+      // for periodic z, where the fixed builds measured slower, it stays a run-time value)
+      auto kf = k_dsm_fused<T, false>;
+      if constexpr (sizeof(T) == 8) {
+        if (g.zbc == LES_ZBC_WALLMODEL) kf = k_dsm_fused<T, false, LES_ZBC_WALLMODEL>;
+        if (g.zbc == LES_ZBC_NOSLIP) kf = k_dsm_fused<T, false, LES_ZBC_NOSLIP>;
+      }
+      LES_LAUNCH(c, "dsm_fused", 4 * pts * sizeof(T), kf, grid, dim3(fused::TX, TL::TY), 0, g,
                  (const T*)c.u, (const T*)c.v, (const T*)c.w, dsm_nut, c.t.dsm_part, kc, gate);
       const int ntile = (int)(grid.x * grid.y) * TL::WV;
       LES_LAUNCH(c, "dsm_reduce", 0, k_dsm_reduce<T>, dim3(g.nz), dim3(256), 0, g, c.t.dsm_part, ntile, c.t.cs,
