@@ -653,8 +653,18 @@ __device__ __forceinline__ void thomas_scan_body(unsigned bx, GridP g, cpx<T>* _
     v[j] = in ? (double)x[(int64_t)k * ncol2] * norm : 0.0;
     fc[j] = in ? fp[(int64_t)k * nfac] : make_double2(0.0, 0.0);
   }
-  seg_scan_solve<S, CG>(v, k0, n, p, P, cl, E, G, [&](int j) { return fc[j].y; }, [&](int j) { return pa[k0 + j]; },
-                        [&](int j) { return fc[j].x; });
+  // a_k: scalar loads when a wave holds one segment; else (two segments per wave) from a copy
+  // in LDS, read where used rather than held in registers (the 16-row variant spilled)
+  __shared__ double sa[CG % 64 == 0 ? 1 : 512];
+  if constexpr (CG % 64 != 0) {
+    for (int k = (int)threadIdx.x; k < n; k += (int)blockDim.x) sa[k] = pa[k];
+    __syncthreads();
+  }
+  auto AF = [&](int j) -> double {
+    if constexpr (CG % 64 == 0) return pa[k0 + j];
+    else return sa[k0 + j];
+  };
+  seg_scan_solve<S, CG>(v, k0, n, p, P, cl, E, G, [&](int j) { return fc[j].y; }, AF, [&](int j) { return fc[j].x; });
   if (ZERO && bx == 0) {
     // zero mode: chains 0 (real part) and 1 (imaginary part) of this block
     double sw = 0.0, sd = 0.0;
