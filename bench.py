@@ -768,7 +768,9 @@ def c4_line(args, torch):
 def batch_line(args, torch):
     """64 periodic boxes of mixed sizes advanced together: one launch per kernel kind per
     substep for all boxes, per-box device time step, the whole step replayed from a
-    hipGraph, tiles chosen by the autotuner first (its time reported separately)."""
+    hipGraph, tiles chosen by the autotuner first (its time reported separately).  Then the
+    ensemble's final state is sampled as learned-closure training data (2^16 pairs per box,
+    `training_samples`)."""
     from paper_2411_09364_amd import les
     from synth import box_ensemble, isotropic_field
     cfgd = CONFIGS["c5"]
@@ -823,6 +825,14 @@ def batch_line(args, torch):
         bad += int(d.nonfinite)
     alg = 25 * 4   # minimal-sweep words per point and substep (explicit), FP32 storage
     achieved = value * 1e6 * alg / 1e9
+    # the ensemble as a training-data generator: 2^16 pairs per box from the final state
+    npb = 1 << 16
+    t0 = time.perf_counter()
+    xs, ys = b.mlp_sample(11, npb)
+    sample_s = time.perf_counter() - t0
+    sampling = {"pairs": int(ys.shape[0]), "pairs_per_box": npb, "seconds": round(sample_s, 4),
+                "pairs_per_s": round(ys.shape[0] / sample_s), "finite": bool(torch.isfinite(xs).all().item())}
+    del xs, ys
     b.close()
     sizes = {}
     for e in ens:
@@ -847,6 +857,7 @@ def batch_line(args, torch):
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "alg_bytes_per_point": alg},
         "autotune": {"seconds": round(tune_s, 3), "choice": tune},
         "state_check": {"max_div": max(divs), "nonfinite": bad},
+        "training_samples": sampling,
     }
 
 

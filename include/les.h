@@ -362,6 +362,14 @@ les_status les_batch_step(les_batch* b, double cfl, int use_graph);
 les_status les_batch_autotune(les_batch* b, int substeps, char* report, size_t len);
 /* Readable quantities and diagnostics of one box (as les_read / les_diag). */
 les_status les_batch_read(les_batch* b, int box, int field, void* dst);
+/* The ensemble as a training-data generator for the learned closure: box i draws n_per_box
+ * training pairs from its current state as les_mlp_sample does with seed + i, into rows
+ * [i n_per_box, (i + 1) n_per_box) of x_raw_dev (float[nbox n_per_box][7], raw inputs) and
+ * y_dev (float[nbox n_per_box], the dynamic-model coefficient of the box).  Boxes with
+ * sgs = DSM, after les_batch_nut or a batched substep; buffers are the caller's, on the
+ * batch stream.  LES_EINVAL for n_per_box < 0 or null buffers, LES_ESTATE before the
+ * batch is bound. */
+les_status les_batch_mlp_sample(les_batch* b, uint64_t seed, int64_t n_per_box, float* x_raw_dev, float* y_dev);
 les_status les_batch_diag(les_batch* b, int box, les_diag_t* out);
 const char* les_batch_last_error(const les_batch* b);
 les_status les_batch_free(les_batch* b);

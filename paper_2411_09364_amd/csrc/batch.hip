@@ -427,6 +427,20 @@ les_status les_batch_read(les_batch* b, int box, int field, void* dst) {
   return les_read(b->box[box], field, dst);
 }
 
+les_status les_batch_mlp_sample(les_batch* b, uint64_t seed, int64_t n, float* x, float* y) {
+  if (!b) return LES_EINVAL;
+  if (n < 0) return bfail(b, LES_EINVAL, "n_per_box must be non-negative");
+  if (n > 0 && (!x || !y)) return bfail(b, LES_EINVAL, "null buffer");
+  les_status s = prepare(b);
+  if (s != LES_OK) return s;
+  // one launch per box on the batch stream: sampling is not on the timed path
+  for (int i = 0; i < b->nbox && n > 0; ++i) {
+    s = les_mlp_sample(b->box[i], seed + (uint64_t)i, n, x + (int64_t)i * n * 7, y + (int64_t)i * n);
+    if (s != LES_OK) return bfail(b, s, les_last_error(b->box[i]));
+  }
+  return LES_OK;
+}
+
 les_status les_batch_diag(les_batch* b, int box, les_diag_t* out) {
   if (!b || box < 0 || box >= b->nbox) return LES_EINVAL;
   return les_diag(b->box[box], out);

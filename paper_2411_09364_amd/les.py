@@ -104,6 +104,7 @@ def _load():
         "les_batch_autotune": [vp, i32, ctypes.c_char_p, ctypes.c_size_t],
         "les_batch_read": [vp, i32, i32, vp],
         "les_batch_diag": [vp, i32, ctypes.POINTER(LesDiag)],
+        "les_batch_mlp_sample": [vp, ctypes.c_uint64, ctypes.c_int64, vp, vp],
         "les_batch_free": [vp],
         "les_timing_report": [vp, ctypes.c_char_p, ctypes.c_size_t],
         "les_stats_reset": [vp],
@@ -138,7 +139,7 @@ def exported_symbols():
             "les_mlp_grad_noalloc", "les_mlp_adam", "les_mlp_train_step", "les_free", "les_strerror", "les_last_error",
             "les_timing", "les_timing_report", "les_batch_init", "les_batch_layout", "les_batch_offset",
             "les_batch_bind", "les_batch_nut", "les_batch_dt", "les_batch_set_dt", "les_batch_substep",
-            "les_batch_step", "les_batch_autotune", "les_batch_read", "les_batch_diag",
+            "les_batch_step", "les_batch_autotune", "les_batch_read", "les_batch_diag", "les_batch_mlp_sample",
             "les_batch_last_error", "les_batch_free", "les_stats_reset", "les_stats_sample", "les_stats_read",
             "les_profile_error"]
 
@@ -614,6 +615,20 @@ class Batch:
         _bcheck(self.h, LIB.les_batch_read(self.h, b, FIELD_NUT, ctypes.c_void_p(out.data_ptr())), "les_batch_read")
         self.stream.synchronize()
         return out.double().cpu().numpy()
+
+    def mlp_sample(self, seed, n_per_box):
+        """Training pairs of every box (les_batch_mlp_sample): box b's rows are
+        [b n_per_box, (b + 1) n_per_box) of x (raw inputs) and y."""
+        torch = self.torch
+        nb = len(self.cfgs)
+        with torch.cuda.stream(self.stream):
+            x = torch.empty((nb * n_per_box, 7), dtype=torch.float32, device=self.buf[0].device)
+            y = torch.empty(nb * n_per_box, dtype=torch.float32, device=self.buf[0].device)
+        _bcheck(self.h, LIB.les_batch_mlp_sample(self.h, ctypes.c_uint64(seed), ctypes.c_int64(n_per_box),
+                                                 ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())),
+                "les_batch_mlp_sample")
+        self.stream.synchronize()
+        return x, y
 
     def box_dt(self, b):
         d = LesDiag()

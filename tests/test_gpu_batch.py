@@ -121,3 +121,48 @@ def test_autotune_keeps_results_bitwise(les):
     for b in range(len(cases)):
         for q in range(4):
             assert np.array_equal(outs[0][b][q], outs[1][b][q]), (b, q)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_sampling_matches_single_contexts(les, precision):
+    """The ensemble as a training-data generator: box b of a batch draws the same training
+    pairs as les_mlp_sample on an unbatched context in the same state with seed + b, bit for
+    bit, after les_nut and after a batched step (which equals the unbatched step bit for bit)."""
+    cases = _cases(precision, SGS_DSM)
+    batch = les.Batch([c[2] for c in cases])
+    singles = []
+    for b, (case, g, cfg, k0) in enumerate(cases):
+        u, v, w = initial_fields(case, g, 20 + b, "iso")
+        if precision == 1:
+            u, v, w = round32(u, v, w)
+        batch.set_state(b, u, v, w)
+        s = les.Solver(cfg)
+        s.set_state(u, v, w)
+        s.nut()
+        singles.append(s)
+    batch.nut()
+    n, seed = 3000, 1234
+    for rnd in range(2):
+        x, y = batch.mlp_sample(seed, n)
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        assert x.shape == (len(cases) * n, 7) and y.shape == (len(cases) * n,)
+        for b, s in enumerate(singles):
+            xs, ys = s.mlp_sample(seed + b, n)
+            assert np.array_equal(x[b * n:(b + 1) * n], xs.cpu().numpy()), (rnd, b)
+            assert np.array_equal(y[b * n:(b + 1) * n], ys.cpu().numpy()), (rnd, b)
+            assert np.all(np.isfinite(x[b * n:(b + 1) * n])) and np.all(y[b * n:(b + 1) * n] >= 0)
+        say(f"  batch sampling round {rnd}: {len(cases)} boxes x {n} pairs, c_s per box",
+            [float(y[b * n]) for b in range(len(cases))])
+        # one step, batched and unbatched, then sample again
+        batch.set_dt(2e-3)
+        for s in singles:
+            s.set_dt(2e-3)
+        for k in range(3):
+            batch.substep(k)
+            for s in singles:
+                s.substep(k)
+    x0, _ = batch.mlp_sample(seed, 0)
+    assert x0.shape == (0, 7)
+    for s in singles:
+        s.close()
+    batch.close()
