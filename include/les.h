@@ -159,7 +159,11 @@ les_status les_nut(les_ctx* ctx);
 /* Time step: Courant-limited (cfl times the inverse of max |u|/dx + |v|/dy + |w|/dzf)
  * and viscous-limited (0.95 * 2.51 / (4 max(nu + nu_t) sum 1/h^2), z term dropped with
  * CN in z), the minimum of the two, written to the context's device time-step slot.  If
- * dt_host is not NULL the stream is synchronised and the value returned there. */
+ * dt_host is not NULL the stream is synchronised and the value returned there.  After a
+ * substep the advective maximum is the one the substep's correction took from the velocity
+ * it wrote (the same per-cell values); les_nut, les_bind and les_project drop it, so fields
+ * written by the caller are read here once les_nut has run for them.  LES_CFL_PASS=1 in the
+ * environment when the context is created: always a pass over the fields. */
 les_status les_dt(les_ctx* ctx, double cfl, double* dt_host);
 
 /* Write dt into the device time-step slot (enqueued; no synchronisation). */

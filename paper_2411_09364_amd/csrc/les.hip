@@ -243,6 +243,8 @@ size_t carve(Ctx& c, char* base) {
     const bool mixed = f.precision == LES_MIXED;
     const int slots16 = mixed ? 1024 : 512;
     c.pred_ty = f.ny % 16 == 0 && whole_rounds(slots16) > 0 ? 16 : 8;
+    // LES_CFL_PASS=1: the time step's advective maxima always take a pass of their own
+    if (const char* e = std::getenv("LES_CFL_PASS")) c.cfl_fold = std::atoi(e) != 1;
     if (const char* e = std::getenv("LES_PRED_TILE_ROWS")) {
       const int r = std::atoi(e);
       if (r == 8 || r == 16) c.pred_ty = r;
@@ -254,6 +256,11 @@ size_t carve(Ctx& c, char* base) {
   const int dty = dsm_tile_rows(f.precision != LES_MIXED);
   const size_t dsm_waves = (size_t)((f.nx + 31) / 32) * ((f.ny + dty - 1) / dty) * (32 * dty / 64);
   t.dsm_part = (double*)take(std::max((size_t)2 * n * dsm_waves, (size_t)2 * n * f.ny * ((f.nx + 31) / 32)) * 8);
+  {
+    int bx, by;
+    tile_shape(f.nx, f.ny, bx, by);
+    t.cflc = (double*)take((size_t)4 * ((f.nx + bx - 1) / bx) * ((f.ny + by - 1) / by) * n * 8);
+  }
   c.ru = take(F * E);
   c.rv = take(F * E);
   c.rw = take(F * E);
@@ -460,6 +467,7 @@ les_status les_bind(les_ctx* ctx, int field, void* ptr) {
   Ctx& c = ctx->c;
   if (!ptr) return fail(&c, LES_EINVAL, "null pointer");
   if (((uintptr_t)ptr) & 255) return fail(&c, LES_EINVAL, "pointer must be 256-byte aligned");
+  c.cfl_adv_ready = false;   // fields not written by the last correction
   switch (field) {
     case LES_FIELD_U: c.u = ptr; break;
     case LES_FIELD_V: c.v = ptr; break;
@@ -553,6 +561,7 @@ les_status les_nut(les_ctx* ctx) {
   Ctx& c = ctx->c;
   les_status s = ready(c, false);
   if (s != LES_OK) return s;
+  c.cfl_adv_ready = false;   // called after the fields are written: the correction's maxima are stale
   if (c.cfg.precision == LES_MIXED) {
     launch_bc_fill<float>(c, (float*)c.u, (float*)c.v, (float*)c.w, (float*)c.p);
     if (c.g.ywall) launch_bc_fill_y<float>(c, (float*)c.u, (float*)c.v, (float*)c.w, (float*)c.p);
@@ -651,6 +660,7 @@ les_status les_project(les_ctx* ctx) {
   if (c.cfg.precision == LES_MIXED) launch_project<float>(c);
   else launch_project<double>(c);
   c.initialised = false;   // the eddy viscosity and ghosts of the new velocity come from les_nut
+  c.cfl_adv_ready = false;
   return check_launch(c, "les_project");
 }
 

@@ -70,6 +70,23 @@ __device__ inline void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Advective time-step measure |u|/dx + |v|/dy + |w|/dzf of one cell from its face values
+// (1/dzf from the table of reciprocals), every product and sum rounded on its own (no
+// contraction into FMAs), so that the kernels that form it get the same bits.
+__device__ inline double cfl_adv(double u, double v, double w, double rdx, double rdy, double rdzf) {
+#pragma clang fp contract(off)
+  return (fabs(u) * rdx + fabs(v) * rdy) + fabs(w) * rdzf;
+}
+
+// Block shape of the one-thread-per-cell tile launches (32 x 8 cells, narrower grids take
+// their full width)
+__host__ __device__ inline void tile_shape(int nx, int ny, int& bx, int& by) {
+  bx = nx >= 32 ? 32 : nx;
+  by = 256 / bx;
+  if (by > 8 && bx == 32) by = 8;
+  if (by > ny) by = ny;
+}
+
 __host__ __device__ inline int64_t idx3(const GridP& g, int k, int j, int i) {
   return ((int64_t)k * g.nys + j) * g.nx + i;
 }
@@ -200,6 +217,7 @@ struct Tables {
   double* twc;      // ducts: 2*ny cos, sin of pi m / (2 ny), the cosine transform's twiddles
   float* twc_f;
   double* dsm_part; // plane partial sums (LM, MM) per tile and wave of the fused dynamic model
+  double* cflc;     // 4 per block of the last correction: max |u|/dx + |v|/dy + |w|/dzf per wave
   double* pfac;     // walls: (c', 1/pivot) of the (l, m) z systems, [nz][nm][nxp] pairs with
                     //   nm = ny/2+1 (periodic y: m and ny - m share them) or ny (ducts)
   double* stats;    // statistics: header[8], sums [11][nz], wall-stress series [cap][2]
@@ -239,6 +257,10 @@ struct Ctx {
   int mlp_kc = 8;         // planes per z chunk of the learned-closure inference kernel
   int pred_kc = 8;        // planes per z chunk of the z-marching predictor
   int pred_ty = 8;        // rows of the predictor's 32-wide tiles: 8 or 16
+  // time step: the advective maxima taken by the correction's blocks (unless LES_CFL_PASS=1),
+  // usable while the fields are those that correction wrote
+  bool cfl_fold = true;
+  bool cfl_adv_ready = false;
   int bulk_nblk = 0;      // forward-x flow-rate partials awaiting the shift (spectral_solve forms it)
   // learned closure
   float* mlp_params = nullptr;   // caller-owned float32 parameters (les_mlp_bind)

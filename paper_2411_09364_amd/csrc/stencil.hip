@@ -26,10 +26,8 @@ Launch3 point_launch(const GridP& g, int planes) {
 // 32 x 8 tiles for the stencil sweeps (a wave covers two 256-byte rows in FP64).
 Launch3 tile_launch(const GridP& g, int planes) {
   Launch3 L;
-  const int bx = g.nx >= 32 ? 32 : g.nx;
-  int by = 256 / bx;
-  if (by > 8 && bx == 32) by = 8;
-  if (by > g.ny) by = g.ny;
+  int bx, by;
+  tile_shape(g.nx, g.ny, bx, by);
   L.block = dim3(bx, by, 1);
   L.grid = dim3((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, planes);
   return L;
@@ -883,16 +881,49 @@ void launch_bc_fill(Ctx& c, T* u, T* v, T* w, T* p) {
 // p += phi - gamma nu dt/2 L_zz phi (Eq. p_update_imp1d), flow-rate shift s q(z) on u,
 // then the non-wall-model ghost planes.  phi ghosts follow the Poisson boundary
 // condition (zero flux at walls, periodic copy otherwise) and are read on the fly.
-template <typename T>
+// Maximum over a whole wave of 64 lanes: DPP steps within each row of 16 lanes (quad
+// permutations, half-row and row mirrors), then the four rows' values by readlane.
+template <int CTRL>
+__device__ inline double dpp_move_f64(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false));
+}
+__device__ inline double readlane_f64(double x, int L) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), L),
+                          __builtin_amdgcn_readlane(__double2loint(x), L));
+}
+__device__ inline double whole_wave_max(double x) {
+  x = fmax(x, dpp_move_f64<0xB1>(x));
+  x = fmax(x, dpp_move_f64<0x4E>(x));
+  x = fmax(x, dpp_move_f64<0x141>(x));
+  x = fmax(x, dpp_move_f64<0x140>(x));
+  return fmax(fmax(readlane_f64(x, 0), readlane_f64(x, 16)), fmax(readlane_f64(x, 32), readlane_f64(x, 48)));
+}
+
+template <typename T, bool ADV = false>
 __device__ __forceinline__ void correct_body(dim3 bid, GridP g, const T* __restrict__ us, const T* __restrict__ vs,
                                                  const T* __restrict__ ws, const T* __restrict__ phi, T* __restrict__ u,
                                                  T* __restrict__ v, T* __restrict__ w, T* __restrict__ p,
                                                  const double* __restrict__ dtp, const double* __restrict__ qprof,
-                                                 double gamma, int implicit) {
+                                                 double gamma, int implicit, double* __restrict__ advp = nullptr) {
   const int i = bid.x * blockDim.x + threadIdx.x;
   const int j = bid.y * blockDim.y + threadIdx.y;
   const int k = bid.z + 1;
-  if (i >= g.nx || j >= g.ny) return;
+  // ADV: the maxima of the time step's advective measure of the new velocity, four slots per
+  // block of the launch (by hardware block index), so every thread stays: one per wave when the
+  // block is whole waves (no barrier; unused slots 0), else (narrow grids) the block's maximum
+  // by LDS atomics on the bits (non-negative doubles order as their bit patterns) in slot 0
+  const int nthr = (int)(blockDim.x * blockDim.y), tid = (int)(threadIdx.y * blockDim.x + threadIdx.x);
+  __shared__ unsigned long long bmax;
+  double adv = 0.0;
+  if constexpr (ADV) {
+    if (nthr % 64 != 0) {
+      if (tid == 0) bmax = 0;
+      __syncthreads();
+    }
+  }
+  if (i < g.nx && j < g.ny) {
   const int n = g.nz;
   const bool per = g.zbc == LES_ZBC_PERIODIC;
   const int kp = (k == n) ? (per ? 1 : n) : k + 1;   // phi ghost plane by BC
@@ -924,6 +955,10 @@ __device__ __forceinline__ void correct_body(dim3 bid, GridP g, const T* __restr
   v[c0] = vn;
   w[c0] = wn;
   p[c0] = pn;
+  if constexpr (ADV) {
+    adv = cfl_adv((double)un, (double)vn, (double)wn, g.rdx, g.rdy, g.rdzf[k]);
+    if (!(adv == adv)) adv = 0.0;   // a NaN counts as 0, as fmax has it
+  }
   // ghost planes
   const int64_t s = g.sxy;
   const int64_t c2 = (int64_t)j * g.nx + i;
@@ -934,13 +969,31 @@ __device__ __forceinline__ void correct_body(dim3 bid, GridP g, const T* __restr
     if (k == 1) { u[c2] = -un; v[c2] = -vn; w[c2] = (T)0; p[c2] = pn; }
     if (k == n) { u[(n + 1) * s + c2] = -un; v[(n + 1) * s + c2] = -vn; w[(n + 1) * s + c2] = (T)0; p[(n + 1) * s + c2] = pn; }
   }
+  }
+  if constexpr (ADV) {
+    double* slot = advp + 4 * (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+    if (nthr % 64 == 0) {
+      adv = whole_wave_max(adv);
+      if (tid % 64 == 0) slot[tid / 64] = adv;
+      if (tid == 0)
+        for (int q = nthr / 64; q < 4; ++q) slot[q] = 0.0;
+    } else {
+      if (i < g.nx && j < g.ny) atomicMax(&bmax, (unsigned long long)__double_as_longlong(adv));
+      __syncthreads();
+      if (tid == 0) {
+        slot[0] = __longlong_as_double((long long)bmax);
+        slot[1] = slot[2] = slot[3] = 0.0;
+      }
+    }
+  }
 }
 
-template <typename T>
+template <typename T, bool ADV>
 __global__ void __launch_bounds__(256) k_correct(GridP g, const T* us, const T* vs, const T* ws, const T* phi, T* u,
                                                  T* v, T* w, T* p, const double* dtp, const double* qprof,
-                                                 double gamma, int implicit) {
-  correct_body<T>(xcd_tile(blockIdx, gridDim), g, us, vs, ws, phi, u, v, w, p, dtp, qprof, gamma, implicit);
+                                                 double gamma, int implicit, double* advp) {
+  correct_body<T, ADV>(xcd_tile(blockIdx, gridDim), g, us, vs, ws, phi, u, v, w, p, dtp, qprof, gamma, implicit,
+                       advp);
 }
 
 template <typename T>
@@ -957,9 +1010,14 @@ void launch_correct(Ctx& c, int stage) {
   static const double G[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
   Launch3 L = tile_launch(c.g, c.g.nz);
   const double* q = c.cfg.ubulk > 0.0 ? c.t.hfac + 4 * c.g.nz : nullptr;
-  LES_LAUNCH(c, "correct", 9.0 * c.g.sxy * c.g.nz * sizeof(T), k_correct<T>, L.grid, L.block, 0, c.g, (const T*)c.us, (const T*)c.vs,
+  // FP64: the advective maxima of the new velocity for the next time step, unless
+  // LES_CFL_PASS=1 (in FP32 the extra work cost the correction more than the pass it saves)
+  const bool adv = c.cfl_fold && sizeof(T) == 8;
+  c.cfl_adv_ready = adv;
+  LES_LAUNCH(c, "correct", 9.0 * c.g.sxy * c.g.nz * sizeof(T), (adv ? k_correct<T, true> : k_correct<T, false>),
+             L.grid, L.block, 0, c.g, (const T*)c.us, (const T*)c.vs,
                      (const T*)c.wsf, (const T*)c.phi, (T*)c.u, (T*)c.v, (T*)c.w, (T*)c.p, c.t.dt, q, G[stage],
-                     c.cfg.implicit_z);
+                     c.cfg.implicit_z, c.t.cflc);
 }
 
 // ============================================================================ wall model
@@ -1174,11 +1232,18 @@ void launch_wallmodel_y(Ctx& c) {
 // ============================================================================ time step
 // Block maxima of |u|/dx + |v|/dy + |w|/dzf and of nu_t, reduced in a fixed order by a
 // single block which then writes dt (R22 reading of the paper's time-step rule).
-template <typename T>
+// VISC_ONLY: the maxima of nu_t alone (the advective ones come from the correction's blocks)
+template <typename T, bool VISC_ONLY = false>
 __device__ __forceinline__ void cfl_partial_body(int b, int nb, GridP g, const T* u, const T* v, const T* w,
-                                                 const T* nut, const double* coef, double* part) {
+                                                 const T* nut, const double* coef, double* part,
+                                                 const double* adv = nullptr, int64_t nadv = 0) {
   __shared__ double sm[2][256];
   double mc = 0.0, mn = 0.0;
+  if constexpr (VISC_ONLY) {
+    // the advective maxima: this block's share of the correction's block maxima
+    const int64_t per = (nadv + nb - 1) / nb, e0 = (int64_t)b * per, e1 = min(e0 + per, nadv);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) mc = fmax(mc, adv[e]);
+  }
   // interior cells: the first nxy of every plane (a duct's ghost rows follow them)
   const int64_t nxy = (int64_t)g.nx * g.ny;
   const int64_t total = (int64_t)g.nz * nxy;
@@ -1191,8 +1256,7 @@ __device__ __forceinline__ void cfl_partial_body(int b, int nb, GridP g, const T
   const int64_t dk = step / nxy, dr = step % nxy;
   for (; e < total; e += step) {
     const int64_t c = (int64_t)k * g.sxy + r;
-    const double a = fabs((double)u[c]) * g.rdx + fabs((double)v[c]) * g.rdy + fabs((double)w[c]) / g.dzf[k];
-    mc = fmax(mc, a);
+    if constexpr (!VISC_ONLY) mc = fmax(mc, cfl_adv((double)u[c], (double)v[c], (double)w[c], g.rdx, g.rdy, g.rdzf[k]));
     mn = fmax(mn, coef[k] * (double)nut[c]);
     k += (int)dk;
     r += dr;
@@ -1217,10 +1281,11 @@ __device__ __forceinline__ void cfl_partial_body(int b, int nb, GridP g, const T
   }
 }
 
-template <typename T>
+template <typename T, bool VISC_ONLY>
 __global__ void __launch_bounds__(256) k_cfl_partial(GridP g, const T* u, const T* v, const T* w, const T* nut,
-                                                     const double* coef, double* part) {
-  cfl_partial_body<T>(blockIdx.x, gridDim.x, g, u, v, w, nut, coef, part);
+                                                     const double* coef, double* part, const double* adv,
+                                                     int64_t nadv) {
+  cfl_partial_body<T, VISC_ONLY>(blockIdx.x, gridDim.x, g, u, v, w, nut, coef, part, adv, nadv);
 }
 
 __device__ __forceinline__ void cfl_final_body(const double* part, int nblk, double* dtp, double cfl, double nu,
@@ -1279,9 +1344,22 @@ __global__ void kb_set_dt(BatchMap m, double dt) {
 
 template <typename T>
 void launch_dt(Ctx& c, double cfl) {
-  const int nblk = 512;
-  LES_LAUNCH(c, "cfl_partial", 4.0 * c.g.sxy * c.g.nz * sizeof(T), k_cfl_partial<T>, dim3(nblk), dim3(256), 0, c.g, (const T*)c.u, (const T*)c.v,
-                     (const T*)c.w, (const T*)c.nut, c.t.coef, c.t.red);
+  // the advective maxima from the last correction's blocks while the fields are those it wrote
+  // (les_nut, les_bind and les_project drop them), else from a pass of their own; the nu_t-only
+  // pass takes more blocks (one load per cell)
+  const bool fold = c.cfl_fold && c.cfl_adv_ready;
+  const int nblk = fold ? 2048 : 512;
+  static_assert(2 * 2048 <= 4096, "partials fit the reduction area");
+  const Launch3 L = tile_launch(c.g, c.g.nz);
+  const int64_t nadv = fold ? 4 * (int64_t)L.grid.x * L.grid.y * L.grid.z : 0;
+  if (fold)
+    LES_LAUNCH(c, "cfl_visc", 1.0 * c.g.sxy * c.g.nz * sizeof(T), (k_cfl_partial<T, true>), dim3(nblk), dim3(256), 0,
+               c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w, (const T*)c.nut, c.t.coef, c.t.red,
+               (const double*)c.t.cflc, nadv);
+  else
+    LES_LAUNCH(c, "cfl_partial", 4.0 * c.g.sxy * c.g.nz * sizeof(T), (k_cfl_partial<T, false>), dim3(nblk), dim3(256),
+               0, c.g, (const T*)c.u, (const T*)c.v, (const T*)c.w, (const T*)c.nut, c.t.coef, c.t.red,
+               (const double*)nullptr, (int64_t)0);
   // viscous limit: z term dropped with CN in z; with CN in all directions only the explicit
   // SGS viscosity limits (molecular viscosity passed as 0)
   double sinv = 1.0 / (c.g.dx * c.g.dx) + 1.0 / (c.g.dy * c.g.dy);

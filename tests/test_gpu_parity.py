@@ -248,6 +248,48 @@ def test_time_step_matches_oracle(les, visc):
     solver.close()
 
 
+CFL_CASES = [
+    ("channel dsm wm cn-z", dict(nx=48, ny=24, nz=20, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5,
+                                 nu=5e-5, sgs=SGS_DSM, ubulk=1.0, implicit_z=True), "channel"),
+    ("periodic dsm", dict(nx=32, ny=32, nz=32, lx=TWO_PI, ly=TWO_PI, lz=TWO_PI, nu=1e-3, sgs=SGS_DSM), "iso"),
+    ("mixed channel dsm wm", dict(nx=48, ny=24, nz=20, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5,
+                                  nu=1.6e-5, sgs=SGS_DSM, ubulk=1.0, precision=1), "channel"),
+    # narrow tiles (nx < 32) and ragged rows
+    ("narrow ragged noslip vd", dict(nx=20, ny=20, nz=9, lx=2.0, ly=2.0, lz=2.0, zbc=ZBC_NOSLIP, beta=1.2, nu=1e-3,
+                                     sgs=SGS_SMAG_VD, ubulk=1.0), "channel"),
+]
+
+
+@pytest.mark.parametrize("name, cfgd, kind", CFL_CASES)
+def test_time_step_from_the_correction(les, monkeypatch, name, cfgd, kind):
+    """After a substep of an FP64 context the time step takes its advective maxima from the
+    correction's blocks (max over the same per-cell values as the pass of its own), so the time
+    steps equal those of LES_CFL_PASS=1 bit for bit, step after step; after les_nut, and in
+    FP32 contexts, the pass of its own runs."""
+    seqs = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("LES_CFL_PASS", env)   # read when the context is created
+        case, g, cfg = make_pair(**cfgd)
+        u, v, w = initial_fields(case, g, 3, kind)
+        solver = les.Solver(cfg)
+        solver.set_state(u, v, w)
+        solver.nut()
+        seq = []
+        for it in range(4):
+            les.les_timing(solver.ctx, True)
+            seq.append(solver.dt(0.5))
+            rep = les.les_timing_report(solver.ctx)
+            les.les_timing(solver.ctx, False)
+            folded = env == "0" and it > 0 and cfgd.get("precision", 0) == 0
+            assert ("cfl_partial" in rep) == (not folded) and ("cfl_visc" in rep) == folded, (it, rep)
+            solver.step()
+        seqs.append(seq)
+        solver.close()
+    say(name, seqs)
+    assert seqs[0] == seqs[1]
+    assert all(np.isfinite(seqs[0])) and min(seqs[0]) > 0
+
+
 MIXED_CASES = [
     ("mixed C3-like dsm wm explicit",
      dict(nx=48, ny=24, nz=20, lx=TWO_PI, ly=np.pi, lz=2.0, zbc=ZBC_WALLMODEL, beta=1.5, nu=1.6e-5,
